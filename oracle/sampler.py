@@ -1,0 +1,103 @@
+"""Oracle: Metropolis sampling of |psi|^2 (test infrastructure only).
+
+Sec. 2.2.5: configurations are drawn from pi(sigma) of Eq. 4 by Markov chains built with
+the Metropolis algorithm, which ensures detailed balance. Listing-level choices the
+paper leaves open, fixed as conventions both sides follow:
+
+* moves: single-spin flip at a uniformly chosen site (MOVE_FLIP), or exchange of the two
+  spins of a uniformly chosen color-0 bond (MOVE_EXCHANGE, the paper's nearest-neighbour
+  swaps conserving total magnetisation). An exchange on two equal spins is the identity
+  move: its random numbers are still drawn and it is not counted as accepted.
+* acceptance: the proposal is symmetric, so accept with probability
+  min(1, |psi(sigma')/psi(sigma)|^2) = min(1, exp(2 Re Delta)), Delta = log psi(sigma') -
+  log psi(sigma): accept iff 2 Re Delta >= 0 or u < exp(2 Re Delta).
+* a sweep is N proposals (N sites); one sample per chain is recorded after each sweep,
+  after ``n_discard`` unrecorded sweeps.
+* random numbers: Philox4x32-10, counter (chain, counter_base + sweep, step, tag); see
+  ``philox``. Chain initialisation: independent +/-1 spins (MOVE_FLIP), or a uniformly
+  random permutation (Fisher-Yates) of N/2 up and N/2 down spins (MOVE_EXCHANGE).
+
+This is the definition: log psi(sigma') is recomputed from scratch for every proposal.
+Chains are independent, so all chains advance together as numpy arrays.
+
+Pins (tests/test_oracle_sampler.py): the empirical one-step transition row of
+``metropolis_step`` against the analytic Metropolis kernel, and the histogram of long
+chains against exact |psi|^2 by enumeration (chi-square), on N <= 6.
+"""
+import numpy as np
+
+from . import philox, rbm
+from .hamiltonian import MOVE_EXCHANGE, MOVE_FLIP
+
+
+def init_chains(model, n_chains, seed, chain_offset=0):
+    N = model.n_sites
+    chains = np.arange(n_chains, dtype=np.uint64) + np.uint64(chain_offset)
+    out = np.empty((n_chains, N), dtype=np.int8)
+    if model.move == MOVE_FLIP:
+        w = philox.draw(seed, chains[:, None], 0, np.arange(N)[None, :], philox.TAG_INIT)
+        out[:] = np.where((w[..., 0] >> np.uint32(31)) == 0, 1, -1)
+    else:
+        if N % 2:
+            raise ValueError("zero magnetisation needs an even number of sites")
+        for c in range(n_chains):
+            s = np.array([1] * (N // 2) + [-1] * (N // 2), dtype=np.int8)
+            for k in range(N - 1, 0, -1):
+                w = philox.draw(seed, chains[c], 0, k, philox.TAG_INIT)
+                r = int(philox.index_from_word(w[0], k + 1))
+                s[k], s[r] = s[r], s[k]
+            out[c] = s
+    return out
+
+
+def metropolis_step(model, params, sigma, seed, chain_ids, sweep, step):
+    """One proposal + accept/reject for every chain. sigma [C, N] is updated in place.
+    Returns a bool array: accepted (real moves only)."""
+    N, M = model.n_sites, model.n_hidden
+    w = philox.draw(seed, chain_ids, sweep, step, philox.TAG_PROPOSAL)
+    u = philox.uniform_from_words(w[:, 1], w[:, 2])
+    prop = sigma.copy()
+    rows = np.arange(sigma.shape[0])
+    if model.move == MOVE_FLIP:
+        site = philox.index_from_word(w[:, 0], N)
+        prop[rows, site] = -prop[rows, site]
+        real_move = np.ones(sigma.shape[0], dtype=bool)
+    else:
+        bl = model.bonds[0]
+        bidx = philox.index_from_word(w[:, 0], bl.shape[0])
+        i, k = bl[bidx, 0], bl[bidx, 1]
+        si, sk = sigma[rows, i].copy(), sigma[rows, k].copy()
+        real_move = si != sk
+        prop[rows, i] = sk
+        prop[rows, k] = si
+    delta = rbm.log_psi(params, prop, N, M) - rbm.log_psi(params, sigma, N, M)
+    two_re = 2.0 * np.real(delta)
+    accept = real_move & ((two_re >= 0.0) | (u < np.exp(np.minimum(two_re, 0.0))))
+    sigma[accept] = prop[accept]
+    return accept, two_re, u
+
+
+def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain_offset=0,
+           record_ties=None):
+    """Run every chain for n_discard + n_sweeps sweeps of N proposals.
+
+    Returns (samples [n_sweeps, C, N], chain_sigma_out [C, N], n_accepted [C]).
+    If ``record_ties`` is a list, each proposal with |u - exp(2 Re Delta)| < 1e-12 is
+    appended to it as (chain, sweep, step)."""
+    sigma = np.array(chain_sigma, dtype=np.int8, copy=True)
+    C, N = sigma.shape
+    chains = np.arange(C, dtype=np.uint64) + np.uint64(chain_offset)
+    out = np.empty((n_sweeps, C, N), dtype=np.int8)
+    n_acc = np.zeros(C, dtype=np.int64)
+    for sw in range(n_discard + n_sweeps):
+        g = counter + sw
+        for st in range(N):
+            acc, two_re, u = metropolis_step(model, params, sigma, seed, chains, g, st)
+            n_acc += acc
+            if record_ties is not None:
+                near = np.abs(u - np.exp(np.minimum(two_re, 0.0))) < 1e-12
+                for c in np.nonzero(near)[0]:
+                    record_ties.append((int(chains[c]), g, st))
+        if sw >= n_discard:
+            out[sw - n_discard] = sigma
+    return out, sigma, n_acc

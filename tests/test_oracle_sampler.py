@@ -1,0 +1,82 @@
+"""Pins of the oracle Metropolis sampler: one-step transition probabilities against the
+analytic Metropolis kernel, and the stationary histogram against exact |psi|^2."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, lattice, rbm, sampler
+from oracle.hamiltonian import HEISENBERG, MOVE_EXCHANGE, MOVE_FLIP, TFIM, Model
+
+
+def model(move, n=6, m=4):
+    b, sub = lattice.hypercube(n, 1)
+    ham = TFIM if move == MOVE_FLIP else HEISENBERG
+    return Model(n, m, b, ham=ham, J=(1.0, 0.0), h=1.0, sublattice=sub, move=move, is_complex=True)
+
+
+@pytest.mark.parametrize("move", [MOVE_FLIP, MOVE_EXCHANGE])
+def test_transition_row_matches_metropolis_kernel(move):
+    m = model(move)
+    N, M = m.n_sites, m.n_hidden
+    p = synth.rbm_params(N, M, True, sigma=0.6, seed=31)
+    s0 = np.array([1, -1, -1, 1, 1, -1], dtype=np.int8)
+    trials = 40000
+    sig = np.repeat(s0[None, :], trials, axis=0)
+    ids = np.arange(trials, dtype=np.uint64)
+    acc, _, _ = sampler.metropolis_step(m, p, sig, seed=77, chain_ids=ids, sweep=5, step=2)
+    lp0 = rbm.log_psi(p, s0[None, :], N, M)[0]
+    moves = []
+    if move == MOVE_FLIP:
+        for i in range(N):
+            t = s0.copy(); t[i] = -t[i]; moves.append((t, 1.0 / N))
+    else:
+        B = m.bonds[0].shape[0]
+        for i, k in m.bonds[0]:
+            t = s0.copy(); t[i], t[k] = s0[k], s0[i]; moves.append((t, 1.0 / B))
+    expect = {}
+    for t, q in moves:
+        if np.array_equal(t, s0):
+            continue
+        r = np.exp(2 * np.real(rbm.log_psi(p, t[None, :], N, M)[0] - lp0))
+        expect[t.tobytes()] = expect.get(t.tobytes(), 0.0) + q * min(1.0, r)
+    keys, counts = np.unique([row.tobytes() for row in sig], return_counts=True)
+    got = dict(zip(keys, counts / trials))
+    for k, pe in expect.items():
+        pg = got.get(k, 0.0)
+        assert abs(pg - pe) < 5 * np.sqrt(pe * (1 - pe) / trials) + 1e-4, (pg, pe)
+    stay = 1.0 - sum(expect.values())
+    assert abs(got.get(s0.tobytes(), 0.0) - stay) < 5 * np.sqrt(stay * (1 - stay) / trials) + 1e-4
+    n_stay = int(np.sum(np.all(sig == s0[None, :], axis=1)))
+    assert int(acc.sum()) == trials - n_stay
+
+
+@pytest.mark.parametrize("move", [MOVE_FLIP, MOVE_EXCHANGE])
+def test_stationary_histogram_chi_square(move):
+    from scipy.stats import chi2
+    m = model(move)
+    N, M = m.n_sites, m.n_hidden
+    p = synth.rbm_params(N, M, True, sigma=0.25, seed=33)  # one sweep damps the slowest mode by >= 7%
+    chains = 3000
+    init = sampler.init_chains(m, chains, seed=91)
+    smp, last, nacc = sampler.sample(m, p, init, n_sweeps=1, n_discard=200, seed=91, counter=0)
+    confs, pi = exact.exact_probabilities(m, p)
+    if move == MOVE_EXCHANGE:
+        keep = confs.sum(axis=1) == 0
+        confs, pi = confs[keep], pi[keep] / pi[keep].sum()
+    index = {c.tobytes(): k for k, c in enumerate(confs)}
+    hist = np.zeros(len(confs))
+    for row in last:
+        hist[index[row.tobytes()]] += 1
+    expct = pi * chains
+    stat = np.sum((hist - expct) ** 2 / expct)
+    pval = chi2.sf(stat, df=len(confs) - 1)
+    assert pval > 1e-3, (stat, pval)
+
+
+def test_init_chains():
+    m = model(MOVE_EXCHANGE, n=10)
+    c = sampler.init_chains(m, 500, seed=3)
+    assert np.all(c.sum(axis=1) == 0)
+    assert len({r.tobytes() for r in c}) > 200
+    f = sampler.init_chains(model(MOVE_FLIP, n=10), 500, seed=3)
+    assert abs(f.mean()) < 0.05
