@@ -1,0 +1,218 @@
+"""Benchmark of the VMC hot path on one MI355X.
+
+One step = one full pass of the hot path over one batch of synthetic input:
+  Metropolis sampling (sweeps with cached hidden angles) + local energies of every
+  sample + SR step (log-derivative products O v / O^dagger u inside an FP64 CG solve of
+  (S + lambda I) x = F, then the parameter update).
+Default workload: 1D spin-1/2 Heisenberg ring, N = 40, periodic, zero magnetisation via
+nearest-neighbour exchange moves, Marshall-rotated; complex RBM with FP32 contractions,
+alpha = 2 (80 hidden units), parameters N(0, 0.01^2) from seed 1234; 1024 chains x 200
+sweeps = 204,800 samples per step; SR diagonal shift 0.01, learning rate 0.01, CG
+tolerance 1e-8.
+
+Prints one JSON line. value = samples per second of whole steps (sampling + local
+energies + SR). Extra fields: the sampling-only rate, SR iterations per second, CG
+iterations, the roofline of the dominant kernel, and the FP64 oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np
+
+PEAK_FP32_VALU = 157.3e12
+PEAK_FP32_MFMA = 157.3e12
+PEAK_FP64 = 78.6e12
+
+WORKLOADS = {
+    "heisenberg1d_n40_cplx_fp32_alpha2": dict(L=40, ndim=1, diag=False, ham=1, J=(1.0, 0.0), h=0.0,
+                                             marshall=True, move=1, cplx=True, prec=1, alpha=2,
+                                             chains=1024, sweeps=200, lr=0.01, shift=0.01,
+                                             cg_tol=1e-8, cg_maxiter=2000),
+    "tfim1d_n10_real_fp64_alpha1": dict(L=10, ndim=1, diag=False, ham=0, J=(1.0, 0.0), h=1.0,
+                                       marshall=False, move=0, cplx=False, prec=0, alpha=1,
+                                       chains=16, sweeps=1000, lr=0.01, shift=0.01,
+                                       cg_tol=1e-8, cg_maxiter=2000),
+}
+
+
+def cpu_baseline(w, N, M, seconds=15.0):
+    """The FP64 oracle (plain numpy, unmodified) on a bounded sample of the same workload:
+    a subset of the chains for a few sweeps, their local energies and one SR step."""
+    import synth
+    from oracle import hamiltonian as oh, lattice as ol, sampler as osamp, sr as osr
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    ob, osub = ol.hypercube(w["L"], w["ndim"], with_diagonals=w["diag"])
+    om = oh.Model(N, M, ob, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
+                  sublattice=osub, move=w["move"], is_complex=w["cplx"])
+    p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
+    chains, sweeps = 64, 4
+    t0 = time.perf_counter()
+    init = osamp.init_chains(om, chains, seed=1234)
+    total_samples = 0
+    while True:
+        smp, init, _ = osamp.sample(om, p, init, sweeps, 0, seed=1234, counter=total_samples)
+        flat = smp.reshape(-1, N)
+        el = oh.local_energy(om, p, flat)
+        osr.sr_step(om, p, flat, el, w["lr"], w["shift"], w["cg_tol"], w["cg_maxiter"])
+        total_samples += flat.shape[0]
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": total_samples / dt, "unit": "samples/s", "cores": int(cores), "kind": "oracle",
+            "sample": "%d chains x %d sweeps per pass, local energies and one SR step per pass, "
+                      "%d passes in %.1f s" % (chains, sweeps, total_samples // (chains * sweeps), dt)}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="heisenberg1d_n40_cplx_fp32_alpha2", choices=list(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path (chains sharded across GPUs, "
+              "one all-reduce of P values per CG iteration) is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    log("importing torch")
+    import torch
+    import paper_1904_00031_amd as nqs
+    import synth
+
+    nqs.load()
+    log("library loaded, building workload " + args.workload)
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    N = w["L"] ** w["ndim"]
+    M = w["alpha"] * N
+    C, S = w["chains"], w["sweeps"]
+    bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
+    model = nqs.Model(N, M, bonds, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
+                      sublattice=sub, move=w["move"], is_complex=w["cplx"], prec=w["prec"])
+    p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234,
+                         dtype=None if w["prec"] == 0 else (np.complex64 if w["cplx"] else np.float32))
+    params = torch.from_numpy(p).to(dev)
+    chains = torch.empty((C, N), dtype=torch.int8, device=dev)
+    model.chain_init(chains, seed=1234)
+    samples = torch.empty((S, C, N), dtype=torch.int8, device=dev)
+    eloc = torch.empty(S * C, dtype=model.value_dtype, device=dev)
+    nacc = torch.zeros(C, dtype=torch.int64, device=dev)
+    ws = torch.empty(model.sr_workspace_bytes(S * C), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    counter = [0]
+
+    def step(discard, times):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        model.sample(params, chains, S, discard, seed=1234, counter=counter[0], samples=samples,
+                     n_accepted=nacc, eloc=eloc)
+        counter[0] += S + discard
+        e1.record(stream)
+        info = model.sr_step(params, samples.view(S * C, N), eloc, w["lr"], w["shift"],
+                             w["cg_tol"], w["cg_maxiter"], workspace=ws)
+        e2.record(stream)
+        if times is not None:
+            times.append((e0, e1, e2, info))
+        return info
+
+    for k in range(args.warmup):
+        info = step(max(10, S // 10) if k == 0 else 0, None)
+        log("warmup step %d: E=%.8f cg_iters=%d" % (k, info["energy_re"], info["cg_iters"]))
+    torch.cuda.synchronize()
+    times = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(0, times)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    samp_ms = sum(a.elapsed_time(b) for a, b, c, i in times) / args.steps
+    sr_ms = sum(b.elapsed_time(c) for a, b, c, i in times) / args.steps
+    cg = [i["cg_iters"] for a, b, c, i in times]
+    energies = [i["energy_re"] for a, b, c, i in times]
+    ms_per_step = wall * 1e3 / args.steps
+    n_samp = S * C
+
+    # live per-launch timing of the two kernels that carry the work
+    flat = samples.view(n_samp, N)
+    reps = 5
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        model.sample(params, chains, S, 0, seed=99, counter=10 ** 6, samples=samples)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    sweep_ms = ev[0].elapsed_time(ev[1]) / reps
+    u = torch.ones(n_samp, dtype=model.value_dtype, device=dev)
+    v = torch.ones(model.n_params, dtype=model.value_dtype, device=dev)
+    model.log_psi_grad(params, flat, u=u, v=v)
+    ev[0].record(stream)
+    for _ in range(reps):
+        model.log_psi_grad(params, flat, u=u, v=v)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    mv_ms = ev[0].elapsed_time(ev[1]) / reps
+
+    cplx = 2 if w["cplx"] else 1
+    # sweep: per proposal M ratio terms of (complex) multiply-add, |.|^2 and product
+    flops_term = 12 if w["cplx"] else 4
+    sweep_flops = float(n_samp) * N * M * flops_term
+    # one O v + one O^dagger u with theta recomputed: four real contractions n x N x M
+    # per complex part
+    mv_flops = 4.0 * 2 * n_samp * N * M * cplx
+    share_sr = sr_ms / (samp_ms + sr_ms)
+    if share_sr > 0.5:
+        peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_MFMA
+        ach = mv_flops / (mv_ms * 1e-3)
+        roof = {"kernel": "k_jvp+k_vjp (one S v product)", "bound": "mfma", "achieved": ach / 1e12,
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None}
+    else:
+        peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_VALU
+        ach = sweep_flops / (sweep_ms * 1e-3)
+        roof = {"kernel": "k_sweep", "bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None}
+
+    out = {
+        "metric": "samples/s (sweep+E_loc+O_k) and SR iters/s",
+        "value": n_samp / (ms_per_step * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if w["prec"] == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_sites": N, "n_hidden": M, "chains": C,
+                   "sweeps_per_step": S, "samples_per_step": n_samp, "cg_tol": w["cg_tol"],
+                   "diag_shift": w["shift"], "lr": w["lr"]},
+        "sr_iters_per_s": 1e3 / ms_per_step,
+        "sampling_samples_per_s": n_samp / (samp_ms * 1e-3),
+        "phase_ms": {"sample_and_eloc": samp_ms, "sr_step": sr_ms},
+        "cg_iters_mean": float(np.mean(cg)),
+        "energy_last": energies[-1],
+        "kernel_ms": {"sample_call": sweep_ms, "sv_product": mv_ms},
+        "roofline": roof,
+    }
+    log("timed %d steps: %.2f ms/step; oracle baseline next" % (args.steps, ms_per_step))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, N, M, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * nqs.h - C ABI of libnqs, an MI355X (gfx950) implementation of the data-parallel hot
+ * path of variational Monte Carlo with a restricted-Boltzmann-machine quantum state, as
+ * described in the NetKet paper (Carleo et al., 2019), Sec. 2.2.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked (device) are HIP device pointers owned by the caller; the library
+ *    only borrows them for the duration of the call. Pointers marked (host) are host
+ *    memory. The library allocates device memory only for the small per-model tables
+ *    created in nqs_model_create, and for caches it keeps per model (see each call).
+ *  - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL = the null
+ *    stream), except where a call states it synchronises.
+ *  - Argument errors are detected on the host before any launch and returned as
+ *    NQS_EINVAL (nothing is launched). HIP launch/runtime errors return NQS_EDEVICE.
+ *  - A handle must not be used from two threads at once.
+ *  - Spins are int8, +1 (up) or -1 (down). Configuration arrays are row-major [n, N].
+ *  - RBM parameters are packed p = [a (N) | b (M) | W (M x N, row j, column i)], with
+ *    P = N + M + N*M entries, in the model's master precision: double for NQS_F64,
+ *    float for NQS_F32 and NQS_BF16; complex models interleave (re, im) pairs.
+ *  - Results that are per-configuration scalars (log psi, local energies, Jacobian
+ *    products) and the SR vectors are always double (complex: interleaved double
+ *    pairs), whatever the compute precision.
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NQS_OK = 0,
+  NQS_ENOTCONV = 1,     /* warning: CG stopped at cg_maxiter before reaching cg_tol */
+  NQS_EINVAL = -1,      /* bad argument: null pointer, size out of range, bad enum */
+  NQS_ENOMEM = -2,      /* device allocation failed, or workspace too small */
+  NQS_EDEVICE = -3,     /* HIP runtime or launch error */
+  NQS_ENONFINITE = -4,  /* a NaN/Inf was produced (energy, force or CG scalar) */
+  NQS_EUNSUPPORTED = -5 /* valid but not supported combination */
+} nqs_status;
+
+typedef enum { NQS_F64 = 0, NQS_F32 = 1, NQS_BF16 = 2 } nqs_prec;
+typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_hamiltonian;
+typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;
+
+/*
+ * Model description (host memory; everything is copied by nqs_model_create).
+ * Sec. 2.2.1: a graph of sites and bonds whose integer color selects the bond type;
+ * color 0 = nearest-neighbour bonds (coupling J[0]), color 1 = next-nearest (J[1]).
+ *  - NQS_TFIM:       H = -sum_c J[c] sum_{(i,j) in c} sz_i sz_j - h sum_i sx_i
+ *  - NQS_HEISENBERG: H = sum_c J[c] sum_{(i,j) in c} (sx sx + sy sy + sz sz)_{ij}
+ *    Pauli matrices throughout. With marshall != 0 the Hamiltonian is rotated by
+ *    prod_{sublattice[i] = 1} sz_i: the exchange element of bonds joining the two
+ *    sublattices changes sign (sublattice must then be given).
+ *  - move: NQS_MOVE_FLIP proposes single-spin flips at uniform sites; NQS_MOVE_EXCHANGE
+ *    swaps the spins of a uniform color-0 bond (conserves total magnetisation; chains
+ *    are initialised at zero magnetisation, so N must be even).
+ *  - n_hidden = M hidden units (alpha = M / N); is_complex selects complex parameters.
+ * Limits: 2 <= n_sites <= 1024, 1 <= n_hidden <= 2048, bonds within [0, n_sites),
+ * i != j, n_bonds[0] >= 1 for exchange moves.
+ */
+typedef struct {
+  int32_t n_sites;
+  int32_t n_hidden;
+  int32_t is_complex;
+  int32_t prec;                 /* nqs_prec */
+  int32_t n_bonds[2];
+  const int32_t *bonds[2];      /* host, [n_bonds[c]][2] site pairs; NULL when n_bonds[c] == 0 */
+  int32_t ham;                  /* nqs_hamiltonian */
+  double J[2];
+  double h;
+  int32_t marshall;
+  const int8_t *sublattice;     /* host [n_sites], 0/1; required when marshall != 0 */
+  int32_t move;                 /* nqs_move */
+} nqs_model_desc;
+
+typedef struct nqs_model nqs_model;
+
+/* Information returned by nqs_sr_step (host struct, filled before the call returns). */
+typedef struct {
+  int32_t cg_iters;        /* matrix-vector products performed */
+  int32_t converged;       /* 1 if ||r|| <= cg_tol * ||F|| */
+  double cg_resid;         /* final recursive residual ||r|| / ||F|| */
+  double energy_re, energy_im;  /* mean local energy */
+  double variance;         /* mean |E_loc - E|^2 */
+  double force_norm;       /* ||F||_2 */
+} nqs_sr_info;
+
+/* Lattice helper (Sec. 2.2.1, Hypercube graph): periodic L^ndim hypercube, ndim 1 or 2.
+ * Site s = x0 + L*x1. Color-0 bonds are listed site by site, dimension by dimension, as
+ * (s, s + e_d); color-1 (ndim = 2 and with_diagonals) as (s, s+ex+ey), (s, s+ex-ey).
+ * sublattice[s] = (x0 + x1) mod 2. Outputs are host arrays sized by the caller:
+ * bonds0 [ndim*L^ndim][2], bonds1 [2*L^2][2] (may be NULL without diagonals),
+ * sublattice [L^ndim]; n_bonds[2] receives the counts. Requires 3 <= L <= 1024. */
+nqs_status nqs_hypercube(int32_t L, int32_t ndim, int32_t with_diagonals, int32_t *bonds0,
+                         int32_t *bonds1, int8_t *sublattice, int32_t *n_bonds);
+
+/* Create a model handle: validates the description and uploads the bond tables. */
+nqs_status nqs_model_create(const nqs_model_desc *desc, nqs_model **out);
+void nqs_model_destroy(nqs_model *model);
+int64_t nqs_n_params(const nqs_model *model);
+
+/* Chain initialisation (Sec. 2.2.5 sampler set-up). chain_sigma (device) [n_chains, N]
+ * receives independent +/-1 spins (flip moves) or a uniformly random permutation of
+ * N/2 up and N/2 down spins (exchange moves), drawn from Philox4x32-10 with key = seed
+ * and counter (chain_offset + c, 0, site, 1). */
+nqs_status nqs_chain_init(nqs_model *model, int8_t *chain_sigma, int32_t n_chains,
+                          uint64_t seed, int32_t chain_offset, void *stream);
+
+/* Metropolis sampling of pi(sigma) = |psi|^2 / sum |psi|^2 (Sec. 2.2.5, Eq. 4).
+ * Every chain runs n_discard + n_sweeps sweeps of N proposals. Proposal `step` of sweep
+ * `sw` of chain c draws Philox4x32-10 with key = seed and counter
+ * (chain_offset + c, counter + sw, step, 0): word 0 picks the site (flip) or color-0
+ * bond (exchange) as floor(w0 * n / 2^32); words 1, 2 give u = (w1 * 2^21 + w2 >> 11)
+ * * 2^-53. Accept iff |psi'/psi|^2 >= 1 or u < |psi'/psi|^2 (decided in double). An
+ * exchange of equal spins is an identity move (not counted). After each of the last
+ * n_sweeps sweeps the configuration is written to samples[sweep][c][:].
+ *  params      (device) packed RBM parameters (master precision; see top)
+ *  chain_sigma (device) [n_chains, N] in: current chains, out: chains after the call
+ *  samples     (device) [n_sweeps, n_chains, N]
+ *  n_accepted  (device) int64 [n_chains] accepted proposals in this call (may be NULL)
+ *  eloc        (device) double/complex double [n_sweeps * n_chains] or NULL: if given,
+ *              the local energy of every recorded sample is computed in the same launch
+ *              from the chain's cached hidden-unit angles (same values as
+ *              nqs_local_energy on `samples`, up to rounding).
+ * Limits: n_chains >= 1, n_sweeps >= 1, n_discard >= 0, chain_offset >= 0. */
+nqs_status nqs_sample(nqs_model *model, const void *params, int8_t *chain_sigma,
+                      int32_t n_chains, int32_t n_sweeps, int32_t n_discard, uint64_t seed,
+                      uint64_t counter, int32_t chain_offset, int8_t *samples,
+                      int64_t *n_accepted, void *eloc, void *stream);
+
+/* log psi(sigma) = sum_i a_i sigma_i + sum_j ln cosh(theta_j), theta = W sigma + b
+ * (Sec. 2.2.2: RBM as a one-layer ln cosh network plus visible bias; the constant
+ * M ln 2 of prod_j 2 cosh is dropped). sigma (device) [n, N]; logpsi (device) [n]
+ * double or complex double (imaginary part defined modulo 2 pi). n >= 0. */
+nqs_status nqs_log_psi(nqs_model *model, const void *params, const int8_t *sigma, int64_t n,
+                       void *logpsi, void *stream);
+
+/* Local energy, Eq. 5: E_loc(sigma) = sum_sigma' <sigma|H|sigma'> psi(sigma')/psi(sigma)
+ * over the configurations connected to sigma. sigma (device) [n, N]; eloc (device) [n]
+ * double (real model) or complex double. n >= 0. */
+nqs_status nqs_local_energy(nqs_model *model, const void *params, const int8_t *sigma,
+                            int64_t n, void *eloc, void *stream);
+
+/* Jacobian products of O_sk = d log psi(sigma_s) / d p_k (Sec. 2.2.5, analytic RBM
+ * derivatives: O_a = sigma, O_b = tanh theta, O_W = tanh(theta) sigma):
+ *   vjp[k] = sum_s conj(O_sk) u[s]     (if u and vjp are both non-NULL)
+ *   jvp[s] = sum_k O_sk v[k]           (if v and jvp are both non-NULL)
+ * theta is recomputed from sigma (nothing is stored between calls). u, jvp: (device)
+ * [n]; v, vjp: (device) [P]; all double / complex double. The contractions run in the
+ * model precision (FP64, FP32 or BF16 inputs with FP32 accumulation). */
+nqs_status nqs_log_psi_grad(nqs_model *model, const void *params, const int8_t *sigma,
+                            int64_t n, const void *u, void *vjp, const void *v, void *jvp,
+                            void *stream);
+
+/* Device workspace (bytes) needed by nqs_sr_step for n samples. */
+size_t nqs_sr_workspace_bytes(nqs_model *model, int64_t n);
+
+/* One stochastic-reconfiguration update (Sec. 2.2.5; the parameter step of Eq. 2):
+ *   E = <E_loc>, F_k = <conj(O_k)(E_loc - E)>, S_kk' = <conj(O_k) O_k'> - <conj O_k><O_k'>
+ *   solve (S + diag_shift I) x = F by conjugate gradients in double (x0 = 0, stop when
+ *   ||r|| <= cg_tol ||F|| or after cg_maxiter products), S applied implicitly as
+ *   S v = O^dagger (O v - mean(O v)) / n, then params <- params - lr x.
+ * Real models use real arithmetic throughout. params (device) in/out; sigma (device)
+ * [n, N]; eloc (device) [n] double/complex double; workspace (device) of at least
+ * nqs_sr_workspace_bytes(model, n) bytes; info (host) may be NULL.
+ * Synchronises `stream` (the CG loop checks convergence on the host every few
+ * iterations). Returns NQS_ENOTCONV if cg_maxiter was reached, NQS_ENONFINITE if the
+ * energy, the force or a CG scalar is not finite (params are then left unchanged).
+ * Limits: n >= 2, cg_maxiter >= 1, cg_tol >= 0, diag_shift >= 0. */
+nqs_status nqs_sr_step(nqs_model *model, void *params, const int8_t *sigma, const void *eloc,
+                       int64_t n, double lr, double diag_shift, double cg_tol,
+                       int32_t cg_maxiter, void *workspace, size_t ws_bytes,
+                       nqs_sr_info *info, void *stream);
+
+const char *nqs_status_string(nqs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_H */

@@ -98,3 +98,25 @@ def vjp(params, sigma, u, n_sites, n_hidden):
     """(O^dagger u)_k = sum_s conj(O_sk) u_s  (no centering, no 1/n)."""
     O = log_derivatives(params, sigma, n_sites, n_hidden)
     return O.conj().T @ np.asarray(u)
+
+
+def vjp_entries(params, sigma, u, ks, n_sites, n_hidden):
+    """Selected entries k of O^dagger u, each from its own column of O (for checks at
+    sizes where the full [n, P] matrix does not fit): O[:, a_i] = sigma_i,
+    O[:, b_j] = tanh(theta_j), O[:, W_ji] = tanh(theta_j) sigma_i."""
+    a, b, W = unpack(params, n_sites, n_hidden)
+    s = np.asarray(sigma, dtype=np.float64)
+    u = np.asarray(u)
+    out = []
+    for k in ks:
+        k = int(k)
+        if k < n_sites:
+            col = s[:, k]
+        elif k < n_sites + n_hidden:
+            j = k - n_sites
+            col = np.tanh(b[j] + s @ W[j])
+        else:
+            j, i = divmod(k - n_sites - n_hidden, n_sites)
+            col = np.tanh(b[j] + s @ W[j]) * s[:, i]
+        out.append(np.sum(np.conj(col) * u))
+    return np.array(out)

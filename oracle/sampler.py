@@ -78,11 +78,11 @@ def metropolis_step(model, params, sigma, seed, chain_ids, sweep, step):
 
 
 def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain_offset=0,
-           record_ties=None):
+           record_ties=None, tie_margin=1e-12):
     """Run every chain for n_discard + n_sweeps sweeps of N proposals.
 
     Returns (samples [n_sweeps, C, N], chain_sigma_out [C, N], n_accepted [C]).
-    If ``record_ties`` is a list, each proposal with |u - exp(2 Re Delta)| < 1e-12 is
+    If ``record_ties`` is a list, each proposal with |u - exp(2 Re Delta)| < tie_margin is
     appended to it as (chain, sweep, step)."""
     sigma = np.array(chain_sigma, dtype=np.int8, copy=True)
     C, N = sigma.shape
@@ -95,7 +95,7 @@ def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain
             acc, two_re, u = metropolis_step(model, params, sigma, seed, chains, g, st)
             n_acc += acc
             if record_ties is not None:
-                near = np.abs(u - np.exp(np.minimum(two_re, 0.0))) < 1e-12
+                near = np.abs(u - np.exp(np.minimum(two_re, 0.0))) < tie_margin
                 for c in np.nonzero(near)[0]:
                     record_ties.append((int(chains[c]), g, st))
         if sw >= n_discard:

@@ -1,0 +1,318 @@
+"""Python binding of libnqs (argument marshalling only).
+
+Every function here checks shapes, dtypes and devices of torch tensors, then calls the C
+ABI declared in ``include/nqs.h`` with raw device pointers and the current HIP stream.
+All arithmetic of the VMC hot path runs in the library's HIP kernels. There is no CPU
+fallback: if ``libnqs.so`` is missing, :func:`load` raises.
+
+Names follow the C ABI (``nqs_sample``, ``nqs_local_energy``, ...); :class:`Model`
+offers the same calls as methods.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnqs.so")
+
+F64, F32, BF16 = 0, 1, 2
+TFIM, HEISENBERG = 0, 1
+MOVE_FLIP, MOVE_EXCHANGE = 0, 1
+OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
+
+_lib = None
+
+
+class NQSError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.nqs_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__("%s: %s (status %d)" % (where, msg, status))
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("n_sites", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+        ("is_complex", ctypes.c_int32), ("prec", ctypes.c_int32),
+        ("n_bonds", ctypes.c_int32 * 2), ("bonds", ctypes.c_void_p * 2),
+        ("ham", ctypes.c_int32), ("J", ctypes.c_double * 2), ("h", ctypes.c_double),
+        ("marshall", ctypes.c_int32), ("sublattice", ctypes.c_void_p), ("move", ctypes.c_int32),
+    ]
+
+
+class SRInfo(ctypes.Structure):
+    _fields_ = [
+        ("cg_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+        ("cg_resid", ctypes.c_double), ("energy_re", ctypes.c_double),
+        ("energy_im", ctypes.c_double), ("variance", ctypes.c_double),
+        ("force_norm", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def load(path=LIB_PATH):
+    """Load libnqs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libnqs.so not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "nqs_status_string": (ctypes.c_char_p, [i32]),
+        "nqs_hypercube": (i32, [i32, i32, i32, vp, vp, vp, vp]),
+        "nqs_model_create": (i32, [ctypes.POINTER(_Desc), ctypes.POINTER(vp)]),
+        "nqs_model_destroy": (None, [vp]),
+        "nqs_n_params": (i64, [vp]),
+        "nqs_chain_init": (i32, [vp, vp, i32, u64, i32, vp]),
+        "nqs_sample": (i32, [vp, vp, vp, i32, i32, i32, u64, u64, i32, vp, vp, vp, vp]),
+        "nqs_log_psi": (i32, [vp, vp, vp, i64, vp, vp]),
+        "nqs_local_energy": (i32, [vp, vp, vp, i64, vp, vp]),
+        "nqs_log_psi_grad": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
+        "nqs_sr_workspace_bytes": (ctypes.c_size_t, [vp, i64]),
+        "nqs_sr_step": (i32, [vp, vp, vp, vp, i64, f64, f64, f64, i32, vp, ctypes.c_size_t,
+                              ctypes.POINTER(SRInfo), vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
+            "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
+            "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step"]
+
+
+def _check(status, where, allow=(OK,)):
+    if status not in allow:
+        raise NQSError(status, where)
+    return status
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, name, dtype, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on the GPU" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return t
+
+
+def nqs_hypercube(L, ndim, with_diagonals=False):
+    """Bond lists (color 0, color 1) and sublattice parity of a periodic L^ndim lattice."""
+    load()
+    n = L ** ndim
+    b0 = np.zeros((max(1, ndim * n), 2), dtype=np.int32)
+    b1 = np.zeros((max(1, 2 * n), 2), dtype=np.int32)
+    sub = np.zeros(n, dtype=np.int8)
+    nb = np.zeros(2, dtype=np.int32)
+    _check(_lib.nqs_hypercube(L, ndim, int(bool(with_diagonals)), b0.ctypes.data, b1.ctypes.data,
+                              sub.ctypes.data, nb.ctypes.data), "nqs_hypercube")
+    return [b0[:nb[0]].copy(), b1[:nb[1]].copy()], sub
+
+
+class Model:
+    """Handle of one lattice model + RBM shape + compute precision (nqs_model_create)."""
+
+    def __init__(self, n_sites, n_hidden, bonds, ham=TFIM, J=(1.0, 0.0), h=1.0, marshall=False,
+                 sublattice=None, move=MOVE_FLIP, is_complex=False, prec=F64):
+        load()
+        self.n_sites, self.n_hidden = int(n_sites), int(n_hidden)
+        self.is_complex, self.prec = bool(is_complex), int(prec)
+        self.ham, self.move = int(ham), int(move)
+        self._bonds = [np.ascontiguousarray(np.asarray(b, dtype=np.int32).reshape(-1, 2)) for b in bonds]
+        while len(self._bonds) < 2:
+            self._bonds.append(np.zeros((0, 2), dtype=np.int32))
+        self._sub = None if sublattice is None else np.ascontiguousarray(np.asarray(sublattice, dtype=np.int8))
+        d = _Desc()
+        d.n_sites, d.n_hidden = self.n_sites, self.n_hidden
+        d.is_complex, d.prec = int(self.is_complex), self.prec
+        for c in range(2):
+            d.n_bonds[c] = self._bonds[c].shape[0]
+            d.bonds[c] = self._bonds[c].ctypes.data if self._bonds[c].shape[0] else None
+        d.ham = self.ham
+        d.J[0], d.J[1] = float(J[0]), float(J[1])
+        d.h = float(h)
+        d.marshall = int(bool(marshall))
+        d.sublattice = self._sub.ctypes.data if self._sub is not None else None
+        d.move = self.move
+        h_ = ctypes.c_void_p()
+        _check(_lib.nqs_model_create(ctypes.byref(d), ctypes.byref(h_)), "nqs_model_create")
+        self._h = h_
+        self.n_params = int(_lib.nqs_n_params(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.nqs_model_destroy(self._h)
+            self._h = None
+
+    # dtypes ---------------------------------------------------------------------------
+    @property
+    def param_dtype(self):
+        import torch
+        if self.prec == F64:
+            return torch.complex128 if self.is_complex else torch.float64
+        return torch.complex64 if self.is_complex else torch.float32
+
+    @property
+    def value_dtype(self):
+        import torch
+        return torch.complex128 if self.is_complex else torch.float64
+
+    # calls ----------------------------------------------------------------------------
+    def chain_init(self, chain_sigma, seed, chain_offset=0):
+        import torch
+        _need(chain_sigma, "chain_sigma", torch.int8)
+        C = chain_sigma.shape[0]
+        _need(chain_sigma, "chain_sigma", torch.int8, (C, self.n_sites))
+        _check(_lib.nqs_chain_init(self._h, _ptr(chain_sigma), C, seed, chain_offset, _stream()),
+               "nqs_chain_init")
+        return chain_sigma
+
+    def sample(self, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain_offset=0,
+               samples=None, n_accepted=None, eloc=None, with_eloc=False):
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        C = chain_sigma.shape[0]
+        _need(chain_sigma, "chain_sigma", torch.int8, (C, self.n_sites))
+        dev = chain_sigma.device
+        if samples is None:
+            samples = torch.empty((n_sweeps, C, self.n_sites), dtype=torch.int8, device=dev)
+        _need(samples, "samples", torch.int8, (n_sweeps, C, self.n_sites))
+        if n_accepted is not None:
+            _need(n_accepted, "n_accepted", torch.int64, (C,))
+        if with_eloc and eloc is None:
+            eloc = torch.empty(n_sweeps * C, dtype=self.value_dtype, device=dev)
+        if eloc is not None:
+            _need(eloc, "eloc", self.value_dtype, (n_sweeps * C,))
+        _check(_lib.nqs_sample(self._h, _ptr(params), _ptr(chain_sigma), C, n_sweeps, n_discard,
+                               seed, counter, chain_offset, _ptr(samples), _ptr(n_accepted),
+                               _ptr(eloc), _stream()), "nqs_sample")
+        return samples, eloc
+
+    def log_psi(self, params, sigma, out=None):
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        if out is None:
+            out = torch.empty(n, dtype=self.value_dtype, device=sigma.device)
+        _need(out, "logpsi", self.value_dtype, (n,))
+        _check(_lib.nqs_log_psi(self._h, _ptr(params), _ptr(sigma), n, _ptr(out), _stream()),
+               "nqs_log_psi")
+        return out
+
+    def local_energy(self, params, sigma, out=None):
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        if out is None:
+            out = torch.empty(n, dtype=self.value_dtype, device=sigma.device)
+        _need(out, "eloc", self.value_dtype, (n,))
+        _check(_lib.nqs_local_energy(self._h, _ptr(params), _ptr(sigma), n, _ptr(out), _stream()),
+               "nqs_local_energy")
+        return out
+
+    def log_psi_grad(self, params, sigma, u=None, v=None, vjp=None, jvp=None):
+        """vjp = O^dagger u (length P), jvp = O v (length n)."""
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        if u is not None:
+            _need(u, "u", self.value_dtype, (n,))
+            if vjp is None:
+                vjp = torch.empty(self.n_params, dtype=self.value_dtype, device=sigma.device)
+            _need(vjp, "vjp", self.value_dtype, (self.n_params,))
+        if v is not None:
+            _need(v, "v", self.value_dtype, (self.n_params,))
+            if jvp is None:
+                jvp = torch.empty(n, dtype=self.value_dtype, device=sigma.device)
+            _need(jvp, "jvp", self.value_dtype, (n,))
+        _check(_lib.nqs_log_psi_grad(self._h, _ptr(params), _ptr(sigma), n,
+                                     _ptr(u) if u is not None else None,
+                                     _ptr(vjp) if u is not None else None,
+                                     _ptr(v) if v is not None else None,
+                                     _ptr(jvp) if v is not None else None, _stream()),
+               "nqs_log_psi_grad")
+        return vjp, jvp
+
+    def sr_workspace_bytes(self, n):
+        return int(_lib.nqs_sr_workspace_bytes(self._h, n))
+
+    def sr_step(self, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None):
+        """One SR update of params in place; returns the info dict (cg_iters, energy, ...)."""
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        _need(eloc, "eloc", self.value_dtype, (n,))
+        nbytes = self.sr_workspace_bytes(n)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=sigma.device)
+        _need(workspace, "workspace", torch.uint8)
+        info = SRInfo()
+        st = _lib.nqs_sr_step(self._h, _ptr(params), _ptr(sigma), _ptr(eloc), n, float(lr),
+                              float(diag_shift), float(cg_tol), int(cg_maxiter), _ptr(workspace),
+                              workspace.numel(), ctypes.byref(info), _stream())
+        _check(st, "nqs_sr_step", allow=(OK, ENOTCONV))
+        d = info.as_dict()
+        d["status"] = st
+        return d
+
+
+# C-ABI-named module functions --------------------------------------------------------
+def nqs_model_create(**kw):
+    return Model(**kw)
+
+
+def nqs_chain_init(model, chain_sigma, seed, chain_offset=0):
+    return model.chain_init(chain_sigma, seed, chain_offset)
+
+
+def nqs_sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, **kw):
+    return model.sample(params, chain_sigma, n_sweeps, n_discard, seed, counter, **kw)
+
+
+def nqs_log_psi(model, params, sigma, out=None):
+    return model.log_psi(params, sigma, out)
+
+
+def nqs_local_energy(model, params, sigma, out=None):
+    return model.local_energy(params, sigma, out)
+
+
+def nqs_log_psi_grad(model, params, sigma, u=None, v=None, vjp=None, jvp=None):
+    return model.log_psi_grad(params, sigma, u=u, v=v, vjp=vjp, jvp=jvp)
+
+
+def nqs_sr_workspace_bytes(model, n):
+    return model.sr_workspace_bytes(n)
+
+
+def nqs_sr_step(model, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None):
+    return model.sr_step(params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace)

@@ -1,0 +1,312 @@
+// C ABI of libnqs: argument validation, model handles and dispatch to the kernels.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace {
+
+__global__ void k_zero(int64_t count, double *x) {
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < count;
+       k += int64_t(gridDim.x) * blockDim.x)
+    x[k] = 0.0;
+}
+
+inline unsigned grid_for(int64_t count) {
+  int64_t b = (count + 255) / 256;
+  return unsigned(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+nqs_status dev(hipError_t e) { return e == hipSuccess ? NQS_OK : NQS_EDEVICE; }
+
+int64_t n_params_of(const nqs_model *m) {
+  return int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+}
+
+nqs_status ensure_scratch(nqs_model *m, size_t bytes) {
+  if (m->scratch_bytes >= bytes) return NQS_OK;
+  if (m->d_scratch) {
+    if (hipDeviceSynchronize() != hipSuccess) return NQS_EDEVICE;
+    (void)hipFree(m->d_scratch);
+    m->d_scratch = nullptr;
+    m->scratch_bytes = 0;
+  }
+  if (hipMalloc(&m->d_scratch, bytes) != hipSuccess) return NQS_ENOMEM;
+  m->scratch_bytes = bytes;
+  return NQS_OK;
+}
+
+}  // namespace
+
+DevModel dev_model(const nqs_model *m) {
+  DevModel d;
+  d.N = m->N;
+  d.M = m->M;
+  d.B0 = m->B[0];
+  d.Btot = m->Btot;
+  d.ham = m->ham;
+  d.move = m->move;
+  d.h = m->h;
+  d.bonds = m->d_bonds;
+  d.bond_diag = m->d_bond_diag;
+  d.bond_off = m->d_bond_off;
+  return d;
+}
+
+extern "C" {
+
+const char *nqs_status_string(nqs_status s) {
+  switch (s) {
+    case NQS_OK: return "ok";
+    case NQS_ENOTCONV: return "conjugate gradients reached cg_maxiter before cg_tol";
+    case NQS_EINVAL: return "invalid argument";
+    case NQS_ENOMEM: return "out of device memory or workspace too small";
+    case NQS_EDEVICE: return "HIP runtime or launch error";
+    case NQS_ENONFINITE: return "non-finite energy, force or CG scalar";
+    case NQS_EUNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+nqs_status nqs_hypercube(int32_t L, int32_t ndim, int32_t with_diagonals, int32_t *bonds0,
+                         int32_t *bonds1, int8_t *sublattice, int32_t *n_bonds) {
+  if (L < 3 || L > 1024 || (ndim != 1 && ndim != 2) || !bonds0 || !sublattice || !n_bonds)
+    return NQS_EINVAL;
+  if (with_diagonals && (ndim != 2 || !bonds1)) return NQS_EINVAL;
+  const int n = ndim == 1 ? L : L * L;
+  int b0 = 0, b1 = 0;
+  for (int s = 0; s < n; ++s) {
+    const int x = s % L, y = ndim == 2 ? s / L : 0;
+    sublattice[s] = int8_t((x + y) % 2);
+    // +e_x
+    bonds0[2 * b0] = s;
+    bonds0[2 * b0 + 1] = (x + 1) % L + L * y;
+    ++b0;
+    if (ndim == 2) {
+      bonds0[2 * b0] = s;
+      bonds0[2 * b0 + 1] = x + L * ((y + 1) % L);
+      ++b0;
+      if (with_diagonals) {
+        bonds1[2 * b1] = s;
+        bonds1[2 * b1 + 1] = (x + 1) % L + L * ((y + 1) % L);
+        ++b1;
+        bonds1[2 * b1] = s;
+        bonds1[2 * b1 + 1] = (x + 1) % L + L * ((y + L - 1) % L);
+        ++b1;
+      }
+    }
+  }
+  n_bonds[0] = b0;
+  n_bonds[1] = b1;
+  return NQS_OK;
+}
+
+nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
+  if (!d || !out) return NQS_EINVAL;
+  *out = nullptr;
+  if (d->n_sites < 2 || d->n_sites > 1024 || d->n_hidden < 1 || d->n_hidden > 2048)
+    return NQS_EINVAL;
+  if (d->prec < NQS_F64 || d->prec > NQS_BF16) return NQS_EINVAL;
+  if (d->ham != NQS_TFIM && d->ham != NQS_HEISENBERG) return NQS_EINVAL;
+  if (d->move != NQS_MOVE_FLIP && d->move != NQS_MOVE_EXCHANGE) return NQS_EINVAL;
+  if (!isfinite(d->J[0]) || !isfinite(d->J[1]) || !isfinite(d->h)) return NQS_EINVAL;
+  for (int c = 0; c < 2; ++c) {
+    if (d->n_bonds[c] < 0 || d->n_bonds[c] > 8 * d->n_sites) return NQS_EINVAL;
+    if (d->n_bonds[c] > 0 && !d->bonds[c]) return NQS_EINVAL;
+    for (int b = 0; b < d->n_bonds[c]; ++b) {
+      int i = d->bonds[c][2 * b], k = d->bonds[c][2 * b + 1];
+      if (i < 0 || k < 0 || i >= d->n_sites || k >= d->n_sites || i == k) return NQS_EINVAL;
+    }
+  }
+  if (d->move == NQS_MOVE_EXCHANGE && (d->n_bonds[0] < 1 || d->n_sites % 2)) return NQS_EINVAL;
+  if (d->marshall && !d->sublattice) return NQS_EINVAL;
+  if (d->prec == NQS_BF16) return NQS_EUNSUPPORTED;
+
+  nqs_model *m = new (std::nothrow) nqs_model();
+  if (!m) return NQS_ENOMEM;
+  m->N = d->n_sites;
+  m->M = d->n_hidden;
+  m->is_complex = d->is_complex ? 1 : 0;
+  m->prec = d->prec;
+  m->ham = d->ham;
+  m->move = d->move;
+  m->marshall = d->marshall ? 1 : 0;
+  m->B[0] = d->n_bonds[0];
+  m->B[1] = d->n_bonds[1];
+  m->Btot = m->B[0] + m->B[1];
+  m->J[0] = d->J[0];
+  m->J[1] = d->J[1];
+  m->h = d->h;
+  m->need_flip = m->move == NQS_MOVE_FLIP || m->ham == NQS_TFIM;
+  m->need_bond = m->move == NQS_MOVE_EXCHANGE || m->ham == NQS_HEISENBERG;
+  if (hipGetDevice(&m->device) != hipSuccess) {
+    delete m;
+    return NQS_EDEVICE;
+  }
+
+  // bond lists with their diagonal and exchange coefficients
+  std::vector<int> bonds(2 * size_t(m->Btot > 0 ? m->Btot : 1));
+  std::vector<double> diag(m->Btot > 0 ? m->Btot : 1), off(m->Btot > 0 ? m->Btot : 1);
+  int q = 0;
+  for (int c = 0; c < 2; ++c) {
+    for (int b = 0; b < m->B[c]; ++b, ++q) {
+      const int i = d->bonds[c][2 * b], k = d->bonds[c][2 * b + 1];
+      bonds[2 * q] = i;
+      bonds[2 * q + 1] = k;
+      if (m->ham == NQS_TFIM) {
+        diag[q] = -m->J[c];
+        off[q] = 0.0;
+      } else {
+        double sgn = (m->marshall && d->sublattice[i] != d->sublattice[k]) ? -1.0 : 1.0;
+        diag[q] = m->J[c];
+        off[q] = 2.0 * m->J[c] * sgn;
+      }
+    }
+  }
+  const size_t nb = size_t(m->Btot > 0 ? m->Btot : 1);
+  bool ok = hipMalloc(&m->d_bonds, 2 * nb * sizeof(int)) == hipSuccess &&
+            hipMalloc(&m->d_bond_diag, nb * sizeof(double)) == hipSuccess &&
+            hipMalloc(&m->d_bond_off, nb * sizeof(double)) == hipSuccess;
+  if (ok)
+    ok = hipMemcpy(m->d_bonds, bonds.data(), 2 * nb * sizeof(int), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(m->d_bond_diag, diag.data(), nb * sizeof(double), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(m->d_bond_off, off.data(), nb * sizeof(double), hipMemcpyHostToDevice) ==
+             hipSuccess;
+
+  // parameter-derived tables, in Tables<T> member order
+  const size_t es = (use_double(m) ? 8 : 4) * (m->is_complex ? 2 : 1);
+  const size_t NM = size_t(m->N) * m->M, BM = size_t(m->Btot) * m->M;
+  size_t sizes[13] = {NM * es,
+                      size_t(m->M) * es,
+                      m->need_flip ? NM * es : 0,
+                      m->need_flip ? NM * es : 0,
+                      m->need_bond ? BM * es : 0,
+                      m->need_bond ? BM * es : 0,
+                      m->need_flip ? NM * es : 0,
+                      m->need_flip ? NM * es : 0,
+                      m->need_bond ? BM * es : 0,
+                      m->need_bond ? BM * es : 0,
+                      size_t(m->N) * 32,
+                      nb * 32,
+                      size_t(m->N) * 16};
+  size_t offs[13], total = 0;
+  for (int k = 0; k < 13; ++k) {
+    offs[k] = total;
+    total += (sizes[k] + 255) / 256 * 256;
+  }
+  if (ok) ok = hipMalloc(&m->d_tables, total) == hipSuccess;
+  if (!ok) {
+    nqs_model_destroy(m);
+    return NQS_ENOMEM;
+  }
+  m->tables_bytes = total;
+  for (int k = 0; k < 13; ++k) m->tab_ptrs[k] = sizes[k] ? (char *)m->d_tables + offs[k] : nullptr;
+  *out = m;
+  return NQS_OK;
+}
+
+void nqs_model_destroy(nqs_model *m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  if (m->d_bonds) (void)hipFree(m->d_bonds);
+  if (m->d_bond_diag) (void)hipFree(m->d_bond_diag);
+  if (m->d_bond_off) (void)hipFree(m->d_bond_off);
+  if (m->d_tables) (void)hipFree(m->d_tables);
+  if (m->d_scratch) (void)hipFree(m->d_scratch);
+  delete m;
+}
+
+int64_t nqs_n_params(const nqs_model *m) { return m ? n_params_of(m) : -1; }
+
+nqs_status nqs_chain_init(nqs_model *m, int8_t *chain_sigma, int32_t n_chains, uint64_t seed,
+                          int32_t chain_offset, void *stream) {
+  if (!m || !chain_sigma || n_chains < 1 || chain_offset < 0) return NQS_EINVAL;
+  return dev(launch_chain_init(m, chain_sigma, n_chains, seed, chain_offset,
+                               (hipStream_t)stream));
+}
+
+nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int32_t n_chains,
+                      int32_t n_sweeps, int32_t n_discard, uint64_t seed, uint64_t counter,
+                      int32_t chain_offset, int8_t *samples, int64_t *n_accepted, void *eloc,
+                      void *stream) {
+  if (!m || !params || !chain_sigma || !samples || n_chains < 1 || n_sweeps < 1 ||
+      n_discard < 0 || chain_offset < 0)
+    return NQS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_tables(m, params, st);
+  if (e == hipSuccess)
+    e = launch_sweep(m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter, chain_offset,
+                     samples, n_accepted, eloc, st);
+  return dev(e);
+}
+
+nqs_status nqs_log_psi(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                       void *logpsi, void *stream) {
+  if (!m || !params || n < 0 || (n > 0 && (!sigma || !logpsi))) return NQS_EINVAL;
+  if (n == 0) return NQS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_tables(m, params, st);
+  if (e == hipSuccess) e = launch_log_psi(m, sigma, n, logpsi, st);
+  return dev(e);
+}
+
+nqs_status nqs_local_energy(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                            void *eloc, void *stream) {
+  if (!m || !params || n < 0 || (n > 0 && (!sigma || !eloc))) return NQS_EINVAL;
+  if (n == 0) return NQS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_tables(m, params, st);
+  if (e == hipSuccess) e = launch_local_energy(m, sigma, n, eloc, st);
+  return dev(e);
+}
+
+nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                            const void *u, void *vjp, const void *v, void *jvp, void *stream) {
+  if (!m || !params || n < 0 || (n > 0 && !sigma)) return NQS_EINVAL;
+  const bool want_vjp = u && vjp, want_jvp = v && jvp;
+  if (!want_vjp && !want_jvp) return NQS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int cs = m->is_complex ? 2 : 1;
+  if (n == 0) {
+    if (want_vjp)
+      hipLaunchKernelGGL(k_zero, dim3(grid_for(n_params_of(m) * cs)), dim3(256), 0, st,
+                         n_params_of(m) * cs, (double *)vjp);
+    return dev(hipGetLastError());
+  }
+  nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
+  if (s != NQS_OK) return s;
+  hipError_t e = launch_tables(m, params, st);
+  if (e == hipSuccess && want_vjp) {
+    e = launch_vjp_partials(m, sigma, n, (const double *)u, m->d_scratch, nullptr, st);
+    if (e == hipSuccess) e = launch_vjp_reduce(m, n, m->d_scratch, (double *)vjp, nullptr, st);
+  }
+  if (e == hipSuccess && want_jvp) {
+    e = launch_prep_dir(m, v, m->d_scratch, st);
+    if (e == hipSuccess)
+      e = launch_jvp(m, sigma, n, m->d_scratch, (double *)jvp, nullptr, nullptr, st);
+  }
+  return dev(e);
+}
+
+size_t nqs_sr_workspace_bytes(nqs_model *m, int64_t n) {
+  if (!m || n < 2) return 0;
+  return sr_workspace_bytes(m, n);
+}
+
+nqs_status nqs_sr_step(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
+                       int64_t n, double lr, double diag_shift, double cg_tol,
+                       int32_t cg_maxiter, void *workspace, size_t ws_bytes,
+                       nqs_sr_info *info, void *stream) {
+  if (!m || !params || !sigma || !eloc || !workspace || n < 2 || cg_maxiter < 1 ||
+      !(cg_tol >= 0) || !(diag_shift >= 0) || !isfinite(lr))
+    return NQS_EINVAL;
+  return sr_step_impl(m, params, sigma, eloc, n, lr, diag_shift, cg_tol, cg_maxiter, workspace,
+                      ws_bytes, info, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// Device-side building blocks shared by the libnqs kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nqs.h"
+
+#define NQS_WAVE 64
+
+// ---------------------------------------------------------------------------------
+// Complex / real scalars. V<T, C> carries an imaginary part only when C is true; with
+// C false every operation below reduces to real arithmetic at compile time.
+// ---------------------------------------------------------------------------------
+template <typename T, bool C>
+struct V {
+  T re, im;
+};
+
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vmake(T re, T im) {
+  V<T, C> r;
+  r.re = re;
+  r.im = C ? im : T(0);
+  return r;
+}
+
+// load element idx of an array stored with stride 2 (complex, interleaved) or 1 (real)
+template <typename T, bool C, typename S>
+__device__ __forceinline__ V<T, C> vload(const S *p, int64_t idx) {
+  if constexpr (C)
+    return vmake<T, C>(T(p[2 * idx]), T(p[2 * idx + 1]));
+  else
+    return vmake<T, C>(T(p[idx]), T(0));
+}
+
+template <typename T, bool C, typename S>
+__device__ __forceinline__ void vstore(S *p, int64_t idx, V<T, C> v) {
+  if constexpr (C) {
+    p[2 * idx] = S(v.re);
+    p[2 * idx + 1] = S(v.im);
+  } else {
+    p[idx] = S(v.re);
+  }
+}
+
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vadd(V<T, C> a, V<T, C> b) {
+  return vmake<T, C>(a.re + b.re, C ? a.im + b.im : T(0));
+}
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vsub(V<T, C> a, V<T, C> b) {
+  return vmake<T, C>(a.re - b.re, C ? a.im - b.im : T(0));
+}
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vmul(V<T, C> a, V<T, C> b) {
+  if constexpr (C)
+    return vmake<T, C>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+  else
+    return vmake<T, C>(a.re * b.re, T(0));
+}
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vscale(V<T, C> a, T s) {
+  return vmake<T, C>(a.re * s, C ? a.im * s : T(0));
+}
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vconj(V<T, C> a) {
+  return vmake<T, C>(a.re, C ? -a.im : T(0));
+}
+template <typename T, bool C>
+__device__ __forceinline__ T vabs2(V<T, C> a) {
+  return C ? a.re * a.re + a.im * a.im : a.re * a.re;
+}
+template <typename T, bool C, typename U>
+__device__ __forceinline__ V<U, C> vcast(V<T, C> a) {
+  return vmake<U, C>(U(a.re), U(a.im));
+}
+
+// ---------------------------------------------------------------------------------
+// Elementary functions of a complex angle z = x + i y, written so that nothing
+// overflows for large |x| (e = exp(-2|x|) <= 1):
+//   tanh z   = [sgn(x)(1 - e^2) + i 2 e sin 2y] / (1 + e^2 + 2 e cos 2y)
+//   ln cosh z = |x| + log(1 + 2 e cos 2y + e^2)/2 - ln 2
+//               + i [sgn(x) y + atan2(-sgn(x) e sin 2y, 1 + e cos 2y)]   (mod 2 pi)
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ float fexp(float x) { return expf(x); }
+__device__ __forceinline__ double fexp(double x) { return exp(x); }
+__device__ __forceinline__ float flog1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double flog1p(double x) { return log1p(x); }
+__device__ __forceinline__ void fsincos(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void fsincos(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ float fatan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double fatan2(double y, double x) { return atan2(y, x); }
+
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vtanh(V<T, C> z) {
+  T ax = z.re < T(0) ? -z.re : z.re;
+  T sg = z.re < T(0) ? T(-1) : T(1);
+  T e = fexp(T(-2) * ax);
+  if constexpr (C) {
+    T s2, c2;
+    fsincos(T(2) * z.im, &s2, &c2);
+    T d = T(1) + e * e + T(2) * e * c2;
+    T inv = T(1) / d;
+    return vmake<T, C>(sg * (T(1) - e * e) * inv, T(2) * e * s2 * inv);
+  } else {
+    return vmake<T, C>(sg * (T(1) - e) / (T(1) + e), T(0));
+  }
+}
+
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vlncosh(V<T, C> z) {
+  const T ln2 = T(0.69314718055994530942);
+  T ax = z.re < T(0) ? -z.re : z.re;
+  T sg = z.re < T(0) ? T(-1) : T(1);
+  T e = fexp(T(-2) * ax);
+  if constexpr (C) {
+    T s2, c2;
+    fsincos(T(2) * z.im, &s2, &c2);
+    T re = ax + T(0.5) * flog1p(T(2) * e * c2 + e * e) - ln2;
+    T im = sg * z.im + fatan2(-sg * e * s2, T(1) + e * c2);
+    return vmake<T, C>(re, im);
+  } else {
+    return vmake<T, C>(ax + flog1p(e * e) - ln2 + T(0) * sg, T(0));
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53 and
+// 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85.
+// ---------------------------------------------------------------------------------
+struct Philox4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  Philox4 o;
+  o.w[0] = c0;
+  o.w[1] = c1;
+  o.w[2] = c2;
+  o.w[3] = c3;
+  return o;
+}
+
+// floor(w * n / 2^32)
+__device__ __forceinline__ int rng_index(uint32_t w, uint32_t n) {
+  return int((uint64_t(w) * uint64_t(n)) >> 32);
+}
+// (w1 * 2^21 + (w2 >> 11)) * 2^-53 in [0, 1)
+__device__ __forceinline__ double rng_uniform(uint32_t w1, uint32_t w2) {
+  uint64_t x = (uint64_t(w1) << 21) | uint64_t(w2 >> 11);
+  return double(x) * 0x1.0p-53;
+}
+
+enum { TAG_PROPOSAL = 0, TAG_INIT = 1 };
+
+// ---------------------------------------------------------------------------------
+// Wave-wide reductions (all 64 lanes receive the result).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, NQS_WAVE);
+  return v;
+}
+
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, NQS_WAVE);
+  return v;
+}
+
+// x = mant * 2^e with mant in [0.5, 1) (mant = 0 for x = 0)
+__device__ __forceinline__ float nfrexp(float x, int *e) { return frexpf(x, e); }
+__device__ __forceinline__ double nfrexp(double x, int *e) { return frexp(x, e); }
+__device__ __forceinline__ float nldexp(float x, int e) { return ldexpf(x, e); }
+__device__ __forceinline__ double nldexp(double x, int e) { return ldexp(x, e); }
+
+// product of positive reals kept as mantissa in [0.5, 1) and a base-2 exponent
+template <typename T>
+__device__ __forceinline__ void wave_prod_norm(T &mant, int &ex) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    T om = __shfl_xor(mant, m, NQS_WAVE);
+    int oe = __shfl_xor(ex, m, NQS_WAVE);
+    int e2;
+    mant = nfrexp(mant * om, &e2);
+    ex += oe + e2;
+  }
+}
+
+// rescale a complex running product by a power of two so that max(|re|, |im|) is in
+// [0.5, 1); the exponent moves to ex (exact)
+template <typename T, bool C>
+__device__ __forceinline__ void vrenorm(V<T, C> &p, int &ex) {
+  T a = p.re < T(0) ? -p.re : p.re;
+  if constexpr (C) {
+    T b = p.im < T(0) ? -p.im : p.im;
+    a = a > b ? a : b;
+  }
+  if (a > T(0)) {
+    int e;
+    nfrexp(a, &e);
+    p.re = nldexp(p.re, -e);
+    if constexpr (C) p.im = nldexp(p.im, -e);
+    ex += e;
+  }
+}
+
+// wave-local memory ordering for LDS written by one lane and read by others
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------------
+// Model data seen by the kernels.
+// ---------------------------------------------------------------------------------
+struct DevModel {
+  int N, M, B0, Btot, ham, move;
+  double h;
+  const int *bonds;        // [Btot][2], color-0 bonds first
+  const double *bond_diag; // [Btot] coefficient of sz_i sz_j on the diagonal
+  const double *bond_off;  // [Btot] exchange element (Heisenberg) incl. Marshall sign
+};
+
+// Parameter-derived tables, refreshed at the start of each call that needs them.
+// Element strides are 2 (complex) or 1 (real) in T; "a"-factors are complex double.
+template <typename T>
+struct Tables {
+  T *Wt;    // [N][M]    W transposed (site-major)
+  T *bv;    // [M]       hidden bias
+  T *fC;    // [N][M]    cosh(2 W_ji)           (single flip of site i)
+  T *fS;    // [N][M]    sinh(2 W_ji)
+  T *bC;    // [Btot][M] cosh(2 (W_ji - W_jk))  (exchange on bond (i, k))
+  T *bS;    // [Btot][M] sinh(2 (W_ji - W_jk))
+  T *fCt;   // [M][N]    hidden-major copies, for lanes over connected configurations
+  T *fSt;
+  T *bCt;   // [M][Btot]
+  T *bSt;
+  double *fa;  // [2][N]    exp(-2 s a_i),           s = +1 -> row 0, s = -1 -> row 1
+  double *ba;  // [2][Btot] exp(-2 s (a_i - a_k)),   s = sigma_i
+  double *av;  // [N]       a (double)
+};

@@ -1,0 +1,77 @@
+// Host-side internals of libnqs: the model handle and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+struct nqs_model {
+  int N, M, is_complex, prec, ham, move, marshall;
+  int B[2], Btot;
+  double J[2], h;
+  int device;
+  bool need_flip, need_bond;
+  // device tables owned by the handle
+  int *d_bonds = nullptr;          // [Btot][2]
+  double *d_bond_diag = nullptr;   // [Btot]
+  double *d_bond_off = nullptr;    // [Btot]
+  void *d_tables = nullptr;        // parameter-derived tables (see Tables<T>)
+  size_t tables_bytes = 0;
+  void *tab_ptrs[13] = {};         // sub-buffers of d_tables, in Tables<T> member order
+  // grow-only scratch for nqs_log_psi_grad
+  void *d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+// compute precision of the VALU kernels: double for NQS_F64, float otherwise
+inline bool use_double(const nqs_model *m) { return m->prec == NQS_F64; }
+
+DevModel dev_model(const nqs_model *m);
+
+// ---- launchers (return hipError_t of the launch) -----------------------------------
+hipError_t launch_tables(const nqs_model *m, const void *params, hipStream_t st);
+hipError_t launch_chain_init(const nqs_model *m, int8_t *sig, int n_chains, uint64_t seed,
+                             int chain_offset, hipStream_t st);
+hipError_t launch_sweep(const nqs_model *m, int8_t *chain_sigma, int n_chains, int n_sweeps,
+                        int n_discard, uint64_t seed, uint64_t counter, int chain_offset,
+                        int8_t *samples, int64_t *n_acc, void *eloc, hipStream_t st);
+hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,
+                               hipStream_t st);
+hipError_t launch_log_psi(const nqs_model *m, const int8_t *sigma, int64_t n, void *out,
+                          hipStream_t st);
+
+// ---- Jacobian products (grad.hip) ---------------------------------------------------
+// scratch layout for one JVP / VJP pair, sized by grad_scratch_bytes
+struct GradPlan {
+  int Mt;        // hidden 16-tiles (covering M hidden units)
+  int Nt;        // site 16-tiles per block (covering up to 256 sites)
+  int Nz;        // site chunks (grid z)
+  int splits;    // sample splits of the VJP
+  int64_t per_split;  // samples per split (multiple of 64)
+  int jchunks;   // hidden chunks of the JVP (grid y)
+  int64_t jvp_blocks; // sample tiles of 64 in the JVP
+};
+GradPlan grad_plan(const nqs_model *m, int64_t n);
+size_t grad_scratch_bytes(const nqs_model *m, int64_t n);
+
+// v (double, params layout) -> direction tables in compute precision, in scratch
+hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, hipStream_t st);
+// y[s] = (O v)[s] with the direction prepared by launch_prep_dir; ysum (may be NULL)
+// receives per-block partial sums of y (complex double) for the centering
+hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                      double *y, double *ysum_part, const int *skip, hipStream_t st);
+// raw partials of O^dagger u into scratch (u: complex/real double [n])
+hipError_t launch_vjp_partials(const nqs_model *m, const int8_t *sigma, int64_t n,
+                               const double *u, void *scratch, const int *skip,
+                               hipStream_t st);
+// out[k] = sum of partials (double, params layout)
+hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, double *out,
+                             const int *skip, hipStream_t st);
+const double *scratch_vjp_partials(const nqs_model *m, int64_t n, void *scratch);
+
+// ---- SR (sr.hip) --------------------------------------------------------------------
+size_t sr_workspace_bytes(const nqs_model *m, int64_t n);
+nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
+                        int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
+                        void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st);

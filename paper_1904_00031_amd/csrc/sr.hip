@@ -1,0 +1,407 @@
+// Stochastic reconfiguration (Sec. 2.2.5: SR with an iterative solver; parameter step of
+// Eq. 2). Given samples s and their local energies E_s:
+//   E = <E_loc>, F = O^dagger (E - E) / n, (S + lambda I) x = F,
+//   S v = O^dagger (O v - mean(O v)) / n = (O^dagger y - mean(y) O^dagger 1) / n,
+// solved by conjugate gradients with every vector and scalar in double; the matrix-vector
+// products run through the JVP/VJP kernels in the model's compute precision.
+// All reductions are two-level (per-block partials, then every consumer block sums the
+// partials in a fixed order), so results are bitwise reproducible run to run.
+#include <math.h>
+
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace {
+
+struct CGState {
+  double E[2];
+  double var;
+  double bnorm;
+  double rr[2];  // r^dagger r, double-buffered by iteration parity
+  double alpha;
+  double fnorm;
+  int iters;
+  int done;
+  int converged;
+  int nonfinite;
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// sum of count partials, identical in every thread of the block (fixed order)
+__device__ double block_sum(const double *part, int64_t count, int stride, double *lds) {
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < count; k += blockDim.x) s += part[k * stride];
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = lds[0];
+  __syncthreads();
+  return r;
+}
+
+// block-level sum of per-thread values -> returned to thread 0
+__device__ double block_reduce(double v, double *lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = lds[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// ---- statistics -----------------------------------------------------------------
+template <bool C>
+__global__ __launch_bounds__(256) void k_sum_e(int64_t n, const double *e, double *part) {
+  __shared__ double lds[256];
+  const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  double r = 0.0, i = 0.0;
+  if (s < n) {
+    r = C ? e[2 * s] : e[s];
+    i = C ? e[2 * s + 1] : 0.0;
+  }
+  r = block_reduce(r, lds);
+  i = block_reduce(i, lds);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r;
+    part[2 * blockIdx.x + 1] = i;
+  }
+}
+
+// u_s = E_s - E (E from the partials), per-block partial sums of |u|^2
+template <bool C>
+__global__ __launch_bounds__(256) void k_center_e(int64_t n, const double *e,
+                                                   const double *part, int64_t nparts,
+                                                   double *u, double *part2, CGState *st) {
+  __shared__ double lds[256];
+  const double Er = block_sum(part, nparts, 2, lds) / double(n);
+  const double Ei = block_sum(part + 1, nparts, 2, lds) / double(n);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->E[0] = Er;
+    st->E[1] = Ei;
+  }
+  const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  double v = 0.0;
+  if (s < n) {
+    double ur = (C ? e[2 * s] : e[s]) - Er;
+    double ui = C ? e[2 * s + 1] - Ei : 0.0;
+    if (C) {
+      u[2 * s] = ur;
+      u[2 * s + 1] = ui;
+    } else {
+      u[s] = ur;
+    }
+    v = ur * ur + ui * ui;
+  }
+  v = block_reduce(v, lds);
+  if (threadIdx.x == 0) part2[blockIdx.x] = v;
+}
+
+__global__ void k_fill(int64_t count, double *x, double val) {
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < count;
+       k += int64_t(gridDim.x) * blockDim.x)
+    x[k] = val;
+}
+
+// variance; F = g / n; x = 0; r = p = F; partial ||F||^2
+template <bool C>
+__global__ __launch_bounds__(256) void k_cg_init(int64_t P, int64_t n, const double *part2,
+                                                  int64_t nparts, const double *g, double *F,
+                                                  double *x, double *r, double *p,
+                                                  double *dpart, CGState *st) {
+  __shared__ double lds[256];
+  const int cs = C ? 2 : 1;
+  if (blockIdx.x == 0) {
+    double var = block_sum(part2, nparts, 1, lds) / double(n);
+    if (threadIdx.x == 0) st->var = var;
+  }
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P * cs;
+       k += int64_t(gridDim.x) * 256) {
+    double f = g[k] / double(n);
+    F[k] = f;
+    x[k] = 0.0;
+    r[k] = f;
+    p[k] = f;
+    acc += f * f;
+  }
+  acc = block_reduce(acc, lds);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_cg_start(const double *dpart, int64_t nparts,
+                                                  double tol, int maxiter, CGState *st) {
+  __shared__ double lds[256];
+  double rr = block_sum(dpart, nparts, 1, lds);
+  if (threadIdx.x == 0) {
+    st->rr[0] = rr;
+    st->rr[1] = rr;
+    st->bnorm = sqrt(rr);
+    st->fnorm = sqrt(rr);
+    st->iters = 0;
+    st->alpha = 0.0;
+    st->converged = 0;
+    st->nonfinite = !(finite(rr) && finite(st->E[0]) && finite(st->E[1]) && finite(st->var));
+    st->done = st->nonfinite || rr == 0.0 || maxiter <= 0;
+    if (rr == 0.0) st->converged = 1;
+  }
+}
+
+// Ap = (O^dagger y - ybar * O^dagger 1) / n + lambda p ; partial Re(p^dagger Ap)
+template <bool C>
+__global__ __launch_bounds__(256) void k_cg_ap(int64_t P, int64_t n, const double *g,
+                                               const double *o1, const double *ysum,
+                                               int64_t nys, const double *p, double lambda,
+                                               double *Ap, double *dpart, const CGState *st) {
+  if (st->done) return;
+  __shared__ double lds[256];
+  const double ybr = block_sum(ysum, nys, 2, lds) / double(n);
+  const double ybi = C ? block_sum(ysum + 1, nys, 2, lds) / double(n) : 0.0;
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
+       k += int64_t(gridDim.x) * 256) {
+    if (C) {
+      double gr = g[2 * k] - (ybr * o1[2 * k] - ybi * o1[2 * k + 1]);
+      double gi = g[2 * k + 1] - (ybr * o1[2 * k + 1] + ybi * o1[2 * k]);
+      double ar = gr / double(n) + lambda * p[2 * k];
+      double ai = gi / double(n) + lambda * p[2 * k + 1];
+      Ap[2 * k] = ar;
+      Ap[2 * k + 1] = ai;
+      acc += p[2 * k] * ar + p[2 * k + 1] * ai;
+    } else {
+      double ar = (g[k] - ybr * o1[k]) / double(n) + lambda * p[k];
+      Ap[k] = ar;
+      acc += p[k] * ar;
+    }
+  }
+  acc = block_reduce(acc, lds);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+}
+
+// alpha = rr / p^dagger Ap ; x += alpha p ; r -= alpha Ap ; partial r^dagger r
+__global__ __launch_bounds__(256) void k_cg_xr(int64_t Pc, const double *dpart, int64_t nparts,
+                                               int parity, double *x, double *r,
+                                               const double *p, const double *Ap,
+                                               double *rpart, CGState *st) {
+  if (st->done) return;
+  __shared__ double lds[256];
+  const double pAp = block_sum(dpart, nparts, 1, lds);
+  const double alpha = st->rr[parity] / pAp;
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Pc;
+       k += int64_t(gridDim.x) * 256) {
+    x[k] += alpha * p[k];
+    double rk = r[k] - alpha * Ap[k];
+    r[k] = rk;
+    acc += rk * rk;
+  }
+  acc = block_reduce(acc, lds);
+  if (threadIdx.x == 0) rpart[blockIdx.x] = acc;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->alpha = alpha;
+}
+
+// rr_new from partials; convergence; beta = rr_new / rr ; p = r + beta p
+__global__ __launch_bounds__(256) void k_cg_p(int64_t Pc, const double *rpart, int64_t nparts,
+                                              int parity, double tol, int maxiter,
+                                              const double *r, double *p, CGState *st) {
+  if (st->done) return;
+  __shared__ double lds[256];
+  const double rr_new = block_sum(rpart, nparts, 1, lds);
+  const double rr = st->rr[parity];
+  const double beta = rr_new / rr;
+  const int iters = st->iters + 1;
+  const bool conv = sqrt(rr_new) <= tol * st->bnorm;
+  const bool bad = !(finite(rr_new) && finite(st->alpha));
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Pc;
+       k += int64_t(gridDim.x) * 256)
+    p[k] = r[k] + beta * p[k];
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rr[parity ^ 1] = rr_new;
+    st->iters = iters;
+    st->converged = conv;
+    st->nonfinite = bad;
+    st->done = conv || bad || iters >= maxiter;
+  }
+}
+
+template <typename PT>
+__global__ void k_update(int64_t Pc, PT *params, const double *x, double lr) {
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < Pc;
+       k += int64_t(gridDim.x) * blockDim.x)
+    params[k] = PT(double(params[k]) - lr * x[k]);
+}
+
+struct SRLayout {
+  size_t grad, y, ysum, u, e_part, e_part2, o1, g, F, x, r, p, Ap, dpart, rpart, state, total;
+};
+
+SRLayout sr_layout(const nqs_model *m, int64_t n) {
+  const int cs = m->is_complex ? 2 : 1;
+  const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+  const int64_t nb = cdiv(n, 256);
+  const int64_t pb = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
+  SRLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  L.grad = take(grad_scratch_bytes(m, n));
+  L.y = take(size_t(n) * cs * 8);
+  L.ysum = take(size_t(nb) * 16);
+  L.u = take(size_t(n) * cs * 8);
+  L.e_part = take(size_t(nb) * 16);
+  L.e_part2 = take(size_t(nb) * 8);
+  L.o1 = take(size_t(P) * cs * 8);
+  L.g = take(size_t(P) * cs * 8);
+  L.F = take(size_t(P) * cs * 8);
+  L.x = take(size_t(P) * cs * 8);
+  L.r = take(size_t(P) * cs * 8);
+  L.p = take(size_t(P) * cs * 8);
+  L.Ap = take(size_t(P) * cs * 8);
+  L.dpart = take(size_t(pb) * 8);
+  const int64_t cb = cdiv(P * cs, 256) < 4096 ? cdiv(P * cs, 256) : 4096;
+  L.rpart = take(size_t(cb) * 8);
+  L.state = take(sizeof(CGState));
+  L.total = off;
+  return L;
+}
+
+#define HIPTRY(x)                             \
+  do {                                        \
+    hipError_t e__ = (x);                     \
+    if (e__ != hipSuccess) return NQS_EDEVICE; \
+  } while (0)
+
+template <bool C>
+__global__ void k_ones(int64_t n, double *u) {
+  for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < n;
+       s += int64_t(gridDim.x) * blockDim.x) {
+    if (C) {
+      u[2 * s] = 1.0;
+      u[2 * s + 1] = 0.0;
+    } else {
+      u[s] = 1.0;
+    }
+  }
+}
+
+inline unsigned grid_for(int64_t count) {
+  int64_t b = cdiv(count, 256);
+  return unsigned(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+template <bool C>
+nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
+                   int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
+                   void *ws, nqs_sr_info *info, hipStream_t st) {
+  SRLayout L = sr_layout(m, n);
+  char *b = (char *)ws;
+  auto D = [&](size_t off) { return (double *)(b + off); };
+  CGState *state = (CGState *)(b + L.state);
+  void *grad = b + L.grad;
+  const int cs = C ? 2 : 1;
+  const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+  const int64_t Pc = P * cs;
+  const int64_t nb = cdiv(n, 256);
+  const int64_t pblocks = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
+  const int64_t cblocks = cdiv(Pc, 256) < 4096 ? cdiv(Pc, 256) : 4096;
+
+  HIPTRY(launch_tables(m, params, st));
+  // mean energy, centred energies u = E_loc - E, variance partials
+  hipLaunchKernelGGL((k_sum_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
+                     (const double *)eloc, D(L.e_part));
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL((k_center_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
+                     (const double *)eloc, D(L.e_part), nb, D(L.u), D(L.e_part2), state);
+  HIPTRY(hipGetLastError());
+  // O^dagger 1 (centring of S v), then g = O^dagger u (force numerator)
+  hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, D(L.y));
+  HIPTRY(hipGetLastError());
+  HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, nullptr, st));
+  HIPTRY(launch_vjp_reduce(m, n, grad, D(L.o1), nullptr, st));
+  HIPTRY(launch_vjp_partials(m, sigma, n, D(L.u), grad, nullptr, st));
+  HIPTRY(launch_vjp_reduce(m, n, grad, D(L.g), nullptr, st));
+  hipLaunchKernelGGL((k_cg_init<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, P, n,
+                     D(L.e_part2), nb, D(L.g), D(L.F), D(L.x), D(L.r), D(L.p), D(L.dpart),
+                     state);
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, st, D(L.dpart), pblocks, cg_tol,
+                     cg_maxiter, state);
+  HIPTRY(hipGetLastError());
+
+  CGState hs;
+  const int check_every = 8;
+  int launched = 0;
+  const int *skip = &state->done;
+  while (true) {
+    HIPTRY(hipMemcpyAsync(&hs, state, sizeof(CGState), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (hs.done || launched >= cg_maxiter) break;
+    const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
+    for (int q = 0; q < batch; ++q, ++launched) {
+      const int parity = launched & 1;
+      HIPTRY(launch_prep_dir(m, D(L.p), grad, st));
+      HIPTRY(launch_jvp(m, sigma, n, grad, D(L.y), D(L.ysum), skip, st));
+      HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, st));
+      HIPTRY(launch_vjp_reduce(m, n, grad, D(L.g), skip, st));
+      hipLaunchKernelGGL((k_cg_ap<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, P, n, D(L.g),
+                         D(L.o1), D(L.ysum), nb, D(L.p), diag_shift, D(L.Ap), D(L.dpart),
+                         state);
+      HIPTRY(hipGetLastError());
+      hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, st, Pc, D(L.dpart),
+                         pblocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+      HIPTRY(hipGetLastError());
+      hipLaunchKernelGGL(k_cg_p, dim3(unsigned(cblocks)), dim3(256), 0, st, Pc, D(L.rpart),
+                         cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p), state);
+      HIPTRY(hipGetLastError());
+    }
+  }
+  const bool nonfinite = hs.nonfinite || !std::isfinite(hs.E[0]) || !std::isfinite(hs.var);
+  if (!nonfinite) {
+    if (use_double(m))
+      hipLaunchKernelGGL(k_update<double>, dim3(grid_for(Pc)), dim3(256), 0, st, Pc,
+                         (double *)params, (const double *)D(L.x), lr);
+    else
+      hipLaunchKernelGGL(k_update<float>, dim3(grid_for(Pc)), dim3(256), 0, st, Pc,
+                         (float *)params, (const double *)D(L.x), lr);
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+  }
+  if (info) {
+    info->cg_iters = hs.iters;
+    info->converged = hs.converged;
+    info->cg_resid = hs.bnorm > 0 ? sqrt(hs.rr[hs.iters & 1]) / hs.bnorm : 0.0;
+    info->energy_re = hs.E[0];
+    info->energy_im = hs.E[1];
+    info->variance = hs.var;
+    info->force_norm = hs.fnorm;
+  }
+  if (nonfinite) return NQS_ENONFINITE;
+  return hs.converged ? NQS_OK : NQS_ENOTCONV;
+}
+
+}  // namespace
+
+size_t sr_workspace_bytes(const nqs_model *m, int64_t n) { return sr_layout(m, n).total; }
+
+nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
+                        int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
+                        void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st) {
+  if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
+  return m->is_complex ? sr_impl<true>(m, params, sigma, eloc, n, lr, diag_shift, cg_tol,
+                                       cg_maxiter, ws, info, st)
+                       : sr_impl<false>(m, params, sigma, eloc, n, lr, diag_shift, cg_tol,
+                                        cg_maxiter, ws, info, st);
+}

@@ -1,0 +1,59 @@
+"""Parity cases: one lattice model + RBM shape + precision, built twice - once as a
+library handle, once as an oracle model - from the same description."""
+import numpy as np
+
+import synth
+from oracle import hamiltonian as oh
+from oracle import lattice as ol
+
+# name: (L, ndim, diagonals, ham, J, h, marshall, move, complex, prec, M)
+# prec: 0 = FP64, 1 = FP32
+CASES = {
+    # 1D TFIM, N = 10, real FP64 RBM, alpha = 1
+    "tfim10_real_f64": (10, 1, False, 0, (1.0, 0.0), 1.0, False, 0, False, 0, 10),
+    # 1D Heisenberg, N = 40, Marshall sign, exchange moves, complex FP32, alpha = 2
+    "heis40_cplx_f32": (40, 1, False, 1, (1.0, 0.0), 0.0, True, 1, True, 1, 80),
+    "heis40_cplx_f64": (40, 1, False, 1, (1.0, 0.0), 0.0, True, 1, True, 0, 80),
+    # 2D J1-J2, 4x4, J2 = 0.5, complex, alpha = 4
+    "j1j2_4x4_cplx_f64": (4, 2, True, 1, (1.0, 0.5), 0.0, True, 1, True, 0, 64),
+    "j1j2_4x4_cplx_f32": (4, 2, True, 1, (1.0, 0.5), 0.0, True, 1, True, 1, 64),
+    # ragged sizes: N = 37 ring, M = 74; 5x5 TFIM with a J2 term
+    "tfim37_real_f32": (37, 1, False, 0, (1.0, 0.0), 0.8, False, 0, False, 1, 74),
+    "tfim37_cplx_f64": (37, 1, False, 0, (1.0, 0.0), 1.3, False, 0, True, 0, 74),
+    "tfim5x5_j2_real_f64": (5, 2, True, 0, (1.0, -0.3), 1.1, False, 0, False, 0, 50),
+    # Heisenberg without Marshall rotation, single flips, real FP64
+    "heis12_real_f64_flip": (12, 1, False, 1, (1.0, 0.0), 0.0, False, 0, False, 0, 36),
+}
+
+TOL = {0: 1e-10, 1: 1e-5}
+
+
+def build(nqs, name):
+    L, ndim, diag, ham, J, h, marshall, move, cplx, prec, M = CASES[name]
+    bonds, sub = nqs.nqs_hypercube(L, ndim, diag)
+    N = L ** ndim
+    lib_model = nqs.Model(N, M, bonds, ham=ham, J=J, h=h, marshall=marshall, sublattice=sub,
+                          move=move, is_complex=cplx, prec=prec)
+    ob, osub = ol.hypercube(L, ndim, with_diagonals=diag)
+    orc = oh.Model(N, M, ob, ham=ham, J=J, h=h, marshall=marshall, sublattice=osub, move=move,
+                   is_complex=cplx)
+    return lib_model, orc
+
+
+def params(name, sigma=0.1, seed=1234):
+    """(numpy params exactly representable in the case's precision, torch dtype)."""
+    L, ndim, diag, ham, J, h, marshall, move, cplx, prec, M = CASES[name]
+    N = L ** ndim
+    p = synth.rbm_params(N, M, cplx, sigma=sigma, seed=seed)
+    if prec == 1:
+        p = p.astype(np.complex64 if cplx else np.float32)
+    return p
+
+
+def configs(name, n, seed):
+    L, ndim, diag, ham, J, h, marshall, move, cplx, prec, M = CASES[name]
+    return synth.spin_configs(n, L ** ndim, seed, zero_magnetisation=(move == 1))
+
+
+def tol(name):
+    return TOL[CASES[name][9]]

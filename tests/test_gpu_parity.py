@@ -1,0 +1,217 @@
+"""GPU parity: every entry point of libnqs against the FP64 oracle on the same seeded
+inputs, element by element. Tolerances: 1e-10 relative for FP64 models, 1e-5 relative
+for FP32 models (scaled by the magnitude of the compared vector); integer results
+(chains, samples, lattices) bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import cases
+from oracle import hamiltonian as oh, rbm as orbm, sampler as osamp, sr as osr
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+ALL = list(cases.CASES)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def wrap(d):
+    return np.angle(np.exp(1j * d))
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_log_psi(lib, name):
+    m, om = cases.build(lib, name)
+    p = cases.params(name, sigma=0.2)
+    s = cases.configs(name, 301, seed=5)
+    got = m.log_psi(to_dev(p), to_dev(s)).cpu().numpy()
+    exp = orbm.log_psi(p.astype(np.complex128 if m.is_complex else np.float64), s, om.n_sites, om.n_hidden)
+    t = cases.tol(name)
+    assert np.all(np.abs(np.real(got) - np.real(exp)) <= t * np.maximum(1.0, np.abs(np.real(exp))))
+    if m.is_complex:
+        assert np.all(np.abs(wrap(np.imag(got) - np.imag(exp))) <= t * np.maximum(1.0, np.abs(np.imag(exp))))
+
+
+@pytest.mark.parametrize("name", ALL)
+@pytest.mark.parametrize("sigma", [0.01, 0.3])
+def test_local_energy(lib, name, sigma):
+    m, om = cases.build(lib, name)
+    p = cases.params(name, sigma=sigma, seed=11)
+    s = cases.configs(name, 203, seed=6)
+    got = m.local_energy(to_dev(p), to_dev(s)).cpu().numpy()
+    exp = oh.local_energy(om, p.astype(np.complex128 if m.is_complex else np.float64), s)
+    scale = max(1.0, np.abs(exp).max())
+    err = np.abs(got - exp).max()
+    assert err <= cases.tol(name) * scale, (err, scale)
+
+
+def test_local_energy_empty_and_single(lib):
+    m, om = cases.build(lib, "heis40_cplx_f64")
+    p = to_dev(cases.params("heis40_cplx_f64"))
+    empty = torch.empty((0, 40), dtype=torch.int8, device=DEV)
+    assert m.local_energy(p, empty).numel() == 0
+    s = cases.configs("heis40_cplx_f64", 1, seed=1)
+    got = m.local_energy(p, to_dev(s)).cpu().numpy()
+    exp = oh.local_energy(om, p.cpu().numpy(), s)
+    assert np.abs(got - exp).max() <= 1e-10 * max(1.0, np.abs(exp).max())
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_jvp_vjp(lib, name):
+    m, om = cases.build(lib, name)
+    p = cases.params(name, sigma=0.2, seed=21)
+    n = 517
+    s = cases.configs(name, n, seed=7)
+    rng = np.random.default_rng(3)
+    P = m.n_params
+    if m.is_complex:
+        u = rng.normal(size=n) + 1j * rng.normal(size=n)
+        v = rng.normal(size=P) + 1j * rng.normal(size=P)
+    else:
+        u = rng.normal(size=n)
+        v = rng.normal(size=P)
+    vjp, jvp = m.log_psi_grad(to_dev(p), to_dev(s), u=to_dev(u), v=to_dev(v))
+    pe = p.astype(np.complex128 if m.is_complex else np.float64)
+    O = orbm.log_derivatives(pe, s, om.n_sites, om.n_hidden)
+    if not m.is_complex:
+        O = O.real
+    ej = O @ v
+    ev = O.conj().T @ u
+    t = cases.tol(name)
+    assert np.abs(jvp.cpu().numpy() - ej).max() <= t * np.abs(ej).max()
+    assert np.abs(vjp.cpu().numpy() - ev).max() <= t * np.abs(ev).max()
+
+
+@pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f64", "j1j2_4x4_cplx_f64", "tfim37_cplx_f64"])
+def test_chain_init_bit_exact(lib, name):
+    m, om = cases.build(lib, name)
+    C = 133
+    ch = torch.empty((C, om.n_sites), dtype=torch.int8, device=DEV)
+    m.chain_init(ch, seed=99, chain_offset=5)
+    exp = osamp.init_chains(om, C, seed=99, chain_offset=5)
+    assert np.array_equal(ch.cpu().numpy(), exp)
+
+
+def _compare_chains(got, exp, ties, n_sweeps):
+    """Bit-exact, except that a chain may diverge after a recorded near-tie."""
+    if np.array_equal(got, exp):
+        return 0
+    diverged = 0
+    for c in range(got.shape[1]):
+        bad = np.nonzero(np.any(got[:, c] != exp[:, c], axis=1))[0]
+        if bad.size:
+            first = bad[0]
+            assert any(tc == c and sw <= first for tc, sw, _ in ties), (c, first)
+            diverged += 1
+    return diverged
+
+
+@pytest.mark.parametrize("name,margin", [("tfim10_real_f64", 1e-12), ("heis40_cplx_f64", 1e-12),
+                                         ("j1j2_4x4_cplx_f64", 1e-12), ("tfim37_cplx_f64", 1e-12),
+                                         ("heis40_cplx_f32", 1e-4), ("tfim37_real_f32", 1e-4)])
+def test_sampling_matches_oracle(lib, name, margin):
+    m, om = cases.build(lib, name)
+    p = cases.params(name, sigma=0.25, seed=31)
+    C, n_sweeps, n_discard = 24, 6, 3
+    ch = torch.empty((C, om.n_sites), dtype=torch.int8, device=DEV)
+    m.chain_init(ch, seed=1234)
+    init = ch.cpu().numpy().copy()
+    nacc = torch.zeros(C, dtype=torch.int64, device=DEV)
+    smp, _ = m.sample(to_dev(p), ch, n_sweeps, n_discard, seed=1234, counter=17, n_accepted=nacc)
+    ties = []
+    exp, last, nacc_o = osamp.sample(om, p.astype(np.complex128 if m.is_complex else np.float64),
+                                     init, n_sweeps, n_discard, seed=1234, counter=17,
+                                     record_ties=ties, tie_margin=margin)
+    got = smp.cpu().numpy()
+    diverged = _compare_chains(got, exp, ties, n_sweeps)
+    if diverged == 0:
+        assert np.array_equal(ch.cpu().numpy(), last)
+        assert np.array_equal(nacc.cpu().numpy(), nacc_o)
+
+
+def test_sampling_resume_is_bit_exact(lib):
+    """Two calls of 3 sweeps (counter advanced) equal one call of 6 sweeps."""
+    m, om = cases.build(lib, "heis40_cplx_f64")
+    p = to_dev(cases.params("heis40_cplx_f64", sigma=0.2))
+    ch1 = torch.empty((40, 40), dtype=torch.int8, device=DEV)
+    m.chain_init(ch1, seed=5)
+    ch2 = ch1.clone()
+    a, _ = m.sample(p, ch1, 6, 0, seed=5, counter=100)
+    b1, _ = m.sample(p, ch2, 3, 0, seed=5, counter=100)
+    b2, _ = m.sample(p, ch2, 3, 0, seed=5, counter=103)
+    assert torch.equal(a, torch.cat([b1, b2]))
+    assert torch.equal(ch1, ch2)
+
+
+@pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f32", "heis40_cplx_f64", "j1j2_4x4_cplx_f64"])
+def test_fused_local_energy_matches_oracle(lib, name):
+    m, om = cases.build(lib, name)
+    p = cases.params(name, sigma=0.2, seed=41)
+    C = 37
+    ch = torch.empty((C, om.n_sites), dtype=torch.int8, device=DEV)
+    m.chain_init(ch, seed=3)
+    smp, el = m.sample(to_dev(p), ch, 3, 2, seed=3, counter=0, with_eloc=True)
+    flat = smp.reshape(-1, om.n_sites).cpu().numpy()
+    exp = oh.local_energy(om, p.astype(np.complex128 if m.is_complex else np.float64), flat)
+    scale = max(1.0, np.abs(exp).max())
+    assert np.abs(el.cpu().numpy() - exp).max() <= cases.tol(name) * scale
+
+
+@pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f64", "j1j2_4x4_cplx_f64", "tfim5x5_j2_real_f64"])
+def test_sr_step_fixed_iterations(lib, name):
+    """Both sides run exactly k CG products (tol = 0): energy, variance and the updated
+    parameters agree to 1e-9 (FP64 CG, FP64 matrix-vector products)."""
+    m, om = cases.build(lib, name)
+    p = cases.params(name, sigma=0.1, seed=51)
+    n = 700
+    s = cases.configs(name, n, seed=8)
+    pe = p.astype(np.complex128 if m.is_complex else np.float64)
+    el = oh.local_energy(om, pe, s)
+    pt = to_dev(p.copy())
+    info = m.sr_step(pt, to_dev(s), to_dev(el), lr=0.05, diag_shift=0.01, cg_tol=0.0, cg_maxiter=12)
+    p_new, info_o = osr.sr_step(om, pe, s, el, lr=0.05, diag_shift=0.01, cg_tol=0.0, cg_maxiter=12)
+    assert info["cg_iters"] == info_o["iters"] == 12
+    E = info_o["energy"]
+    assert abs(info["energy_re"] - np.real(E)) <= 1e-10 * max(1, abs(E))
+    assert abs(info["variance"] - info_o["variance"]) <= 1e-9 * max(1, info_o["variance"])
+    assert abs(info["force_norm"] - np.linalg.norm(info_o["force"])) <= 1e-9 * np.linalg.norm(info_o["force"])
+    dx = pt.cpu().numpy() - p_new
+    assert np.abs(dx).max() <= 1e-9 * np.abs(p_new - pe).max()
+
+
+@pytest.mark.parametrize("name", ["heis40_cplx_f32", "j1j2_4x4_cplx_f32", "tfim37_real_f32"])
+def test_sr_step_fp32_products(lib, name):
+    """FP32 matrix-vector products inside the FP64 CG: the step agrees with the FP64
+    oracle to 1e-4 of its size (FP32 rounding, amplified by at most the condition number
+    of S + 0.01 I over 12 iterations)."""
+    m, om = cases.build(lib, name)
+    p = cases.params(name, sigma=0.1, seed=52)
+    n = 640
+    s = cases.configs(name, n, seed=9)
+    pe = p.astype(np.complex128 if m.is_complex else np.float64)
+    el = oh.local_energy(om, pe, s)
+    pt = to_dev(p.copy())
+    info = m.sr_step(pt, to_dev(s), to_dev(el), lr=0.05, diag_shift=0.01, cg_tol=0.0, cg_maxiter=12)
+    p_new, info_o = osr.sr_step(om, pe, s, el, lr=0.05, diag_shift=0.01, cg_tol=0.0, cg_maxiter=12)
+    step_o = p_new - pe
+    step_g = pt.cpu().numpy().astype(pe.dtype) - pe
+    assert np.abs(step_g - step_o).max() <= 1e-4 * np.abs(step_o).max() + 1e-7
+
+
+def test_sr_step_converged_and_notconv(lib):
+    m, om = cases.build(lib, "tfim10_real_f64")
+    p = cases.params("tfim10_real_f64", sigma=0.1, seed=53)
+    s = cases.configs("tfim10_real_f64", 400, seed=10)
+    el = oh.local_energy(om, p, s)
+    pt = to_dev(p.copy())
+    info = m.sr_step(pt, to_dev(s), to_dev(el), lr=0.05, diag_shift=0.01, cg_tol=1e-10, cg_maxiter=500)
+    p_new, info_o = osr.sr_step(om, p, s, el, lr=0.05, diag_shift=0.01, cg_tol=1e-10, cg_maxiter=500)
+    assert info["converged"] == 1 and abs(info["cg_iters"] - info_o["iters"]) <= 1
+    assert np.abs(pt.cpu().numpy() - p_new).max() <= 1e-7 * np.abs(p_new - p).max()
+    pt2 = to_dev(p.copy())
+    info2 = m.sr_step(pt2, to_dev(s), to_dev(el), lr=0.05, diag_shift=0.01, cg_tol=1e-14, cg_maxiter=2)
+    assert info2["status"] == 1 and info2["converged"] == 0 and info2["cg_iters"] == 2
