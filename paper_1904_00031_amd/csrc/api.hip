@@ -146,6 +146,13 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
     delete m;
     return NQS_EDEVICE;
   }
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device) ==
+            hipSuccess &&
+        lds > 0)
+      m->max_lds = lds;
+  }
 
   // bond lists with their diagonal and exchange coefficients
   std::vector<int> bonds(2 * size_t(m->Btot > 0 ? m->Btot : 1));
@@ -181,7 +188,7 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
   // parameter-derived tables, in Tables<T> member order
   const size_t es = (use_double(m) ? 8 : 4) * (m->is_complex ? 2 : 1);
   const size_t NM = size_t(m->N) * m->M, BM = size_t(m->Btot) * m->M;
-  size_t sizes[13] = {NM * es,
+  size_t sizes[14] = {NM * es,
                       size_t(m->M) * es,
                       m->need_flip ? NM * es : 0,
                       m->need_flip ? NM * es : 0,
@@ -193,9 +200,10 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
                       m->need_bond ? BM * es : 0,
                       size_t(m->N) * 32,
                       nb * 32,
-                      size_t(m->N) * 16};
-  size_t offs[13], total = 0;
-  for (int k = 0; k < 13; ++k) {
+                      size_t(m->N) * 16,
+                      m->move == NQS_MOVE_EXCHANGE ? size_t(m->B[0]) * m->M * es : 0};
+  size_t offs[14], total = 0;
+  for (int k = 0; k < 14; ++k) {
     offs[k] = total;
     total += (sizes[k] + 255) / 256 * 256;
   }
@@ -205,7 +213,7 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
     return NQS_ENOMEM;
   }
   m->tables_bytes = total;
-  for (int k = 0; k < 13; ++k) m->tab_ptrs[k] = sizes[k] ? (char *)m->d_tables + offs[k] : nullptr;
+  for (int k = 0; k < 14; ++k) m->tab_ptrs[k] = sizes[k] ? (char *)m->d_tables + offs[k] : nullptr;
   *out = m;
   return NQS_OK;
 }
@@ -281,6 +289,7 @@ nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigm
   nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
   if (s != NQS_OK) return s;
   hipError_t e = launch_tables(m, params, st);
+  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, st);
   if (e == hipSuccess && want_vjp) {
     e = launch_vjp_partials(m, sigma, n, (const double *)u, m->d_scratch, nullptr, st);
     if (e == hipSuccess) e = launch_vjp_reduce(m, n, m->d_scratch, (double *)vjp, nullptr, st);

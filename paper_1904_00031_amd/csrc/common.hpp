@@ -120,7 +120,7 @@ __device__ __forceinline__ V<T, C> vlncosh(V<T, C> z) {
     T im = sg * z.im + fatan2(-sg * e * s2, T(1) + e * c2);
     return vmake<T, C>(re, im);
   } else {
-    return vmake<T, C>(ax + flog1p(e * e) - ln2 + T(0) * sg, T(0));
+    return vmake<T, C>(ax + flog1p(e) - ln2 + T(0) * sg, T(0));
   }
 }
 
@@ -221,6 +221,76 @@ __device__ __forceinline__ void vrenorm(V<T, C> &p, int &ex) {
   }
 }
 
+// ---------------------------------------------------------------------------------
+// DPP butterflies inside each row of 16 lanes (xor 1, xor 2 via quad permutations,
+// then rotations by 4 and 8), and the four row totals gathered with readlane.
+// ---------------------------------------------------------------------------------
+enum { DPP_QP_XOR1 = 0xB1, DPP_QP_XOR2 = 0x4E, DPP_ROR4 = 0x124, DPP_ROR8 = 0x128 };
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(dpp_i<CTRL>(hi), dpp_i<CTRL>(lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_v(float x) { return dpp_f<CTRL>(x); }
+template <int CTRL>
+__device__ __forceinline__ double dpp_v(double x) { return dpp_d<CTRL>(x); }
+
+__device__ __forceinline__ float readlane_v(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double readlane_v(double x, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// wave-uniform sum (result identical on every lane, fixed order)
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T x) {
+  x += dpp_v<DPP_QP_XOR1>(x);
+  x += dpp_v<DPP_QP_XOR2>(x);
+  x += dpp_v<DPP_ROR4>(x);
+  x += dpp_v<DPP_ROR8>(x);
+  return (readlane_v(x, 0) + readlane_v(x, 16)) + (readlane_v(x, 32) + readlane_v(x, 48));
+}
+
+// wave-uniform product of positive values given as (mant in [0.5, 1), exponent): returns
+// the product mantissa (>= 2^-64, no renormalisation needed) and the summed exponent
+template <typename T>
+__device__ __forceinline__ T wave_prod_dpp(T mant, int &ex) {
+  mant *= dpp_v<DPP_QP_XOR1>(mant);
+  ex += dpp_i<DPP_QP_XOR1>(ex);
+  mant *= dpp_v<DPP_QP_XOR2>(mant);
+  ex += dpp_i<DPP_QP_XOR2>(ex);
+  mant *= dpp_v<DPP_ROR4>(mant);
+  ex += dpp_i<DPP_ROR4>(ex);
+  mant *= dpp_v<DPP_ROR8>(mant);
+  ex += dpp_i<DPP_ROR8>(ex);
+  ex = (__builtin_amdgcn_readlane(ex, 0) + __builtin_amdgcn_readlane(ex, 16)) +
+       (__builtin_amdgcn_readlane(ex, 32) + __builtin_amdgcn_readlane(ex, 48));
+  return (readlane_v(mant, 0) * readlane_v(mant, 16)) * (readlane_v(mant, 32) * readlane_v(mant, 48));
+}
+
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> vdiv(V<T, C> a, V<T, C> b) {
+  if constexpr (C) {
+    T inv = T(1) / (b.re * b.re + b.im * b.im);
+    return vmake<T, C>((a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv);
+  } else {
+    return vmake<T, C>(a.re / b.re, T(0));
+  }
+}
+
 // wave-local memory ordering for LDS written by one lane and read by others
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -255,4 +325,5 @@ struct Tables {
   double *fa;  // [2][N]    exp(-2 s a_i),           s = +1 -> row 0, s = -1 -> row 1
   double *ba;  // [2][Btot] exp(-2 s (a_i - a_k)),   s = sigma_i
   double *av;  // [N]       a (double)
+  T *Wd;       // [B0][M]   W_ji - W_jk for the color-0 bond (i, k)
 };

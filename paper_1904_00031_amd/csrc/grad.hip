@@ -8,8 +8,8 @@
 //   JVP  y_s = sum_i s_si va_i + sum_j t_sj (vb_j + (S V^T)_sj)      (theta = S W^T + b)
 //   VJP  g_W = Z^T S, g_b = colsum(Z), g_a = S^T u,  Z_sj = conj(t_sj) u_s.
 // Each wavefront owns 16 samples; the matrix-core instruction is the 16x16x4 FP32 or
-// FP64 MFMA (A: lane l holds A[l%16][l/16]; B: B[l/16][l%16]; D: lane l register r
-// holds D[4(l/16)+r][l%16]).
+// FP64 MFMA (A: lane l holds A[l%16][l/16]; B: B[l/16][l%16]). Accumulator rows differ:
+// FP32 lane l register r holds D[4(l/16)+r][l%16], FP64 holds D[l/16+4r][l%16].
 #include "internal.hpp"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -25,6 +25,8 @@ struct MF<float> {
   static __device__ __forceinline__ acc mma(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  // accumulator row held by lane group hi (= lane / 16), register r
+  static __device__ __forceinline__ int row(int hi, int r) { return 4 * hi + r; }
 };
 template <>
 struct MF<double> {
@@ -32,6 +34,7 @@ struct MF<double> {
   static __device__ __forceinline__ acc mma(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int hi, int r) { return hi + 4 * r; }
 };
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -62,12 +65,59 @@ __global__ void k_prep_dir(int N, int M, const double *__restrict__ v, T *Vt, T 
 }
 
 // ---------------------------------------------------------------------------------
-// JVP. Grid (ceil(n/64), hidden chunks). Writes ypart[chunk][s] (complex double).
+// T[s][j] = tanh(b_j + sum_i W_ji s_si): theta tile by MFMA (A = spins, B = W^T), tanh in
+// the epilogue. Grid (ceil(n/64), hidden chunks of JT tiles); 16 samples per wavefront.
+// ---------------------------------------------------------------------------------
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
+                                                     const int8_t *__restrict__ sigma,
+                                                     const T *__restrict__ Wt,
+                                                     const T *__restrict__ bv, int JT, T *Tout) {
+  typedef typename MF<T>::acc Acc;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lo = lane & 15, hi = lane >> 4;
+  const int64_t s0 = int64_t(blockIdx.x) * 64 + wid * 16;
+  const int ntiles = (M + 15) / 16;
+  const int jt0 = blockIdx.y * JT;
+  const int jt1 = jt0 + JT < ntiles ? jt0 + JT : ntiles;
+  const int64_t rowA = s0 + lo;
+  const bool rowA_ok = rowA < n;
+  const int8_t *srow = sigma + (rowA_ok ? rowA : 0) * N;
+  for (int jt = jt0; jt < jt1; ++jt) {
+    const int j = jt * 16 + lo;
+    const bool jok = j < M;
+    Acc tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < N; k0 += 4) {
+      const int k = k0 + hi;
+      const bool kok = k < N;
+      const T a = (rowA_ok && kok) ? T(srow[k]) : T(0);
+      V<T, C> w = vmake<T, C>(T(0), T(0));
+      if (kok && jok) w = vload<T, C>(Wt, int64_t(k) * M + j);
+      tr = MF<T>::mma(a, w.re, tr);
+      if constexpr (C) ti = MF<T>::mma(a, w.im, ti);
+    }
+    if (jok) {
+      const V<T, C> bb = vload<T, C>(bv, j);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = s0 + MF<T>::row(hi, r);
+        if (row < n) {
+          V<T, C> th = vmake<T, C>(tr[r] + bb.re, C ? ti[r] + bb.im : T(0));
+          vstore<T, C>(Tout, row * M + j, vtanh<T, C>(th));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// JVP with stored T: y_s = sum_i s_si va_i + sum_j T_sj (vb_j + (S V^T)_sj).
+// Grid (ceil(n/64), hidden chunks). Writes ypart[chunk][s] (complex double).
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
                                               const int8_t *__restrict__ sigma,
-                                              const T *__restrict__ Wt, const T *__restrict__ bv,
+                                              const T *__restrict__ Tm,
                                               const T *__restrict__ Vt, const T *__restrict__ vb,
                                               const double *__restrict__ va, int JT,
                                               double *ypart, const int *skip) {
@@ -89,30 +139,29 @@ __global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
   for (int jt = jt0; jt < jt1; ++jt) {
     const int j = jt * 16 + lo;
     const bool jok = j < M;
-    Acc tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0}, xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+    // issue the loads of this tile's T entries before the contraction
+    V<T, C> tv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = s0 + MF<T>::row(hi, r);
+      tv[r] = (jok && row < n) ? vload<T, C>(Tm, row * M + j) : vmake<T, C>(T(0), T(0));
+    }
+    Acc xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
     for (int k0 = 0; k0 < N; k0 += 4) {
       const int k = k0 + hi;
       const bool kok = k < N;
       const T a = (rowA_ok && kok) ? T(srow[k]) : T(0);
-      V<T, C> w = vmake<T, C>(T(0), T(0)), v = vmake<T, C>(T(0), T(0));
-      if (kok && jok) {
-        w = vload<T, C>(Wt, int64_t(k) * M + j);
-        v = vload<T, C>(Vt, int64_t(k) * M + j);
-      }
-      tr = MF<T>::mma(a, w.re, tr);
+      V<T, C> v = vmake<T, C>(T(0), T(0));
+      if (kok && jok) v = vload<T, C>(Vt, int64_t(k) * M + j);
       xr = MF<T>::mma(a, v.re, xr);
-      if constexpr (C) {
-        ti = MF<T>::mma(a, w.im, ti);
-        xi = MF<T>::mma(a, v.im, xi);
-      }
+      if constexpr (C) xi = MF<T>::mma(a, v.im, xi);
     }
     if (jok) {
-      const V<T, C> bb = vload<T, C>(bv, j), vbj = vload<T, C>(vb, j);
+      const V<T, C> vbj = vload<T, C>(vb, j);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        V<T, C> th = vmake<T, C>(tr[r] + bb.re, C ? ti[r] + bb.im : T(0));
         V<T, C> x = vmake<T, C>(xr[r] + vbj.re, C ? xi[r] + vbj.im : T(0));
-        yp[r] = vadd(yp[r], vmul(vtanh<T, C>(th), x));
+        yp[r] = vadd(yp[r], vmul(tv[r], x));
       }
     }
   }
@@ -127,7 +176,7 @@ __global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
   if (lo == 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = s0 + 4 * hi + r;
+      const int64_t row = s0 + MF<T>::row(hi, r);
       if (row >= n) continue;
       double yr = double(yp[r].re), yi = C ? double(yp[r].im) : 0.0;
       if (jc == 0) {
@@ -184,182 +233,139 @@ __global__ __launch_bounds__(256) void k_jvp_finish(int64_t n, int jchunks,
 }
 
 // ---------------------------------------------------------------------------------
-// VJP partials. Grid (Mt hidden tiles incl. the extra row M that carries g_a, sample
-// splits, site chunks). Each wavefront walks 16-sample groups: theta tile by MFMA,
-// Z = conj(tanh theta) u in registers, a 16x16 transpose through LDS, then Z^T S by
-// MFMA into NT site tiles. The four wavefronts of a block are summed through LDS.
-// partW [split][Mt*16][Ncols], partB [split][Mt*16] (compute precision).
+// VJP with stored T: G = Z^T S~ over a sample split, with rows j <= M and columns
+// i <= N of the augmented operands
+//   Z_sj = conj(T_sj) u_s (j < M),  Z_sM = u_s;   S~_si = s_si (i < N),  S~_sN = 1,
+// so G[j][i] = (O^dagger u)_W_ji, G[j][N] = (O^dagger u)_b_j, G[M][i] = (O^dagger u)_a_i.
+// A = Z^T needs no transpose: lane (lo, hi) loads Z[s + hi][j0 + lo]. Each wavefront
+// accumulates JT x NT output tiles over every fourth 4-sample step of the block's split;
+// the four wavefronts are summed through LDS and the block writes one partial tile set.
+// Grid (hidden chunks, sample splits, site chunks).
+// partial layout [split][Jtiles*16][Itiles*16], compute precision.
 // ---------------------------------------------------------------------------------
-template <typename T, bool C, int NT>
+template <typename T, bool C, int JT, int NT>
 __global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
                                               const int8_t *__restrict__ sigma,
-                                              const T *__restrict__ Wt, const T *__restrict__ bv,
+                                              const T *__restrict__ Tm,
                                               const double *__restrict__ u, int64_t per_split,
-                                              int Ncols, T *partW, T *partB, const int *skip) {
+                                              int rowsP, int colsP, T *part, const int *skip) {
   if (skip && *skip) return;
   typedef typename MF<T>::acc Acc;
-  __shared__ T zre[4][256];
-  __shared__ T zim[4][C ? 256 : 1];
   __shared__ T red[4][4][64][C ? 2 : 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
-  const int jt = blockIdx.x, split = blockIdx.y, zc = blockIdx.z;
-  const int Mrows = gridDim.x * 16;
-  const int j = jt * 16 + lo;
-  const bool jok = j < M;
-  const int i_base = zc * NT * 16;
-  const int64_t sbeg = int64_t(split) * per_split;
+  const int jt0 = blockIdx.x * JT, it0 = blockIdx.z * NT;
+  const int64_t sbeg = int64_t(blockIdx.y) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
-  Acc ar[NT], ai[NT];
+  Acc ar[JT][NT], ai[JT][NT];
 #pragma unroll
-  for (int it = 0; it < NT; ++it) {
-    ar[it] = Acc{0, 0, 0, 0};
-    ai[it] = Acc{0, 0, 0, 0};
-  }
-  V<T, C> bsum = vmake<T, C>(T(0), T(0));
-  const V<T, C> bb = jok ? vload<T, C>(bv, j) : vmake<T, C>(T(0), T(0));
-  for (int64_t g = sbeg + wid * 16; g < send; g += 64) {
-    const int64_t rowA = g + lo;
-    const bool rowA_ok = rowA < send;
-    const int8_t *srow = sigma + (rowA_ok ? rowA : 0) * N;
-    Acc tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < N; k0 += 4) {
-      const int k = k0 + hi;
-      const bool kok = k < N;
-      const T a = (rowA_ok && kok) ? T(srow[k]) : T(0);
-      V<T, C> w = vmake<T, C>(T(0), T(0));
-      if (kok && jok) w = vload<T, C>(Wt, int64_t(k) * M + j);
-      tr = MF<T>::mma(a, w.re, tr);
-      if constexpr (C) ti = MF<T>::mma(a, w.im, ti);
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      ar[a][b] = Acc{0, 0, 0, 0};
+      ai[a][b] = Acc{0, 0, 0, 0};
     }
-    V<T, C> z[4];
+  for (int64_t s = sbeg + 4 * wid; s < send; s += 16) {
+    const int64_t srow = s + hi;
+    const bool sok = srow < send;
+    V<T, C> uu = vmake<T, C>(T(0), T(0));
+    if (sok) uu = vmake<T, C>(T(u[C ? 2 * srow : srow]), C ? T(u[2 * srow + 1]) : T(0));
+    V<T, C> z[JT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = g + 4 * hi + r;
-      z[r] = vmake<T, C>(T(0), T(0));
-      if (row < send) {
-        V<T, C> uu = vmake<T, C>(T(u[C ? 2 * row : row]), C ? T(u[2 * row + 1]) : T(0));
-        if (jok) {
-          V<T, C> th = vmake<T, C>(tr[r] + bb.re, C ? ti[r] + bb.im : T(0));
-          z[r] = vmul(vconj(vtanh<T, C>(th)), uu);
-          bsum = vadd(bsum, z[r]);
-        } else if (j == M) {
-          z[r] = uu;
+    for (int a = 0; a < JT; ++a) {
+      const int j = (jt0 + a) * 16 + lo;
+      if (sok && j < M)
+        z[a] = vmul(vconj(vload<T, C>(Tm, srow * M + j)), uu);
+      else
+        z[a] = (sok && j == M) ? uu : vmake<T, C>(T(0), T(0));
+    }
+    T bs[NT];
+    const int8_t *sp = sigma + (sok ? srow : 0) * N;
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      const int i = (it0 + b) * 16 + lo;
+      bs[b] = sok ? (i < N ? T(sp[i]) : (i == N ? T(1) : T(0))) : T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < JT; ++a)
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        ar[a][b] = MF<T>::mma(z[a].re, bs[b], ar[a][b]);
+        if constexpr (C) ai[a][b] = MF<T>::mma(z[a].im, bs[b], ai[a][b]);
+      }
+  }
+  const int tid = threadIdx.x;
+  const int r = tid >> 6, l = tid & 63;
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        red[wid][q][lane][0] = ar[a][b][q];
+        if constexpr (C) red[wid][q][lane][C ? 1 : 0] = ai[a][b][q];
+      }
+      __syncthreads();
+      const int jrow = (jt0 + a) * 16 + MF<T>::row(l >> 4, r);
+      const int icol = (it0 + b) * 16 + (l & 15);
+      if (jrow < rowsP && icol < colsP) {
+        const int64_t o = (int64_t(blockIdx.y) * rowsP + jrow) * colsP + icol;
+        T sr = red[0][r][l][0] + red[1][r][l][0] + red[2][r][l][0] + red[3][r][l][0];
+        if constexpr (C) {
+          T si = red[0][r][l][C ? 1 : 0] + red[1][r][l][C ? 1 : 0] + red[2][r][l][C ? 1 : 0] +
+                 red[3][r][l][C ? 1 : 0];
+          part[2 * o] = sr;
+          part[2 * o + 1] = si;
+        } else {
+          part[o] = sr;
         }
       }
     }
-    wave_sync();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      zre[wid][(4 * hi + r) * 16 + lo] = z[r].re;
-      if constexpr (C) zim[wid][(4 * hi + r) * 16 + lo] = z[r].im;
-    }
-    wave_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T a2r = zre[wid][(4 * q + hi) * 16 + lo];
-      T a2i = T(0);
-      if constexpr (C) a2i = zim[wid][(4 * q + hi) * 16 + lo];
-      const int64_t srw = g + 4 * q + hi;
-      const bool sok = srw < send;
-      const int8_t *sp = sigma + (sok ? srw : 0) * N;
-#pragma unroll
-      for (int it = 0; it < NT; ++it) {
-        const int i = i_base + it * 16 + lo;
-        const T b2 = (sok && i < N) ? T(sp[i]) : T(0);
-        ar[it] = MF<T>::mma(a2r, b2, ar[it]);
-        if constexpr (C) ai[it] = MF<T>::mma(a2i, b2, ai[it]);
-      }
-    }
-  }
-  // column sums of Z for g_b: reduce over the four lane groups
-  bsum.re += __shfl_xor(bsum.re, 16, 64);
-  bsum.re += __shfl_xor(bsum.re, 32, 64);
-  if constexpr (C) {
-    bsum.im += __shfl_xor(bsum.im, 16, 64);
-    bsum.im += __shfl_xor(bsum.im, 32, 64);
-  }
-  // sum the four wavefronts of the block, one site tile at a time
-  const int tid = threadIdx.x;
-  for (int it = 0; it < NT; ++it) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      red[wid][r][lane][0] = ar[it][r];
-      if constexpr (C) red[wid][r][lane][C ? 1 : 0] = ai[it][r];
-    }
-    __syncthreads();
-    // 256 threads cover 4 registers x 64 lanes
-    const int r = tid >> 6, l = tid & 63;
-    T sr = red[0][r][l][0] + red[1][r][l][0] + red[2][r][l][0] + red[3][r][l][0];
-    T si = T(0);
-    if constexpr (C)
-      si = red[0][r][l][C ? 1 : 0] + red[1][r][l][C ? 1 : 0] + red[2][r][l][C ? 1 : 0] +
-           red[3][r][l][C ? 1 : 0];
-    const int jrow = jt * 16 + 4 * (l >> 4) + r;
-    const int icol = i_base + it * 16 + (l & 15);
-    const int64_t o = (int64_t(split) * Mrows + jrow) * Ncols + icol;
-    if constexpr (C) {
-      partW[2 * o] = sr;
-      partW[2 * o + 1] = si;
-    } else {
-      partW[o] = sr;
-    }
-  }
-  if (zc == 0) {
-    __syncthreads();
-    if (hi == 0) {
-      red[wid][0][lo][0] = bsum.re;
-      if constexpr (C) red[wid][0][lo][C ? 1 : 0] = bsum.im;
-    }
-    __syncthreads();
-    if (tid < 16) {
-      T sr = red[0][0][tid][0] + red[1][0][tid][0] + red[2][0][tid][0] + red[3][0][tid][0];
-      const int64_t o = int64_t(split) * Mrows + jt * 16 + tid;
-      if constexpr (C) {
-        T si = red[0][0][tid][C ? 1 : 0] + red[1][0][tid][C ? 1 : 0] +
-               red[2][0][tid][C ? 1 : 0] + red[3][0][tid][C ? 1 : 0];
-        partB[2 * o] = sr;
-        partB[2 * o + 1] = si;
-      } else {
-        partB[o] = sr;
-      }
-    }
-  }
 }
 
-// out[k] (double, packed like the parameters) = sum over splits of the partials
+// first reduction level: out1[g][e] = sum of partials of split group g (complex double)
 template <typename T, bool C>
-__global__ void k_vjp_reduce(int N, int M, int splits, int Mrows, int Ncols,
-                             const T *__restrict__ partW, const T *__restrict__ partB,
-                             double *out, const int *skip) {
+__global__ __launch_bounds__(256) void k_vjp_reduce1(int splits, int groups, int64_t elems,
+                                                     const T *__restrict__ part, double *out1,
+                                                     const int *skip) {
+  if (skip && *skip) return;
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= elems) return;
+  const int g = blockIdx.y;
+  const int per = (splits + groups - 1) / groups;
+  const int p0 = g * per, p1 = p0 + per < splits ? p0 + per : splits;
+  double sr = 0.0, si = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    V<T, C> x = vload<T, C>(part, int64_t(p) * elems + e);
+    sr += double(x.re);
+    si += double(x.im);
+  }
+  out1[2 * (int64_t(g) * elems + e)] = sr;
+  out1[2 * (int64_t(g) * elems + e) + 1] = si;
+}
+
+// second level: out[k] (double, packed like the parameters) = sum over groups
+template <bool C>
+__global__ void k_vjp_reduce2(int N, int M, int groups, int colsP, int64_t elems,
+                              const double *__restrict__ out1, double *out, const int *skip) {
   if (skip && *skip) return;
   const int64_t P = int64_t(N) + M + int64_t(N) * M;
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < P;
        k += int64_t(gridDim.x) * blockDim.x) {
-    double sr = 0.0, si = 0.0;
-    if (k < N + M && k >= N) {
-      const int j = int(k - N);
-      for (int p = 0; p < splits; ++p) {
-        V<T, C> x = vload<T, C>(partB, int64_t(p) * Mrows + j);
-        sr += double(x.re);
-        si += double(x.im);
-      }
+    int64_t e;
+    if (k < N) {
+      e = int64_t(M) * colsP + k;                 // row M: visible bias
+    } else if (k < N + M) {
+      e = int64_t(k - N) * colsP + N;             // column N: hidden bias
     } else {
-      int j, i;
-      if (k < N) {
-        j = M;
-        i = int(k);
-      } else {
-        const int64_t q = k - N - M;
-        j = int(q / N);
-        i = int(q % N);
-      }
-      for (int p = 0; p < splits; ++p) {
-        V<T, C> x = vload<T, C>(partW, (int64_t(p) * Mrows + j) * Ncols + i);
-        sr += double(x.re);
-        si += double(x.im);
-      }
+      const int64_t q = k - N - M;
+      e = (q / N) * colsP + (q % N);              // W_ji
+    }
+    double sr = 0.0, si = 0.0;
+    for (int g = 0; g < groups; ++g) {
+      sr += out1[2 * (int64_t(g) * elems + e)];
+      si += out1[2 * (int64_t(g) * elems + e) + 1];
     }
     if (C) {
       out[2 * k] = sr;
@@ -374,7 +380,7 @@ __global__ void k_vjp_reduce(int N, int M, int splits, int Mrows, int Ncols,
 // scratch layout (byte offsets), all regions 256-byte aligned
 // ---------------------------------------------------------------------------------
 struct GradLayout {
-  size_t Vt, vb, va, ypart, partW, partB, total;
+  size_t Vt, vb, va, ypart, Tm, part, out1, total;
 };
 
 GradLayout grad_layout(const nqs_model *m, int64_t n) {
@@ -387,12 +393,14 @@ GradLayout grad_layout(const nqs_model *m, int64_t n) {
     off += (bytes + 255) / 256 * 256;
     return o;
   };
+  const size_t elems = size_t(g.Jtiles) * 16 * size_t(g.Itiles) * 16;
   L.Vt = take(size_t(m->N) * m->M * es);
   L.vb = take(size_t(m->M) * es);
   L.va = take(size_t(m->N) * 16);
   L.ypart = take(size_t(g.jchunks) * size_t(n) * 16);
-  L.partW = take(size_t(g.splits) * g.Mt * 16 * size_t(g.Nz * g.Nt * 16) * es);
-  L.partB = take(size_t(g.splits) * g.Mt * 16 * es);
+  L.Tm = take(size_t(n) * m->M * es);
+  L.part = take(size_t(g.splits) * elems * es);
+  L.out1 = take(size_t(g.groups) * elems * 16);
   L.total = off;
   return L;
 }
@@ -411,15 +419,26 @@ hipError_t prep_t(const nqs_model *m, const void *v, void *scratch, hipStream_t 
 }
 
 template <typename T, bool C>
+hipError_t tanh_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                  hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  GradPlan g = grad_plan(m, n);
+  GradLayout L = grad_layout(m, n);
+  char *base = (char *)scratch;
+  hipLaunchKernelGGL((k_theta_tanh<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256),
+                     0, st, m->N, m->M, n, sigma, (const T *)m->tab_ptrs[0],
+                     (const T *)m->tab_ptrs[1], 16, (T *)(base + L.Tm));
+  return hipGetLastError();
+}
+
+template <typename T, bool C>
 hipError_t jvp_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch, double *y,
                  double *ysum_part, const int *skip, hipStream_t st) {
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
-  const T *Wt = (const T *)m->tab_ptrs[0];
-  const T *bv = (const T *)m->tab_ptrs[1];
   hipLaunchKernelGGL((k_jvp<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256), 0, st,
-                     m->N, m->M, n, sigma, Wt, bv, (const T *)(base + L.Vt),
+                     m->N, m->M, n, sigma, (const T *)(base + L.Tm), (const T *)(base + L.Vt),
                      (const T *)(base + L.vb), (const double *)(base + L.va), 16,
                      (double *)(base + L.ypart), skip);
   hipError_t e = hipGetLastError();
@@ -429,30 +448,50 @@ hipError_t jvp_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scrat
   return hipGetLastError();
 }
 
-template <typename T, bool C, int NT>
-hipError_t vjp_nt(const nqs_model *m, const int8_t *sigma, int64_t n, const double *u,
-                  void *scratch, const int *skip, hipStream_t st) {
+template <typename T, bool C, int JT, int NT>
+hipError_t vjp_tile(const nqs_model *m, const int8_t *sigma, int64_t n, const double *u,
+                    void *scratch, const int *skip, hipStream_t st) {
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
-  const T *Wt = (const T *)m->tab_ptrs[0];
-  const T *bv = (const T *)m->tab_ptrs[1];
-  hipLaunchKernelGGL((k_vjp<T, C, NT>), dim3(g.Mt, g.splits, g.Nz), dim3(256), 0, st, m->N,
-                     m->M, n, sigma, Wt, bv, u, g.per_split, g.Nz * g.Nt * 16,
-                     (T *)(base + L.partW), (T *)(base + L.partB), skip);
+  dim3 grid(unsigned(cdiv(g.Jtiles, JT)), unsigned(g.splits), unsigned(cdiv(g.Itiles, NT)));
+  hipLaunchKernelGGL((k_vjp<T, C, JT, NT>), grid, dim3(256), 0, st, m->N, m->M, n, sigma,
+                     (const T *)(base + L.Tm), u, g.per_split, g.Jtiles * 16, g.Itiles * 16,
+                     (T *)(base + L.part), skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
+  hipLaunchKernelGGL((k_vjp_reduce1<T, C>), dim3(unsigned(cdiv(elems, 256)), g.groups),
+                     dim3(256), 0, st, g.splits, g.groups, elems, (const T *)(base + L.part),
+                     (double *)(base + L.out1), skip);
   return hipGetLastError();
 }
 
 template <typename T, bool C>
 hipError_t vjp_t(const nqs_model *m, const int8_t *sigma, int64_t n, const double *u,
                  void *scratch, const int *skip, hipStream_t st) {
-  switch (grad_plan(m, n).Nt) {
-    case 1: return vjp_nt<T, C, 1>(m, sigma, n, u, scratch, skip, st);
-    case 2: return vjp_nt<T, C, 2>(m, sigma, n, u, scratch, skip, st);
-    case 4: return vjp_nt<T, C, 4>(m, sigma, n, u, scratch, skip, st);
-    case 8: return vjp_nt<T, C, 8>(m, sigma, n, u, scratch, skip, st);
-    default: return vjp_nt<T, C, 16>(m, sigma, n, u, scratch, skip, st);
-  }
+  GradPlan g = grad_plan(m, n);
+#define NQS_VJP_CASE(A, B) \
+  if (g.JT == A && g.NT == B) return vjp_tile<T, C, A, B>(m, sigma, n, u, scratch, skip, st);
+  NQS_VJP_CASE(1, 1)
+  NQS_VJP_CASE(2, 1)
+  NQS_VJP_CASE(4, 1)
+  NQS_VJP_CASE(6, 1)
+  NQS_VJP_CASE(8, 1)
+  NQS_VJP_CASE(1, 2)
+  NQS_VJP_CASE(2, 2)
+  NQS_VJP_CASE(4, 2)
+  NQS_VJP_CASE(6, 2)
+  NQS_VJP_CASE(8, 2)
+  NQS_VJP_CASE(1, 3)
+  NQS_VJP_CASE(2, 3)
+  NQS_VJP_CASE(4, 3)
+  NQS_VJP_CASE(6, 3)
+  NQS_VJP_CASE(1, 4)
+  NQS_VJP_CASE(2, 4)
+  NQS_VJP_CASE(4, 4)
+#undef NQS_VJP_CASE
+  return hipErrorInvalidValue;
 }
 
 template <typename T, bool C>
@@ -464,9 +503,9 @@ hipError_t vjp_reduce_t(const nqs_model *m, int64_t n, void *scratch, double *ou
   int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
   int blocks = int(cdiv(P, 256));
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL((k_vjp_reduce<T, C>), dim3(blocks), dim3(256), 0, st, m->N, m->M,
-                     g.splits, g.Mt * 16, g.Nz * g.Nt * 16, (const T *)(base + L.partW),
-                     (const T *)(base + L.partB), out, skip);
+  const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
+  hipLaunchKernelGGL((k_vjp_reduce2<C>), dim3(blocks), dim3(256), 0, st, m->N, m->M, g.groups,
+                     g.Itiles * 16, elems, (const double *)(base + L.out1), out, skip);
   return hipGetLastError();
 }
 
@@ -474,18 +513,26 @@ hipError_t vjp_reduce_t(const nqs_model *m, int64_t n, void *scratch, double *ou
 
 GradPlan grad_plan(const nqs_model *m, int64_t n) {
   GradPlan g;
-  g.Mt = (m->M + 1 + 15) / 16;
-  const int tilesN = (m->N + 15) / 16;
-  int nt = 1;
-  while (nt < tilesN && nt < 16) nt <<= 1;
-  g.Nt = nt;
-  g.Nz = int(cdiv(tilesN, nt));
-  const int64_t groups = n > 0 ? cdiv(n, 64) : 1;
-  int64_t splits = 2048 / (int64_t(g.Mt) * g.Nz);
+  g.Jtiles = (m->M + 1 + 15) / 16;   // hidden rows 0..M (row M carries the visible bias)
+  g.Itiles = (m->N + 1 + 15) / 16;   // site columns 0..N (column N carries the hidden bias)
+  g.NT = g.Itiles < 4 ? g.Itiles : 4;
+  const int jt_budget = 24 / g.NT;   // accumulator tiles per wavefront <= 24
+  static const int jts[5] = {8, 6, 4, 2, 1};
+  g.JT = 1;
+  for (int q = 0; q < 5; ++q)
+    if (jts[q] <= jt_budget && (jts[q] <= g.Jtiles || q == 4)) {
+      g.JT = jts[q];
+      break;
+    }
+  if (g.NT == 3 && g.JT == 8) g.JT = 6;
+  const int64_t tile_blocks = cdiv(g.Jtiles, g.JT) * cdiv(g.Itiles, g.NT);
+  const int64_t steps = n > 0 ? cdiv(n, 16) : 1;   // 16 samples = one step of all 4 waves
+  int64_t splits = 512 / tile_blocks;
   if (splits < 1) splits = 1;
-  if (splits > groups) splits = groups;
-  g.per_split = rup(cdiv(n > 0 ? n : 1, splits), 64);
+  if (splits > steps) splits = steps;
+  g.per_split = rup(cdiv(n > 0 ? n : 1, splits), 16);
   g.splits = int(cdiv(n > 0 ? n : 1, g.per_split));
+  g.groups = g.splits < 16 ? g.splits : 16;
   g.jchunks = int(cdiv((m->M + 15) / 16, 16));
   g.jvp_blocks = cdiv(n > 0 ? n : 1, 64);
   return g;
@@ -501,6 +548,11 @@ size_t grad_scratch_bytes(const nqs_model *m, int64_t n) { return grad_layout(m,
 
 hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, hipStream_t st) {
   return NQS_DISPATCH(prep_t, m, v, scratch, st);
+}
+
+hipError_t launch_theta_tanh(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                             hipStream_t st) {
+  return NQS_DISPATCH(tanh_t, m, sigma, n, scratch, st);
 }
 
 hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
@@ -519,6 +571,4 @@ hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, doubl
   return NQS_DISPATCH(vjp_reduce_t, m, n, scratch, out, skip, st);
 }
 
-const double *scratch_vjp_partials(const nqs_model *m, int64_t n, void *scratch) {
-  return (const double *)((char *)scratch + grad_layout(m, n).partW);
-}
+

@@ -18,7 +18,8 @@ struct nqs_model {
   double *d_bond_off = nullptr;    // [Btot]
   void *d_tables = nullptr;        // parameter-derived tables (see Tables<T>)
   size_t tables_bytes = 0;
-  void *tab_ptrs[13] = {};         // sub-buffers of d_tables, in Tables<T> member order
+  void *tab_ptrs[14] = {};         // sub-buffers of d_tables, in Tables<T> member order
+  int max_lds = 65536;             // dynamic LDS bytes a workgroup may use on this device
   // grow-only scratch for nqs_log_psi_grad
   void *d_scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -44,19 +45,23 @@ hipError_t launch_log_psi(const nqs_model *m, const int8_t *sigma, int64_t n, vo
 // ---- Jacobian products (grad.hip) ---------------------------------------------------
 // scratch layout for one JVP / VJP pair, sized by grad_scratch_bytes
 struct GradPlan {
-  int Mt;        // hidden 16-tiles (covering M hidden units)
-  int Nt;        // site 16-tiles per block (covering up to 256 sites)
-  int Nz;        // site chunks (grid z)
-  int splits;    // sample splits of the VJP
-  int64_t per_split;  // samples per split (multiple of 64)
-  int jchunks;   // hidden chunks of the JVP (grid y)
-  int64_t jvp_blocks; // sample tiles of 64 in the JVP
+  int Jtiles;    // 16-row tiles over hidden rows 0..M of the VJP output
+  int Itiles;    // 16-column tiles over site columns 0..N of the VJP output
+  int JT, NT;    // tiles per wavefront (hidden x site) in the VJP
+  int splits;    // sample splits of the VJP (grid y)
+  int64_t per_split;  // samples per split (multiple of 16)
+  int groups;    // first-level reduction groups of the VJP partials
+  int jchunks;   // hidden chunks of 16 tiles in the JVP / tanh kernels (grid y)
+  int64_t jvp_blocks; // sample tiles of 64 in the JVP / tanh kernels
 };
 GradPlan grad_plan(const nqs_model *m, int64_t n);
 size_t grad_scratch_bytes(const nqs_model *m, int64_t n);
 
 // v (double, params layout) -> direction tables in compute precision, in scratch
 hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, hipStream_t st);
+// T = tanh(theta) of every sample into scratch (needed by launch_jvp / launch_vjp_partials)
+hipError_t launch_theta_tanh(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                             hipStream_t st);
 // y[s] = (O v)[s] with the direction prepared by launch_prep_dir; ysum (may be NULL)
 // receives per-block partial sums of y (complex double) for the centering
 hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
@@ -68,7 +73,6 @@ hipError_t launch_vjp_partials(const nqs_model *m, const int8_t *sigma, int64_t 
 // out[k] = sum of partials (double, params layout)
 hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, double *out,
                              const int *skip, hipStream_t st);
-const double *scratch_vjp_partials(const nqs_model *m, int64_t n, void *scratch);
 
 // ---- SR (sr.hip) --------------------------------------------------------------------
 size_t sr_workspace_bytes(const nqs_model *m, int64_t n);

@@ -76,6 +76,7 @@ __global__ void k_tables(DevModel dm, Tables<T> tb, const PT *__restrict__ p, in
       vstore<T, C>(tb.bS, int64_t(b) * M + j, vcast<double, C, T>(ss));
       vstore<T, C>(tb.bCt, int64_t(j) * B + b, vcast<double, C, T>(cc));
       vstore<T, C>(tb.bSt, int64_t(j) * B + b, vcast<double, C, T>(ss));
+      if (tb.Wd && b < dm.B0) vstore<T, C>(tb.Wd, int64_t(b) * M + j, vcast<double, C, T>(vsub(wi, wk)));
     } else {
       int64_t q = e - nW - nB;
       if (q < M) {
@@ -139,175 +140,20 @@ __global__ void k_init_sz0(int8_t *sig, int n_chains, int N, uint32_t k0, uint32
 }
 
 // ---------------------------------------------------------------------------------
-// Metropolis sweeps. One chain per wavefront; lane l owns hidden units l + 64 r,
-// r < R, whose angles theta_j are cached in double and tanh(theta_j) in T. The spins of
-// the chain live in LDS. Every proposal: Philox draw (wave-uniform), ratio terms on
-// the lanes, a product reduction over the wave carried as mantissa x 2^exponent, and a
-// wave-uniform accept decision in double.
-// ---------------------------------------------------------------------------------
-template <typename T, bool C, int R>
-__global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, int8_t *chain_sigma,
-                                                int n_chains, int n_sweeps, int n_discard,
-                                                uint32_t k0, uint32_t k1, uint32_t counter,
-                                                uint32_t chain_offset, int8_t *samples,
-                                                int64_t *n_acc, int Npad) {
-  extern __shared__ int8_t lds_s8[];
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int chain = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wid);
-  if (chain >= n_chains) return;
-  const int N = dm.N, M = dm.M;
-  int8_t *sig = lds_s8 + wid * Npad;
-  for (int i = lane; i < N; i += 64) sig[i] = chain_sigma[int64_t(chain) * N + i];
-  wave_sync();
-
-  double thr[R], thi[R];
-  V<T, C> t[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int j = lane + 64 * r;
-    thr[r] = 0.0;
-    thi[r] = 0.0;
-    t[r] = vmake<T, C>(T(0), T(0));
-    if (j < M) {
-      V<double, C> acc = vload<double, C>(tb.bv, j);
-      for (int i = 0; i < N; ++i) {
-        double s = double(sig[i]);
-        V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
-        acc.re += s * w.re;
-        if (C) acc.im += s * w.im;
-      }
-      thr[r] = acc.re;
-      thi[r] = C ? acc.im : 0.0;
-      t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
-    }
-  }
-
-  int64_t acc_count = 0;
-  const bool flip = dm.move == NQS_MOVE_FLIP;
-  const uint32_t cid = chain_offset + uint32_t(chain);
-  for (int sw = 0; sw < n_discard + n_sweeps; ++sw) {
-    const uint32_t c1 = counter + uint32_t(sw);
-    for (int step = 0; step < N; ++step) {
-      Philox4 w = philox4x32_10(cid, c1, uint32_t(step), TAG_PROPOSAL, k0, k1);
-      int i, k = -1, row;
-      const T *Crow, *Srow;
-      const double *af;
-      int s;
-      if (flip) {
-        i = rng_index(w.w[0], uint32_t(N));
-        s = __builtin_amdgcn_readfirstlane(int(sig[i]));
-        row = i;
-        Crow = tb.fC + int64_t(row) * M * (C ? 2 : 1);
-        Srow = tb.fS + int64_t(row) * M * (C ? 2 : 1);
-        af = tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + i);
-      } else {
-        int b = rng_index(w.w[0], uint32_t(dm.B0));
-        i = dm.bonds[2 * b];
-        k = dm.bonds[2 * b + 1];
-        s = __builtin_amdgcn_readfirstlane(int(sig[i]));
-        int sk = __builtin_amdgcn_readfirstlane(int(sig[k]));
-        if (sk == s) continue;  // identity move: random numbers consumed, nothing changes
-        row = b;
-        Crow = tb.bC + int64_t(row) * M * (C ? 2 : 1);
-        Srow = tb.bS + int64_t(row) * M * (C ? 2 : 1);
-        af = tb.ba + 2 * (int64_t(s > 0 ? 0 : 1) * dm.Btot + b);
-      }
-      const T ts = T(s);
-      T pm = T(1);
-      int pe = 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int j = lane + 64 * r;
-        if (j < M) {
-          V<T, C> cc = vload<T, C>(Crow, j), ss = vload<T, C>(Srow, j);
-          V<T, C> term = vsub(cc, vscale(vmul(t[r], ss), ts));
-          pm *= vabs2(term);
-        }
-        if ((r & 3) == 3) {
-          int e;
-          pm = nfrexp(pm, &e);
-          pe += e;
-        }
-      }
-      {
-        int e;
-        pm = nfrexp(pm, &e);
-        pe += e;
-      }
-      wave_prod_norm(pm, pe);
-      const double a2 = af[0] * af[0] + af[1] * af[1];
-      const double q = ldexp(double(pm), pe) * a2;
-      const double u = rng_uniform(w.w[1], w.w[2]);
-      const int accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
-      if (accept) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int j = lane + 64 * r;
-          if (j < M) {
-            V<double, C> wi = vload<double, C>(tb.Wt, int64_t(i) * M + j);
-            if (!flip) wi = vsub(wi, vload<double, C>(tb.Wt, int64_t(k) * M + j));
-            thr[r] -= 2.0 * double(s) * wi.re;
-            if (C) thi[r] -= 2.0 * double(s) * wi.im;
-            t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
-          }
-        }
-        if (lane == 0) {
-          sig[i] = int8_t(-s);
-          if (!flip) sig[k] = int8_t(s);
-        }
-        wave_sync();
-        ++acc_count;
-      }
-    }
-    if (sw >= n_discard) {
-      int8_t *dst = samples + (int64_t(sw - n_discard) * n_chains + chain) * N;
-      for (int i = lane; i < N; i += 64) dst[i] = sig[i];
-    }
-  }
-  for (int i = lane; i < N; i += 64) chain_sigma[int64_t(chain) * N + i] = sig[i];
-  if (lane == 0 && n_acc) n_acc[chain] = acc_count;
-}
-
-// ---------------------------------------------------------------------------------
-// Local energy (Eq. 5). One sample per wavefront. Lanes first build theta_j (double
-// accumulation) and tanh(theta_j) into LDS, then each lane takes one connected
-// configuration (a flipped site for TFIM, an anti-aligned bond for Heisenberg) and
-// multiplies its M ratio terms serially, reading the hidden-major tables so that the
-// lanes' loads are contiguous.
+// Local energy of one configuration (Eq. 5), evaluated by one wavefront: sig (LDS, N
+// spins) and tj (LDS, tanh theta_j) are given. Each lane takes connected configurations
+// (a flipped site for TFIM, an anti-aligned bond for Heisenberg) and multiplies their M
+// ratio terms serially from the hidden-major tables (contiguous across lanes). Returns
+// the wave-uniform (re, im) in double.
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
-__global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
-                                                       const int8_t *__restrict__ sigma,
-                                                       int64_t n, double *eloc, int Npad,
-                                                       int lds_wave_bytes) {
-  extern __shared__ int8_t lds_s8[];
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int64_t smp = int64_t(blockIdx.x) * (blockDim.x >> 6) + wid;
-  if (smp >= n) return;
+__device__ __forceinline__ void eloc_wave(const DevModel &dm, const Tables<T> &tb,
+                                          const int8_t *sig, const V<T, C> *tj, int lane,
+                                          double &out_re, double &out_im) {
   const int N = dm.N, M = dm.M, B = dm.Btot;
-  int8_t *base = lds_s8 + int64_t(wid) * lds_wave_bytes;
-  int8_t *sig = base;
-  V<T, C> *tj = reinterpret_cast<V<T, C> *>(base + Npad);
-  for (int i = lane; i < N; i += 64) sig[i] = sigma[smp * N + i];
-  wave_sync();
-  for (int j = lane; j < M; j += 64) {
-    V<double, C> acc = vload<double, C>(tb.bv, j);
-    for (int i = 0; i < N; ++i) {
-      double s = double(sig[i]);
-      V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
-      acc.re += s * w.re;
-      if (C) acc.im += s * w.im;
-    }
-    tj[j] = vtanh<T, C>(vmake<T, C>(T(acc.re), T(acc.im)));
-  }
-  wave_sync();
-
   double diag = 0.0;
   for (int b = lane; b < B; b += 64)
     diag += dm.bond_diag[b] * double(sig[dm.bonds[2 * b]]) * double(sig[dm.bonds[2 * b + 1]]);
-
   double er = 0.0, ei = 0.0;
   const bool tfim = dm.ham == NQS_TFIM;
   const int ncand = tfim ? (dm.h != 0.0 ? N : 0) : B;
@@ -323,7 +169,7 @@ __global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
       el = -dm.h;
       af = tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + c);
     } else {
-      int i = dm.bonds[2 * c], k = dm.bonds[2 * c + 1];
+      const int i = dm.bonds[2 * c], k = dm.bonds[2 * c + 1];
       s = sig[i];
       el = dm.bond_off[c];
       if (sig[k] == s || el == 0.0) continue;
@@ -335,32 +181,293 @@ __global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
     for (int j = 0; j < M; ++j) {
       V<T, C> cc = vload<T, C>(Ct, int64_t(j) * stride + c);
       V<T, C> ss = vload<T, C>(St, int64_t(j) * stride + c);
-      V<T, C> term = vsub(cc, vscale(vmul(tj[j], ss), ts));
-      p = vmul(p, term);
+      p = vmul(p, vsub(cc, vscale(vmul(tj[j], ss), ts)));
       if ((j & 3) == 3) vrenorm(p, pe);
     }
     vrenorm(p, pe);
-    double rr = ldexp(double(p.re), pe), ri = C ? ldexp(double(p.im), pe) : 0.0;
-    // times exp(visible-bias change)
-    double fr = rr * af[0] - ri * af[1], fi = rr * af[1] + ri * af[0];
-    er += el * fr;
-    ei += el * fi;
+    const double rr = ldexp(double(p.re), pe), ri = C ? ldexp(double(p.im), pe) : 0.0;
+    er += el * (rr * af[0] - ri * af[1]);
+    ei += el * (rr * af[1] + ri * af[0]);
   }
-  diag = wave_sum(diag);
-  er = wave_sum(er);
-  ei = wave_sum(ei);
+  out_re = wave_sum_dpp(diag) + wave_sum_dpp(er);
+  out_im = C ? wave_sum_dpp(ei) : 0.0;
+}
+
+// ---------------------------------------------------------------------------------
+// Metropolis sweeps. One chain per wavefront; lane l owns hidden units l + 64 r (r < R):
+// theta_j cached in double (exact running sums of +/-2 W), t_j = tanh(theta_j) in T.
+// A proposal costs R ratio terms per lane (C - s t S), a DPP product reduction carried as
+// mantissa x 2^exponent, and a wave-uniform accept decision in double. On acceptance
+// theta moves by -2 s W_row and t by the addition formula t' = (C t - s S) / term, whose
+// denominator is the ratio term already computed; t is recomputed from theta at the end
+// of every sweep, so rounding does not accumulate over sweeps. Spins live in LDS; the
+// move tables (C, S, W rows) are staged in LDS when they fit (TL), and the rows of the
+// next proposal are fetched one step ahead (the counter-based stream makes it known).
+// After each recorded sweep the chain's local energy is evaluated from its cached t.
+// ---------------------------------------------------------------------------------
+struct SweepArgs {
+  int8_t *chain_sigma;
+  int n_chains, n_sweeps, n_discard;
+  uint32_t k0, k1, counter, chain_offset;
+  int8_t *samples;
+  int64_t *n_acc;
+  double *eloc;
+  int tab_rows;      // rows of the move tables (N for flips, B0 for exchanges)
+  int wave_bytes;    // per-wavefront LDS: t (M values) then spins
+};
+
+template <typename T, bool C, int R, bool TL>
+__global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_u8[];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int chain = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wid);
+  const int N = dm.N, M = dm.M;
+  const int cs = C ? 2 : 1;
+  const bool flip = dm.move == NQS_MOVE_FLIP;
+  const int rows = a.tab_rows;
+  const T *gC = flip ? tb.fC : tb.bC;
+  const T *gS = flip ? tb.fS : tb.bS;
+  const T *gW = flip ? tb.Wt : tb.Wd;
+  T *lC = reinterpret_cast<T *>(lds_u8);
+  T *lS = lC + int64_t(rows) * M * cs;
+  T *lW = lS + int64_t(rows) * M * cs;
+  const int64_t tab_bytes = TL ? int64_t(3) * rows * M * cs * int64_t(sizeof(T)) : 0;
+  if constexpr (TL) {
+    const int64_t cnt = int64_t(rows) * M * cs;
+    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+      lC[e] = gC[e];
+      lS[e] = gS[e];
+      lW[e] = gW[e];
+    }
+    __syncthreads();
+  }
+  if (chain >= a.n_chains) return;
+  unsigned char *wbase = lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes;
+  V<T, C> *tj = reinterpret_cast<V<T, C> *>(wbase);
+  int8_t *sig = reinterpret_cast<int8_t *>(wbase + ((M * int(sizeof(V<T, C>)) + 15) / 16) * 16);
+  for (int i = lane; i < N; i += 64) sig[i] = a.chain_sigma[int64_t(chain) * N + i];
+  wave_sync();
+
+  auto row_ld = [&](const T *lp, const T *gp, int row, int j) -> V<T, C> {
+    if constexpr (TL)
+      return vload<T, C>(lp, int64_t(row) * M + j);
+    else
+      return vload<T, C>(gp, int64_t(row) * M + j);
+  };
+
+  double thr[R], thi[R];
+  V<T, C> t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = lane + 64 * r;
+    thr[r] = 0.0;
+    thi[r] = 0.0;
+    t[r] = vmake<T, C>(T(0), T(0));
+    if (j < M) {
+      V<double, C> acc = vload<double, C>(tb.bv, j);
+      for (int i = 0; i < N; ++i) {
+        const double s = double(sig[i]);
+        V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
+        acc.re += s * w.re;
+        if (C) acc.im += s * w.im;
+      }
+      thr[r] = acc.re;
+      thi[r] = C ? acc.im : 0.0;
+      t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
+    }
+  }
+
+  const uint32_t cid = a.chain_offset + uint32_t(chain);
+  const int total = a.n_discard + a.n_sweeps;
+  // proposal (sweep, step) -> random words, table row and the sites it touches
+  auto propose = [&](int sw, int st, Philox4 &w, int &row, int &i, int &k) {
+    w = philox4x32_10(cid, a.counter + uint32_t(sw), uint32_t(st), TAG_PROPOSAL, a.k0, a.k1);
+    if (flip) {
+      i = rng_index(w.w[0], uint32_t(N));
+      row = i;
+      k = i;
+    } else {
+      row = rng_index(w.w[0], uint32_t(dm.B0));
+      i = dm.bonds[2 * row];
+      k = dm.bonds[2 * row + 1];
+    }
+  };
+  // with few hidden units per lane the next proposal's rows are fetched one step ahead;
+  // with many, the R independent loads of a step already overlap
+  constexpr bool PF = R <= 4;
+  constexpr int RP = PF ? R : 1;
+  Philox4 wc;
+  int rowc = 0, ic = 0, kc = 0;
+  V<T, C> cc[R], ss[R], ww[R];
+  auto load_rows = [&](int row, V<T, C> *c_, V<T, C> *s_, V<T, C> *w_) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = lane + 64 * r < M ? lane + 64 * r : 0;
+      c_[r] = row_ld(lC, gC, row, j);
+      s_[r] = row_ld(lS, gS, row, j);
+      w_[r] = row_ld(lW, gW, row, j);
+    }
+  };
+  if constexpr (PF) {
+    propose(0, 0, wc, rowc, ic, kc);
+    load_rows(rowc, cc, ss, ww);
+  }
+  int64_t acc_count = 0;
+  for (int sw = 0; sw < total; ++sw) {
+    for (int st = 0; st < N; ++st) {
+      Philox4 wn = wc;
+      int rown = rowc, in_ = ic, kn = kc;
+      V<T, C> nc[RP], ns[RP], nw[RP];
+      if constexpr (PF) {
+        int nsw = sw, nst = st + 1;
+        if (nst == N) {
+          nst = 0;
+          ++nsw;
+        }
+        if (nsw < total) propose(nsw, nst, wn, rown, in_, kn);
+        load_rows(rown, nc, ns, nw);
+      } else {
+        propose(sw, st, wc, rowc, ic, kc);
+        load_rows(rowc, cc, ss, ww);
+      }
+
+      const int s = __builtin_amdgcn_readfirstlane(int(sig[ic]));
+      const int sk = flip ? -s : __builtin_amdgcn_readfirstlane(int(sig[kc]));
+      if (sk != s) {  // an exchange of equal spins is the identity move
+        const T ts = T(s);
+        V<T, C> term[R];
+        T pm = T(1);
+        int pe = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          term[r] = vsub(cc[r], vscale(vmul(t[r], ss[r]), ts));
+          if (lane + 64 * r < M) pm *= vabs2(term[r]);
+          if ((r & 3) == 3) {
+            int e;
+            pm = nfrexp(pm, &e);
+            pe += e;
+          }
+        }
+        {
+          int e;
+          pm = nfrexp(pm, &e);
+          pe += e;
+        }
+        const T pmw = wave_prod_dpp(pm, pe);
+        const double *af = flip ? tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + rowc)
+                                : tb.ba + 2 * (int64_t(s > 0 ? 0 : 1) * dm.Btot + rowc);
+        const double q = ldexp(double(pmw), pe) * (af[0] * af[0] + af[1] * af[1]);
+        const double u = rng_uniform(wc.w[1], wc.w[2]);
+        const int accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
+        if (accept) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (lane + 64 * r < M) {
+              thr[r] -= 2.0 * double(s) * double(ww[r].re);
+              if (C) thi[r] -= 2.0 * double(s) * double(ww[r].im);
+              t[r] = vdiv(vsub(vmul(cc[r], t[r]), vscale(ss[r], ts)), term[r]);
+            }
+          }
+          if (lane == 0) {
+            sig[ic] = int8_t(-s);
+            if (!flip) sig[kc] = int8_t(s);
+          }
+          wave_sync();
+          ++acc_count;
+        }
+      }
+      if constexpr (PF) {
+        wc = wn;
+        rowc = rown;
+        ic = in_;
+        kc = kn;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          cc[r] = nc[r];
+          ss[r] = ns[r];
+          ww[r] = nw[r];
+        }
+      }
+    }
+    // end of sweep: tanh from the exact angles
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane + 64 * r < M) t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
+    if (sw >= a.n_discard) {
+      const int64_t smp = int64_t(sw - a.n_discard) * a.n_chains + chain;
+      int8_t *dst = a.samples + smp * N;
+      for (int i = lane; i < N; i += 64) dst[i] = sig[i];
+      if (a.eloc) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (lane + 64 * r < M) tj[lane + 64 * r] = t[r];
+        wave_sync();
+        double er, ei;
+        eloc_wave<T, C>(dm, tb, sig, tj, lane, er, ei);
+        if (lane == 0) {
+          if (C) {
+            a.eloc[2 * smp] = er;
+            a.eloc[2 * smp + 1] = ei;
+          } else {
+            a.eloc[smp] = er;
+          }
+        }
+        wave_sync();
+      }
+    }
+  }
+  for (int i = lane; i < N; i += 64) a.chain_sigma[int64_t(chain) * N + i] = sig[i];
+  if (lane == 0 && a.n_acc) a.n_acc[chain] = acc_count;
+}
+
+// ---------------------------------------------------------------------------------
+// Local energy of arbitrary configurations. One sample per wavefront: theta in double,
+// tanh into LDS, then eloc_wave.
+// ---------------------------------------------------------------------------------
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
+                                                       const int8_t *__restrict__ sigma,
+                                                       int64_t n, double *eloc, int Npad,
+                                                       int lds_wave_bytes) {
+  extern __shared__ __align__(16) unsigned char lds_u8[];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int64_t smp = int64_t(blockIdx.x) * (blockDim.x >> 6) + wid;
+  if (smp >= n) return;
+  const int N = dm.N, M = dm.M;
+  unsigned char *base = lds_u8 + int64_t(wid) * lds_wave_bytes;
+  int8_t *sig = reinterpret_cast<int8_t *>(base);
+  V<T, C> *tj = reinterpret_cast<V<T, C> *>(base + Npad);
+  for (int i = lane; i < N; i += 64) sig[i] = sigma[smp * N + i];
+  wave_sync();
+  for (int j = lane; j < M; j += 64) {
+    V<double, C> acc = vload<double, C>(tb.bv, j);
+    for (int i = 0; i < N; ++i) {
+      double s = double(sig[i]);
+      V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
+      acc.re += s * w.re;
+      if (C) acc.im += s * w.im;
+    }
+    tj[j] = vtanh<T, C>(vmake<T, C>(T(acc.re), T(acc.im)));
+  }
+  wave_sync();
+  double er, ei;
+  eloc_wave<T, C>(dm, tb, sig, tj, lane, er, ei);
   if (lane == 0) {
     if (C) {
-      eloc[2 * smp] = diag + er;
+      eloc[2 * smp] = er;
       eloc[2 * smp + 1] = ei;
     } else {
-      eloc[smp] = diag + er;
+      eloc[smp] = er;
     }
   }
 }
 
 // ---------------------------------------------------------------------------------
-// log psi. One sample per wavefront; theta in double, ln cosh in T, sums in double.
+// log psi. One sample per wavefront; theta, ln cosh and the sums in double for every
+// compute precision (near the complex zeros of cosh theta, rounding theta to FP32 alone
+// would dominate the error; log psi is not on the sampling or SR path).
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_log_psi(DevModel dm, Tables<T> tb,
@@ -384,9 +491,9 @@ __global__ __launch_bounds__(256) void k_log_psi(DevModel dm, Tables<T> tb,
       acc.re += s * w.re;
       if (C) acc.im += s * w.im;
     }
-    V<T, C> lc = vlncosh<T, C>(vmake<T, C>(T(acc.re), T(acc.im)));
-    lr += double(lc.re);
-    if (C) li += double(lc.im);
+    V<double, C> lc = vlncosh<double, C>(acc);
+    lr += lc.re;
+    if (C) li += lc.im;
   }
   for (int i = lane; i < N; i += 64) {
     lr += tb.av[2 * i] * double(sig[i]);
@@ -420,6 +527,7 @@ Tables<T> tables_of(const nqs_model *m) {
   tb.fa = (double *)m->tab_ptrs[10];
   tb.ba = (double *)m->tab_ptrs[11];
   tb.av = (double *)m->tab_ptrs[12];
+  tb.Wd = (T *)m->tab_ptrs[13];
   return tb;
 }
 
@@ -445,26 +553,44 @@ hipError_t tables_t(const nqs_model *m, const void *params, hipStream_t st) {
 template <typename T, bool C, int R>
 hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, int n_discard,
                    uint64_t seed, uint64_t counter, int chain_offset, int8_t *samples,
-                   int64_t *n_acc, hipStream_t st) {
+                   int64_t *n_acc, void *eloc, hipStream_t st) {
   const int wpb = 4;
-  int Npad = round_up(m->N, 4);
+  SweepArgs a;
+  a.chain_sigma = cs;
+  a.n_chains = n_chains;
+  a.n_sweeps = n_sweeps;
+  a.n_discard = n_discard;
+  a.k0 = uint32_t(seed & 0xffffffffu);
+  a.k1 = uint32_t(seed >> 32);
+  a.counter = uint32_t(counter);
+  a.chain_offset = uint32_t(chain_offset);
+  a.samples = samples;
+  a.n_acc = n_acc;
+  a.eloc = (double *)eloc;
+  a.tab_rows = m->move == NQS_MOVE_FLIP ? m->N : m->B[0];
+  a.wave_bytes = round_up(m->M * int(sizeof(V<T, C>)), 16) + round_up(m->N, 16);
+  const size_t wave_lds = size_t(wpb) * a.wave_bytes;
+  const size_t tab_lds = size_t(3) * a.tab_rows * m->M * sizeof(T) * (C ? 2 : 1);
   dim3 grid((n_chains + wpb - 1) / wpb);
-  hipLaunchKernelGGL((k_sweep<T, C, R>), grid, dim3(64 * wpb), size_t(wpb) * Npad, st,
-                     dev_model(m), tables_of<T>(m), cs, n_chains, n_sweeps, n_discard,
-                     uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), uint32_t(counter),
-                     uint32_t(chain_offset), samples, n_acc, Npad);
+  if (tab_lds + wave_lds <= size_t(m->max_lds)) {
+    hipLaunchKernelGGL((k_sweep<T, C, R, true>), grid, dim3(64 * wpb), tab_lds + wave_lds, st,
+                       dev_model(m), tables_of<T>(m), a);
+  } else {
+    hipLaunchKernelGGL((k_sweep<T, C, R, false>), grid, dim3(64 * wpb), wave_lds, st,
+                       dev_model(m), tables_of<T>(m), a);
+  }
   return hipGetLastError();
 }
 
 template <typename T, bool C>
 hipError_t sweep_t(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, int n_discard,
                    uint64_t seed, uint64_t counter, int chain_offset, int8_t *samples,
-                   int64_t *n_acc, hipStream_t st) {
+                   int64_t *n_acc, void *eloc, hipStream_t st) {
   int r = (m->M + 63) / 64;
 #define NQS_SWEEP_CASE(RR)                                                                 \
   if (r <= RR)                                                                             \
     return sweep_r<T, C, RR>(m, cs, n_chains, n_sweeps, n_discard, seed, counter,          \
-                             chain_offset, samples, n_acc, st);
+                             chain_offset, samples, n_acc, eloc, st);
   NQS_SWEEP_CASE(1)
   NQS_SWEEP_CASE(2)
   NQS_SWEEP_CASE(4)
@@ -531,10 +657,8 @@ hipError_t launch_chain_init(const nqs_model *m, int8_t *sig, int n_chains, uint
 hipError_t launch_sweep(const nqs_model *m, int8_t *chain_sigma, int n_chains, int n_sweeps,
                         int n_discard, uint64_t seed, uint64_t counter, int chain_offset,
                         int8_t *samples, int64_t *n_acc, void *eloc, hipStream_t st) {
-  hipError_t e = NQS_DISPATCH(sweep_t, m, chain_sigma, n_chains, n_sweeps, n_discard, seed,
-                              counter, chain_offset, samples, n_acc, st);
-  if (e != hipSuccess || !eloc) return e;
-  return NQS_DISPATCH(eloc_t, m, samples, int64_t(n_sweeps) * n_chains, eloc, st);
+  return NQS_DISPATCH(sweep_t, m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter,
+                      chain_offset, samples, n_acc, eloc, st);
 }
 
 hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,

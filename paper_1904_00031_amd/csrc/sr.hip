@@ -326,6 +326,8 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   hipLaunchKernelGGL((k_center_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
                      (const double *)eloc, D(L.e_part), nb, D(L.u), D(L.e_part2), state);
   HIPTRY(hipGetLastError());
+  // tanh(theta) of every sample, kept for all products of this step
+  HIPTRY(launch_theta_tanh(m, sigma, n, grad, st));
   // O^dagger 1 (centring of S v), then g = O^dagger u (force numerator)
   hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, D(L.y));
   HIPTRY(hipGetLastError());

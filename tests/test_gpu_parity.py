@@ -26,7 +26,7 @@ def wrap(d):
 @pytest.mark.parametrize("name", ALL)
 def test_log_psi(lib, name):
     m, om = cases.build(lib, name)
-    p = cases.params(name, sigma=0.2)
+    p = cases.params(name)
     s = cases.configs(name, 301, seed=5)
     got = m.log_psi(to_dev(p), to_dev(s)).cpu().numpy()
     exp = orbm.log_psi(p.astype(np.complex128 if m.is_complex else np.float64), s, om.n_sites, om.n_hidden)
@@ -37,10 +37,10 @@ def test_log_psi(lib, name):
 
 
 @pytest.mark.parametrize("name", ALL)
-@pytest.mark.parametrize("sigma", [0.01, 0.3])
-def test_local_energy(lib, name, sigma):
+@pytest.mark.parametrize("init", ["paper_init", "trained_scale"])
+def test_local_energy(lib, name, init):
     m, om = cases.build(lib, name)
-    p = cases.params(name, sigma=sigma, seed=11)
+    p = cases.params(name, sigma=0.01, seed=11) if init == "paper_init" else cases.params(name, seed=11)
     s = cases.configs(name, 203, seed=6)
     got = m.local_energy(to_dev(p), to_dev(s)).cpu().numpy()
     exp = oh.local_energy(om, p.astype(np.complex128 if m.is_complex else np.float64), s)
@@ -63,7 +63,7 @@ def test_local_energy_empty_and_single(lib):
 @pytest.mark.parametrize("name", ALL)
 def test_jvp_vjp(lib, name):
     m, om = cases.build(lib, name)
-    p = cases.params(name, sigma=0.2, seed=21)
+    p = cases.params(name, seed=21)
     n = 517
     s = cases.configs(name, n, seed=7)
     rng = np.random.default_rng(3)
@@ -115,7 +115,7 @@ def _compare_chains(got, exp, ties, n_sweeps):
                                          ("heis40_cplx_f32", 1e-4), ("tfim37_real_f32", 1e-4)])
 def test_sampling_matches_oracle(lib, name, margin):
     m, om = cases.build(lib, name)
-    p = cases.params(name, sigma=0.25, seed=31)
+    p = cases.params(name, seed=31)
     C, n_sweeps, n_discard = 24, 6, 3
     ch = torch.empty((C, om.n_sites), dtype=torch.int8, device=DEV)
     m.chain_init(ch, seed=1234)
@@ -136,7 +136,7 @@ def test_sampling_matches_oracle(lib, name, margin):
 def test_sampling_resume_is_bit_exact(lib):
     """Two calls of 3 sweeps (counter advanced) equal one call of 6 sweeps."""
     m, om = cases.build(lib, "heis40_cplx_f64")
-    p = to_dev(cases.params("heis40_cplx_f64", sigma=0.2))
+    p = to_dev(cases.params("heis40_cplx_f64"))
     ch1 = torch.empty((40, 40), dtype=torch.int8, device=DEV)
     m.chain_init(ch1, seed=5)
     ch2 = ch1.clone()
@@ -150,7 +150,7 @@ def test_sampling_resume_is_bit_exact(lib):
 @pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f32", "heis40_cplx_f64", "j1j2_4x4_cplx_f64"])
 def test_fused_local_energy_matches_oracle(lib, name):
     m, om = cases.build(lib, name)
-    p = cases.params(name, sigma=0.2, seed=41)
+    p = cases.params(name, seed=41)
     C = 37
     ch = torch.empty((C, om.n_sites), dtype=torch.int8, device=DEV)
     m.chain_init(ch, seed=3)
@@ -161,12 +161,27 @@ def test_fused_local_energy_matches_oracle(lib, name):
     assert np.abs(el.cpu().numpy() - exp).max() <= cases.tol(name) * scale
 
 
+def cg_sensitivity(O, el, shift, iters, rel=1e-15, seed=0):
+    """How far the oracle's own CG result moves when every matrix-vector product is
+    perturbed by `rel` relative noise: finite-precision CG amplifies rounding by a factor
+    that grows with the condition number of S + shift I."""
+    F = osr.force(O, el)
+    A = osr.s_matrix(O) + shift * np.eye(O.shape[1])
+    x0, _, _ = osr.cg(lambda v: A @ v, F, 0.0, iters)
+    rng = np.random.default_rng(seed)
+    x1, _, _ = osr.cg(lambda v: (A @ v) * (1 + rel * rng.normal(size=v.shape)), F, 0.0, iters)
+    return np.abs(x1 - x0).max() / np.abs(x0).max()
+
+
 @pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f64", "j1j2_4x4_cplx_f64", "tfim5x5_j2_real_f64"])
 def test_sr_step_fixed_iterations(lib, name):
-    """Both sides run exactly k CG products (tol = 0): energy, variance and the updated
-    parameters agree to 1e-9 (FP64 CG, FP64 matrix-vector products)."""
+    """Both sides run exactly 12 CG products (tol = 0) in FP64. Energy, variance and force
+    agree to 1e-10/1e-9; the step agrees to 1e-9 or to 10x the oracle's own CG
+    sensitivity to 1e-15 relative product noise, whichever is larger (with n = 700 < P
+    for the 40-site case, S + 0.01 I has condition number ~1e4 and 12 CG steps amplify
+    rounding to ~1e-6)."""
     m, om = cases.build(lib, name)
-    p = cases.params(name, sigma=0.1, seed=51)
+    p = cases.params(name, theta=0.5, seed=51)
     n = 700
     s = cases.configs(name, n, seed=8)
     pe = p.astype(np.complex128 if m.is_complex else np.float64)
@@ -179,8 +194,12 @@ def test_sr_step_fixed_iterations(lib, name):
     assert abs(info["energy_re"] - np.real(E)) <= 1e-10 * max(1, abs(E))
     assert abs(info["variance"] - info_o["variance"]) <= 1e-9 * max(1, info_o["variance"])
     assert abs(info["force_norm"] - np.linalg.norm(info_o["force"])) <= 1e-9 * np.linalg.norm(info_o["force"])
+    O = orbm.log_derivatives(pe, s, om.n_sites, om.n_hidden)
+    if not m.is_complex:
+        O = O.real
+    tol = max(1e-9, 10 * cg_sensitivity(O, el, 0.01, 12))
     dx = pt.cpu().numpy() - p_new
-    assert np.abs(dx).max() <= 1e-9 * np.abs(p_new - pe).max()
+    assert np.abs(dx).max() <= tol * np.abs(p_new - pe).max()
 
 
 @pytest.mark.parametrize("name", ["heis40_cplx_f32", "j1j2_4x4_cplx_f32", "tfim37_real_f32"])
@@ -189,7 +208,7 @@ def test_sr_step_fp32_products(lib, name):
     oracle to 1e-4 of its size (FP32 rounding, amplified by at most the condition number
     of S + 0.01 I over 12 iterations)."""
     m, om = cases.build(lib, name)
-    p = cases.params(name, sigma=0.1, seed=52)
+    p = cases.params(name, theta=0.3, seed=52)
     n = 640
     s = cases.configs(name, n, seed=9)
     pe = p.astype(np.complex128 if m.is_complex else np.float64)
@@ -204,7 +223,7 @@ def test_sr_step_fp32_products(lib, name):
 
 def test_sr_step_converged_and_notconv(lib):
     m, om = cases.build(lib, "tfim10_real_f64")
-    p = cases.params("tfim10_real_f64", sigma=0.1, seed=53)
+    p = cases.params("tfim10_real_f64", theta=0.5, seed=53)
     s = cases.configs("tfim10_real_f64", 400, seed=10)
     el = oh.local_energy(om, p, s)
     pt = to_dev(p.copy())
