@@ -194,10 +194,10 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
                       m->need_flip ? NM * es : 0,
                       m->need_bond ? BM * es : 0,
                       m->need_bond ? BM * es : 0,
-                      m->need_flip ? NM * es : 0,
-                      m->need_flip ? NM * es : 0,
-                      m->need_bond ? BM * es : 0,
-                      m->need_bond ? BM * es : 0,
+                      0,
+                      0,
+                      0,
+                      0,
                       size_t(m->N) * 32,
                       nb * 32,
                       size_t(m->N) * 16,

@@ -91,6 +91,11 @@ __device__ __forceinline__ void fsincos(double x, double *s, double *c) { sincos
 __device__ __forceinline__ float fatan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double fatan2(double y, double x) { return atan2(y, x); }
 
+// reciprocal: the hardware v_rcp_f32 (1 ulp) in single precision, correctly rounded
+// division in double
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+
 template <typename T, bool C>
 __device__ __forceinline__ V<T, C> vtanh(V<T, C> z) {
   T ax = z.re < T(0) ? -z.re : z.re;
@@ -100,10 +105,10 @@ __device__ __forceinline__ V<T, C> vtanh(V<T, C> z) {
     T s2, c2;
     fsincos(T(2) * z.im, &s2, &c2);
     T d = T(1) + e * e + T(2) * e * c2;
-    T inv = T(1) / d;
+    T inv = frcp(d);
     return vmake<T, C>(sg * (T(1) - e * e) * inv, T(2) * e * s2 * inv);
   } else {
-    return vmake<T, C>(sg * (T(1) - e) / (T(1) + e), T(0));
+    return vmake<T, C>(sg * (T(1) - e) * frcp(T(1) + e), T(0));
   }
 }
 
@@ -281,13 +286,42 @@ __device__ __forceinline__ T wave_prod_dpp(T mant, int &ex) {
   return (readlane_v(mant, 0) * readlane_v(mant, 16)) * (readlane_v(mant, 32) * readlane_v(mant, 48));
 }
 
+// wave-uniform complex product of per-lane values p * 2^ex, each normalised by vrenorm;
+// the result is renormalised (mantissa with max(|re|, |im|) in [0.5, 1), exponent ex)
+template <typename T, bool C, int CTRL>
+__device__ __forceinline__ void cprod_step(V<T, C> &p, int &ex) {
+  V<T, C> q = vmake<T, C>(dpp_v<CTRL>(p.re), C ? dpp_v<CTRL>(p.im) : T(0));
+  ex += dpp_i<CTRL>(ex);
+  p = vmul(p, q);
+}
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> wave_cprod_dpp(V<T, C> p, int &ex) {
+  // inside a row: 4 steps, magnitudes stay within [2^-8, 2^4] of the normalised inputs
+  cprod_step<T, C, DPP_QP_XOR1>(p, ex);
+  cprod_step<T, C, DPP_QP_XOR2>(p, ex);
+  cprod_step<T, C, DPP_ROR4>(p, ex);
+  cprod_step<T, C, DPP_ROR8>(p, ex);
+  vrenorm(p, ex);
+  V<T, C> acc = vmake<T, C>(readlane_v(p.re, 0), C ? readlane_v(p.im, 0) : T(0));
+  int e = __builtin_amdgcn_readlane(ex, 0);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    V<T, C> q = vmake<T, C>(readlane_v(p.re, 16 * row), C ? readlane_v(p.im, 16 * row) : T(0));
+    e += __builtin_amdgcn_readlane(ex, 16 * row);
+    acc = vmul(acc, q);
+    vrenorm(acc, e);
+  }
+  ex = e;
+  return acc;
+}
+
 template <typename T, bool C>
 __device__ __forceinline__ V<T, C> vdiv(V<T, C> a, V<T, C> b) {
   if constexpr (C) {
-    T inv = T(1) / (b.re * b.re + b.im * b.im);
+    T inv = frcp(b.re * b.re + b.im * b.im);
     return vmake<T, C>((a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv);
   } else {
-    return vmake<T, C>(a.re / b.re, T(0));
+    return vmake<T, C>(a.re * frcp(b.re), T(0));
   }
 }
 
@@ -318,10 +352,6 @@ struct Tables {
   T *fS;    // [N][M]    sinh(2 W_ji)
   T *bC;    // [Btot][M] cosh(2 (W_ji - W_jk))  (exchange on bond (i, k))
   T *bS;    // [Btot][M] sinh(2 (W_ji - W_jk))
-  T *fCt;   // [M][N]    hidden-major copies, for lanes over connected configurations
-  T *fSt;
-  T *bCt;   // [M][Btot]
-  T *bSt;
   double *fa;  // [2][N]    exp(-2 s a_i),           s = +1 -> row 0, s = -1 -> row 1
   double *ba;  // [2][Btot] exp(-2 s (a_i - a_k)),   s = sigma_i
   double *av;  // [N]       a (double)

@@ -324,6 +324,215 @@ __global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
     }
 }
 
+// sum over the 16 lanes of each DPP row (every lane of the row receives the total)
+template <typename T>
+__device__ __forceinline__ T rowsum16(T x) {
+  x += dpp_v<DPP_QP_XOR1>(x);
+  x += dpp_v<DPP_QP_XOR2>(x);
+  x += dpp_v<DPP_ROR4>(x);
+  x += dpp_v<DPP_ROR8>(x);
+  return x;
+}
+
+// ---------------------------------------------------------------------------------
+// Fused S v product for shapes whose whole VJP output fits one block's tiles
+// (ceil((M+1)/16) <= JT and ceil((N+1)/16) <= NT). Per 16-sample group a wavefront
+//   1. forms y_s = sum_j T_sj (vb_j + (S V^T)_sj) + sum_i s_si va_i (X by MFMA, the
+//      hidden-unit sum by DPP row reductions),
+//   2. accumulates O^dagger y with Z_sj = conj(T_sj) y_s over the same samples, while
+//      their T rows are still in cache,
+// so T is streamed from memory once per product. Output: one partial tile set per
+// block (as k_vjp) and the block's sum of y (complex double) for the centring.
+// Grid: sample splits. Vt is staged in LDS when VL.
+// ---------------------------------------------------------------------------------
+template <typename T, bool C, int JT, int NT>
+__global__ __launch_bounds__(256) void k_sv(int N, int M, int64_t n,
+                                             const int8_t *__restrict__ sigma,
+                                             const T *__restrict__ Tm, const T *__restrict__ Vt_g,
+                                             const T *__restrict__ vb,
+                                             const double *__restrict__ va, int64_t per_split,
+                                             int rowsP, int colsP, T *part, double *ysum_part,
+                                             const int *skip) {
+  if (skip && *skip) return;
+  typedef typename MF<T>::acc Acc;
+  constexpr int cs = C ? 2 : 1;
+  constexpr int JW = JT * 16;  // padded hidden width of the staged direction
+  constexpr int SW = NT * 16;  // padded site width of the spin tile (>= N + 1)
+  extern __shared__ __align__(16) unsigned char lds_u8[];
+  __shared__ T red[4][4][64][cs];
+  __shared__ double dsum[2][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lo = lane & 15, hi = lane >> 4;
+  const int Kp = (N + 3) / 4 * 4;
+  // dynamic LDS: V^T zero-padded to [Kp][JW], then one 16 x SW spin tile per wavefront
+  T *Vl = reinterpret_cast<T *>(lds_u8);
+  const int64_t vbytes = (int64_t(Kp) * JW * cs * int64_t(sizeof(T)) + 15) / 16 * 16;
+  int8_t *stile = reinterpret_cast<int8_t *>(lds_u8 + vbytes) + wid * 16 * SW;
+  for (int e = threadIdx.x; e < Kp * JW; e += 256) {
+    const int k = e / JW, j = e % JW;
+    const V<T, C> v = (k < N && j < M) ? vload<T, C>(Vt_g, int64_t(k) * M + j)
+                                       : vmake<T, C>(T(0), T(0));
+    vstore<T, C>(Vl, e, v);
+  }
+  __syncthreads();
+  const int64_t sbeg = int64_t(blockIdx.x) * per_split;
+  const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
+  Acc ar[JT][NT], ai[JT][NT];
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      ar[a][b] = Acc{0, 0, 0, 0};
+      ai[a][b] = Acc{0, 0, 0, 0};
+    }
+  double ysr = 0.0, ysi = 0.0;
+  const int Mt = (M + 15) / 16;
+  // spin-tile fill: lane owns row lane/4 and columns lane%4 + 4 c
+  const int frow = lane >> 2, fcol = lane & 3;
+  for (int64_t g = sbeg + 16 * wid; g < send; g += 64) {
+    const int rows_here = send - g < 16 ? int(send - g) : 16;
+    // T tile of the group in the accumulator layout: lane (lo, hi) holds rows
+    // MF::row(hi, r), columns 16 a + lo. The same registers feed the JVP epilogue and,
+    // with the VJP samples of step q taken as row MF::row(hi, q), the VJP A operand.
+    V<T, C> tv[JT][4];
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      const int j = a * 16 + lo;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = MF<T>::row(hi, r);
+        tv[a][r] = (a < Mt && j < M && rr < rows_here) ? vload<T, C>(Tm, (g + rr) * M + j)
+                                                       : vmake<T, C>(T(0), T(0));
+      }
+    }
+    // spins of the 16 samples, zero-padded, with a column of ones at site N (hidden bias)
+    wave_sync();
+    {
+      const bool rok = frow < rows_here;
+      const int8_t *src = sigma + (g + (rok ? frow : 0)) * N;
+      for (int c = fcol; c < SW; c += 4) {
+        int8_t v = 0;
+        if (rok) v = c < N ? src[c] : (c == N ? int8_t(1) : int8_t(0));
+        stile[frow * SW + c] = v;
+      }
+    }
+    wave_sync();
+    // ---- y for rows g .. g+15: X = S V^T for all hidden tiles, A operand loaded once ----
+    Acc xr[JT], xi[JT];
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      xr[a] = Acc{0, 0, 0, 0};
+      xi[a] = Acc{0, 0, 0, 0};
+    }
+    for (int k0 = 0; k0 < Kp; k0 += 4) {
+      const int k = k0 + hi;
+      const T av = T(stile[lo * SW + k]);
+      V<T, C> v[JT];
+#pragma unroll
+      for (int a = 0; a < JT; ++a) v[a] = vload<T, C>(Vl, int64_t(k) * JW + a * 16 + lo);
+#pragma unroll
+      for (int a = 0; a < JT; ++a) {
+        xr[a] = MF<T>::mma(av, v[a].re, xr[a]);
+        if constexpr (C) xi[a] = MF<T>::mma(av, v[a].im, xi[a]);
+      }
+    }
+    V<T, C> yp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) yp[r] = vmake<T, C>(T(0), T(0));
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      const int j = a * 16 + lo;
+      const V<T, C> vbj = (a < Mt && j < M) ? vload<T, C>(vb, j) : vmake<T, C>(T(0), T(0));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        V<T, C> x = vmake<T, C>(xr[a][r] + vbj.re, C ? xi[a][r] + vbj.im : T(0));
+        yp[r] = vadd(yp[r], vmul(tv[a][r], x));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = MF<T>::row(hi, r);
+      for (int i = lo; i < N; i += 16) {
+        const T si = T(stile[rr * SW + i]);
+        yp[r].re += si * T(va[2 * i]);
+        if constexpr (C) yp[r].im += si * T(va[2 * i + 1]);
+      }
+      yp[r].re = rowsum16(yp[r].re);
+      if constexpr (C) yp[r].im = rowsum16(yp[r].im);
+      if (rr >= rows_here) yp[r] = vmake<T, C>(T(0), T(0));
+      if (lo == 0) {
+        ysr += double(yp[r].re);
+        if constexpr (C) ysi += double(yp[r].im);
+      }
+    }
+    // ---- accumulate O^dagger y over the same 16 samples (step q: row MF::row(hi, q)) ----
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = MF<T>::row(hi, q);
+      V<T, C> z[JT];
+#pragma unroll
+      for (int a = 0; a < JT; ++a) {
+        const int j = a * 16 + lo;
+        z[a] = j < M ? vmul(vconj(tv[a][q]), yp[q])
+                     : (j == M ? yp[q] : vmake<T, C>(T(0), T(0)));
+      }
+      T bs[NT];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) bs[b] = T(stile[rr * SW + b * 16 + lo]);
+#pragma unroll
+      for (int a = 0; a < JT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+          ar[a][b] = MF<T>::mma(z[a].re, bs[b], ar[a][b]);
+          if constexpr (C) ai[a][b] = MF<T>::mma(z[a].im, bs[b], ai[a][b]);
+        }
+    }
+  }
+  // block sums: partial tiles, then sum of y
+  const int tid = threadIdx.x;
+  const int r = tid >> 6, l = tid & 63;
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        red[wid][q][lane][0] = ar[a][b][q];
+        if constexpr (C) red[wid][q][lane][cs - 1] = ai[a][b][q];
+      }
+      __syncthreads();
+      const int jrow = a * 16 + MF<T>::row(l >> 4, r);
+      const int icol = b * 16 + (l & 15);
+      if (jrow < rowsP && icol < colsP) {
+        const int64_t o = (int64_t(blockIdx.x) * rowsP + jrow) * colsP + icol;
+        T sr = red[0][r][l][0] + red[1][r][l][0] + red[2][r][l][0] + red[3][r][l][0];
+        if constexpr (C) {
+          T si = red[0][r][l][cs - 1] + red[1][r][l][cs - 1] + red[2][r][l][cs - 1] +
+                 red[3][r][l][cs - 1];
+          part[2 * o] = sr;
+          part[2 * o + 1] = si;
+        } else {
+          part[o] = sr;
+        }
+      }
+    }
+  dsum[0][tid] = ysr;
+  dsum[1][tid] = ysi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      dsum[0][tid] += dsum[0][tid + w];
+      dsum[1][tid] += dsum[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ysum_part[2 * blockIdx.x] = dsum[0][0];
+    ysum_part[2 * blockIdx.x + 1] = dsum[1][0];
+  }
+}
+
 // first reduction level: out1[g][e] = sum of partials of split group g (complex double)
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_vjp_reduce1(int splits, int groups, int64_t elems,
@@ -494,6 +703,56 @@ hipError_t vjp_t(const nqs_model *m, const int8_t *sigma, int64_t n, const doubl
   return hipErrorInvalidValue;
 }
 
+template <typename T, bool C, int JT, int NT>
+hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                   double *ysum_part, const int *skip, hipStream_t st) {
+  GradPlan g = grad_plan(m, n);
+  GradLayout L = grad_layout(m, n);
+  char *base = (char *)scratch;
+  const int Kp = (m->N + 3) / 4 * 4;
+  const size_t vbytes = (size_t(Kp) * JT * 16 * sizeof(T) * (C ? 2 : 1) + 15) / 16 * 16;
+  const size_t tile_bytes = size_t(4) * 16 * NT * 16;
+  hipLaunchKernelGGL((k_sv<T, C, JT, NT>), dim3(unsigned(g.splits)), dim3(256),
+                     vbytes + tile_bytes, st, m->N, m->M, n, sigma, (const T *)(base + L.Tm),
+                     (const T *)(base + L.Vt), (const T *)(base + L.vb),
+                     (const double *)(base + L.va), g.per_split, g.Jtiles * 16, g.Itiles * 16,
+                     (T *)(base + L.part), ysum_part, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
+  hipLaunchKernelGGL((k_vjp_reduce1<T, C>), dim3(unsigned(cdiv(elems, 256)), g.groups),
+                     dim3(256), 0, st, g.splits, g.groups, elems, (const T *)(base + L.part),
+                     (double *)(base + L.out1), skip);
+  return hipGetLastError();
+}
+
+template <typename T, bool C>
+hipError_t sv_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                double *ysum_part, const int *skip, hipStream_t st) {
+  GradPlan g = grad_plan(m, n);
+#define NQS_SV_CASE(A, B) \
+  if (g.JT == A && g.NT == B) return sv_tile<T, C, A, B>(m, sigma, n, scratch, ysum_part, skip, st);
+  NQS_SV_CASE(1, 1)
+  NQS_SV_CASE(2, 1)
+  NQS_SV_CASE(4, 1)
+  NQS_SV_CASE(6, 1)
+  NQS_SV_CASE(8, 1)
+  NQS_SV_CASE(1, 2)
+  NQS_SV_CASE(2, 2)
+  NQS_SV_CASE(4, 2)
+  NQS_SV_CASE(6, 2)
+  NQS_SV_CASE(8, 2)
+  NQS_SV_CASE(1, 3)
+  NQS_SV_CASE(2, 3)
+  NQS_SV_CASE(4, 3)
+  NQS_SV_CASE(6, 3)
+  NQS_SV_CASE(1, 4)
+  NQS_SV_CASE(2, 4)
+  NQS_SV_CASE(4, 4)
+#undef NQS_SV_CASE
+  return hipErrorInvalidValue;
+}
+
 template <typename T, bool C>
 hipError_t vjp_reduce_t(const nqs_model *m, int64_t n, void *scratch, double *out,
                         const int *skip, hipStream_t st) {
@@ -532,6 +791,19 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
   if (splits > steps) splits = steps;
   g.per_split = rup(cdiv(n > 0 ? n : 1, splits), 16);
   g.splits = int(cdiv(n > 0 ? n : 1, g.per_split));
+  {
+    const size_t es = (use_double(m) ? 8 : 4) * (m->is_complex ? 2 : 1);
+    const size_t vbytes = size_t((m->N + 3) / 4 * 4) * g.JT * 16 * es;
+    g.fused = tile_blocks == 1 && vbytes <= 48 * 1024;
+  }
+  if (g.fused) {
+    // fused S v: blocks of 4 wavefronts x 16-sample groups
+    int64_t sp = 512;
+    const int64_t groups64 = n > 0 ? cdiv(n, 64) : 1;
+    if (sp > groups64) sp = groups64;
+    g.per_split = rup(cdiv(n > 0 ? n : 1, sp), 64);
+    g.splits = int(cdiv(n > 0 ? n : 1, g.per_split));
+  }
   g.groups = g.splits < 16 ? g.splits : 16;
   g.jchunks = int(cdiv((m->M + 15) / 16, 16));
   g.jvp_blocks = cdiv(n > 0 ? n : 1, 64);
@@ -564,6 +836,22 @@ hipError_t launch_vjp_partials(const nqs_model *m, const int8_t *sigma, int64_t 
                                const double *u, void *scratch, const int *skip,
                                hipStream_t st) {
   return NQS_DISPATCH(vjp_t, m, sigma, n, u, scratch, skip, st);
+}
+
+hipError_t launch_sv(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                     double *ysum_part, const int *skip, hipStream_t st) {
+  return NQS_DISPATCH(sv_t, m, sigma, n, scratch, ysum_part, skip, st);
+}
+
+GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch) {
+  GradLayout L = grad_layout(m, n);
+  char *base = (char *)scratch;
+  GradBuffers b;
+  b.Vt = base + L.Vt;
+  b.vb = base + L.vb;
+  b.va = (double *)(base + L.va);
+  b.out1 = (double *)(base + L.out1);
+  return b;
 }
 
 hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, double *out,

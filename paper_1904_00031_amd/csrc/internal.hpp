@@ -51,6 +51,7 @@ struct GradPlan {
   int splits;    // sample splits of the VJP (grid y)
   int64_t per_split;  // samples per split (multiple of 16)
   int groups;    // first-level reduction groups of the VJP partials
+  bool fused;    // all VJP tiles fit one block: S v in one pass (k_sv)
   int jchunks;   // hidden chunks of 16 tiles in the JVP / tanh kernels (grid y)
   int64_t jvp_blocks; // sample tiles of 64 in the JVP / tanh kernels
 };
@@ -70,6 +71,16 @@ hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *
 hipError_t launch_vjp_partials(const nqs_model *m, const int8_t *sigma, int64_t n,
                                const double *u, void *scratch, const int *skip,
                                hipStream_t st);
+// fused S v (requires plan.fused): partials of O^dagger y with y = O v, plus per-block sums
+// of y (complex double, plan.splits entries), then the first reduction level
+hipError_t launch_sv(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
+                     double *ysum_part, const int *skip, hipStream_t st);
+struct GradBuffers {
+  void *Vt, *vb;   // direction tables in compute precision
+  double *va;      // visible part of the direction, complex double
+  double *out1;    // first-level VJP sums [groups][Jtiles*16*Itiles*16] complex double
+};
+GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch);
 // out[k] = sum of partials (double, params layout)
 hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, double *out,
                              const int *skip, hipStream_t st);

@@ -49,8 +49,6 @@ __global__ void k_tables(DevModel dm, Tables<T> tb, const PT *__restrict__ p, in
         V<double, C> ss = vmake<double, C>(sh * cy, ch * sy);
         vstore<T, C>(tb.fC, int64_t(i) * M + j, vcast<double, C, T>(cc));
         vstore<T, C>(tb.fS, int64_t(i) * M + j, vcast<double, C, T>(ss));
-        vstore<T, C>(tb.fCt, int64_t(j) * N + i, vcast<double, C, T>(cc));
-        vstore<T, C>(tb.fSt, int64_t(j) * N + i, vcast<double, C, T>(ss));
       }
     } else if (e < nW + nB) {
       if (!need_bond) continue;
@@ -74,8 +72,6 @@ __global__ void k_tables(DevModel dm, Tables<T> tb, const PT *__restrict__ p, in
       V<double, C> ss = vmake<double, C>(sh * cy, ch * sy);
       vstore<T, C>(tb.bC, int64_t(b) * M + j, vcast<double, C, T>(cc));
       vstore<T, C>(tb.bS, int64_t(b) * M + j, vcast<double, C, T>(ss));
-      vstore<T, C>(tb.bCt, int64_t(j) * B + b, vcast<double, C, T>(cc));
-      vstore<T, C>(tb.bSt, int64_t(j) * B + b, vcast<double, C, T>(ss));
       if (tb.Wd && b < dm.B0) vstore<T, C>(tb.Wd, int64_t(b) * M + j, vcast<double, C, T>(vsub(wi, wk)));
     } else {
       int64_t q = e - nW - nB;
@@ -140,57 +136,172 @@ __global__ void k_init_sz0(int8_t *sig, int n_chains, int N, uint32_t k0, uint32
 }
 
 // ---------------------------------------------------------------------------------
-// Local energy of one configuration (Eq. 5), evaluated by one wavefront: sig (LDS, N
-// spins) and tj (LDS, tanh theta_j) are given. Each lane takes connected configurations
-// (a flipped site for TFIM, an anti-aligned bond for Heisenberg) and multiplies their M
-// ratio terms serially from the hidden-major tables (contiguous across lanes). Returns
-// the wave-uniform (re, im) in double.
+// Local energy of one configuration (Eq. 5), evaluated by one wavefront whose lane l
+// holds t_j = tanh(theta_j) for j = l + 64 r (r < R) in registers; the spins are in LDS.
+// Connected configurations (every site for TFIM, every anti-aligned bond with a nonzero
+// coupling for Heisenberg) are enumerated as a wave-uniform bit mask; for each one the
+// lanes form their ratio terms C_row,j - s t_j S_row,j from the row-major tables (LDS
+// when staged) and a DPP complex product gives psi(s')/psi(s) up to the visible-bias
+// factor. Accumulates in double; returns (re, im) on every lane.
 // ---------------------------------------------------------------------------------
-template <typename T, bool C>
-__device__ __forceinline__ void eloc_wave(const DevModel &dm, const Tables<T> &tb,
-                                          const int8_t *sig, const V<T, C> *tj, int lane,
-                                          double &out_re, double &out_im) {
+template <typename T, bool C, int R, bool TL>
+__device__ __forceinline__ void eloc_regs(const DevModel &dm, const Tables<T> &tb,
+                                          const int8_t *sig, const V<T, C> *t, int lane,
+                                          const T *lCe, const T *lSe, double &out_re,
+                                          double &out_im) {
   const int N = dm.N, M = dm.M, B = dm.Btot;
+  const bool tfim = dm.ham == NQS_TFIM;
+  const T *gCe = tfim ? tb.fC : tb.bC;
+  const T *gSe = tfim ? tb.fS : tb.bS;
   double diag = 0.0;
   for (int b = lane; b < B; b += 64)
     diag += dm.bond_diag[b] * double(sig[dm.bonds[2 * b]]) * double(sig[dm.bonds[2 * b + 1]]);
   double er = 0.0, ei = 0.0;
-  const bool tfim = dm.ham == NQS_TFIM;
   const int ncand = tfim ? (dm.h != 0.0 ? N : 0) : B;
-  const int stride = tfim ? N : B;
-  const T *Ct = tfim ? tb.fCt : tb.bCt;
-  const T *St = tfim ? tb.fSt : tb.bSt;
-  for (int c = lane; c < ncand; c += 64) {
-    int s;
-    double el;
-    const double *af;
-    if (tfim) {
-      s = sig[c];
-      el = -dm.h;
-      af = tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + c);
-    } else {
-      const int i = dm.bonds[2 * c], k = dm.bonds[2 * c + 1];
-      s = sig[i];
-      el = dm.bond_off[c];
-      if (sig[k] == s || el == 0.0) continue;
-      af = tb.ba + 2 * (int64_t(s > 0 ? 0 : 1) * B + c);
+  for (int c0 = 0; c0 < ncand; c0 += 64) {
+    // bit q of `mask`: configuration c0 + q is connected; bit q of `up`: its spin s = +1
+    const int c = c0 + lane;
+    bool on = false, sup = false;
+    if (c < ncand) {
+      if (tfim) {
+        on = true;
+        sup = sig[c] > 0;
+      } else {
+        const int si = sig[dm.bonds[2 * c]], sk = sig[dm.bonds[2 * c + 1]];
+        on = si != sk && dm.bond_off[c] != 0.0;
+        sup = si > 0;
+      }
     }
-    const T ts = T(s);
-    V<T, C> p = vmake<T, C>(T(1), T(0));
-    int pe = 0;
-    for (int j = 0; j < M; ++j) {
-      V<T, C> cc = vload<T, C>(Ct, int64_t(j) * stride + c);
-      V<T, C> ss = vload<T, C>(St, int64_t(j) * stride + c);
-      p = vmul(p, vsub(cc, vscale(vmul(tj[j], ss), ts)));
-      if ((j & 3) == 3) vrenorm(p, pe);
+    uint64_t mask = __ballot(on);
+    const uint64_t up = __ballot(sup);
+    while (mask) {
+      const int q = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const int row = c0 + q;
+      const int s = ((up >> q) & 1) ? 1 : -1;
+      const T ts = T(s);
+      V<T, C> p = vmake<T, C>(T(1), T(0));
+      int pe = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j = lane + 64 * r;
+        if (j < M) {
+          V<T, C> cc, ss;
+          if constexpr (TL) {
+            cc = vload<T, C>(lCe, int64_t(row) * M + j);
+            ss = vload<T, C>(lSe, int64_t(row) * M + j);
+          } else {
+            cc = vload<T, C>(gCe, int64_t(row) * M + j);
+            ss = vload<T, C>(gSe, int64_t(row) * M + j);
+          }
+          p = vmul(p, vsub(cc, vscale(vmul(t[r], ss), ts)));
+        }
+        if ((r & 3) == 3) vrenorm(p, pe);
+      }
+      vrenorm(p, pe);
+      const V<T, C> w = wave_cprod_dpp(p, pe);
+      const double el = tfim ? -dm.h : dm.bond_off[row];
+      const double *af = tfim ? tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + row)
+                              : tb.ba + 2 * (int64_t(s > 0 ? 0 : 1) * B + row);
+      const double rr = ldexp(double(w.re), pe), ri = C ? ldexp(double(w.im), pe) : 0.0;
+      er += el * (rr * af[0] - ri * af[1]);
+      ei += el * (rr * af[1] + ri * af[0]);
     }
-    vrenorm(p, pe);
-    const double rr = ldexp(double(p.re), pe), ri = C ? ldexp(double(p.im), pe) : 0.0;
-    er += el * (rr * af[0] - ri * af[1]);
-    ei += el * (rr * af[1] + ri * af[0]);
   }
-  out_re = wave_sum_dpp(diag) + wave_sum_dpp(er);
-  out_im = C ? wave_sum_dpp(ei) : 0.0;
+  out_re = wave_sum_dpp(diag) + er;
+  out_im = C ? ei : 0.0;
+}
+
+// ---------------------------------------------------------------------------------
+// Local energy with four connected configurations per pass (M <= 256): the 16 lanes of
+// DPP row g take configuration g of the pass, each lane multiplies the ratio terms of
+// hidden units j = lane%16 + 16 q (t_j read from LDS), and a 4-step DPP product inside
+// the row finishes each ratio. Same result as eloc_regs, a quarter of the reductions.
+// ---------------------------------------------------------------------------------
+template <typename T, bool C, bool TL>
+__device__ __forceinline__ void eloc_grouped(const DevModel &dm, const Tables<T> &tb,
+                                             const int8_t *sig, const V<T, C> *tj, int lane,
+                                             const T *lCe, const T *lSe, double &out_re,
+                                             double &out_im) {
+  const int N = dm.N, M = dm.M, B = dm.Btot;
+  const bool tfim = dm.ham == NQS_TFIM;
+  const T *gCe = tfim ? tb.fC : tb.bC;
+  const T *gSe = tfim ? tb.fS : tb.bS;
+  const int lo = lane & 15, g = lane >> 4;
+  double diag = 0.0;
+  for (int b = lane; b < B; b += 64)
+    diag += dm.bond_diag[b] * double(sig[dm.bonds[2 * b]]) * double(sig[dm.bonds[2 * b + 1]]);
+  double er = 0.0, ei = 0.0;
+  const int ncand = tfim ? (dm.h != 0.0 ? N : 0) : B;
+  for (int c0 = 0; c0 < ncand; c0 += 64) {
+    const int c = c0 + lane;
+    bool on = false, sup = false;
+    if (c < ncand) {
+      if (tfim) {
+        on = true;
+        sup = sig[c] > 0;
+      } else {
+        const int si = sig[dm.bonds[2 * c]], sk = sig[dm.bonds[2 * c + 1]];
+        on = si != sk && dm.bond_off[c] != 0.0;
+        sup = si > 0;
+      }
+    }
+    uint64_t mask = __ballot(on);
+    const uint64_t up = __ballot(sup);
+    while (mask) {
+      int q4[4], cnt = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        q4[u] = -1;
+        if (mask) {
+          q4[u] = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          ++cnt;
+        }
+      }
+      const int myq = g == 0 ? q4[0] : (g == 1 ? q4[1] : (g == 2 ? q4[2] : q4[3]));
+      V<T, C> p = vmake<T, C>(T(1), T(0));
+      int pe = 0;
+      if (myq >= 0) {
+        const int row = c0 + myq;
+        const T ts = ((up >> myq) & 1) ? T(1) : T(-1);
+        int k = 0;
+        for (int j = lo; j < M; j += 16, ++k) {
+          V<T, C> cc, ss;
+          if constexpr (TL) {
+            cc = vload<T, C>(lCe, int64_t(row) * M + j);
+            ss = vload<T, C>(lSe, int64_t(row) * M + j);
+          } else {
+            cc = vload<T, C>(gCe, int64_t(row) * M + j);
+            ss = vload<T, C>(gSe, int64_t(row) * M + j);
+          }
+          p = vmul(p, vsub(cc, vscale(vmul(tj[j], ss), ts)));
+          if ((k & 3) == 3) vrenorm(p, pe);
+        }
+      }
+      vrenorm(p, pe);
+      cprod_step<T, C, DPP_QP_XOR1>(p, pe);
+      cprod_step<T, C, DPP_QP_XOR2>(p, pe);
+      cprod_step<T, C, DPP_ROR4>(p, pe);
+      cprod_step<T, C, DPP_ROR8>(p, pe);
+      vrenorm(p, pe);
+      for (int u = 0; u < cnt; ++u) {
+        const int row = c0 + q4[u];
+        const int s = ((up >> q4[u]) & 1) ? 1 : -1;
+        const double wr = double(readlane_v(p.re, 16 * u));
+        const double wi = C ? double(readlane_v(p.im, 16 * u)) : 0.0;
+        const int we = __builtin_amdgcn_readlane(pe, 16 * u);
+        const double el = tfim ? -dm.h : dm.bond_off[row];
+        const double *af = tfim ? tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + row)
+                                : tb.ba + 2 * (int64_t(s > 0 ? 0 : 1) * B + row);
+        const double rr = ldexp(wr, we), ri = ldexp(wi, we);
+        er += el * (rr * af[0] - ri * af[1]);
+        ei += el * (rr * af[1] + ri * af[0]);
+      }
+    }
+  }
+  out_re = wave_sum_dpp(diag) + er;
+  out_im = C ? ei : 0.0;
 }
 
 // ---------------------------------------------------------------------------------
@@ -200,10 +311,12 @@ __device__ __forceinline__ void eloc_wave(const DevModel &dm, const Tables<T> &t
 // mantissa x 2^exponent, and a wave-uniform accept decision in double. On acceptance
 // theta moves by -2 s W_row and t by the addition formula t' = (C t - s S) / term, whose
 // denominator is the ratio term already computed; t is recomputed from theta at the end
-// of every sweep, so rounding does not accumulate over sweeps. Spins live in LDS; the
-// move tables (C, S, W rows) are staged in LDS when they fit (TL), and the rows of the
-// next proposal are fetched one step ahead (the counter-based stream makes it known).
-// After each recorded sweep the chain's local energy is evaluated from its cached t.
+// of every sweep, so rounding does not accumulate over sweeps. Spins live in LDS. When
+// TL, the C/S rows of every connected configuration (which then include the move rows)
+// and the W rows of the moves are staged in LDS; otherwise they are read from global
+// memory, with the next proposal's rows fetched one step ahead for small R (the
+// counter-based stream makes the next proposal known). After each recorded sweep the
+// chain's local energy is evaluated from its cached t.
 // ---------------------------------------------------------------------------------
 struct SweepArgs {
   int8_t *chain_sigma;
@@ -212,8 +325,10 @@ struct SweepArgs {
   int8_t *samples;
   int64_t *n_acc;
   double *eloc;
-  int tab_rows;      // rows of the move tables (N for flips, B0 for exchanges)
-  int wave_bytes;    // per-wavefront LDS: t (M values) then spins
+  int cs_rows;       // C/S rows staged when TL (N for TFIM, Btot for Heisenberg)
+  int w_rows;        // W rows of the moves (N for flips, B0 for exchanges)
+  int wave_bytes;    // per-wavefront LDS: spins (Npad bytes), then t (M values)
+  int Npad;
 };
 
 template <typename T, bool C, int R, bool TL>
@@ -223,33 +338,35 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
   const int wid = threadIdx.x >> 6;
   const int chain = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wid);
   const int N = dm.N, M = dm.M;
-  const int cs = C ? 2 : 1;
+  constexpr int cs = C ? 2 : 1;
   const bool flip = dm.move == NQS_MOVE_FLIP;
-  const int rows = a.tab_rows;
   const T *gC = flip ? tb.fC : tb.bC;
   const T *gS = flip ? tb.fS : tb.bS;
   const T *gW = flip ? tb.Wt : tb.Wd;
   T *lC = reinterpret_cast<T *>(lds_u8);
-  T *lS = lC + int64_t(rows) * M * cs;
-  T *lW = lS + int64_t(rows) * M * cs;
-  const int64_t tab_bytes = TL ? int64_t(3) * rows * M * cs * int64_t(sizeof(T)) : 0;
+  T *lS = lC + int64_t(a.cs_rows) * M * cs;
+  T *lW = lS + int64_t(a.cs_rows) * M * cs;
+  const int64_t tab_bytes =
+      TL ? (int64_t(2) * a.cs_rows + a.w_rows) * M * cs * int64_t(sizeof(T)) : 0;
   if constexpr (TL) {
-    const int64_t cnt = int64_t(rows) * M * cs;
-    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-      lC[e] = gC[e];
-      lS[e] = gS[e];
-      lW[e] = gW[e];
+    const T *gCe = dm.ham == NQS_TFIM ? tb.fC : tb.bC;
+    const T *gSe = dm.ham == NQS_TFIM ? tb.fS : tb.bS;
+    const int64_t ce = int64_t(a.cs_rows) * M * cs, we = int64_t(a.w_rows) * M * cs;
+    for (int64_t e = threadIdx.x; e < ce; e += blockDim.x) {
+      lC[e] = gCe[e];
+      lS[e] = gSe[e];
     }
+    for (int64_t e = threadIdx.x; e < we; e += blockDim.x) lW[e] = gW[e];
     __syncthreads();
   }
   if (chain >= a.n_chains) return;
-  unsigned char *wbase = lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes;
-  V<T, C> *tj = reinterpret_cast<V<T, C> *>(wbase);
-  int8_t *sig = reinterpret_cast<int8_t *>(wbase + ((M * int(sizeof(V<T, C>)) + 15) / 16) * 16);
+  int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes);
+  V<T, C> *tj = reinterpret_cast<V<T, C> *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes +
+                                            a.Npad);
   for (int i = lane; i < N; i += 64) sig[i] = a.chain_sigma[int64_t(chain) * N + i];
   wave_sync();
 
-  auto row_ld = [&](const T *lp, const T *gp, int row, int j) -> V<T, C> {
+  auto row_ld = [&](const T *lp, const T *gp, int row, int j) __attribute__((always_inline)) -> V<T, C> {
     if constexpr (TL)
       return vload<T, C>(lp, int64_t(row) * M + j);
     else
@@ -280,116 +397,171 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
 
   const uint32_t cid = a.chain_offset + uint32_t(chain);
   const int total = a.n_discard + a.n_sweeps;
-  // proposal (sweep, step) -> random words, table row and the sites it touches
-  auto propose = [&](int sw, int st, Philox4 &w, int &row, int &i, int &k) {
-    w = philox4x32_10(cid, a.counter + uint32_t(sw), uint32_t(st), TAG_PROPOSAL, a.k0, a.k1);
-    if (flip) {
-      i = rng_index(w.w[0], uint32_t(N));
-      row = i;
-      k = i;
-    } else {
-      row = rng_index(w.w[0], uint32_t(dm.B0));
-      i = dm.bonds[2 * row];
-      k = dm.bonds[2 * row + 1];
-    }
-  };
+  // spins mirrored in registers (lane l holds sites l, l+64, l+128, l+192) for N <= 256,
+  // so that the spin of a proposed site is one readlane
+  const bool sregs = N <= 256;
+  int sp0 = 0, sp1 = 0, sp2 = 0, sp3 = 0;
+  if (sregs) {
+    sp0 = lane < N ? sig[lane] : 0;
+    sp1 = lane + 64 < N ? sig[lane + 64] : 0;
+    sp2 = lane + 128 < N ? sig[lane + 128] : 0;
+    sp3 = lane + 192 < N ? sig[lane + 192] : 0;
+  }
   // with few hidden units per lane the next proposal's rows are fetched one step ahead;
   // with many, the R independent loads of a step already overlap
   constexpr bool PF = R <= 4;
-  constexpr int RP = PF ? R : 1;
-  Philox4 wc;
-  int rowc = 0, ic = 0, kc = 0;
-  V<T, C> cc[R], ss[R], ww[R];
-  auto load_rows = [&](int row, V<T, C> *c_, V<T, C> *s_, V<T, C> *w_) {
+  struct Rows {
+    V<T, C> c[R], s[R], w[R];
+  };
+  auto load_rows = [&](int row) __attribute__((always_inline)) -> Rows {
+    Rows o;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j = lane + 64 * r < M ? lane + 64 * r : 0;
-      c_[r] = row_ld(lC, gC, row, j);
-      s_[r] = row_ld(lS, gS, row, j);
-      w_[r] = row_ld(lW, gW, row, j);
+      o.c[r] = row_ld(lC, gC, row, j);
+      o.s[r] = row_ld(lS, gS, row, j);
+      o.w[r] = row_ld(lW, gW, row, j);
     }
+    return o;
   };
-  if constexpr (PF) {
-    propose(0, 0, wc, rowc, ic, kc);
-    load_rows(rowc, cc, ss, ww);
-  }
+  const double *afb = flip ? tb.fa : tb.ba;
+  const int afn = flip ? N : dm.Btot;
   int64_t acc_count = 0;
   for (int sw = 0; sw < total; ++sw) {
-    for (int st = 0; st < N; ++st) {
-      Philox4 wn = wc;
-      int rown = rowc, in_ = ic, kn = kc;
-      V<T, C> nc[RP], ns[RP], nw[RP];
-      if constexpr (PF) {
-        int nsw = sw, nst = st + 1;
-        if (nst == N) {
-          nst = 0;
-          ++nsw;
+    for (int st0 = 0; st0 < N; st0 += 64) {
+      // the random numbers of proposals st0 .. st0+63, one per lane: table row, the two
+      // sites, the uniform, and |exp(visible-bias change)|^2 for either spin
+      const int nst = N - st0 < 64 ? N - st0 : 64;
+      int rowv = 0, iv = 0, kv = 0;
+      double uv = 0.0, a2p = 0.0, a2m = 0.0;
+      float thp = 0.f, thm = 0.f;  // log2(u) - log2|a-factor|^2, for the FP32 decision
+      if (lane < nst) {
+        const Philox4 w = philox4x32_10(cid, a.counter + uint32_t(sw), uint32_t(st0 + lane),
+                                        TAG_PROPOSAL, a.k0, a.k1);
+        if (flip) {
+          iv = rng_index(w.w[0], uint32_t(N));
+          rowv = iv;
+          kv = iv;
+        } else {
+          rowv = rng_index(w.w[0], uint32_t(dm.B0));
+          iv = dm.bonds[2 * rowv];
+          kv = dm.bonds[2 * rowv + 1];
         }
-        if (nsw < total) propose(nsw, nst, wn, rown, in_, kn);
-        load_rows(rown, nc, ns, nw);
-      } else {
-        propose(sw, st, wc, rowc, ic, kc);
-        load_rows(rowc, cc, ss, ww);
+        uv = rng_uniform(w.w[1], w.w[2]);
+        const double *f0 = afb + 2 * int64_t(rowv);
+        const double *f1 = afb + 2 * (int64_t(afn) + rowv);
+        a2p = f0[0] * f0[0] + f0[1] * f0[1];
+        a2m = f1[0] * f1[0] + f1[1] * f1[1];
+        const float lu = __log2f(float(uv));
+        thp = lu - __log2f(float(a2p));
+        thm = lu - __log2f(float(a2m));
       }
-
-      const int s = __builtin_amdgcn_readfirstlane(int(sig[ic]));
-      const int sk = flip ? -s : __builtin_amdgcn_readfirstlane(int(sig[kc]));
-      if (sk != s) {  // an exchange of equal spins is the identity move
-        const T ts = T(s);
-        V<T, C> term[R];
-        T pm = T(1);
-        int pe = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          term[r] = vsub(cc[r], vscale(vmul(t[r], ss[r]), ts));
-          if (lane + 64 * r < M) pm *= vabs2(term[r]);
-          if ((r & 3) == 3) {
-            int e;
-            pm = nfrexp(pm, &e);
-            pe += e;
-          }
+      Rows cur = load_rows(__builtin_amdgcn_readlane(rowv, 0));
+      for (int l = 0; l < nst; ++l) {
+        const int ic = __builtin_amdgcn_readlane(iv, l);
+        const int kc = __builtin_amdgcn_readlane(kv, l);
+        Rows nxt;
+        if constexpr (PF) {
+          nxt = load_rows(__builtin_amdgcn_readlane(rowv, l + 1 < nst ? l + 1 : l));
+        } else {
+          if (l > 0) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
         }
-        {
-          int e;
-          pm = nfrexp(pm, &e);
-          pe += e;
+        int s, sk;
+        if (sregs) {
+          s = __builtin_amdgcn_readlane(ic < 64 ? sp0 : (ic < 128 ? sp1 : (ic < 192 ? sp2 : sp3)),
+                                        ic & 63);
+          sk = flip ? -s
+                    : __builtin_amdgcn_readlane(
+                          kc < 64 ? sp0 : (kc < 128 ? sp1 : (kc < 192 ? sp2 : sp3)), kc & 63);
+        } else {
+          s = __builtin_amdgcn_readfirstlane(int(sig[ic]));
+          sk = flip ? -s : __builtin_amdgcn_readfirstlane(int(sig[kc]));
         }
-        const T pmw = wave_prod_dpp(pm, pe);
-        const double *af = flip ? tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + rowc)
-                                : tb.ba + 2 * (int64_t(s > 0 ? 0 : 1) * dm.Btot + rowc);
-        const double q = ldexp(double(pmw), pe) * (af[0] * af[0] + af[1] * af[1]);
-        const double u = rng_uniform(wc.w[1], wc.w[2]);
-        const int accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
-        if (accept) {
+        if (sk != s) {  // an exchange of equal spins is the identity move
+          const T ts = T(s);
+          V<T, C> term[R];
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (lane + 64 * r < M) {
-              thr[r] -= 2.0 * double(s) * double(ww[r].re);
-              if (C) thi[r] -= 2.0 * double(s) * double(ww[r].im);
-              t[r] = vdiv(vsub(vmul(cc[r], t[r]), vscale(ss[r], ts)), term[r]);
+          for (int r = 0; r < R; ++r) term[r] = vsub(cur.c[r], vscale(vmul(t[r], cur.s[r]), ts));
+          int accept;
+          if constexpr (sizeof(T) == 4) {
+            // log-domain decision: accept iff sum_j log2|term_j|^2 > log2(u) - log2|a|^2
+            float lp = 0.f;
+#pragma unroll
+            for (int r0 = 0; r0 < R; r0 += 4) {
+              float pm = 1.f;
+#pragma unroll
+              for (int r = r0; r < r0 + 4 && r < R; ++r)
+                if (lane + 64 * r < M) pm *= float(vabs2(term[r]));
+              lp += __log2f(pm);
             }
-          }
-          if (lane == 0) {
-            sig[ic] = int8_t(-s);
-            if (!flip) sig[kc] = int8_t(s);
-          }
-          wave_sync();
-          ++acc_count;
-        }
-      }
-      if constexpr (PF) {
-        wc = wn;
-        rowc = rown;
-        ic = in_;
-        kc = kn;
+            lp = wave_sum_dpp(lp);
+            const float th = readlane_v(s > 0 ? thp : thm, l);
+            accept = __builtin_amdgcn_readfirstlane(int(lp > th));
+          } else {
+            T pm = T(1);
+            int pe = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          cc[r] = nc[r];
-          ss[r] = ns[r];
-          ww[r] = nw[r];
+            for (int r = 0; r < R; ++r) {
+              if (lane + 64 * r < M) pm *= vabs2(term[r]);
+              if ((r & 3) == 3) {
+                int e;
+                pm = nfrexp(pm, &e);
+                pe += e;
+              }
+            }
+            {
+              int e;
+              pm = nfrexp(pm, &e);
+              pe += e;
+            }
+            const T pmw = wave_prod_dpp(pm, pe);
+            const double a2 = readlane_v(s > 0 ? a2p : a2m, l);
+            const double q = ldexp(double(pmw), pe) * a2;
+            const double u = readlane_v(uv, l);
+            accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
+          }
+          if (accept) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              if (lane + 64 * r < M) {
+                thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
+                if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
+                t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
+              }
+            }
+            // spin registers (one lane each) and the LDS copy
+            if (sregs) {
+              if (ic < 64)
+                sp0 = lane == (ic & 63) ? -s : sp0;
+              else if (ic < 128)
+                sp1 = lane == (ic & 63) ? -s : sp1;
+              else if (ic < 192)
+                sp2 = lane == (ic & 63) ? -s : sp2;
+              else
+                sp3 = lane == (ic & 63) ? -s : sp3;
+              if (!flip) {
+                if (kc < 64)
+                  sp0 = lane == (kc & 63) ? s : sp0;
+                else if (kc < 128)
+                  sp1 = lane == (kc & 63) ? s : sp1;
+                else if (kc < 192)
+                  sp2 = lane == (kc & 63) ? s : sp2;
+                else
+                  sp3 = lane == (kc & 63) ? s : sp3;
+              }
+            }
+            if (lane == 0) {
+              sig[ic] = int8_t(-s);
+              if (!flip) sig[kc] = int8_t(s);
+            }
+            if (!sregs) wave_sync();
+            ++acc_count;
+          }
         }
+        if constexpr (PF) cur = nxt;
       }
     }
+    wave_sync();
     // end of sweep: tanh from the exact angles
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -399,12 +571,17 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
       int8_t *dst = a.samples + smp * N;
       for (int i = lane; i < N; i += 64) dst[i] = sig[i];
       if (a.eloc) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (lane + 64 * r < M) tj[lane + 64 * r] = t[r];
-        wave_sync();
         double er, ei;
-        eloc_wave<T, C>(dm, tb, sig, tj, lane, er, ei);
+        if (M <= 256) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (lane + 64 * r < M) tj[lane + 64 * r] = t[r];
+          wave_sync();
+          eloc_grouped<T, C, TL>(dm, tb, sig, tj, lane, lC, lS, er, ei);
+          wave_sync();
+        } else {
+          eloc_regs<T, C, R, TL>(dm, tb, sig, t, lane, lC, lS, er, ei);
+        }
         if (lane == 0) {
           if (C) {
             a.eloc[2 * smp] = er;
@@ -413,7 +590,6 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
             a.eloc[smp] = er;
           }
         }
-        wave_sync();
       }
     }
   }
@@ -422,38 +598,50 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
 }
 
 // ---------------------------------------------------------------------------------
-// Local energy of arbitrary configurations. One sample per wavefront: theta in double,
-// tanh into LDS, then eloc_wave.
+// Local energy of arbitrary configurations: one sample per wavefront, theta in double
+// for the lane's hidden units, tanh in T, then eloc_regs with the global tables.
 // ---------------------------------------------------------------------------------
-template <typename T, bool C>
+template <typename T, bool C, int R>
 __global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
                                                        const int8_t *__restrict__ sigma,
                                                        int64_t n, double *eloc, int Npad,
-                                                       int lds_wave_bytes) {
+                                                       int wave_bytes) {
   extern __shared__ __align__(16) unsigned char lds_u8[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int64_t smp = int64_t(blockIdx.x) * (blockDim.x >> 6) + wid;
   if (smp >= n) return;
   const int N = dm.N, M = dm.M;
-  unsigned char *base = lds_u8 + int64_t(wid) * lds_wave_bytes;
-  int8_t *sig = reinterpret_cast<int8_t *>(base);
-  V<T, C> *tj = reinterpret_cast<V<T, C> *>(base + Npad);
+  int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + int64_t(wid) * wave_bytes);
+  V<T, C> *tj = reinterpret_cast<V<T, C> *>(lds_u8 + int64_t(wid) * wave_bytes + Npad);
   for (int i = lane; i < N; i += 64) sig[i] = sigma[smp * N + i];
   wave_sync();
-  for (int j = lane; j < M; j += 64) {
-    V<double, C> acc = vload<double, C>(tb.bv, j);
-    for (int i = 0; i < N; ++i) {
-      double s = double(sig[i]);
-      V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
-      acc.re += s * w.re;
-      if (C) acc.im += s * w.im;
+  V<T, C> t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = lane + 64 * r;
+    t[r] = vmake<T, C>(T(0), T(0));
+    if (j < M) {
+      V<double, C> acc = vload<double, C>(tb.bv, j);
+      for (int i = 0; i < N; ++i) {
+        const double s = double(sig[i]);
+        V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
+        acc.re += s * w.re;
+        if (C) acc.im += s * w.im;
+      }
+      t[r] = vtanh<T, C>(vmake<T, C>(T(acc.re), T(acc.im)));
     }
-    tj[j] = vtanh<T, C>(vmake<T, C>(T(acc.re), T(acc.im)));
   }
-  wave_sync();
   double er, ei;
-  eloc_wave<T, C>(dm, tb, sig, tj, lane, er, ei);
+  if (M <= 256) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane + 64 * r < M) tj[lane + 64 * r] = t[r];
+    wave_sync();
+    eloc_grouped<T, C, false>(dm, tb, sig, tj, lane, nullptr, nullptr, er, ei);
+  } else {
+    eloc_regs<T, C, R, false>(dm, tb, sig, t, lane, nullptr, nullptr, er, ei);
+  }
   if (lane == 0) {
     if (C) {
       eloc[2 * smp] = er;
@@ -520,10 +708,6 @@ Tables<T> tables_of(const nqs_model *m) {
   tb.fS = (T *)m->tab_ptrs[3];
   tb.bC = (T *)m->tab_ptrs[4];
   tb.bS = (T *)m->tab_ptrs[5];
-  tb.fCt = (T *)m->tab_ptrs[6];
-  tb.fSt = (T *)m->tab_ptrs[7];
-  tb.bCt = (T *)m->tab_ptrs[8];
-  tb.bSt = (T *)m->tab_ptrs[9];
   tb.fa = (double *)m->tab_ptrs[10];
   tb.ba = (double *)m->tab_ptrs[11];
   tb.av = (double *)m->tab_ptrs[12];
@@ -567,12 +751,19 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   a.samples = samples;
   a.n_acc = n_acc;
   a.eloc = (double *)eloc;
-  a.tab_rows = m->move == NQS_MOVE_FLIP ? m->N : m->B[0];
-  a.wave_bytes = round_up(m->M * int(sizeof(V<T, C>)), 16) + round_up(m->N, 16);
+  const bool flip = m->move == NQS_MOVE_FLIP;
+  a.cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
+  a.w_rows = flip ? m->N : m->B[0];
+  a.Npad = round_up(m->N, 16);
+  a.wave_bytes = a.Npad + round_up(m->M * int(sizeof(V<T, C>)), 16);
   const size_t wave_lds = size_t(wpb) * a.wave_bytes;
-  const size_t tab_lds = size_t(3) * a.tab_rows * m->M * sizeof(T) * (C ? 2 : 1);
+  const size_t tab_lds =
+      size_t(2 * a.cs_rows + a.w_rows) * m->M * sizeof(T) * (C ? 2 : 1);
+  // the staged C/S rows serve both the moves and the local energy only when the move
+  // set is contained in the connected set: flips with TFIM, exchanges with Heisenberg
+  const bool shared_rows = (m->ham == NQS_TFIM && flip) || (m->ham == NQS_HEISENBERG && !flip);
   dim3 grid((n_chains + wpb - 1) / wpb);
-  if (tab_lds + wave_lds <= size_t(m->max_lds)) {
+  if (shared_rows && tab_lds + wave_lds <= size_t(m->max_lds)) {
     hipLaunchKernelGGL((k_sweep<T, C, R, true>), grid, dim3(64 * wpb), tab_lds + wave_lds, st,
                        dev_model(m), tables_of<T>(m), a);
   } else {
@@ -601,19 +792,30 @@ hipError_t sweep_t(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   return hipErrorInvalidValue;
 }
 
+template <typename T, bool C, int R>
+hipError_t eloc_r(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,
+                  hipStream_t st) {
+  const int Npad = round_up(m->N, 16);
+  const int wave_bytes = Npad + round_up(m->M * int(sizeof(V<T, C>)), 16);
+  const int wpb = 4;
+  dim3 grid(unsigned((n + wpb - 1) / wpb));
+  hipLaunchKernelGGL((k_local_energy<T, C, R>), grid, dim3(64 * wpb), size_t(wpb) * wave_bytes,
+                     st, dev_model(m), tables_of<T>(m), sigma, n, (double *)eloc, Npad,
+                     wave_bytes);
+  return hipGetLastError();
+}
+
 template <typename T, bool C>
 hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,
                   hipStream_t st) {
   if (n == 0) return hipSuccess;
-  int Npad = round_up(m->N, 16);
-  int wave_bytes = Npad + round_up(m->M * int(sizeof(V<T, C>)), 16);
-  int wpb = 4;
-  while (wpb > 1 && wpb * wave_bytes > 64 * 1024) wpb /= 2;
-  dim3 grid(unsigned((n + wpb - 1) / wpb));
-  hipLaunchKernelGGL((k_local_energy<T, C>), grid, dim3(64 * wpb), size_t(wpb) * wave_bytes,
-                     st, dev_model(m), tables_of<T>(m), sigma, n, (double *)eloc, Npad,
-                     wave_bytes);
-  return hipGetLastError();
+  const int r = (m->M + 63) / 64;
+  if (r <= 1) return eloc_r<T, C, 1>(m, sigma, n, eloc, st);
+  if (r <= 2) return eloc_r<T, C, 2>(m, sigma, n, eloc, st);
+  if (r <= 4) return eloc_r<T, C, 4>(m, sigma, n, eloc, st);
+  if (r <= 8) return eloc_r<T, C, 8>(m, sigma, n, eloc, st);
+  if (r <= 16) return eloc_r<T, C, 16>(m, sigma, n, eloc, st);
+  return eloc_r<T, C, 32>(m, sigma, n, eloc, st);
 }
 
 template <typename T, bool C>

@@ -112,27 +112,56 @@ __global__ void k_fill(int64_t count, double *x, double val) {
     x[k] = val;
 }
 
-// variance; F = g / n; x = 0; r = p = F; partial ||F||^2
-template <bool C>
-__global__ __launch_bounds__(256) void k_cg_init(int64_t P, int64_t n, const double *part2,
+// write the CG direction p (complex double, packed like the parameters) as the tables the
+// product kernels read: Vt[i][j] = p_W[j][i], vb = p_b (compute precision), va = p_a
+template <typename T, bool C>
+__device__ __forceinline__ void dir_write(int N, int M, int64_t k, double pr, double pi, T *Vt,
+                                          T *vb, double *va) {
+  if (k < N) {
+    va[2 * k] = pr;
+    va[2 * k + 1] = pi;
+  } else if (k < N + M) {
+    vstore<T, C>(vb, k - N, vmake<T, C>(T(pr), T(pi)));
+  } else {
+    const int64_t q = k - N - M;
+    vstore<T, C>(Vt, (q % N) * M + q / N, vmake<T, C>(T(pr), T(pi)));
+  }
+}
+
+// variance; F = g / n; x = 0; r = p = F (+ direction tables); partial ||F||^2
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_cg_init(int N, int M, int64_t n, const double *part2,
                                                   int64_t nparts, const double *g, double *F,
-                                                  double *x, double *r, double *p,
-                                                  double *dpart, CGState *st) {
+                                                  double *x, double *r, double *p, T *Vt, T *vb,
+                                                  double *va, double *dpart, CGState *st) {
   __shared__ double lds[256];
-  const int cs = C ? 2 : 1;
+  const int64_t P = int64_t(N) + M + int64_t(N) * M;
   if (blockIdx.x == 0) {
     double var = block_sum(part2, nparts, 1, lds) / double(n);
     if (threadIdx.x == 0) st->var = var;
   }
   double acc = 0.0;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P * cs;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
        k += int64_t(gridDim.x) * 256) {
-    double f = g[k] / double(n);
-    F[k] = f;
-    x[k] = 0.0;
-    r[k] = f;
-    p[k] = f;
-    acc += f * f;
+    const double fr = (C ? g[2 * k] : g[k]) / double(n);
+    const double fi = C ? g[2 * k + 1] / double(n) : 0.0;
+    if (C) {
+      F[2 * k] = fr;
+      F[2 * k + 1] = fi;
+      x[2 * k] = 0.0;
+      x[2 * k + 1] = 0.0;
+      r[2 * k] = fr;
+      r[2 * k + 1] = fi;
+      p[2 * k] = fr;
+      p[2 * k + 1] = fi;
+    } else {
+      F[k] = fr;
+      x[k] = 0.0;
+      r[k] = fr;
+      p[k] = fr;
+    }
+    dir_write<T, C>(N, M, k, fr, fi, Vt, vb, va);
+    acc += fr * fr + fi * fi;
   }
   acc = block_reduce(acc, lds);
   if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
@@ -156,29 +185,44 @@ __global__ __launch_bounds__(256) void k_cg_start(const double *dpart, int64_t n
   }
 }
 
-// Ap = (O^dagger y - ybar * O^dagger 1) / n + lambda p ; partial Re(p^dagger Ap)
+// g = O^dagger y from the first-level sums, then
+// Ap = (g - ybar * O^dagger 1) / n + lambda p ; partial Re(p^dagger Ap)
 template <bool C>
-__global__ __launch_bounds__(256) void k_cg_ap(int64_t P, int64_t n, const double *g,
+__global__ __launch_bounds__(256) void k_cg_ap(int N, int M, int64_t n, int groups, int colsP,
+                                               int64_t elems, const double *out1,
                                                const double *o1, const double *ysum,
                                                int64_t nys, const double *p, double lambda,
                                                double *Ap, double *dpart, const CGState *st) {
   if (st->done) return;
   __shared__ double lds[256];
+  const int64_t P = int64_t(N) + M + int64_t(N) * M;
   const double ybr = block_sum(ysum, nys, 2, lds) / double(n);
   const double ybi = C ? block_sum(ysum + 1, nys, 2, lds) / double(n) : 0.0;
   double acc = 0.0;
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
        k += int64_t(gridDim.x) * 256) {
+    int64_t e;
+    if (k < N)
+      e = int64_t(M) * colsP + k;
+    else if (k < N + M)
+      e = int64_t(k - N) * colsP + N;
+    else
+      e = ((k - N - M) / N) * colsP + ((k - N - M) % N);
+    double gr = 0.0, gi = 0.0;
+    for (int q = 0; q < groups; ++q) {
+      gr += out1[2 * (int64_t(q) * elems + e)];
+      gi += out1[2 * (int64_t(q) * elems + e) + 1];
+    }
     if (C) {
-      double gr = g[2 * k] - (ybr * o1[2 * k] - ybi * o1[2 * k + 1]);
-      double gi = g[2 * k + 1] - (ybr * o1[2 * k + 1] + ybi * o1[2 * k]);
-      double ar = gr / double(n) + lambda * p[2 * k];
-      double ai = gi / double(n) + lambda * p[2 * k + 1];
+      gr -= ybr * o1[2 * k] - ybi * o1[2 * k + 1];
+      gi -= ybr * o1[2 * k + 1] + ybi * o1[2 * k];
+      const double ar = gr / double(n) + lambda * p[2 * k];
+      const double ai = gi / double(n) + lambda * p[2 * k + 1];
       Ap[2 * k] = ar;
       Ap[2 * k + 1] = ai;
       acc += p[2 * k] * ar + p[2 * k + 1] * ai;
     } else {
-      double ar = (g[k] - ybr * o1[k]) / double(n) + lambda * p[k];
+      const double ar = (gr - ybr * o1[k]) / double(n) + lambda * p[k];
       Ap[k] = ar;
       acc += p[k] * ar;
     }
@@ -209,21 +253,36 @@ __global__ __launch_bounds__(256) void k_cg_xr(int64_t Pc, const double *dpart, 
   if (blockIdx.x == 0 && threadIdx.x == 0) st->alpha = alpha;
 }
 
-// rr_new from partials; convergence; beta = rr_new / rr ; p = r + beta p
-__global__ __launch_bounds__(256) void k_cg_p(int64_t Pc, const double *rpart, int64_t nparts,
+// rr_new from partials; convergence; beta = rr_new / rr ; p = r + beta p (+ direction
+// tables for the next product)
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart, int64_t nparts,
                                               int parity, double tol, int maxiter,
-                                              const double *r, double *p, CGState *st) {
+                                              const double *r, double *p, T *Vt, T *vb,
+                                              double *va, CGState *st) {
   if (st->done) return;
   __shared__ double lds[256];
+  const int64_t P = int64_t(N) + M + int64_t(N) * M;
   const double rr_new = block_sum(rpart, nparts, 1, lds);
   const double rr = st->rr[parity];
   const double beta = rr_new / rr;
   const int iters = st->iters + 1;
   const bool conv = sqrt(rr_new) <= tol * st->bnorm;
   const bool bad = !(finite(rr_new) && finite(st->alpha));
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Pc;
-       k += int64_t(gridDim.x) * 256)
-    p[k] = r[k] + beta * p[k];
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
+       k += int64_t(gridDim.x) * 256) {
+    double pr, pi = 0.0;
+    if (C) {
+      pr = r[2 * k] + beta * p[2 * k];
+      pi = r[2 * k + 1] + beta * p[2 * k + 1];
+      p[2 * k] = pr;
+      p[2 * k + 1] = pi;
+    } else {
+      pr = r[k] + beta * p[k];
+      p[k] = pr;
+    }
+    dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va);
+  }
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->rr[parity ^ 1] = rr_new;
@@ -259,7 +318,8 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   };
   L.grad = take(grad_scratch_bytes(m, n));
   L.y = take(size_t(n) * cs * 8);
-  L.ysum = take(size_t(nb) * 16);
+  const int64_t ns = grad_plan(m, n).splits;
+  L.ysum = take(size_t(nb > ns ? nb : ns) * 16);
   L.u = take(size_t(n) * cs * 8);
   L.e_part = take(size_t(nb) * 16);
   L.e_part2 = take(size_t(nb) * 8);
@@ -302,7 +362,7 @@ inline unsigned grid_for(int64_t count) {
   return unsigned(b < 8192 ? (b > 0 ? b : 1) : 8192);
 }
 
-template <bool C>
+template <typename T, bool C>
 nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
                    int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
                    void *ws, nqs_sr_info *info, hipStream_t st) {
@@ -312,11 +372,16 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   CGState *state = (CGState *)(b + L.state);
   void *grad = b + L.grad;
   const int cs = C ? 2 : 1;
-  const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+  const int N = m->N, M = m->M;
+  const int64_t P = int64_t(N) + M + int64_t(N) * M;
   const int64_t Pc = P * cs;
   const int64_t nb = cdiv(n, 256);
   const int64_t pblocks = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
   const int64_t cblocks = cdiv(Pc, 256) < 4096 ? cdiv(Pc, 256) : 4096;
+  const GradPlan gp = grad_plan(m, n);
+  const GradBuffers gb = grad_buffers(m, n, grad);
+  const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
+  const int64_t nys = gp.fused ? gp.splits : nb;
 
   HIPTRY(launch_tables(m, params, st));
   // mean energy, centred energies u = E_loc - E, variance partials
@@ -335,9 +400,9 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   HIPTRY(launch_vjp_reduce(m, n, grad, D(L.o1), nullptr, st));
   HIPTRY(launch_vjp_partials(m, sigma, n, D(L.u), grad, nullptr, st));
   HIPTRY(launch_vjp_reduce(m, n, grad, D(L.g), nullptr, st));
-  hipLaunchKernelGGL((k_cg_init<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, P, n,
-                     D(L.e_part2), nb, D(L.g), D(L.F), D(L.x), D(L.r), D(L.p), D(L.dpart),
-                     state);
+  hipLaunchKernelGGL((k_cg_init<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, st, N, M, n,
+                     D(L.e_part2), nb, D(L.g), D(L.F), D(L.x), D(L.r), D(L.p), (T *)gb.Vt,
+                     (T *)gb.vb, gb.va, D(L.dpart), state);
   HIPTRY(hipGetLastError());
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, st, D(L.dpart), pblocks, cg_tol,
                      cg_maxiter, state);
@@ -354,19 +419,22 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
     const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
     for (int q = 0; q < batch; ++q, ++launched) {
       const int parity = launched & 1;
-      HIPTRY(launch_prep_dir(m, D(L.p), grad, st));
-      HIPTRY(launch_jvp(m, sigma, n, grad, D(L.y), D(L.ysum), skip, st));
-      HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, st));
-      HIPTRY(launch_vjp_reduce(m, n, grad, D(L.g), skip, st));
-      hipLaunchKernelGGL((k_cg_ap<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, P, n, D(L.g),
-                         D(L.o1), D(L.ysum), nb, D(L.p), diag_shift, D(L.Ap), D(L.dpart),
-                         state);
+      if (gp.fused) {
+        HIPTRY(launch_sv(m, sigma, n, grad, D(L.ysum), skip, st));
+      } else {
+        HIPTRY(launch_jvp(m, sigma, n, grad, D(L.y), D(L.ysum), skip, st));
+        HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, st));
+      }
+      hipLaunchKernelGGL((k_cg_ap<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, N, M, n,
+                         gp.groups, gp.Itiles * 16, elems, gb.out1, D(L.o1), D(L.ysum), nys,
+                         D(L.p), diag_shift, D(L.Ap), D(L.dpart), state);
       HIPTRY(hipGetLastError());
       hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, st, Pc, D(L.dpart),
                          pblocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
       HIPTRY(hipGetLastError());
-      hipLaunchKernelGGL(k_cg_p, dim3(unsigned(cblocks)), dim3(256), 0, st, Pc, D(L.rpart),
-                         cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p), state);
+      hipLaunchKernelGGL((k_cg_p<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, st, N, M,
+                         D(L.rpart), cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
+                         (T *)gb.Vt, (T *)gb.vb, gb.va, state);
       HIPTRY(hipGetLastError());
     }
   }
@@ -402,8 +470,9 @@ nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const v
                         int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
                         void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st) {
   if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
-  return m->is_complex ? sr_impl<true>(m, params, sigma, eloc, n, lr, diag_shift, cg_tol,
-                                       cg_maxiter, ws, info, st)
-                       : sr_impl<false>(m, params, sigma, eloc, n, lr, diag_shift, cg_tol,
-                                        cg_maxiter, ws, info, st);
+#define NQS_SR(T, C) \
+  sr_impl<T, C>(m, params, sigma, eloc, n, lr, diag_shift, cg_tol, cg_maxiter, ws, info, st)
+  if (use_double(m)) return m->is_complex ? NQS_SR(double, true) : NQS_SR(double, false);
+  return m->is_complex ? NQS_SR(float, true) : NQS_SR(float, false);
+#undef NQS_SR
 }

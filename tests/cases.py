@@ -23,7 +23,19 @@ CASES = {
     "tfim5x5_j2_real_f64": (5, 2, True, 0, (1.0, -0.3), 1.1, False, 0, False, 0, 50),
     # Heisenberg without Marshall rotation, single flips, real FP64
     "heis12_real_f64_flip": (12, 1, False, 1, (1.0, 0.0), 0.0, False, 0, False, 0, 36),
+    # tables too large for LDS (global rows, next-row prefetch), 4 hidden units per lane
+    "heis6x6_cplx_f32": (6, 2, False, 1, (1.0, 0.0), 0.0, True, 1, True, 1, 144),
+    "j1j2_6x6_cplx_f64": (6, 2, True, 1, (1.0, 0.5), 0.0, True, 1, True, 0, 72),
+    # 16 hidden units per lane
+    "heis4x4_cplx_f32_m1024": (4, 2, False, 1, (1.0, 0.0), 0.0, True, 1, True, 1, 1024),
 }
+
+# larger lattices used by selected tests only (the oracle is slow for them)
+BIG = {
+    # more than 256 sites: spins read from LDS instead of lane registers
+    "tfim300_real_f32": (300, 1, False, 0, (1.0, 0.0), 1.0, False, 0, False, 1, 300),
+}
+CASES.update(BIG)
 
 TOL = {0: 1e-10, 1: 1e-5}
 
