@@ -6,8 +6,12 @@
  * Conventions for every entry point:
  *  - Pointers marked (device) are HIP device pointers owned by the caller; the library
  *    only borrows them for the duration of the call. Pointers marked (host) are host
- *    memory. The library allocates device memory only for the small per-model tables
- *    created in nqs_model_create, and for caches it keeps per model (see each call).
+ *    memory. The library allocates device memory only for the per-model tables created
+ *    in nqs_model_create and for one grow-only scratch buffer per model, used by
+ *    nqs_sample (when it computes local energies), nqs_local_energy and nqs_log_psi_grad
+ *    (about n * n_hidden complex values in the compute precision). Growing it allocates
+ *    and synchronises the device; calls with one handle must therefore be issued on one
+ *    stream.
  *  - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL = the null
  *    stream), except where a call states it synchronises.
  *  - Argument errors are detected on the host before any launch and returned as
@@ -122,9 +126,10 @@ nqs_status nqs_chain_init(nqs_model *model, int8_t *chain_sigma, int32_t n_chain
  *  samples     (device) [n_sweeps, n_chains, N]
  *  n_accepted  (device) int64 [n_chains] accepted proposals in this call (may be NULL)
  *  eloc        (device) double/complex double [n_sweeps * n_chains] or NULL: if given,
- *              the local energy of every recorded sample is computed in the same launch
- *              from the chain's cached hidden-unit angles (same values as
- *              nqs_local_energy on `samples`, up to rounding).
+ *              the local energy of every recorded sample (same values as
+ *              nqs_local_energy on `samples`, up to rounding). With at least 16 chains per
+ *              compute unit it is evaluated inside the sweep from the chain's cached
+ *              hidden-unit angles; otherwise by a separate pass over the samples.
  * Limits: n_chains >= 1, n_sweeps >= 1, n_discard >= 0, chain_offset >= 0. */
 nqs_status nqs_sample(nqs_model *model, const void *params, int8_t *chain_sigma,
                       int32_t n_chains, int32_t n_sweeps, int32_t n_discard, uint64_t seed,

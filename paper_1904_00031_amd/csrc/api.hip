@@ -152,6 +152,11 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
             hipSuccess &&
         lds > 0)
       m->max_lds = lds;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) ==
+            hipSuccess &&
+        cus > 0)
+      m->cu_count = cus;
   }
 
   // bond lists with their diagonal and exchange coefficients
@@ -246,10 +251,24 @@ nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int
       n_discard < 0 || chain_offset < 0)
     return NQS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  // With fewer than 16 chains per compute unit (at most one wavefront per SIMD pair) the
+  // sweep is latency-bound and local energies are cheaper as a separate full-occupancy
+  // pass over the recorded samples; with many chains they are fused into the sweep.
+  const bool fuse = eloc && int64_t(n_chains) >= 16 * int64_t(m->cu_count);
+  const int64_t n = int64_t(n_sweeps) * n_chains;
+  if (eloc && !fuse) {
+    nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
+    if (s != NQS_OK) return s;
+  }
   hipError_t e = launch_tables(m, params, st);
   if (e == hipSuccess)
     e = launch_sweep(m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter, chain_offset,
-                     samples, n_accepted, eloc, st);
+                     samples, n_accepted, fuse ? eloc : nullptr, st);
+  if (e == hipSuccess && eloc && !fuse) {
+    e = launch_theta_tanh(m, samples, n, m->d_scratch, st);
+    if (e == hipSuccess)
+      e = launch_local_energy(m, samples, grad_buffers(m, n, m->d_scratch).Tm, n, eloc, st);
+  }
   return dev(e);
 }
 
@@ -268,8 +287,12 @@ nqs_status nqs_local_energy(nqs_model *m, const void *params, const int8_t *sigm
   if (!m || !params || n < 0 || (n > 0 && (!sigma || !eloc))) return NQS_EINVAL;
   if (n == 0) return NQS_OK;
   hipStream_t st = (hipStream_t)stream;
+  nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
+  if (s != NQS_OK) return s;
   hipError_t e = launch_tables(m, params, st);
-  if (e == hipSuccess) e = launch_local_energy(m, sigma, n, eloc, st);
+  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, st);
+  if (e == hipSuccess)
+    e = launch_local_energy(m, sigma, grad_buffers(m, n, m->d_scratch).Tm, n, eloc, st);
   return dev(e);
 }
 

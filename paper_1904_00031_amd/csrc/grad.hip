@@ -786,7 +786,7 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
   if (g.NT == 3 && g.JT == 8) g.JT = 6;
   const int64_t tile_blocks = cdiv(g.Jtiles, g.JT) * cdiv(g.Itiles, g.NT);
   const int64_t steps = n > 0 ? cdiv(n, 16) : 1;   // 16 samples = one step of all 4 waves
-  int64_t splits = 512 / tile_blocks;
+  int64_t splits = 2 * int64_t(m->cu_count) / tile_blocks;
   if (splits < 1) splits = 1;
   if (splits > steps) splits = steps;
   g.per_split = rup(cdiv(n > 0 ? n : 1, splits), 16);
@@ -847,6 +847,7 @@ GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch) {
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
   GradBuffers b;
+  b.Tm = base + L.Tm;
   b.Vt = base + L.Vt;
   b.vb = base + L.vb;
   b.va = (double *)(base + L.va);

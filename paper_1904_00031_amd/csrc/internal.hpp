@@ -20,6 +20,7 @@ struct nqs_model {
   size_t tables_bytes = 0;
   void *tab_ptrs[14] = {};         // sub-buffers of d_tables, in Tables<T> member order
   int max_lds = 65536;             // dynamic LDS bytes a workgroup may use on this device
+  int cu_count = 256;              // compute units of the device
   // grow-only scratch for nqs_log_psi_grad
   void *d_scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -37,8 +38,9 @@ hipError_t launch_chain_init(const nqs_model *m, int8_t *sig, int n_chains, uint
 hipError_t launch_sweep(const nqs_model *m, int8_t *chain_sigma, int n_chains, int n_sweeps,
                         int n_discard, uint64_t seed, uint64_t counter, int chain_offset,
                         int8_t *samples, int64_t *n_acc, void *eloc, hipStream_t st);
-hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,
-                               hipStream_t st);
+// local energies from rows Tm [n][M] of tanh(theta) (compute precision)
+hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, const void *Tm,
+                               int64_t n, void *eloc, hipStream_t st);
 hipError_t launch_log_psi(const nqs_model *m, const int8_t *sigma, int64_t n, void *out,
                           hipStream_t st);
 
@@ -76,6 +78,7 @@ hipError_t launch_vjp_partials(const nqs_model *m, const int8_t *sigma, int64_t 
 hipError_t launch_sv(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
                      double *ysum_part, const int *skip, hipStream_t st);
 struct GradBuffers {
+  void *Tm;        // tanh(theta) rows [n][M] (compute precision)
   void *Vt, *vb;   // direction tables in compute precision
   double *va;      // visible part of the direction, complex double
   double *out1;    // first-level VJP sums [groups][Jtiles*16*Itiles*16] complex double

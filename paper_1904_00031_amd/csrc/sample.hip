@@ -218,9 +218,9 @@ __device__ __forceinline__ void eloc_regs(const DevModel &dm, const Tables<T> &t
 // hidden units j = lane%16 + 16 q (t_j read from LDS), and a 4-step DPP product inside
 // the row finishes each ratio. Same result as eloc_regs, a quarter of the reductions.
 // ---------------------------------------------------------------------------------
-template <typename T, bool C, bool TL>
+template <typename T, bool C, bool TL, int TP>
 __device__ __forceinline__ void eloc_grouped(const DevModel &dm, const Tables<T> &tb,
-                                             const int8_t *sig, const V<T, C> *tj, int lane,
+                                             const int8_t *sig, const T *tj, int lane,
                                              const T *lCe, const T *lSe, double &out_re,
                                              double &out_im) {
   const int N = dm.N, M = dm.M, B = dm.Btot;
@@ -228,6 +228,11 @@ __device__ __forceinline__ void eloc_grouped(const DevModel &dm, const Tables<T>
   const T *gCe = tfim ? tb.fC : tb.bC;
   const T *gSe = tfim ? tb.fS : tb.bS;
   const int lo = lane & 15, g = lane >> 4;
+  // the lane's t_j (j = lo + 16 q) for every pass, loaded once
+  V<T, C> tv[TP];
+#pragma unroll
+  for (int q = 0; q < TP; ++q)
+    tv[q] = lo + 16 * q < M ? vload<T, C>(tj, lo + 16 * q) : vmake<T, C>(T(0), T(0));
   double diag = 0.0;
   for (int b = lane; b < B; b += 64)
     diag += dm.bond_diag[b] * double(sig[dm.bonds[2 * b]]) * double(sig[dm.bonds[2 * b + 1]]);
@@ -265,18 +270,22 @@ __device__ __forceinline__ void eloc_grouped(const DevModel &dm, const Tables<T>
       if (myq >= 0) {
         const int row = c0 + myq;
         const T ts = ((up >> myq) & 1) ? T(1) : T(-1);
-        int k = 0;
-        for (int j = lo; j < M; j += 16, ++k) {
-          V<T, C> cc, ss;
+        V<T, C> cc[TP], ss[TP];
+#pragma unroll
+        for (int q = 0; q < TP; ++q) {
+          const int j = lo + 16 * q < M ? lo + 16 * q : 0;
           if constexpr (TL) {
-            cc = vload<T, C>(lCe, int64_t(row) * M + j);
-            ss = vload<T, C>(lSe, int64_t(row) * M + j);
+            cc[q] = vload<T, C>(lCe, int64_t(row) * M + j);
+            ss[q] = vload<T, C>(lSe, int64_t(row) * M + j);
           } else {
-            cc = vload<T, C>(gCe, int64_t(row) * M + j);
-            ss = vload<T, C>(gSe, int64_t(row) * M + j);
+            cc[q] = vload<T, C>(gCe, int64_t(row) * M + j);
+            ss[q] = vload<T, C>(gSe, int64_t(row) * M + j);
           }
-          p = vmul(p, vsub(cc, vscale(vmul(tj[j], ss), ts)));
-          if ((k & 3) == 3) vrenorm(p, pe);
+        }
+#pragma unroll
+        for (int q = 0; q < TP; ++q) {
+          if (lo + 16 * q < M) p = vmul(p, vsub(cc[q], vscale(vmul(tv[q], ss[q]), ts)));
+          if ((q & 3) == 3) vrenorm(p, pe);
         }
       }
       vrenorm(p, pe);
@@ -361,8 +370,7 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
   }
   if (chain >= a.n_chains) return;
   int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes);
-  V<T, C> *tj = reinterpret_cast<V<T, C> *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes +
-                                            a.Npad);
+  T *tj = reinterpret_cast<T *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes + a.Npad);
   for (int i = lane; i < N; i += 64) sig[i] = a.chain_sigma[int64_t(chain) * N + i];
   wave_sync();
 
@@ -575,9 +583,9 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
         if (M <= 256) {
 #pragma unroll
           for (int r = 0; r < R; ++r)
-            if (lane + 64 * r < M) tj[lane + 64 * r] = t[r];
+            if (lane + 64 * r < M) vstore<T, C>(tj, lane + 64 * r, t[r]);
           wave_sync();
-          eloc_grouped<T, C, TL>(dm, tb, sig, tj, lane, lC, lS, er, ei);
+          eloc_grouped<T, C, TL, (4 * R < 16 ? 4 * R : 16)>(dm, tb, sig, tj, lane, lC, lS, er, ei);
           wave_sync();
         } else {
           eloc_regs<T, C, R, TL>(dm, tb, sig, t, lane, lC, lS, er, ei);
@@ -598,56 +606,58 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
 }
 
 // ---------------------------------------------------------------------------------
-// Local energy of arbitrary configurations: one sample per wavefront, theta in double
-// for the lane's hidden units, tanh in T, then eloc_regs with the global tables.
+// Local energy of arbitrary configurations from precomputed rows T[s][j] = tanh(theta_j)
+// (the matrix-core kernel k_theta_tanh): one sample per wavefront at full occupancy; the
+// C/S rows of the connected configurations are staged in LDS when they fit (TL).
 // ---------------------------------------------------------------------------------
-template <typename T, bool C, int R>
+template <typename T, bool C, int R, bool TL>
 __global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
                                                        const int8_t *__restrict__ sigma,
-                                                       int64_t n, double *eloc, int Npad,
-                                                       int wave_bytes) {
+                                                       const T *__restrict__ Tm, int64_t n,
+                                                       double *eloc, int Npad, int cs_rows) {
   extern __shared__ __align__(16) unsigned char lds_u8[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int64_t smp = int64_t(blockIdx.x) * (blockDim.x >> 6) + wid;
-  if (smp >= n) return;
   const int N = dm.N, M = dm.M;
-  int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + int64_t(wid) * wave_bytes);
-  V<T, C> *tj = reinterpret_cast<V<T, C> *>(lds_u8 + int64_t(wid) * wave_bytes + Npad);
-  for (int i = lane; i < N; i += 64) sig[i] = sigma[smp * N + i];
-  wave_sync();
-  V<T, C> t[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int j = lane + 64 * r;
-    t[r] = vmake<T, C>(T(0), T(0));
-    if (j < M) {
-      V<double, C> acc = vload<double, C>(tb.bv, j);
-      for (int i = 0; i < N; ++i) {
-        const double s = double(sig[i]);
-        V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
-        acc.re += s * w.re;
-        if (C) acc.im += s * w.im;
-      }
-      t[r] = vtanh<T, C>(vmake<T, C>(T(acc.re), T(acc.im)));
+  constexpr int cs = C ? 2 : 1;
+  T *lC = reinterpret_cast<T *>(lds_u8);
+  T *lS = lC + int64_t(cs_rows) * M * cs;
+  const int64_t tab_bytes = TL ? int64_t(2) * cs_rows * M * cs * int64_t(sizeof(T)) : 0;
+  if constexpr (TL) {
+    const T *gCe = dm.ham == NQS_TFIM ? tb.fC : tb.bC;
+    const T *gSe = dm.ham == NQS_TFIM ? tb.fS : tb.bS;
+    const int64_t ce = int64_t(cs_rows) * M * cs;
+    for (int64_t e = threadIdx.x; e < ce; e += blockDim.x) {
+      lC[e] = gCe[e];
+      lS[e] = gSe[e];
     }
+    __syncthreads();
   }
-  double er, ei;
-  if (M <= 256) {
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (lane + 64 * r < M) tj[lane + 64 * r] = t[r];
+  int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + tab_bytes + int64_t(wid) * Npad);
+  // persistent blocks: the staged rows serve every sample the block visits
+  for (int64_t smp = int64_t(blockIdx.x) * (blockDim.x >> 6) + wid; smp < n;
+       smp += int64_t(gridDim.x) * (blockDim.x >> 6)) {
     wave_sync();
-    eloc_grouped<T, C, false>(dm, tb, sig, tj, lane, nullptr, nullptr, er, ei);
-  } else {
-    eloc_regs<T, C, R, false>(dm, tb, sig, t, lane, nullptr, nullptr, er, ei);
-  }
-  if (lane == 0) {
-    if (C) {
-      eloc[2 * smp] = er;
-      eloc[2 * smp + 1] = ei;
+    for (int i = lane; i < N; i += 64) sig[i] = sigma[smp * N + i];
+    wave_sync();
+    const T *trow = Tm + smp * M * cs;
+    double er, ei;
+    if (M <= 256) {
+      eloc_grouped<T, C, TL, (4 * R < 16 ? 4 * R : 16)>(dm, tb, sig, trow, lane, lC, lS, er, ei);
     } else {
-      eloc[smp] = er;
+      V<T, C> t[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        t[r] = lane + 64 * r < M ? vload<T, C>(trow, lane + 64 * r) : vmake<T, C>(T(0), T(0));
+      eloc_regs<T, C, R, TL>(dm, tb, sig, t, lane, lC, lS, er, ei);
+    }
+    if (lane == 0) {
+      if (C) {
+        eloc[2 * smp] = er;
+        eloc[2 * smp + 1] = ei;
+      } else {
+        eloc[smp] = er;
+      }
     }
   }
 }
@@ -793,29 +803,45 @@ hipError_t sweep_t(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
 }
 
 template <typename T, bool C, int R>
-hipError_t eloc_r(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,
-                  hipStream_t st) {
+hipError_t eloc_r(const nqs_model *m, const int8_t *sigma, const void *Tm, int64_t n,
+                  void *eloc, hipStream_t st) {
   const int Npad = round_up(m->N, 16);
-  const int wave_bytes = Npad + round_up(m->M * int(sizeof(V<T, C>)), 16);
   const int wpb = 4;
-  dim3 grid(unsigned((n + wpb - 1) / wpb));
-  hipLaunchKernelGGL((k_local_energy<T, C, R>), grid, dim3(64 * wpb), size_t(wpb) * wave_bytes,
-                     st, dev_model(m), tables_of<T>(m), sigma, n, (double *)eloc, Npad,
-                     wave_bytes);
+  const int cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
+  const size_t tab_lds = size_t(2) * cs_rows * m->M * sizeof(T) * (C ? 2 : 1);
+  const size_t wave_lds = size_t(wpb) * Npad;
+  // persistent grid: as many blocks as fit on the device at once (at most 8 per CU)
+  const bool tl = tab_lds + wave_lds <= size_t(m->max_lds) / 2;
+  int per_cu = 8;
+  if (tl) {
+    const int by_lds = int(size_t(160 * 1024) / (tab_lds + wave_lds));
+    per_cu = by_lds < 1 ? 1 : (by_lds < 8 ? by_lds : 8);
+  }
+  int64_t blocks = (n + wpb - 1) / wpb;
+  if (blocks > int64_t(per_cu) * m->cu_count) blocks = int64_t(per_cu) * m->cu_count;
+  dim3 grid((unsigned)blocks);
+  if (tl)
+    hipLaunchKernelGGL((k_local_energy<T, C, R, true>), grid, dim3(64 * wpb), tab_lds + wave_lds,
+                       st, dev_model(m), tables_of<T>(m), sigma, (const T *)Tm, n,
+                       (double *)eloc, Npad, cs_rows);
+  else
+    hipLaunchKernelGGL((k_local_energy<T, C, R, false>), grid, dim3(64 * wpb), wave_lds, st,
+                       dev_model(m), tables_of<T>(m), sigma, (const T *)Tm, n, (double *)eloc,
+                       Npad, cs_rows);
   return hipGetLastError();
 }
 
 template <typename T, bool C>
-hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,
-                  hipStream_t st) {
+hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64_t n,
+                  void *eloc, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const int r = (m->M + 63) / 64;
-  if (r <= 1) return eloc_r<T, C, 1>(m, sigma, n, eloc, st);
-  if (r <= 2) return eloc_r<T, C, 2>(m, sigma, n, eloc, st);
-  if (r <= 4) return eloc_r<T, C, 4>(m, sigma, n, eloc, st);
-  if (r <= 8) return eloc_r<T, C, 8>(m, sigma, n, eloc, st);
-  if (r <= 16) return eloc_r<T, C, 16>(m, sigma, n, eloc, st);
-  return eloc_r<T, C, 32>(m, sigma, n, eloc, st);
+  if (r <= 1) return eloc_r<T, C, 1>(m, sigma, Tm, n, eloc, st);
+  if (r <= 2) return eloc_r<T, C, 2>(m, sigma, Tm, n, eloc, st);
+  if (r <= 4) return eloc_r<T, C, 4>(m, sigma, Tm, n, eloc, st);
+  if (r <= 8) return eloc_r<T, C, 8>(m, sigma, Tm, n, eloc, st);
+  if (r <= 16) return eloc_r<T, C, 16>(m, sigma, Tm, n, eloc, st);
+  return eloc_r<T, C, 32>(m, sigma, Tm, n, eloc, st);
 }
 
 template <typename T, bool C>
@@ -863,9 +889,9 @@ hipError_t launch_sweep(const nqs_model *m, int8_t *chain_sigma, int n_chains, i
                       chain_offset, samples, n_acc, eloc, st);
 }
 
-hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, int64_t n, void *eloc,
-                               hipStream_t st) {
-  return NQS_DISPATCH(eloc_t, m, sigma, n, eloc, st);
+hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, const void *Tm,
+                               int64_t n, void *eloc, hipStream_t st) {
+  return NQS_DISPATCH(eloc_t, m, sigma, Tm, n, eloc, st);
 }
 
 hipError_t launch_log_psi(const nqs_model *m, const int8_t *sigma, int64_t n, void *out,

@@ -178,6 +178,23 @@ def cg_sensitivity(O, el, shift, iters, rel=1e-15, seed=0):
     return np.abs(x1 - x0).max() / np.abs(x0).max()
 
 
+@pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f32", "j1j2_4x4_cplx_f64", "heis6x6_cplx_f32"])
+def test_local_energy_fused_in_sweep(lib, name):
+    """With >= 16 chains per compute unit the local energies are evaluated inside the
+    sweep kernel; check a random subset of them against the oracle."""
+    m, om = cases.build(lib, name)
+    p = cases.params(name, seed=42)
+    C = 16 * torch.cuda.get_device_properties(0).multi_processor_count
+    ch = torch.empty((C, om.n_sites), dtype=torch.int8, device=DEV)
+    m.chain_init(ch, seed=4)
+    smp, el = m.sample(to_dev(p), ch, 2, 1, seed=4, counter=0, with_eloc=True)
+    flat = smp.reshape(-1, om.n_sites).cpu().numpy()
+    rows = np.random.default_rng(0).choice(flat.shape[0], 150, replace=False)
+    exp = oh.local_energy(om, p.astype(np.complex128 if m.is_complex else np.float64), flat[rows])
+    scale = max(1.0, np.abs(exp).max())
+    assert np.abs(el.cpu().numpy()[rows] - exp).max() <= cases.tol(name) * scale
+
+
 @pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f64", "j1j2_4x4_cplx_f64", "tfim5x5_j2_real_f64"])
 def test_sr_step_fixed_iterations(lib, name):
     """Both sides run exactly 12 CG products (tol = 0) in FP64. Energy, variance and force
