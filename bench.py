@@ -73,6 +73,54 @@ def cpu_baseline(w, N, M, seconds=15.0):
                       "%d passes in %.1f s" % (chains, sweeps, total_samples // (chains * sweeps), dt)}
 
 
+def sv_flops(n, N, M, cplx):
+    """Algorithmic flops of one S v product from cached tanh(theta) (n samples): z = sigma V
+    (n x N x M, real spins times a real or complex direction), y = sum_j T (v_b + z) + sigma
+    v_a, w = conj(T) y, O^dagger y = (w^T sigma, sum_s w, sigma^T y). Complex: 8nNM + 16nM +
+    4nN; real: 4nNM + 6nM + 4nN."""
+    if cplx:
+        return 8.0 * n * N * M + 16.0 * n * M + 4.0 * n * N
+    return 4.0 * n * N * M + 6.0 * n * M + 4.0 * n * N
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, if one exists for the current kernel sources (the summary
+    records a hash of them); None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    try:
+        srcs = fields["sources"].split()
+        h = hashlib.sha256()
+        for name in srcs:
+            with open(os.path.join(ROOT, name), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != fields["sources_sha256"]:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
+def copy_probe(torch, dev, mib=1024, reps=3):
+    """A plain device-to-device copy of known size, for calibrating the FETCH_SIZE and
+    WRITE_SIZE counters (each should read `mib` MiB per copy)."""
+    a = torch.empty(mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy probe: %d copies of %d MiB" % (reps, mib))
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -85,6 +133,8 @@ def main():
     ap.add_argument("--workload", default="heisenberg1d_n40_cplx_fp32_alpha2", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (chains sharded across GPUs, "
@@ -97,6 +147,8 @@ def main():
     import synth
 
     nqs.load()
+    if args.copy_probe:
+        copy_probe(torch, torch.device("cuda:0"))
     log("library loaded, building workload " + args.workload)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
@@ -149,44 +201,45 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     n_samp = S * C
 
-    # live per-launch timing of the two kernels that carry the work
+    # live per-launch timing of the two parts that carry the work: the sampling call
+    # (sweeps with fused local energies) and one S v product of the CG
     flat = samples.view(n_samp, N)
     reps = 5
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record(stream)
     for _ in range(reps):
-        model.sample(params, chains, S, 0, seed=99, counter=10 ** 6, samples=samples)
+        model.sample(params, chains, S, 0, seed=99, counter=10 ** 6, samples=samples, eloc=eloc)
     ev[1].record(stream)
     torch.cuda.synchronize()
     sweep_ms = ev[0].elapsed_time(ev[1]) / reps
-    u = torch.ones(n_samp, dtype=model.value_dtype, device=dev)
-    v = torch.ones(model.n_params, dtype=model.value_dtype, device=dev)
-    model.log_psi_grad(params, flat, u=u, v=v)
+    sv_reps = 20
+    sv_ws = model.sr_prepare(params, flat, workspace=ws)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    v = torch.randn(model.n_params, dtype=model.value_dtype, generator=gen).to(dev)
+    sv_out = torch.empty_like(v)
+    model.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
     ev[0].record(stream)
-    for _ in range(reps):
-        model.log_psi_grad(params, flat, u=u, v=v)
+    for _ in range(sv_reps):
+        model.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
     ev[1].record(stream)
     torch.cuda.synchronize()
-    mv_ms = ev[0].elapsed_time(ev[1]) / reps
+    mv_ms = ev[0].elapsed_time(ev[1]) / sv_reps
 
-    cplx = 2 if w["cplx"] else 1
-    # sweep: per proposal M ratio terms of (complex) multiply-add, |.|^2 and product
-    flops_term = 12 if w["cplx"] else 4
-    sweep_flops = float(n_samp) * N * M * flops_term
-    # one O v + one O^dagger u with theta recomputed: four real contractions n x N x M
-    # per complex part
-    mv_flops = 4.0 * 2 * n_samp * N * M * cplx
+    sweep_flops = float(n_samp) * N * M * (12 if w["cplx"] else 4)
+    mv_flops = sv_flops(n_samp, N, M, w["cplx"])
     share_sr = sr_ms / (samp_ms + sr_ms)
     if share_sr > 0.5:
         peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_MFMA
         ach = mv_flops / (mv_ms * 1e-3)
-        roof = {"kernel": "k_jvp+k_vjp (one S v product)", "bound": "mfma", "achieved": ach / 1e12,
-                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None}
+        roof = {"kernel": "S v product (k_prep_dir + k_sv + k_matvec_finish)", "bound": "mfma",
+                "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": recorded_traffic("k_sv", args.workload)}
     else:
         peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_VALU
         ach = sweep_flops / (sweep_ms * 1e-3)
         roof = {"kernel": "k_sweep", "bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None}
+                "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": recorded_traffic("k_sweep", args.workload)}
 
     out = {
         "metric": "samples/s (sweep+E_loc+O_k) and SR iters/s",

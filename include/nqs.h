@@ -180,6 +180,20 @@ nqs_status nqs_sr_step(nqs_model *model, void *params, const int8_t *sigma, cons
                        int32_t cg_maxiter, void *workspace, size_t ws_bytes,
                        nqs_sr_info *info, void *stream);
 
+/* The S v product of stochastic reconfiguration on its own (Sec. 2.2.5; the implicit form
+ * S v = O^dagger (O v - mean(O v)) / n of the same S as nqs_sr_step), for custom solvers
+ * and for measurement. nqs_sr_prepare computes tanh(theta) of every sample and
+ * O^dagger 1 into `workspace` (nqs_sr_workspace_bytes(model, n) bytes) from params and
+ * sigma [n, N]; then each nqs_sr_matvec writes out = (S + diag_shift I) v for v, out
+ * (device) [P] double / complex double, reusing the prepared workspace (the sigma passed
+ * must be the same). The workspace holds the preparation until it is reused by another
+ * call. Limits: n >= 2, diag_shift >= 0. */
+nqs_status nqs_sr_prepare(nqs_model *model, const void *params, const int8_t *sigma, int64_t n,
+                          void *workspace, size_t ws_bytes, void *stream);
+nqs_status nqs_sr_matvec(nqs_model *model, const int8_t *sigma, int64_t n, void *workspace,
+                         size_t ws_bytes, const void *v, double diag_shift, void *out,
+                         void *stream);
+
 const char *nqs_status_string(nqs_status s);
 
 #ifdef __cplusplus

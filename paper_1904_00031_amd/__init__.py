@@ -76,6 +76,8 @@ def load(path=LIB_PATH):
         "nqs_sr_workspace_bytes": (ctypes.c_size_t, [vp, i64]),
         "nqs_sr_step": (i32, [vp, vp, vp, vp, i64, f64, f64, f64, i32, vp, ctypes.c_size_t,
                               ctypes.POINTER(SRInfo), vp]),
+        "nqs_sr_prepare": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, vp]),
+        "nqs_sr_matvec": (i32, [vp, vp, i64, vp, ctypes.c_size_t, vp, f64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -88,7 +90,8 @@ def load(path=LIB_PATH):
 def exported_symbols():
     return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
             "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
-            "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step"]
+            "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_prepare",
+            "nqs_sr_matvec"]
 
 
 def _check(status, where, allow=(OK,)):
@@ -285,6 +288,36 @@ class Model:
         return d
 
 
+    def sr_prepare(self, params, sigma, workspace=None):
+        """Prepare the implicit S of these samples; returns the workspace to pass to
+        sr_matvec."""
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        nbytes = self.sr_workspace_bytes(n)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=sigma.device)
+        _need(workspace, "workspace", torch.uint8)
+        _check(_lib.nqs_sr_prepare(self._h, _ptr(params), _ptr(sigma), n, _ptr(workspace),
+                                   workspace.numel(), _stream()), "nqs_sr_prepare")
+        return workspace
+
+    def sr_matvec(self, sigma, workspace, v, diag_shift=0.0, out=None):
+        """out = (S + diag_shift I) v with the workspace of sr_prepare."""
+        import torch
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        _need(v, "v", self.value_dtype, (self.n_params,))
+        if out is None:
+            out = torch.empty(self.n_params, dtype=self.value_dtype, device=sigma.device)
+        _need(out, "out", self.value_dtype, (self.n_params,))
+        _check(_lib.nqs_sr_matvec(self._h, _ptr(sigma), n, _ptr(workspace), workspace.numel(),
+                                  _ptr(v), float(diag_shift), _ptr(out), _stream()),
+               "nqs_sr_matvec")
+        return out
+
+
 # C-ABI-named module functions --------------------------------------------------------
 def nqs_model_create(**kw):
     return Model(**kw)
@@ -312,6 +345,14 @@ def nqs_log_psi_grad(model, params, sigma, u=None, v=None, vjp=None, jvp=None):
 
 def nqs_sr_workspace_bytes(model, n):
     return model.sr_workspace_bytes(n)
+
+
+def nqs_sr_prepare(model, params, sigma, workspace=None):
+    return model.sr_prepare(params, sigma, workspace)
+
+
+def nqs_sr_matvec(model, sigma, workspace, v, diag_shift=0.0, out=None):
+    return model.sr_matvec(sigma, workspace, v, diag_shift, out)
 
 
 def nqs_sr_step(model, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None):

@@ -341,4 +341,19 @@ nqs_status nqs_sr_step(nqs_model *m, void *params, const int8_t *sigma, const vo
                       ws_bytes, info, (hipStream_t)stream);
 }
 
+nqs_status nqs_sr_prepare(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                          void *workspace, size_t ws_bytes, void *stream) {
+  if (!m || !params || !sigma || !workspace || n < 2) return NQS_EINVAL;
+  return sr_prepare_impl(m, params, sigma, n, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+nqs_status nqs_sr_matvec(nqs_model *m, const int8_t *sigma, int64_t n, void *workspace,
+                         size_t ws_bytes, const void *v, double diag_shift, void *out,
+                         void *stream) {
+  if (!m || !sigma || !workspace || !v || !out || n < 2 || !(diag_shift >= 0))
+    return NQS_EINVAL;
+  return sr_matvec_impl(m, sigma, n, workspace, ws_bytes, v, diag_shift, out,
+                        (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -90,6 +90,11 @@ hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, doubl
 
 // ---- SR (sr.hip) --------------------------------------------------------------------
 size_t sr_workspace_bytes(const nqs_model *m, int64_t n);
+nqs_status sr_prepare_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                           void *ws, size_t ws_bytes, hipStream_t st);
+nqs_status sr_matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws,
+                          size_t ws_bytes, const void *v, double lambda, void *out,
+                          hipStream_t st);
 nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
                         int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
                         void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st);

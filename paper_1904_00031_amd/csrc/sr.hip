@@ -462,9 +462,103 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   return hs.converged ? NQS_OK : NQS_ENOTCONV;
 }
 
+// out = (g - ybar O^dagger 1) / n + lambda v, g = O^dagger y from the first-level sums
+template <bool C>
+__global__ __launch_bounds__(256) void k_matvec_finish(int N, int M, int64_t n, int groups,
+                                                       int colsP, int64_t elems,
+                                                       const double *out1, const double *o1,
+                                                       const double *ysum, int64_t nys,
+                                                       const double *v, double lambda,
+                                                       double *out) {
+  __shared__ double lds[256];
+  const int64_t P = int64_t(N) + M + int64_t(N) * M;
+  const double ybr = block_sum(ysum, nys, 2, lds) / double(n);
+  const double ybi = C ? block_sum(ysum + 1, nys, 2, lds) / double(n) : 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
+       k += int64_t(gridDim.x) * 256) {
+    int64_t e;
+    if (k < N)
+      e = int64_t(M) * colsP + k;
+    else if (k < N + M)
+      e = int64_t(k - N) * colsP + N;
+    else
+      e = ((k - N - M) / N) * colsP + ((k - N - M) % N);
+    double gr = 0.0, gi = 0.0;
+    for (int q = 0; q < groups; ++q) {
+      gr += out1[2 * (int64_t(q) * elems + e)];
+      gi += out1[2 * (int64_t(q) * elems + e) + 1];
+    }
+    if (C) {
+      gr -= ybr * o1[2 * k] - ybi * o1[2 * k + 1];
+      gi -= ybr * o1[2 * k + 1] + ybi * o1[2 * k];
+      out[2 * k] = gr / double(n) + lambda * v[2 * k];
+      out[2 * k + 1] = gi / double(n) + lambda * v[2 * k + 1];
+    } else {
+      out[k] = (gr - ybr * o1[k]) / double(n) + lambda * v[k];
+    }
+  }
+}
+
+template <bool C>
+nqs_status prepare_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                        void *ws, hipStream_t st) {
+  SRLayout L = sr_layout(m, n);
+  char *b = (char *)ws;
+  void *grad = b + L.grad;
+  HIPTRY(launch_tables(m, params, st));
+  HIPTRY(launch_theta_tanh(m, sigma, n, grad, st));
+  hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, (double *)(b + L.y));
+  HIPTRY(hipGetLastError());
+  HIPTRY(launch_vjp_partials(m, sigma, n, (double *)(b + L.y), grad, nullptr, st));
+  HIPTRY(launch_vjp_reduce(m, n, grad, (double *)(b + L.o1), nullptr, st));
+  return NQS_OK;
+}
+
+template <bool C>
+nqs_status matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws, const void *v,
+                       double lambda, void *out, hipStream_t st) {
+  SRLayout L = sr_layout(m, n);
+  char *b = (char *)ws;
+  void *grad = b + L.grad;
+  const GradPlan gp = grad_plan(m, n);
+  const GradBuffers gb = grad_buffers(m, n, grad);
+  const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+  const int64_t pblocks = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
+  const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
+  HIPTRY(launch_prep_dir(m, v, grad, st));
+  if (gp.fused) {
+    HIPTRY(launch_sv(m, sigma, n, grad, (double *)(b + L.ysum), nullptr, st));
+  } else {
+    HIPTRY(launch_jvp(m, sigma, n, grad, (double *)(b + L.y), (double *)(b + L.ysum), nullptr, st));
+    HIPTRY(launch_vjp_partials(m, sigma, n, (double *)(b + L.y), grad, nullptr, st));
+  }
+  const int64_t nys = gp.fused ? gp.splits : cdiv(n, 256);
+  hipLaunchKernelGGL((k_matvec_finish<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, m->N,
+                     m->M, n, gp.groups, gp.Itiles * 16, elems, gb.out1,
+                     (const double *)(b + L.o1), (const double *)(b + L.ysum), nys,
+                     (const double *)v, lambda, (double *)out);
+  HIPTRY(hipGetLastError());
+  return NQS_OK;
+}
+
 }  // namespace
 
 size_t sr_workspace_bytes(const nqs_model *m, int64_t n) { return sr_layout(m, n).total; }
+
+nqs_status sr_prepare_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                           void *ws, size_t ws_bytes, hipStream_t st) {
+  if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
+  return m->is_complex ? prepare_impl<true>(m, params, sigma, n, ws, st)
+                       : prepare_impl<false>(m, params, sigma, n, ws, st);
+}
+
+nqs_status sr_matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws,
+                          size_t ws_bytes, const void *v, double lambda, void *out,
+                          hipStream_t st) {
+  if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
+  return m->is_complex ? matvec_impl<true>(m, sigma, n, ws, v, lambda, out, st)
+                       : matvec_impl<false>(m, sigma, n, ws, v, lambda, out, st);
+}
 
 nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
                         int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,

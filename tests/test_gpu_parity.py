@@ -257,3 +257,62 @@ def test_sr_step_converged_and_notconv(lib):
     pt2 = to_dev(p.copy())
     info2 = m.sr_step(pt2, to_dev(s), to_dev(el), lr=0.05, diag_shift=0.01, cg_tol=1e-14, cg_maxiter=2)
     assert info2["status"] == 1 and info2["converged"] == 0 and info2["cg_iters"] == 2
+
+
+def _sv_expected(om, pe, s, v, shift):
+    """(S + shift I) v from the oracle's explicit S, and the size of the uncentred
+    product O^dagger O v / n that rounding is measured against."""
+    O = orbm.log_derivatives(pe, s, om.n_sites, om.n_hidden)
+    if not np.iscomplexobj(pe):
+        O = O.real
+    exp = osr.s_matrix(O) @ v + shift * v
+    scale = np.abs(O.conj().T @ (O @ v)).max() / s.shape[0]
+    return exp, scale
+
+
+@pytest.mark.parametrize("name,n", [("tfim10_real_f64", 700), ("heis40_cplx_f64", 700),
+                                    ("heis40_cplx_f32", 1000), ("j1j2_4x4_cplx_f32", 333),
+                                    ("tfim37_real_f32", 517), ("j1j2_6x6_cplx_f64", 129)])
+def test_sr_matvec(lib, name, n):
+    """nqs_sr_matvec against (S + lambda I) v with the oracle's explicit S, for two
+    directions in a row on one preparation (the workspace is reused)."""
+    m, om = cases.build(lib, name)
+    p = cases.params(name, theta=0.5, seed=61)
+    pe = p.astype(np.complex128 if m.is_complex else np.float64)
+    s = cases.configs(name, n, seed=10)
+    st = to_dev(s)
+    ws = m.sr_prepare(to_dev(p), st)
+    rng = np.random.default_rng(62)
+    for shift in (0.01, 0.0):
+        v = rng.normal(size=m.n_params)
+        if m.is_complex:
+            v = v + 1j * rng.normal(size=m.n_params)
+        got = m.sr_matvec(st, ws, to_dev(v), diag_shift=shift).cpu().numpy()
+        exp, scale = _sv_expected(om, pe, s, v, shift)
+        assert np.abs(got - exp).max() <= cases.tol(name) * max(scale, shift * np.abs(v).max())
+
+
+def test_sr_matvec_full_size_sampled(lib):
+    """The 40-site Heisenberg ring, complex FP32, alpha = 2, at the full 1024 chains x 200
+    sweeps = 204800 samples of the benchmark (same kernels and launch shape): entries of
+    S v computed one by one by the oracle (y = O v by chunks, then single columns of
+    O^dagger (y - mean y) / n)."""
+    name = "heis40_cplx_f32"
+    m, om = cases.build(lib, name)
+    p = cases.params(name, theta=0.3, seed=63)
+    pe = p.astype(np.complex128)
+    n = 1024 * 200
+    s = cases.configs(name, n, seed=11)
+    st = to_dev(s)
+    ws = m.sr_prepare(to_dev(p), st)
+    rng = np.random.default_rng(64)
+    v = rng.normal(size=m.n_params) + 1j * rng.normal(size=m.n_params)
+    got = m.sr_matvec(st, ws, to_dev(v), diag_shift=0.01).cpu().numpy()
+    y = np.concatenate([orbm.jvp(pe, s[i:i + 8192], v, om.n_sites, om.n_hidden)
+                        for i in range(0, n, 8192)])
+    N, M = om.n_sites, om.n_hidden
+    ks = np.unique(np.concatenate([[0, N - 1, N, N + M - 1, m.n_params - 1],
+                                   rng.integers(0, m.n_params, 27)]))
+    exp = orbm.vjp_entries(pe, s, y - y.mean(), ks, N, M) / n + 0.01 * v[ks]
+    scale = np.abs(orbm.vjp_entries(pe, s, y, ks, N, M)).max() / n
+    assert np.abs(got[ks] - exp).max() <= cases.tol(name) * scale
