@@ -10,6 +10,8 @@
 // Each wavefront owns 16 samples; the matrix-core instruction is the 16x16x4 FP32 or
 // FP64 MFMA (A: lane l holds A[l%16][l/16]; B: B[l/16][l%16]). Accumulator rows differ:
 // FP32 lane l register r holds D[4(l/16)+r][l%16], FP64 holds D[l/16+4r][l%16].
+#include <type_traits>
+
 #include "internal.hpp"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -533,6 +535,241 @@ __global__ __launch_bounds__(256) void k_sv(int N, int M, int64_t n,
   }
 }
 
+// Spins of every sample as a 64-bit mask (bit i set when spin i is up), N <= 63.
+__global__ void k_pack_spins(int N, int64_t n, const int8_t *__restrict__ sigma,
+                             uint64_t *masks) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int8_t *row = sigma + s * N;
+  uint64_t m = 0;
+  for (int i = 0; i < N; ++i) m |= uint64_t(row[i] > 0) << i;
+  masks[s] = m;
+}
+
+// ---------------------------------------------------------------------------------
+// Fused S v product for complex models with N <= 63 and all VJP tiles in one block.
+// The real and imaginary planes of both contractions are split between the two
+// wavefronts of a pair, which then hold half the accumulators each (two pairs = two
+// 16-sample groups in flight per block, two blocks per SIMD). Wavefront h of a pair:
+//   X_h = S (plane h of V)^T by MFMA, and its share of y:
+//     h = 0: Re y += Re T (X_0 + Re vb) + s.Re va,  Im y += Im T (X_0 + Re vb) + s.Im va
+//     h = 1: Re y -= Im T (X_1 + Im vb),            Im y += Re T (X_1 + Im vb)
+//   the 16 partial sums of y are exchanged through LDS (double-buffered, one barrier);
+//   then plane h of Z^T S with Z = conj(T) y:
+//     Re Z = Re T Re y + Im T Im y,  Im Z = Re T Im y - Im T Re y  (row M: Z = y).
+// Spins enter as 64-bit masks (k_pack_spins), so no spin tile is staged.
+// ---------------------------------------------------------------------------------
+template <typename T, int JT, int NT>
+__global__ __launch_bounds__(256, 2) void k_svc(int N, int M, int64_t n,
+                                                const uint64_t *__restrict__ masks,
+                                                const T *__restrict__ Tm,
+                                                const T *__restrict__ Vt_g,
+                                                const T *__restrict__ vb,
+                                                const double *__restrict__ va,
+                                                int64_t per_split, int rowsP, int colsP,
+                                                T *part, double *ysum_part, const int *skip) {
+  if (skip && *skip) return;
+  typedef typename MF<T>::acc Acc;
+  constexpr int JW = JT * 16;
+  constexpr int VS = JW + ((JT & 1) ? 0 : 16);  // plane row stride: 16 banks apart per k
+  constexpr int NVA = 4;                        // site columns per lane: lo + 16 c, N <= 63
+  extern __shared__ __align__(16) unsigned char lds_u8[];
+  __shared__ T ybuf[2][2][2][16][2];  // [parity][pair][plane of origin][row][re, im]
+  __shared__ T red[4][4][64];
+  __shared__ double dsum[2][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lo = lane & 15, hi = lane >> 4;
+  const int pr = wid >> 1, h = wid & 1;
+  const int Kp = (N + 3) / 4 * 4;
+  const int Mt = (M + 15) / 16, Jt = rowsP / 16;
+  T *Vl = reinterpret_cast<T *>(lds_u8);  // [plane][Kp][VS]
+  for (int e = threadIdx.x; e < 2 * Kp * VS; e += 256) {
+    const int pl = e / (Kp * VS), rem = e - pl * (Kp * VS);
+    const int k = rem / VS, j = rem - k * VS;
+    T x = T(0);
+    if (k < N && j < M) {
+      const V<T, true> v = vload<T, true>(Vt_g, int64_t(k) * M + j);
+      x = pl ? v.im : v.re;
+    }
+    Vl[e] = x;
+  }
+  // per-lane constants: plane h of vb for the lane's hidden columns, va for its sites
+  T vbh[JT], var[NVA], vai[NVA];
+#pragma unroll
+  for (int a = 0; a < JT; ++a) {
+    const int j = a * 16 + lo;
+    vbh[a] = j < M ? (h ? vb[2 * j + 1] : vb[2 * j]) : T(0);
+  }
+#pragma unroll
+  for (int c = 0; c < NVA; ++c) {
+    const int i = lo + 16 * c;
+    var[c] = i < N ? T(va[2 * i]) : T(0);
+    vai[c] = i < N ? T(va[2 * i + 1]) : T(0);
+  }
+  __syncthreads();
+  const T *Vp = Vl + h * Kp * VS;
+  const int64_t sbeg = int64_t(blockIdx.x) * per_split;
+  const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
+  const int64_t iters = send > sbeg ? (send - sbeg + 31) / 32 : 0;
+  Acc acc[JT][NT];
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+  double ysr = 0.0, ysi = 0.0;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t g = sbeg + 32 * it + 16 * pr;
+    const int64_t left = send - g;
+    const int rows_here = left <= 0 ? 0 : (left < 16 ? int(left) : 16);
+    const uint64_t mA = lo < rows_here ? masks[g + lo] : 0ull;
+    uint64_t mB[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = MF<T>::row(hi, q);
+      mB[q] = rr < rows_here ? masks[g + rr] : 0ull;
+    }
+    V<T, true> tv[JT][4];
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      const int j = a * 16 + lo;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = MF<T>::row(hi, r);
+        tv[a][r] = (j < M && rr < rows_here) ? vload<T, true>(Tm, (g + rr) * M + j)
+                                             : vmake<T, true>(T(0), T(0));
+      }
+    }
+    // ---- X_h = S (plane h of V)^T over the valid hidden tiles ----
+    Acc x[JT];
+#pragma unroll
+    for (int a = 0; a < JT; ++a) x[a] = Acc{0, 0, 0, 0};
+    for (int k0 = 0; k0 < Kp; k0 += 4) {
+      const int k = k0 + hi;
+      const T av = ((mA >> k) & 1ull) ? T(1) : T(-1);
+      T v[JT];
+#pragma unroll
+      for (int a = 0; a < JT; ++a) v[a] = Vp[k * VS + a * 16 + lo];
+#pragma unroll
+      for (int a = 0; a < JT; ++a)
+        if (a < Mt) x[a] = MF<T>::mma(av, v[a], x[a]);
+    }
+    // ---- this plane's share of y for rows MF::row(hi, r) ----
+    T yre[4], yim[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      yre[r] = T(0);
+      yim[r] = T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      if (a >= Mt) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const T xv = x[a][r] + vbh[a];
+        if (h == 0) {
+          yre[r] += tv[a][r].re * xv;
+          yim[r] += tv[a][r].im * xv;
+        } else {
+          yre[r] -= tv[a][r].im * xv;
+          yim[r] += tv[a][r].re * xv;
+        }
+      }
+    }
+    if (h == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < NVA; ++c) {
+          const T sgn = ((mB[r] >> (lo + 16 * c)) & 1ull) ? T(1) : T(-1);
+          yre[r] += sgn * var[c];
+          yim[r] += sgn * vai[c];
+        }
+    }
+    const int par = int(it & 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = MF<T>::row(hi, r);
+      yre[r] = rowsum16(yre[r]);
+      yim[r] = rowsum16(yim[r]);
+      if (rr >= rows_here) {
+        yre[r] = T(0);
+        yim[r] = T(0);
+      }
+      if (lo == 0) {
+        ybuf[par][pr][h][rr][0] = yre[r];
+        ybuf[par][pr][h][rr][1] = yim[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = MF<T>::row(hi, r);
+      yre[r] += ybuf[par][pr][h ^ 1][rr][0];
+      yim[r] += ybuf[par][pr][h ^ 1][rr][1];
+      if (h == 0 && lo == 0) {
+        ysr += double(yre[r]);
+        ysi += double(yim[r]);
+      }
+    }
+    // ---- plane h of Z^T S over the same 16 samples (step q: row MF::row(hi, q)) ----
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T z[JT];
+#pragma unroll
+      for (int a = 0; a < JT; ++a) {
+        const int j = a * 16 + lo;
+        const T zq = h == 0 ? tv[a][q].re * yre[q] + tv[a][q].im * yim[q]
+                            : tv[a][q].re * yim[q] - tv[a][q].im * yre[q];
+        z[a] = j == M ? (h == 0 ? yre[q] : yim[q]) : zq;
+      }
+      T bs[NT];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const int c = b * 16 + lo;
+        bs[b] = c < N ? (((mB[q] >> c) & 1ull) ? T(1) : T(-1)) : (c == N ? T(1) : T(0));
+      }
+#pragma unroll
+      for (int a = 0; a < JT; ++a)
+        if (a < Jt)
+#pragma unroll
+          for (int b = 0; b < NT; ++b) acc[a][b] = MF<T>::mma(z[a], bs[b], acc[a][b]);
+    }
+  }
+  // block sums: plane 0 of both pairs -> real part, plane 1 -> imaginary part
+  const int tid = threadIdx.x;
+  const int r = tid >> 6, l = tid & 63;
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[wid][q][lane] = acc[a][b][q];
+      __syncthreads();
+      const int jrow = a * 16 + MF<T>::row(l >> 4, r);
+      const int icol = b * 16 + (l & 15);
+      if (jrow < rowsP && icol < colsP) {
+        const int64_t o = (int64_t(blockIdx.x) * rowsP + jrow) * colsP + icol;
+        part[2 * o] = red[0][r][l] + red[2][r][l];
+        part[2 * o + 1] = red[1][r][l] + red[3][r][l];
+      }
+    }
+  dsum[0][tid] = ysr;
+  dsum[1][tid] = ysi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      dsum[0][tid] += dsum[0][tid + w];
+      dsum[1][tid] += dsum[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ysum_part[2 * blockIdx.x] = dsum[0][0];
+    ysum_part[2 * blockIdx.x + 1] = dsum[1][0];
+  }
+}
+
 // first reduction level: out1[g][e] = sum of partials of split group g (complex double)
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_vjp_reduce1(int splits, int groups, int64_t elems,
@@ -589,7 +826,7 @@ __global__ void k_vjp_reduce2(int N, int M, int groups, int colsP, int64_t elems
 // scratch layout (byte offsets), all regions 256-byte aligned
 // ---------------------------------------------------------------------------------
 struct GradLayout {
-  size_t Vt, vb, va, ypart, Tm, part, out1, total;
+  size_t Vt, vb, va, ypart, Tm, masks, part, out1, total;
 };
 
 GradLayout grad_layout(const nqs_model *m, int64_t n) {
@@ -608,6 +845,7 @@ GradLayout grad_layout(const nqs_model *m, int64_t n) {
   L.va = take(size_t(m->N) * 16);
   L.ypart = take(size_t(g.jchunks) * size_t(n) * 16);
   L.Tm = take(size_t(n) * m->M * es);
+  L.masks = take(g.pair ? size_t(n) * 8 : 0);
   L.part = take(size_t(g.splits) * elems * es);
   L.out1 = take(size_t(g.groups) * elems * 16);
   L.total = off;
@@ -637,6 +875,12 @@ hipError_t tanh_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scra
   hipLaunchKernelGGL((k_theta_tanh<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256),
                      0, st, m->N, m->M, n, sigma, (const T *)m->tab_ptrs[0],
                      (const T *)m->tab_ptrs[1], 16, (T *)(base + L.Tm));
+  if (g.pair) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack_spins, dim3(unsigned(cdiv(n, 256))), dim3(256), 0, st, m->N, n,
+                       sigma, (uint64_t *)(base + L.masks));
+  }
   return hipGetLastError();
 }
 
@@ -712,6 +956,20 @@ hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scr
   const int Kp = (m->N + 3) / 4 * 4;
   const size_t vbytes = (size_t(Kp) * JT * 16 * sizeof(T) * (C ? 2 : 1) + 15) / 16 * 16;
   const size_t tile_bytes = size_t(4) * 16 * NT * 16;
+  bool launched = false;
+  if constexpr (C && std::is_same<T, float>::value) {
+    if (g.pair) {
+      const int VS = JT * 16 + ((JT & 1) ? 0 : 16);
+      hipLaunchKernelGGL((k_svc<T, JT, NT>), dim3(unsigned(g.splits)), dim3(256),
+                         size_t(2) * Kp * VS * sizeof(T), st, m->N, m->M, n,
+                         (const uint64_t *)(base + L.masks), (const T *)(base + L.Tm),
+                         (const T *)(base + L.Vt), (const T *)(base + L.vb),
+                         (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
+                         g.Itiles * 16, (T *)(base + L.part), ysum_part, skip);
+      launched = true;
+    }
+  }
+  if (!launched)
   hipLaunchKernelGGL((k_sv<T, C, JT, NT>), dim3(unsigned(g.splits)), dim3(256),
                      vbytes + tile_bytes, st, m->N, m->M, n, sigma, (const T *)(base + L.Tm),
                      (const T *)(base + L.Vt), (const T *)(base + L.vb),
@@ -795,6 +1053,21 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
     const size_t es = (use_double(m) ? 8 : 4) * (m->is_complex ? 2 : 1);
     const size_t vbytes = size_t((m->N + 3) / 4 * 4) * g.JT * 16 * es;
     g.fused = tile_blocks == 1 && vbytes <= 48 * 1024;
+  }
+  // complex FP32 with N <= 63: the plane-split fused product (k_svc) with the smallest
+  // hidden-tile count covering rows 0..M, at most 6 x 3 accumulator tiles per wavefront
+  g.pair = false;
+  if (m->is_complex && !use_double(m) && m->N <= 63) {
+    static const int pj[4] = {1, 2, 4, 6};
+    const size_t Kp = size_t(m->N + 3) / 4 * 4;
+    for (int q = 0; q < 4; ++q)
+      if (pj[q] >= g.Jtiles && pj[q] * g.NT <= 18 &&
+          2 * Kp * size_t(pj[q] * 16 + ((pj[q] & 1) ? 0 : 16)) * 4 <= 54 * 1024) {
+        g.JT = pj[q];
+        g.pair = true;
+        g.fused = true;
+        break;
+      }
   }
   if (g.fused) {
     // fused S v: blocks of 4 wavefronts x 16-sample groups

@@ -54,6 +54,7 @@ struct GradPlan {
   int64_t per_split;  // samples per split (multiple of 16)
   int groups;    // first-level reduction groups of the VJP partials
   bool fused;    // all VJP tiles fit one block: S v in one pass (k_sv)
+  bool pair;     // fused, complex FP32 and N <= 63: plane-split pairs on spin masks (k_svc)
   int jchunks;   // hidden chunks of 16 tiles in the JVP / tanh kernels (grid y)
   int64_t jvp_blocks; // sample tiles of 64 in the JVP / tanh kernels
 };

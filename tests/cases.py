@@ -20,6 +20,7 @@ CASES = {
     # ragged sizes: N = 37 ring, M = 74; 5x5 TFIM with a J2 term
     "tfim37_real_f32": (37, 1, False, 0, (1.0, 0.0), 0.8, False, 0, False, 1, 74),
     "tfim37_cplx_f64": (37, 1, False, 0, (1.0, 0.0), 1.3, False, 0, True, 0, 74),
+    "tfim37_cplx_f32_m37": (37, 1, False, 0, (1.0, 0.0), 0.9, False, 0, True, 1, 37),
     "tfim5x5_j2_real_f64": (5, 2, True, 0, (1.0, -0.3), 1.1, False, 0, False, 0, 50),
     # Heisenberg without Marshall rotation, single flips, real FP64
     "heis12_real_f64_flip": (12, 1, False, 1, (1.0, 0.0), 0.0, False, 0, False, 0, 36),
