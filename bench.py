@@ -184,6 +184,10 @@ def main():
             times.append((e0, e1, e2, info))
         return info
 
+    # pick the S v kernel shape for this model and sample count (timed on the
+    # initial chains, before the timed region)
+    tune = model.autotune(params, chains.repeat(S, 1), workspace=ws)
+    log("autotune: %s" % tune)
     for k in range(args.warmup):
         info = step(max(10, S // 10) if k == 0 else 0, None)
         log("warmup step %d: E=%.8f cg_iters=%d" % (k, info["energy_re"], info["cg_iters"]))
@@ -231,7 +235,8 @@ def main():
     if share_sr > 0.5:
         peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_MFMA
         ach = mv_flops / (mv_ms * 1e-3)
-        roof = {"kernel": "S v product (k_prep_dir + k_sv + k_matvec_finish)", "bound": "mfma",
+        roof = {"kernel": "S v product (direction tables, fused contraction, partial-sum "
+                          "reduction, centring)", "bound": "mfma",
                 "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": recorded_traffic("k_sv", args.workload)}
     else:
@@ -259,6 +264,7 @@ def main():
         "cg_iters_mean": float(np.mean(cg)),
         "energy_last": energies[-1],
         "kernel_ms": {"sample_call": sweep_ms, "sv_product": mv_ms},
+        "sv_tuning": tune,
         "roofline": roof,
     }
     log("timed %d steps: %.2f ms/step; oracle baseline next" % (args.steps, ms_per_step))

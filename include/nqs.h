@@ -194,6 +194,29 @@ nqs_status nqs_sr_matvec(nqs_model *model, const int8_t *sigma, int64_t n, void 
                          size_t ws_bytes, const void *v, double diag_shift, void *out,
                          void *stream);
 
+/* Tile-shape autotuner for the S v product of stochastic reconfiguration (the contraction
+ * that dominates an SR step, Sec. 2.2.5). Times every kernel shape that applies to this
+ * model at this sample count (n samples sigma [n, N] on the device, parameters params)
+ * with one prepared workspace (nqs_sr_workspace_bytes(model, n) bytes), ten products
+ * each, and keeps the fastest in the model for all later calls. Workspace sizes do not
+ * depend on the shape chosen. Synchronizes the stream. report (host, may be NULL)
+ * receives the candidates and their mean times. The product's result differs between
+ * shapes only by floating-point summation order. */
+#define NQS_TUNE_MAX 4
+typedef struct {
+  int32_t n_candidates;          /* shapes timed (1 when the model has no choice) */
+  int32_t chosen;                /* index of the shape kept */
+  int32_t pairs[NQS_TUNE_MAX];   /* wavefront pairs per block of each candidate */
+  double us[NQS_TUNE_MAX];       /* mean microseconds of one S v product */
+} nqs_tune_report;
+nqs_status nqs_autotune(nqs_model *model, const void *params, const int8_t *sigma, int64_t n,
+                        void *workspace, size_t ws_bytes, nqs_tune_report *report,
+                        void *stream);
+/* Re-applies a shape the autotuner chose earlier (report.pairs[report.chosen]) without
+ * timing again; 2 or 4, otherwise NQS_EINVAL. Models where the shape does not apply
+ * ignore it. */
+nqs_status nqs_set_sv_shape(nqs_model *model, int32_t pairs);
+
 const char *nqs_status_string(nqs_status s);
 
 #ifdef __cplusplus

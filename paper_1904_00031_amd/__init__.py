@@ -41,6 +41,17 @@ class _Desc(ctypes.Structure):
     ]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [
+        ("n_candidates", ctypes.c_int32), ("chosen", ctypes.c_int32),
+        ("pairs", ctypes.c_int32 * 4), ("us", ctypes.c_double * 4),
+    ]
+
+    def as_dict(self):
+        n = self.n_candidates
+        return {"chosen": self.chosen, "pairs": list(self.pairs[:n]), "us": list(self.us[:n])}
+
+
 class SRInfo(ctypes.Structure):
     _fields_ = [
         ("cg_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
@@ -78,6 +89,8 @@ def load(path=LIB_PATH):
                               ctypes.POINTER(SRInfo), vp]),
         "nqs_sr_prepare": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, vp]),
         "nqs_sr_matvec": (i32, [vp, vp, i64, vp, ctypes.c_size_t, vp, f64, vp, vp]),
+        "nqs_set_sv_shape": (i32, [vp, i32]),
+        "nqs_autotune": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, ctypes.POINTER(TuneReport), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -91,7 +104,7 @@ def exported_symbols():
     return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
             "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
             "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_prepare",
-            "nqs_sr_matvec"]
+            "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape"]
 
 
 def _check(status, where, allow=(OK,)):
@@ -318,6 +331,27 @@ class Model:
         return out
 
 
+    def autotune(self, params, sigma, workspace=None):
+        """Time the S v kernel shapes for these samples and keep the fastest; returns
+        {"chosen", "pairs", "us"}."""
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        if workspace is None:
+            workspace = torch.empty(self.sr_workspace_bytes(n), dtype=torch.uint8,
+                                    device=sigma.device)
+        _need(workspace, "workspace", torch.uint8)
+        rep = TuneReport()
+        _check(_lib.nqs_autotune(self._h, _ptr(params), _ptr(sigma), n, _ptr(workspace),
+                                 workspace.numel(), ctypes.byref(rep), _stream()), "nqs_autotune")
+        return rep.as_dict()
+
+
+    def set_sv_shape(self, pairs):
+        _check(_lib.nqs_set_sv_shape(self._h, int(pairs)), "nqs_set_sv_shape")
+
+
 # C-ABI-named module functions --------------------------------------------------------
 def nqs_model_create(**kw):
     return Model(**kw)
@@ -353,6 +387,14 @@ def nqs_sr_prepare(model, params, sigma, workspace=None):
 
 def nqs_sr_matvec(model, sigma, workspace, v, diag_shift=0.0, out=None):
     return model.sr_matvec(sigma, workspace, v, diag_shift, out)
+
+
+def nqs_set_sv_shape(model, pairs):
+    return model.set_sv_shape(pairs)
+
+
+def nqs_autotune(model, params, sigma, workspace=None):
+    return model.autotune(params, sigma, workspace)
 
 
 def nqs_sr_step(model, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None):

@@ -356,4 +356,17 @@ nqs_status nqs_sr_matvec(nqs_model *m, const int8_t *sigma, int64_t n, void *wor
                         (hipStream_t)stream);
 }
 
+nqs_status nqs_autotune(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                        void *workspace, size_t ws_bytes, nqs_tune_report *report,
+                        void *stream) {
+  if (!m || !params || !sigma || !workspace || n < 2) return NQS_EINVAL;
+  return autotune_impl(m, params, sigma, n, workspace, ws_bytes, report, (hipStream_t)stream);
+}
+
+nqs_status nqs_set_sv_shape(nqs_model *m, int32_t pairs) {
+  if (!m || (pairs != 2 && pairs != 4)) return NQS_EINVAL;
+  m->sv_pairs = pairs;
+  return NQS_OK;
+}
+
 }  // extern "C"

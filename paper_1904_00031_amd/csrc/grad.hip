@@ -559,8 +559,8 @@ __global__ void k_pack_spins(int N, int64_t n, const int8_t *__restrict__ sigma,
 //     Re Z = Re T Re y + Im T Im y,  Im Z = Re T Im y - Im T Re y  (row M: Z = y).
 // Spins enter as 64-bit masks (k_pack_spins), so no spin tile is staged.
 // ---------------------------------------------------------------------------------
-template <typename T, int JT, int NT>
-__global__ __launch_bounds__(256, 2) void k_svc(int N, int M, int64_t n,
+template <typename T, int JT, int NT, int PAIRS>
+__global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
                                                 const uint64_t *__restrict__ masks,
                                                 const T *__restrict__ Tm,
                                                 const T *__restrict__ Vt_g,
@@ -574,16 +574,17 @@ __global__ __launch_bounds__(256, 2) void k_svc(int N, int M, int64_t n,
   constexpr int VS = JW + ((JT & 1) ? 0 : 16);  // plane row stride: 16 banks apart per k
   constexpr int NVA = 4;                        // site columns per lane: lo + 16 c, N <= 63
   extern __shared__ __align__(16) unsigned char lds_u8[];
-  __shared__ T ybuf[2][2][2][16][2];  // [parity][pair][plane of origin][row][re, im]
-  __shared__ T red[4][4][64];
-  __shared__ double dsum[2][256];
+  constexpr int NTH = 128 * PAIRS;
+  __shared__ T ybuf[2][PAIRS][2][16][2];  // [parity][pair][plane of origin][row][re, im]
+  __shared__ T red[2 * PAIRS][4][64];
+  __shared__ double dsum[2][NTH];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
   const int pr = wid >> 1, h = wid & 1;
   const int Kp = (N + 3) / 4 * 4;
   const int Mt = (M + 15) / 16, Jt = rowsP / 16;
   T *Vl = reinterpret_cast<T *>(lds_u8);  // [plane][Kp][VS]
-  for (int e = threadIdx.x; e < 2 * Kp * VS; e += 256) {
+  for (int e = threadIdx.x; e < 2 * Kp * VS; e += NTH) {
     const int pl = e / (Kp * VS), rem = e - pl * (Kp * VS);
     const int k = rem / VS, j = rem - k * VS;
     T x = T(0);
@@ -610,7 +611,7 @@ __global__ __launch_bounds__(256, 2) void k_svc(int N, int M, int64_t n,
   const T *Vp = Vl + h * Kp * VS;
   const int64_t sbeg = int64_t(blockIdx.x) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
-  const int64_t iters = send > sbeg ? (send - sbeg + 31) / 32 : 0;
+  const int64_t iters = send > sbeg ? (send - sbeg + 16 * PAIRS - 1) / (16 * PAIRS) : 0;
   Acc acc[JT][NT];
 #pragma unroll
   for (int a = 0; a < JT; ++a)
@@ -618,7 +619,7 @@ __global__ __launch_bounds__(256, 2) void k_svc(int N, int M, int64_t n,
     for (int b = 0; b < NT; ++b) acc[a][b] = Acc{0, 0, 0, 0};
   double ysr = 0.0, ysi = 0.0;
   for (int64_t it = 0; it < iters; ++it) {
-    const int64_t g = sbeg + 32 * it + 16 * pr;
+    const int64_t g = sbeg + 16 * PAIRS * it + 16 * pr;
     const int64_t left = send - g;
     const int rows_here = left <= 0 ? 0 : (left < 16 ? int(left) : 16);
     const uint64_t mA = lo < rows_here ? masks[g + lo] : 0ull;
@@ -735,9 +736,9 @@ __global__ __launch_bounds__(256, 2) void k_svc(int N, int M, int64_t n,
           for (int b = 0; b < NT; ++b) acc[a][b] = MF<T>::mma(z[a], bs[b], acc[a][b]);
     }
   }
-  // block sums: plane 0 of both pairs -> real part, plane 1 -> imaginary part
+  // block sums: plane 0 of every pair -> real part, plane 1 -> imaginary part
   const int tid = threadIdx.x;
-  const int r = tid >> 6, l = tid & 63;
+  const int r = (tid >> 6) & 3, l = tid & 63;
 #pragma unroll
   for (int a = 0; a < JT; ++a)
 #pragma unroll
@@ -748,16 +749,22 @@ __global__ __launch_bounds__(256, 2) void k_svc(int N, int M, int64_t n,
       __syncthreads();
       const int jrow = a * 16 + MF<T>::row(l >> 4, r);
       const int icol = b * 16 + (l & 15);
-      if (jrow < rowsP && icol < colsP) {
+      if (tid < 256 && jrow < rowsP && icol < colsP) {
         const int64_t o = (int64_t(blockIdx.x) * rowsP + jrow) * colsP + icol;
-        part[2 * o] = red[0][r][l] + red[2][r][l];
-        part[2 * o + 1] = red[1][r][l] + red[3][r][l];
+        T sr = T(0), si = T(0);
+#pragma unroll
+        for (int p = 0; p < PAIRS; ++p) {
+          sr += red[2 * p][r][l];
+          si += red[2 * p + 1][r][l];
+        }
+        part[2 * o] = sr;
+        part[2 * o + 1] = si;
       }
     }
   dsum[0][tid] = ysr;
   dsum[1][tid] = ysi;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = NTH / 2; w > 0; w >>= 1) {
     if (tid < w) {
       dsum[0][tid] += dsum[0][tid + w];
       dsum[1][tid] += dsum[1][tid + w];
@@ -846,7 +853,11 @@ GradLayout grad_layout(const nqs_model *m, int64_t n) {
   L.ypart = take(size_t(g.jchunks) * size_t(n) * 16);
   L.Tm = take(size_t(n) * m->M * es);
   L.masks = take(g.pair ? size_t(n) * 8 : 0);
-  L.part = take(size_t(g.splits) * elems * es);
+  // sized for the largest split count any plan of this device uses, so that a later
+  // change of the tuned S v shape never outgrows a workspace sized earlier
+  const size_t splits_cap = size_t(g.splits) > size_t(2 * m->cu_count) ? size_t(g.splits)
+                                                                        : size_t(2 * m->cu_count);
+  L.part = take(splits_cap * elems * es);
   L.out1 = take(size_t(g.groups) * elems * 16);
   L.total = off;
   return L;
@@ -960,7 +971,15 @@ hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scr
   if constexpr (C && std::is_same<T, float>::value) {
     if (g.pair) {
       const int VS = JT * 16 + ((JT & 1) ? 0 : 16);
-      hipLaunchKernelGGL((k_svc<T, JT, NT>), dim3(unsigned(g.splits)), dim3(256),
+      if (g.pairs == 4)
+        hipLaunchKernelGGL((k_svc<T, JT, NT, 4>), dim3(unsigned(g.splits)), dim3(512),
+                           size_t(2) * Kp * VS * sizeof(T), st, m->N, m->M, n,
+                           (const uint64_t *)(base + L.masks), (const T *)(base + L.Tm),
+                           (const T *)(base + L.Vt), (const T *)(base + L.vb),
+                           (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
+                           g.Itiles * 16, (T *)(base + L.part), ysum_part, skip);
+      else
+      hipLaunchKernelGGL((k_svc<T, JT, NT, 2>), dim3(unsigned(g.splits)), dim3(256),
                          size_t(2) * Kp * VS * sizeof(T), st, m->N, m->M, n,
                          (const uint64_t *)(base + L.masks), (const T *)(base + L.Tm),
                          (const T *)(base + L.Vt), (const T *)(base + L.vb),
@@ -1069,12 +1088,14 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
         break;
       }
   }
+  g.pairs = g.pair ? (m->sv_pairs == 4 ? 4 : 2) : 0;
   if (g.fused) {
-    // fused S v: blocks of 4 wavefronts x 16-sample groups
-    int64_t sp = 512;
-    const int64_t groups64 = n > 0 ? cdiv(n, 64) : 1;
-    if (sp > groups64) sp = groups64;
-    g.per_split = rup(cdiv(n > 0 ? n : 1, sp), 64);
+    // fused S v: two blocks of 4 wavefronts per compute unit (one of 8 with 4 pairs),
+    // splits of whole 16-sample groups
+    int64_t sp = g.pairs == 4 ? int64_t(m->cu_count) : 2 * int64_t(m->cu_count);
+    const int64_t groups16 = n > 0 ? cdiv(n, 16) : 1;
+    if (sp > groups16) sp = groups16;
+    g.per_split = rup(cdiv(n > 0 ? n : 1, sp), 16);
     g.splits = int(cdiv(n > 0 ? n : 1, g.per_split));
   }
   g.groups = g.splits < 16 ? g.splits : 16;

@@ -21,6 +21,7 @@ struct nqs_model {
   void *tab_ptrs[14] = {};         // sub-buffers of d_tables, in Tables<T> member order
   int max_lds = 65536;             // dynamic LDS bytes a workgroup may use on this device
   int cu_count = 256;              // compute units of the device
+  int sv_pairs = 2;                // plane-split S v: wavefront pairs per block (2 or 4)
   // grow-only scratch for nqs_log_psi_grad
   void *d_scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -55,6 +56,7 @@ struct GradPlan {
   int groups;    // first-level reduction groups of the VJP partials
   bool fused;    // all VJP tiles fit one block: S v in one pass (k_sv)
   bool pair;     // fused, complex FP32 and N <= 63: plane-split pairs on spin masks (k_svc)
+  int pairs;     // wavefront pairs per k_svc block
   int jchunks;   // hidden chunks of 16 tiles in the JVP / tanh kernels (grid y)
   int64_t jvp_blocks; // sample tiles of 64 in the JVP / tanh kernels
 };
@@ -96,6 +98,8 @@ nqs_status sr_prepare_impl(nqs_model *m, const void *params, const int8_t *sigma
 nqs_status sr_matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws,
                           size_t ws_bytes, const void *v, double lambda, void *out,
                           hipStream_t st);
+nqs_status autotune_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                         void *ws, size_t ws_bytes, nqs_tune_report *rep, hipStream_t st);
 nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
                         int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
                         void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st);

@@ -319,7 +319,8 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   L.grad = take(grad_scratch_bytes(m, n));
   L.y = take(size_t(n) * cs * 8);
   const int64_t ns = grad_plan(m, n).splits;
-  L.ysum = take(size_t(nb > ns ? nb : ns) * 16);
+  const int64_t ncap = ns > 2 * int64_t(m->cu_count) ? ns : 2 * int64_t(m->cu_count);
+  L.ysum = take(size_t(nb > ncap ? nb : ncap) * 16);
   L.u = take(size_t(n) * cs * 8);
   L.e_part = take(size_t(nb) * 16);
   L.e_part2 = take(size_t(nb) * 8);
@@ -558,6 +559,65 @@ nqs_status sr_matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws
   if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
   return m->is_complex ? matvec_impl<true>(m, sigma, n, ws, v, lambda, out, st)
                        : matvec_impl<false>(m, sigma, n, ws, v, lambda, out, st);
+}
+
+nqs_status autotune_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                         void *ws, size_t ws_bytes, nqs_tune_report *rep, hipStream_t st) {
+  SRLayout L = sr_layout(m, n);
+  if (ws_bytes < L.total) return NQS_ENOMEM;
+  char *b = (char *)ws;
+  const int cs = m->is_complex ? 2 : 1;
+  const int64_t Pc = (int64_t(m->N) + m->M + int64_t(m->N) * m->M) * cs;
+  int cand[NQS_TUNE_MAX];
+  int nc = 0;
+  const int keep = m->sv_pairs;
+  m->sv_pairs = 2;
+  const bool pair = grad_plan(m, n).pair;
+  cand[nc++] = 2;
+  if (pair) cand[nc++] = 4;
+  nqs_status s = sr_prepare_impl(m, params, sigma, n, ws, ws_bytes, st);
+  if (s != NQS_OK) {
+    m->sv_pairs = keep;
+    return s;
+  }
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(Pc)), dim3(256), 0, st, Pc, (double *)(b + L.p), 1.0);
+  HIPTRY(hipGetLastError());
+  hipEvent_t e0, e1;
+  HIPTRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return NQS_EDEVICE;
+  }
+  double us[NQS_TUNE_MAX] = {0, 0, 0, 0};
+  const int reps = 10;
+  int best = 0;
+  for (int c = 0; c < nc && s == NQS_OK; ++c) {
+    m->sv_pairs = cand[c];
+    for (int q = 0; q < reps + 2 && s == NQS_OK; ++q) {
+      if (q == 2 && hipEventRecord(e0, st) != hipSuccess) s = NQS_EDEVICE;
+      if (s == NQS_OK)
+        s = sr_matvec_impl(m, sigma, n, ws, ws_bytes, b + L.p, 0.0, b + L.Ap, st);
+    }
+    float ms = 0.f;
+    if (s == NQS_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                        hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      s = NQS_EDEVICE;
+    us[c] = 1e3 * double(ms) / reps;
+    if (us[c] < us[best]) best = c;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  m->sv_pairs = s == NQS_OK ? cand[best] : keep;
+  if (rep) {
+    rep->n_candidates = nc;
+    rep->chosen = best;
+    for (int c = 0; c < NQS_TUNE_MAX; ++c) {
+      rep->pairs[c] = c < nc ? cand[c] : 0;
+      rep->us[c] = c < nc ? us[c] : 0.0;
+    }
+  }
+  return s;
 }
 
 nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,

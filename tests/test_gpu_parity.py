@@ -296,6 +296,30 @@ def test_sr_matvec(lib, name, n):
         assert np.abs(got - exp).max() <= cases.tol(name) * max(scale, shift * np.abs(v).max())
 
 
+@pytest.mark.parametrize("name,n", [("heis40_cplx_f32", 3000), ("tfim37_cplx_f32_m37", 777)])
+def test_sv_shapes_and_autotune(lib, name, n):
+    """Every S v kernel shape the autotuner may pick agrees with the oracle's explicit S;
+    the autotuner times them all and keeps one."""
+    m, om = cases.build(lib, name)
+    p = cases.params(name, theta=cases.theta_scale(name), seed=65)
+    pe = p.astype(np.complex128)
+    s = cases.configs(name, n, seed=12)
+    st = to_dev(s)
+    rng = np.random.default_rng(66)
+    v = rng.normal(size=m.n_params) + 1j * rng.normal(size=m.n_params)
+    exp, scale = _sv_expected(om, pe, s, v, 0.01)
+    for pairs in (2, 4):
+        m.set_sv_shape(pairs)
+        ws = m.sr_prepare(to_dev(p), st)
+        got = m.sr_matvec(st, ws, to_dev(v), diag_shift=0.01).cpu().numpy()
+        assert np.abs(got - exp).max() <= cases.tol(name) * scale, pairs
+    rep = m.autotune(to_dev(p), st)
+    assert rep["pairs"] == [2, 4] and all(t > 0 for t in rep["us"])
+    ws = m.sr_prepare(to_dev(p), st)
+    got = m.sr_matvec(st, ws, to_dev(v), diag_shift=0.01).cpu().numpy()
+    assert np.abs(got - exp).max() <= cases.tol(name) * scale
+
+
 def test_sr_matvec_full_size_sampled(lib):
     """The 40-site Heisenberg ring, complex FP32, alpha = 2, at the full 1024 chains x 200
     sweeps = 204800 samples of the benchmark (same kernels and launch shape): entries of
