@@ -546,6 +546,54 @@ __global__ void k_pack_spins(int N, int64_t n, const int8_t *__restrict__ sigma,
   masks[s] = m;
 }
 
+// rows of the 16-sample group starting at g that lie before send (0..16)
+__device__ __forceinline__ int svc_rows(int64_t send, int64_t g) {
+  const int64_t left = send - g;
+  return left <= 0 ? 0 : (left < 16 ? int(left) : 16);
+}
+
+// masks (A operand rows lo, accumulator rows MF::row(hi, q)) and T rows of one group.
+// Loads are unconditional with selects after them (no branches around loads). FULL: all
+// 16 rows valid. Otherwise rows outside the group read a valid row of the group (or row
+// 0) and are zeroed. Hidden tiles below JV - 1 are complete; tile JV - 1 reads columns
+// j >= M past the row end (next row, or the slack after T) and zeroes them; tiles from
+// JV on hold no hidden unit and are not loaded.
+template <typename T, int JT, int JV, bool FULL>
+__device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
+                                         const T *__restrict__ Tm, int M, int64_t g,
+                                         int rows_here, int lo, int hi, uint64_t &mA,
+                                         uint64_t (&mB)[4], V<T, true> (&tv)[JT][4]) {
+  const int64_t gc = FULL || rows_here > 0 ? g : 0;
+  {
+    const bool ok = FULL || lo < rows_here;
+    const uint64_t x = masks[gc + (ok ? lo : 0)];
+    mA = ok ? x : 0ull;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = MF<T>::row(hi, q);
+    const bool ok = FULL || rr < rows_here;
+    const uint64_t x = masks[gc + (ok ? rr : 0)];
+    mB[q] = ok ? x : 0ull;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = MF<T>::row(hi, r);
+    const bool okr = FULL || rr < rows_here;
+    const T *rowp = Tm + 2 * ((gc + (okr ? rr : 0)) * M + lo);
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      if (a >= JV) {
+        tv[a][r] = vmake<T, true>(T(0), T(0));
+        continue;
+      }
+      const V<T, true> x = vload<T, true>(rowp, a * 16);
+      const bool ok = okr && (a < JV - 1 || a * 16 + lo < M);
+      tv[a][r] = ok ? x : vmake<T, true>(T(0), T(0));
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // Fused S v product for complex models with N <= 63 and all VJP tiles in one block.
 // The real and imaginary planes of both contractions are split between the two
@@ -554,12 +602,15 @@ __global__ void k_pack_spins(int N, int64_t n, const int8_t *__restrict__ sigma,
 //   X_h = S (plane h of V)^T by MFMA, and its share of y:
 //     h = 0: Re y += Re T (X_0 + Re vb) + s.Re va,  Im y += Im T (X_0 + Re vb) + s.Im va
 //     h = 1: Re y -= Im T (X_1 + Im vb),            Im y += Re T (X_1 + Im vb)
-//   the 16 partial sums of y are exchanged through LDS (double-buffered, one barrier);
+//   the 16 partial sums of y are exchanged through LDS (double-buffered, flag-synchronised
+//   within the pair);
 //   then plane h of Z^T S with Z = conj(T) y:
 //     Re Z = Re T Re y + Im T Im y,  Im Z = Re T Im y - Im T Re y  (row M: Z = y).
 // Spins enter as 64-bit masks (k_pack_spins), so no spin tile is staged.
+// JT = ceil((M+1)/16) hidden tiles of the VJP output, JV = ceil(M/16) of them carry
+// hidden units in the JVP, NT = ceil((N+1)/16) site tiles.
 // ---------------------------------------------------------------------------------
-template <typename T, int JT, int NT, int PAIRS>
+template <typename T, int JT, int JV, int NT, int PAIRS>
 __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
                                                 const uint64_t *__restrict__ masks,
                                                 const T *__restrict__ Tm,
@@ -582,7 +633,6 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   const int lo = lane & 15, hi = lane >> 4;
   const int pr = wid >> 1, h = wid & 1;
   const int Kp = (N + 3) / 4 * 4;
-  const int Mt = (M + 15) / 16, Jt = rowsP / 16;
   T *Vl = reinterpret_cast<T *>(lds_u8);  // [plane][Kp][VS]
   for (int e = threadIdx.x; e < 2 * Kp * VS; e += NTH) {
     const int pl = e / (Kp * VS), rem = e - pl * (Kp * VS);
@@ -594,21 +644,22 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     }
     Vl[e] = x;
   }
-  // per-lane constants: plane h of vb for the lane's hidden columns, va for its sites
-  T vbh[JT], var[NVA], vai[NVA];
-#pragma unroll
-  for (int a = 0; a < JT; ++a) {
-    const int j = a * 16 + lo;
-    vbh[a] = j < M ? (h ? vb[2 * j + 1] : vb[2 * j]) : T(0);
+  // both planes of vb (zero past M) and va (zero past N) in LDS, read per group
+  __shared__ T vbl[2][JW];
+  __shared__ T val[2][16 * NVA];
+  __shared__ int pflag[2 * PAIRS];  // per wavefront: groups whose partial y is published
+  if (threadIdx.x < 2 * PAIRS) pflag[threadIdx.x] = 0;
+  for (int e = threadIdx.x; e < 2 * JW; e += NTH) {
+    const int pl = e / JW, j = e - pl * JW;
+    vbl[pl][j] = j < M ? vb[2 * j + pl] : T(0);
   }
-#pragma unroll
-  for (int c = 0; c < NVA; ++c) {
-    const int i = lo + 16 * c;
-    var[c] = i < N ? T(va[2 * i]) : T(0);
-    vai[c] = i < N ? T(va[2 * i + 1]) : T(0);
+  for (int e = threadIdx.x; e < 2 * 16 * NVA; e += NTH) {
+    const int pl = e / (16 * NVA), i = e - pl * (16 * NVA);
+    val[pl][i] = i < N ? T(va[2 * i + pl]) : T(0);
   }
   __syncthreads();
   const T *Vp = Vl + h * Kp * VS;
+  bool stalled = false;
   const int64_t sbeg = int64_t(blockIdx.x) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
   const int64_t iters = send > sbeg ? (send - sbeg + 16 * PAIRS - 1) / (16 * PAIRS) : 0;
@@ -618,32 +669,24 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = Acc{0, 0, 0, 0};
   double ysr = 0.0, ysi = 0.0;
+  // software pipeline: the masks and T rows of the pair's next group are loaded while
+  // the current group's O^dagger y contraction runs
+  int64_t g = sbeg + 16 * pr;
+  int rows_here = svc_rows(send, g);
+  uint64_t mA, mB[4];
+  V<T, true> tv[JT][4];
+  if (iters > 0) {
+    if (rows_here == 16)
+      svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+    else
+      svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+  }
   for (int64_t it = 0; it < iters; ++it) {
-    const int64_t g = sbeg + 16 * PAIRS * it + 16 * pr;
-    const int64_t left = send - g;
-    const int rows_here = left <= 0 ? 0 : (left < 16 ? int(left) : 16);
-    const uint64_t mA = lo < rows_here ? masks[g + lo] : 0ull;
-    uint64_t mB[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int rr = MF<T>::row(hi, q);
-      mB[q] = rr < rows_here ? masks[g + rr] : 0ull;
-    }
-    V<T, true> tv[JT][4];
-#pragma unroll
-    for (int a = 0; a < JT; ++a) {
-      const int j = a * 16 + lo;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = MF<T>::row(hi, r);
-        tv[a][r] = (j < M && rr < rows_here) ? vload<T, true>(Tm, (g + rr) * M + j)
-                                             : vmake<T, true>(T(0), T(0));
-      }
-    }
     // ---- X_h = S (plane h of V)^T over the valid hidden tiles ----
     Acc x[JT];
 #pragma unroll
     for (int a = 0; a < JT; ++a) x[a] = Acc{0, 0, 0, 0};
+#pragma unroll 2
     for (int k0 = 0; k0 < Kp; k0 += 4) {
       const int k = k0 + hi;
       const T av = ((mA >> k) & 1ull) ? T(1) : T(-1);
@@ -652,7 +695,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       for (int a = 0; a < JT; ++a) v[a] = Vp[k * VS + a * 16 + lo];
 #pragma unroll
       for (int a = 0; a < JT; ++a)
-        if (a < Mt) x[a] = MF<T>::mma(av, v[a], x[a]);
+        if (a < JV) x[a] = MF<T>::mma(av, v[a], x[a]);
     }
     // ---- this plane's share of y for rows MF::row(hi, r) ----
     T yre[4], yim[4];
@@ -663,10 +706,10 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     }
 #pragma unroll
     for (int a = 0; a < JT; ++a) {
-      if (a >= Mt) continue;
+      if (a >= JV) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const T xv = x[a][r] + vbh[a];
+        const T xv = x[a][r] + vbl[h][a * 16 + lo];
         if (h == 0) {
           yre[r] += tv[a][r].re * xv;
           yim[r] += tv[a][r].im * xv;
@@ -682,8 +725,8 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
 #pragma unroll
         for (int c = 0; c < NVA; ++c) {
           const T sgn = ((mB[r] >> (lo + 16 * c)) & 1ull) ? T(1) : T(-1);
-          yre[r] += sgn * var[c];
-          yim[r] += sgn * vai[c];
+          yre[r] += sgn * val[0][lo + 16 * c];
+          yim[r] += sgn * val[1][lo + 16 * c];
         }
     }
     const int par = int(it & 1);
@@ -701,7 +744,27 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
         ybuf[par][pr][h][rr][1] = yim[r];
       }
     }
-    __syncthreads();
+    // publish this wavefront's partial sums, then wait (bounded) for the partner's: the
+    // two wavefronts of a pair synchronise through LDS flags only, so pairs drift apart
+    // and one wavefront's VALU work overlaps the other's matrix-core work on a SIMD
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0)
+      __hip_atomic_store(&pflag[wid], int(it + 1), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    {
+      int spins = 0;
+#pragma nounroll
+      while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                 &pflag[wid ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+             int(it + 1)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1 << 24)) {
+          stalled = true;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int rr = MF<T>::row(hi, r);
@@ -712,28 +775,42 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
         ysi += double(yim[r]);
       }
     }
-    // ---- plane h of Z^T S over the same 16 samples (step q: row MF::row(hi, q)) ----
+    // ---- plane h of Z = conj(T) y (row M: Z = y), then the next group's loads ----
+    T z[4][JT];
+    uint64_t mq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      T z[JT];
+      mq[q] = mB[q];
 #pragma unroll
       for (int a = 0; a < JT; ++a) {
         const int j = a * 16 + lo;
         const T zq = h == 0 ? tv[a][q].re * yre[q] + tv[a][q].im * yim[q]
                             : tv[a][q].re * yim[q] - tv[a][q].im * yre[q];
-        z[a] = j == M ? (h == 0 ? yre[q] : yim[q]) : zq;
+        z[q][a] = (a == JT - 1 && j == M) ? (h == 0 ? yre[q] : yim[q]) : zq;
       }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the next loads after the last reads of tv
+    if (it + 1 < iters) {
+      g += 16 * PAIRS;
+      rows_here = svc_rows(send, g);
+      if (rows_here == 16)
+        svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+      else
+        svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+    }
+    // ---- plane h of Z^T S over the 16 samples (step q: row MF::row(hi, q)) ----
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
       T bs[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
         const int c = b * 16 + lo;
-        bs[b] = c < N ? (((mB[q] >> c) & 1ull) ? T(1) : T(-1)) : (c == N ? T(1) : T(0));
+        bs[b] = c < N ? (((mq[q] >> c) & 1ull) ? T(1) : T(-1)) : (c == N ? T(1) : T(0));
       }
 #pragma unroll
       for (int a = 0; a < JT; ++a)
-        if (a < Jt)
 #pragma unroll
-          for (int b = 0; b < NT; ++b) acc[a][b] = MF<T>::mma(z[a], bs[b], acc[a][b]);
+        for (int b = 0; b < NT; ++b) acc[a][b] = MF<T>::mma(z[q][a], bs[b], acc[a][b]);
     }
   }
   // block sums: plane 0 of every pair -> real part, plane 1 -> imaginary part
@@ -761,7 +838,9 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
         part[2 * o + 1] = si;
       }
     }
-  dsum[0][tid] = ysr;
+  // a wavefront that gave up waiting for its partner poisons the block's sum of y, so
+  // the solver reports a non-finite result instead of a wrong one
+  dsum[0][tid] = stalled ? __builtin_nan("") : ysr;
   dsum[1][tid] = ysi;
   __syncthreads();
   for (int w = NTH / 2; w > 0; w >>= 1) {
@@ -851,7 +930,7 @@ GradLayout grad_layout(const nqs_model *m, int64_t n) {
   L.vb = take(size_t(m->M) * es);
   L.va = take(size_t(m->N) * 16);
   L.ypart = take(size_t(g.jchunks) * size_t(n) * 16);
-  L.Tm = take(size_t(n) * m->M * es);
+  L.Tm = take(size_t(n) * m->M * es + 128 * es);  // slack: whole-tile reads past the last row
   L.masks = take(g.pair ? size_t(n) * 8 : 0);
   // sized for the largest split count any plan of this device uses, so that a later
   // change of the tuned S v shape never outgrows a workspace sized earlier
@@ -958,6 +1037,60 @@ hipError_t vjp_t(const nqs_model *m, const int8_t *sigma, int64_t n, const doubl
   return hipErrorInvalidValue;
 }
 
+template <int JT, int JV, int NT, int PAIRS>
+hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_part,
+                  const int *skip, hipStream_t st) {
+  GradPlan g = grad_plan(m, n);
+  GradLayout L = grad_layout(m, n);
+  char *base = (char *)scratch;
+  const int Kp = (m->N + 3) / 4 * 4;
+  const int VS = JT * 16 + ((JT & 1) ? 0 : 16);
+  hipLaunchKernelGGL((k_svc<float, JT, JV, NT, PAIRS>), dim3(unsigned(g.splits)),
+                     dim3(128 * PAIRS), size_t(2) * Kp * VS * sizeof(float), st, m->N, m->M, n,
+                     (const uint64_t *)(base + L.masks), (const float *)(base + L.Tm),
+                     (const float *)(base + L.Vt), (const float *)(base + L.vb),
+                     (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
+                     g.Itiles * 16, (float *)(base + L.part), ysum_part, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
+  hipLaunchKernelGGL((k_vjp_reduce1<float, true>), dim3(unsigned(cdiv(elems, 256)), g.groups),
+                     dim3(256), 0, st, g.splits, g.groups, elems,
+                     (const float *)(base + L.part), (double *)(base + L.out1), skip);
+  return hipGetLastError();
+}
+
+template <int JT, int NT>
+hipError_t svc_pick(const nqs_model *m, int64_t n, void *scratch, double *ysum_part,
+                    const int *skip, hipStream_t st) {
+  const GradPlan g = grad_plan(m, n);
+  const bool full = (m->M % 16) == 0;  // row M starts a tile of its own
+  if constexpr (JT > 1) {
+    if (full)
+      return g.pairs == 4 ? svc_go<JT, JT - 1, NT, 4>(m, n, scratch, ysum_part, skip, st)
+                          : svc_go<JT, JT - 1, NT, 2>(m, n, scratch, ysum_part, skip, st);
+  }
+  if (full) return hipErrorInvalidValue;
+  return g.pairs == 4 ? svc_go<JT, JT, NT, 4>(m, n, scratch, ysum_part, skip, st)
+                      : svc_go<JT, JT, NT, 2>(m, n, scratch, ysum_part, skip, st);
+}
+
+// plane-split S v for complex FP32 (grad_plan(...).pair): JT = Jtiles exactly
+hipError_t svc_launch(const nqs_model *m, int64_t n, void *scratch, double *ysum_part,
+                      const int *skip, hipStream_t st) {
+  const GradPlan g = grad_plan(m, n);
+#define NQS_SVC_CASE(A, B) \
+  if (g.Jtiles == A && g.NT == B) return svc_pick<A, B>(m, n, scratch, ysum_part, skip, st);
+  NQS_SVC_CASE(1, 1) NQS_SVC_CASE(1, 2) NQS_SVC_CASE(1, 3) NQS_SVC_CASE(1, 4)
+  NQS_SVC_CASE(2, 1) NQS_SVC_CASE(2, 2) NQS_SVC_CASE(2, 3) NQS_SVC_CASE(2, 4)
+  NQS_SVC_CASE(3, 1) NQS_SVC_CASE(3, 2) NQS_SVC_CASE(3, 3) NQS_SVC_CASE(3, 4)
+  NQS_SVC_CASE(4, 1) NQS_SVC_CASE(4, 2) NQS_SVC_CASE(4, 3) NQS_SVC_CASE(4, 4)
+  NQS_SVC_CASE(5, 1) NQS_SVC_CASE(5, 2) NQS_SVC_CASE(5, 3)
+  NQS_SVC_CASE(6, 1) NQS_SVC_CASE(6, 2) NQS_SVC_CASE(6, 3)
+#undef NQS_SVC_CASE
+  return hipErrorInvalidValue;
+}
+
 template <typename T, bool C, int JT, int NT>
 hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
                    double *ysum_part, const int *skip, hipStream_t st) {
@@ -967,28 +1100,6 @@ hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scr
   const int Kp = (m->N + 3) / 4 * 4;
   const size_t vbytes = (size_t(Kp) * JT * 16 * sizeof(T) * (C ? 2 : 1) + 15) / 16 * 16;
   const size_t tile_bytes = size_t(4) * 16 * NT * 16;
-  bool launched = false;
-  if constexpr (C && std::is_same<T, float>::value) {
-    if (g.pair) {
-      const int VS = JT * 16 + ((JT & 1) ? 0 : 16);
-      if (g.pairs == 4)
-        hipLaunchKernelGGL((k_svc<T, JT, NT, 4>), dim3(unsigned(g.splits)), dim3(512),
-                           size_t(2) * Kp * VS * sizeof(T), st, m->N, m->M, n,
-                           (const uint64_t *)(base + L.masks), (const T *)(base + L.Tm),
-                           (const T *)(base + L.Vt), (const T *)(base + L.vb),
-                           (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
-                           g.Itiles * 16, (T *)(base + L.part), ysum_part, skip);
-      else
-      hipLaunchKernelGGL((k_svc<T, JT, NT, 2>), dim3(unsigned(g.splits)), dim3(256),
-                         size_t(2) * Kp * VS * sizeof(T), st, m->N, m->M, n,
-                         (const uint64_t *)(base + L.masks), (const T *)(base + L.Tm),
-                         (const T *)(base + L.Vt), (const T *)(base + L.vb),
-                         (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
-                         g.Itiles * 16, (T *)(base + L.part), ysum_part, skip);
-      launched = true;
-    }
-  }
-  if (!launched)
   hipLaunchKernelGGL((k_sv<T, C, JT, NT>), dim3(unsigned(g.splits)), dim3(256),
                      vbytes + tile_bytes, st, m->N, m->M, n, sigma, (const T *)(base + L.Tm),
                      (const T *)(base + L.Vt), (const T *)(base + L.vb),
@@ -1007,6 +1118,9 @@ template <typename T, bool C>
 hipError_t sv_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
                 double *ysum_part, const int *skip, hipStream_t st) {
   GradPlan g = grad_plan(m, n);
+  if constexpr (C && std::is_same<T, float>::value) {
+    if (g.pair) return svc_launch(m, n, scratch, ysum_part, skip, st);
+  }
 #define NQS_SV_CASE(A, B) \
   if (g.JT == A && g.NT == B) return sv_tile<T, C, A, B>(m, sigma, n, scratch, ysum_part, skip, st);
   NQS_SV_CASE(1, 1)
@@ -1076,17 +1190,22 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
   // complex FP32 with N <= 63: the plane-split fused product (k_svc) with the smallest
   // hidden-tile count covering rows 0..M, at most 6 x 3 accumulator tiles per wavefront
   g.pair = false;
-  if (m->is_complex && !use_double(m) && m->N <= 63) {
-    static const int pj[4] = {1, 2, 4, 6};
+  if (m->is_complex && !use_double(m) && m->N <= 63 && g.Jtiles <= 6 &&
+      g.Jtiles * g.NT <= 18) {
     const size_t Kp = size_t(m->N + 3) / 4 * 4;
-    for (int q = 0; q < 4; ++q)
-      if (pj[q] >= g.Jtiles && pj[q] * g.NT <= 18 &&
-          2 * Kp * size_t(pj[q] * 16 + ((pj[q] & 1) ? 0 : 16)) * 4 <= 54 * 1024) {
-        g.JT = pj[q];
-        g.pair = true;
-        g.fused = true;
-        break;
-      }
+    const size_t VS = size_t(g.Jtiles) * 16 + ((g.Jtiles & 1) ? 0 : 16);
+    if (2 * Kp * VS * 4 <= 54 * 1024) {
+      g.pair = true;
+      g.fused = true;
+      // the separate k_vjp (O^dagger 1, force) takes the smallest tile count covering
+      // every hidden row in one block
+      static const int pj[4] = {1, 2, 4, 6};
+      for (int q = 0; q < 4; ++q)
+        if (pj[q] >= g.Jtiles) {
+          g.JT = pj[q];
+          break;
+        }
+    }
   }
   g.pairs = g.pair ? (m->sv_pairs == 4 ? 4 : 2) : 0;
   if (g.fused) {
