@@ -121,6 +121,74 @@ def copy_probe(torch, dev, mib=1024, reps=3):
     log("copy probe: %d copies of %d MiB" % (reps, mib))
 
 
+# exact ground energies of the workloads (Pauli units): Bethe ansatz for the 40-site
+# Heisenberg ring, free-fermion closed form for the 10-site TFIM ring
+E_REF = {"heisenberg1d_n40_cplx_fp32_alpha2": -70.98609115333286,
+         "tfim1d_n10_real_fp64_alpha1": -12.784906442999324}
+FORM_NAMES = {0: "fp64", 1: "fp32", 2: "bf16"}
+
+
+def run_form(nqs, synth, torch, w, prec, iters):
+    """SR trajectory of the workload in one precision form from the common start
+    (parameters N(0, 0.01^2) from seed 1234, chains from seed 1234): per iteration one
+    sampling call and one SR step; returns per-iteration energies and wall times."""
+    dev = torch.device("cuda:0")
+    N = w["L"] ** w["ndim"]
+    M = w["alpha"] * N
+    C, S = w["chains"], w["sweeps"]
+    bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
+    model = nqs.Model(N, M, bonds, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
+                      sublattice=sub, move=w["move"], is_complex=w["cplx"], prec=prec)
+    p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
+    params = torch.from_numpy(p).to(dev).to(model.param_dtype)
+    chains = torch.empty((C, N), dtype=torch.int8, device=dev)
+    model.chain_init(chains, seed=1234)
+    samples = torch.empty((S, C, N), dtype=torch.int8, device=dev)
+    eloc = torch.empty(S * C, dtype=model.value_dtype, device=dev)
+    ws = torch.empty(model.sr_workspace_bytes(S * C), dtype=torch.uint8, device=dev)
+    model.autotune(params, chains.repeat(S, 1), workspace=ws)
+    energies, walls = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    counter = 0
+    for k in range(iters):
+        discard = max(10, S // 10) if k == 0 else 0
+        model.sample(params, chains, S, discard, seed=1234, counter=counter, samples=samples,
+                     eloc=eloc)
+        counter += S + discard
+        info = model.sr_step(params, samples.view(S * C, N), eloc, w["lr"], w["shift"],
+                             w["cg_tol"], w["cg_maxiter"], workspace=ws)
+        torch.cuda.synchronize()
+        energies.append(info["energy_re"])
+        walls.append(time.perf_counter() - t0)
+    return energies, walls, S * C
+
+
+def compare_forms(nqs, synth, torch, w, workload, iters):
+    """The same SR trajectory in the FP64, FP32 and BF16 forms: rates, and the time each
+    form needs to reach the energy error that all of them reach (dE = relative error of
+    the 5-iteration running mean of the energy against the exact ground energy)."""
+    out, curves = {}, {}
+    e_ref = E_REF[workload]
+    for prec in (0, 1, 2):
+        name = FORM_NAMES[prec]
+        log("forms: %s, %d SR iterations" % (name, iters))
+        energies, walls, n = run_form(nqs, synth, torch, w, prec, iters)
+        sm = [np.mean(energies[max(0, k - 4):k + 1]) for k in range(len(energies))]
+        de = [abs(e - e_ref) / abs(e_ref) for e in sm]
+        steady = (walls[-1] - walls[0]) / max(1, len(walls) - 1)   # excludes the burn-in call
+        curves[name] = (de, walls)
+        out[name] = {"ms_per_iter": 1e3 * steady, "samples_per_s": n / steady,
+                     "sr_iters_per_s": 1.0 / steady, "dE_final": de[-1],
+                     "energy_final": float(sm[-1])}
+    target = max(v["dE_final"] for v in out.values())
+    for name, (de, walls) in curves.items():
+        k = next(i for i, d in enumerate(de) if d <= target)
+        out[name]["iters_to_dE"] = k + 1
+        out[name]["time_to_dE_s"] = walls[k]
+    return {"dE_target": target, "e_ref": e_ref, "iters": iters, "forms": out}
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -135,6 +203,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sv-pairs", type=int, default=0, choices=[0, 2, 4],
                     help="fixed S v kernel shape instead of the autotuner's choice")
+    ap.add_argument("--forms-iters", type=int, default=40,
+                    help="SR iterations per precision form in the FP64/FP32/BF16 comparison "
+                         "(0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -253,7 +324,7 @@ def main():
                 "traffic": recorded_traffic("k_sweep", args.workload)}
 
     out = {
-        "metric": "samples/s (sweep+E_loc+O_k) and SR iters/s",
+        "metric": "samples/s (sweep+E_loc+O_k) and SR iters/s, BF16/FP32 vs FP64 at fixed dE",
         "value": n_samp / (ms_per_step * 1e-3),
         "unit": "samples/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -273,7 +344,10 @@ def main():
         "sv_tuning": tune,
         "roofline": roof,
     }
-    log("timed %d steps: %.2f ms/step; oracle baseline next" % (args.steps, ms_per_step))
+    log("timed %d steps: %.2f ms/step" % (args.steps, ms_per_step))
+    if args.forms_iters > 0:
+        out["precision_forms"] = compare_forms(nqs, synth, torch, w, args.workload,
+                                               args.forms_iters)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, N, M, args.cpu_seconds)
     print(json.dumps(out))

@@ -45,6 +45,16 @@ typedef enum {
   NQS_EUNSUPPORTED = -5 /* valid but not supported combination */
 } nqs_status;
 
+/* Precision forms (Sec. 2.2.2 RBM, Sec. 2.2.5 SR; the paper fixes none):
+ *  NQS_F64  - every kernel in double.
+ *  NQS_F32  - ratio products, local energies, theta/tanh and the Jacobian contractions
+ *             in float (matrix cores with float accumulation); hidden angles cached in
+ *             double in the sampler; log psi, statistics and the CG solve in double.
+ *  NQS_BF16 - the quantised model: every weight W_ji is rounded to the nearest bfloat16
+ *             (a, b are not), and the Jacobian contractions of nqs_log_psi_grad and the
+ *             SR entry points read tanh(theta) rounded to bfloat16; arithmetic as
+ *             NQS_F32. Sampling is exact for the quantised model, so its energies stay
+ *             variational. */
 typedef enum { NQS_F64 = 0, NQS_F32 = 1, NQS_BF16 = 2 } nqs_prec;
 typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_hamiltonian;
 typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;

@@ -18,6 +18,7 @@ cites, in float64 / complex128 numpy. Modules:
 * ``sampler``      - Metropolis chains on |psi|^2 (Eq. 4, Sec. 2.2.5).
 * ``sr``           - statistics, force, stochastic reconfiguration and CG (Sec. 2.2.5,
                      Eq. 2).
+* ``quant``        - bfloat16 rounding of the BF16 precision form.
 * ``exact``        - exact diagonalisation, full enumeration, TFIM closed form and the
                      Bethe ansatz for the Heisenberg ring (ground truth for the pins).
 

@@ -79,24 +79,27 @@ def log_psi_hidden_sum(params, sigma, n_sites, n_hidden):
     return np.log(np.exp(expo).sum(axis=1)) - n_hidden * np.log(2.0)
 
 
-def log_derivatives(params, sigma, n_sites, n_hidden):
-    """O[s, k] = d log psi(sigma_s) / d p_k, packed like p: [n, P]."""
+def log_derivatives(params, sigma, n_sites, n_hidden, round_tanh=None):
+    """O[s, k] = d log psi(sigma_s) / d p_k, packed like p: [n, P]. round_tanh (optional)
+    is applied to tanh(theta) first (the BF16 form's contractions read rounded rows)."""
     s = np.asarray(sigma, dtype=np.float64)
     th = theta(params, s, n_sites, n_hidden)
     t = np.tanh(th)
+    if round_tanh is not None:
+        t = round_tanh(t)
     n = s.shape[0]
     oW = t[:, :, None] * s[:, None, :]                    # [n, M, N], row j col i
     return np.concatenate([s.astype(t.dtype), t, oW.reshape(n, -1)], axis=1)
 
 
-def jvp(params, sigma, v, n_sites, n_hidden):
+def jvp(params, sigma, v, n_sites, n_hidden, round_tanh=None):
     """(O v)_s = sum_k O_sk v_k  (no centering)."""
-    return log_derivatives(params, sigma, n_sites, n_hidden) @ np.asarray(v)
+    return log_derivatives(params, sigma, n_sites, n_hidden, round_tanh) @ np.asarray(v)
 
 
-def vjp(params, sigma, u, n_sites, n_hidden):
+def vjp(params, sigma, u, n_sites, n_hidden, round_tanh=None):
     """(O^dagger u)_k = sum_s conj(O_sk) u_s  (no centering, no 1/n)."""
-    O = log_derivatives(params, sigma, n_sites, n_hidden)
+    O = log_derivatives(params, sigma, n_sites, n_hidden, round_tanh)
     return O.conj().T @ np.asarray(u)
 
 

@@ -85,10 +85,11 @@ def cg(matvec, b, tol, maxiter):
     return x, it, np.sqrt(rr) / bnorm
 
 
-def sr_step(model, params, samples, eloc, lr, diag_shift, cg_tol, cg_maxiter, weights=None):
+def sr_step(model, params, samples, eloc, lr, diag_shift, cg_tol, cg_maxiter, weights=None,
+            round_tanh=None):
     """One SR update from samples [n, N] and their local energies [n].
-    Returns (new_params, info dict)."""
-    O = rbm.log_derivatives(params, samples, model.n_sites, model.n_hidden)
+    Returns (new_params, info dict). round_tanh: see rbm.log_derivatives."""
+    O = rbm.log_derivatives(params, samples, model.n_sites, model.n_hidden, round_tanh)
     e = np.asarray(eloc)
     if not np.iscomplexobj(params):
         O = O.real

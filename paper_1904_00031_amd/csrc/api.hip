@@ -123,7 +123,6 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
   }
   if (d->move == NQS_MOVE_EXCHANGE && (d->n_bonds[0] < 1 || d->n_sites % 2)) return NQS_EINVAL;
   if (d->marshall && !d->sublattice) return NQS_EINVAL;
-  if (d->prec == NQS_BF16) return NQS_EUNSUPPORTED;
 
   nqs_model *m = new (std::nothrow) nqs_model();
   if (!m) return NQS_ENOMEM;
@@ -265,7 +264,7 @@ nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int
     e = launch_sweep(m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter, chain_offset,
                      samples, n_accepted, fuse ? eloc : nullptr, st);
   if (e == hipSuccess && eloc && !fuse) {
-    e = launch_theta_tanh(m, samples, n, m->d_scratch, st);
+    e = launch_theta_tanh(m, samples, n, m->d_scratch, false, st);
     if (e == hipSuccess)
       e = launch_local_energy(m, samples, grad_buffers(m, n, m->d_scratch).Tm, n, eloc, st);
   }
@@ -290,7 +289,7 @@ nqs_status nqs_local_energy(nqs_model *m, const void *params, const int8_t *sigm
   nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
   if (s != NQS_OK) return s;
   hipError_t e = launch_tables(m, params, st);
-  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, st);
+  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, false, st);
   if (e == hipSuccess)
     e = launch_local_energy(m, sigma, grad_buffers(m, n, m->d_scratch).Tm, n, eloc, st);
   return dev(e);
@@ -312,7 +311,7 @@ nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigm
   nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
   if (s != NQS_OK) return s;
   hipError_t e = launch_tables(m, params, st);
-  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, st);
+  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, true, st);
   if (e == hipSuccess && want_vjp) {
     e = launch_vjp_partials(m, sigma, n, (const double *)u, m->d_scratch, nullptr, st);
     if (e == hipSuccess) e = launch_vjp_reduce(m, n, m->d_scratch, (double *)vjp, nullptr, st);

@@ -91,6 +91,13 @@ __device__ __forceinline__ void fsincos(double x, double *s, double *c) { sincos
 __device__ __forceinline__ float fatan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double fatan2(double y, double x) { return atan2(y, x); }
 
+// round to the nearest bfloat16 (ties to even), kept in a float; finite inputs only
+__device__ __forceinline__ float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
 // reciprocal: the hardware v_rcp_f32 (1 ulp) in single precision, correctly rounded
 // division in double
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }

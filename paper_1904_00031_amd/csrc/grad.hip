@@ -74,7 +74,8 @@ template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
                                                      const int8_t *__restrict__ sigma,
                                                      const T *__restrict__ Wt,
-                                                     const T *__restrict__ bv, int JT, T *Tout) {
+                                                     const T *__restrict__ bv, int JT, int quant,
+                                                     T *Tout) {
   typedef typename MF<T>::acc Acc;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
@@ -105,7 +106,12 @@ __global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
         const int64_t row = s0 + MF<T>::row(hi, r);
         if (row < n) {
           V<T, C> th = vmake<T, C>(tr[r] + bb.re, C ? ti[r] + bb.im : T(0));
-          vstore<T, C>(Tout, row * M + j, vtanh<T, C>(th));
+          V<T, C> tv = vtanh<T, C>(th);
+          if (quant) {  // BF16 form: the Jacobian contractions see bfloat16 tanh(theta)
+            tv.re = T(bf16_round(float(tv.re)));
+            if (C) tv.im = T(bf16_round(float(tv.im)));
+          }
+          vstore<T, C>(Tout, row * M + j, tv);
         }
       }
     }
@@ -957,14 +963,15 @@ hipError_t prep_t(const nqs_model *m, const void *v, void *scratch, hipStream_t 
 
 template <typename T, bool C>
 hipError_t tanh_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
-                  hipStream_t st) {
+                  bool for_grad, hipStream_t st) {
   if (n == 0) return hipSuccess;
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
   hipLaunchKernelGGL((k_theta_tanh<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256),
                      0, st, m->N, m->M, n, sigma, (const T *)m->tab_ptrs[0],
-                     (const T *)m->tab_ptrs[1], 16, (T *)(base + L.Tm));
+                     (const T *)m->tab_ptrs[1], 16, int(for_grad && m->prec == NQS_BF16),
+                     (T *)(base + L.Tm));
   if (g.pair) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1236,8 +1243,8 @@ hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, hip
 }
 
 hipError_t launch_theta_tanh(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
-                             hipStream_t st) {
-  return NQS_DISPATCH(tanh_t, m, sigma, n, scratch, st);
+                             bool for_grad, hipStream_t st) {
+  return NQS_DISPATCH(tanh_t, m, sigma, n, scratch, for_grad, st);
 }
 
 hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,

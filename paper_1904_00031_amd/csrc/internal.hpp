@@ -65,9 +65,11 @@ size_t grad_scratch_bytes(const nqs_model *m, int64_t n);
 
 // v (double, params layout) -> direction tables in compute precision, in scratch
 hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, hipStream_t st);
-// T = tanh(theta) of every sample into scratch (needed by launch_jvp / launch_vjp_partials)
+// T = tanh(theta) of every sample into scratch (needed by launch_jvp / launch_vjp_partials
+// and the local energies from rows); for_grad: rows for the Jacobian contractions, which
+// the BF16 form rounds to bfloat16
 hipError_t launch_theta_tanh(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
-                             hipStream_t st);
+                             bool for_grad, hipStream_t st);
 // y[s] = (O v)[s] with the direction prepared by launch_prep_dir; ysum (may be NULL)
 // receives per-block partial sums of y (complex double) for the centering
 hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,

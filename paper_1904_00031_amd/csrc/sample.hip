@@ -12,12 +12,6 @@
 
 namespace {
 
-__device__ __forceinline__ float bf16_round(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return __uint_as_float(u & 0xffff0000u);
-}
-
 // ---------------------------------------------------------------------------------
 // Tables: one thread per element of the three index ranges
 //   [0, N*M)            W transposed + flip tables

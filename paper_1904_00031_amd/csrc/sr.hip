@@ -393,7 +393,7 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
                      (const double *)eloc, D(L.e_part), nb, D(L.u), D(L.e_part2), state);
   HIPTRY(hipGetLastError());
   // tanh(theta) of every sample, kept for all products of this step
-  HIPTRY(launch_theta_tanh(m, sigma, n, grad, st));
+  HIPTRY(launch_theta_tanh(m, sigma, n, grad, true, st));
   // O^dagger 1 (centring of S v), then g = O^dagger u (force numerator)
   hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, D(L.y));
   HIPTRY(hipGetLastError());
@@ -507,7 +507,7 @@ nqs_status prepare_impl(nqs_model *m, const void *params, const int8_t *sigma, i
   char *b = (char *)ws;
   void *grad = b + L.grad;
   HIPTRY(launch_tables(m, params, st));
-  HIPTRY(launch_theta_tanh(m, sigma, n, grad, st));
+  HIPTRY(launch_theta_tanh(m, sigma, n, grad, true, st));
   hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, (double *)(b + L.y));
   HIPTRY(hipGetLastError());
   HIPTRY(launch_vjp_partials(m, sigma, n, (double *)(b + L.y), grad, nullptr, st));

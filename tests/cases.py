@@ -7,7 +7,7 @@ from oracle import hamiltonian as oh
 from oracle import lattice as ol
 
 # name: (L, ndim, diagonals, ham, J, h, marshall, move, complex, prec, M)
-# prec: 0 = FP64, 1 = FP32
+# prec: 0 = FP64, 1 = FP32, 2 = BF16
 CASES = {
     # 1D TFIM, N = 10, real FP64 RBM, alpha = 1
     "tfim10_real_f64": (10, 1, False, 0, (1.0, 0.0), 1.0, False, 0, False, 0, 10),
@@ -38,7 +38,17 @@ BIG = {
 }
 CASES.update(BIG)
 
-TOL = {0: 1e-10, 1: 1e-5}
+# BF16 form (prec 2): weights rounded to bfloat16, tanh(theta) rounded for the Jacobian
+# contractions, FP32 arithmetic; compared with the oracle running the same quantised
+# model (oracle.quant), so the FP32 tolerance applies
+BF16 = {
+    "heis40_cplx_bf16": (40, 1, False, 1, (1.0, 0.0), 0.0, True, 1, True, 2, 80),
+    "j1j2_4x4_cplx_bf16": (4, 2, True, 1, (1.0, 0.5), 0.0, True, 1, True, 2, 64),
+    "tfim37_real_bf16": (37, 1, False, 0, (1.0, 0.0), 0.8, False, 0, False, 2, 74),
+}
+CASES.update(BF16)
+
+TOL = {0: 1e-10, 1: 1e-5, 2: 1e-5}
 
 
 def build(nqs, name):
@@ -59,7 +69,7 @@ def theta_scale(name):
     to FP32 alone moves log psi, E_loc and tanh(theta) by more than 1e-5 relative, so the
     FP32 tolerance is stated for theta away from them. FP64 and real cases run at ~1.5."""
     L, ndim, diag, ham, J, h, marshall, move, cplx, prec, M = CASES[name]
-    return 0.3 if (cplx and prec == 1) else 1.5
+    return 0.3 if (cplx and prec >= 1) else 1.5
 
 
 def params(name, sigma=None, seed=1234, theta=None):
@@ -70,9 +80,24 @@ def params(name, sigma=None, seed=1234, theta=None):
     if sigma is None:
         sigma = (theta if theta is not None else theta_scale(name)) / np.sqrt(N + 1.0)
     p = synth.rbm_params(N, M, cplx, sigma=sigma, seed=seed)
-    if prec == 1:
+    if prec >= 1:
         p = p.astype(np.complex64 if cplx else np.float32)
     return p
+
+
+def oracle_params(name, p):
+    """The parameters the oracle evaluates for this case: double precision, with W
+    rounded to bfloat16 for the BF16 form."""
+    from oracle import quant
+    L, ndim, diag, ham, J, h, marshall, move, cplx, prec, M = CASES[name]
+    pe = np.asarray(p).astype(np.complex128 if cplx else np.float64)
+    return quant.quantize_weights(pe, L ** ndim, M) if prec == 2 else pe
+
+
+def round_tanh(name):
+    """Rounding the case's Jacobian contractions apply to tanh(theta) (BF16 form)."""
+    from oracle import quant
+    return quant.bf16 if CASES[name][9] == 2 else None
 
 
 def configs(name, n, seed):
