@@ -103,7 +103,7 @@ def vjp(params, sigma, u, n_sites, n_hidden, round_tanh=None):
     return O.conj().T @ np.asarray(u)
 
 
-def vjp_entries(params, sigma, u, ks, n_sites, n_hidden):
+def vjp_entries(params, sigma, u, ks, n_sites, n_hidden, round_tanh=None):
     """Selected entries k of O^dagger u, each from its own column of O (for checks at
     sizes where the full [n, P] matrix does not fit): O[:, a_i] = sigma_i,
     O[:, b_j] = tanh(theta_j), O[:, W_ji] = tanh(theta_j) sigma_i."""
@@ -118,8 +118,13 @@ def vjp_entries(params, sigma, u, ks, n_sites, n_hidden):
         elif k < n_sites + n_hidden:
             j = k - n_sites
             col = np.tanh(b[j] + s @ W[j])
+            if round_tanh is not None:
+                col = round_tanh(col)
         else:
             j, i = divmod(k - n_sites - n_hidden, n_sites)
-            col = np.tanh(b[j] + s @ W[j]) * s[:, i]
+            t = np.tanh(b[j] + s @ W[j])
+            if round_tanh is not None:
+                t = round_tanh(t)
+            col = t * s[:, i]
         out.append(np.sum(np.conj(col) * u))
     return np.array(out)

@@ -35,7 +35,16 @@ CASES = {
 BIG = {
     # more than 256 sites: spins read from LDS instead of lane registers
     "tfim300_real_f32": (300, 1, False, 0, (1.0, 0.0), 1.0, False, 0, False, 1, 300),
+    # the 10x10 J1-J2 lattice with alpha = 4 and the 16x16 Heisenberg lattice with
+    # alpha = 8 of the large workloads
+    "j1j2_10x10_cplx_f32": (10, 2, True, 1, (1.0, 0.5), 0.0, True, 1, True, 1, 400),
+    "heis16x16_cplx_f32": (16, 2, False, 1, (1.0, 0.0), 0.0, True, 1, True, 1, 2048),
 }
+BIG_BF16 = {
+    "j1j2_10x10_cplx_bf16": (10, 2, True, 1, (1.0, 0.5), 0.0, True, 1, True, 2, 400),
+    "heis16x16_cplx_bf16": (16, 2, False, 1, (1.0, 0.0), 0.0, True, 1, True, 2, 2048),
+}
+BIG.update(BIG_BF16)
 CASES.update(BIG)
 
 # BF16 form (prec 2): weights rounded to bfloat16, tanh(theta) rounded for the Jacobian
