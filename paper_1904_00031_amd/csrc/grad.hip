@@ -1173,7 +1173,9 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
   g.Jtiles = (m->M + 1 + 15) / 16;   // hidden rows 0..M (row M carries the visible bias)
   g.Itiles = (m->N + 1 + 15) / 16;   // site columns 0..N (column N carries the hidden bias)
   g.NT = g.Itiles < 4 ? g.Itiles : 4;
-  const int jt_budget = 24 / g.NT;   // accumulator tiles per wavefront <= 24
+  // accumulator tiles per wavefront: <= 24, <= 16 with 4 site tiles (the instantiated
+  // (JT, NT) pairs of k_vjp / k_sv)
+  const int jt_budget = (g.NT == 4 ? 16 : 24) / g.NT;
   static const int jts[5] = {8, 6, 4, 2, 1};
   g.JT = 1;
   for (int q = 0; q < 5; ++q)
