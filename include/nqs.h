@@ -227,6 +227,34 @@ nqs_status nqs_autotune(nqs_model *model, const void *params, const int8_t *sigm
  * ignore it. */
 nqs_status nqs_set_sv_shape(nqs_model *model, int32_t pairs);
 
+/* ---- Batches of independent models (uneven sizes) --------------------------------
+ * A batch holds K models created from K descriptions (all with the same is_complex and
+ * prec; sizes, Hamiltonians, couplings and moves may differ). Buffers of the models are
+ * concatenated in model order, each in the layout of the single-model call:
+ *   params      model k at element offset sum_{i<k} P_i (P_i = nqs_batch_n_params(i))
+ *   chain_sigma model k at byte offset sum_{i<k} C_i N_i          ([C_k, N_k])
+ *   samples     model k at byte offset n_sweeps sum_{i<k} C_i N_i  ([n_sweeps, C_k, N_k])
+ *   eloc        model k at element offset n_sweeps sum_{i<k} C_i  ([n_sweeps * C_k])
+ *   n_accepted  model k at offset sum_{i<k} C_i
+ * n_chains is a host array [K]. Model k draws its random numbers with seed ^ k: its
+ * chains and samples equal those of nqs_chain_init / nqs_sample on its own model with
+ * that seed and chain_offset 0. Sampling (Sec. 2.2.5) runs every chain of every model in
+ * one persistent launch, after one launch that refreshes every model's tables; local
+ * energies (Eq. 5) are evaluated inside the sweep when eloc is not NULL. The block-to-
+ * model tables are uploaded (synchronously) only when buffers or sizes change, so a
+ * repeated call with the same arguments issues no host-to-device copy and can be
+ * captured into a hipGraph after one uncaptured call. */
+typedef struct nqs_batch nqs_batch;
+nqs_status nqs_batch_create(const nqs_model_desc *descs, int32_t n_models, nqs_batch **out);
+void nqs_batch_destroy(nqs_batch *batch);
+int64_t nqs_batch_n_params(const nqs_batch *batch, int32_t k);
+nqs_status nqs_batch_chain_init(nqs_batch *batch, int8_t *chain_sigma, const int32_t *n_chains,
+                                uint64_t seed, void *stream);
+nqs_status nqs_batch_sample(nqs_batch *batch, const void *params, int8_t *chain_sigma,
+                            const int32_t *n_chains, int32_t n_sweeps, int32_t n_discard,
+                            uint64_t seed, uint64_t counter, int8_t *samples,
+                            int64_t *n_accepted, void *eloc, void *stream);
+
 const char *nqs_status_string(nqs_status s);
 
 #ifdef __cplusplus

@@ -90,6 +90,12 @@ def load(path=LIB_PATH):
         "nqs_sr_prepare": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, vp]),
         "nqs_sr_matvec": (i32, [vp, vp, i64, vp, ctypes.c_size_t, vp, f64, vp, vp]),
         "nqs_set_sv_shape": (i32, [vp, i32]),
+        "nqs_batch_create": (i32, [ctypes.POINTER(_Desc), i32, ctypes.POINTER(vp)]),
+        "nqs_batch_destroy": (None, [vp]),
+        "nqs_batch_n_params": (i64, [vp, i32]),
+        "nqs_batch_chain_init": (i32, [vp, vp, ctypes.POINTER(i32), u64, vp]),
+        "nqs_batch_sample": (i32, [vp, vp, vp, ctypes.POINTER(i32), i32, i32, u64, u64, vp, vp,
+                                   vp, vp]),
         "nqs_autotune": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, ctypes.POINTER(TuneReport), vp]),
     }
     for name, (res, args) in sig.items():
@@ -104,7 +110,9 @@ def exported_symbols():
     return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
             "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
             "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_prepare",
-            "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape"]
+            "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_batch_create",
+            "nqs_batch_destroy", "nqs_batch_n_params", "nqs_batch_chain_init",
+            "nqs_batch_sample"]
 
 
 def _check(status, where, allow=(OK,)):
@@ -150,6 +158,21 @@ def nqs_hypercube(L, ndim, with_diagonals=False):
     return [b0[:nb[0]].copy(), b1[:nb[1]].copy()], sub
 
 
+def _fill_desc(d, n_sites, n_hidden, bonds, ham, J, h, marshall, sub, move, is_complex, prec):
+    """Fill an nqs_model_desc; bonds (two int32 [B, 2] arrays) and sub must stay alive."""
+    d.n_sites, d.n_hidden = int(n_sites), int(n_hidden)
+    d.is_complex, d.prec = int(bool(is_complex)), int(prec)
+    for c in range(2):
+        d.n_bonds[c] = bonds[c].shape[0]
+        d.bonds[c] = bonds[c].ctypes.data if bonds[c].shape[0] else None
+    d.ham = int(ham)
+    d.J[0], d.J[1] = float(J[0]), float(J[1])
+    d.h = float(h)
+    d.marshall = int(bool(marshall))
+    d.sublattice = sub.ctypes.data if sub is not None else None
+    d.move = int(move)
+
+
 class Model:
     """Handle of one lattice model + RBM shape + compute precision (nqs_model_create)."""
 
@@ -164,17 +187,8 @@ class Model:
             self._bonds.append(np.zeros((0, 2), dtype=np.int32))
         self._sub = None if sublattice is None else np.ascontiguousarray(np.asarray(sublattice, dtype=np.int8))
         d = _Desc()
-        d.n_sites, d.n_hidden = self.n_sites, self.n_hidden
-        d.is_complex, d.prec = int(self.is_complex), self.prec
-        for c in range(2):
-            d.n_bonds[c] = self._bonds[c].shape[0]
-            d.bonds[c] = self._bonds[c].ctypes.data if self._bonds[c].shape[0] else None
-        d.ham = self.ham
-        d.J[0], d.J[1] = float(J[0]), float(J[1])
-        d.h = float(h)
-        d.marshall = int(bool(marshall))
-        d.sublattice = self._sub.ctypes.data if self._sub is not None else None
-        d.move = self.move
+        _fill_desc(d, self.n_sites, self.n_hidden, self._bonds, self.ham, J, h, marshall,
+                   self._sub, self.move, self.is_complex, self.prec)
         h_ = ctypes.c_void_p()
         _check(_lib.nqs_model_create(ctypes.byref(d), ctypes.byref(h_)), "nqs_model_create")
         self._h = h_
@@ -350,6 +364,81 @@ class Model:
 
     def set_sv_shape(self, pairs):
         _check(_lib.nqs_set_sv_shape(self._h, int(pairs)), "nqs_set_sv_shape")
+
+
+class Batch:
+    """K independent models sampled together (nqs_batch_*). specs: list of dicts with the
+    keyword arguments of Model (n_sites, n_hidden, bonds, ham, J, h, marshall, sublattice,
+    move, is_complex, prec); all with the same is_complex and prec. Buffers are flat
+    tensors holding the models' buffers back to back (see include/nqs.h)."""
+
+    def __init__(self, specs):
+        load()
+        self.K = len(specs)
+        arr = (_Desc * self.K)()
+        self._keep = []
+        self.n_sites, self.n_hidden = [], []
+        for k, sp in enumerate(specs):
+            sp = dict(sp)
+            bonds = [np.ascontiguousarray(np.asarray(b, dtype=np.int32).reshape(-1, 2))
+                     for b in sp["bonds"]]
+            while len(bonds) < 2:
+                bonds.append(np.zeros((0, 2), dtype=np.int32))
+            sub = sp.get("sublattice")
+            sub = None if sub is None else np.ascontiguousarray(np.asarray(sub, dtype=np.int8))
+            self._keep.append((bonds, sub))
+            _fill_desc(arr[k], sp["n_sites"], sp["n_hidden"], bonds, sp.get("ham", TFIM),
+                       sp.get("J", (1.0, 0.0)), sp.get("h", 1.0), sp.get("marshall", False), sub,
+                       sp.get("move", MOVE_FLIP), sp.get("is_complex", False), sp.get("prec", F64))
+            self.n_sites.append(int(sp["n_sites"]))
+            self.n_hidden.append(int(sp["n_hidden"]))
+        self.is_complex = bool(specs[0].get("is_complex", False))
+        self.prec = int(specs[0].get("prec", F64))
+        h_ = ctypes.c_void_p()
+        _check(_lib.nqs_batch_create(arr, self.K, ctypes.byref(h_)), "nqs_batch_create")
+        self._h = h_
+        self.n_params = [int(_lib.nqs_batch_n_params(self._h, k)) for k in range(self.K)]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.nqs_batch_destroy(self._h)
+            self._h = None
+
+    param_dtype = Model.param_dtype
+    value_dtype = Model.value_dtype
+
+    def offsets(self, sizes):
+        return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+    def chain_init(self, chains, n_chains, seed):
+        nc = (ctypes.c_int32 * self.K)(*[int(c) for c in n_chains])
+        _need(chains, "chain_sigma", __import__("torch").int8,
+              (sum(int(c) * n for c, n in zip(n_chains, self.n_sites)),))
+        _check(_lib.nqs_batch_chain_init(self._h, _ptr(chains), nc, seed, _stream()),
+               "nqs_batch_chain_init")
+        return chains
+
+    def sample(self, params, chains, n_chains, n_sweeps, n_discard, seed, counter,
+               samples=None, n_accepted=None, eloc=None, with_eloc=True):
+        import torch
+        nc = (ctypes.c_int32 * self.K)(*[int(c) for c in n_chains])
+        _need(params, "params", self.param_dtype, (sum(self.n_params),))
+        spins = sum(int(c) * n for c, n in zip(n_chains, self.n_sites))
+        _need(chains, "chain_sigma", torch.int8, (spins,))
+        if samples is None:
+            samples = torch.empty(n_sweeps * spins, dtype=torch.int8, device=chains.device)
+        _need(samples, "samples", torch.int8, (n_sweeps * spins,))
+        if n_accepted is not None:
+            _need(n_accepted, "n_accepted", torch.int64, (sum(int(c) for c in n_chains),))
+        if with_eloc and eloc is None:
+            eloc = torch.empty(n_sweeps * sum(int(c) for c in n_chains), dtype=self.value_dtype,
+                               device=chains.device)
+        if eloc is not None:
+            _need(eloc, "eloc", self.value_dtype, (n_sweeps * sum(int(c) for c in n_chains),))
+        _check(_lib.nqs_batch_sample(self._h, _ptr(params), _ptr(chains), nc, n_sweeps, n_discard,
+                                     seed, counter, _ptr(samples), _ptr(n_accepted), _ptr(eloc),
+                                     _stream()), "nqs_batch_sample")
+        return samples, eloc
 
 
 # C-ABI-named module functions --------------------------------------------------------

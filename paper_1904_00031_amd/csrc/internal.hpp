@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.hpp"
 
 struct nqs_model {
@@ -26,6 +28,41 @@ struct nqs_model {
   void *d_scratch = nullptr;
   size_t scratch_bytes = 0;
 };
+
+// Device copy of a host-built job table. upload() copies only when the bytes differ from
+// the previous upload, so a repeated call with the same buffers and sizes issues no
+// host-to-device copy (and can then be captured into a graph).
+struct JobBuffer {
+  void *d = nullptr;
+  size_t cap = 0;
+  std::vector<char> last;
+  hipError_t upload(const void *host, size_t bytes, hipStream_t st);
+  void release();
+};
+
+// one model of a batch, with its buffers for one sampling call (device pointers)
+struct BatchSampleItem {
+  const nqs_model *m;
+  const void *params;
+  int8_t *chains;
+  int n_chains;
+  int8_t *samples;
+  int64_t *n_acc;
+  void *eloc;
+  uint64_t seed;
+};
+
+struct nqs_batch {
+  int K = 0;
+  int is_complex = 0, prec = 0;
+  std::vector<nqs_model *> models;
+  JobBuffer tab_jobs, tab_map, sweep_jobs, sweep_map;   // sampling
+  std::vector<JobBuffer> sr_bufs;                       // SR step job tables
+};
+
+// tables of every model, then every chain of every model in one persistent launch
+hipError_t launch_sample_batch(nqs_batch *b, const std::vector<BatchSampleItem> &items,
+                               int n_sweeps, int n_discard, uint64_t counter, hipStream_t st);
 
 // compute precision of the VALU kernels: double for NQS_F64, float otherwise
 inline bool use_double(const nqs_model *m) { return m->prec == NQS_F64; }

@@ -8,6 +8,8 @@
 // s_k = -s has delta_j = -2 s (W_ji - W_jk). cosh/sinh of 2 W_ji and of 2 (W_ji - W_jk)
 // do not depend on the configuration, so they are tabulated once per call and each ratio
 // term costs one complex multiply-add, with no transcendental function.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace {
@@ -19,14 +21,15 @@ namespace {
 //   then M + N + Btot   bias, a, a-factors
 // ---------------------------------------------------------------------------------
 template <typename T, bool C, typename PT>
-__global__ void k_tables(DevModel dm, Tables<T> tb, const PT *__restrict__ p, int quant,
-                         int need_flip, int need_bond) {
+__device__ __forceinline__ void tables_body(const DevModel &dm, const Tables<T> &tb,
+                                            const PT *__restrict__ p, int quant, int need_flip,
+                                            int need_bond, int bx, int gx) {
   const int N = dm.N, M = dm.M, B = dm.Btot;
   const int64_t nW = int64_t(N) * M, nB = int64_t(B) * M;
   const int64_t total = nW + nB + M + N + B;
   const int64_t offW = N + M;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t e = bx * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gx) * blockDim.x) {
     if (e < nW) {
       int i = int(e / M), j = int(e % M);
       V<double, C> w = vload<double, C>(p, offW + int64_t(j) * N + i);
@@ -99,6 +102,12 @@ __global__ void k_tables(DevModel dm, Tables<T> tb, const PT *__restrict__ p, in
       }
     }
   }
+}
+
+template <typename T, bool C, typename PT>
+__global__ void k_tables(DevModel dm, Tables<T> tb, const PT *__restrict__ p, int quant,
+                         int need_flip, int need_bond) {
+  tables_body<T, C, PT>(dm, tb, p, quant, need_flip, need_bond, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------------
@@ -335,11 +344,12 @@ struct SweepArgs {
 };
 
 template <typename T, bool C, int R, bool TL>
-__global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepArgs a) {
+__device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> &tb,
+                                            const SweepArgs &a, int chain_base) {
   extern __shared__ __align__(16) unsigned char lds_u8[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int chain = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wid);
+  const int chain = __builtin_amdgcn_readfirstlane(chain_base + wid);
   const int N = dm.N, M = dm.M;
   constexpr int cs = C ? 2 : 1;
   const bool flip = dm.move == NQS_MOVE_FLIP;
@@ -599,6 +609,47 @@ __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepA
   if (lane == 0 && a.n_acc) a.n_acc[chain] = acc_count;
 }
 
+template <typename T, bool C, int R, bool TL>
+__global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepArgs a) {
+  sweep_block<T, C, R, TL>(dm, tb, a, blockIdx.x * (blockDim.x >> 6));
+}
+
+// ---------------------------------------------------------------------------------
+// Batches of independent models in one launch: each block reads its job (one model's
+// tables and arguments) and its first chain (or element block) from a block map built
+// on the host, then runs the single-model body. Tables are read from global memory.
+// ---------------------------------------------------------------------------------
+template <typename T>
+struct SweepJob {
+  DevModel dm;
+  Tables<T> tb;
+  SweepArgs a;
+};
+
+template <typename T, bool C, int R>
+__global__ __launch_bounds__(256) void k_sweep_batch(const SweepJob<T> *__restrict__ jobs,
+                                                     const int2 *__restrict__ bmap) {
+  const int2 bm = bmap[blockIdx.x];  // (job, first chain of the block)
+  const SweepJob<T> J = jobs[bm.x];
+  sweep_block<T, C, R, false>(J.dm, J.tb, J.a, bm.y);
+}
+
+template <typename T, typename PT>
+struct TabJob {
+  DevModel dm;
+  Tables<T> tb;
+  const PT *p;
+  int quant, need_flip, need_bond, blocks;
+};
+
+template <typename T, bool C, typename PT>
+__global__ void k_tables_batch(const TabJob<T, PT> *__restrict__ jobs,
+                               const int2 *__restrict__ bmap) {
+  const int2 bm = bmap[blockIdx.x];  // (job, block within the job)
+  const TabJob<T, PT> J = jobs[bm.x];
+  tables_body<T, C, PT>(J.dm, J.tb, J.p, J.quant, J.need_flip, J.need_bond, bm.y, J.blocks);
+}
+
 // ---------------------------------------------------------------------------------
 // Local energy of arbitrary configurations from precomputed rows T[s][j] = tanh(theta_j)
 // (the matrix-core kernel k_theta_tanh): one sample per wavefront at full occupancy; the
@@ -851,6 +902,100 @@ hipError_t logpsi_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *ou
 }
 
 }  // namespace
+
+namespace {
+
+template <typename T, bool C, int R>
+hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &items,
+                          int n_sweeps, int n_discard, uint64_t counter, hipStream_t st) {
+  typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type PT;
+  const int wpb = 4;
+  std::vector<TabJob<T, PT>> tj;
+  std::vector<int2> tmap;
+  std::vector<SweepJob<T>> sj;
+  std::vector<int2> smap;
+  size_t wave_max = 0;
+  for (size_t k = 0; k < items.size(); ++k) {
+    const BatchSampleItem &it = items[k];
+    const nqs_model *m = it.m;
+    TabJob<T, PT> t;
+    t.dm = dev_model(m);
+    t.tb = tables_of<T>(m);
+    t.p = (const PT *)it.params;
+    t.quant = m->prec == NQS_BF16;
+    t.need_flip = int(m->need_flip);
+    t.need_bond = int(m->need_bond);
+    const int64_t total =
+        int64_t(m->N) * m->M + int64_t(m->Btot) * m->M + m->M + m->N + m->Btot;
+    t.blocks = int((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+    for (int q = 0; q < t.blocks; ++q) tmap.push_back(make_int2(int(k), q));
+    tj.push_back(t);
+    SweepJob<T> w;
+    w.dm = dev_model(m);
+    w.tb = tables_of<T>(m);
+    SweepArgs &a = w.a;
+    a.chain_sigma = it.chains;
+    a.n_chains = it.n_chains;
+    a.n_sweeps = n_sweeps;
+    a.n_discard = n_discard;
+    a.k0 = uint32_t(it.seed & 0xffffffffu);
+    a.k1 = uint32_t(it.seed >> 32);
+    a.counter = uint32_t(counter);
+    a.chain_offset = 0;
+    a.samples = it.samples;
+    a.n_acc = it.n_acc;
+    a.eloc = (double *)it.eloc;
+    a.cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
+    a.w_rows = m->move == NQS_MOVE_FLIP ? m->N : m->B[0];
+    a.Npad = round_up(m->N, 16);
+    a.wave_bytes = a.Npad + round_up(m->M * int(sizeof(V<T, C>)), 16);
+    if (size_t(a.wave_bytes) > wave_max) wave_max = size_t(a.wave_bytes);
+    for (int c = 0; c < it.n_chains; c += wpb) smap.push_back(make_int2(int(k), c));
+    sj.push_back(w);
+  }
+  if (smap.empty()) return hipSuccess;
+  hipError_t e;
+  if ((e = b->tab_jobs.upload(tj.data(), tj.size() * sizeof(tj[0]), st)) != hipSuccess) return e;
+  if ((e = b->tab_map.upload(tmap.data(), tmap.size() * sizeof(int2), st)) != hipSuccess) return e;
+  if ((e = b->sweep_jobs.upload(sj.data(), sj.size() * sizeof(sj[0]), st)) != hipSuccess) return e;
+  if ((e = b->sweep_map.upload(smap.data(), smap.size() * sizeof(int2), st)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL((k_tables_batch<T, C, PT>), dim3(unsigned(tmap.size())), dim3(256), 0, st,
+                     (const TabJob<T, PT> *)b->tab_jobs.d, (const int2 *)b->tab_map.d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sweep_batch<T, C, R>), dim3(unsigned(smap.size())), dim3(64 * wpb),
+                     size_t(wpb) * wave_max, st, (const SweepJob<T> *)b->sweep_jobs.d,
+                     (const int2 *)b->sweep_map.d);
+  return hipGetLastError();
+}
+
+template <typename T, bool C>
+hipError_t sample_batch_t(nqs_batch *b, const std::vector<BatchSampleItem> &items,
+                          int n_sweeps, int n_discard, uint64_t counter, hipStream_t st) {
+  int r = 1;
+  for (const BatchSampleItem &it : items) {
+    const int rk = (it.m->M + 63) / 64;
+    if (rk > r) r = rk;
+  }
+  if (r <= 1) return sample_batch_r<T, C, 1>(b, items, n_sweeps, n_discard, counter, st);
+  if (r <= 2) return sample_batch_r<T, C, 2>(b, items, n_sweeps, n_discard, counter, st);
+  if (r <= 4) return sample_batch_r<T, C, 4>(b, items, n_sweeps, n_discard, counter, st);
+  if (r <= 8) return sample_batch_r<T, C, 8>(b, items, n_sweeps, n_discard, counter, st);
+  if (r <= 16) return sample_batch_r<T, C, 16>(b, items, n_sweeps, n_discard, counter, st);
+  return sample_batch_r<T, C, 32>(b, items, n_sweeps, n_discard, counter, st);
+}
+
+}  // namespace
+
+hipError_t launch_sample_batch(nqs_batch *b, const std::vector<BatchSampleItem> &items,
+                               int n_sweeps, int n_discard, uint64_t counter, hipStream_t st) {
+  if (items.empty()) return hipSuccess;
+  const nqs_model *m = items[0].m;
+  return use_double(m) ? (m->is_complex ? sample_batch_t<double, true>(b, items, n_sweeps, n_discard, counter, st)
+                                        : sample_batch_t<double, false>(b, items, n_sweeps, n_discard, counter, st))
+                       : (m->is_complex ? sample_batch_t<float, true>(b, items, n_sweeps, n_discard, counter, st)
+                                        : sample_batch_t<float, false>(b, items, n_sweeps, n_discard, counter, st));
+}
 
 #define NQS_DISPATCH(FN, ...)                                                              \
   (use_double(m) ? (m->is_complex ? FN<double, true>(__VA_ARGS__)                          \
