@@ -71,7 +71,7 @@ __global__ void k_prep_dir(int N, int M, const double *__restrict__ v, T *Vt, T 
 // the epilogue. Grid (ceil(n/64), hidden chunks of JT tiles); 16 samples per wavefront.
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
-__global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
+__device__ __forceinline__ void k_theta_tanh_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n,
                                                      const int8_t *__restrict__ sigma,
                                                      const T *__restrict__ Wt,
                                                      const T *__restrict__ bv, int JT, int quant,
@@ -79,9 +79,9 @@ __global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
   typedef typename MF<T>::acc Acc;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
-  const int64_t s0 = int64_t(blockIdx.x) * 64 + wid * 16;
+  const int64_t s0 = int64_t(BX) * 64 + wid * 16;
   const int ntiles = (M + 15) / 16;
-  const int jt0 = blockIdx.y * JT;
+  const int jt0 = BY * JT;
   const int jt1 = jt0 + JT < ntiles ? jt0 + JT : ntiles;
   const int64_t rowA = s0 + lo;
   const bool rowA_ok = rowA < n;
@@ -118,12 +118,21 @@ __global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
   }
 }
 
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
+                                                     const int8_t *__restrict__ sigma,
+                                                     const T *__restrict__ Wt,
+                                                     const T *__restrict__ bv, int JT, int quant,
+                                                     T *Tout) {
+  k_theta_tanh_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, sigma, Wt, bv, JT, quant, Tout);
+}
+
 // ---------------------------------------------------------------------------------
 // JVP with stored T: y_s = sum_i s_si va_i + sum_j T_sj (vb_j + (S V^T)_sj).
 // Grid (ceil(n/64), hidden chunks). Writes ypart[chunk][s] (complex double).
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
-__global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
+__device__ __forceinline__ void k_jvp_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n,
                                               const int8_t *__restrict__ sigma,
                                               const T *__restrict__ Tm,
                                               const T *__restrict__ Vt, const T *__restrict__ vb,
@@ -133,8 +142,8 @@ __global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
   typedef typename MF<T>::acc Acc;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
-  const int64_t s0 = int64_t(blockIdx.x) * 64 + wid * 16;
-  const int jc = blockIdx.y;
+  const int64_t s0 = int64_t(BX) * 64 + wid * 16;
+  const int jc = BY;
   const int ntiles = (M + 15) / 16;
   const int jt0 = jc * JT;
   const int jt1 = jt0 + JT < ntiles ? jt0 + JT : ntiles;
@@ -200,15 +209,25 @@ __global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
   }
 }
 
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
+                                              const int8_t *__restrict__ sigma,
+                                              const T *__restrict__ Tm,
+                                              const T *__restrict__ Vt, const T *__restrict__ vb,
+                                              const double *__restrict__ va, int JT,
+                                              double *ypart, const int *skip) {
+  k_jvp_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, sigma, Tm, Vt, vb, va, JT, ypart, skip);
+}
+
 // y[s] = sum over chunks; per-block partial sums of y (complex double) for centering
 template <bool C>
-__global__ __launch_bounds__(256) void k_jvp_finish(int64_t n, int jchunks,
+__device__ __forceinline__ void k_jvp_finish_body(int BX, int BY, int BZ, int GX, int64_t n, int jchunks,
                                                      const double *__restrict__ ypart,
                                                      double *y, double *ysum_part,
                                                      const int *skip) {
   if (skip && *skip) return;
   __shared__ double sr[256], si[256];
-  const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t s = int64_t(BX) * 256 + threadIdx.x;
   double yr = 0.0, yi = 0.0;
   if (s < n) {
     for (int c = 0; c < jchunks; ++c) {
@@ -234,10 +253,18 @@ __global__ __launch_bounds__(256) void k_jvp_finish(int64_t n, int jchunks,
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      ysum_part[2 * blockIdx.x] = sr[0];
-      ysum_part[2 * blockIdx.x + 1] = si[0];
+      ysum_part[2 * BX] = sr[0];
+      ysum_part[2 * BX + 1] = si[0];
     }
   }
+}
+
+template <bool C>
+__global__ __launch_bounds__(256) void k_jvp_finish(int64_t n, int jchunks,
+                                                     const double *__restrict__ ypart,
+                                                     double *y, double *ysum_part,
+                                                     const int *skip) {
+  k_jvp_finish_body<C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, n, jchunks, ypart, y, ysum_part, skip);
 }
 
 // ---------------------------------------------------------------------------------
@@ -252,7 +279,7 @@ __global__ __launch_bounds__(256) void k_jvp_finish(int64_t n, int jchunks,
 // partial layout [split][Jtiles*16][Itiles*16], compute precision.
 // ---------------------------------------------------------------------------------
 template <typename T, bool C, int JT, int NT>
-__global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
+__device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n,
                                               const int8_t *__restrict__ sigma,
                                               const T *__restrict__ Tm,
                                               const double *__restrict__ u, int64_t per_split,
@@ -262,8 +289,8 @@ __global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
   __shared__ T red[4][4][64][C ? 2 : 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
-  const int jt0 = blockIdx.x * JT, it0 = blockIdx.z * NT;
-  const int64_t sbeg = int64_t(blockIdx.y) * per_split;
+  const int jt0 = BX * JT, it0 = BZ * NT;
+  const int64_t sbeg = int64_t(BY) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
   Acc ar[JT][NT], ai[JT][NT];
 #pragma unroll
@@ -318,7 +345,7 @@ __global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
       const int jrow = (jt0 + a) * 16 + MF<T>::row(l >> 4, r);
       const int icol = (it0 + b) * 16 + (l & 15);
       if (jrow < rowsP && icol < colsP) {
-        const int64_t o = (int64_t(blockIdx.y) * rowsP + jrow) * colsP + icol;
+        const int64_t o = (int64_t(BY) * rowsP + jrow) * colsP + icol;
         T sr = red[0][r][l][0] + red[1][r][l][0] + red[2][r][l][0] + red[3][r][l][0];
         if constexpr (C) {
           T si = red[0][r][l][C ? 1 : 0] + red[1][r][l][C ? 1 : 0] + red[2][r][l][C ? 1 : 0] +
@@ -330,6 +357,15 @@ __global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
         }
       }
     }
+}
+
+template <typename T, bool C, int JT, int NT>
+__global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
+                                              const int8_t *__restrict__ sigma,
+                                              const T *__restrict__ Tm,
+                                              const double *__restrict__ u, int64_t per_split,
+                                              int rowsP, int colsP, T *part, const int *skip) {
+  k_vjp_body<T, C, JT, NT>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, sigma, Tm, u, per_split, rowsP, colsP, part, skip);
 }
 
 // sum over the 16 lanes of each DPP row (every lane of the row receives the total)
@@ -864,13 +900,13 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
 
 // first reduction level: out1[g][e] = sum of partials of split group g (complex double)
 template <typename T, bool C>
-__global__ __launch_bounds__(256) void k_vjp_reduce1(int splits, int groups, int64_t elems,
+__device__ __forceinline__ void k_vjp_reduce1_body(int BX, int BY, int BZ, int GX, int splits, int groups, int64_t elems,
                                                      const T *__restrict__ part, double *out1,
                                                      const int *skip) {
   if (skip && *skip) return;
-  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t e = int64_t(BX) * 256 + threadIdx.x;
   if (e >= elems) return;
-  const int g = blockIdx.y;
+  const int g = BY;
   const int per = (splits + groups - 1) / groups;
   const int p0 = g * per, p1 = p0 + per < splits ? p0 + per : splits;
   double sr = 0.0, si = 0.0;
@@ -883,14 +919,21 @@ __global__ __launch_bounds__(256) void k_vjp_reduce1(int splits, int groups, int
   out1[2 * (int64_t(g) * elems + e) + 1] = si;
 }
 
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_vjp_reduce1(int splits, int groups, int64_t elems,
+                                                     const T *__restrict__ part, double *out1,
+                                                     const int *skip) {
+  k_vjp_reduce1_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, splits, groups, elems, part, out1, skip);
+}
+
 // second level: out[k] (double, packed like the parameters) = sum over groups
 template <bool C>
-__global__ void k_vjp_reduce2(int N, int M, int groups, int colsP, int64_t elems,
+__device__ __forceinline__ void k_vjp_reduce2_body(int BX, int BY, int BZ, int GX, int N, int M, int groups, int colsP, int64_t elems,
                               const double *__restrict__ out1, double *out, const int *skip) {
   if (skip && *skip) return;
   const int64_t P = int64_t(N) + M + int64_t(N) * M;
-  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < P;
-       k += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t k = BX * int64_t(blockDim.x) + threadIdx.x; k < P;
+       k += int64_t(GX) * blockDim.x) {
     int64_t e;
     if (k < N) {
       e = int64_t(M) * colsP + k;                 // row M: visible bias
@@ -912,6 +955,12 @@ __global__ void k_vjp_reduce2(int N, int M, int groups, int colsP, int64_t elems
       out[k] = sr;
     }
   }
+}
+
+template <bool C>
+__global__ void k_vjp_reduce2(int N, int M, int groups, int colsP, int64_t elems,
+                              const double *__restrict__ out1, double *out, const int *skip) {
+  k_vjp_reduce2_body<C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, groups, colsP, elems, out1, out, skip);
 }
 
 // ---------------------------------------------------------------------------------

@@ -61,9 +61,9 @@ __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
 // ---- statistics -----------------------------------------------------------------
 template <bool C>
-__global__ __launch_bounds__(256) void k_sum_e(int64_t n, const double *e, double *part) {
+__device__ __forceinline__ void k_sum_e_body(int BX, int BY, int BZ, int GX, int64_t n, const double *e, double *part) {
   __shared__ double lds[256];
-  const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t s = int64_t(BX) * 256 + threadIdx.x;
   double r = 0.0, i = 0.0;
   if (s < n) {
     r = C ? e[2 * s] : e[s];
@@ -72,24 +72,29 @@ __global__ __launch_bounds__(256) void k_sum_e(int64_t n, const double *e, doubl
   r = block_reduce(r, lds);
   i = block_reduce(i, lds);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = r;
-    part[2 * blockIdx.x + 1] = i;
+    part[2 * BX] = r;
+    part[2 * BX + 1] = i;
   }
+}
+
+template <bool C>
+__global__ __launch_bounds__(256) void k_sum_e(int64_t n, const double *e, double *part) {
+  k_sum_e_body<C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, n, e, part);
 }
 
 // u_s = E_s - E (E from the partials), per-block partial sums of |u|^2
 template <bool C>
-__global__ __launch_bounds__(256) void k_center_e(int64_t n, const double *e,
+__device__ __forceinline__ void k_center_e_body(int BX, int BY, int BZ, int GX, int64_t n, const double *e,
                                                    const double *part, int64_t nparts,
                                                    double *u, double *part2, CGState *st) {
   __shared__ double lds[256];
   const double Er = block_sum(part, nparts, 2, lds) / double(n);
   const double Ei = block_sum(part + 1, nparts, 2, lds) / double(n);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (BX == 0 && threadIdx.x == 0) {
     st->E[0] = Er;
     st->E[1] = Ei;
   }
-  const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t s = int64_t(BX) * 256 + threadIdx.x;
   double v = 0.0;
   if (s < n) {
     double ur = (C ? e[2 * s] : e[s]) - Er;
@@ -103,7 +108,14 @@ __global__ __launch_bounds__(256) void k_center_e(int64_t n, const double *e,
     v = ur * ur + ui * ui;
   }
   v = block_reduce(v, lds);
-  if (threadIdx.x == 0) part2[blockIdx.x] = v;
+  if (threadIdx.x == 0) part2[BX] = v;
+}
+
+template <bool C>
+__global__ __launch_bounds__(256) void k_center_e(int64_t n, const double *e,
+                                                   const double *part, int64_t nparts,
+                                                   double *u, double *part2, CGState *st) {
+  k_center_e_body<C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, n, e, part, nparts, u, part2, st);
 }
 
 __global__ void k_fill(int64_t count, double *x, double val) {
@@ -130,19 +142,19 @@ __device__ __forceinline__ void dir_write(int N, int M, int64_t k, double pr, do
 
 // variance; F = g / n; x = 0; r = p = F (+ direction tables); partial ||F||^2
 template <typename T, bool C>
-__global__ __launch_bounds__(256) void k_cg_init(int N, int M, int64_t n, const double *part2,
+__device__ __forceinline__ void k_cg_init_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n, const double *part2,
                                                   int64_t nparts, const double *g, double *F,
                                                   double *x, double *r, double *p, T *Vt, T *vb,
                                                   double *va, double *dpart, CGState *st) {
   __shared__ double lds[256];
   const int64_t P = int64_t(N) + M + int64_t(N) * M;
-  if (blockIdx.x == 0) {
+  if (BX == 0) {
     double var = block_sum(part2, nparts, 1, lds) / double(n);
     if (threadIdx.x == 0) st->var = var;
   }
   double acc = 0.0;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
-       k += int64_t(gridDim.x) * 256) {
+  for (int64_t k = int64_t(BX) * 256 + threadIdx.x; k < P;
+       k += int64_t(GX) * 256) {
     const double fr = (C ? g[2 * k] : g[k]) / double(n);
     const double fi = C ? g[2 * k + 1] / double(n) : 0.0;
     if (C) {
@@ -164,10 +176,18 @@ __global__ __launch_bounds__(256) void k_cg_init(int N, int M, int64_t n, const 
     acc += fr * fr + fi * fi;
   }
   acc = block_reduce(acc, lds);
-  if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+  if (threadIdx.x == 0) dpart[BX] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_cg_start(const double *dpart, int64_t nparts,
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_cg_init(int N, int M, int64_t n, const double *part2,
+                                                  int64_t nparts, const double *g, double *F,
+                                                  double *x, double *r, double *p, T *Vt, T *vb,
+                                                  double *va, double *dpart, CGState *st) {
+  k_cg_init_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, part2, nparts, g, F, x, r, p, Vt, vb, va, dpart, st);
+}
+
+__device__ __forceinline__ void k_cg_start_body(int BX, int BY, int BZ, int GX, const double *dpart, int64_t nparts,
                                                   double tol, int maxiter, CGState *st) {
   __shared__ double lds[256];
   double rr = block_sum(dpart, nparts, 1, lds);
@@ -185,10 +205,15 @@ __global__ __launch_bounds__(256) void k_cg_start(const double *dpart, int64_t n
   }
 }
 
+__global__ __launch_bounds__(256) void k_cg_start(const double *dpart, int64_t nparts,
+                                                  double tol, int maxiter, CGState *st) {
+  k_cg_start_body(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, dpart, nparts, tol, maxiter, st);
+}
+
 // g = O^dagger y from the first-level sums, then
 // Ap = (g - ybar * O^dagger 1) / n + lambda p ; partial Re(p^dagger Ap)
 template <bool C>
-__global__ __launch_bounds__(256) void k_cg_ap(int N, int M, int64_t n, int groups, int colsP,
+__device__ __forceinline__ void k_cg_ap_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n, int groups, int colsP,
                                                int64_t elems, const double *out1,
                                                const double *o1, const double *ysum,
                                                int64_t nys, const double *p, double lambda,
@@ -199,8 +224,8 @@ __global__ __launch_bounds__(256) void k_cg_ap(int N, int M, int64_t n, int grou
   const double ybr = block_sum(ysum, nys, 2, lds) / double(n);
   const double ybi = C ? block_sum(ysum + 1, nys, 2, lds) / double(n) : 0.0;
   double acc = 0.0;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
-       k += int64_t(gridDim.x) * 256) {
+  for (int64_t k = int64_t(BX) * 256 + threadIdx.x; k < P;
+       k += int64_t(GX) * 256) {
     int64_t e;
     if (k < N)
       e = int64_t(M) * colsP + k;
@@ -228,11 +253,20 @@ __global__ __launch_bounds__(256) void k_cg_ap(int N, int M, int64_t n, int grou
     }
   }
   acc = block_reduce(acc, lds);
-  if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+  if (threadIdx.x == 0) dpart[BX] = acc;
+}
+
+template <bool C>
+__global__ __launch_bounds__(256) void k_cg_ap(int N, int M, int64_t n, int groups, int colsP,
+                                               int64_t elems, const double *out1,
+                                               const double *o1, const double *ysum,
+                                               int64_t nys, const double *p, double lambda,
+                                               double *Ap, double *dpart, const CGState *st) {
+  k_cg_ap_body<C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, groups, colsP, elems, out1, o1, ysum, nys, p, lambda, Ap, dpart, st);
 }
 
 // alpha = rr / p^dagger Ap ; x += alpha p ; r -= alpha Ap ; partial r^dagger r
-__global__ __launch_bounds__(256) void k_cg_xr(int64_t Pc, const double *dpart, int64_t nparts,
+__device__ __forceinline__ void k_cg_xr_body(int BX, int BY, int BZ, int GX, int64_t Pc, const double *dpart, int64_t nparts,
                                                int parity, double *x, double *r,
                                                const double *p, const double *Ap,
                                                double *rpart, CGState *st) {
@@ -241,22 +275,29 @@ __global__ __launch_bounds__(256) void k_cg_xr(int64_t Pc, const double *dpart, 
   const double pAp = block_sum(dpart, nparts, 1, lds);
   const double alpha = st->rr[parity] / pAp;
   double acc = 0.0;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Pc;
-       k += int64_t(gridDim.x) * 256) {
+  for (int64_t k = int64_t(BX) * 256 + threadIdx.x; k < Pc;
+       k += int64_t(GX) * 256) {
     x[k] += alpha * p[k];
     double rk = r[k] - alpha * Ap[k];
     r[k] = rk;
     acc += rk * rk;
   }
   acc = block_reduce(acc, lds);
-  if (threadIdx.x == 0) rpart[blockIdx.x] = acc;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->alpha = alpha;
+  if (threadIdx.x == 0) rpart[BX] = acc;
+  if (BX == 0 && threadIdx.x == 0) st->alpha = alpha;
+}
+
+__global__ __launch_bounds__(256) void k_cg_xr(int64_t Pc, const double *dpart, int64_t nparts,
+                                               int parity, double *x, double *r,
+                                               const double *p, const double *Ap,
+                                               double *rpart, CGState *st) {
+  k_cg_xr_body(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, Pc, dpart, nparts, parity, x, r, p, Ap, rpart, st);
 }
 
 // rr_new from partials; convergence; beta = rr_new / rr ; p = r + beta p (+ direction
 // tables for the next product)
 template <typename T, bool C>
-__global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart, int64_t nparts,
+__device__ __forceinline__ void k_cg_p_body(int BX, int BY, int BZ, int GX, int N, int M, const double *rpart, int64_t nparts,
                                               int parity, double tol, int maxiter,
                                               const double *r, double *p, T *Vt, T *vb,
                                               double *va, CGState *st) {
@@ -269,8 +310,8 @@ __global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart,
   const int iters = st->iters + 1;
   const bool conv = sqrt(rr_new) <= tol * st->bnorm;
   const bool bad = !(finite(rr_new) && finite(st->alpha));
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
-       k += int64_t(gridDim.x) * 256) {
+  for (int64_t k = int64_t(BX) * 256 + threadIdx.x; k < P;
+       k += int64_t(GX) * 256) {
     double pr, pi = 0.0;
     if (C) {
       pr = r[2 * k] + beta * p[2 * k];
@@ -284,7 +325,7 @@ __global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart,
     dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va);
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (BX == 0 && threadIdx.x == 0) {
     st->rr[parity ^ 1] = rr_new;
     st->iters = iters;
     st->converged = conv;
@@ -293,11 +334,24 @@ __global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart,
   }
 }
 
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart, int64_t nparts,
+                                              int parity, double tol, int maxiter,
+                                              const double *r, double *p, T *Vt, T *vb,
+                                              double *va, CGState *st) {
+  k_cg_p_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, rpart, nparts, parity, tol, maxiter, r, p, Vt, vb, va, st);
+}
+
+template <typename PT>
+__device__ __forceinline__ void k_update_body(int BX, int BY, int BZ, int GX, int64_t Pc, PT *params, const double *x, double lr) {
+  for (int64_t k = BX * int64_t(blockDim.x) + threadIdx.x; k < Pc;
+       k += int64_t(GX) * blockDim.x)
+    params[k] = PT(double(params[k]) - lr * x[k]);
+}
+
 template <typename PT>
 __global__ void k_update(int64_t Pc, PT *params, const double *x, double lr) {
-  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < Pc;
-       k += int64_t(gridDim.x) * blockDim.x)
-    params[k] = PT(double(params[k]) - lr * x[k]);
+  k_update_body<PT>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, Pc, params, x, lr);
 }
 
 struct SRLayout {
@@ -346,9 +400,9 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   } while (0)
 
 template <bool C>
-__global__ void k_ones(int64_t n, double *u) {
-  for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < n;
-       s += int64_t(gridDim.x) * blockDim.x) {
+__device__ __forceinline__ void k_ones_body(int BX, int BY, int BZ, int GX, int64_t n, double *u) {
+  for (int64_t s = BX * int64_t(blockDim.x) + threadIdx.x; s < n;
+       s += int64_t(GX) * blockDim.x) {
     if (C) {
       u[2 * s] = 1.0;
       u[2 * s + 1] = 0.0;
@@ -356,6 +410,11 @@ __global__ void k_ones(int64_t n, double *u) {
       u[s] = 1.0;
     }
   }
+}
+
+template <bool C>
+__global__ void k_ones(int64_t n, double *u) {
+  k_ones_body<C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, n, u);
 }
 
 inline unsigned grid_for(int64_t count) {
