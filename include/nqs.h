@@ -254,6 +254,19 @@ nqs_status nqs_batch_sample(nqs_batch *batch, const void *params, int8_t *chain_
                             const int32_t *n_chains, int32_t n_sweeps, int32_t n_discard,
                             uint64_t seed, uint64_t counter, int8_t *samples,
                             int64_t *n_accepted, void *eloc, void *stream);
+/* One SR step (Sec. 2.2.5, Eq. 2) of every model of the batch, as nqs_sr_step on each:
+ * samples and eloc concatenated in model order (model k: n_samples[k] rows of N_k spins,
+ * n_samples[k] local energies), params updated in place, info (host) an array [K]. The
+ * solves advance together: every kernel of a CG iteration is one launch for all models,
+ * and models that have converged stop updating. Returns NQS_ENONFINITE if any model's
+ * solve is non-finite (its parameters are left unchanged), else NQS_ENOTCONV if any
+ * model reached cg_maxiter, else NQS_OK. Synchronizes the stream. Workspace:
+ * nqs_batch_sr_workspace_bytes(batch, n_samples) bytes (0 if some n_samples[k] < 2). */
+size_t nqs_batch_sr_workspace_bytes(nqs_batch *batch, const int64_t *n_samples);
+nqs_status nqs_batch_sr_step(nqs_batch *batch, void *params, const int8_t *samples,
+                             const void *eloc, const int64_t *n_samples, double lr,
+                             double diag_shift, double cg_tol, int32_t cg_maxiter,
+                             void *workspace, size_t ws_bytes, nqs_sr_info *info, void *stream);
 
 const char *nqs_status_string(nqs_status s);
 

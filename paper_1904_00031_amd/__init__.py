@@ -96,6 +96,9 @@ def load(path=LIB_PATH):
         "nqs_batch_chain_init": (i32, [vp, vp, ctypes.POINTER(i32), u64, vp]),
         "nqs_batch_sample": (i32, [vp, vp, vp, ctypes.POINTER(i32), i32, i32, u64, u64, vp, vp,
                                    vp, vp]),
+        "nqs_batch_sr_workspace_bytes": (ctypes.c_size_t, [vp, ctypes.POINTER(i64)]),
+        "nqs_batch_sr_step": (i32, [vp, vp, vp, vp, ctypes.POINTER(i64), f64, f64, f64, i32, vp,
+                                    ctypes.c_size_t, ctypes.POINTER(SRInfo), vp]),
         "nqs_autotune": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, ctypes.POINTER(TuneReport), vp]),
     }
     for name, (res, args) in sig.items():
@@ -112,7 +115,7 @@ def exported_symbols():
             "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_prepare",
             "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_batch_create",
             "nqs_batch_destroy", "nqs_batch_n_params", "nqs_batch_chain_init",
-            "nqs_batch_sample"]
+            "nqs_batch_sample", "nqs_batch_sr_workspace_bytes", "nqs_batch_sr_step"]
 
 
 def _check(status, where, allow=(OK,)):
@@ -439,6 +442,29 @@ class Batch:
                                      seed, counter, _ptr(samples), _ptr(n_accepted), _ptr(eloc),
                                      _stream()), "nqs_batch_sample")
         return samples, eloc
+
+    def sr_workspace_bytes(self, n_samples):
+        ns = (ctypes.c_int64 * self.K)(*[int(x) for x in n_samples])
+        return int(_lib.nqs_batch_sr_workspace_bytes(self._h, ns))
+
+    def sr_step(self, params, samples, eloc, n_samples, lr, diag_shift, cg_tol, cg_maxiter,
+                workspace=None):
+        """One SR step of every model; returns a list of info dicts."""
+        import torch
+        ns = (ctypes.c_int64 * self.K)(*[int(x) for x in n_samples])
+        _need(params, "params", self.param_dtype, (sum(self.n_params),))
+        _need(samples, "samples", torch.int8, (sum(int(x) * n for x, n in zip(n_samples, self.n_sites)),))
+        _need(eloc, "eloc", self.value_dtype, (sum(int(x) for x in n_samples),))
+        nbytes = int(_lib.nqs_batch_sr_workspace_bytes(self._h, ns))
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=samples.device)
+        _need(workspace, "workspace", torch.uint8)
+        infos = (SRInfo * self.K)()
+        _check(_lib.nqs_batch_sr_step(self._h, _ptr(params), _ptr(samples), _ptr(eloc), ns,
+                                      float(lr), float(diag_shift), float(cg_tol), int(cg_maxiter),
+                                      _ptr(workspace), workspace.numel(), infos, _stream()),
+               "nqs_batch_sr_step", allow=(OK, ENOTCONV))
+        return [infos[k].as_dict() for k in range(self.K)]
 
 
 # C-ABI-named module functions --------------------------------------------------------

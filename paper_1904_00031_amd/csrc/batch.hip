@@ -5,6 +5,8 @@
 // to its model are built on the host and uploaded only when they change.
 #include <string.h>
 
+#include <cmath>
+
 #include <new>
 #include <vector>
 
@@ -139,6 +141,26 @@ nqs_status nqs_batch_sample(nqs_batch *b, const void *params, int8_t *chain_sigm
     oa += size_t(n_chains[k]);
   }
   return dev(launch_sample_batch(b, items, n_sweeps, n_discard, counter, (hipStream_t)stream));
+}
+
+size_t nqs_batch_sr_workspace_bytes(nqs_batch *b, const int64_t *n_samples) {
+  if (!b || !n_samples) return 0;
+  for (int k = 0; k < b->K; ++k)
+    if (n_samples[k] < 2) return 0;
+  return batch_sr_workspace_bytes(b, n_samples);
+}
+
+nqs_status nqs_batch_sr_step(nqs_batch *b, void *params, const int8_t *samples,
+                             const void *eloc, const int64_t *n_samples, double lr,
+                             double diag_shift, double cg_tol, int32_t cg_maxiter,
+                             void *workspace, size_t ws_bytes, nqs_sr_info *info, void *stream) {
+  if (!b || !params || !samples || !eloc || !n_samples || !workspace || cg_maxiter < 0 ||
+      !(diag_shift >= 0) || !(cg_tol >= 0) || !std::isfinite(lr))
+    return NQS_EINVAL;
+  for (int k = 0; k < b->K; ++k)
+    if (n_samples[k] < 2) return NQS_EINVAL;
+  return batch_sr_step_impl(b, params, samples, eloc, n_samples, lr, diag_shift, cg_tol,
+                            cg_maxiter, workspace, ws_bytes, info, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -1215,6 +1215,200 @@ hipError_t vjp_reduce_t(const nqs_model *m, int64_t n, void *scratch, double *ou
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------
+// Batches of models (nqs_batch): one launch per kernel for every model. Each block reads
+// its model's arguments from a job table and its block indices from a block map, then
+// runs the single-model body. The VJP uses 4 x 2 output tiles per block and splits of
+// 256 samples for every model.
+// ---------------------------------------------------------------------------------
+constexpr int kBJT = 4, kBNT = 2, kBSplit = 256;
+
+template <typename T>
+struct TanhJob {
+  int N, M;
+  int64_t n;
+  const int8_t *sigma;
+  const T *Wt, *bv;
+  int quant;
+  T *Tout;
+};
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_theta_tanh(const TanhJob<T> *jobs, const int4 *map) {
+  const int4 b = map[blockIdx.x];
+  const TanhJob<T> J = jobs[b.x];
+  k_theta_tanh_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Wt, J.bv, 16, J.quant,
+                          J.Tout);
+}
+
+template <typename T>
+struct JvpJob {
+  int N, M;
+  int64_t n;
+  const int8_t *sigma;
+  const T *Tm, *Vt, *vb;
+  const double *va;
+  double *ypart, *y, *ysum;
+  int jchunks;
+  const int *skip;
+};
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_jvp(const JvpJob<T> *jobs, const int4 *map) {
+  const int4 b = map[blockIdx.x];
+  const JvpJob<T> J = jobs[b.x];
+  k_jvp_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Tm, J.Vt, J.vb, J.va, 16, J.ypart,
+                   J.skip);
+}
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_jvp_finish(const JvpJob<T> *jobs, const int4 *map) {
+  const int4 b = map[blockIdx.x];
+  const JvpJob<T> J = jobs[b.x];
+  k_jvp_finish_body<C>(b.y, 0, 0, 0, J.n, J.jchunks, J.ypart, J.y, J.ysum, J.skip);
+}
+
+template <typename T>
+struct VjpJob {
+  int N, M;
+  int64_t n;
+  const int8_t *sigma;
+  const T *Tm;
+  const double *u;
+  int rowsP, colsP, splits;
+  int64_t elems;
+  T *part;
+  double *out1;  // [rowsP][colsP] complex double
+  double *out;   // packed like the parameters, or NULL (kept in out1)
+  int pblocks;
+  const int *skip;
+};
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_vjp(const VjpJob<T> *jobs, const int4 *map) {
+  const int4 b = map[blockIdx.x];
+  const VjpJob<T> J = jobs[b.x];
+  k_vjp_body<T, C, kBJT, kBNT>(b.y, b.z, b.w, 0, J.N, J.M, J.n, J.sigma, J.Tm, J.u, kBSplit,
+                               J.rowsP, J.colsP, J.part, J.skip);
+}
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_vjp_reduce1(const VjpJob<T> *jobs, const int4 *map) {
+  const int4 b = map[blockIdx.x];
+  const VjpJob<T> J = jobs[b.x];
+  if (int64_t(b.y) * 256 + threadIdx.x >= J.elems) return;
+  k_vjp_reduce1_body<T, C>(b.y, 0, 0, 0, J.splits, 1, J.elems, J.part, J.out1, J.skip);
+}
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_vjp_reduce2(const VjpJob<T> *jobs, const int4 *map) {
+  const int4 b = map[blockIdx.x];
+  const VjpJob<T> J = jobs[b.x];
+  k_vjp_reduce2_body<C>(b.y, 0, 0, J.pblocks, J.N, J.M, 1, J.colsP, J.elems, J.out1, J.out,
+                        J.skip);
+}
+
+template <typename T>
+hipError_t upload_launch_map(JobBuffer &jb, JobBuffer &mb, const std::vector<T> &jobs,
+                             const std::vector<int4> &map, hipStream_t st) {
+  hipError_t e = jb.upload(jobs.data(), jobs.size() * sizeof(T), st);
+  if (e != hipSuccess) return e;
+  if ((e = mb.upload(map.data(), map.size() * sizeof(int4), st)) != hipSuccess) return e;
+  // never launch on a table that is not there
+  if (!map.empty() && (!jb.d || !mb.d)) return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+template <typename T, bool C>
+hipError_t tanh_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, int slot,
+                        hipStream_t st) {
+  std::vector<TanhJob<T>> jobs;
+  std::vector<int4> map;
+  for (size_t k = 0; k < items.size(); ++k) {
+    const BatchGradItem &it = items[k];
+    const nqs_model *m = it.m;
+    TanhJob<T> J{m->N, m->M, it.n, it.sigma, (const T *)m->tab_ptrs[0], (const T *)m->tab_ptrs[1],
+                 int(m->prec == NQS_BF16), (T *)it.Tm};
+    jobs.push_back(J);
+    const int gx = int(cdiv(it.n, 64)), gy = int(cdiv((m->M + 15) / 16, 16));
+    for (int y = 0; y < gy; ++y)
+      for (int x = 0; x < gx; ++x) map.push_back(make_int4(int(k), x, y, 0));
+  }
+  hipError_t e = upload_launch_map(b->buf(slot), b->buf(slot + 1), jobs, map, st);
+  if (e != hipSuccess || map.empty()) return e;
+  hipLaunchKernelGGL((kb_theta_tanh<T, C>), dim3(unsigned(map.size())), dim3(256), 0, st,
+                     (const TanhJob<T> *)b->buf(slot).d, (const int4 *)b->buf(slot + 1).d);
+  return hipGetLastError();
+}
+
+template <typename T, bool C>
+hipError_t jvp_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, int slot,
+                       hipStream_t st) {
+  std::vector<JvpJob<T>> jobs;
+  std::vector<int4> map, map2;
+  for (size_t k = 0; k < items.size(); ++k) {
+    const BatchGradItem &it = items[k];
+    const nqs_model *m = it.m;
+    const int jchunks = int(cdiv((m->M + 15) / 16, 16));
+    JvpJob<T> J{m->N, m->M, it.n, it.sigma, (const T *)it.Tm, (const T *)it.Vt, (const T *)it.vb,
+                it.va, it.ypart, it.y, it.ysum, jchunks, it.skip};
+    jobs.push_back(J);
+    const int gx = int(cdiv(it.n, 64));
+    for (int y = 0; y < jchunks; ++y)
+      for (int x = 0; x < gx; ++x) map.push_back(make_int4(int(k), x, y, 0));
+    for (int x = 0; x < int(cdiv(it.n, 256)); ++x) map2.push_back(make_int4(int(k), x, 0, 0));
+  }
+  hipError_t e = upload_launch_map(b->buf(slot), b->buf(slot + 1), jobs, map, st);
+  if (e == hipSuccess) e = b->buf(slot + 2).upload(map2.data(), map2.size() * sizeof(int4), st);
+  if (e != hipSuccess || map.empty()) return e;
+  if (!b->buf(slot + 2).d) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((kb_jvp<T, C>), dim3(unsigned(map.size())), dim3(256), 0, st,
+                     (const JvpJob<T> *)b->buf(slot).d, (const int4 *)b->buf(slot + 1).d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((kb_jvp_finish<T, C>), dim3(unsigned(map2.size())), dim3(256), 0, st,
+                     (const JvpJob<T> *)b->buf(slot).d, (const int4 *)b->buf(slot + 2).d);
+  return hipGetLastError();
+}
+
+template <typename T, bool C>
+hipError_t vjp_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, bool to_params,
+                       int slot, hipStream_t st) {
+  std::vector<VjpJob<T>> jobs;
+  std::vector<int4> map, map1, map2;
+  for (size_t k = 0; k < items.size(); ++k) {
+    const BatchGradItem &it = items[k];
+    const nqs_model *m = it.m;
+    const int Jtiles = (m->M + 1 + 15) / 16, Itiles = (m->N + 1 + 15) / 16;
+    const int splits = int(cdiv(it.n > 0 ? it.n : 1, kBSplit));
+    const int64_t elems = int64_t(Jtiles) * 16 * Itiles * 16;
+    const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+    const int pblocks = int(cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096);
+    VjpJob<T> J{m->N,  m->M,    it.n,         it.sigma,  (const T *)it.Tm, it.u,
+                Jtiles * 16, Itiles * 16, splits, elems, (T *)it.part, it.out1,
+                to_params ? it.out : nullptr, pblocks, it.skip};
+    jobs.push_back(J);
+    for (int z = 0; z < int(cdiv(Itiles, kBNT)); ++z)
+      for (int y = 0; y < splits; ++y)
+        for (int x = 0; x < int(cdiv(Jtiles, kBJT)); ++x)
+          map.push_back(make_int4(int(k), x, y, z));
+    for (int x = 0; x < int(cdiv(elems, 256)); ++x) map1.push_back(make_int4(int(k), x, 0, 0));
+    for (int x = 0; x < pblocks; ++x) map2.push_back(make_int4(int(k), x, 0, 0));
+  }
+  hipError_t e = upload_launch_map(b->buf(slot), b->buf(slot + 1), jobs, map, st);
+  if (e == hipSuccess) e = b->buf(slot + 2).upload(map1.data(), map1.size() * sizeof(int4), st);
+  if (e == hipSuccess && to_params)
+    e = b->buf(slot + 3).upload(map2.data(), map2.size() * sizeof(int4), st);
+  if (e != hipSuccess || map.empty()) return e;
+  if (!b->buf(slot + 2).d || (to_params && !b->buf(slot + 3).d)) return hipErrorInvalidValue;
+  const VjpJob<T> *dj = (const VjpJob<T> *)b->buf(slot).d;
+  hipLaunchKernelGGL((kb_vjp<T, C>), dim3(unsigned(map.size())), dim3(256), 0, st, dj,
+                     (const int4 *)b->buf(slot + 1).d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((kb_vjp_reduce1<T, C>), dim3(unsigned(map1.size())), dim3(256), 0, st, dj,
+                     (const int4 *)b->buf(slot + 2).d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (to_params) {
+    hipLaunchKernelGGL((kb_vjp_reduce2<T, C>), dim3(unsigned(map2.size())), dim3(256), 0, st,
+                       dj, (const int4 *)b->buf(slot + 3).d);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
 }  // namespace
 
 GradPlan grad_plan(const nqs_model *m, int64_t n) {
@@ -1331,4 +1525,40 @@ hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, doubl
   return NQS_DISPATCH(vjp_reduce_t, m, n, scratch, out, skip, st);
 }
 
+BatchGradSizes batch_grad_sizes(const nqs_model *m, int64_t n) {
+  BatchGradSizes z;
+  const size_t es = (use_double(m) ? 8 : 4) * (m->is_complex ? 2 : 1);
+  const int Jtiles = (m->M + 1 + 15) / 16, Itiles = (m->N + 1 + 15) / 16;
+  const int64_t splits = cdiv(n > 0 ? n : 1, kBSplit);
+  z.Tm = size_t(n) * m->M * es + 128 * es;
+  z.Vt = size_t(m->N) * m->M * es;
+  z.vb = size_t(m->M) * es;
+  z.va = size_t(m->N) * 16;
+  z.ypart = size_t(cdiv((m->M + 15) / 16, 16)) * size_t(n) * 16;
+  z.part = size_t(splits) * Jtiles * 16 * Itiles * 16 * es;
+  z.out1 = size_t(Jtiles) * 16 * Itiles * 16 * 16;
+  z.colsP = Itiles * 16;
+  z.elems = int64_t(Jtiles) * 16 * Itiles * 16;
+  return z;
+}
 
+hipError_t launch_theta_tanh_batch(nqs_batch *b, const std::vector<BatchGradItem> &items,
+                                   int slot, hipStream_t st) {
+  if (items.empty()) return hipSuccess;
+  const nqs_model *m = items[0].m;
+  return NQS_DISPATCH(tanh_batch_t, b, items, slot, st);
+}
+
+hipError_t launch_jvp_batch(nqs_batch *b, const std::vector<BatchGradItem> &items, int slot,
+                            hipStream_t st) {
+  if (items.empty()) return hipSuccess;
+  const nqs_model *m = items[0].m;
+  return NQS_DISPATCH(jvp_batch_t, b, items, slot, st);
+}
+
+hipError_t launch_vjp_batch(nqs_batch *b, const std::vector<BatchGradItem> &items,
+                            bool to_params, int slot, hipStream_t st) {
+  if (items.empty()) return hipSuccess;
+  const nqs_model *m = items[0].m;
+  return NQS_DISPATCH(vjp_batch_t, b, items, to_params, slot, st);
+}

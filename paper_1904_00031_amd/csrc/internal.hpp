@@ -57,8 +57,42 @@ struct nqs_batch {
   int is_complex = 0, prec = 0;
   std::vector<nqs_model *> models;
   JobBuffer tab_jobs, tab_map, sweep_jobs, sweep_map;   // sampling
-  std::vector<JobBuffer> sr_bufs;                       // SR step job tables
+  // SR step job tables, by slot. A fixed array: references to slots stay valid while
+  // other slots are used (a growing container would move them).
+  static constexpr int kSlots = 32;
+  JobBuffer sr_bufs[kSlots];
+  JobBuffer &buf(int slot) { return sr_bufs[slot < kSlots ? slot : kSlots - 1]; }
 };
+
+// one model of a batched Jacobian pass (device pointers into the model's workspace)
+struct BatchGradItem {
+  const nqs_model *m;
+  int64_t n;
+  const int8_t *sigma;
+  void *Tm, *Vt, *vb;   // tanh rows, direction tables (compute precision)
+  double *va;           // direction of a (complex double)
+  double *ypart, *y, *ysum;  // JVP: per-chunk sums, O v, per-block sums of O v
+  const double *u;      // VJP input
+  void *part;           // VJP partial tiles
+  double *out1, *out;   // VJP tile sums, packed result
+  const int *skip;      // nonzero: the model's solve is finished, kernels return at once
+};
+// workspace pieces of one model in a batched Jacobian pass
+struct BatchGradSizes {
+  size_t Tm, Vt, vb, va, ypart, part, out1;
+  int colsP;
+  int64_t elems;
+};
+BatchGradSizes batch_grad_sizes(const nqs_model *m, int64_t n);
+// slot: first of the batch's job-table slots the call may use (theta/tanh 2, JVP 3, VJP 4)
+hipError_t launch_theta_tanh_batch(nqs_batch *b, const std::vector<BatchGradItem> &items,
+                                   int slot, hipStream_t st);
+hipError_t launch_jvp_batch(nqs_batch *b, const std::vector<BatchGradItem> &items, int slot,
+                            hipStream_t st);
+hipError_t launch_vjp_batch(nqs_batch *b, const std::vector<BatchGradItem> &items,
+                            bool to_params, int slot, hipStream_t st);
+hipError_t launch_tables_batch(nqs_batch *b, const std::vector<const void *> &params,
+                               hipStream_t st);
 
 // tables of every model, then every chain of every model in one persistent launch
 hipError_t launch_sample_batch(nqs_batch *b, const std::vector<BatchSampleItem> &items,
@@ -142,3 +176,9 @@ nqs_status autotune_impl(nqs_model *m, const void *params, const int8_t *sigma, 
 nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
                         int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
                         void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st);
+
+size_t batch_sr_workspace_bytes(nqs_batch *b, const int64_t *n_samples);
+nqs_status batch_sr_step_impl(nqs_batch *b, void *params, const int8_t *samples,
+                              const void *eloc, const int64_t *n_samples, double lr,
+                              double diag_shift, double cg_tol, int cg_maxiter, void *ws,
+                              size_t ws_bytes, nqs_sr_info *info, hipStream_t st);

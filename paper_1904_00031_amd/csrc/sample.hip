@@ -960,6 +960,8 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
   if ((e = b->sweep_jobs.upload(sj.data(), sj.size() * sizeof(sj[0]), st)) != hipSuccess) return e;
   if ((e = b->sweep_map.upload(smap.data(), smap.size() * sizeof(int2), st)) != hipSuccess)
     return e;
+  if (!b->tab_jobs.d || !b->tab_map.d || !b->sweep_jobs.d || !b->sweep_map.d)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_tables_batch<T, C, PT>), dim3(unsigned(tmap.size())), dim3(256), 0, st,
                      (const TabJob<T, PT> *)b->tab_jobs.d, (const int2 *)b->tab_map.d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -985,7 +987,47 @@ hipError_t sample_batch_t(nqs_batch *b, const std::vector<BatchSampleItem> &item
   return sample_batch_r<T, C, 32>(b, items, n_sweeps, n_discard, counter, st);
 }
 
+template <typename T, bool C>
+hipError_t tables_batch_t(nqs_batch *b, const std::vector<const void *> &params,
+                          hipStream_t st) {
+  typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type PT;
+  std::vector<TabJob<T, PT>> tj;
+  std::vector<int2> tmap;
+  for (size_t k = 0; k < params.size(); ++k) {
+    const nqs_model *m = b->models[k];
+    TabJob<T, PT> t;
+    t.dm = dev_model(m);
+    t.tb = tables_of<T>(m);
+    t.p = (const PT *)params[k];
+    t.quant = m->prec == NQS_BF16;
+    t.need_flip = int(m->need_flip);
+    t.need_bond = int(m->need_bond);
+    const int64_t total =
+        int64_t(m->N) * m->M + int64_t(m->Btot) * m->M + m->M + m->N + m->Btot;
+    t.blocks = int((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+    for (int q = 0; q < t.blocks; ++q) tmap.push_back(make_int2(int(k), q));
+    tj.push_back(t);
+  }
+  hipError_t e;
+  if ((e = b->tab_jobs.upload(tj.data(), tj.size() * sizeof(tj[0]), st)) != hipSuccess) return e;
+  if ((e = b->tab_map.upload(tmap.data(), tmap.size() * sizeof(int2), st)) != hipSuccess) return e;
+  if (!b->tab_jobs.d || !b->tab_map.d) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_tables_batch<T, C, PT>), dim3(unsigned(tmap.size())), dim3(256), 0, st,
+                     (const TabJob<T, PT> *)b->tab_jobs.d, (const int2 *)b->tab_map.d);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_tables_batch(nqs_batch *b, const std::vector<const void *> &params,
+                               hipStream_t st) {
+  if (params.empty()) return hipSuccess;
+  const nqs_model *m = b->models[0];
+  return use_double(m) ? (m->is_complex ? tables_batch_t<double, true>(b, params, st)
+                                        : tables_batch_t<double, false>(b, params, st))
+                       : (m->is_complex ? tables_batch_t<float, true>(b, params, st)
+                                        : tables_batch_t<float, false>(b, params, st));
+}
 
 hipError_t launch_sample_batch(nqs_batch *b, const std::vector<BatchSampleItem> &items,
                                int n_sweeps, int n_discard, uint64_t counter, hipStream_t st) {

@@ -9,6 +9,7 @@
 #include <math.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -601,6 +602,320 @@ nqs_status matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws, c
   return NQS_OK;
 }
 
+// ---------------------------------------------------------------------------------
+// Batched SR (nqs_batch): every model's solve advances in the same launches. Each block
+// reads its model's job and its block index from a block map and runs the single-model
+// body; models whose CG has finished return at once (their state's done flag).
+// ---------------------------------------------------------------------------------
+template <typename T>
+struct BJob {
+  int N, M;
+  int64_t n, P, Pc, nb;
+  int pblocks, cblocks, colsP;
+  int64_t elems;
+  const double *e;
+  double *epart, *epart2, *u, *ones;
+  double *g, *F, *x, *r, *p, *Ap, *o1, *dpart, *rpart;
+  const double *out1, *ysum;
+  T *Vt, *vb;
+  double *va;
+  void *params;
+  CGState *st;
+};
+
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_stats1(const BJob<T> *jobs, const int2 *map) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_sum_e_body<C>(b.y, 0, 0, 0, J.n, J.e, J.epart);
+}
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_stats2(const BJob<T> *jobs, const int2 *map) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_center_e_body<C>(b.y, 0, 0, 0, J.n, J.e, J.epart, J.nb, J.u, J.epart2, J.st);
+  // O^dagger 1 needs a vector of ones
+  const int64_t s = int64_t(b.y) * 256 + threadIdx.x;
+  if (s < J.n) {
+    if (C) {
+      J.ones[2 * s] = 1.0;
+      J.ones[2 * s + 1] = 0.0;
+    } else {
+      J.ones[s] = 1.0;
+    }
+  }
+}
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_cg_init(const BJob<T> *jobs, const int2 *map) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_cg_init_body<T, C>(b.y, 0, 0, J.pblocks, J.N, J.M, J.n, J.epart2, J.nb, J.g, J.F, J.x, J.r,
+                       J.p, J.Vt, J.vb, J.va, J.dpart, J.st);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void kb_cg_start(const BJob<T> *jobs, double tol,
+                                                   int maxiter) {
+  const BJob<T> J = jobs[blockIdx.x];
+  k_cg_start_body(0, 0, 0, 1, J.dpart, J.pblocks, tol, maxiter, J.st);
+}
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_cg_ap(const BJob<T> *jobs, const int2 *map,
+                                                double lambda) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_cg_ap_body<C>(b.y, 0, 0, J.pblocks, J.N, J.M, J.n, 1, J.colsP, J.elems, J.out1, J.o1,
+                  J.ysum, J.nb, J.p, lambda, J.Ap, J.dpart, J.st);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void kb_cg_xr(const BJob<T> *jobs, const int2 *map,
+                                                int parity) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_cg_xr_body(b.y, 0, 0, J.cblocks, J.Pc, J.dpart, J.pblocks, parity, J.x, J.r, J.p, J.Ap,
+               J.rpart, J.st);
+}
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_cg_p(const BJob<T> *jobs, const int2 *map,
+                                               int parity, double tol, int maxiter) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_cg_p_body<T, C>(b.y, 0, 0, J.pblocks, J.N, J.M, J.rpart, J.cblocks, parity, tol, maxiter,
+                    J.r, J.p, J.Vt, J.vb, J.va, J.st);
+}
+// parameter update of the models whose energy and solve are finite
+template <typename T, typename PT>
+__global__ __launch_bounds__(256) void kb_update(const BJob<T> *jobs, const int2 *map,
+                                                 double lr) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  const CGState *st = J.st;
+  if (st->nonfinite || !finite(st->E[0]) || !finite(st->E[1]) || !finite(st->var)) return;
+  k_update_body<PT>(b.y, 0, 0, J.cblocks, J.Pc, (PT *)J.params, J.x, lr);
+}
+
+struct BLayout {
+  size_t Tm, Vt, vb, va, ypart, part, out1, y, ysum, u, ones, epart, epart2, o1, g, F, x, r, p, Ap,
+      dpart, rpart, state, total;
+};
+
+BLayout batch_layout(const nqs_model *m, int64_t n) {
+  const int cs = m->is_complex ? 2 : 1;
+  const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+  const int64_t nb = cdiv(n, 256);
+  const int64_t pb = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
+  const int64_t cb = cdiv(P * cs, 256) < 4096 ? cdiv(P * cs, 256) : 4096;
+  const BatchGradSizes z = batch_grad_sizes(m, n);
+  BLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  L.Tm = take(z.Tm);
+  L.Vt = take(z.Vt);
+  L.vb = take(z.vb);
+  L.va = take(z.va);
+  L.ypart = take(z.ypart);
+  L.part = take(z.part);
+  L.out1 = take(z.out1);
+  L.y = take(size_t(n) * cs * 8);
+  L.ysum = take(size_t(nb) * 16);
+  L.u = take(size_t(n) * cs * 8);
+  L.ones = take(size_t(n) * cs * 8);
+  L.epart = take(size_t(nb) * 16);
+  L.epart2 = take(size_t(nb) * 8);
+  L.o1 = take(size_t(P) * cs * 8);
+  L.g = take(size_t(P) * cs * 8);
+  L.F = take(size_t(P) * cs * 8);
+  L.x = take(size_t(P) * cs * 8);
+  L.r = take(size_t(P) * cs * 8);
+  L.p = take(size_t(P) * cs * 8);
+  L.Ap = take(size_t(P) * cs * 8);
+  L.dpart = take(size_t(pb) * 8);
+  L.rpart = take(size_t(cb) * 8);
+  L.state = take(sizeof(CGState));
+  L.total = off;
+  return L;
+}
+
+// job-table slots of the batch handle used by the SR step
+enum { kSlotJobs = 0, kSlotStats, kSlotP, kSlotC, kSlotStart, kSlotTanh = 10, kSlotJvp = 12,
+       kSlotVjp1 = 16, kSlotVjpU = 20, kSlotVjpY = 24 };
+
+template <typename T, bool C>
+nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, const void *eloc,
+                         const int64_t *n_samples, double lr, double diag_shift, double cg_tol,
+                         int cg_maxiter, void *ws, nqs_sr_info *info, hipStream_t st) {
+  typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type PT;
+  const int K = b->K;
+  const int cs = C ? 2 : 1;
+  std::vector<BJob<T>> jobs(K);
+  std::vector<BatchGradItem> gi(K);
+  std::vector<const void *> pk(K);
+  std::vector<int2> map_s, map_p, map_c;
+  std::vector<CGState *> states(K);
+  size_t wo = 0, po = 0, so = 0, eo = 0;
+  for (int k = 0; k < K; ++k) {
+    const nqs_model *m = b->models[k];
+    const int64_t n = n_samples[k];
+    const BLayout L = batch_layout(m, n);
+    char *w = (char *)ws + wo;
+    const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+    BJob<T> &J = jobs[k];
+    J.N = m->N;
+    J.M = m->M;
+    J.n = n;
+    J.P = P;
+    J.Pc = P * cs;
+    J.nb = cdiv(n, 256);
+    J.pblocks = int(cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096);
+    J.cblocks = int(cdiv(P * cs, 256) < 4096 ? cdiv(P * cs, 256) : 4096);
+    const BatchGradSizes z = batch_grad_sizes(m, n);
+    J.colsP = z.colsP;
+    J.elems = z.elems;
+    J.e = (const double *)((const char *)eloc + eo);
+    J.epart = (double *)(w + L.epart);
+    J.epart2 = (double *)(w + L.epart2);
+    J.u = (double *)(w + L.u);
+    J.ones = (double *)(w + L.ones);
+    J.g = (double *)(w + L.g);
+    J.F = (double *)(w + L.F);
+    J.x = (double *)(w + L.x);
+    J.r = (double *)(w + L.r);
+    J.p = (double *)(w + L.p);
+    J.Ap = (double *)(w + L.Ap);
+    J.o1 = (double *)(w + L.o1);
+    J.dpart = (double *)(w + L.dpart);
+    J.rpart = (double *)(w + L.rpart);
+    J.out1 = (const double *)(w + L.out1);
+    J.ysum = (const double *)(w + L.ysum);
+    J.Vt = (T *)(w + L.Vt);
+    J.vb = (T *)(w + L.vb);
+    J.va = (double *)(w + L.va);
+    J.params = (char *)params + po;
+    J.st = (CGState *)(w + L.state);
+    states[k] = J.st;
+    pk[k] = J.params;
+    BatchGradItem &G = gi[k];
+    G.m = m;
+    G.n = n;
+    G.sigma = samples + so;
+    G.Tm = w + L.Tm;
+    G.Vt = w + L.Vt;
+    G.vb = w + L.vb;
+    G.va = (double *)(w + L.va);
+    G.ypart = (double *)(w + L.ypart);
+    G.y = (double *)(w + L.y);
+    G.ysum = (double *)(w + L.ysum);
+    G.u = nullptr;
+    G.part = w + L.part;
+    G.out1 = (double *)(w + L.out1);
+    G.out = nullptr;
+    G.skip = nullptr;
+    for (int x = 0; x < int(J.nb); ++x) map_s.push_back(make_int2(k, x));
+    for (int x = 0; x < J.pblocks; ++x) map_p.push_back(make_int2(k, x));
+    for (int x = 0; x < J.cblocks; ++x) map_c.push_back(make_int2(k, x));
+    wo += L.total;
+    po += size_t(P) * cs * (std::is_same<T, double>::value ? 8 : 4);
+    so += size_t(n) * m->N;
+    eo += size_t(n) * cs * 8;
+  }
+  hipError_t e;
+#define BTRY(x)                            \
+  do {                                     \
+    if ((e = (x)) != hipSuccess) return NQS_EDEVICE; \
+  } while (0)
+  BTRY(b->buf(kSlotJobs).upload(jobs.data(), jobs.size() * sizeof(BJob<T>), st));
+  BTRY(b->buf(kSlotStats).upload(map_s.data(), map_s.size() * sizeof(int2), st));
+  BTRY(b->buf(kSlotP).upload(map_p.data(), map_p.size() * sizeof(int2), st));
+  BTRY(b->buf(kSlotC).upload(map_c.data(), map_c.size() * sizeof(int2), st));
+  if (!b->buf(kSlotJobs).d || !b->buf(kSlotStats).d || !b->buf(kSlotP).d || !b->buf(kSlotC).d)
+    return NQS_EDEVICE;
+  const BJob<T> *dj = (const BJob<T> *)b->buf(kSlotJobs).d;
+  const int2 *ms = (const int2 *)b->buf(kSlotStats).d;
+  const int2 *mp = (const int2 *)b->buf(kSlotP).d;
+  const int2 *mc = (const int2 *)b->buf(kSlotC).d;
+
+  BTRY(launch_tables_batch(b, pk, st));
+  hipLaunchKernelGGL((kb_stats1<T, C>), dim3(unsigned(map_s.size())), dim3(256), 0, st, dj, ms);
+  BTRY(hipGetLastError());
+  hipLaunchKernelGGL((kb_stats2<T, C>), dim3(unsigned(map_s.size())), dim3(256), 0, st, dj, ms);
+  BTRY(hipGetLastError());
+  BTRY(launch_theta_tanh_batch(b, gi, kSlotTanh, st));
+  // O^dagger 1 and the force numerator g = O^dagger (E - E)
+  for (int k = 0; k < K; ++k) {
+    gi[k].u = jobs[k].ones;
+    gi[k].out = jobs[k].o1;
+  }
+  BTRY(launch_vjp_batch(b, gi, true, kSlotVjp1, st));
+  for (int k = 0; k < K; ++k) {
+    gi[k].u = jobs[k].u;
+    gi[k].out = jobs[k].g;
+  }
+  BTRY(launch_vjp_batch(b, gi, true, kSlotVjpU, st));
+  hipLaunchKernelGGL((kb_cg_init<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj, mp);
+  BTRY(hipGetLastError());
+  hipLaunchKernelGGL((kb_cg_start<T>), dim3(unsigned(K)), dim3(256), 0, st, dj, cg_tol,
+                     cg_maxiter);
+  BTRY(hipGetLastError());
+  // CG products: y = O p, then O^dagger y into the tile sums read by kb_cg_ap
+  for (int k = 0; k < K; ++k) {
+    gi[k].u = gi[k].y;
+    gi[k].out = nullptr;
+    gi[k].skip = &states[k]->done;
+  }
+  std::vector<CGState> hs(K);
+  const int check_every = 8;
+  int launched = 0;
+  while (true) {
+    for (int k = 0; k < K; ++k)
+      BTRY(hipMemcpyAsync(&hs[k], states[k], sizeof(CGState), hipMemcpyDeviceToHost, st));
+    BTRY(hipStreamSynchronize(st));
+    bool all_done = true;
+    for (int k = 0; k < K; ++k) all_done = all_done && hs[k].done;
+    if (all_done || launched >= cg_maxiter) break;
+    const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
+    for (int q = 0; q < batch; ++q, ++launched) {
+      const int parity = launched & 1;
+      BTRY(launch_jvp_batch(b, gi, kSlotJvp, st));
+      BTRY(launch_vjp_batch(b, gi, false, kSlotVjpY, st));
+      hipLaunchKernelGGL((kb_cg_ap<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj,
+                         mp, diag_shift);
+      BTRY(hipGetLastError());
+      hipLaunchKernelGGL((kb_cg_xr<T>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj, mc,
+                         parity);
+      BTRY(hipGetLastError());
+      hipLaunchKernelGGL((kb_cg_p<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj, mp,
+                         parity, cg_tol, cg_maxiter);
+      BTRY(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL((kb_update<T, PT>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj, mc,
+                     lr);
+  BTRY(hipGetLastError());
+  BTRY(hipStreamSynchronize(st));
+#undef BTRY
+  bool any_nonfinite = false, all_conv = true;
+  for (int k = 0; k < K; ++k) {
+    const CGState &h = hs[k];
+    const bool nf = h.nonfinite || !std::isfinite(h.E[0]) || !std::isfinite(h.var);
+    any_nonfinite = any_nonfinite || nf;
+    all_conv = all_conv && h.converged;
+    if (info) {
+      info[k].cg_iters = h.iters;
+      info[k].converged = h.converged;
+      info[k].cg_resid = h.bnorm > 0 ? sqrt(h.rr[h.iters & 1]) / h.bnorm : 0.0;
+      info[k].energy_re = h.E[0];
+      info[k].energy_im = h.E[1];
+      info[k].variance = h.var;
+      info[k].force_norm = h.fnorm;
+    }
+  }
+  if (any_nonfinite) return NQS_ENONFINITE;
+  return all_conv ? NQS_OK : NQS_ENOTCONV;
+}
+
 }  // namespace
 
 size_t sr_workspace_bytes(const nqs_model *m, int64_t n) { return sr_layout(m, n).total; }
@@ -688,4 +1003,27 @@ nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const v
   if (use_double(m)) return m->is_complex ? NQS_SR(double, true) : NQS_SR(double, false);
   return m->is_complex ? NQS_SR(float, true) : NQS_SR(float, false);
 #undef NQS_SR
+}
+
+size_t batch_sr_workspace_bytes(nqs_batch *b, const int64_t *n_samples) {
+  size_t total = 0;
+  for (int k = 0; k < b->K; ++k) total += batch_layout(b->models[k], n_samples[k]).total;
+  return total;
+}
+
+nqs_status batch_sr_step_impl(nqs_batch *b, void *params, const int8_t *samples,
+                              const void *eloc, const int64_t *n_samples, double lr,
+                              double diag_shift, double cg_tol, int cg_maxiter, void *ws,
+                              size_t ws_bytes, nqs_sr_info *info, hipStream_t st) {
+  if (ws_bytes < batch_sr_workspace_bytes(b, n_samples)) return NQS_ENOMEM;
+  const nqs_model *m = b->models[0];
+  if (use_double(m))
+    return m->is_complex ? batch_sr_impl<double, true>(b, params, samples, eloc, n_samples, lr,
+                                                       diag_shift, cg_tol, cg_maxiter, ws, info, st)
+                         : batch_sr_impl<double, false>(b, params, samples, eloc, n_samples, lr,
+                                                        diag_shift, cg_tol, cg_maxiter, ws, info, st);
+  return m->is_complex ? batch_sr_impl<float, true>(b, params, samples, eloc, n_samples, lr,
+                                                    diag_shift, cg_tol, cg_maxiter, ws, info, st)
+                       : batch_sr_impl<float, false>(b, params, samples, eloc, n_samples, lr,
+                                                     diag_shift, cg_tol, cg_maxiter, ws, info, st);
 }

@@ -98,3 +98,52 @@ def test_batch_mixed_models_fp64(lib):
     kinds = [("tfim", 10, 1, False, 1.0, 1), ("heis", 12, 1, False, 0.0, 3),
              ("heis", 4, 2, True, 0.5, 4)]
     check_batch(lib, kinds, 0, True, [5, 17, 8], 1e-12, 1e-10)
+
+
+def check_batch_sr(lib, kinds, prec, cplx, n_list, fp64):
+    from oracle import rbm as orbm, sr as osr
+    from test_gpu_parity import cg_sensitivity
+    b, specs, oracles = make(lib, kinds, prec, cplx)
+    ps = params_of(oracles, cplx, prec, seed=200)
+    ss, els = [], []
+    for k, om in enumerate(oracles):
+        s = synth.spin_configs(n_list[k], om.n_sites, 300 + k,
+                               zero_magnetisation=(om.move == oh.MOVE_EXCHANGE))
+        pe = ps[k].astype(np.complex128 if cplx else np.float64)
+        ss.append(s)
+        els.append(oh.local_energy(om, pe, s))
+    pt = to_dev(np.concatenate(ps))
+    infos = b.sr_step(pt, to_dev(np.concatenate([s.reshape(-1) for s in ss])),
+                      to_dev(np.concatenate(els)), n_list, lr=0.05, diag_shift=0.01, cg_tol=0.0,
+                      cg_maxiter=12)
+    got = pt.cpu().numpy()
+    off = 0
+    for k, om in enumerate(oracles):
+        P = b.n_params[k]
+        pe = ps[k].astype(np.complex128 if cplx else np.float64)
+        p_new, io = osr.sr_step(om, pe, ss[k], els[k], lr=0.05, diag_shift=0.01, cg_tol=0.0,
+                                cg_maxiter=12)
+        assert infos[k]["cg_iters"] == io["iters"] == 12
+        assert abs(infos[k]["energy_re"] - np.real(io["energy"])) <= 1e-10 * max(1, abs(io["energy"]))
+        step_o = p_new - pe
+        step_g = got[off:off + P].astype(pe.dtype) - pe
+        if fp64:
+            O = orbm.log_derivatives(pe, ss[k], om.n_sites, om.n_hidden)
+            if not cplx:
+                O = O.real
+            tol = max(1e-9, 10 * cg_sensitivity(O, els[k], 0.01, 12))
+            assert np.abs(step_g - step_o).max() <= tol * np.abs(step_o).max(), k
+        else:
+            assert np.abs(step_g - step_o).max() <= 1e-4 * np.abs(step_o).max() + 1e-7, k
+        off += P
+
+
+def test_batch_sr_mixed_models_fp64(lib):
+    kinds = [("tfim", 10, 1, False, 1.0, 1), ("heis", 12, 1, False, 0.0, 3),
+             ("heis", 4, 2, True, 0.5, 4)]
+    check_batch_sr(lib, kinds, 0, True, [300, 411, 257], True)
+
+
+def test_batch_sr_tfim_uneven_fp32(lib):
+    kinds = [("tfim", L, 1, False, h, 2) for L, h in [(16, 0.6), (23, 1.4), (40, 1.0), (64, 0.8)]]
+    check_batch_sr(lib, kinds, 1, False, [512, 300, 640, 257], False)
