@@ -143,6 +143,132 @@ def copy_probe(torch, dev, mib=1024, reps=3):
     log("copy probe: %d copies of %d MiB" % (reps, mib))
 
 
+# batches of independent models: 64 periodic TFIM rings, N uniform in [16, 128], h uniform in
+# [0.5, 1.5] (numpy PCG64, seed 1234), real FP32 RBM alpha = 2 each, 256 chains x 4 sweeps
+# per ring per step
+BATCH_WORKLOADS = {
+    "tfim1d_batch64_n16to128_real_fp32_alpha2": dict(K=64, Nmin=16, Nmax=128, hmin=0.5, hmax=1.5,
+                                                     alpha=2, chains=256, sweeps=4, prec=1,
+                                                     lr=0.01, shift=0.01, cg_tol=1e-8,
+                                                     cg_maxiter=500),
+}
+
+
+def batch_instances(w):
+    rng = np.random.default_rng(1234)
+    Ns = rng.integers(w["Nmin"], w["Nmax"] + 1, size=w["K"])
+    hs = rng.uniform(w["hmin"], w["hmax"], size=w["K"])
+    return [int(x) for x in Ns], [float(x) for x in hs]
+
+
+def batch_cpu_baseline(w, seconds=15.0):
+    """The FP64 oracle on a bounded sample of the batch: the first 8 rings, 16 chains x 4
+    sweeps each, their local energies, and one SR step where the ring's dense S fits."""
+    import synth
+    from oracle import hamiltonian as oh, lattice as ol, sampler as osamp, sr as osr
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    Ns, hs = batch_instances(w)
+    t0 = time.perf_counter()
+    total, passes = 0, 0
+    while time.perf_counter() - t0 < seconds:
+        for k in range(8):
+            N, M = Ns[k], w["alpha"] * Ns[k]
+            ob, _ = ol.hypercube(N, 1)
+            om = oh.Model(N, M, ob, ham=oh.TFIM, J=(1.0, 0.0), h=hs[k], move=oh.MOVE_FLIP)
+            p = synth.rbm_params(N, M, False, sigma=0.01, seed=1234 + k)
+            init = osamp.init_chains(om, 16, seed=1234 ^ k)
+            smp, _, _ = osamp.sample(om, p, init, 4, 0, seed=1234 ^ k, counter=0)
+            flat = smp.reshape(-1, N)
+            el = oh.local_energy(om, p, flat)
+            if N + M + N * M <= 5000:
+                osr.sr_step(om, p, flat, el, w["lr"], w["shift"], w["cg_tol"], w["cg_maxiter"])
+            total += flat.shape[0]
+        passes += 1
+    dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "samples/s", "cores": int(cores), "kind": "oracle",
+            "sample": "first 8 rings of the batch, 16 chains x 4 sweeps each, local energies, and "
+                      "one SR step for rings with at most 5000 parameters; %d passes in %.1f s"
+                      % (passes, dt)}
+
+
+def bench_batch(args, nqs, synth, torch, name):
+    w = BATCH_WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    Ns, hs = batch_instances(w)
+    specs = []
+    for N, h in zip(Ns, hs):
+        bonds, sub = nqs.nqs_hypercube(N, 1)
+        specs.append(dict(n_sites=N, n_hidden=w["alpha"] * N, bonds=bonds, ham=nqs.TFIM,
+                          J=(1.0, 0.0), h=h, move=nqs.MOVE_FLIP, is_complex=False, prec=w["prec"]))
+    b = nqs.Batch(specs)
+    params = torch.from_numpy(np.concatenate(
+        [synth.rbm_params(N, w["alpha"] * N, False, sigma=0.01, seed=1234 + k).astype(np.float32)
+         for k, N in enumerate(Ns)])).to(dev)
+    C, S = w["chains"], w["sweeps"]
+    nch = [C] * w["K"]
+    ns = [C * S] * w["K"]
+    spins = sum(C * N for N in Ns)
+    chains = torch.empty(spins, dtype=torch.int8, device=dev)
+    b.chain_init(chains, nch, seed=1234)
+    samples = torch.empty(S * spins, dtype=torch.int8, device=dev)
+    eloc = torch.empty(S * C * w["K"], dtype=torch.float64, device=dev)
+    ws = torch.empty(b.sr_workspace_bytes(ns), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    counter = [0]
+
+    def step(discard):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.sample(params, chains, nch, S, discard, seed=1234, counter=counter[0], samples=samples,
+                 eloc=eloc)
+        e1.record(stream)
+        counter[0] += S + discard
+        infos = b.sr_step(params, samples, eloc, ns, w["lr"], w["shift"], w["cg_tol"],
+                          w["cg_maxiter"], workspace=ws)
+        return infos, (e0, e1)
+
+    for k in range(args.warmup):
+        infos, _ = step(10 if k == 0 else 0)
+        log("warmup step %d: max cg_iters %d" % (k, max(i["cg_iters"] for i in infos)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs, iters = [], []
+    for k in range(args.steps):
+        infos, ev = step(0)
+        evs.append(ev)
+        iters.append(max(i["cg_iters"] for i in infos))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    samp_ms = sum(a.elapsed_time(c) for a, c in evs) / args.steps
+    n_samp = C * S * w["K"]
+    flops = float(sum(C * S * N * (w["alpha"] * N) * 4 for N in Ns))
+    ach = flops / (samp_ms * 1e-3)
+    out = {
+        "metric": "samples/s (sweep+E_loc+O_k) and SR iters/s, BF16/FP32 vs FP64 at fixed dE",
+        "value": n_samp / (ms_per_step * 1e-3), "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "instances": w["K"], "n_sites_min": min(Ns),
+                   "n_sites_max": max(Ns), "chains_per_instance": C, "sweeps_per_step": S,
+                   "samples_per_step": n_samp, "cg_tol": w["cg_tol"]},
+        "sr_iters_per_s": 1e3 / ms_per_step,
+        "phase_ms": {"sample_and_eloc": samp_ms, "sr_step": ms_per_step - samp_ms},
+        "cg_iters_max_mean": float(np.mean(iters)),
+        "roofline": {"kernel": "batched sweep with fused local energies (one launch)",
+                     "bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batch_cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out))
+
+
 # exact ground energies of the workloads (Pauli units): Bethe ansatz for the 40-site
 # Heisenberg ring, free-fermion closed form for the 10-site TFIM ring
 E_REF = {"heisenberg1d_n40_cplx_fp32_alpha2": -70.98609115333286,
@@ -228,7 +354,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="heisenberg1d_n40_cplx_fp32_alpha2", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="heisenberg1d_n40_cplx_fp32_alpha2",
+                    choices=list(WORKLOADS) + list(BATCH_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sv-pairs", type=int, default=0, choices=[0, 2, 4],
@@ -253,6 +380,8 @@ def main():
     if args.copy_probe:
         copy_probe(torch, torch.device("cuda:0"))
     log("library loaded, building workload " + args.workload)
+    if args.workload in BATCH_WORKLOADS:
+        return bench_batch(args, nqs, synth, torch, args.workload)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     N = w["L"] ** w["ndim"]
