@@ -70,49 +70,71 @@ __global__ void k_prep_dir(int N, int M, const double *__restrict__ v, T *Vt, T 
 // T[s][j] = tanh(b_j + sum_i W_ji s_si): theta tile by MFMA (A = spins, B = W^T), tanh in
 // the epilogue. Grid (ceil(n/64), hidden chunks of JT tiles); 16 samples per wavefront.
 // ---------------------------------------------------------------------------------
+// hidden tiles per block of the theta/tanh and JVP kernels (accumulators per wavefront):
+// 8 for real FP32, 4 otherwise
 template <typename T, bool C>
-__device__ __forceinline__ void k_theta_tanh_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n,
-                                                     const int8_t *__restrict__ sigma,
-                                                     const T *__restrict__ Wt,
-                                                     const T *__restrict__ bv, int JT, int quant,
-                                                     T *Tout) {
+struct Chunk {
+  static constexpr int JT = (sizeof(T) == 8 || C) ? 4 : 8;
+};
+
+template <typename T, bool C>
+__device__ __forceinline__ void k_theta_tanh_body(int BX, int BY, int BZ, int GX, int N, int M,
+                                                  int64_t n, const int8_t *__restrict__ sigma,
+                                                  const T *__restrict__ Wt,
+                                                  const T *__restrict__ bv, int quant, T *Tout) {
   typedef typename MF<T>::acc Acc;
+  constexpr int JT = Chunk<T, C>::JT;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
   const int64_t s0 = int64_t(BX) * 64 + wid * 16;
-  const int ntiles = (M + 15) / 16;
   const int jt0 = BY * JT;
-  const int jt1 = jt0 + JT < ntiles ? jt0 + JT : ntiles;
   const int64_t rowA = s0 + lo;
   const bool rowA_ok = rowA < n;
   const int8_t *srow = sigma + (rowA_ok ? rowA : 0) * N;
-  for (int jt = jt0; jt < jt1; ++jt) {
-    const int j = jt * 16 + lo;
-    const bool jok = j < M;
-    Acc tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < N; k0 += 4) {
-      const int k = k0 + hi;
-      const bool kok = k < N;
-      const T a = (rowA_ok && kok) ? T(srow[k]) : T(0);
-      V<T, C> w = vmake<T, C>(T(0), T(0));
-      if (kok && jok) w = vload<T, C>(Wt, int64_t(k) * M + j);
-      tr = MF<T>::mma(a, w.re, tr);
-      if constexpr (C) ti = MF<T>::mma(a, w.im, ti);
-    }
-    if (jok) {
-      const V<T, C> bb = vload<T, C>(bv, j);
+  Acc tr[JT], ti[JT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = s0 + MF<T>::row(hi, r);
-        if (row < n) {
-          V<T, C> th = vmake<T, C>(tr[r] + bb.re, C ? ti[r] + bb.im : T(0));
-          V<T, C> tv = vtanh<T, C>(th);
-          if (quant) {  // BF16 form: the Jacobian contractions see bfloat16 tanh(theta)
-            tv.re = T(bf16_round(float(tv.re)));
-            if (C) tv.im = T(bf16_round(float(tv.im)));
-          }
-          vstore<T, C>(Tout, row * M + j, tv);
+  for (int a = 0; a < JT; ++a) {
+    tr[a] = Acc{0, 0, 0, 0};
+    ti[a] = Acc{0, 0, 0, 0};
+  }
+  // k outer, tiles inner: the A operand and the JT weight loads of a step are issued
+  // together (clamped addresses, selects instead of branches)
+#pragma unroll 2
+  for (int k0 = 0; k0 < N; k0 += 4) {
+    const int k = k0 + hi;
+    const bool kok = k < N;
+    const int8_t sv = srow[kok ? k : 0];
+    const T a = (rowA_ok && kok) ? T(sv) : T(0);
+    V<T, C> w[JT];
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      const int j = (jt0 + q) * 16 + lo;
+      const bool ok = kok && j < M;
+      const V<T, C> x = vload<T, C>(Wt, ok ? int64_t(k) * M + j : 0);
+      w[q] = ok ? x : vmake<T, C>(T(0), T(0));
+    }
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      tr[q] = MF<T>::mma(a, w[q].re, tr[q]);
+      if constexpr (C) ti[q] = MF<T>::mma(a, w[q].im, ti[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < JT; ++q) {
+    const int j = (jt0 + q) * 16 + lo;
+    if (j >= M) continue;
+    const V<T, C> bb = vload<T, C>(bv, j);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = s0 + MF<T>::row(hi, r);
+      if (row < n) {
+        V<T, C> th = vmake<T, C>(tr[q][r] + bb.re, C ? ti[q][r] + bb.im : T(0));
+        V<T, C> tv = vtanh<T, C>(th);
+        if (quant) {  // BF16 form: the Jacobian contractions see bfloat16 tanh(theta)
+          tv.re = T(bf16_round(float(tv.re)));
+          if (C) tv.im = T(bf16_round(float(tv.im)));
         }
+        vstore<T, C>(Tout, row * M + j, tv);
       }
     }
   }
@@ -122,9 +144,9 @@ template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
                                                      const int8_t *__restrict__ sigma,
                                                      const T *__restrict__ Wt,
-                                                     const T *__restrict__ bv, int JT, int quant,
+                                                     const T *__restrict__ bv, int quant,
                                                      T *Tout) {
-  k_theta_tanh_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, sigma, Wt, bv, JT, quant, Tout);
+  k_theta_tanh_body<T, C>(blockIdx.x, blockIdx.y, 0, 0, N, M, n, sigma, Wt, bv, quant, Tout);
 }
 
 // ---------------------------------------------------------------------------------
@@ -132,54 +154,73 @@ __global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
 // Grid (ceil(n/64), hidden chunks). Writes ypart[chunk][s] (complex double).
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
-__device__ __forceinline__ void k_jvp_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n,
-                                              const int8_t *__restrict__ sigma,
-                                              const T *__restrict__ Tm,
-                                              const T *__restrict__ Vt, const T *__restrict__ vb,
-                                              const double *__restrict__ va, int JT,
-                                              double *ypart, const int *skip) {
+__device__ __forceinline__ void k_jvp_body(int BX, int BY, int BZ, int GX, int N, int M,
+                                           int64_t n, const int8_t *__restrict__ sigma,
+                                           const T *__restrict__ Tm, const T *__restrict__ Vt,
+                                           const T *__restrict__ vb,
+                                           const double *__restrict__ va, double *ypart,
+                                           const int *skip) {
   if (skip && *skip) return;
   typedef typename MF<T>::acc Acc;
+  constexpr int JT = Chunk<T, C>::JT;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
   const int64_t s0 = int64_t(BX) * 64 + wid * 16;
   const int jc = BY;
-  const int ntiles = (M + 15) / 16;
   const int jt0 = jc * JT;
-  const int jt1 = jt0 + JT < ntiles ? jt0 + JT : ntiles;
   const int64_t rowA = s0 + lo;
   const bool rowA_ok = rowA < n;
   const int8_t *srow = sigma + (rowA_ok ? rowA : 0) * N;
-  V<T, C> yp[4];
+  // the T entries of every tile are loaded first; they arrive during the contraction
+  V<T, C> tv[JT][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) yp[r] = vmake<T, C>(T(0), T(0));
-  for (int jt = jt0; jt < jt1; ++jt) {
-    const int j = jt * 16 + lo;
-    const bool jok = j < M;
-    // issue the loads of this tile's T entries before the contraction
-    V<T, C> tv[4];
+  for (int q = 0; q < JT; ++q) {
+    const int j = (jt0 + q) * 16 + lo;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = s0 + MF<T>::row(hi, r);
-      tv[r] = (jok && row < n) ? vload<T, C>(Tm, row * M + j) : vmake<T, C>(T(0), T(0));
+      const bool ok = j < M && row < n;
+      const V<T, C> x = vload<T, C>(Tm, ok ? row * M + j : 0);
+      tv[q][r] = ok ? x : vmake<T, C>(T(0), T(0));
     }
-    Acc xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < N; k0 += 4) {
-      const int k = k0 + hi;
-      const bool kok = k < N;
-      const T a = (rowA_ok && kok) ? T(srow[k]) : T(0);
-      V<T, C> v = vmake<T, C>(T(0), T(0));
-      if (kok && jok) v = vload<T, C>(Vt, int64_t(k) * M + j);
-      xr = MF<T>::mma(a, v.re, xr);
-      if constexpr (C) xi = MF<T>::mma(a, v.im, xi);
-    }
-    if (jok) {
-      const V<T, C> vbj = vload<T, C>(vb, j);
+  }
+  Acc xr[JT], xi[JT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        V<T, C> x = vmake<T, C>(xr[r] + vbj.re, C ? xi[r] + vbj.im : T(0));
-        yp[r] = vadd(yp[r], vmul(tv[r], x));
-      }
+  for (int q = 0; q < JT; ++q) {
+    xr[q] = Acc{0, 0, 0, 0};
+    xi[q] = Acc{0, 0, 0, 0};
+  }
+#pragma unroll 2
+  for (int k0 = 0; k0 < N; k0 += 4) {
+    const int k = k0 + hi;
+    const bool kok = k < N;
+    const int8_t sv = srow[kok ? k : 0];
+    const T a = (rowA_ok && kok) ? T(sv) : T(0);
+    V<T, C> v[JT];
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      const int j = (jt0 + q) * 16 + lo;
+      const bool ok = kok && j < M;
+      const V<T, C> x = vload<T, C>(Vt, ok ? int64_t(k) * M + j : 0);
+      v[q] = ok ? x : vmake<T, C>(T(0), T(0));
+    }
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      xr[q] = MF<T>::mma(a, v[q].re, xr[q]);
+      if constexpr (C) xi[q] = MF<T>::mma(a, v[q].im, xi[q]);
+    }
+  }
+  V<T, C> yp[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) yp[r] = vmake<T, C>(T(0), T(0));
+#pragma unroll
+  for (int q = 0; q < JT; ++q) {
+    const int j = (jt0 + q) * 16 + lo;
+    const V<T, C> vbj = j < M ? vload<T, C>(vb, j) : vmake<T, C>(T(0), T(0));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      V<T, C> x = vmake<T, C>(xr[q][r] + vbj.re, C ? xi[q][r] + vbj.im : T(0));
+      yp[r] = vadd(yp[r], vmul(tv[q][r], x));
     }
   }
 #pragma unroll
@@ -214,9 +255,9 @@ __global__ __launch_bounds__(256) void k_jvp(int N, int M, int64_t n,
                                               const int8_t *__restrict__ sigma,
                                               const T *__restrict__ Tm,
                                               const T *__restrict__ Vt, const T *__restrict__ vb,
-                                              const double *__restrict__ va, int JT,
-                                              double *ypart, const int *skip) {
-  k_jvp_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, sigma, Tm, Vt, vb, va, JT, ypart, skip);
+                                              const double *__restrict__ va, double *ypart,
+                                              const int *skip) {
+  k_jvp_body<T, C>(blockIdx.x, blockIdx.y, 0, 0, N, M, n, sigma, Tm, Vt, vb, va, ypart, skip);
 }
 
 // y[s] = sum over chunks; per-block partial sums of y (complex double) for centering
@@ -1019,7 +1060,7 @@ hipError_t tanh_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scra
   char *base = (char *)scratch;
   hipLaunchKernelGGL((k_theta_tanh<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256),
                      0, st, m->N, m->M, n, sigma, (const T *)m->tab_ptrs[0],
-                     (const T *)m->tab_ptrs[1], 16, int(for_grad && m->prec == NQS_BF16),
+                     (const T *)m->tab_ptrs[1], int(for_grad && m->prec == NQS_BF16),
                      (T *)(base + L.Tm));
   if (g.pair) {
     hipError_t e = hipGetLastError();
@@ -1038,7 +1079,7 @@ hipError_t jvp_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scrat
   char *base = (char *)scratch;
   hipLaunchKernelGGL((k_jvp<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256), 0, st,
                      m->N, m->M, n, sigma, (const T *)(base + L.Tm), (const T *)(base + L.Vt),
-                     (const T *)(base + L.vb), (const double *)(base + L.va), 16,
+                     (const T *)(base + L.vb), (const double *)(base + L.va),
                      (double *)(base + L.ypart), skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1236,8 +1277,7 @@ template <typename T, bool C>
 __global__ __launch_bounds__(256) void kb_theta_tanh(const TanhJob<T> *jobs, const int4 *map) {
   const int4 b = map[blockIdx.x];
   const TanhJob<T> J = jobs[b.x];
-  k_theta_tanh_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Wt, J.bv, 16, J.quant,
-                          J.Tout);
+  k_theta_tanh_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Wt, J.bv, J.quant, J.Tout);
 }
 
 template <typename T>
@@ -1255,7 +1295,7 @@ template <typename T, bool C>
 __global__ __launch_bounds__(256) void kb_jvp(const JvpJob<T> *jobs, const int4 *map) {
   const int4 b = map[blockIdx.x];
   const JvpJob<T> J = jobs[b.x];
-  k_jvp_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Tm, J.Vt, J.vb, J.va, 16, J.ypart,
+  k_jvp_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Tm, J.Vt, J.vb, J.va, J.ypart,
                    J.skip);
 }
 template <typename T, bool C>
@@ -1324,7 +1364,7 @@ hipError_t tanh_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, i
     TanhJob<T> J{m->N, m->M, it.n, it.sigma, (const T *)m->tab_ptrs[0], (const T *)m->tab_ptrs[1],
                  int(m->prec == NQS_BF16), (T *)it.Tm};
     jobs.push_back(J);
-    const int gx = int(cdiv(it.n, 64)), gy = int(cdiv((m->M + 15) / 16, 16));
+    const int gx = int(cdiv(it.n, 64)), gy = int(cdiv((m->M + 15) / 16, Chunk<T, C>::JT));
     for (int y = 0; y < gy; ++y)
       for (int x = 0; x < gx; ++x) map.push_back(make_int4(int(k), x, y, 0));
   }
@@ -1343,7 +1383,7 @@ hipError_t jvp_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, in
   for (size_t k = 0; k < items.size(); ++k) {
     const BatchGradItem &it = items[k];
     const nqs_model *m = it.m;
-    const int jchunks = int(cdiv((m->M + 15) / 16, 16));
+    const int jchunks = int(cdiv((m->M + 15) / 16, Chunk<T, C>::JT));
     JvpJob<T> J{m->N, m->M, it.n, it.sigma, (const T *)it.Tm, (const T *)it.Vt, (const T *)it.vb,
                 it.va, it.ypart, it.y, it.ysum, jchunks, it.skip};
     jobs.push_back(J);
@@ -1470,7 +1510,7 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
     g.splits = int(cdiv(n > 0 ? n : 1, g.per_split));
   }
   g.groups = g.splits < 16 ? g.splits : 16;
-  g.jchunks = int(cdiv((m->M + 15) / 16, 16));
+  g.jchunks = int(cdiv((m->M + 15) / 16, (use_double(m) || m->is_complex) ? 4 : 8));
   g.jvp_blocks = cdiv(n > 0 ? n : 1, 64);
   return g;
 }
@@ -1534,7 +1574,8 @@ BatchGradSizes batch_grad_sizes(const nqs_model *m, int64_t n) {
   z.Vt = size_t(m->N) * m->M * es;
   z.vb = size_t(m->M) * es;
   z.va = size_t(m->N) * 16;
-  z.ypart = size_t(cdiv((m->M + 15) / 16, 16)) * size_t(n) * 16;
+  z.ypart = size_t(cdiv((m->M + 15) / 16, (use_double(m) || m->is_complex) ? 4 : 8)) *
+            size_t(n) * 16;
   z.part = size_t(splits) * Jtiles * 16 * Itiles * 16 * es;
   z.out1 = size_t(Jtiles) * 16 * Itiles * 16 * 16;
   z.colsP = Itiles * 16;

@@ -128,7 +128,7 @@ struct GradPlan {
   bool fused;    // all VJP tiles fit one block: S v in one pass (k_sv)
   bool pair;     // fused, complex FP32 and N <= 63: plane-split pairs on spin masks (k_svc)
   int pairs;     // wavefront pairs per k_svc block
-  int jchunks;   // hidden chunks of 16 tiles in the JVP / tanh kernels (grid y)
+  int jchunks;   // hidden chunks (8 tiles FP32, 4 FP64) of the JVP / tanh kernels (grid y)
   int64_t jvp_blocks; // sample tiles of 64 in the JVP / tanh kernels
 };
 GradPlan grad_plan(const nqs_model *m, int64_t n);
