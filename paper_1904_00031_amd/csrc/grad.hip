@@ -635,29 +635,24 @@ __device__ __forceinline__ int svc_rows(int64_t send, int64_t g) {
   return left <= 0 ? 0 : (left < 16 ? int(left) : 16);
 }
 
-// masks (A operand rows lo, accumulator rows MF::row(hi, q)) and T rows of one group.
-// Loads are unconditional with selects after them (no branches around loads). FULL: all
-// 16 rows valid. Otherwise rows outside the group read a valid row of the group (or row
-// 0) and are zeroed. Hidden tiles below JV - 1 are complete; tile JV - 1 reads columns
-// j >= M past the row end (next row, or the slack after T) and zeroes them; tiles from
-// JV on hold no hidden unit and are not loaded.
+// the spin mask of row lane / 4 and the T rows of one 16-sample group. Loads are
+// unconditional with selects after them (no branches around loads). FULL: all 16 rows
+// valid. Otherwise rows outside the group read a valid row of the group (or row 0) and
+// are zeroed. Hidden tiles below JV - 1 are complete; tile JV - 1 reads columns j >= M
+// past the row end (next row, or the slack after T) and zeroes them; tiles from JV on
+// hold no hidden unit and are not loaded.
 template <typename T, int JT, int JV, bool FULL>
 __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
                                          const T *__restrict__ Tm, int M, int64_t g,
-                                         int rows_here, int lo, int hi, uint64_t &mA,
-                                         uint64_t (&mB)[4], V<T, true> (&tv)[JT][4]) {
+                                         int rows_here, int lane, int lo, int hi,
+                                         uint64_t &mrow, bool &row_ok,
+                                         V<T, true> (&tv)[JT][4]) {
   const int64_t gc = FULL || rows_here > 0 ? g : 0;
   {
-    const bool ok = FULL || lo < rows_here;
-    const uint64_t x = masks[gc + (ok ? lo : 0)];
-    mA = ok ? x : 0ull;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int rr = MF<T>::row(hi, q);
-    const bool ok = FULL || rr < rows_here;
-    const uint64_t x = masks[gc + (ok ? rr : 0)];
-    mB[q] = ok ? x : 0ull;
+    const int rr = lane >> 2;
+    row_ok = FULL || rr < rows_here;
+    const uint64_t x = masks[gc + (row_ok ? rr : 0)];
+    mrow = row_ok ? x : 0ull;
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -676,6 +671,31 @@ __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
     }
   }
 }
+
+// The group's spins as floats in the wavefront's LDS tile [16][kSpinStride]: row rr,
+// column c holds s_c (+/-1) for c < N, 1 at c = N (the ones column of the bias
+// gradients), 0 beyond and in rows outside the group. Lane l writes row l / 4, columns
+// 16 (l % 4) .. 16 (l % 4) + 15.
+constexpr int kSpinStride = 66;  // 2-float skew per row: conflict-free A-operand reads
+template <typename T>
+__device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, bool row_ok, int N,
+                                              int lane) {
+  const int rr = lane >> 2, c0 = 16 * (lane & 3);
+  const uint32_t bits = uint32_t(mrow >> c0) & 0xffffu;
+  T *dst = tile + rr * kSpinStride + c0;
+#pragma unroll
+  for (int t = 0; t < 16; t += 2) {
+    T v2[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int c = c0 + t + u;
+      const T s = ((bits >> (t + u)) & 1u) ? T(1) : T(-1);
+      v2[u] = !row_ok ? T(0) : (c < N ? s : (c == N ? T(1) : T(0)));
+    }
+    *reinterpret_cast<float2 *>(dst + t) = make_float2(v2[0], v2[1]);
+  }
+}
+
 
 // ---------------------------------------------------------------------------------
 // Fused S v product for complex models with N <= 63 and all VJP tiles in one block.
@@ -708,6 +728,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   constexpr int VS = JW + ((JT & 1) ? 0 : 16);  // plane row stride: 16 banks apart per k
   constexpr int NVA = 4;                        // site columns per lane: lo + 16 c, N <= 63
   extern __shared__ __align__(16) unsigned char lds_u8[];
+  static_assert(sizeof(T) == 4, "spin tiles are float");
   constexpr int NTH = 128 * PAIRS;
   __shared__ T ybuf[2][PAIRS][2][16][2];  // [parity][pair][plane of origin][row][re, im]
   __shared__ T red[2 * PAIRS][4][64];
@@ -742,6 +763,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   }
   __syncthreads();
   const T *Vp = Vl + h * Kp * VS;
+  T *stile = Vl + 2 * Kp * VS + wid * 16 * kSpinStride;  // this wavefront's spin tile
   bool stalled = false;
   const int64_t sbeg = int64_t(blockIdx.x) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
@@ -756,29 +778,45 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   // the current group's O^dagger y contraction runs
   int64_t g = sbeg + 16 * pr;
   int rows_here = svc_rows(send, g);
-  uint64_t mA, mB[4];
+  uint64_t mrow;
+  bool row_ok;
   V<T, true> tv[JT][4];
   if (iters > 0) {
     if (rows_here == 16)
-      svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+      svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
     else
-      svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+      svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
   }
   for (int64_t it = 0; it < iters; ++it) {
+    // spins of the group into the tile (the previous group's reads are done: same wave)
+    svc_spin_tile<T>(stile, mrow, row_ok, N, lane);
+    wave_sync();
     // ---- X_h = S (plane h of V)^T over the valid hidden tiles ----
     Acc x[JT];
 #pragma unroll
     for (int a = 0; a < JT; ++a) x[a] = Acc{0, 0, 0, 0};
-#pragma unroll 2
-    for (int k0 = 0; k0 < Kp; k0 += 4) {
-      const int k = k0 + hi;
-      const T av = ((mA >> k) & 1ull) ? T(1) : T(-1);
-      T v[JT];
+    {
+      // operands of step k0 + 4 are read from LDS while the matrix cores work on k0
+      T av_n = stile[lo * kSpinStride + hi];
+      T v_n[JT];
 #pragma unroll
-      for (int a = 0; a < JT; ++a) v[a] = Vp[k * VS + a * 16 + lo];
+      for (int a = 0; a < JT; ++a) v_n[a] = a < JV ? Vp[hi * VS + a * 16 + lo] : T(0);
+      for (int k0 = 0; k0 < Kp; k0 += 4) {
+        const T av = av_n;
+        T v[JT];
 #pragma unroll
-      for (int a = 0; a < JT; ++a)
-        if (a < JV) x[a] = MF<T>::mma(av, v[a], x[a]);
+        for (int a = 0; a < JT; ++a) v[a] = v_n[a];
+        if (k0 + 4 < Kp) {
+          const int k = k0 + 4 + hi;
+          av_n = stile[lo * kSpinStride + k];
+#pragma unroll
+          for (int a = 0; a < JT; ++a)
+            if (a < JV) v_n[a] = Vp[k * VS + a * 16 + lo];
+        }
+#pragma unroll
+        for (int a = 0; a < JT; ++a)
+          if (a < JV) x[a] = MF<T>::mma(av, v[a], x[a]);
+      }
     }
     // ---- this plane's share of y for rows MF::row(hi, r) ----
     T yre[4], yim[4];
@@ -787,30 +825,36 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       yre[r] = T(0);
       yim[r] = T(0);
     }
+    // plane 1 works with i T = (-Im T, Re T): then both planes share the formulas
+    //   y += (Re, Im of the rotated T) (X_h + vb_h),  Z_h = Re' Re y + Im' Im y
+    if (__builtin_amdgcn_readfirstlane(h)) {
+#pragma unroll
+      for (int a = 0; a < JT; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tv[a][r] = vmake<T, true>(-tv[a][r].im, tv[a][r].re);
+    }
 #pragma unroll
     for (int a = 0; a < JT; ++a) {
       if (a >= JV) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const T xv = x[a][r] + vbl[h][a * 16 + lo];
-        if (h == 0) {
-          yre[r] += tv[a][r].re * xv;
-          yim[r] += tv[a][r].im * xv;
-        } else {
-          yre[r] -= tv[a][r].im * xv;
-          yim[r] += tv[a][r].re * xv;
-        }
+        yre[r] += tv[a][r].re * xv;
+        yim[r] += tv[a][r].im * xv;
       }
     }
     if (h == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r) {
+        const T *srow = stile + MF<T>::row(hi, r) * kSpinStride;
 #pragma unroll
         for (int c = 0; c < NVA; ++c) {
-          const T sgn = ((mB[r] >> (lo + 16 * c)) & 1ull) ? T(1) : T(-1);
+          // columns >= N of the tile are 1 (c = N) or 0, and val is 0 there
+          const T sgn = srow[lo + 16 * c];
           yre[r] += sgn * val[0][lo + 16 * c];
           yim[r] += sgn * val[1][lo + 16 * c];
         }
+      }
     }
     const int par = int(it & 1);
 #pragma unroll
@@ -860,15 +904,12 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     }
     // ---- plane h of Z = conj(T) y (row M: Z = y), then the next group's loads ----
     T z[4][JT];
-    uint64_t mq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      mq[q] = mB[q];
 #pragma unroll
       for (int a = 0; a < JT; ++a) {
         const int j = a * 16 + lo;
-        const T zq = h == 0 ? tv[a][q].re * yre[q] + tv[a][q].im * yim[q]
-                            : tv[a][q].re * yim[q] - tv[a][q].im * yre[q];
+        const T zq = tv[a][q].re * yre[q] + tv[a][q].im * yim[q];
         z[q][a] = (a == JT - 1 && j == M) ? (h == 0 ? yre[q] : yim[q]) : zq;
       }
     }
@@ -877,19 +918,16 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       g += 16 * PAIRS;
       rows_here = svc_rows(send, g);
       if (rows_here == 16)
-        svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+        svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
       else
-        svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lo, hi, mA, mB, tv);
+        svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
     }
     // ---- plane h of Z^T S over the 16 samples (step q: row MF::row(hi, q)) ----
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       T bs[NT];
 #pragma unroll
-      for (int b = 0; b < NT; ++b) {
-        const int c = b * 16 + lo;
-        bs[b] = c < N ? (((mq[q] >> c) & 1ull) ? T(1) : T(-1)) : (c == N ? T(1) : T(0));
-      }
+      for (int b = 0; b < NT; ++b) bs[b] = stile[MF<T>::row(hi, q) * kSpinStride + b * 16 + lo];
 #pragma unroll
       for (int a = 0; a < JT; ++a)
 #pragma unroll
@@ -1142,8 +1180,9 @@ hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_par
   char *base = (char *)scratch;
   const int Kp = (m->N + 3) / 4 * 4;
   const int VS = JT * 16 + ((JT & 1) ? 0 : 16);
+  const size_t lds = (size_t(2) * Kp * VS + size_t(2 * PAIRS) * 16 * kSpinStride) * sizeof(float);
   hipLaunchKernelGGL((k_svc<float, JT, JV, NT, PAIRS>), dim3(unsigned(g.splits)),
-                     dim3(128 * PAIRS), size_t(2) * Kp * VS * sizeof(float), st, m->N, m->M, n,
+                     dim3(128 * PAIRS), lds, st, m->N, m->M, n,
                      (const uint64_t *)(base + L.masks), (const float *)(base + L.Tm),
                      (const float *)(base + L.Vt), (const float *)(base + L.vb),
                      (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
@@ -1486,7 +1525,8 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
       g.Jtiles * g.NT <= 18) {
     const size_t Kp = size_t(m->N + 3) / 4 * 4;
     const size_t VS = size_t(g.Jtiles) * 16 + ((g.Jtiles & 1) ? 0 : 16);
-    if (2 * Kp * VS * 4 <= 54 * 1024) {
+    const size_t lds = 2 * Kp * VS * 4 + size_t(8) * 16 * kSpinStride * 4 + 12 * 1024;
+    if (2 * Kp * VS * 4 <= 54 * 1024 && lds <= size_t(m->max_lds)) {
       g.pair = true;
       g.fused = true;
       // the separate k_vjp (O^dagger 1, force) takes the smallest tile count covering
