@@ -1128,7 +1128,7 @@ hipError_t jvp_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scrat
 
 template <typename T, bool C, int JT, int NT>
 hipError_t vjp_tile(const nqs_model *m, const int8_t *sigma, int64_t n, const double *u,
-                    void *scratch, const int *skip, hipStream_t st) {
+                    void *scratch, const int *skip, hipStream_t st, bool reduce) {
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
@@ -1137,7 +1137,7 @@ hipError_t vjp_tile(const nqs_model *m, const int8_t *sigma, int64_t n, const do
                      (const T *)(base + L.Tm), u, g.per_split, g.Jtiles * 16, g.Itiles * 16,
                      (T *)(base + L.part), skip);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !reduce) return e;
   const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
   hipLaunchKernelGGL((k_vjp_reduce1<T, C>), dim3(unsigned(cdiv(elems, 256)), g.groups),
                      dim3(256), 0, st, g.splits, g.groups, elems, (const T *)(base + L.part),
@@ -1147,10 +1147,10 @@ hipError_t vjp_tile(const nqs_model *m, const int8_t *sigma, int64_t n, const do
 
 template <typename T, bool C>
 hipError_t vjp_t(const nqs_model *m, const int8_t *sigma, int64_t n, const double *u,
-                 void *scratch, const int *skip, hipStream_t st) {
+                 void *scratch, const int *skip, hipStream_t st, bool reduce) {
   GradPlan g = grad_plan(m, n);
 #define NQS_VJP_CASE(A, B) \
-  if (g.JT == A && g.NT == B) return vjp_tile<T, C, A, B>(m, sigma, n, u, scratch, skip, st);
+  if (g.JT == A && g.NT == B) return vjp_tile<T, C, A, B>(m, sigma, n, u, scratch, skip, st, reduce);
   NQS_VJP_CASE(1, 1)
   NQS_VJP_CASE(2, 1)
   NQS_VJP_CASE(4, 1)
@@ -1174,7 +1174,7 @@ hipError_t vjp_t(const nqs_model *m, const int8_t *sigma, int64_t n, const doubl
 
 template <int JT, int JV, int NT, int PAIRS>
 hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_part,
-                  const int *skip, hipStream_t st) {
+                  const int *skip, hipStream_t st, bool reduce) {
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
@@ -1188,7 +1188,7 @@ hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_par
                      (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
                      g.Itiles * 16, (float *)(base + L.part), ysum_part, skip);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !reduce) return e;
   const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
   hipLaunchKernelGGL((k_vjp_reduce1<float, true>), dim3(unsigned(cdiv(elems, 256)), g.groups),
                      dim3(256), 0, st, g.splits, g.groups, elems,
@@ -1198,25 +1198,25 @@ hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_par
 
 template <int JT, int NT>
 hipError_t svc_pick(const nqs_model *m, int64_t n, void *scratch, double *ysum_part,
-                    const int *skip, hipStream_t st) {
+                    const int *skip, hipStream_t st, bool reduce) {
   const GradPlan g = grad_plan(m, n);
   const bool full = (m->M % 16) == 0;  // row M starts a tile of its own
   if constexpr (JT > 1) {
     if (full)
-      return g.pairs == 4 ? svc_go<JT, JT - 1, NT, 4>(m, n, scratch, ysum_part, skip, st)
-                          : svc_go<JT, JT - 1, NT, 2>(m, n, scratch, ysum_part, skip, st);
+      return g.pairs == 4 ? svc_go<JT, JT - 1, NT, 4>(m, n, scratch, ysum_part, skip, st, reduce)
+                          : svc_go<JT, JT - 1, NT, 2>(m, n, scratch, ysum_part, skip, st, reduce);
   }
   if (full) return hipErrorInvalidValue;
-  return g.pairs == 4 ? svc_go<JT, JT, NT, 4>(m, n, scratch, ysum_part, skip, st)
-                      : svc_go<JT, JT, NT, 2>(m, n, scratch, ysum_part, skip, st);
+  return g.pairs == 4 ? svc_go<JT, JT, NT, 4>(m, n, scratch, ysum_part, skip, st, reduce)
+                      : svc_go<JT, JT, NT, 2>(m, n, scratch, ysum_part, skip, st, reduce);
 }
 
 // plane-split S v for complex FP32 (grad_plan(...).pair): JT = Jtiles exactly
 hipError_t svc_launch(const nqs_model *m, int64_t n, void *scratch, double *ysum_part,
-                      const int *skip, hipStream_t st) {
+                      const int *skip, hipStream_t st, bool reduce) {
   const GradPlan g = grad_plan(m, n);
 #define NQS_SVC_CASE(A, B) \
-  if (g.Jtiles == A && g.NT == B) return svc_pick<A, B>(m, n, scratch, ysum_part, skip, st);
+  if (g.Jtiles == A && g.NT == B) return svc_pick<A, B>(m, n, scratch, ysum_part, skip, st, reduce);
   NQS_SVC_CASE(1, 1) NQS_SVC_CASE(1, 2) NQS_SVC_CASE(1, 3) NQS_SVC_CASE(1, 4)
   NQS_SVC_CASE(2, 1) NQS_SVC_CASE(2, 2) NQS_SVC_CASE(2, 3) NQS_SVC_CASE(2, 4)
   NQS_SVC_CASE(3, 1) NQS_SVC_CASE(3, 2) NQS_SVC_CASE(3, 3) NQS_SVC_CASE(3, 4)
@@ -1229,7 +1229,7 @@ hipError_t svc_launch(const nqs_model *m, int64_t n, void *scratch, double *ysum
 
 template <typename T, bool C, int JT, int NT>
 hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
-                   double *ysum_part, const int *skip, hipStream_t st) {
+                   double *ysum_part, const int *skip, hipStream_t st, bool reduce) {
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
@@ -1242,7 +1242,7 @@ hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scr
                      (const double *)(base + L.va), g.per_split, g.Jtiles * 16, g.Itiles * 16,
                      (T *)(base + L.part), ysum_part, skip);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !reduce) return e;
   const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
   hipLaunchKernelGGL((k_vjp_reduce1<T, C>), dim3(unsigned(cdiv(elems, 256)), g.groups),
                      dim3(256), 0, st, g.splits, g.groups, elems, (const T *)(base + L.part),
@@ -1252,13 +1252,13 @@ hipError_t sv_tile(const nqs_model *m, const int8_t *sigma, int64_t n, void *scr
 
 template <typename T, bool C>
 hipError_t sv_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
-                double *ysum_part, const int *skip, hipStream_t st) {
+                double *ysum_part, const int *skip, hipStream_t st, bool reduce) {
   GradPlan g = grad_plan(m, n);
   if constexpr (C && std::is_same<T, float>::value) {
-    if (g.pair) return svc_launch(m, n, scratch, ysum_part, skip, st);
+    if (g.pair) return svc_launch(m, n, scratch, ysum_part, skip, st, reduce);
   }
 #define NQS_SV_CASE(A, B) \
-  if (g.JT == A && g.NT == B) return sv_tile<T, C, A, B>(m, sigma, n, scratch, ysum_part, skip, st);
+  if (g.JT == A && g.NT == B) return sv_tile<T, C, A, B>(m, sigma, n, scratch, ysum_part, skip, st, reduce);
   NQS_SV_CASE(1, 1)
   NQS_SV_CASE(2, 1)
   NQS_SV_CASE(4, 1)
@@ -1579,13 +1579,13 @@ hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *
 
 hipError_t launch_vjp_partials(const nqs_model *m, const int8_t *sigma, int64_t n,
                                const double *u, void *scratch, const int *skip,
-                               hipStream_t st) {
-  return NQS_DISPATCH(vjp_t, m, sigma, n, u, scratch, skip, st);
+                               hipStream_t st, bool reduce) {
+  return NQS_DISPATCH(vjp_t, m, sigma, n, u, scratch, skip, st, reduce);
 }
 
 hipError_t launch_sv(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
-                     double *ysum_part, const int *skip, hipStream_t st) {
-  return NQS_DISPATCH(sv_t, m, sigma, n, scratch, ysum_part, skip, st);
+                     double *ysum_part, const int *skip, hipStream_t st, bool reduce) {
+  return NQS_DISPATCH(sv_t, m, sigma, n, scratch, ysum_part, skip, st, reduce);
 }
 
 GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch) {
@@ -1597,6 +1597,7 @@ GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch) {
   b.vb = base + L.vb;
   b.va = (double *)(base + L.va);
   b.out1 = (double *)(base + L.out1);
+  b.part = base + L.part;
   return b;
 }
 

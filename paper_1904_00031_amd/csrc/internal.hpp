@@ -148,16 +148,17 @@ hipError_t launch_jvp(const nqs_model *m, const int8_t *sigma, int64_t n, void *
 // raw partials of O^dagger u into scratch (u: complex/real double [n])
 hipError_t launch_vjp_partials(const nqs_model *m, const int8_t *sigma, int64_t n,
                                const double *u, void *scratch, const int *skip,
-                               hipStream_t st);
+                               hipStream_t st, bool reduce = true);
 // fused S v (requires plan.fused): partials of O^dagger y with y = O v, plus per-block sums
 // of y (complex double, plan.splits entries), then the first reduction level
 hipError_t launch_sv(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,
-                     double *ysum_part, const int *skip, hipStream_t st);
+                     double *ysum_part, const int *skip, hipStream_t st, bool reduce = true);
 struct GradBuffers {
   void *Tm;        // tanh(theta) rows [n][M] (compute precision)
   void *Vt, *vb;   // direction tables in compute precision
   double *va;      // visible part of the direction, complex double
   double *out1;    // first-level VJP sums [groups][Jtiles*16*Itiles*16] complex double
+  void *part;      // per-split VJP partial tiles [splits][Jtiles*16][Itiles*16], compute precision
 };
 GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch);
 // out[k] = sum of partials (double, params layout)

@@ -343,6 +343,73 @@ __global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart,
   k_cg_p_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, rpart, nparts, parity, tol, maxiter, r, p, Vt, vb, va, st);
 }
 
+// ---- fused CG iteration kernel (single model) -----------------------------------
+// g = sum over the sample splits of the VJP partial tiles, then
+// Ap = (g - ybar O^dagger 1) / n + lambda p and per-block partial sums of Re(p^dagger Ap).
+// A block takes 32 elements of the tile layout; its 8 thread slices sum every eighth
+// split of them, and the slices are added in a fixed order (deterministic). Elements
+// outside the parameters are idle.
+constexpr int kAprElems = 32, kAprSlices = 8;
+
+template <typename T, bool C>
+__global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int splits,
+                                                int colsP, int64_t elems,
+                                                const T *__restrict__ part,
+                                                const double *o1, const double *ysum,
+                                                int64_t nys, const double *p, double lambda,
+                                                double *Ap, double *dpart, const CGState *st) {
+  if (st->done) return;
+  __shared__ double lds[256];
+  __shared__ double sr[kAprSlices][kAprElems], si[kAprSlices][kAprElems];
+  const double ybr = block_sum(ysum, nys, 2, lds) / double(n);
+  const double ybi = C ? block_sum(ysum + 1, nys, 2, lds) / double(n) : 0.0;
+  const int el = threadIdx.x % kAprElems, sl = threadIdx.x / kAprElems;
+  const int64_t e = int64_t(blockIdx.x) * kAprElems + el;
+  double gr = 0.0, gi = 0.0;
+  if (e < elems) {
+    for (int q = sl; q < splits; q += kAprSlices) {
+      const V<T, C> x = vload<T, C>(part, int64_t(q) * elems + e);
+      gr += double(x.re);
+      if (C) gi += double(x.im);
+    }
+  }
+  sr[sl][el] = gr;
+  si[sl][el] = gi;
+  __syncthreads();
+  double acc = 0.0;
+  if (sl == 0 && e < elems) {
+    for (int q = 1; q < kAprSlices; ++q) {
+      gr += sr[q][el];
+      gi += si[q][el];
+    }
+    const int jrow = int(e / colsP), icol = int(e % colsP);
+    int64_t k = -1;
+    if (jrow < M && icol < N)
+      k = int64_t(N) + M + int64_t(jrow) * N + icol;  // W_ji
+    else if (jrow < M && icol == N)
+      k = N + jrow;  // b_j
+    else if (jrow == M && icol < N)
+      k = icol;  // a_i
+    if (k >= 0) {
+      if (C) {
+        gr -= ybr * o1[2 * k] - ybi * o1[2 * k + 1];
+        gi -= ybr * o1[2 * k + 1] + ybi * o1[2 * k];
+        const double ar = gr / double(n) + lambda * p[2 * k];
+        const double ai = gi / double(n) + lambda * p[2 * k + 1];
+        Ap[2 * k] = ar;
+        Ap[2 * k + 1] = ai;
+        acc = p[2 * k] * ar + p[2 * k + 1] * ai;
+      } else {
+        const double ar = (gr - ybr * o1[k]) / double(n) + lambda * p[k];
+        Ap[k] = ar;
+        acc = p[k] * ar;
+      }
+    }
+  }
+  acc = block_reduce(acc, lds);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+}
+
 template <typename PT>
 __device__ __forceinline__ void k_update_body(int BX, int BY, int BZ, int GX, int64_t Pc, PT *params, const double *x, double lr) {
   for (int64_t k = BX * int64_t(blockDim.x) + threadIdx.x; k < Pc;
@@ -386,7 +453,13 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   L.r = take(size_t(P) * cs * 8);
   L.p = take(size_t(P) * cs * 8);
   L.Ap = take(size_t(P) * cs * 8);
-  L.dpart = take(size_t(pb) * 8);
+  {
+    // partial sums of p^dagger Ap: per block of the parameter range, or of the VJP tile
+    // layout (k_cg_apr), whichever has more blocks
+    const GradPlan gq = grad_plan(m, n);
+    const int64_t ab = cdiv(int64_t(gq.Jtiles) * 16 * gq.Itiles * 16, kAprElems);
+    L.dpart = take(size_t(pb > ab ? pb : ab) * 8);
+  }
   const int64_t cb = cdiv(P * cs, 256) < 4096 ? cdiv(P * cs, 256) : 4096;
   L.rpart = take(size_t(cb) * 8);
   L.state = take(sizeof(CGState));
@@ -478,20 +551,22 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
     HIPTRY(hipStreamSynchronize(st));
     if (hs.done || launched >= cg_maxiter) break;
     const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
+    // one CG iteration = the product's partial tiles, k_cg_apr, k_cg_xr, k_cg_p
+    const int64_t ablocks = cdiv(elems, kAprElems);
     for (int q = 0; q < batch; ++q, ++launched) {
       const int parity = launched & 1;
       if (gp.fused) {
-        HIPTRY(launch_sv(m, sigma, n, grad, D(L.ysum), skip, st));
+        HIPTRY(launch_sv(m, sigma, n, grad, D(L.ysum), skip, st, false));
       } else {
         HIPTRY(launch_jvp(m, sigma, n, grad, D(L.y), D(L.ysum), skip, st));
-        HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, st));
+        HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, st, false));
       }
-      hipLaunchKernelGGL((k_cg_ap<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, N, M, n,
-                         gp.groups, gp.Itiles * 16, elems, gb.out1, D(L.o1), D(L.ysum), nys,
-                         D(L.p), diag_shift, D(L.Ap), D(L.dpart), state);
+      hipLaunchKernelGGL((k_cg_apr<T, C>), dim3(unsigned(ablocks)), dim3(256), 0, st, N, M, n,
+                         gp.splits, gp.Itiles * 16, elems, (const T *)gb.part, D(L.o1),
+                         D(L.ysum), nys, D(L.p), diag_shift, D(L.Ap), D(L.dpart), state);
       HIPTRY(hipGetLastError());
       hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, st, Pc, D(L.dpart),
-                         pblocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+                         ablocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
       HIPTRY(hipGetLastError());
       hipLaunchKernelGGL((k_cg_p<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, st, N, M,
                          D(L.rpart), cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
