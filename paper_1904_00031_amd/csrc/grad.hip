@@ -768,11 +768,17 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   const int64_t sbeg = int64_t(blockIdx.x) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
   const int64_t iters = send > sbeg ? (send - sbeg + 16 * PAIRS - 1) / (16 * PAIRS) : 0;
-  Acc acc[JT][NT];
+  // row-M tile on the vector units when it holds nothing else (M a multiple of 16)
+  constexpr bool AROW = JV == JT - 1;
+  constexpr int JTM = AROW ? JT - 1 : JT;  // hidden tiles accumulated on the matrix cores
+  Acc acc[JTM][NT];
 #pragma unroll
-  for (int a = 0; a < JT; ++a)
+  for (int a = 0; a < JTM; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+  T ga[NT];
+#pragma unroll
+  for (int b = 0; b < NT; ++b) ga[b] = T(0);
   double ysr = 0.0, ysi = 0.0;
   // software pipeline: the masks and T rows of the pair's next group are loaded while
   // the current group's O^dagger y contraction runs
@@ -923,15 +929,30 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
         svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
     }
     // ---- plane h of Z^T S over the 16 samples (step q: row MF::row(hi, q)) ----
+    // With M a multiple of 16 the last hidden tile holds only row M (Z = y): its sums
+    // g_a = sum_s y_s s_s are accumulated on the vector units instead.
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       T bs[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b) bs[b] = stile[MF<T>::row(hi, q) * kSpinStride + b * 16 + lo];
 #pragma unroll
-      for (int a = 0; a < JT; ++a)
+      for (int a = 0; a < JTM; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) acc[a][b] = MF<T>::mma(z[q][a], bs[b], acc[a][b]);
+      if constexpr (AROW) {
+        const T yq = h == 0 ? yre[q] : yim[q];
+#pragma unroll
+        for (int b = 0; b < NT; ++b) ga[b] += yq * bs[b];
+      }
+    }
+  }
+  if constexpr (AROW) {
+    // lanes of one column (lo) hold the sums of rows 4 hi .. 4 hi + 3: add the four
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      ga[b] += __shfl_xor(ga[b], 16, 64);
+      ga[b] += __shfl_xor(ga[b], 32, 64);
     }
   }
   // block sums: plane 0 of every pair -> real part, plane 1 -> imaginary part
@@ -943,7 +964,12 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     for (int b = 0; b < NT; ++b) {
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) red[wid][q][lane] = acc[a][b][q];
+      for (int q = 0; q < 4; ++q) {
+        if (a < JTM)
+          red[wid][q][lane] = acc[a < JTM ? a : 0][b][q];
+        else  // the row-M tile: only row M is nonzero
+          red[wid][q][lane] = a * 16 + MF<T>::row(hi, q) == M ? ga[b] : T(0);
+      }
       __syncthreads();
       const int jrow = a * 16 + MF<T>::row(l >> 4, r);
       const int icol = b * 16 + (l & 15);
