@@ -227,6 +227,13 @@ nqs_status nqs_autotune(nqs_model *model, const void *params, const int8_t *sigm
  * ignore it. */
 nqs_status nqs_set_sv_shape(nqs_model *model, int32_t pairs);
 
+/* nqs_sr_step launches its CG iterations in chunks of 8 and, by default, replays full
+ * chunks from a graph captured on the first chunk (re-captured when the workspace,
+ * samples, n, shift, tolerance, iteration limit or S v shape change); the results are
+ * those of the plain launches. enable = 0 launches every kernel directly (for callers
+ * that capture the whole step into a graph of their own). */
+nqs_status nqs_set_cg_graphs(nqs_model *model, int32_t enable);
+
 /* ---- Batches of independent models (uneven sizes) --------------------------------
  * A batch holds K models created from K descriptions (all with the same is_complex and
  * prec; sizes, Hamiltonians, couplings and moves may differ). Buffers of the models are

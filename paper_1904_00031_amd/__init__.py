@@ -90,6 +90,7 @@ def load(path=LIB_PATH):
         "nqs_sr_prepare": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, vp]),
         "nqs_sr_matvec": (i32, [vp, vp, i64, vp, ctypes.c_size_t, vp, f64, vp, vp]),
         "nqs_set_sv_shape": (i32, [vp, i32]),
+        "nqs_set_cg_graphs": (i32, [vp, i32]),
         "nqs_batch_create": (i32, [ctypes.POINTER(_Desc), i32, ctypes.POINTER(vp)]),
         "nqs_batch_destroy": (None, [vp]),
         "nqs_batch_n_params": (i64, [vp, i32]),
@@ -113,7 +114,8 @@ def exported_symbols():
     return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
             "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
             "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_prepare",
-            "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_batch_create",
+            "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_set_cg_graphs",
+            "nqs_batch_create",
             "nqs_batch_destroy", "nqs_batch_n_params", "nqs_batch_chain_init",
             "nqs_batch_sample", "nqs_batch_sr_workspace_bytes", "nqs_batch_sr_step"]
 
@@ -367,6 +369,9 @@ class Model:
 
     def set_sv_shape(self, pairs):
         _check(_lib.nqs_set_sv_shape(self._h, int(pairs)), "nqs_set_sv_shape")
+
+    def set_cg_graphs(self, enable):
+        _check(_lib.nqs_set_cg_graphs(self._h, int(bool(enable))), "nqs_set_cg_graphs")
 
 
 class Batch:

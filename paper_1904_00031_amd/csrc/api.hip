@@ -230,6 +230,8 @@ void nqs_model_destroy(nqs_model *m) {
   if (m->d_bond_off) (void)hipFree(m->d_bond_off);
   if (m->d_tables) (void)hipFree(m->d_tables);
   if (m->d_scratch) (void)hipFree(m->d_scratch);
+  if (m->cg_exec) (void)hipGraphExecDestroy(m->cg_exec);
+  if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
   delete m;
 }
 
@@ -360,6 +362,12 @@ nqs_status nqs_autotune(nqs_model *m, const void *params, const int8_t *sigma, i
                         void *stream) {
   if (!m || !params || !sigma || !workspace || n < 2) return NQS_EINVAL;
   return autotune_impl(m, params, sigma, n, workspace, ws_bytes, report, (hipStream_t)stream);
+}
+
+nqs_status nqs_set_cg_graphs(nqs_model *m, int32_t enable) {
+  if (!m) return NQS_EINVAL;
+  m->cg_graphs = enable != 0;
+  return NQS_OK;
 }
 
 nqs_status nqs_set_sv_shape(nqs_model *m, int32_t pairs) {

@@ -8,6 +8,19 @@
 
 #include "common.hpp"
 
+// arguments that fix the launches of a captured chunk of CG iterations
+struct CgGraphKey {
+  const void *ws = nullptr;
+  const int8_t *sigma = nullptr;
+  int64_t n = 0;
+  double shift = 0, tol = 0;
+  int maxiter = 0, sv_pairs = 0;
+  bool operator==(const CgGraphKey &o) const {
+    return ws == o.ws && sigma == o.sigma && n == o.n && shift == o.shift && tol == o.tol &&
+           maxiter == o.maxiter && sv_pairs == o.sv_pairs;
+  }
+};
+
 struct nqs_model {
   int N, M, is_complex, prec, ham, move, marshall;
   int B[2], Btot;
@@ -27,6 +40,11 @@ struct nqs_model {
   // grow-only scratch for nqs_log_psi_grad
   void *d_scratch = nullptr;
   size_t scratch_bytes = 0;
+  // chunks of 8 CG iterations of nqs_sr_step replayed from a captured graph
+  bool cg_graphs = true;
+  hipStream_t cap_stream = nullptr;  // capture only (default priority)
+  hipGraphExec_t cg_exec = nullptr;
+  CgGraphKey cg_key;
 };
 
 // Device copy of a host-built job table. upload() copies only when the bytes differ from

@@ -553,26 +553,63 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
     const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
     // one CG iteration = the product's partial tiles, k_cg_apr, k_cg_xr, k_cg_p
     const int64_t ablocks = cdiv(elems, kAprElems);
-    for (int q = 0; q < batch; ++q, ++launched) {
-      const int parity = launched & 1;
-      if (gp.fused) {
-        HIPTRY(launch_sv(m, sigma, n, grad, D(L.ysum), skip, st, false));
-      } else {
-        HIPTRY(launch_jvp(m, sigma, n, grad, D(L.y), D(L.ysum), skip, st));
-        HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, st, false));
+    auto iterations = [&](int count, hipStream_t s2) -> hipError_t {
+      for (int q = 0; q < count; ++q) {
+        const int parity = q & 1;  // chunks start at an even iteration
+        hipError_t e2;
+        if (gp.fused) {
+          e2 = launch_sv(m, sigma, n, grad, D(L.ysum), skip, s2, false);
+        } else {
+          e2 = launch_jvp(m, sigma, n, grad, D(L.y), D(L.ysum), skip, s2);
+          if (e2 == hipSuccess)
+            e2 = launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, s2, false);
+        }
+        if (e2 != hipSuccess) return e2;
+        hipLaunchKernelGGL((k_cg_apr<T, C>), dim3(unsigned(ablocks)), dim3(256), 0, s2, N, M, n,
+                           gp.splits, gp.Itiles * 16, elems, (const T *)gb.part, D(L.o1),
+                           D(L.ysum), nys, D(L.p), diag_shift, D(L.Ap), D(L.dpart), state);
+        if ((e2 = hipGetLastError()) != hipSuccess) return e2;
+        hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, s2, Pc, D(L.dpart),
+                           ablocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+        if ((e2 = hipGetLastError()) != hipSuccess) return e2;
+        hipLaunchKernelGGL((k_cg_p<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, s2, N, M,
+                           D(L.rpart), cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
+                           (T *)gb.Vt, (T *)gb.vb, gb.va, state);
+        if ((e2 = hipGetLastError()) != hipSuccess) return e2;
       }
-      hipLaunchKernelGGL((k_cg_apr<T, C>), dim3(unsigned(ablocks)), dim3(256), 0, st, N, M, n,
-                         gp.splits, gp.Itiles * 16, elems, (const T *)gb.part, D(L.o1),
-                         D(L.ysum), nys, D(L.p), diag_shift, D(L.Ap), D(L.dpart), state);
-      HIPTRY(hipGetLastError());
-      hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, st, Pc, D(L.dpart),
-                         ablocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
-      HIPTRY(hipGetLastError());
-      hipLaunchKernelGGL((k_cg_p<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, st, N, M,
-                         D(L.rpart), cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
-                         (T *)gb.Vt, (T *)gb.vb, gb.va, state);
-      HIPTRY(hipGetLastError());
+      return hipSuccess;
+    };
+    if (batch == check_every && m->cg_graphs) {
+      // full chunks replay one captured graph: the arguments of the chunk's launches
+      // depend only on the key below
+      const CgGraphKey key{ws, sigma, n, diag_shift, cg_tol, cg_maxiter, m->sv_pairs};
+      if (!m->cg_exec || !(m->cg_key == key)) {
+        if (m->cg_exec) {
+          (void)hipGraphExecDestroy(m->cg_exec);
+          m->cg_exec = nullptr;
+        }
+        if (!m->cap_stream) HIPTRY(hipStreamCreate(&m->cap_stream));
+        hipGraph_t graph = nullptr;
+        HIPTRY(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t e1 = iterations(check_every, m->cap_stream);
+        const hipError_t e2 = hipStreamEndCapture(m->cap_stream, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return NQS_EDEVICE;
+        }
+        const hipError_t e3 = hipGraphInstantiate(&m->cg_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+          m->cg_exec = nullptr;
+          return NQS_EDEVICE;
+        }
+        m->cg_key = key;
+      }
+      HIPTRY(hipGraphLaunch(m->cg_exec, st));
+    } else {
+      HIPTRY(iterations(batch, st));
     }
+    launched += batch;
   }
   const bool nonfinite = hs.nonfinite || !std::isfinite(hs.E[0]) || !std::isfinite(hs.var);
   if (!nonfinite) {

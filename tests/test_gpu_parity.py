@@ -344,3 +344,29 @@ def test_sr_matvec_full_size_sampled(lib):
     exp = orbm.vjp_entries(pe, s, y - y.mean(), ks, N, M) / n + 0.01 * v[ks]
     scale = np.abs(orbm.vjp_entries(pe, s, y, ks, N, M)).max() / n
     assert np.abs(got[ks] - exp).max() <= cases.tol(name) * scale
+
+
+@pytest.mark.parametrize("name", ["heis40_cplx_f32", "tfim10_real_f64", "j1j2_4x4_cplx_f64"])
+def test_sr_step_graph_replays_match_direct_launches(lib, name):
+    """Chunks of CG iterations replayed from a captured graph (several replays per call,
+    with the host reading the solver state between them; the second graph call reuses
+    the cached graph) give bitwise the parameters of direct launches."""
+    m, om = cases.build(lib, name)
+    p = cases.params(name, theta=0.3, seed=91)
+    n = 700
+    s = cases.configs(name, n, seed=92)
+    pe = p.astype(np.complex128 if m.is_complex else np.float64)
+    el = to_dev(oh.local_energy(om, pe, s))
+    st = to_dev(s)
+    ws = torch.empty(m.sr_workspace_bytes(n), dtype=torch.uint8, device=DEV)
+    out = []
+    for graphs in (False, True, True, False):
+        m.set_cg_graphs(graphs)
+        pt = to_dev(p.copy())
+        info = m.sr_step(pt, st, el, lr=0.05, diag_shift=0.01, cg_tol=1e-14, cg_maxiter=40,
+                         workspace=ws)
+        torch.cuda.synchronize()
+        out.append((pt.cpu().numpy(), info["cg_iters"], info["energy_re"]))
+    for q in range(1, 4):
+        assert np.array_equal(out[0][0], out[q][0]), q
+        assert out[0][1] == out[q][1] == 40
