@@ -635,7 +635,8 @@ __device__ __forceinline__ int svc_rows(int64_t send, int64_t g) {
   return left <= 0 ? 0 : (left < 16 ? int(left) : 16);
 }
 
-// the spin mask of row lane / 4 and the T rows of one 16-sample group. Loads are
+// the spin masks of rows lane / 4 (mrow) and lane % 16 (mlo) and the T rows of one
+// 16-sample group. Loads are
 // unconditional with selects after them (no branches around loads). FULL: all 16 rows
 // valid. Otherwise rows outside the group read a valid row of the group (or row 0) and
 // are zeroed. Hidden tiles below JV - 1 are complete; tile JV - 1 reads columns j >= M
@@ -645,9 +646,10 @@ template <typename T, int JT, int JV, bool FULL>
 __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
                                          const T *__restrict__ Tm, int M, int64_t g,
                                          int rows_here, int lane, int lo, int hi,
-                                         uint64_t &mrow, bool &row_ok,
+                                         uint64_t &mrow, bool &row_ok, uint64_t &mlo,
                                          V<T, true> (&tv)[JT][4]) {
   const int64_t gc = FULL || rows_here > 0 ? g : 0;
+  mlo = masks[gc + (FULL || lo < rows_here ? lo : 0)];
   {
     const int rr = lane >> 2;
     row_ok = FULL || rr < rows_here;
@@ -697,6 +699,28 @@ __device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, bool row_o
 }
 
 
+// Exact three-way bf16 split of an FP32 value by truncation: x = h + m + l, h the upper
+// 16 bits of x, m those of r = x - h, l = r - m. Both differences are exact in FP32
+// (r keeps at most 16 significant bits, l at most 8), so l is itself a bf16 and the
+// three parts sum to x exactly. Against a +/-1 operand every product is exact, and a
+// bf16 matrix-core contraction with FP32 accumulation gives the FP32 result up to the
+// order of the additions.
+__device__ __forceinline__ float bf16_rest(float x) {
+  return x - __uint_as_float(__float_as_uint(x) & 0xffff0000u);
+}
+// the upper halves (bf16 truncations) of a and b in one register, a in the low half
+__device__ __forceinline__ uint32_t pack_hi(float a, float b) {
+  return (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xffff0000u);
+}
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// 16x16x32 bf16 MFMA, FP32 accumulate. A: lane l holds A[l%16][8(l/16) .. 8(l/16)+7];
+// B: lane l holds B[8(l/16) .. 8(l/16)+7][l%16]; D as the 16x16x4 FP32 instruction.
+// Element e of a register quad is bits 16e .. 16e+15 (dword e/2, low half first).
+__device__ __forceinline__ floatx4 mfma_bf16(uint4 a, uint4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------------
 // Fused S v product for complex models with N <= 63 and all VJP tiles in one block.
 // The real and imaginary planes of both contractions are split between the two
@@ -709,10 +733,21 @@ __device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, bool row_o
 //   within the pair);
 //   then plane h of Z^T S with Z = conj(T) y:
 //     Re Z = Re T Re y + Im T Im y,  Im Z = Re T Im y - Im T Re y  (row M: Z = y).
-// Spins enter as 64-bit masks (k_pack_spins), so no spin tile is staged.
+// Spins enter as 64-bit masks (k_pack_spins). Both contractions run on the bf16 matrix
+// cores: the FP32 factor (V, then Z) is split exactly into three bf16 parts against the
+// +/-1 spins, so the products are exact and the sums FP32.
 // JT = ceil((M+1)/16) hidden tiles of the VJP output, JV = ceil(M/16) of them carry
 // hidden units in the JVP, NT = ceil((N+1)/16) site tiles.
 // ---------------------------------------------------------------------------------
+// dynamic LDS of k_svc: the bf16 split of V for both planes ([2][G][16 JV] groups of
+// 8 bf16, G = 4 ceil(3 ceil(N / 8) / 4), JV = ceil(M / 16)) and one float spin tile per
+// wavefront
+inline size_t svc_dynamic_lds(int N, int M, int pairs) {
+  const size_t G = size_t(4) * ((3 * ((N + 7) / 8) + 3) / 4);
+  const size_t JVW = size_t((M + 15) / 16) * 16;
+  return 2 * G * JVW * 16 + size_t(2 * pairs) * 16 * kSpinStride * sizeof(float);
+}
+
 template <typename T, int JT, int JV, int NT, int PAIRS>
 __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
                                                 const uint64_t *__restrict__ masks,
@@ -725,28 +760,69 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   if (skip && *skip) return;
   typedef typename MF<T>::acc Acc;
   constexpr int JW = JT * 16;
-  constexpr int VS = JW + ((JT & 1) ? 0 : 16);  // plane row stride: 16 banks apart per k
   constexpr int NVA = 4;                        // site columns per lane: lo + 16 c, N <= 63
   extern __shared__ __align__(16) unsigned char lds_u8[];
-  static_assert(sizeof(T) == 4, "spin tiles are float");
+  static_assert(sizeof(T) == 4, "spin tiles and the bf16 split are FP32");
   constexpr int NTH = 128 * PAIRS;
   __shared__ T ybuf[2][PAIRS][2][16][2];  // [parity][pair][plane of origin][row][re, im]
   __shared__ T red[2 * PAIRS][4][64];
   __shared__ double dsum[2][NTH];
+  // spin byte b -> the 8 spins (bit e set: +1, else -1) as bf16, element e = site e
+  __shared__ __align__(16) uint32_t stab[256 * 4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
   const int pr = wid >> 1, h = wid & 1;
-  const int Kp = (N + 3) / 4 * 4;
-  T *Vl = reinterpret_cast<T *>(lds_u8);  // [plane][Kp][VS]
-  for (int e = threadIdx.x; e < 2 * Kp * VS; e += NTH) {
-    const int pl = e / (Kp * VS), rem = e - pl * (Kp * VS);
-    const int k = rem / VS, j = rem - k * VS;
-    T x = T(0);
-    if (k < N && j < M) {
-      const V<T, true> v = vload<T, true>(Vt_g, int64_t(k) * M + j);
-      x = pl ? v.im : v.re;
+  // JVP contraction dimension: k group g (8 consecutive k) = part g % 3 of the bf16 split
+  // of V at sites 8 (g / 3) .. 8 (g / 3) + 7; GP site groups, KS steps of 32 k, and
+  // G = 4 KS groups per plane (those from 3 GP on are zero)
+  const int GP = (N + 7) >> 3;
+  const int KS = (3 * GP + 3) >> 2;
+  const int G = 4 * KS;
+  constexpr int JVW = JV * 16;
+  uint4 *Vb = reinterpret_cast<uint4 *>(lds_u8);  // [plane][G][JVW]: B operands of the JVP
+  for (int e = threadIdx.x; e < GP * JVW; e += NTH) {
+    const int sg = e / JVW, j = e - sg * JVW;
+    uint32_t w[2][3][4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = 8 * sg + u;
+      V<T, true> x = vmake<T, true>(T(0), T(0));
+      if (i < N && j < M) x = vload<T, true>(Vt_g, int64_t(i) * M + j);
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        const float v0 = pl ? x.im : x.re;
+        const float r = bf16_rest(v0), l = bf16_rest(r);
+        const uint32_t bits[3] = {__float_as_uint(v0) >> 16, __float_as_uint(r) >> 16,
+                                  __float_as_uint(l) >> 16};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (u & 1)
+            w[pl][q][u >> 1] |= bits[q] << 16;
+          else
+            w[pl][q][u >> 1] = bits[q];
+        }
+      }
     }
-    Vl[e] = x;
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        Vb[(pl * G + 3 * sg + q) * JVW + j] =
+            make_uint4(w[pl][q][0], w[pl][q][1], w[pl][q][2], w[pl][q][3]);
+  }
+  {
+    const int pad = G - 3 * GP;
+    for (int e = threadIdx.x; e < 2 * pad * JVW; e += NTH) {
+      const int q = e / JVW, j = e - q * JVW;
+      const int pl = q / pad, gq = 3 * GP + (q - pl * pad);
+      Vb[(pl * G + gq) * JVW + j] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+  for (int e = threadIdx.x; e < 256 * 4; e += NTH) {
+    const uint32_t b = uint32_t(e) >> 2, u = uint32_t(e) & 3u;
+    const uint32_t s0 = ((b >> (2 * u)) & 1u) ? 0x3F80u : 0xBF80u;
+    const uint32_t s1 = ((b >> (2 * u + 1)) & 1u) ? 0x3F80u : 0xBF80u;
+    stab[e] = s0 | (s1 << 16);
   }
   // both planes of vb (zero past M) and va (zero past N) in LDS, read per group
   __shared__ T vbl[2][JW];
@@ -762,8 +838,8 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     val[pl][i] = i < N ? T(va[2 * i + pl]) : T(0);
   }
   __syncthreads();
-  const T *Vp = Vl + h * Kp * VS;
-  T *stile = Vl + 2 * Kp * VS + wid * 16 * kSpinStride;  // this wavefront's spin tile
+  // this wavefront's spin tile, after the JVP operands
+  T *stile = reinterpret_cast<T *>(Vb + 2 * G * JVW) + wid * 16 * kSpinStride;
   bool stalled = false;
   const int64_t sbeg = int64_t(blockIdx.x) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
@@ -784,44 +860,46 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   // the current group's O^dagger y contraction runs
   int64_t g = sbeg + 16 * pr;
   int rows_here = svc_rows(send, g);
-  uint64_t mrow;
+  uint64_t mrow, mlo;
   bool row_ok;
   V<T, true> tv[JT][4];
   if (iters > 0) {
     if (rows_here == 16)
-      svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
+      svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
     else
-      svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
+      svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
   }
   for (int64_t it = 0; it < iters; ++it) {
     // spins of the group into the tile (the previous group's reads are done: same wave)
     svc_spin_tile<T>(stile, mrow, row_ok, N, lane);
     wave_sync();
-    // ---- X_h = S (plane h of V)^T over the valid hidden tiles ----
+    // ---- X_h = S (plane h of V)^T over the valid hidden tiles, bf16 split ----
+    // A (sample lo, k group g): the spins of sites 8 (g / 3) .. + 7 from the byte table;
+    // sites past N meet zeros in B. Operands of step t + 1 are read during step t.
     Acc x[JT];
 #pragma unroll
     for (int a = 0; a < JT; ++a) x[a] = Acc{0, 0, 0, 0};
     {
-      // operands of step k0 + 4 are read from LDS while the matrix cores work on k0
-      T av_n = stile[lo * kSpinStride + hi];
-      T v_n[JT];
+      const uint4 *tab4 = reinterpret_cast<const uint4 *>(stab);
+      const uint4 *Vh = Vb + h * G * JVW + lo;
+      int g8 = hi;
+      uint4 an = tab4[uint32_t(mlo >> (8 * (g8 / 3))) & 0xffu];
+      uint4 bn[JV];
 #pragma unroll
-      for (int a = 0; a < JT; ++a) v_n[a] = a < JV ? Vp[hi * VS + a * 16 + lo] : T(0);
-      for (int k0 = 0; k0 < Kp; k0 += 4) {
-        const T av = av_n;
-        T v[JT];
+      for (int a = 0; a < JV; ++a) bn[a] = Vh[g8 * JVW + 16 * a];
+      for (int t = 0; t < KS; ++t) {
+        const uint4 av = an;
+        uint4 bv[JV];
 #pragma unroll
-        for (int a = 0; a < JT; ++a) v[a] = v_n[a];
-        if (k0 + 4 < Kp) {
-          const int k = k0 + 4 + hi;
-          av_n = stile[lo * kSpinStride + k];
+        for (int a = 0; a < JV; ++a) bv[a] = bn[a];
+        if (t + 1 < KS) {
+          g8 += 4;
+          an = tab4[uint32_t(mlo >> (8 * (g8 / 3))) & 0xffu];
 #pragma unroll
-          for (int a = 0; a < JT; ++a)
-            if (a < JV) v_n[a] = Vp[k * VS + a * 16 + lo];
+          for (int a = 0; a < JV; ++a) bn[a] = Vh[g8 * JVW + 16 * a];
         }
 #pragma unroll
-        for (int a = 0; a < JT; ++a)
-          if (a < JV) x[a] = MF<T>::mma(av, v[a], x[a]);
+        for (int a = 0; a < JV; ++a) x[a] = mfma_bf16(av, bv[a], x[a]);
       }
     }
     // ---- this plane's share of y for rows MF::row(hi, r) ----
@@ -924,27 +1002,43 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       g += 16 * PAIRS;
       rows_here = svc_rows(send, g);
       if (rows_here == 16)
-        svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
+        svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
       else
-        svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, tv);
+        svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
     }
-    // ---- plane h of Z^T S over the 16 samples (step q: row MF::row(hi, q)) ----
+    // ---- plane h of Z^T S over the 16 samples, bf16 split of Z ----
+    // k of lane group hi: element e < 4 pairs part h of Z at sample 4 hi + e with that
+    // sample's spin, e >= 4 part m; a second step takes part l (upper half zero).
     // With M a multiple of 16 the last hidden tile holds only row M (Z = y): its sums
     // g_a = sum_s y_s s_s are accumulated on the vector units instead.
+    uint4 sb[NT];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      T bs[NT];
+    for (int b = 0; b < NT; ++b) {
+      T bs[4];
 #pragma unroll
-      for (int b = 0; b < NT; ++b) bs[b] = stile[MF<T>::row(hi, q) * kSpinStride + b * 16 + lo];
-#pragma unroll
-      for (int a = 0; a < JTM; ++a)
-#pragma unroll
-        for (int b = 0; b < NT; ++b) acc[a][b] = MF<T>::mma(z[q][a], bs[b], acc[a][b]);
+      for (int q = 0; q < 4; ++q) bs[q] = stile[MF<T>::row(hi, q) * kSpinStride + b * 16 + lo];
       if constexpr (AROW) {
-        const T yq = h == 0 ? yre[q] : yim[q];
 #pragma unroll
-        for (int b = 0; b < NT; ++b) ga[b] += yq * bs[b];
+        for (int q = 0; q < 4; ++q) ga[b] += (h == 0 ? yre[q] : yim[q]) * bs[q];
       }
+      const uint32_t s01 = pack_hi(bs[0], bs[1]), s23 = pack_hi(bs[2], bs[3]);
+      sb[b] = make_uint4(s01, s23, s01, s23);
+    }
+#pragma unroll
+    for (int a = 0; a < JTM; ++a) {
+      T r[4], l[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        r[q] = bf16_rest(z[q][a]);
+        l[q] = bf16_rest(r[q]);
+      }
+      const uint4 a0 = make_uint4(pack_hi(z[0][a], z[1][a]), pack_hi(z[2][a], z[3][a]),
+                                  pack_hi(r[0], r[1]), pack_hi(r[2], r[3]));
+      const uint4 a1 = make_uint4(pack_hi(l[0], l[1]), pack_hi(l[2], l[3]), 0u, 0u);
+#pragma unroll
+      for (int b = 0; b < NT; ++b) acc[a][b] = mfma_bf16(a0, sb[b], acc[a][b]);
+#pragma unroll
+      for (int b = 0; b < NT; ++b) acc[a][b] = mfma_bf16(a1, sb[b], acc[a][b]);
     }
   }
   if constexpr (AROW) {
@@ -1204,9 +1298,13 @@ hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_par
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
-  const int Kp = (m->N + 3) / 4 * 4;
-  const int VS = JT * 16 + ((JT & 1) ? 0 : 16);
-  const size_t lds = (size_t(2) * Kp * VS + size_t(2 * PAIRS) * 16 * kSpinStride) * sizeof(float);
+  const size_t lds = svc_dynamic_lds(m->N, m->M, PAIRS);
+  // dynamic LDS beyond 64 KiB is opted into once per instantiation (up to the device limit
+  // checked by grad_plan)
+  static const hipError_t opt = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(&k_svc<float, JT, JV, NT, PAIRS>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, m->max_lds - 24 * 1024);
+  if (opt != hipSuccess) return opt;
   hipLaunchKernelGGL((k_svc<float, JT, JV, NT, PAIRS>), dim3(unsigned(g.splits)),
                      dim3(128 * PAIRS), lds, st, m->N, m->M, n,
                      (const uint64_t *)(base + L.masks), (const float *)(base + L.Tm),
@@ -1549,10 +1647,9 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
   g.pair = false;
   if (m->is_complex && !use_double(m) && m->N <= 63 && g.Jtiles <= 6 &&
       g.Jtiles * g.NT <= 18) {
-    const size_t Kp = size_t(m->N + 3) / 4 * 4;
-    const size_t VS = size_t(g.Jtiles) * 16 + ((g.Jtiles & 1) ? 0 : 16);
-    const size_t lds = 2 * Kp * VS * 4 + size_t(8) * 16 * kSpinStride * 4 + 12 * 1024;
-    if (2 * Kp * VS * 4 <= 54 * 1024 && lds <= size_t(m->max_lds)) {
+    // dynamic LDS of the 4-pair shape plus the kernel's static arrays (<= 24 KiB)
+    const size_t lds = svc_dynamic_lds(m->N, m->M, 4) + 24 * 1024;
+    if (lds <= size_t(m->max_lds)) {
       g.pair = true;
       g.fused = true;
       // the separate k_vjp (O^dagger 1, force) takes the smallest tile count covering
