@@ -30,32 +30,24 @@ struct CGState {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// sum of count partials, identical in every thread of the block (fixed order)
-__device__ double block_sum(const double *part, int64_t count, int stride, double *lds) {
-  double s = 0.0;
-  for (int64_t k = threadIdx.x; k < count; k += blockDim.x) s += part[k * stride];
-  lds[threadIdx.x] = s;
+// block-level sum of per-thread values, identical in every thread (fixed order): DPP
+// sums inside each wavefront, then the wavefront sums in index order. lds holds at least
+// blockDim.x / 64 doubles.
+__device__ double block_reduce(double v, double *lds) {
+  v = wave_sum_dpp(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-    __syncthreads();
-  }
-  double r = lds[0];
+  double r = 0.0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) r += lds[w];
   __syncthreads();
   return r;
 }
 
-// block-level sum of per-thread values -> returned to thread 0
-__device__ double block_reduce(double v, double *lds) {
-  lds[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-    __syncthreads();
-  }
-  double r = lds[0];
-  __syncthreads();
-  return r;
+// sum of count partials, identical in every thread of the block (fixed order)
+__device__ double block_sum(const double *part, int64_t count, int stride, double *lds) {
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < count; k += blockDim.x) s += part[k * stride];
+  return block_reduce(s, lds);
 }
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
@@ -367,7 +359,19 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
   const int64_t e = int64_t(blockIdx.x) * kAprElems + el;
   double gr = 0.0, gi = 0.0;
   if (e < elems) {
-    for (int q = sl; q < splits; q += kAprSlices) {
+    // eight loads in flight, added in split order
+    int q = sl;
+    for (; q + 7 * kAprSlices < splits; q += 8 * kAprSlices) {
+      V<T, C> xs[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xs[u] = vload<T, C>(part, int64_t(q + u * kAprSlices) * elems + e);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        gr += double(xs[u].re);
+        if (C) gi += double(xs[u].im);
+      }
+    }
+    for (; q < splits; q += kAprSlices) {
       const V<T, C> x = vload<T, C>(part, int64_t(q) * elems + e);
       gr += double(x.re);
       if (C) gi += double(x.im);
@@ -408,6 +412,71 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
   }
   acc = block_reduce(acc, lds);
   if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+}
+
+// ---- x, r and p of one CG iteration in one block (small parameter counts) ----------
+// alpha = rr / p^dagger Ap; x += alpha p; r -= alpha Ap; rr_new = r^dagger r;
+// beta = rr_new / rr; p = r + beta p (+ direction tables). Every thread updates the same
+// elements in both passes, so the block needs no barrier between them beyond the sum.
+constexpr int kXrpThreads = 1024;
+constexpr int64_t kXrpMaxParams = 8192;
+
+template <typename T, bool C>
+__global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const double *dpart,
+                                                        int64_t nparts, int parity, double tol,
+                                                        int maxiter, double *x, double *r,
+                                                        double *p, const double *Ap, T *Vt,
+                                                        T *vb, double *va, CGState *st) {
+  if (st->done) return;
+  __shared__ double lds[kXrpThreads / 64];
+  const int64_t P = int64_t(N) + M + int64_t(N) * M;
+  const double pAp = block_sum(dpart, nparts, 1, lds);
+  const double rr = st->rr[parity];
+  const double alpha = rr / pAp;
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < P; k += kXrpThreads) {
+    if (C) {
+      x[2 * k] += alpha * p[2 * k];
+      x[2 * k + 1] += alpha * p[2 * k + 1];
+      const double r0 = r[2 * k] - alpha * Ap[2 * k];
+      const double r1 = r[2 * k + 1] - alpha * Ap[2 * k + 1];
+      r[2 * k] = r0;
+      r[2 * k + 1] = r1;
+      acc += r0 * r0;
+      acc += r1 * r1;
+    } else {
+      x[k] += alpha * p[k];
+      const double r0 = r[k] - alpha * Ap[k];
+      r[k] = r0;
+      acc += r0 * r0;
+    }
+  }
+  const double rr_new = block_reduce(acc, lds);
+  const double beta = rr_new / rr;
+  for (int64_t k = threadIdx.x; k < P; k += kXrpThreads) {
+    double pr, pi = 0.0;
+    if (C) {
+      pr = r[2 * k] + beta * p[2 * k];
+      pi = r[2 * k + 1] + beta * p[2 * k + 1];
+      p[2 * k] = pr;
+      p[2 * k + 1] = pi;
+    } else {
+      pr = r[k] + beta * p[k];
+      p[k] = pr;
+    }
+    dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va);
+  }
+  if (threadIdx.x == 0) {
+    const int iters = st->iters + 1;
+    const bool conv = sqrt(rr_new) <= tol * st->bnorm;
+    const bool bad = !(finite(rr_new) && finite(alpha));
+    st->alpha = alpha;
+    st->rr[parity ^ 1] = rr_new;
+    st->iters = iters;
+    st->converged = conv;
+    st->nonfinite = bad;
+    st->done = conv || bad || iters >= maxiter;
+  }
 }
 
 template <typename PT>
@@ -569,6 +638,13 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
                            gp.splits, gp.Itiles * 16, elems, (const T *)gb.part, D(L.o1),
                            D(L.ysum), nys, D(L.p), diag_shift, D(L.Ap), D(L.dpart), state);
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
+        if (P <= kXrpMaxParams) {
+          hipLaunchKernelGGL((k_cg_xrp<T, C>), dim3(1), dim3(kXrpThreads), 0, s2, N, M,
+                             D(L.dpart), ablocks, parity, cg_tol, cg_maxiter, D(L.x), D(L.r),
+                             D(L.p), D(L.Ap), (T *)gb.Vt, (T *)gb.vb, gb.va, state);
+          if ((e2 = hipGetLastError()) != hipSuccess) return e2;
+          continue;
+        }
         hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, s2, Pc, D(L.dpart),
                            ablocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
