@@ -238,6 +238,8 @@ __device__ __forceinline__ void vrenorm(V<T, C> &p, int &ex) {
 // then rotations by 4 and 8), and the four row totals gathered with readlane.
 // ---------------------------------------------------------------------------------
 enum { DPP_QP_XOR1 = 0xB1, DPP_QP_XOR2 = 0x4E, DPP_ROR4 = 0x124, DPP_ROR8 = 0x128 };
+// lane 15 of each row to the next row, lane 31 to rows 2 and 3 (row_mask selects targets)
+enum { DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143 };
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int x) {

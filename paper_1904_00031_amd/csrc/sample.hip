@@ -343,7 +343,22 @@ struct SweepArgs {
   int Npad;
 };
 
-template <typename T, bool C, int R, bool TL>
+// whether the wavefront's sum of x exceeds th, the same on every lane: row sums by DPP,
+// rows combined by the row broadcasts (lane 63 ends with (rows 0 + 1) + (rows 2 + 3)),
+// and one compare on lane 63
+__device__ __forceinline__ int wave_sum_gt(float x, float th) {
+  x += dpp_v<DPP_QP_XOR1>(x);
+  x += dpp_v<DPP_QP_XOR2>(x);
+  x += dpp_v<DPP_ROR4>(x);
+  x += dpp_v<DPP_ROR8>(x);
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), DPP_BCAST15, 0xA, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), DPP_BCAST31, 0xC, 0xF, false));
+  return int((__ballot(x > th) >> 63) & 1ull);
+}
+
+// SM: N <= 64, the spins also held as a wave-uniform bit mask (bit i set: spin i up), so
+// the spins of a proposal and their update are scalar bit operations
+template <typename T, bool C, int R, bool TL, bool SM>
 __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> &tb,
                                             const SweepArgs &a, int chain_base) {
   extern __shared__ __align__(16) unsigned char lds_u8[];
@@ -411,9 +426,12 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
   const int total = a.n_discard + a.n_sweeps;
   // spins mirrored in registers (lane l holds sites l, l+64, l+128, l+192) for N <= 256,
   // so that the spin of a proposed site is one readlane
-  const bool sregs = N <= 256;
+  const bool sregs = !SM && N <= 256;
   int sp0 = 0, sp1 = 0, sp2 = 0, sp3 = 0;
-  if (sregs) {
+  uint64_t smask = 0;
+  if constexpr (SM) {
+    smask = __ballot(lane < N && sig[lane] > 0);
+  } else if (sregs) {
     sp0 = lane < N ? sig[lane] : 0;
     sp1 = lane + 64 < N ? sig[lane + 64] : 0;
     sp2 = lane + 128 < N ? sig[lane + 128] : 0;
@@ -468,18 +486,21 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
         thp = lu - __log2f(float(a2p));
         thm = lu - __log2f(float(a2m));
       }
-      Rows cur = load_rows(__builtin_amdgcn_readlane(rowv, 0));
-      for (int l = 0; l < nst; ++l) {
+      // one proposal; with prefetch, the rows of proposal l + 1 go to nxt (the loop below
+      // alternates the two buffers, so no rows are copied)
+      auto proposal = [&](int l, Rows &cur, Rows &nxt) __attribute__((always_inline)) {
         const int ic = __builtin_amdgcn_readlane(iv, l);
         const int kc = __builtin_amdgcn_readlane(kv, l);
-        Rows nxt;
         if constexpr (PF) {
           nxt = load_rows(__builtin_amdgcn_readlane(rowv, l + 1 < nst ? l + 1 : l));
         } else {
           if (l > 0) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
         }
         int s, sk;
-        if (sregs) {
+        if constexpr (SM) {
+          s = ((smask >> ic) & 1ull) ? 1 : -1;
+          sk = flip ? -s : (((smask >> kc) & 1ull) ? 1 : -1);
+        } else if (sregs) {
           s = __builtin_amdgcn_readlane(ic < 64 ? sp0 : (ic < 128 ? sp1 : (ic < 192 ? sp2 : sp3)),
                                         ic & 63);
           sk = flip ? -s
@@ -506,9 +527,8 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
                 if (lane + 64 * r < M) pm *= float(vabs2(term[r]));
               lp += __log2f(pm);
             }
-            lp = wave_sum_dpp(lp);
             const float th = readlane_v(s > 0 ? thp : thm, l);
-            accept = __builtin_amdgcn_readfirstlane(int(lp > th));
+            accept = wave_sum_gt(lp, th);
           } else {
             T pm = T(1);
             int pe = 0;
@@ -533,16 +553,18 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
             accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
           }
           if (accept) {
+            // every lane updates (no branch on the lane); lanes past M carry values that
+            // no sum reads and that the end of the sweep clears
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-              if (lane + 64 * r < M) {
-                thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
-                if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
-                t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
-              }
+              thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
+              if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
+              t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
             }
-            // spin registers (one lane each) and the LDS copy
-            if (sregs) {
+            // spin registers (one lane each) or the mask, and the LDS copy
+            if constexpr (SM) {
+              smask ^= (1ull << ic) | (flip ? 0ull : (1ull << kc));
+            } else if (sregs) {
               if (ic < 64)
                 sp0 = lane == (ic & 63) ? -s : sp0;
               else if (ic < 128)
@@ -566,18 +588,35 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
               sig[ic] = int8_t(-s);
               if (!flip) sig[kc] = int8_t(s);
             }
-            if (!sregs) wave_sync();
+            if (!SM && !sregs) wave_sync();
             ++acc_count;
           }
         }
-        if constexpr (PF) cur = nxt;
+      };
+      Rows ra = load_rows(__builtin_amdgcn_readlane(rowv, 0)), rb;
+      if constexpr (PF) {
+        int l = 0;
+        for (; l + 1 < nst; l += 2) {
+          proposal(l, ra, rb);
+          proposal(l + 1, rb, ra);
+        }
+        if (l < nst) proposal(l, ra, rb);
+      } else {
+        for (int l = 0; l < nst; ++l) proposal(l, ra, rb);
       }
     }
     wave_sync();
-    // end of sweep: tanh from the exact angles
+    // end of sweep: tanh from the exact angles (zero, with the angles, past M)
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (lane + 64 * r < M) t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
+    for (int r = 0; r < R; ++r) {
+      if (lane + 64 * r < M) {
+        t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
+      } else {
+        t[r] = vmake<T, C>(T(0), T(0));
+        thr[r] = 0.0;
+        thi[r] = 0.0;
+      }
+    }
     if (sw >= a.n_discard) {
       const int64_t smp = int64_t(sw - a.n_discard) * a.n_chains + chain;
       int8_t *dst = a.samples + smp * N;
@@ -609,9 +648,9 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
   if (lane == 0 && a.n_acc) a.n_acc[chain] = acc_count;
 }
 
-template <typename T, bool C, int R, bool TL>
+template <typename T, bool C, int R, bool TL, bool SM>
 __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepArgs a) {
-  sweep_block<T, C, R, TL>(dm, tb, a, blockIdx.x * (blockDim.x >> 6));
+  sweep_block<T, C, R, TL, SM>(dm, tb, a, blockIdx.x * (blockDim.x >> 6));
 }
 
 // ---------------------------------------------------------------------------------
@@ -631,7 +670,7 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const SweepJob<T> *__restri
                                                      const int2 *__restrict__ bmap) {
   const int2 bm = bmap[blockIdx.x];  // (job, first chain of the block)
   const SweepJob<T> J = jobs[bm.x];
-  sweep_block<T, C, R, false>(J.dm, J.tb, J.a, bm.y);
+  sweep_block<T, C, R, false, false>(J.dm, J.tb, J.a, bm.y);
 }
 
 template <typename T, typename PT>
@@ -818,11 +857,23 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   // set is contained in the connected set: flips with TFIM, exchanges with Heisenberg
   const bool shared_rows = (m->ham == NQS_TFIM && flip) || (m->ham == NQS_HEISENBERG && !flip);
   dim3 grid((n_chains + wpb - 1) / wpb);
-  if (shared_rows && tab_lds + wave_lds <= size_t(m->max_lds)) {
-    hipLaunchKernelGGL((k_sweep<T, C, R, true>), grid, dim3(64 * wpb), tab_lds + wave_lds, st,
-                       dev_model(m), tables_of<T>(m), a);
+  const bool tl = shared_rows && tab_lds + wave_lds <= size_t(m->max_lds);
+  if constexpr (R <= 4) {
+    if (m->N <= 64) {
+      if (tl)
+        hipLaunchKernelGGL((k_sweep<T, C, R, true, true>), grid, dim3(64 * wpb),
+                           tab_lds + wave_lds, st, dev_model(m), tables_of<T>(m), a);
+      else
+        hipLaunchKernelGGL((k_sweep<T, C, R, false, true>), grid, dim3(64 * wpb), wave_lds, st,
+                           dev_model(m), tables_of<T>(m), a);
+      return hipGetLastError();
+    }
+  }
+  if (tl) {
+    hipLaunchKernelGGL((k_sweep<T, C, R, true, false>), grid, dim3(64 * wpb), tab_lds + wave_lds,
+                       st, dev_model(m), tables_of<T>(m), a);
   } else {
-    hipLaunchKernelGGL((k_sweep<T, C, R, false>), grid, dim3(64 * wpb), wave_lds, st,
+    hipLaunchKernelGGL((k_sweep<T, C, R, false, false>), grid, dim3(64 * wpb), wave_lds, st,
                        dev_model(m), tables_of<T>(m), a);
   }
   return hipGetLastError();
