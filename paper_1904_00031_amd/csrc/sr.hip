@@ -416,10 +416,12 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
 
 // ---- x, r and p of one CG iteration in one block (small parameter counts) ----------
 // alpha = rr / p^dagger Ap; x += alpha p; r -= alpha Ap; rr_new = r^dagger r;
-// beta = rr_new / rr; p = r + beta p (+ direction tables). Every thread updates the same
-// elements in both passes, so the block needs no barrier between them beyond the sum.
+// beta = rr_new / rr; p = r + beta p (+ direction tables). Thread t owns elements
+// t + kXrpThreads i (i < kXrpPer): all their loads are issued before the sum of p^dagger Ap
+// is formed, and the values stay in registers between the two passes.
 constexpr int kXrpThreads = 1024;
-constexpr int64_t kXrpMaxParams = 8192;
+constexpr int kXrpPer = 4;
+constexpr int64_t kXrpMaxParams = int64_t(kXrpThreads) * kXrpPer;
 
 template <typename T, bool C>
 __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const double *dpart,
@@ -429,42 +431,51 @@ __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const doub
                                                         T *vb, double *va, CGState *st) {
   if (st->done) return;
   __shared__ double lds[kXrpThreads / 64];
+  constexpr int cs = C ? 2 : 1;
   const int64_t P = int64_t(N) + M + int64_t(N) * M;
+  double xv[kXrpPer][cs], rv[kXrpPer][cs], pv[kXrpPer][cs], av[kXrpPer][cs];
+#pragma unroll
+  for (int i = 0; i < kXrpPer; ++i) {
+    const int64_t k = threadIdx.x + int64_t(kXrpThreads) * i;
+    const int64_t kk = k < P ? k : 0;
+#pragma unroll
+    for (int c = 0; c < cs; ++c) {
+      xv[i][c] = x[cs * kk + c];
+      rv[i][c] = r[cs * kk + c];
+      pv[i][c] = p[cs * kk + c];
+      av[i][c] = Ap[cs * kk + c];
+    }
+  }
   const double pAp = block_sum(dpart, nparts, 1, lds);
   const double rr = st->rr[parity];
   const double alpha = rr / pAp;
   double acc = 0.0;
-  for (int64_t k = threadIdx.x; k < P; k += kXrpThreads) {
-    if (C) {
-      x[2 * k] += alpha * p[2 * k];
-      x[2 * k + 1] += alpha * p[2 * k + 1];
-      const double r0 = r[2 * k] - alpha * Ap[2 * k];
-      const double r1 = r[2 * k + 1] - alpha * Ap[2 * k + 1];
-      r[2 * k] = r0;
-      r[2 * k + 1] = r1;
-      acc += r0 * r0;
-      acc += r1 * r1;
-    } else {
-      x[k] += alpha * p[k];
-      const double r0 = r[k] - alpha * Ap[k];
-      r[k] = r0;
-      acc += r0 * r0;
+#pragma unroll
+  for (int i = 0; i < kXrpPer; ++i) {
+    const int64_t k = threadIdx.x + int64_t(kXrpThreads) * i;
+    if (k < P) {
+#pragma unroll
+      for (int c = 0; c < cs; ++c) {
+        xv[i][c] += alpha * pv[i][c];
+        rv[i][c] -= alpha * av[i][c];
+        x[cs * k + c] = xv[i][c];
+        r[cs * k + c] = rv[i][c];
+        acc += rv[i][c] * rv[i][c];
+      }
     }
   }
   const double rr_new = block_reduce(acc, lds);
   const double beta = rr_new / rr;
-  for (int64_t k = threadIdx.x; k < P; k += kXrpThreads) {
-    double pr, pi = 0.0;
-    if (C) {
-      pr = r[2 * k] + beta * p[2 * k];
-      pi = r[2 * k + 1] + beta * p[2 * k + 1];
-      p[2 * k] = pr;
-      p[2 * k + 1] = pi;
-    } else {
-      pr = r[k] + beta * p[k];
-      p[k] = pr;
+#pragma unroll
+  for (int i = 0; i < kXrpPer; ++i) {
+    const int64_t k = threadIdx.x + int64_t(kXrpThreads) * i;
+    if (k < P) {
+      const double pr = rv[i][0] + beta * pv[i][0];
+      const double pi = C ? rv[i][cs - 1] + beta * pv[i][cs - 1] : 0.0;
+      p[cs * k] = pr;
+      if (C) p[cs * k + cs - 1] = pi;
+      dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va);
     }
-    dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va);
   }
   if (threadIdx.x == 0) {
     const int iters = st->iters + 1;
