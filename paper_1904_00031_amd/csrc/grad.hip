@@ -636,52 +636,40 @@ __device__ __forceinline__ int svc_rows(int64_t send, int64_t g) {
 }
 
 // the spin masks of rows lane / 4 (mrow) and lane % 16 (mlo) and the T rows of one
-// 16-sample group. Loads are
-// unconditional with selects after them (no branches around loads). FULL: all 16 rows
-// valid. Otherwise rows outside the group read a valid row of the group (or row 0) and
-// are zeroed. Hidden tiles below JV - 1 are complete; tile JV - 1 reads columns j >= M
-// past the row end (next row, or the slack after T) and zeroes them; tiles from JV on
-// hold no hidden unit and are not loaded.
-template <typename T, int JT, int JV, bool FULL>
+// 16-sample group (rows 4 hi + r, hidden tiles below JV). One code path for every group:
+// rows past the last valid one (rows_here of them, 0 past the end of the split) read the
+// last valid row instead, and their y is zeroed later, so their Z = conj(T) y vanishes
+// exactly; columns j >= M of the last tile read the next row (or the slack after T) and
+// meet zero direction entries in the JVP and ignored output rows in the VJP. Addresses
+// are a uniform row base plus a 32-bit lane offset.
+template <typename T, int JT, int JV>
 __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
                                          const T *__restrict__ Tm, int M, int64_t g,
-                                         int rows_here, int lane, int lo, int hi,
-                                         uint64_t &mrow, bool &row_ok, uint64_t &mlo,
+                                         int64_t send, int rows_here, int lane, int lo, int hi,
+                                         uint64_t &mrow, uint64_t &mlo,
                                          V<T, true> (&tv)[JT][4]) {
-  const int64_t gc = FULL || rows_here > 0 ? g : 0;
-  mlo = masks[gc + (FULL || lo < rows_here ? lo : 0)];
-  {
-    const int rr = lane >> 2;
-    row_ok = FULL || rr < rows_here;
-    const uint64_t x = masks[gc + (row_ok ? rr : 0)];
-    mrow = row_ok ? x : 0ull;
-  }
+  const int64_t gb = rows_here > 0 ? g : send - 1;
+  const int rmax = rows_here > 0 ? rows_here - 1 : 0;
+  const uint64_t *mb = masks + gb;
+  mrow = mb[min(lane >> 2, rmax)];
+  mlo = mb[min(lo, rmax)];
+  const T *tb = Tm + 2 * gb * int64_t(M);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int rr = MF<T>::row(hi, r);
-    const bool okr = FULL || rr < rows_here;
-    const T *rowp = Tm + 2 * ((gc + (okr ? rr : 0)) * M + lo);
+    const uint32_t off = uint32_t(2 * (min(MF<T>::row(hi, r), rmax) * M + lo));
 #pragma unroll
-    for (int a = 0; a < JT; ++a) {
-      if (a >= JV) {
-        tv[a][r] = vmake<T, true>(T(0), T(0));
-        continue;
-      }
-      const V<T, true> x = vload<T, true>(rowp, a * 16);
-      const bool ok = okr && (a < JV - 1 || a * 16 + lo < M);
-      tv[a][r] = ok ? x : vmake<T, true>(T(0), T(0));
-    }
+    for (int a = 0; a < JT; ++a)
+      tv[a][r] = a < JV ? vload<T, true>(tb + off, a * 16) : vmake<T, true>(T(0), T(0));
   }
 }
 
 // The group's spins as floats in the wavefront's LDS tile [16][kSpinStride]: row rr,
 // column c holds s_c (+/-1) for c < N, 1 at c = N (the ones column of the bias
-// gradients), 0 beyond and in rows outside the group. Lane l writes row l / 4, columns
+// gradients), 0 beyond (rows past the group's end repeat a valid row). Lane l writes row l / 4, columns
 // 16 (l % 4) .. 16 (l % 4) + 15.
 constexpr int kSpinStride = 66;  // 2-float skew per row: conflict-free A-operand reads
 template <typename T>
-__device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, bool row_ok, int N,
-                                              int lane) {
+__device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, int N, int lane) {
   const int rr = lane >> 2, c0 = 16 * (lane & 3);
   const uint32_t bits = uint32_t(mrow >> c0) & 0xffffu;
   T *dst = tile + rr * kSpinStride + c0;
@@ -692,7 +680,7 @@ __device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, bool row_o
     for (int u = 0; u < 2; ++u) {
       const int c = c0 + t + u;
       const T s = ((bits >> (t + u)) & 1u) ? T(1) : T(-1);
-      v2[u] = !row_ok ? T(0) : (c < N ? s : (c == N ? T(1) : T(0)));
+      v2[u] = c < N ? s : (c == N ? T(1) : T(0));
     }
     *reinterpret_cast<float2 *>(dst + t) = make_float2(v2[0], v2[1]);
   }
@@ -856,191 +844,214 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
 #pragma unroll
   for (int b = 0; b < NT; ++b) ga[b] = T(0);
   double ysr = 0.0, ysi = 0.0;
-  // software pipeline: the masks and T rows of the pair's next group are loaded while
-  // the current group's O^dagger y contraction runs
-  int64_t g = sbeg + 16 * pr;
-  int rows_here = svc_rows(send, g);
-  uint64_t mrow, mlo;
-  bool row_ok;
-  V<T, true> tv[JT][4];
-  if (iters > 0) {
-    if (rows_here == 16)
-      svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
-    else
-      svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
-  }
-  for (int64_t it = 0; it < iters; ++it) {
-    // spins of the group into the tile (the previous group's reads are done: same wave)
-    svc_spin_tile<T>(stile, mrow, row_ok, N, lane);
-    wave_sync();
-    // ---- X_h = S (plane h of V)^T over the valid hidden tiles, bf16 split ----
-    // A (sample lo, k group g): the spins of sites 8 (g / 3) .. + 7 from the byte table;
-    // sites past N meet zeros in B. Operands of step t + 1 are read during step t.
-    Acc x[JT];
+  // per-lane constants of the group loop: the byte shift of the JVP A operand at each
+  // step (k group 4 t + hi covers sites 8 ((4 t + hi) / 3) ..), the lane's bias entries
+  constexpr int KSMAX = 6;  // N <= 63: 3 ceil(N / 8) <= 24 k groups
+  uint32_t ash[KSMAX];
 #pragma unroll
-    for (int a = 0; a < JT; ++a) x[a] = Acc{0, 0, 0, 0};
-    {
-      const uint4 *tab4 = reinterpret_cast<const uint4 *>(stab);
-      const uint4 *Vh = Vb + h * G * JVW + lo;
-      int g8 = hi;
-      uint4 an = tab4[uint32_t(mlo >> (8 * (g8 / 3))) & 0xffu];
-      uint4 bn[JV];
+  for (int t = 0; t < KSMAX; ++t) ash[t] = uint32_t(8 * ((4 * t + hi) / 3));
+  // the loop is specialised for the plane H of the wavefront (uniform branch below):
+  // plane 1 uses i T = (-Im T, Re T), so that with (Re', Im') the plane's view of T
+  //   y += (Re', Im') (X_H + vb_H),  Z_H = Re' Re y + Im' Im y
+  auto run = [&](auto hc) __attribute__((always_inline)) {
+    constexpr int H = decltype(hc)::value;
+    T vbr[JV], var[NVA];
 #pragma unroll
-      for (int a = 0; a < JV; ++a) bn[a] = Vh[g8 * JVW + 16 * a];
-      for (int t = 0; t < KS; ++t) {
-        const uint4 av = an;
-        uint4 bv[JV];
+    for (int a = 0; a < JV; ++a) vbr[a] = vbl[H][a * 16 + lo];
 #pragma unroll
-        for (int a = 0; a < JV; ++a) bv[a] = bn[a];
-        if (t + 1 < KS) {
-          g8 += 4;
-          an = tab4[uint32_t(mlo >> (8 * (g8 / 3))) & 0xffu];
+    for (int c = 0; c < NVA; ++c) var[c] = val[H][lo + 16 * c];
+    const uint4 *tab4 = reinterpret_cast<const uint4 *>(stab);
+    const uint4 *Vh = Vb + H * G * JVW + lo;
+    // software pipeline: the masks and T rows of the pair's next group are loaded while
+    // the current group's O^dagger y contraction runs
+    int64_t g = sbeg + 16 * pr;
+    int rows_here = svc_rows(send, g);
+    uint64_t mrow, mlo;
+    V<T, true> tv[JT][4];
+    if (iters > 0) svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mrow, mlo, tv);
+    for (int64_t it = 0; it < iters; ++it) {
+      // spins of the group into the tile (the previous group's reads are done: same wave)
+      svc_spin_tile<T>(stile, mrow, N, lane);
+      wave_sync();
+      // ---- X_H = S (plane H of V)^T over the valid hidden tiles, bf16 split ----
+      // A (sample lo, k group g): the spins of sites 8 (g / 3) .. + 7 from the byte
+      // table; sites past N meet zeros in B. Steps unrolled to KSMAX, uniform guards.
+      Acc x[JV];
 #pragma unroll
-          for (int a = 0; a < JV; ++a) bn[a] = Vh[g8 * JVW + 16 * a];
-        }
+      for (int t = 0; t < KSMAX; ++t) {
+        if (t < KS) {
+          const uint4 av = tab4[uint32_t(mlo >> ash[t]) & 0xffu];
+          uint4 bv[JV];
 #pragma unroll
-        for (int a = 0; a < JV; ++a) x[a] = mfma_bf16(av, bv[a], x[a]);
-      }
-    }
-    // ---- this plane's share of y for rows MF::row(hi, r) ----
-    T yre[4], yim[4];
+          for (int a = 0; a < JV; ++a) bv[a] = Vh[(4 * t + hi) * JVW + 16 * a];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      yre[r] = T(0);
-      yim[r] = T(0);
-    }
-    // plane 1 works with i T = (-Im T, Re T): then both planes share the formulas
-    //   y += (Re, Im of the rotated T) (X_h + vb_h),  Z_h = Re' Re y + Im' Im y
-    if (__builtin_amdgcn_readfirstlane(h)) {
-#pragma unroll
-      for (int a = 0; a < JT; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tv[a][r] = vmake<T, true>(-tv[a][r].im, tv[a][r].re);
-    }
-#pragma unroll
-    for (int a = 0; a < JT; ++a) {
-      if (a >= JV) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const T xv = x[a][r] + vbl[h][a * 16 + lo];
-        yre[r] += tv[a][r].re * xv;
-        yim[r] += tv[a][r].im * xv;
-      }
-    }
-    if (h == 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const T *srow = stile + MF<T>::row(hi, r) * kSpinStride;
-#pragma unroll
-        for (int c = 0; c < NVA; ++c) {
-          // columns >= N of the tile are 1 (c = N) or 0, and val is 0 there
-          const T sgn = srow[lo + 16 * c];
-          yre[r] += sgn * val[0][lo + 16 * c];
-          yim[r] += sgn * val[1][lo + 16 * c];
+          for (int a = 0; a < JV; ++a)
+            x[a] = mfma_bf16(av, bv[a], t == 0 ? Acc{0, 0, 0, 0} : x[a]);
         }
       }
-    }
-    const int par = int(it & 1);
+      // ---- this plane's share of y for rows MF::row(hi, r) ----
+      T yre[4], yim[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = MF<T>::row(hi, r);
-      yre[r] = rowsum16(yre[r]);
-      yim[r] = rowsum16(yim[r]);
-      if (rr >= rows_here) {
+      for (int r = 0; r < 4; ++r) {
         yre[r] = T(0);
         yim[r] = T(0);
       }
-      if (lo == 0) {
-        ybuf[par][pr][h][rr][0] = yre[r];
-        ybuf[par][pr][h][rr][1] = yim[r];
-      }
-    }
-    // publish this wavefront's partial sums, then wait (bounded) for the partner's: the
-    // two wavefronts of a pair synchronise through LDS flags only, so pairs drift apart
-    // and one wavefront's VALU work overlaps the other's matrix-core work on a SIMD
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (lane == 0)
-      __hip_atomic_store(&pflag[wid], int(it + 1), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_WORKGROUP);
-    {
-      int spins = 0;
-#pragma nounroll
-      while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                 &pflag[wid ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) <
-             int(it + 1)) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1 << 24)) {
-          stalled = true;
-          break;
+#pragma unroll
+      for (int a = 0; a < JV; ++a) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T xv = x[a][r] + vbr[a];
+          if constexpr (H == 0) {
+            yre[r] += tv[a][r].re * xv;
+            yim[r] += tv[a][r].im * xv;
+          } else {
+            yre[r] -= tv[a][r].im * xv;
+            yim[r] += tv[a][r].re * xv;
+          }
         }
       }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      if constexpr (H == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = MF<T>::row(hi, r);
-      yre[r] += ybuf[par][pr][h ^ 1][rr][0];
-      yim[r] += ybuf[par][pr][h ^ 1][rr][1];
-      if (h == 0 && lo == 0) {
-        ysr += double(yre[r]);
-        ysi += double(yim[r]);
+        for (int r = 0; r < 4; ++r) {
+          const T *srow = stile + MF<T>::row(hi, r) * kSpinStride;
+#pragma unroll
+          for (int c = 0; c < NVA; ++c) {
+            // columns >= N of the tile are 1 (c = N) or 0, and va is 0 there
+            const T sgn = srow[lo + 16 * c];
+            yre[r] += sgn * var[c];
+          }
+        }
       }
-    }
-    // ---- plane h of Z = conj(T) y (row M: Z = y), then the next group's loads ----
-    T z[4][JT];
+      if constexpr (H == 1) {
+        // the imaginary part of va enters through plane 1's share of Im y
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+        for (int r = 0; r < 4; ++r) {
+          const T *srow = stile + MF<T>::row(hi, r) * kSpinStride;
 #pragma unroll
-      for (int a = 0; a < JT; ++a) {
-        const int j = a * 16 + lo;
-        const T zq = tv[a][q].re * yre[q] + tv[a][q].im * yim[q];
-        z[q][a] = (a == JT - 1 && j == M) ? (h == 0 ? yre[q] : yim[q]) : zq;
+          for (int c = 0; c < NVA; ++c) yim[r] += srow[lo + 16 * c] * var[c];
+        }
       }
-    }
-    __builtin_amdgcn_sched_barrier(0);  // keep the next loads after the last reads of tv
-    if (it + 1 < iters) {
-      g += 16 * PAIRS;
-      rows_here = svc_rows(send, g);
-      if (rows_here == 16)
-        svc_load<T, JT, JV, true>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
-      else
-        svc_load<T, JT, JV, false>(masks, Tm, M, g, rows_here, lane, lo, hi, mrow, row_ok, mlo, tv);
-    }
-    // ---- plane h of Z^T S over the 16 samples, bf16 split of Z ----
-    // k of lane group hi: element e < 4 pairs part h of Z at sample 4 hi + e with that
-    // sample's spin, e >= 4 part m; a second step takes part l (upper half zero).
-    // With M a multiple of 16 the last hidden tile holds only row M (Z = y): its sums
-    // g_a = sum_s y_s s_s are accumulated on the vector units instead.
-    uint4 sb[NT];
+      const int par = int(it & 1);
 #pragma unroll
-    for (int b = 0; b < NT; ++b) {
-      T bs[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bs[q] = stile[MF<T>::row(hi, q) * kSpinStride + b * 16 + lo];
-      if constexpr (AROW) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ga[b] += (h == 0 ? yre[q] : yim[q]) * bs[q];
+      for (int r = 0; r < 4; ++r) {
+        yre[r] = rowsum16(yre[r]);
+        yim[r] = rowsum16(yim[r]);
       }
-      const uint32_t s01 = pack_hi(bs[0], bs[1]), s23 = pack_hi(bs[2], bs[3]);
-      sb[b] = make_uint4(s01, s23, s01, s23);
-    }
+      if (rows_here < 16) {
 #pragma unroll
-    for (int a = 0; a < JTM; ++a) {
-      T r[4], l[4];
+        for (int r = 0; r < 4; ++r)
+          if (MF<T>::row(hi, r) >= rows_here) {
+            yre[r] = T(0);
+            yim[r] = T(0);
+          }
+      }
+      if (lo == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = MF<T>::row(hi, r);
+          ybuf[par][pr][H][rr][0] = yre[r];
+          ybuf[par][pr][H][rr][1] = yim[r];
+        }
+      }
+      // publish this wavefront's partial sums, then wait (bounded) for the partner's: the
+      // two wavefronts of a pair synchronise through LDS flags only, so pairs drift apart
+      // and one wavefront's VALU work overlaps the other's matrix-core work on a SIMD
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0)
+        __hip_atomic_store(&pflag[wid], int(it + 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+      {
+        int spins = 0;
+#pragma nounroll
+        while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                   &pflag[wid ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+               int(it + 1)) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > (1 << 24)) {
+            stalled = true;
+            break;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = MF<T>::row(hi, r);
+        yre[r] += ybuf[par][pr][H ^ 1][rr][0];
+        yim[r] += ybuf[par][pr][H ^ 1][rr][1];
+      }
+      if constexpr (H == 0) {
+        if (lo == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            ysr += double(yre[r]);
+            ysi += double(yim[r]);
+          }
+        }
+      }
+      // ---- plane H of Z = conj(T) y (row M: Z = y), then the next group's loads ----
+      T z[4][JTM];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        r[q] = bf16_rest(z[q][a]);
-        l[q] = bf16_rest(r[q]);
+#pragma unroll
+        for (int a = 0; a < JTM; ++a) {
+          T zq;
+          if constexpr (H == 0)
+            zq = tv[a][q].re * yre[q] + tv[a][q].im * yim[q];
+          else
+            zq = tv[a][q].re * yim[q] - tv[a][q].im * yre[q];
+          if constexpr (!AROW) {
+            if (a == JT - 1 && a * 16 + lo == M) zq = H == 0 ? yre[q] : yim[q];
+          }
+          z[q][a] = zq;
+        }
       }
-      const uint4 a0 = make_uint4(pack_hi(z[0][a], z[1][a]), pack_hi(z[2][a], z[3][a]),
-                                  pack_hi(r[0], r[1]), pack_hi(r[2], r[3]));
-      const uint4 a1 = make_uint4(pack_hi(l[0], l[1]), pack_hi(l[2], l[3]), 0u, 0u);
+      __builtin_amdgcn_sched_barrier(0);  // keep the next loads after the last reads of tv
+      // unconditional (after the last group they re-read a valid row), so the loaded
+      // registers are the next iteration's operands with no merge copies
+      g += 16 * PAIRS;
+      rows_here = svc_rows(send, g);
+      svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mrow, mlo, tv);
+      // ---- plane H of Z^T S over the 16 samples, bf16 split of Z ----
+      // k of lane group hi: element e < 4 pairs part h of Z at sample 4 hi + e with that
+      // sample's spin, e >= 4 part m; a second step takes part l (upper half zero).
+      // With M a multiple of 16 the last hidden tile holds only row M (Z = y): its sums
+      // g_a = sum_s y_s s_s are accumulated on the vector units instead.
+      uint4 sb[NT];
 #pragma unroll
-      for (int b = 0; b < NT; ++b) acc[a][b] = mfma_bf16(a0, sb[b], acc[a][b]);
+      for (int b = 0; b < NT; ++b) {
+        T bs[4];
 #pragma unroll
-      for (int b = 0; b < NT; ++b) acc[a][b] = mfma_bf16(a1, sb[b], acc[a][b]);
+        for (int q = 0; q < 4; ++q) bs[q] = stile[MF<T>::row(hi, q) * kSpinStride + b * 16 + lo];
+        if constexpr (AROW) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ga[b] += (H == 0 ? yre[q] : yim[q]) * bs[q];
+        }
+        const uint32_t s01 = pack_hi(bs[0], bs[1]), s23 = pack_hi(bs[2], bs[3]);
+        sb[b] = make_uint4(s01, s23, s01, s23);
+      }
+#pragma unroll
+      for (int a = 0; a < JTM; ++a) {
+        T r[4], l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          r[q] = bf16_rest(z[q][a]);
+          l[q] = bf16_rest(r[q]);
+        }
+        const uint4 a0 = make_uint4(pack_hi(z[0][a], z[1][a]), pack_hi(z[2][a], z[3][a]),
+                                    pack_hi(r[0], r[1]), pack_hi(r[2], r[3]));
+        const uint4 a1 = make_uint4(pack_hi(l[0], l[1]), pack_hi(l[2], l[3]), 0u, 0u);
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = mfma_bf16(a0, sb[b], acc[a][b]);
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = mfma_bf16(a1, sb[b], acc[a][b]);
+      }
     }
-  }
+  };
+  if (h == 0)
+    run(std::integral_constant<int, 0>{});
+  else
+    run(std::integral_constant<int, 1>{});
   if constexpr (AROW) {
     // lanes of one column (lo) hold the sums of rows 4 hi .. 4 hi + 3: add the four
 #pragma unroll
