@@ -691,11 +691,14 @@ __global__ void k_tables_batch(const TabJob<T, PT> *__restrict__ jobs,
 
 // ---------------------------------------------------------------------------------
 // Local energy of arbitrary configurations from precomputed rows T[s][j] = tanh(theta_j)
-// (the matrix-core kernel k_theta_tanh): one sample per wavefront at full occupancy; the
-// C/S rows of the connected configurations are staged in LDS when they fit (TL).
+// (the matrix-core kernel k_theta_tanh): one sample per wavefront, eight wavefronts per
+// block sharing the C/S rows of the connected configurations, staged in LDS when they fit
+// (TL). TP > 0 (M <= 16 TP <= 256): four configurations per pass, TP hidden tiles of 16
+// per lane group (eloc_grouped); TP = 0: R hidden units per lane (eloc_regs).
 // ---------------------------------------------------------------------------------
-template <typename T, bool C, int R, bool TL>
-__global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
+constexpr int kElocWaves = 8;
+template <typename T, bool C, int R, bool TL, int TP>
+__global__ __launch_bounds__(64 * kElocWaves) void k_local_energy(DevModel dm, Tables<T> tb,
                                                        const int8_t *__restrict__ sigma,
                                                        const T *__restrict__ Tm, int64_t n,
                                                        double *eloc, int Npad, int cs_rows) {
@@ -726,8 +729,8 @@ __global__ __launch_bounds__(256) void k_local_energy(DevModel dm, Tables<T> tb,
     wave_sync();
     const T *trow = Tm + smp * M * cs;
     double er, ei;
-    if (M <= 256) {
-      eloc_grouped<T, C, TL, (4 * R < 16 ? 4 * R : 16)>(dm, tb, sig, trow, lane, lC, lS, er, ei);
+    if constexpr (TP > 0) {
+      eloc_grouped<T, C, TL, TP>(dm, tb, sig, trow, lane, lC, lS, er, ei);
     } else {
       V<T, C> t[R];
 #pragma unroll
@@ -898,30 +901,30 @@ hipError_t sweep_t(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   return hipErrorInvalidValue;
 }
 
-template <typename T, bool C, int R>
+template <typename T, bool C, int R, int TP>
 hipError_t eloc_r(const nqs_model *m, const int8_t *sigma, const void *Tm, int64_t n,
                   void *eloc, hipStream_t st) {
   const int Npad = round_up(m->N, 16);
-  const int wpb = 4;
+  const int wpb = kElocWaves;
   const int cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
   const size_t tab_lds = size_t(2) * cs_rows * m->M * sizeof(T) * (C ? 2 : 1);
   const size_t wave_lds = size_t(wpb) * Npad;
-  // persistent grid: as many blocks as fit on the device at once (at most 8 per CU)
+  // persistent grid: as many blocks as fit on the device at once (at most 4 per CU)
   const bool tl = tab_lds + wave_lds <= size_t(m->max_lds) / 2;
-  int per_cu = 8;
+  int per_cu = 4;
   if (tl) {
     const int by_lds = int(size_t(160 * 1024) / (tab_lds + wave_lds));
-    per_cu = by_lds < 1 ? 1 : (by_lds < 8 ? by_lds : 8);
+    per_cu = by_lds < 1 ? 1 : (by_lds < 4 ? by_lds : 4);
   }
   int64_t blocks = (n + wpb - 1) / wpb;
   if (blocks > int64_t(per_cu) * m->cu_count) blocks = int64_t(per_cu) * m->cu_count;
   dim3 grid((unsigned)blocks);
   if (tl)
-    hipLaunchKernelGGL((k_local_energy<T, C, R, true>), grid, dim3(64 * wpb), tab_lds + wave_lds,
-                       st, dev_model(m), tables_of<T>(m), sigma, (const T *)Tm, n,
-                       (double *)eloc, Npad, cs_rows);
+    hipLaunchKernelGGL((k_local_energy<T, C, R, true, TP>), grid, dim3(64 * wpb),
+                       tab_lds + wave_lds, st, dev_model(m), tables_of<T>(m), sigma,
+                       (const T *)Tm, n, (double *)eloc, Npad, cs_rows);
   else
-    hipLaunchKernelGGL((k_local_energy<T, C, R, false>), grid, dim3(64 * wpb), wave_lds, st,
+    hipLaunchKernelGGL((k_local_energy<T, C, R, false, TP>), grid, dim3(64 * wpb), wave_lds, st,
                        dev_model(m), tables_of<T>(m), sigma, (const T *)Tm, n, (double *)eloc,
                        Npad, cs_rows);
   return hipGetLastError();
@@ -931,13 +934,20 @@ template <typename T, bool C>
 hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64_t n,
                   void *eloc, hipStream_t st) {
   if (n == 0) return hipSuccess;
+  // M <= 256: the smallest tile count of 16 hidden units per lane group covering M
+  const int tp = (m->M + 15) / 16;
+  if (tp <= 2) return eloc_r<T, C, 1, 2>(m, sigma, Tm, n, eloc, st);
+  if (tp <= 3) return eloc_r<T, C, 1, 3>(m, sigma, Tm, n, eloc, st);
+  if (tp <= 4) return eloc_r<T, C, 1, 4>(m, sigma, Tm, n, eloc, st);
+  if (tp <= 5) return eloc_r<T, C, 1, 5>(m, sigma, Tm, n, eloc, st);
+  if (tp <= 6) return eloc_r<T, C, 1, 6>(m, sigma, Tm, n, eloc, st);
+  if (tp <= 8) return eloc_r<T, C, 1, 8>(m, sigma, Tm, n, eloc, st);
+  if (tp <= 12) return eloc_r<T, C, 1, 12>(m, sigma, Tm, n, eloc, st);
+  if (tp <= 16) return eloc_r<T, C, 1, 16>(m, sigma, Tm, n, eloc, st);
   const int r = (m->M + 63) / 64;
-  if (r <= 1) return eloc_r<T, C, 1>(m, sigma, Tm, n, eloc, st);
-  if (r <= 2) return eloc_r<T, C, 2>(m, sigma, Tm, n, eloc, st);
-  if (r <= 4) return eloc_r<T, C, 4>(m, sigma, Tm, n, eloc, st);
-  if (r <= 8) return eloc_r<T, C, 8>(m, sigma, Tm, n, eloc, st);
-  if (r <= 16) return eloc_r<T, C, 16>(m, sigma, Tm, n, eloc, st);
-  return eloc_r<T, C, 32>(m, sigma, Tm, n, eloc, st);
+  if (r <= 8) return eloc_r<T, C, 8, 0>(m, sigma, Tm, n, eloc, st);
+  if (r <= 16) return eloc_r<T, C, 16, 0>(m, sigma, Tm, n, eloc, st);
+  return eloc_r<T, C, 32, 0>(m, sigma, Tm, n, eloc, st);
 }
 
 template <typename T, bool C>
