@@ -28,6 +28,7 @@ import numpy as np
 PEAK_FP32_VALU = 157.3e12
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12
 
 WORKLOADS = {
     "heisenberg1d_n40_cplx_fp32_alpha2": dict(L=40, ndim=1, diag=False, ham=1, J=(1.0, 0.0), h=0.0,
@@ -103,6 +104,16 @@ def sv_flops(n, N, M, cplx):
     if cplx:
         return 8.0 * n * N * M + 16.0 * n * M + 4.0 * n * N
     return 4.0 * n * N * M + 6.0 * n * M + 4.0 * n * N
+
+
+def sv_bytes(n, N, M, cplx, masks):
+    """Algorithmic HBM bytes of one S v product from cached tanh(theta): the T rows (n M
+    values of 4 B, 8 B complex), the spins (one 8-byte mask per sample for the plane-split
+    kernel, else n N int8), the direction in and the product out (P values in double)."""
+    es = 8 if cplx else 4
+    P = N + M + N * M
+    spins = 8.0 * n if masks else float(n) * N
+    return float(n) * M * es + spins + 2.0 * P * (16 if cplx else 8)
 
 
 def recorded_traffic(kernel, workload):
@@ -468,7 +479,21 @@ def main():
     sweep_flops = float(n_samp) * N * M * (12 if w["cplx"] else 4)
     mv_flops = sv_flops(n_samp, N, M, w["cplx"])
     share_sr = sr_ms / (samp_ms + sr_ms)
-    if share_sr > 0.5:
+    # the plane-split product (complex, FP32 or BF16 form, N <= 63) runs its contractions
+    # on the bf16 matrix cores with an exact three-part split (floor ~3x the flops at the
+    # bf16 rate, below the time to stream T once): bounded by HBM. Other shapes run the
+    # FP32 or FP64 16x16x4 MFMA and are reported against that peak.
+    plane_split = w["cplx"] and w["prec"] != 0 and N <= 63
+    if share_sr > 0.5 and plane_split:
+        nbytes = sv_bytes(n_samp, N, M, w["cplx"], True)
+        ach = nbytes / (mv_ms * 1e-3)
+        roof = {"kernel": "S v product (direction tables, fused contraction, partial-sum "
+                          "reduction, centring)", "bound": "hbm",
+                "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": ach / PEAK_HBM, "traffic": recorded_traffic("sv_product", args.workload),
+                "algorithmic_bytes": nbytes,
+                "fp32_equivalent_tflops": mv_flops / (mv_ms * 1e-3) / 1e12}
+    elif share_sr > 0.5:
         peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_MFMA
         ach = mv_flops / (mv_ms * 1e-3)
         roof = {"kernel": "S v product (direction tables, fused contraction, partial-sum "
