@@ -486,31 +486,118 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
         thp = lu - __log2f(float(a2p));
         thm = lu - __log2f(float(a2m));
       }
-      // one proposal; with prefetch, the rows of proposal l + 1 go to nxt (the loop below
-      // alternates the two buffers, so no rows are copied)
-      auto proposal = [&](int l, Rows &cur, Rows &nxt) __attribute__((always_inline)) {
-        const int ic = __builtin_amdgcn_readlane(iv, l);
-        const int kc = __builtin_amdgcn_readlane(kv, l);
+      if constexpr (SM) {
+        // one proposal; with prefetch, the rows of proposal l + 1 go to nxt (the loop
+        // below alternates the two buffers, so no rows are copied)
+        auto proposal = [&](int l, Rows &cur, Rows &nxt) __attribute__((always_inline)) {
+          const int ic = __builtin_amdgcn_readlane(iv, l);
+          const int kc = __builtin_amdgcn_readlane(kv, l);
+          if constexpr (PF) {
+            nxt = load_rows(__builtin_amdgcn_readlane(rowv, l + 1 < nst ? l + 1 : l));
+          } else {
+            if (l > 0) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
+          }
+          const int s = ((smask >> ic) & 1ull) ? 1 : -1;
+          const int sk = flip ? -s : (((smask >> kc) & 1ull) ? 1 : -1);
+          if (sk != s) {  // an exchange of equal spins is the identity move
+            const T ts = T(s);
+            V<T, C> term[R];
+  #pragma unroll
+            for (int r = 0; r < R; ++r) term[r] = vsub(cur.c[r], vscale(vmul(t[r], cur.s[r]), ts));
+            int accept;
+            if constexpr (sizeof(T) == 4) {
+              // log-domain decision: accept iff sum_j log2|term_j|^2 > log2(u) - log2|a|^2
+              float lp = 0.f;
+  #pragma unroll
+              for (int r0 = 0; r0 < R; r0 += 4) {
+                float pm = 1.f;
+  #pragma unroll
+                for (int r = r0; r < r0 + 4 && r < R; ++r)
+                  if (lane + 64 * r < M) pm *= float(vabs2(term[r]));
+                lp += __log2f(pm);
+              }
+              const float th = readlane_v(s > 0 ? thp : thm, l);
+              accept = wave_sum_gt(lp, th);
+            } else {
+              T pm = T(1);
+              int pe = 0;
+  #pragma unroll
+              for (int r = 0; r < R; ++r) {
+                if (lane + 64 * r < M) pm *= vabs2(term[r]);
+                if ((r & 3) == 3) {
+                  int e;
+                  pm = nfrexp(pm, &e);
+                  pe += e;
+                }
+              }
+              {
+                int e;
+                pm = nfrexp(pm, &e);
+                pe += e;
+              }
+              const T pmw = wave_prod_dpp(pm, pe);
+              const double a2 = readlane_v(s > 0 ? a2p : a2m, l);
+              const double q = ldexp(double(pmw), pe) * a2;
+              const double u = readlane_v(uv, l);
+              accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
+            }
+            if (accept) {
+              // with few units per lane every lane updates (no branch on the lane; lanes past
+              // M carry values that no sum reads and that the end of the sweep clears); with
+              // many, the lane test keeps the register allocation of the update compact
+  #pragma unroll
+              for (int r = 0; r < R; ++r) {
+                if (R <= 4 || lane + 64 * r < M) {
+                  thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
+                  if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
+                  t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
+                }
+              }
+              smask ^= (1ull << ic) | (flip ? 0ull : (1ull << kc));
+              if (lane == 0) {
+                sig[ic] = int8_t(-s);
+                if (!flip) sig[kc] = int8_t(s);
+              }
+              ++acc_count;
+            }
+          }
+        };
+        Rows ra = load_rows(__builtin_amdgcn_readlane(rowv, 0)), rb;
         if constexpr (PF) {
-          nxt = load_rows(__builtin_amdgcn_readlane(rowv, l + 1 < nst ? l + 1 : l));
+          int l = 0;
+          for (; l + 1 < nst; l += 2) {
+            proposal(l, ra, rb);
+            proposal(l + 1, rb, ra);
+          }
+          if (l < nst) proposal(l, ra, rb);
         } else {
-          if (l > 0) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
+          for (int l = 0; l < nst; ++l) proposal(l, ra, rb);
         }
-        int s, sk;
-        if constexpr (SM) {
-          s = ((smask >> ic) & 1ull) ? 1 : -1;
-          sk = flip ? -s : (((smask >> kc) & 1ull) ? 1 : -1);
-        } else if (sregs) {
-          s = __builtin_amdgcn_readlane(ic < 64 ? sp0 : (ic < 128 ? sp1 : (ic < 192 ? sp2 : sp3)),
-                                        ic & 63);
-          sk = flip ? -s
-                    : __builtin_amdgcn_readlane(
-                          kc < 64 ? sp0 : (kc < 128 ? sp1 : (kc < 192 ? sp2 : sp3)), kc & 63);
-        } else {
-          s = __builtin_amdgcn_readfirstlane(int(sig[ic]));
-          sk = flip ? -s : __builtin_amdgcn_readfirstlane(int(sig[kc]));
-        }
-        if (sk != s) {  // an exchange of equal spins is the identity move
+      } else {
+        // the same proposal with the spins in registers or LDS (a plain loop: a closure
+        // here made the compiler keep the chain state in scratch memory)
+        Rows cur = load_rows(__builtin_amdgcn_readlane(rowv, 0));
+        for (int l = 0; l < nst; ++l) {
+          const int ic = __builtin_amdgcn_readlane(iv, l);
+          const int kc = __builtin_amdgcn_readlane(kv, l);
+          Rows nxt;
+          if constexpr (PF) {
+            nxt = load_rows(__builtin_amdgcn_readlane(rowv, l + 1 < nst ? l + 1 : l));
+          } else {
+            if (l > 0) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
+          }
+          int s, sk;
+          if (sregs) {
+            s = __builtin_amdgcn_readlane(ic < 64 ? sp0 : (ic < 128 ? sp1 : (ic < 192 ? sp2 : sp3)),
+                                          ic & 63);
+            sk = flip ? -s
+                      : __builtin_amdgcn_readlane(
+                            kc < 64 ? sp0 : (kc < 128 ? sp1 : (kc < 192 ? sp2 : sp3)), kc & 63);
+          } else {
+            s = __builtin_amdgcn_readfirstlane(int(sig[ic]));
+            sk = flip ? -s : __builtin_amdgcn_readfirstlane(int(sig[kc]));
+          }
+          if (sk != s) {  // an exchange of equal spins is the identity move
           const T ts = T(s);
           V<T, C> term[R];
 #pragma unroll
@@ -553,65 +640,58 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
             accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
           }
           if (accept) {
-            // every lane updates (no branch on the lane); lanes past M carry values that
-            // no sum reads and that the end of the sweep clears
+            // with few units per lane every lane updates (no branch on the lane; lanes past
+            // M carry values that no sum reads and that the end of the sweep clears); with
+            // many, the lane test keeps the register allocation of the update compact
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-              thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
-              if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
-              t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
-            }
-            // spin registers (one lane each) or the mask, and the LDS copy
-            if constexpr (SM) {
-              smask ^= (1ull << ic) | (flip ? 0ull : (1ull << kc));
-            } else if (sregs) {
-              if (ic < 64)
-                sp0 = lane == (ic & 63) ? -s : sp0;
-              else if (ic < 128)
-                sp1 = lane == (ic & 63) ? -s : sp1;
-              else if (ic < 192)
-                sp2 = lane == (ic & 63) ? -s : sp2;
-              else
-                sp3 = lane == (ic & 63) ? -s : sp3;
-              if (!flip) {
-                if (kc < 64)
-                  sp0 = lane == (kc & 63) ? s : sp0;
-                else if (kc < 128)
-                  sp1 = lane == (kc & 63) ? s : sp1;
-                else if (kc < 192)
-                  sp2 = lane == (kc & 63) ? s : sp2;
-                else
-                  sp3 = lane == (kc & 63) ? s : sp3;
+              if (R <= 4 || lane + 64 * r < M) {
+                thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
+                if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
+                t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
               }
             }
-            if (lane == 0) {
-              sig[ic] = int8_t(-s);
-              if (!flip) sig[kc] = int8_t(s);
+              // spin registers (one lane each) and the LDS copy
+              if (sregs) {
+                if (ic < 64)
+                  sp0 = lane == (ic & 63) ? -s : sp0;
+                else if (ic < 128)
+                  sp1 = lane == (ic & 63) ? -s : sp1;
+                else if (ic < 192)
+                  sp2 = lane == (ic & 63) ? -s : sp2;
+                else
+                  sp3 = lane == (ic & 63) ? -s : sp3;
+                if (!flip) {
+                  if (kc < 64)
+                    sp0 = lane == (kc & 63) ? s : sp0;
+                  else if (kc < 128)
+                    sp1 = lane == (kc & 63) ? s : sp1;
+                  else if (kc < 192)
+                    sp2 = lane == (kc & 63) ? s : sp2;
+                  else
+                    sp3 = lane == (kc & 63) ? s : sp3;
+                }
+              }
+              if (lane == 0) {
+                sig[ic] = int8_t(-s);
+                if (!flip) sig[kc] = int8_t(s);
+              }
+              if (!sregs) wave_sync();
+              ++acc_count;
             }
-            if (!SM && !sregs) wave_sync();
-            ++acc_count;
           }
+          if constexpr (PF) cur = nxt;
         }
-      };
-      Rows ra = load_rows(__builtin_amdgcn_readlane(rowv, 0)), rb;
-      if constexpr (PF) {
-        int l = 0;
-        for (; l + 1 < nst; l += 2) {
-          proposal(l, ra, rb);
-          proposal(l + 1, rb, ra);
-        }
-        if (l < nst) proposal(l, ra, rb);
-      } else {
-        for (int l = 0; l < nst; ++l) proposal(l, ra, rb);
       }
     }
     wave_sync();
-    // end of sweep: tanh from the exact angles (zero, with the angles, past M)
+    // end of sweep: tanh from the exact angles (zero, with the angles, past M when the
+    // accept update runs on every lane)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (lane + 64 * r < M) {
         t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
-      } else {
+      } else if (R <= 4) {
         t[r] = vmake<T, C>(T(0), T(0));
         thr[r] = 0.0;
         thi[r] = 0.0;
