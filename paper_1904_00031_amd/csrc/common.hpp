@@ -98,6 +98,47 @@ __device__ __forceinline__ float bf16_round(float x) {
   return __uint_as_float(u & 0xffff0000u);
 }
 
+// Exact three-way bf16 split of an FP32 value by truncation: x = h + m + l, h the upper
+// 16 bits of x, m those of r = x - h, l = r - m. Both differences are exact in FP32
+// (r keeps at most 16 significant bits, l at most 8), so l is itself a bf16 and the
+// three parts sum to x exactly. Against a +/-1 operand every product is exact, and a
+// bf16 matrix-core contraction with FP32 accumulation gives the FP32 result up to the
+// order of the additions.
+__device__ __forceinline__ float bf16_rest(float x) {
+  return x - __uint_as_float(__float_as_uint(x) & 0xffff0000u);
+}
+// the upper halves (bf16 truncations) of a and b in one register, a in the low half
+__device__ __forceinline__ uint32_t pack_hi(float a, float b) {
+  return (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xffff0000u);
+}
+// The bf16 split of an FP32 direction table, the B operand of the JVP on the bf16 matrix
+// cores, is stored right after the FP32 table V^T [N][M] (compute precision, es bytes per
+// value): 16-bit parts, part p of plane pl of V_ij at
+// (((pl * 3 + p) * Np8 / 8 + i / 8) * M + j) * 8 + i % 8, Np8 = N rounded up to 8: the
+// eight consecutive sites of one hidden unit are 16 bytes, and consecutive hidden units
+// are consecutive 16-byte groups. The entries i >= N are zero.
+__host__ __device__ inline int vsplit_np8(int N) { return (N + 7) / 8 * 8; }
+__host__ __device__ inline size_t vsplit_offset(int N, int M, size_t es) {
+  return (size_t(N) * M * es + 255) / 256 * 256;
+}
+__host__ __device__ inline size_t vsplit_bytes(int N, int M, int planes) {
+  return size_t(planes) * 3 * M * vsplit_np8(N) * 2;
+}
+template <bool C>
+__device__ __forceinline__ void vsplit_store(uint16_t *Vs, int N, int M, int i, int j, float re,
+                                             float im) {
+  const size_t gp = size_t(vsplit_np8(N) / 8);
+#pragma unroll
+  for (int pl = 0; pl < (C ? 2 : 1); ++pl) {
+    const float x = pl ? im : re;
+    const float r = bf16_rest(x), l = bf16_rest(r);
+    const size_t o = ((size_t(pl * 3) * gp + i / 8) * M + j) * 8 + i % 8, ps = gp * M * 8;
+    Vs[o] = uint16_t(__float_as_uint(x) >> 16);
+    Vs[o + ps] = uint16_t(__float_as_uint(r) >> 16);
+    Vs[o + 2 * ps] = uint16_t(__float_as_uint(l) >> 16);
+  }
+}
+
 // reciprocal: the hardware v_rcp_f32 (1 ulp) in single precision, correctly rounded
 // division in double
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }

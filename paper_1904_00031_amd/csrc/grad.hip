@@ -42,18 +42,41 @@ struct MF<double> {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// 16x16x32 bf16 MFMA, FP32 accumulate. A: lane l holds A[l%16][8(l/16) .. 8(l/16)+7];
+// B: lane l holds B[8(l/16) .. 8(l/16)+7][l%16]; D as the 16x16x4 FP32 instruction.
+// Element e of a register quad is bits 16e .. 16e+15 (dword e/2, low half first).
+__device__ __forceinline__ floatx4 mfma_bf16(uint4 a, uint4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------------
 // Direction v (double, packed like the parameters) -> compute-precision tables.
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
 __global__ void k_prep_dir(int N, int M, const double *__restrict__ v, T *Vt, T *vb,
                            double *va) {
-  const int64_t total = int64_t(N) * M + M + N;
+  // FP32: the bf16 split of V^T follows V^T (its padding sites i in [N, Np8) zeroed here)
+  constexpr bool SPLIT = sizeof(T) == 4;
+  uint16_t *Vs = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(Vt) +
+                                              vsplit_offset(N, M, sizeof(T) * (C ? 2 : 1)));
+  const int np = vsplit_np8(N);
+  const int64_t pad = SPLIT ? int64_t(C ? 2 : 1) * 3 * M * (np - N) : 0;
+  const int64_t total = int64_t(N) * M + M + N + pad;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
     if (e < int64_t(N) * M) {
       int j = int(e / N), i = int(e % N);  // read v_W row-major (j, i)
-      vstore<T, C>(Vt, int64_t(i) * M + j, vcast<double, C, T>(vload<double, C>(v, N + M + e)));
+      const V<T, C> x = vcast<double, C, T>(vload<double, C>(v, N + M + e));
+      vstore<T, C>(Vt, int64_t(i) * M + j, x);
+      if constexpr (SPLIT) vsplit_store<C>(Vs, N, M, i, j, float(x.re), C ? float(x.im) : 0.f);
+    } else if (e >= int64_t(N) * M + M + N) {
+      const int64_t q = e - (int64_t(N) * M + M + N);  // padding entry (plane-part, j, site)
+      const int i = N + int(q % (np - N));
+      const int64_t r = q / (np - N);
+      const int64_t pp = r / M, j = r % M;
+      Vs[((pp * (np / 8) + i / 8) * M + j) * 8 + i % 8] = 0;
     } else if (e < int64_t(N) * M + M) {
       int j = int(e - int64_t(N) * M);
       vstore<T, C>(vb, j, vcast<double, C, T>(vload<double, C>(v, N + j)));
@@ -190,6 +213,69 @@ __device__ __forceinline__ void k_jvp_body(int BX, int BY, int BZ, int GX, int N
     xr[q] = Acc{0, 0, 0, 0};
     xi[q] = Acc{0, 0, 0, 0};
   }
+  if constexpr (sizeof(T) == 4) {
+    // FP32: X = S V^T on the bf16 matrix cores against the exact bf16 split of V stored
+    // after V^T. k group g (8 consecutive k) = part g % 3 of sites 8 (g / 3) .. + 7; lane
+    // group hi takes group 4 t + hi of step t. A: the spins of sample lo there (zero past N,
+    // past n and past the last group), from the wavefront's 16 rows staged in LDS (N <= 256)
+    // or read byte by byte; B: one 16-byte group of the split per tile and plane.
+    const uint16_t *Vs = reinterpret_cast<const uint16_t *>(
+        reinterpret_cast<const char *>(Vt) + vsplit_offset(N, M, sizeof(T) * (C ? 2 : 1)));
+    const int np = vsplit_np8(N), GP = np / 8;
+    const int KS = (3 * GP + 3) / 4;
+    constexpr int kRow = 264;  // staged row stride: 256 sites + 8 (rows 2 banks apart)
+    __shared__ __align__(16) int8_t sl[4][16 * kRow];
+    const bool staged = N <= 256;
+    if (staged) {
+      for (int e = lane; e < 16 * np; e += 64) {
+        const int r = e / np, c = e - r * np;
+        const int64_t row = s0 + r;
+        sl[wid][r * kRow + c] = (row < n && c < N) ? sigma[row * N + c] : int8_t(0);
+      }
+      wave_sync();
+    }
+#pragma unroll 2
+    for (int t = 0; t < KS; ++t) {
+      const int g8 = 4 * t + hi;
+      const int sg = g8 / 3, p = g8 - 3 * sg;
+      const bool gok = sg < GP;
+      const int sgc = gok ? sg : GP - 1;
+      T sv[8];
+      if (staged) {
+        const uint2 w = *reinterpret_cast<const uint2 *>(&sl[wid][lo * kRow + 8 * sgc]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int b = int(int8_t(((e < 4 ? w.x : w.y) >> (8 * (e & 3))) & 0xffu));
+          sv[e] = gok ? T(b) : T(0);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int i = 8 * sgc + e;
+          const bool ok = rowA_ok && gok && i < N;
+          const int8_t b = srow[ok ? i : 0];
+          sv[e] = ok ? T(b) : T(0);
+        }
+      }
+      const uint4 av = make_uint4(pack_hi(sv[0], sv[1]), pack_hi(sv[2], sv[3]),
+                                  pack_hi(sv[4], sv[5]), pack_hi(sv[6], sv[7]));
+      uint4 bv[JT][C ? 2 : 1];
+#pragma unroll
+      for (int q = 0; q < JT; ++q) {
+        const int j = (jt0 + q) * 16 + lo;
+        const int jc = j < M ? j : M - 1;
+#pragma unroll
+        for (int pl = 0; pl < (C ? 2 : 1); ++pl)
+          bv[q][pl] = *reinterpret_cast<const uint4 *>(
+              Vs + ((size_t(pl * 3 + p) * GP + sgc) * M + jc) * 8);
+      }
+#pragma unroll
+      for (int q = 0; q < JT; ++q) {
+        xr[q] = mfma_bf16(av, bv[q][0], xr[q]);
+        if constexpr (C) xi[q] = mfma_bf16(av, bv[q][C ? 1 : 0], xi[q]);
+      }
+    }
+  } else
 #pragma unroll 2
   for (int k0 = 0; k0 < N; k0 += 4) {
     const int k = k0 + hi;
@@ -341,6 +427,73 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
       ar[a][b] = Acc{0, 0, 0, 0};
       ai[a][b] = Acc{0, 0, 0, 0};
     }
+  if constexpr (sizeof(T) == 4) {
+    // FP32: 16-sample groups on the bf16 matrix cores. Lane (lo, hi) holds Z at samples
+    // 4 hi + q (q < 4) of hidden row lo of each tile, split exactly into three bf16
+    // parts (step 1: parts h and m, step 2: part l with a zero half) against the spins
+    // of the same samples, which are exact in bf16.
+    for (int64_t s = sbeg + 16 * wid; s < send; s += 64) {
+      V<T, C> uu[4];
+      bool sok[4];
+      int64_t srow[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        srow[q] = s + 4 * hi + q;
+        sok[q] = srow[q] < send;
+        uu[q] = vmake<T, C>(T(0), T(0));
+        if (sok[q])
+          uu[q] = vmake<T, C>(T(u[C ? 2 * srow[q] : srow[q]]), C ? T(u[2 * srow[q] + 1]) : T(0));
+      }
+      uint4 sb[NT];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const int i = (it0 + b) * 16 + lo;
+        T bs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int8_t *sp = sigma + (sok[q] ? srow[q] : 0) * N;
+          bs[q] = sok[q] ? (i < N ? T(sp[i]) : (i == N ? T(1) : T(0))) : T(0);
+        }
+        const uint32_t s01 = pack_hi(bs[0], bs[1]), s23 = pack_hi(bs[2], bs[3]);
+        sb[b] = make_uint4(s01, s23, s01, s23);
+      }
+#pragma unroll
+      for (int a = 0; a < JT; ++a) {
+        const int j = (jt0 + a) * 16 + lo;
+        V<T, C> z[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (sok[q] && j < M)
+            z[q] = vmul(vconj(vload<T, C>(Tm, srow[q] * M + j)), uu[q]);
+          else
+            z[q] = (sok[q] && j == M) ? uu[q] : vmake<T, C>(T(0), T(0));
+        }
+#pragma unroll
+        for (int pl = 0; pl < (C ? 2 : 1); ++pl) {
+          T zz[4], r[4], l[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            zz[q] = pl ? z[q].im : z[q].re;
+            r[q] = bf16_rest(zz[q]);
+            l[q] = bf16_rest(r[q]);
+          }
+          const uint4 a0 = make_uint4(pack_hi(zz[0], zz[1]), pack_hi(zz[2], zz[3]),
+                                      pack_hi(r[0], r[1]), pack_hi(r[2], r[3]));
+          const uint4 a1 = make_uint4(pack_hi(l[0], l[1]), pack_hi(l[2], l[3]), 0u, 0u);
+#pragma unroll
+          for (int b = 0; b < NT; ++b) {
+            if (pl) {
+              ai[a][b] = mfma_bf16(a0, sb[b], ai[a][b]);
+              ai[a][b] = mfma_bf16(a1, sb[b], ai[a][b]);
+            } else {
+              ar[a][b] = mfma_bf16(a0, sb[b], ar[a][b]);
+              ar[a][b] = mfma_bf16(a1, sb[b], ar[a][b]);
+            }
+          }
+        }
+      }
+    }
+  } else
   for (int64_t s = sbeg + 4 * wid; s < send; s += 16) {
     const int64_t srow = s + hi;
     const bool sok = srow < send;
@@ -687,27 +840,6 @@ __device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, int N, int
 }
 
 
-// Exact three-way bf16 split of an FP32 value by truncation: x = h + m + l, h the upper
-// 16 bits of x, m those of r = x - h, l = r - m. Both differences are exact in FP32
-// (r keeps at most 16 significant bits, l at most 8), so l is itself a bf16 and the
-// three parts sum to x exactly. Against a +/-1 operand every product is exact, and a
-// bf16 matrix-core contraction with FP32 accumulation gives the FP32 result up to the
-// order of the additions.
-__device__ __forceinline__ float bf16_rest(float x) {
-  return x - __uint_as_float(__float_as_uint(x) & 0xffff0000u);
-}
-// the upper halves (bf16 truncations) of a and b in one register, a in the low half
-__device__ __forceinline__ uint32_t pack_hi(float a, float b) {
-  return (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xffff0000u);
-}
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-// 16x16x32 bf16 MFMA, FP32 accumulate. A: lane l holds A[l%16][8(l/16) .. 8(l/16)+7];
-// B: lane l holds B[8(l/16) .. 8(l/16)+7][l%16]; D as the 16x16x4 FP32 instruction.
-// Element e of a register quad is bits 16e .. 16e+15 (dword e/2, low half first).
-__device__ __forceinline__ floatx4 mfma_bf16(uint4 a, uint4 b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
-}
 
 // ---------------------------------------------------------------------------------
 // Fused S v product for complex models with N <= 63 and all VJP tiles in one block.
@@ -1191,7 +1323,9 @@ GradLayout grad_layout(const nqs_model *m, int64_t n) {
     return o;
   };
   const size_t elems = size_t(g.Jtiles) * 16 * size_t(g.Itiles) * 16;
-  L.Vt = take(size_t(m->N) * m->M * es);
+  // FP32 direction tables are followed by their bf16 split (the JVP's B operand)
+  L.Vt = take(vsplit_offset(m->N, m->M, es) +
+              (use_double(m) ? 0 : vsplit_bytes(m->N, m->M, m->is_complex ? 2 : 1)));
   L.vb = take(size_t(m->M) * es);
   L.va = take(size_t(m->N) * 16);
   L.ypart = take(size_t(g.jchunks) * size_t(n) * 16);
@@ -1746,7 +1880,8 @@ BatchGradSizes batch_grad_sizes(const nqs_model *m, int64_t n) {
   const int Jtiles = (m->M + 1 + 15) / 16, Itiles = (m->N + 1 + 15) / 16;
   const int64_t splits = cdiv(n > 0 ? n : 1, kBSplit);
   z.Tm = size_t(n) * m->M * es + 128 * es;
-  z.Vt = size_t(m->N) * m->M * es;
+  z.Vt = vsplit_offset(m->N, m->M, es) +
+         (use_double(m) ? 0 : vsplit_bytes(m->N, m->M, m->is_complex ? 2 : 1));
   z.vb = size_t(m->M) * es;
   z.va = size_t(m->N) * 16;
   z.ypart = size_t(cdiv((m->M + 15) / 16, (use_double(m) || m->is_complex) ? 4 : 8)) *

@@ -130,6 +130,30 @@ __device__ __forceinline__ void dir_write(int N, int M, int64_t k, double pr, do
   } else {
     const int64_t q = k - N - M;
     vstore<T, C>(Vt, (q % N) * M + q / N, vmake<T, C>(T(pr), T(pi)));
+    if constexpr (sizeof(T) == 4) {
+      // the bf16 split that follows V^T (the JVP's operand on the bf16 matrix cores)
+      uint16_t *Vs = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(Vt) +
+                                                  vsplit_offset(N, M, sizeof(T) * (C ? 2 : 1)));
+      vsplit_store<C>(Vs, N, M, int(q % N), int(q / N), float(pr), float(pi));
+    }
+  }
+}
+
+// zero the padding sites [N, Np8) of the split direction (FP32 tables)
+template <typename T, bool C>
+__device__ __forceinline__ void dir_pad_zero(int N, int M, int64_t first, int64_t stride, T *Vt) {
+  if constexpr (sizeof(T) == 4) {
+    const int np = vsplit_np8(N);
+    if (np == N) return;
+    uint16_t *Vs = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(Vt) +
+                                                vsplit_offset(N, M, sizeof(T) * (C ? 2 : 1)));
+    const int64_t pad = int64_t(C ? 2 : 1) * 3 * M * (np - N);
+    for (int64_t q = first; q < pad; q += stride) {
+      const int i = N + int(q % (np - N));
+      const int64_t r = q / (np - N);
+      const int64_t pp = r / M, j = r % M;
+      Vs[((pp * (np / 8) + i / 8) * M + j) * 8 + i % 8] = 0;
+    }
   }
 }
 
@@ -168,6 +192,7 @@ __device__ __forceinline__ void k_cg_init_body(int BX, int BY, int BZ, int GX, i
     dir_write<T, C>(N, M, k, fr, fi, Vt, vb, va);
     acc += fr * fr + fi * fi;
   }
+  dir_pad_zero<T, C>(N, M, int64_t(BX) * 256 + threadIdx.x, int64_t(GX) * 256, Vt);
   acc = block_reduce(acc, lds);
   if (threadIdx.x == 0) dpart[BX] = acc;
 }
