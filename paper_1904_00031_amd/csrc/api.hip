@@ -319,7 +319,7 @@ nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigm
     if (e == hipSuccess) e = launch_vjp_reduce(m, n, m->d_scratch, (double *)vjp, nullptr, st);
   }
   if (e == hipSuccess && want_jvp) {
-    e = launch_prep_dir(m, v, m->d_scratch, st);
+    e = launch_prep_dir(m, v, m->d_scratch, true, st);
     if (e == hipSuccess)
       e = launch_jvp(m, sigma, n, m->d_scratch, (double *)jvp, nullptr, nullptr, st);
   }

@@ -56,9 +56,10 @@ __device__ __forceinline__ floatx4 mfma_bf16(uint4 a, uint4 b, floatx4 c) {
 // ---------------------------------------------------------------------------------
 template <typename T, bool C>
 __global__ void k_prep_dir(int N, int M, const double *__restrict__ v, T *Vt, T *vb,
-                           double *va) {
-  // FP32: the bf16 split of V^T follows V^T (its padding sites i in [N, Np8) zeroed here)
-  constexpr bool SPLIT = sizeof(T) == 4;
+                           double *va, int split) {
+  // FP32 with split: the bf16 split of V^T follows V^T (its padding sites i in [N, Np8)
+  // zeroed here)
+  const bool SPLIT = sizeof(T) == 4 && split;
   uint16_t *Vs = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(Vt) +
                                               vsplit_offset(N, M, sizeof(T) * (C ? 2 : 1)));
   const int np = vsplit_np8(N);
@@ -70,7 +71,7 @@ __global__ void k_prep_dir(int N, int M, const double *__restrict__ v, T *Vt, T 
       int j = int(e / N), i = int(e % N);  // read v_W row-major (j, i)
       const V<T, C> x = vcast<double, C, T>(vload<double, C>(v, N + M + e));
       vstore<T, C>(Vt, int64_t(i) * M + j, x);
-      if constexpr (SPLIT) vsplit_store<C>(Vs, N, M, i, j, float(x.re), C ? float(x.im) : 0.f);
+      if (SPLIT) vsplit_store<C>(Vs, N, M, i, j, float(x.re), C ? float(x.im) : 0.f);
     } else if (e >= int64_t(N) * M + M + N) {
       const int64_t q = e - (int64_t(N) * M + M + N);  // padding entry (plane-part, j, site)
       const int i = N + int(q % (np - N));
@@ -1342,7 +1343,7 @@ GradLayout grad_layout(const nqs_model *m, int64_t n) {
 }
 
 template <typename T, bool C>
-hipError_t prep_t(const nqs_model *m, const void *v, void *scratch, hipStream_t st) {
+hipError_t prep_t(const nqs_model *m, const void *v, void *scratch, bool split, hipStream_t st) {
   GradLayout L = grad_layout(m, 0);
   char *base = (char *)scratch;
   int64_t total = int64_t(m->N) * m->M + m->M + m->N;
@@ -1350,7 +1351,7 @@ hipError_t prep_t(const nqs_model *m, const void *v, void *scratch, hipStream_t 
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL((k_prep_dir<T, C>), dim3(blocks), dim3(256), 0, st, m->N, m->M,
                      (const double *)v, (T *)(base + L.Vt), (T *)(base + L.vb),
-                     (double *)(base + L.va));
+                     (double *)(base + L.va), int(split));
   return hipGetLastError();
 }
 
@@ -1831,8 +1832,9 @@ size_t grad_scratch_bytes(const nqs_model *m, int64_t n) { return grad_layout(m,
                  : (m->is_complex ? FN<float, true>(__VA_ARGS__)                           \
                                   : FN<float, false>(__VA_ARGS__)))
 
-hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, hipStream_t st) {
-  return NQS_DISPATCH(prep_t, m, v, scratch, st);
+hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, bool split,
+                           hipStream_t st) {
+  return NQS_DISPATCH(prep_t, m, v, scratch, split, st);
 }
 
 hipError_t launch_theta_tanh(const nqs_model *m, const int8_t *sigma, int64_t n, void *scratch,

@@ -153,7 +153,9 @@ GradPlan grad_plan(const nqs_model *m, int64_t n);
 size_t grad_scratch_bytes(const nqs_model *m, int64_t n);
 
 // v (double, params layout) -> direction tables in compute precision, in scratch
-hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, hipStream_t st);
+// split: also write the bf16 split of the direction (read only by the separate JVP kernel)
+hipError_t launch_prep_dir(const nqs_model *m, const void *v, void *scratch, bool split,
+                           hipStream_t st);
 // T = tanh(theta) of every sample into scratch (needed by launch_jvp / launch_vjp_partials
 // and the local energies from rows); for_grad: rows for the Jacobian contractions, which
 // the BF16 form rounds to bfloat16

@@ -121,7 +121,7 @@ __global__ void k_fill(int64_t count, double *x, double val) {
 // product kernels read: Vt[i][j] = p_W[j][i], vb = p_b (compute precision), va = p_a
 template <typename T, bool C>
 __device__ __forceinline__ void dir_write(int N, int M, int64_t k, double pr, double pi, T *Vt,
-                                          T *vb, double *va) {
+                                          T *vb, double *va, int split) {
   if (k < N) {
     va[2 * k] = pr;
     va[2 * k + 1] = pi;
@@ -130,7 +130,7 @@ __device__ __forceinline__ void dir_write(int N, int M, int64_t k, double pr, do
   } else {
     const int64_t q = k - N - M;
     vstore<T, C>(Vt, (q % N) * M + q / N, vmake<T, C>(T(pr), T(pi)));
-    if constexpr (sizeof(T) == 4) {
+    if (sizeof(T) == 4 && split) {
       // the bf16 split that follows V^T (the JVP's operand on the bf16 matrix cores)
       uint16_t *Vs = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(Vt) +
                                                   vsplit_offset(N, M, sizeof(T) * (C ? 2 : 1)));
@@ -162,7 +162,8 @@ template <typename T, bool C>
 __device__ __forceinline__ void k_cg_init_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n, const double *part2,
                                                   int64_t nparts, const double *g, double *F,
                                                   double *x, double *r, double *p, T *Vt, T *vb,
-                                                  double *va, double *dpart, CGState *st) {
+                                                  double *va, double *dpart, CGState *st,
+    int split) {
   __shared__ double lds[256];
   const int64_t P = int64_t(N) + M + int64_t(N) * M;
   if (BX == 0) {
@@ -189,10 +190,10 @@ __device__ __forceinline__ void k_cg_init_body(int BX, int BY, int BZ, int GX, i
       r[k] = fr;
       p[k] = fr;
     }
-    dir_write<T, C>(N, M, k, fr, fi, Vt, vb, va);
+    dir_write<T, C>(N, M, k, fr, fi, Vt, vb, va, split);
     acc += fr * fr + fi * fi;
   }
-  dir_pad_zero<T, C>(N, M, int64_t(BX) * 256 + threadIdx.x, int64_t(GX) * 256, Vt);
+  if (split) dir_pad_zero<T, C>(N, M, int64_t(BX) * 256 + threadIdx.x, int64_t(GX) * 256, Vt);
   acc = block_reduce(acc, lds);
   if (threadIdx.x == 0) dpart[BX] = acc;
 }
@@ -201,8 +202,9 @@ template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_cg_init(int N, int M, int64_t n, const double *part2,
                                                   int64_t nparts, const double *g, double *F,
                                                   double *x, double *r, double *p, T *Vt, T *vb,
-                                                  double *va, double *dpart, CGState *st) {
-  k_cg_init_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, part2, nparts, g, F, x, r, p, Vt, vb, va, dpart, st);
+                                                  double *va, double *dpart, CGState *st,
+    int split) {
+  k_cg_init_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, part2, nparts, g, F, x, r, p, Vt, vb, va, dpart, st, split);
 }
 
 __device__ __forceinline__ void k_cg_start_body(int BX, int BY, int BZ, int GX, const double *dpart, int64_t nparts,
@@ -318,7 +320,8 @@ template <typename T, bool C>
 __device__ __forceinline__ void k_cg_p_body(int BX, int BY, int BZ, int GX, int N, int M, const double *rpart, int64_t nparts,
                                               int parity, double tol, int maxiter,
                                               const double *r, double *p, T *Vt, T *vb,
-                                              double *va, CGState *st) {
+                                              double *va, CGState *st,
+    int split) {
   if (st->done) return;
   __shared__ double lds[256];
   const int64_t P = int64_t(N) + M + int64_t(N) * M;
@@ -340,7 +343,7 @@ __device__ __forceinline__ void k_cg_p_body(int BX, int BY, int BZ, int GX, int 
       pr = r[k] + beta * p[k];
       p[k] = pr;
     }
-    dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va);
+    dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va, split);
   }
   __syncthreads();
   if (BX == 0 && threadIdx.x == 0) {
@@ -356,8 +359,9 @@ template <typename T, bool C>
 __global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart, int64_t nparts,
                                               int parity, double tol, int maxiter,
                                               const double *r, double *p, T *Vt, T *vb,
-                                              double *va, CGState *st) {
-  k_cg_p_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, rpart, nparts, parity, tol, maxiter, r, p, Vt, vb, va, st);
+                                              double *va, CGState *st,
+    int split) {
+  k_cg_p_body<T, C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, rpart, nparts, parity, tol, maxiter, r, p, Vt, vb, va, st, split);
 }
 
 // ---- fused CG iteration kernel (single model) -----------------------------------
@@ -453,7 +457,8 @@ __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const doub
                                                         int64_t nparts, int parity, double tol,
                                                         int maxiter, double *x, double *r,
                                                         double *p, const double *Ap, T *Vt,
-                                                        T *vb, double *va, CGState *st) {
+                                                        T *vb, double *va, CGState *st,
+    int split) {
   if (st->done) return;
   __shared__ double lds[kXrpThreads / 64];
   constexpr int cs = C ? 2 : 1;
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const doub
       const double pi = C ? rv[i][cs - 1] + beta * pv[i][cs - 1] : 0.0;
       p[cs * k] = pr;
       if (C) p[cs * k + cs - 1] = pi;
-      dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va);
+      dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va, split);
     }
   }
   if (threadIdx.x == 0) {
@@ -621,6 +626,8 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   const GradBuffers gb = grad_buffers(m, n, grad);
   const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
   const int64_t nys = gp.fused ? gp.splits : nb;
+  // the bf16 split of the direction feeds only the separate JVP kernel
+  const int split = gp.fused ? 0 : 1;
 
   HIPTRY(launch_tables(m, params, st));
   // mean energy, centred energies u = E_loc - E, variance partials
@@ -641,7 +648,7 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   HIPTRY(launch_vjp_reduce(m, n, grad, D(L.g), nullptr, st));
   hipLaunchKernelGGL((k_cg_init<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, st, N, M, n,
                      D(L.e_part2), nb, D(L.g), D(L.F), D(L.x), D(L.r), D(L.p), (T *)gb.Vt,
-                     (T *)gb.vb, gb.va, D(L.dpart), state);
+                     (T *)gb.vb, gb.va, D(L.dpart), state, split);
   HIPTRY(hipGetLastError());
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, st, D(L.dpart), pblocks, cg_tol,
                      cg_maxiter, state);
@@ -677,7 +684,7 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
         if (P <= kXrpMaxParams) {
           hipLaunchKernelGGL((k_cg_xrp<T, C>), dim3(1), dim3(kXrpThreads), 0, s2, N, M,
                              D(L.dpart), ablocks, parity, cg_tol, cg_maxiter, D(L.x), D(L.r),
-                             D(L.p), D(L.Ap), (T *)gb.Vt, (T *)gb.vb, gb.va, state);
+                             D(L.p), D(L.Ap), (T *)gb.Vt, (T *)gb.vb, gb.va, state, split);
           if ((e2 = hipGetLastError()) != hipSuccess) return e2;
           continue;
         }
@@ -686,7 +693,7 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
         hipLaunchKernelGGL((k_cg_p<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, s2, N, M,
                            D(L.rpart), cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
-                           (T *)gb.Vt, (T *)gb.vb, gb.va, state);
+                           (T *)gb.Vt, (T *)gb.vb, gb.va, state, split);
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
       }
       return hipSuccess;
@@ -810,7 +817,7 @@ nqs_status matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws, c
   const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
   const int64_t pblocks = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
   const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
-  HIPTRY(launch_prep_dir(m, v, grad, st));
+  HIPTRY(launch_prep_dir(m, v, grad, !gp.fused, st));
   if (gp.fused) {
     HIPTRY(launch_sv(m, sigma, n, grad, (double *)(b + L.ysum), nullptr, st));
   } else {
@@ -874,7 +881,7 @@ __global__ __launch_bounds__(256) void kb_cg_init(const BJob<T> *jobs, const int
   const int2 b = map[blockIdx.x];
   const BJob<T> J = jobs[b.x];
   k_cg_init_body<T, C>(b.y, 0, 0, J.pblocks, J.N, J.M, J.n, J.epart2, J.nb, J.g, J.F, J.x, J.r,
-                       J.p, J.Vt, J.vb, J.va, J.dpart, J.st);
+                       J.p, J.Vt, J.vb, J.va, J.dpart, J.st, 1);
 }
 template <typename T>
 __global__ __launch_bounds__(256) void kb_cg_start(const BJob<T> *jobs, double tol,
@@ -904,7 +911,7 @@ __global__ __launch_bounds__(256) void kb_cg_p(const BJob<T> *jobs, const int2 *
   const int2 b = map[blockIdx.x];
   const BJob<T> J = jobs[b.x];
   k_cg_p_body<T, C>(b.y, 0, 0, J.pblocks, J.N, J.M, J.rpart, J.cblocks, parity, tol, maxiter,
-                    J.r, J.p, J.Vt, J.vb, J.va, J.st);
+                    J.r, J.p, J.Vt, J.vb, J.va, J.st, 1);
 }
 // parameter update of the models whose energy and solve are finite
 template <typename T, typename PT>
