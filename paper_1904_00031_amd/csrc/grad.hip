@@ -878,7 +878,8 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
                                                 const double *__restrict__ va,
                                                 int64_t per_split, int rowsP, int colsP,
                                                 T *part, double *ysum_part, const int *skip) {
-  if (skip && *skip) return;
+  // a finished solve returns after the staging below (the flag is read with its loads)
+  const int skipped = skip ? *skip : 0;
   typedef typename MF<T>::acc Acc;
   constexpr int JW = JT * 16;
   constexpr int NVA = 4;                        // site columns per lane: lo + 16 c, N <= 63
@@ -959,6 +960,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     val[pl][i] = i < N ? T(va[2 * i + pl]) : T(0);
   }
   __syncthreads();
+  if (skipped) return;
   // this wavefront's spin tile, after the JVP operands
   T *stile = reinterpret_cast<T *>(Vb + 2 * G * JVW) + wid * 16 * kSpinStride;
   bool stalled = false;

@@ -379,11 +379,18 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
                                                 const double *o1, const double *ysum,
                                                 int64_t nys, const double *p, double lambda,
                                                 double *Ap, double *dpart, const CGState *st) {
-  if (st->done) return;
   __shared__ double lds[256];
   __shared__ double sr[kAprSlices][kAprElems], si[kAprSlices][kAprElems];
-  const double ybr = block_sum(ysum, nys, 2, lds) / double(n);
-  const double ybi = C ? block_sum(ysum + 1, nys, 2, lds) / double(n) : 0.0;
+  // the solver state and the sums of y in one memory round trip
+  const int done = st->done;
+  double ysr = 0.0, ysi = 0.0;
+  for (int64_t k = threadIdx.x; k < nys; k += blockDim.x) {
+    ysr += ysum[2 * k];
+    if (C) ysi += ysum[2 * k + 1];
+  }
+  if (done) return;
+  const double ybr = block_reduce(ysr, lds) / double(n);
+  const double ybi = C ? block_reduce(ysi, lds) / double(n) : 0.0;
   const int el = threadIdx.x % kAprElems, sl = threadIdx.x / kAprElems;
   const int64_t e = int64_t(blockIdx.x) * kAprElems + el;
   double gr = 0.0, gi = 0.0;
@@ -459,10 +466,14 @@ __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const doub
                                                         double *p, const double *Ap, T *Vt,
                                                         T *vb, double *va, CGState *st,
     int split) {
-  if (st->done) return;
   __shared__ double lds[kXrpThreads / 64];
   constexpr int cs = C ? 2 : 1;
   const int64_t P = int64_t(N) + M + int64_t(N) * M;
+  // the solver state is read together with the vectors (one memory round trip); a
+  // finished solve returns after the loads
+  const int done = st->done;
+  const double rr = st->rr[parity], bnorm = st->bnorm;
+  const int iters0 = st->iters;
   double xv[kXrpPer][cs], rv[kXrpPer][cs], pv[kXrpPer][cs], av[kXrpPer][cs];
 #pragma unroll
   for (int i = 0; i < kXrpPer; ++i) {
@@ -476,8 +487,10 @@ __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const doub
       av[i][c] = Ap[cs * kk + c];
     }
   }
-  const double pAp = block_sum(dpart, nparts, 1, lds);
-  const double rr = st->rr[parity];
+  double pa = 0.0;
+  for (int64_t k = threadIdx.x; k < nparts; k += kXrpThreads) pa += dpart[k];
+  if (done) return;
+  const double pAp = block_reduce(pa, lds);
   const double alpha = rr / pAp;
   double acc = 0.0;
 #pragma unroll
@@ -508,8 +521,8 @@ __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const doub
     }
   }
   if (threadIdx.x == 0) {
-    const int iters = st->iters + 1;
-    const bool conv = sqrt(rr_new) <= tol * st->bnorm;
+    const int iters = iters0 + 1;
+    const bool conv = sqrt(rr_new) <= tol * bnorm;
     const bool bad = !(finite(rr_new) && finite(alpha));
     st->alpha = alpha;
     st->rr[parity ^ 1] = rr_new;
