@@ -830,6 +830,110 @@ __global__ __launch_bounds__(64 * kElocWaves) void k_local_energy(DevModel dm, T
 }
 
 // ---------------------------------------------------------------------------------
+// Local energy with one sample per lane, for small models (M <= 16 TPM, N <= 64, at most
+// 64 connected rows, rows staged in LDS): the lane's tanh row sits in registers, the
+// connected rows (every site for TFIM, every bond for Heisenberg) are visited in a
+// wave-uniform loop with their C/S entries broadcast from LDS, and each lane multiplies its
+// own ratio terms, so no cross-lane reduction is needed. Rows that a lane's sample does
+// not connect are computed and discarded. Same terms as eloc_grouped (Eq. 5).
+// ---------------------------------------------------------------------------------
+template <typename T, bool C, int TPM>
+__global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
+                                                     const int8_t *__restrict__ sigma,
+                                                     const T *__restrict__ Tm, int64_t n,
+                                                     double *eloc, int cs_rows) {
+  extern __shared__ __align__(16) unsigned char lds_u8[];
+  constexpr int cs = C ? 2 : 1;
+  constexpr int MJ = 16 * TPM;
+  const int N = dm.N, M = dm.M, B = dm.Btot;
+  const bool tfim = dm.ham == NQS_TFIM;
+  // rows staged with the compile-time width MJ; entries past M hold C = 1, S = 0, so their
+  // ratio term is exactly 1 and the product loop has no bound test
+  T *lC = reinterpret_cast<T *>(lds_u8);
+  T *lS = lC + int64_t(cs_rows) * MJ * cs;
+  {
+    const T *gC = tfim ? tb.fC : tb.bC;
+    const T *gS = tfim ? tb.fS : tb.bS;
+    for (int e = threadIdx.x; e < cs_rows * MJ; e += blockDim.x) {
+      const int r = e / MJ, j = e - r * MJ;
+      V<T, C> cc = vmake<T, C>(T(1), T(0)), ss = vmake<T, C>(T(0), T(0));
+      if (j < M) {
+        cc = vload<T, C>(gC, int64_t(r) * M + j);
+        ss = vload<T, C>(gS, int64_t(r) * M + j);
+      }
+      vstore<T, C>(lC, e, cc);
+      vstore<T, C>(lS, e, ss);
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nrows = tfim ? (dm.h != 0.0 ? N : 0) : B;
+  for (int64_t s0 = (int64_t(blockIdx.x) * (blockDim.x >> 6) + wid) * 64; s0 < n;
+       s0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t smp = s0 + lane;
+    const bool ok = smp < n;
+    const int64_t sr = ok ? smp : n - 1;
+    uint64_t mask = 0;  // bit i: spin i up
+    const int8_t *row = sigma + sr * N;
+    for (int i = 0; i < N; ++i) mask |= uint64_t(row[i] > 0) << i;
+    V<T, C> t[MJ];
+#pragma unroll
+    for (int j = 0; j < MJ; ++j)
+      t[j] = j < M ? vload<T, C>(Tm, sr * M + j) : vmake<T, C>(T(0), T(0));
+    double diag = 0.0;
+    for (int b = 0; b < B; ++b) {
+      const int i = dm.bonds[2 * b], k = dm.bonds[2 * b + 1];
+      const int si = ((mask >> i) & 1ull) ? 1 : -1, sk = ((mask >> k) & 1ull) ? 1 : -1;
+      diag += dm.bond_diag[b] * double(si * sk);
+    }
+    double er = 0.0, ei = 0.0;
+    for (int c = 0; c < nrows; ++c) {
+      int sgn;
+      bool conn;
+      double el;
+      if (tfim) {
+        sgn = ((mask >> c) & 1ull) ? 1 : -1;
+        conn = true;
+        el = -dm.h;
+      } else {
+        const int i = dm.bonds[2 * c], k = dm.bonds[2 * c + 1];
+        const bool ui = (mask >> i) & 1ull, uk = (mask >> k) & 1ull;
+        sgn = ui ? 1 : -1;
+        el = dm.bond_off[c];
+        conn = ui != uk && el != 0.0;
+      }
+      if (__ballot(conn && ok) == 0) continue;  // no lane connects this row
+      const T ts = T(sgn);
+      const T *crow = lC + int64_t(c) * MJ * cs, *srow = lS + int64_t(c) * MJ * cs;
+      V<T, C> p = vmake<T, C>(T(1), T(0));
+      int pe = 0;
+#pragma unroll
+      for (int j = 0; j < MJ; ++j) {
+        const V<T, C> cc = vload<T, C>(crow, j), ss = vload<T, C>(srow, j);
+        p = vmul(p, vsub(cc, vscale(vmul(t[j], ss), ts)));
+        if ((j & 7) == 7) vrenorm(p, pe);
+      }
+      vrenorm(p, pe);
+      const double *af = tfim ? tb.fa + 2 * (int64_t(sgn > 0 ? 0 : 1) * N + c)
+                              : tb.ba + 2 * (int64_t(sgn > 0 ? 0 : 1) * B + c);
+      const double rr = ldexp(double(p.re), pe), ri = C ? ldexp(double(p.im), pe) : 0.0;
+      if (conn) {
+        er += el * (rr * af[0] - ri * af[1]);
+        ei += el * (rr * af[1] + ri * af[0]);
+      }
+    }
+    if (ok) {
+      if (C) {
+        eloc[2 * smp] = diag + er;
+        eloc[2 * smp + 1] = ei;
+      } else {
+        eloc[smp] = diag + er;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // log psi. One sample per wavefront; theta, ln cosh and the sums in double for every
 // compute precision (near the complex zeros of cosh theta, rounding theta to FP32 alone
 // would dominate the error; log psi is not on the sampling or SR path).
@@ -1016,6 +1120,29 @@ hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64
   if (n == 0) return hipSuccess;
   // M <= 256: the smallest tile count of 16 hidden units per lane group covering M
   const int tp = (m->M + 15) / 16;
+  // small models: one sample per lane (FP64 complex rows beyond 48 hidden units would
+  // exceed 256 registers per lane; those keep the grouped kernel)
+  if (tp <= 6 && m->N <= 64 && (sizeof(T) == 4 || !C || tp <= 3)) {
+    const int cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
+    const size_t tab_lds = size_t(2) * cs_rows * (16 * tp) * sizeof(T) * (C ? 2 : 1);
+    if (cs_rows <= 64 && tab_lds <= size_t(m->max_lds) / 2) {
+      // one block of four wavefronts per compute unit (the row in registers takes up to
+      // 512 registers per lane)
+      int64_t blocks = (n + 255) / 256;
+      const int per_cu = 1;
+      if (blocks > int64_t(per_cu) * m->cu_count) blocks = int64_t(per_cu) * m->cu_count;
+#define NQS_ELOC_LANES(TPM)                                                                   \
+  if (tp <= TPM) {                                                                            \
+    hipLaunchKernelGGL((k_eloc_lanes<T, C, TPM>), dim3(unsigned(blocks)), dim3(256), tab_lds, \
+                       st, dev_model(m), tables_of<T>(m), sigma, (const T *)Tm, n,            \
+                       (double *)eloc, cs_rows);                                              \
+    return hipGetLastError();                                                                 \
+  }
+      NQS_ELOC_LANES(1) NQS_ELOC_LANES(2) NQS_ELOC_LANES(3)
+      NQS_ELOC_LANES(4) NQS_ELOC_LANES(5) NQS_ELOC_LANES(6)
+#undef NQS_ELOC_LANES
+    }
+  }
   if (tp <= 2) return eloc_r<T, C, 1, 2>(m, sigma, Tm, n, eloc, st);
   if (tp <= 3) return eloc_r<T, C, 1, 3>(m, sigma, Tm, n, eloc, st);
   if (tp <= 4) return eloc_r<T, C, 1, 4>(m, sigma, Tm, n, eloc, st);
