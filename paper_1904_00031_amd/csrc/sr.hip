@@ -867,6 +867,13 @@ struct BJob {
   CGState *st;
 };
 
+// the solver states of all models of a batch, gathered for one host read
+template <typename T>
+__global__ void kb_gather_states(const BJob<T> *jobs, int K, CGState *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) out[k] = *jobs[k].st;
+}
+
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void kb_stats1(const BJob<T> *jobs, const int2 *map) {
   const int2 b = map[blockIdx.x];
@@ -984,7 +991,8 @@ BLayout batch_layout(const nqs_model *m, int64_t n) {
 }
 
 // job-table slots of the batch handle used by the SR step
-enum { kSlotJobs = 0, kSlotStats, kSlotP, kSlotC, kSlotStart, kSlotTanh = 10, kSlotJvp = 12,
+enum { kSlotJobs = 0, kSlotStats, kSlotP, kSlotC, kSlotStart, kSlotStates = 6, kSlotTanh = 10,
+       kSlotJvp = 12,
        kSlotVjp1 = 16, kSlotVjpU = 20, kSlotVjpY = 24 };
 
 template <typename T, bool C>
@@ -1110,11 +1118,18 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
     gi[k].skip = &states[k]->done;
   }
   std::vector<CGState> hs(K);
+  // every model's solver state is gathered into one device array and read in one copy
+  BTRY(b->buf(kSlotStates).upload(hs.data(), hs.size() * sizeof(CGState), st));
+  if (!b->buf(kSlotStates).d) return NQS_EDEVICE;
+  CGState *dstates = (CGState *)b->buf(kSlotStates).d;
   const int check_every = 8;
   int launched = 0;
   while (true) {
-    for (int k = 0; k < K; ++k)
-      BTRY(hipMemcpyAsync(&hs[k], states[k], sizeof(CGState), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL((kb_gather_states<T>), dim3(unsigned((K + 63) / 64)), dim3(64), 0, st, dj,
+                       K, dstates);
+    BTRY(hipGetLastError());
+    BTRY(hipMemcpyAsync(hs.data(), dstates, hs.size() * sizeof(CGState), hipMemcpyDeviceToHost,
+                        st));
     BTRY(hipStreamSynchronize(st));
     bool all_done = true;
     for (int k = 0; k < K; ++k) all_done = all_done && hs[k].done;
