@@ -254,8 +254,11 @@ nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int
   hipStream_t st = (hipStream_t)stream;
   // With fewer than 16 chains per compute unit (at most one wavefront per SIMD pair) the
   // sweep is latency-bound and local energies are cheaper as a separate full-occupancy
-  // pass over the recorded samples; with many chains they are fused into the sweep.
-  const bool fuse = eloc && int64_t(n_chains) >= 16 * int64_t(m->cu_count);
+  // pass over the recorded samples; with many chains they are fused into the sweep, unless
+  // the sweep holds more than 4 hidden units per lane (its registers then leave room for
+  // one wavefront per SIMD, and the separate pass is faster).
+  const bool fuse = eloc && int64_t(n_chains) >= 16 * int64_t(m->cu_count) &&
+                    (m->M + 63) / 64 <= 4;
   const int64_t n = int64_t(n_sweeps) * n_chains;
   if (eloc && !fuse) {
     nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
