@@ -406,6 +406,42 @@ __global__ __launch_bounds__(256) void k_jvp_finish(int64_t n, int jchunks,
 // Grid (hidden chunks, sample splits, site chunks).
 // partial layout [split][Jtiles*16][Itiles*16], compute precision.
 // ---------------------------------------------------------------------------------
+// one 16-sample group of the FP32 VJP as loaded: u, the spins of the lane's site columns
+// and the T entries of its hidden rows, for samples s + 4 hi + q (rows past send read row
+// send - 1 with u = 0)
+template <typename T, bool C, int JT, int NT>
+struct VjpGroup {
+  V<T, C> uu[4];
+  int8_t sp[NT][4];
+  V<T, C> tv[JT][4];
+};
+template <typename T, bool C, int JT, int NT>
+__device__ __forceinline__ void vjp_group_load(VjpGroup<T, C, JT, NT> &g,
+                                               const int8_t *__restrict__ sigma,
+                                               const T *__restrict__ Tm,
+                                               const double *__restrict__ u, int N, int M,
+                                               int64_t s, int64_t send, int hi, int lo, int jt0,
+                                               int it0) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t row = s + 4 * hi + q;
+    const bool ok = row < send;
+    const int64_t rc = ok ? row : send - 1;
+    const V<T, C> x = vmake<T, C>(T(u[C ? 2 * rc : rc]), C ? T(u[2 * rc + 1]) : T(0));
+    g.uu[q] = ok ? x : vmake<T, C>(T(0), T(0));
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      const int i = (it0 + b) * 16 + lo;
+      g.sp[b][q] = sigma[rc * N + (i < N ? i : 0)];
+    }
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      const int j = (jt0 + a) * 16 + lo;
+      g.tv[a][q] = vload<T, C>(Tm, rc * M + (j < M ? j : 0));
+    }
+  }
+}
+
 template <typename T, bool C, int JT, int NT>
 __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n,
                                               const int8_t *__restrict__ sigma,
@@ -432,29 +468,22 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
     // FP32: 16-sample groups on the bf16 matrix cores. Lane (lo, hi) holds Z at samples
     // 4 hi + q (q < 4) of hidden row lo of each tile, split exactly into three bf16
     // parts (step 1: parts h and m, step 2: part l with a zero half) against the spins
-    // of the same samples, which are exact in bf16.
-    for (int64_t s = sbeg + 16 * wid; s < send; s += 64) {
-      V<T, C> uu[4];
-      bool sok[4];
-      int64_t srow[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        srow[q] = s + 4 * hi + q;
-        sok[q] = srow[q] < send;
-        uu[q] = vmake<T, C>(T(0), T(0));
-        if (sok[q])
-          uu[q] = vmake<T, C>(T(u[C ? 2 * srow[q] : srow[q]]), C ? T(u[2 * srow[q] + 1]) : T(0));
-      }
+    // of the same samples, which are exact in bf16. The next group's u, spins and T
+    // entries are loaded while the current group is contracted (rows past the end of the
+    // split read its last row and get u = 0, so their Z vanishes).
+    VjpGroup<T, C, JT, NT> cur, nxt;
+    const int64_t s0 = sbeg + 16 * wid;
+    if (s0 < send) vjp_group_load(cur, sigma, Tm, u, N, M, s0, send, hi, lo, jt0, it0);
+    for (int64_t s = s0; s < send; s += 64) {
+      vjp_group_load(nxt, sigma, Tm, u, N, M, s + 64, send, hi, lo, jt0, it0);
       uint4 sb[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
         const int i = (it0 + b) * 16 + lo;
         T bs[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int8_t *sp = sigma + (sok[q] ? srow[q] : 0) * N;
-          bs[q] = sok[q] ? (i < N ? T(sp[i]) : (i == N ? T(1) : T(0))) : T(0);
-        }
+        for (int q = 0; q < 4; ++q)
+          bs[q] = i < N ? T(cur.sp[b][q]) : (i == N ? T(1) : T(0));
         const uint32_t s01 = pack_hi(bs[0], bs[1]), s23 = pack_hi(bs[2], bs[3]);
         sb[b] = make_uint4(s01, s23, s01, s23);
       }
@@ -463,12 +492,9 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
         const int j = (jt0 + a) * 16 + lo;
         V<T, C> z[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (sok[q] && j < M)
-            z[q] = vmul(vconj(vload<T, C>(Tm, srow[q] * M + j)), uu[q]);
-          else
-            z[q] = (sok[q] && j == M) ? uu[q] : vmake<T, C>(T(0), T(0));
-        }
+        for (int q = 0; q < 4; ++q)
+          z[q] = j < M ? vmul(vconj(cur.tv[a][q]), cur.uu[q])
+                       : (j == M ? cur.uu[q] : vmake<T, C>(T(0), T(0)));
 #pragma unroll
         for (int pl = 0; pl < (C ? 2 : 1); ++pl) {
           T zz[4], r[4], l[4];
@@ -493,6 +519,7 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
           }
         }
       }
+      cur = nxt;
     }
   } else
   for (int64_t s = sbeg + 4 * wid; s < send; s += 16) {
