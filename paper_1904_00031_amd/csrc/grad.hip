@@ -214,69 +214,6 @@ __device__ __forceinline__ void k_jvp_body(int BX, int BY, int BZ, int GX, int N
     xr[q] = Acc{0, 0, 0, 0};
     xi[q] = Acc{0, 0, 0, 0};
   }
-  if constexpr (sizeof(T) == 4) {
-    // FP32: X = S V^T on the bf16 matrix cores against the exact bf16 split of V stored
-    // after V^T. k group g (8 consecutive k) = part g % 3 of sites 8 (g / 3) .. + 7; lane
-    // group hi takes group 4 t + hi of step t. A: the spins of sample lo there (zero past N,
-    // past n and past the last group), from the wavefront's 16 rows staged in LDS (N <= 256)
-    // or read byte by byte; B: one 16-byte group of the split per tile and plane.
-    const uint16_t *Vs = reinterpret_cast<const uint16_t *>(
-        reinterpret_cast<const char *>(Vt) + vsplit_offset(N, M, sizeof(T) * (C ? 2 : 1)));
-    const int np = vsplit_np8(N), GP = np / 8;
-    const int KS = (3 * GP + 3) / 4;
-    constexpr int kRow = 264;  // staged row stride: 256 sites + 8 (rows 2 banks apart)
-    __shared__ __align__(16) int8_t sl[4][16 * kRow];
-    const bool staged = N <= 256;
-    if (staged) {
-      for (int e = lane; e < 16 * np; e += 64) {
-        const int r = e / np, c = e - r * np;
-        const int64_t row = s0 + r;
-        sl[wid][r * kRow + c] = (row < n && c < N) ? sigma[row * N + c] : int8_t(0);
-      }
-      wave_sync();
-    }
-#pragma unroll 2
-    for (int t = 0; t < KS; ++t) {
-      const int g8 = 4 * t + hi;
-      const int sg = g8 / 3, p = g8 - 3 * sg;
-      const bool gok = sg < GP;
-      const int sgc = gok ? sg : GP - 1;
-      T sv[8];
-      if (staged) {
-        const uint2 w = *reinterpret_cast<const uint2 *>(&sl[wid][lo * kRow + 8 * sgc]);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int b = int(int8_t(((e < 4 ? w.x : w.y) >> (8 * (e & 3))) & 0xffu));
-          sv[e] = gok ? T(b) : T(0);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int i = 8 * sgc + e;
-          const bool ok = rowA_ok && gok && i < N;
-          const int8_t b = srow[ok ? i : 0];
-          sv[e] = ok ? T(b) : T(0);
-        }
-      }
-      const uint4 av = make_uint4(pack_hi(sv[0], sv[1]), pack_hi(sv[2], sv[3]),
-                                  pack_hi(sv[4], sv[5]), pack_hi(sv[6], sv[7]));
-      uint4 bv[JT][C ? 2 : 1];
-#pragma unroll
-      for (int q = 0; q < JT; ++q) {
-        const int j = (jt0 + q) * 16 + lo;
-        const int jc = j < M ? j : M - 1;
-#pragma unroll
-        for (int pl = 0; pl < (C ? 2 : 1); ++pl)
-          bv[q][pl] = *reinterpret_cast<const uint4 *>(
-              Vs + ((size_t(pl * 3 + p) * GP + sgc) * M + jc) * 8);
-      }
-#pragma unroll
-      for (int q = 0; q < JT; ++q) {
-        xr[q] = mfma_bf16(av, bv[q][0], xr[q]);
-        if constexpr (C) xi[q] = mfma_bf16(av, bv[q][C ? 1 : 0], xi[q]);
-      }
-    }
-  } else
 #pragma unroll 2
   for (int k0 = 0; k0 < N; k0 += 4) {
     const int k = k0 + hi;
@@ -318,23 +255,278 @@ __device__ __forceinline__ void k_jvp_body(int BX, int BY, int BZ, int GX, int N
       if constexpr (C) yp[r].im += __shfl_xor(yp[r].im, m, 64);
     }
   }
+  // visible term of chunk 0: sample s0 + lo split over its four lane groups by site
+  double vr = 0.0, vi = 0.0;
+  if (jc == 0 && rowA_ok) {
+    for (int i = hi; i < N; i += 4) {
+      const double x = double(srow[i]);
+      vr += va[2 * i] * x;
+      vi += va[2 * i + 1] * x;
+    }
+  }
+  vr += __shfl_xor(vr, 16, 64);
+  vi += __shfl_xor(vi, 16, 64);
+  vr += __shfl_xor(vr, 32, 64);
+  vi += __shfl_xor(vi, 32, 64);
+  double var[4], vai[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    var[r] = __shfl(vr, MF<T>::row(hi, r), 64);
+    vai[r] = __shfl(vi, MF<T>::row(hi, r), 64);
+  }
   if (lo == 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = s0 + MF<T>::row(hi, r);
       if (row >= n) continue;
-      double yr = double(yp[r].re), yi = C ? double(yp[r].im) : 0.0;
-      if (jc == 0) {
-        const int8_t *sr = sigma + row * N;
-        for (int i = 0; i < N; ++i) {
-          yr += va[2 * i] * double(sr[i]);
-          yi += va[2 * i + 1] * double(sr[i]);
-        }
-      }
-      ypart[2 * (int64_t(jc) * n + row)] = yr;
-      ypart[2 * (int64_t(jc) * n + row) + 1] = yi;
+      ypart[2 * (int64_t(jc) * n + row)] = double(yp[r].re) + var[r];
+      ypart[2 * (int64_t(jc) * n + row) + 1] = (C ? double(yp[r].im) : 0.0) + vai[r];
     }
   }
+}
+
+// ---------------------------------------------------------------------------------
+// FP32 JVP on the bf16 matrix cores: X = S V^T against the exact three-part bf16 split
+// of V stored after V^T (k group g of 8 = part g % 3 of sites 8 (g / 3) .. + 7), then
+// y_s = sum_j t_sj (vb_j + X_sj) + sum_i s_si va_i. A block of four wavefronts covers
+// CW hidden chunks (JT tiles of 16) and 64 (4 / CW) samples: wavefront w takes chunk
+// BY CW + w % CW and the 64 samples of set w / CW as four 16-sample groups, so each
+// 16-byte load of the split feeds four MFMAs. The block's spins are staged in LDS as
+// bf16 (+1 = 0x3f80, -1 = 0xbf80, zero past N and past n), one window of 256 / sets
+// sites at a time. Writes ypart[chunk][s] (complex double); chunk 0 adds the visible
+// term, summed in FP64 by one lane per sample.
+// ---------------------------------------------------------------------------------
+constexpr int kJvpLdsWords = 9216;  // 256 rows x 144 B, 128 x 272 B or 64 x 528 B
+
+// spins s0 s1 (bytes 0 and 2 of u, +/-1 or 0) -> two bf16 in one dword
+__device__ __forceinline__ uint32_t spin_pair_bf16(uint32_t u) {
+  return ((u << 8) & 0x80008000u) | ((u & 0x00010001u) * 0x3f80u);
+}
+__device__ __forceinline__ uint4 spins8_bf16(uint32_t a, uint32_t b) {
+  return make_uint4(spin_pair_bf16((a & 0xffu) | ((a & 0xff00u) << 8)),
+                    spin_pair_bf16(((a >> 16) & 0xffu) | ((a >> 8) & 0xff0000u)),
+                    spin_pair_bf16((b & 0xffu) | ((b & 0xff00u) << 8)),
+                    spin_pair_bf16(((b >> 16) & 0xffu) | ((b >> 8) & 0xff0000u)));
+}
+
+inline int jvp32_cw(int jchunks) { return jchunks >= 3 ? 4 : (jchunks == 2 ? 2 : 1); }
+
+template <bool C>
+__device__ __forceinline__ void k_jvp32_body(int BX, int BY, int CW, int jchunks, int N, int M,
+                                             int64_t n, const int8_t *__restrict__ sigma,
+                                             const float *__restrict__ Tm,
+                                             const float *__restrict__ Vt,
+                                             const float *__restrict__ vb,
+                                             const double *__restrict__ va, double *ypart,
+                                             const int *skip) {
+  if (skip && *skip) return;
+  constexpr int JT = Chunk<float, C>::JT, PL = C ? 2 : 1;
+  __shared__ __align__(16) uint32_t sl[kJvpLdsWords];
+  __shared__ double2 ysh[4][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lo = lane & 15, hi = lane >> 4;
+  const int SB = 4 / CW, rows = 64 * SB;
+  const int wn = 256 / SB, WG = wn / 8;
+  // staged row: WG slots of 8 sites (16 bytes) and one zero slot read by idle k groups
+  const int kRowW = 4 * (WG + 1);
+  const int chunk = BY * CW + wid % CW, set = wid / CW;
+  const bool active = chunk < jchunks;
+  const int64_t sb0 = int64_t(BX) * rows, s0 = sb0 + 64 * set;
+  const uint4 *Vs = reinterpret_cast<const uint4 *>(
+      reinterpret_cast<const char *>(Vt) + vsplit_offset(N, M, sizeof(float) * (C ? 2 : 1)));
+  const int GP = vsplit_np8(N) / 8;
+  const uint32_t plane = uint32_t(3 * GP) * uint32_t(M);  // uint4 units per plane
+  uint32_t jcl[JT];
+#pragma unroll
+  for (int q = 0; q < JT; ++q) {
+    const int j = (chunk * JT + q) * 16 + lo;
+    jcl[q] = uint32_t(j < M ? j : M - 1);
+  }
+  floatx4 acc[4][JT][PL];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int q = 0; q < JT; ++q)
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) acc[g][q][pl] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bool vis = active && chunk == 0;
+  double vr = 0.0, vi = 0.0;  // visible term of sample s0 + lane
+  const bool al8 = (N & 7) == 0 && (reinterpret_cast<uintptr_t>(sigma) & 7) == 0;
+  const bool al4 = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(sigma) & 3) == 0;
+  for (int wg0 = 0; wg0 < GP; wg0 += WG) {
+    const int GPw = GP - wg0 < WG ? GP - wg0 : WG;
+    const int c0 = 8 * wg0;
+    if (wg0 > 0) __syncthreads();
+    // stage rows [sb0, sb0 + rows) x sites [c0, c0 + 8 GPw), 8 sites per item; the last
+    // item of a row clears its zero slot
+    for (int e = threadIdx.x; e < rows * (GPw + 1); e += 256) {
+      const int r = e / (GPw + 1), c = e - r * (GPw + 1);
+      const int64_t row = sb0 + r;
+      const int col = c0 + 8 * c;
+      uint32_t a = 0, b = 0;
+      if (row < n && c < GPw) {
+        const int8_t *src = sigma + row * N + col;
+        if (al8) {
+          const uint2 w = *reinterpret_cast<const uint2 *>(src);
+          a = w.x;
+          b = w.y;
+        } else if (al4) {
+          a = *reinterpret_cast<const uint32_t *>(src);
+          if (col + 4 < N) b = *reinterpret_cast<const uint32_t *>(src + 4);
+        } else {
+          const int8_t *rp = sigma + row * N;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int i = col + k < N ? col + k : N - 1;
+            const uint32_t x = col + k < N ? uint32_t(uint8_t(rp[i])) : 0u;
+            if (k < 4) a |= x << (8 * k);
+            else b |= x << (8 * (k - 4));
+          }
+        }
+      }
+      *reinterpret_cast<uint4 *>(&sl[r * kRowW + 4 * (c < GPw ? c : WG)]) = spins8_bf16(a, b);
+    }
+    __syncthreads();
+    if (vis) {
+      // s_i from the sign bit of the staged bf16 spin, 8 sites per LDS read
+      const int nw = N - c0 < 8 * GPw ? N - c0 : 8 * GPw;
+      const uint32_t *sr = &sl[(64 * set + lane) * kRowW];
+      for (int c = 0; c < GPw; ++c) {
+        const uint4 d = *reinterpret_cast<const uint4 *>(sr + 4 * c);
+        const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = 8 * c + k;
+          const uint32_t sb = dw[k >> 1] & ((k & 1) ? 0x80000000u : 0x8000u);
+          const double x = i < nw ? (sb ? -1.0 : 1.0) : 0.0;
+          const int ic = c0 + (i < nw ? i : nw - 1);
+          vr += va[2 * ic] * x;
+          vi += va[2 * ic + 1] * x;
+        }
+      }
+    }
+    if (active) {
+      // step t: lane group hi takes k group 4 t + hi (part p of site group sg); the split
+      // of step t + 1 is loaded while step t is contracted
+      const int KSw = (3 * GPw + 3) / 4;
+      const uint32_t *arow = &sl[(64 * set + lo) * kRowW];
+      auto load_b = [&](int t, uint4 (&bv)[JT][PL]) {
+        const int g8 = 4 * t + hi;
+        const int sg = g8 / 3, p = g8 - 3 * sg;
+        const int sgc = sg < GPw ? sg : GPw - 1;
+        const uint32_t o = (uint32_t(p * GP + wg0 + sgc)) * uint32_t(M);
+#pragma unroll
+        for (int q = 0; q < JT; ++q)
+#pragma unroll
+          for (int pl = 0; pl < PL; ++pl) bv[q][pl] = Vs[o + jcl[q] + pl * plane];
+      };
+      auto step = [&](int t, const uint4 (&bv)[JT][PL]) {
+        const int sg = (4 * t + hi) / 3;
+        const uint32_t *ap = arow + 4 * (sg < GPw ? sg : WG);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const uint4 av = *reinterpret_cast<const uint4 *>(ap + 16 * g * kRowW);
+#pragma unroll
+          for (int q = 0; q < JT; ++q)
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+              acc[g][q][pl] = mfma_bf16(av, bv[q][pl], acc[g][q][pl]);
+        }
+      };
+      // two buffers in turn; a step past the last one reads the zero slot
+      uint4 b0[JT][PL], b1[JT][PL];
+      load_b(0, b0);
+      for (int t = 0; t < KSw; t += 2) {
+        load_b(t + 1 < KSw ? t + 1 : t, b1);
+        step(t, b0);
+        load_b(t + 2 < KSw ? t + 2 : t, b0);
+        step(t + 1, b1);
+      }
+    }
+  }
+  if (!active) return;
+  V<float, C> vbj[JT];
+#pragma unroll
+  for (int q = 0; q < JT; ++q) {
+    const int j = (chunk * JT + q) * 16 + lo;
+    vbj[q] = j < M ? vload<float, C>(vb, j) : vmake<float, C>(0.f, 0.f);
+  }
+  // T entries one group ahead of the group being summed
+  auto load_t = [&](int g, V<float, C> (&tv)[JT][4]) {
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      const int j = (chunk * JT + q) * 16 + lo;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = s0 + 16 * g + 4 * hi + r;
+        const bool ok = j < M && row < n;
+        const V<float, C> x = vload<float, C>(Tm, ok ? row * M + j : 0);
+        tv[q][r] = ok ? x : vmake<float, C>(0.f, 0.f);
+      }
+    }
+  };
+  V<float, C> tc[JT][4], tn[JT][4];
+  load_t(0, tc);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    if (g + 1 < 4) load_t(g + 1, tn);
+    __builtin_amdgcn_sched_barrier(0);
+    V<float, C> yp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) yp[r] = vmake<float, C>(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < JT; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const V<float, C> x = vmake<float, C>(acc[g][q][0][r] + vbj[q].re,
+                                              C ? acc[g][q][C ? 1 : 0][r] + vbj[q].im : 0.f);
+        yp[r] = vadd(yp[r], vmul(tc[q][r], x));
+      }
+    // sums over the 16 columns of each row; lane lo < 4 keeps row 4 hi + lo of the group
+    float yr = 0.f, yi = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float a = yp[r].re;
+      a += dpp_f<DPP_QP_XOR1>(a);
+      a += dpp_f<DPP_QP_XOR2>(a);
+      a += dpp_f<DPP_ROR4>(a);
+      a += dpp_f<DPP_ROR8>(a);
+      yr = lo == r ? a : yr;
+      if constexpr (C) {
+        float b = yp[r].im;
+        b += dpp_f<DPP_QP_XOR1>(b);
+        b += dpp_f<DPP_QP_XOR2>(b);
+        b += dpp_f<DPP_ROR4>(b);
+        b += dpp_f<DPP_ROR8>(b);
+        yi = lo == r ? b : yi;
+      }
+    }
+    if (lo < 4) ysh[wid][16 * g + 4 * hi + lo] = make_double2(double(yr), double(yi));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < JT; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tc[q][r] = tn[q][r];
+  }
+  wave_sync();
+  const int64_t s = s0 + lane;
+  if (s < n) {
+    const double2 y = ysh[wid][lane];
+    *reinterpret_cast<double2 *>(ypart + 2 * (int64_t(chunk) * n + s)) =
+        make_double2(y.x + vr, y.y + vi);
+  }
+}
+
+template <bool C>
+__global__ __launch_bounds__(256, 2) void k_jvp32(int CW, int jchunks, int N, int M, int64_t n,
+                                                   const int8_t *__restrict__ sigma,
+                                                   const float *__restrict__ Tm,
+                                                   const float *__restrict__ Vt,
+                                                   const float *__restrict__ vb,
+                                                   const double *__restrict__ va,
+                                                   double *ypart, const int *skip) {
+  k_jvp32_body<C>(blockIdx.x, blockIdx.y, CW, jchunks, N, M, n, sigma, Tm, Vt, vb, va, ypart,
+                  skip);
 }
 
 template <typename T, bool C>
@@ -1410,10 +1602,19 @@ hipError_t jvp_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scrat
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
-  hipLaunchKernelGGL((k_jvp<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256), 0, st,
-                     m->N, m->M, n, sigma, (const T *)(base + L.Tm), (const T *)(base + L.Vt),
-                     (const T *)(base + L.vb), (const double *)(base + L.va),
-                     (double *)(base + L.ypart), skip);
+  if constexpr (sizeof(T) == 4) {
+    const int cw = jvp32_cw(g.jchunks);
+    const dim3 grid(unsigned(cdiv(n > 0 ? n : 1, 256 / cw)), unsigned(cdiv(g.jchunks, cw)));
+    hipLaunchKernelGGL((k_jvp32<C>), grid, dim3(256), 0, st, cw, g.jchunks, m->N, m->M, n, sigma,
+                       (const T *)(base + L.Tm), (const T *)(base + L.Vt),
+                       (const T *)(base + L.vb), (const double *)(base + L.va),
+                       (double *)(base + L.ypart), skip);
+  } else {
+    hipLaunchKernelGGL((k_jvp<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256), 0, st,
+                       m->N, m->M, n, sigma, (const T *)(base + L.Tm), (const T *)(base + L.Vt),
+                       (const T *)(base + L.vb), (const double *)(base + L.va),
+                       (double *)(base + L.ypart), skip);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_jvp_finish<C>), dim3(unsigned(cdiv(n, 256))), dim3(256), 0, st, n,
@@ -1626,15 +1827,19 @@ struct JvpJob {
   const T *Tm, *Vt, *vb;
   const double *va;
   double *ypart, *y, *ysum;
-  int jchunks;
+  int jchunks, cw;  // cw: hidden chunks per block of the FP32 kernel
   const int *skip;
 };
 template <typename T, bool C>
-__global__ __launch_bounds__(256) void kb_jvp(const JvpJob<T> *jobs, const int4 *map) {
+__global__ __launch_bounds__(256, 2) void kb_jvp(const JvpJob<T> *jobs, const int4 *map) {
   const int4 b = map[blockIdx.x];
   const JvpJob<T> J = jobs[b.x];
-  k_jvp_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Tm, J.Vt, J.vb, J.va, J.ypart,
-                   J.skip);
+  if constexpr (sizeof(T) == 4)
+    k_jvp32_body<C>(b.y, b.z, J.cw, J.jchunks, J.N, J.M, J.n, J.sigma, J.Tm, J.Vt, J.vb, J.va,
+                    J.ypart, J.skip);
+  else
+    k_jvp_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Tm, J.Vt, J.vb, J.va, J.ypart,
+                     J.skip);
 }
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void kb_jvp_finish(const JvpJob<T> *jobs, const int4 *map) {
@@ -1722,11 +1927,12 @@ hipError_t jvp_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, in
     const BatchGradItem &it = items[k];
     const nqs_model *m = it.m;
     const int jchunks = int(cdiv((m->M + 15) / 16, Chunk<T, C>::JT));
+    const int cw = sizeof(T) == 4 ? jvp32_cw(jchunks) : 1;
     JvpJob<T> J{m->N, m->M, it.n, it.sigma, (const T *)it.Tm, (const T *)it.Vt, (const T *)it.vb,
-                it.va, it.ypart, it.y, it.ysum, jchunks, it.skip};
+                it.va, it.ypart, it.y, it.ysum, jchunks, cw, it.skip};
     jobs.push_back(J);
-    const int gx = int(cdiv(it.n, 64));
-    for (int y = 0; y < jchunks; ++y)
+    const int gx = int(cdiv(it.n, sizeof(T) == 4 ? 256 / cw : 64));
+    for (int y = 0; y < int(cdiv(jchunks, cw)); ++y)
       for (int x = 0; x < gx; ++x) map.push_back(make_int4(int(k), x, y, 0));
     for (int x = 0; x < int(cdiv(it.n, 256)); ++x) map2.push_back(make_int4(int(k), x, 0, 0));
   }
