@@ -232,6 +232,9 @@ void nqs_model_destroy(nqs_model *m) {
   if (m->d_scratch) (void)hipFree(m->d_scratch);
   if (m->cg_exec) (void)hipGraphExecDestroy(m->cg_exec);
   if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+  if (m->cg_host) (void)hipHostFree(m->cg_host);
+  for (hipEvent_t e : m->cg_ev)
+    if (e) (void)hipEventDestroy(e);
   delete m;
 }
 

@@ -88,6 +88,9 @@ void nqs_batch_destroy(nqs_batch *b) {
   b->sweep_jobs.release();
   b->sweep_map.release();
   for (JobBuffer &j : b->sr_bufs) j.release();
+  if (b->cg_host) (void)hipHostFree(b->cg_host);
+  for (hipEvent_t e : b->cg_ev)
+    if (e) (void)hipEventDestroy(e);
   delete b;
 }
 

@@ -45,6 +45,10 @@ struct nqs_model {
   hipStream_t cap_stream = nullptr;  // capture only (default priority)
   hipGraphExec_t cg_exec = nullptr;
   CgGraphKey cg_key;
+  // solver-state copies read by the host while the next chunk runs: pinned host memory
+  // (two slots) and the events that mark each copy complete
+  void *cg_host = nullptr;
+  hipEvent_t cg_ev[2] = {nullptr, nullptr};
 };
 
 // Device copy of a host-built job table. upload() copies only when the bytes differ from
@@ -80,6 +84,10 @@ struct nqs_batch {
   static constexpr int kSlots = 32;
   JobBuffer sr_bufs[kSlots];
   JobBuffer &buf(int slot) { return sr_bufs[slot < kSlots ? slot : kSlots - 1]; }
+  // gathered solver states read by the host while the next chunk runs (pinned, two slots)
+  void *cg_host = nullptr;
+  size_t cg_host_bytes = 0;
+  hipEvent_t cg_ev[2] = {nullptr, nullptr};
 };
 
 // one model of a batched Jacobian pass (device pointers into the model's workspace)

@@ -8,6 +8,7 @@
 // partials in a fixed order), so results are bitwise reproducible run to run.
 #include <math.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -667,15 +668,19 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
                      cg_maxiter, state);
   HIPTRY(hipGetLastError());
 
+  // Chunks of check_every iterations. The state after each chunk is copied to pinned host
+  // memory behind the chunk, and the next chunk is queued before the host reads the copy,
+  // so the device does not wait for the check; a chunk queued after convergence returns
+  // at once in every kernel (the done flag).
+  if (!m->cg_host) HIPTRY(hipHostMalloc(&m->cg_host, 2 * sizeof(CGState), hipHostMallocDefault));
+  for (hipEvent_t &e : m->cg_ev)
+    if (!e) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  CGState *hslot = (CGState *)m->cg_host;
   CGState hs;
   const int check_every = 8;
-  int launched = 0;
+  int launched = 0, queued = 0, checked = 0;
   const int *skip = &state->done;
-  while (true) {
-    HIPTRY(hipMemcpyAsync(&hs, state, sizeof(CGState), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    if (hs.done || launched >= cg_maxiter) break;
-    const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
+  auto enqueue = [&](int batch) -> nqs_status {
     // one CG iteration = the product's partial tiles, k_cg_apr, k_cg_xr, k_cg_p
     const int64_t ablocks = cdiv(elems, kAprElems);
     auto iterations = [&](int count, hipStream_t s2) -> hipError_t {
@@ -741,8 +746,32 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
     } else {
       HIPTRY(iterations(batch, st));
     }
-    launched += batch;
+    const int slot = queued & 1;
+    HIPTRY(hipMemcpyAsync(&hslot[slot], state, sizeof(CGState), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipEventRecord(m->cg_ev[slot], st));
+    ++queued;
+    return NQS_OK;
+  };
+  // the state before the first chunk (k_cg_start may already have finished the solve)
+  HIPTRY(hipMemcpyAsync(&hs, state, sizeof(CGState), hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  bool done = hs.done != 0;
+  while (!done) {
+    while (queued - checked < 2 && launched < cg_maxiter) {
+      const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
+      const nqs_status qs = enqueue(batch);
+      if (qs != NQS_OK) return qs;
+      launched += batch;
+    }
+    if (queued == checked) break;
+    const int slot = checked & 1;
+    HIPTRY(hipEventSynchronize(m->cg_ev[slot]));
+    hs = hslot[slot];
+    ++checked;
+    done = hs.done != 0;
   }
+  // chunks still queued return at once; the state no longer changes once done is set
+  // (and the stream orders them before the update below)
   const bool nonfinite = hs.nonfinite || !std::isfinite(hs.E[0]) || !std::isfinite(hs.var);
   if (!nonfinite) {
     if (use_double(m))
@@ -752,8 +781,8 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
       hipLaunchKernelGGL(k_update<float>, dim3(grid_for(Pc)), dim3(256), 0, st, Pc,
                          (float *)params, (const double *)D(L.x), lr);
     HIPTRY(hipGetLastError());
-    HIPTRY(hipStreamSynchronize(st));
   }
+  HIPTRY(hipStreamSynchronize(st));
   if (info) {
     info->cg_iters = hs.iters;
     info->converged = hs.converged;
@@ -1122,34 +1151,69 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
   BTRY(b->buf(kSlotStates).upload(hs.data(), hs.size() * sizeof(CGState), st));
   if (!b->buf(kSlotStates).d) return NQS_EDEVICE;
   CGState *dstates = (CGState *)b->buf(kSlotStates).d;
+  // chunks of check_every iterations; the gathered states after each chunk are copied to
+  // pinned host memory behind it, and the next chunk is queued before the host reads them
+  const size_t hbytes = 2 * size_t(K) * sizeof(CGState);
+  if (b->cg_host_bytes < hbytes) {
+    if (b->cg_host) BTRY(hipHostFree(b->cg_host));
+    b->cg_host = nullptr;
+    b->cg_host_bytes = 0;
+    BTRY(hipHostMalloc(&b->cg_host, hbytes, hipHostMallocDefault));
+    b->cg_host_bytes = hbytes;
+  }
+  for (hipEvent_t &ev : b->cg_ev)
+    if (!ev) BTRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  CGState *hslot = (CGState *)b->cg_host;
   const int check_every = 8;
-  int launched = 0;
-  while (true) {
+  int launched = 0, queued = 0, checked = 0;
+  auto gather = [&](CGState *dst) -> hipError_t {
     hipLaunchKernelGGL((kb_gather_states<T>), dim3(unsigned((K + 63) / 64)), dim3(64), 0, st, dj,
                        K, dstates);
-    BTRY(hipGetLastError());
-    BTRY(hipMemcpyAsync(hs.data(), dstates, hs.size() * sizeof(CGState), hipMemcpyDeviceToHost,
-                        st));
-    BTRY(hipStreamSynchronize(st));
-    bool all_done = true;
-    for (int k = 0; k < K; ++k) all_done = all_done && hs[k].done;
-    if (all_done || launched >= cg_maxiter) break;
-    const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
-    for (int q = 0; q < batch; ++q, ++launched) {
-      const int parity = launched & 1;
-      BTRY(launch_jvp_batch(b, gi, kSlotJvp, st));
-      BTRY(launch_vjp_batch(b, gi, false, kSlotVjpY, st));
-      hipLaunchKernelGGL((kb_cg_ap<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj,
-                         mp, diag_shift);
-      BTRY(hipGetLastError());
-      hipLaunchKernelGGL((kb_cg_xr<T>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj, mc,
-                         parity);
-      BTRY(hipGetLastError());
-      hipLaunchKernelGGL((kb_cg_p<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj, mp,
-                         parity, cg_tol, cg_maxiter);
-      BTRY(hipGetLastError());
+    hipError_t e2 = hipGetLastError();
+    if (e2 == hipSuccess)
+      e2 = hipMemcpyAsync(dst, dstates, size_t(K) * sizeof(CGState), hipMemcpyDeviceToHost, st);
+    return e2;
+  };
+  auto all_done = [&]() {
+    bool d = true;
+    for (int k = 0; k < K; ++k) d = d && hs[k].done;
+    return d;
+  };
+  // the states before the first chunk
+  BTRY(gather(hs.data()));
+  BTRY(hipStreamSynchronize(st));
+  bool done = all_done();
+  while (!done) {
+    while (queued - checked < 2 && launched < cg_maxiter) {
+      const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
+      for (int q = 0; q < batch; ++q, ++launched) {
+        const int parity = launched & 1;
+        BTRY(launch_jvp_batch(b, gi, kSlotJvp, st));
+        BTRY(launch_vjp_batch(b, gi, false, kSlotVjpY, st));
+        hipLaunchKernelGGL((kb_cg_ap<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj,
+                           mp, diag_shift);
+        BTRY(hipGetLastError());
+        hipLaunchKernelGGL((kb_cg_xr<T>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj,
+                           mc, parity);
+        BTRY(hipGetLastError());
+        hipLaunchKernelGGL((kb_cg_p<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj,
+                           mp, parity, cg_tol, cg_maxiter);
+        BTRY(hipGetLastError());
+      }
+      const int slot = queued & 1;
+      BTRY(gather(hslot + size_t(slot) * K));
+      BTRY(hipEventRecord(b->cg_ev[slot], st));
+      ++queued;
     }
+    if (queued == checked) break;
+    const int slot = checked & 1;
+    BTRY(hipEventSynchronize(b->cg_ev[slot]));
+    std::copy(hslot + size_t(slot) * K, hslot + size_t(slot + 1) * K, hs.begin());
+    ++checked;
+    done = all_done();
   }
+  // chunks still queued return at once (every model's done flag is set, and the states no
+  // longer change)
   hipLaunchKernelGGL((kb_update<T, PT>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj, mc,
                      lr);
   BTRY(hipGetLastError());
