@@ -504,6 +504,14 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
             V<T, C> term[R];
   #pragma unroll
             for (int r = 0; r < R; ++r) term[r] = vsub(cur.c[r], vscale(vmul(t[r], cur.s[r]), ts));
+            // with few units per lane the updated t is formed before the decision (it
+            // overlaps the reduction) and only selected after it
+            V<T, C> tn[PF ? R : 1];
+            if constexpr (PF) {
+  #pragma unroll
+              for (int r = 0; r < R; ++r)
+                tn[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
+            }
             int accept;
             if constexpr (sizeof(T) == 4) {
               // log-domain decision: accept iff sum_j log2|term_j|^2 > log2(u) - log2|a|^2
@@ -550,7 +558,10 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
                 if (R <= 4 || lane + 64 * r < M) {
                   thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
                   if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
-                  t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
+                  if constexpr (PF)
+                    t[r] = tn[r];
+                  else
+                    t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
                 }
               }
               smask ^= (1ull << ic) | (flip ? 0ull : (1ull << kc));
@@ -602,6 +613,13 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
           V<T, C> term[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) term[r] = vsub(cur.c[r], vscale(vmul(t[r], cur.s[r]), ts));
+          // updated t formed before the decision for few units per lane (as above)
+          V<T, C> tn[PF ? R : 1];
+          if constexpr (PF) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              tn[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
+          }
           int accept;
           if constexpr (sizeof(T) == 4) {
             // log-domain decision: accept iff sum_j log2|term_j|^2 > log2(u) - log2|a|^2
@@ -648,7 +666,10 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
               if (R <= 4 || lane + 64 * r < M) {
                 thr[r] -= 2.0 * double(s) * double(cur.w[r].re);
                 if (C) thi[r] -= 2.0 * double(s) * double(cur.w[r].im);
-                t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
+                if constexpr (PF)
+                  t[r] = tn[r];
+                else
+                  t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
               }
             }
               // spin registers (one lane each) and the LDS copy
@@ -905,14 +926,25 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
       if (__ballot(conn && ok) == 0) continue;  // no lane connects this row
       const T ts = T(sgn);
       const T *crow = lC + int64_t(c) * MJ * cs, *srow = lS + int64_t(c) * MJ * cs;
-      V<T, C> p = vmake<T, C>(T(1), T(0));
-      int pe = 0;
+      // four interleaved partial products (j mod 4), so that four independent
+      // multiplication chains are in flight, then combined
+      V<T, C> pq[4];
+      int peq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pq[q] = vmake<T, C>(T(1), T(0));
+        peq[q] = 0;
+      }
 #pragma unroll
       for (int j = 0; j < MJ; ++j) {
         const V<T, C> cc = vload<T, C>(crow, j), ss = vload<T, C>(srow, j);
-        p = vmul(p, vsub(cc, vscale(vmul(t[j], ss), ts)));
-        if ((j & 7) == 7) vrenorm(p, pe);
+        pq[j & 3] = vmul(pq[j & 3], vsub(cc, vscale(vmul(t[j], ss), ts)));
+        if ((j & 31) >= 28) vrenorm(pq[j & 3], peq[j & 3]);
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vrenorm(pq[q], peq[q]);
+      V<T, C> p = vmul(vmul(pq[0], pq[1]), vmul(pq[2], pq[3]));
+      int pe = (peq[0] + peq[1]) + (peq[2] + peq[3]);
       vrenorm(p, pe);
       const double *af = tfim ? tb.fa + 2 * (int64_t(sgn > 0 ? 0 : 1) * N + c)
                               : tb.ba + 2 * (int64_t(sgn > 0 ? 0 : 1) * B + c);
@@ -1129,7 +1161,8 @@ hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64
       // one block of four wavefronts per compute unit (the row in registers takes up to
       // 512 registers per lane)
       int64_t blocks = (n + 255) / 256;
-      const int per_cu = 1;
+      // up to 48 hidden units the row and products fit two wavefronts per SIMD
+      const int per_cu = tp <= 3 ? 2 : 1;
       if (blocks > int64_t(per_cu) * m->cu_count) blocks = int64_t(per_cu) * m->cu_count;
 #define NQS_ELOC_LANES(TPM)                                                                   \
   if (tp <= TPM) {                                                                            \
