@@ -382,8 +382,9 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
                                                 double *Ap, double *dpart, const CGState *st) {
   __shared__ double lds[256];
   __shared__ double sr[kAprSlices][kAprElems], si[kAprSlices][kAprElems];
-  // the solver state and the sums of y in one memory round trip
-  const int done = st->done;
+  // the solver state and the sums of y in one memory round trip (no state: a single
+  // product, always computed)
+  const int done = st ? st->done : 0;
   double ysr = 0.0, ysi = 0.0;
   for (int64_t k = threadIdx.x; k < nys; k += blockDim.x) {
     ysr += ysum[2 * k];
@@ -796,43 +797,6 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   return hs.converged ? NQS_OK : NQS_ENOTCONV;
 }
 
-// out = (g - ybar O^dagger 1) / n + lambda v, g = O^dagger y from the first-level sums
-template <bool C>
-__global__ __launch_bounds__(256) void k_matvec_finish(int N, int M, int64_t n, int groups,
-                                                       int colsP, int64_t elems,
-                                                       const double *out1, const double *o1,
-                                                       const double *ysum, int64_t nys,
-                                                       const double *v, double lambda,
-                                                       double *out) {
-  __shared__ double lds[256];
-  const int64_t P = int64_t(N) + M + int64_t(N) * M;
-  const double ybr = block_sum(ysum, nys, 2, lds) / double(n);
-  const double ybi = C ? block_sum(ysum + 1, nys, 2, lds) / double(n) : 0.0;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < P;
-       k += int64_t(gridDim.x) * 256) {
-    int64_t e;
-    if (k < N)
-      e = int64_t(M) * colsP + k;
-    else if (k < N + M)
-      e = int64_t(k - N) * colsP + N;
-    else
-      e = ((k - N - M) / N) * colsP + ((k - N - M) % N);
-    double gr = 0.0, gi = 0.0;
-    for (int q = 0; q < groups; ++q) {
-      gr += out1[2 * (int64_t(q) * elems + e)];
-      gi += out1[2 * (int64_t(q) * elems + e) + 1];
-    }
-    if (C) {
-      gr -= ybr * o1[2 * k] - ybi * o1[2 * k + 1];
-      gi -= ybr * o1[2 * k + 1] + ybi * o1[2 * k];
-      out[2 * k] = gr / double(n) + lambda * v[2 * k];
-      out[2 * k + 1] = gi / double(n) + lambda * v[2 * k + 1];
-    } else {
-      out[k] = (gr - ybr * o1[k]) / double(n) + lambda * v[k];
-    }
-  }
-}
-
 template <bool C>
 nqs_status prepare_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
                         void *ws, hipStream_t st) {
@@ -856,21 +820,29 @@ nqs_status matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws, c
   void *grad = b + L.grad;
   const GradPlan gp = grad_plan(m, n);
   const GradBuffers gb = grad_buffers(m, n, grad);
-  const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
-  const int64_t pblocks = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
   const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
   HIPTRY(launch_prep_dir(m, v, grad, !gp.fused, st));
+  // the partial tiles of the product, summed over the sample splits by the kernel of the
+  // CG iterations (no solver state)
   if (gp.fused) {
-    HIPTRY(launch_sv(m, sigma, n, grad, (double *)(b + L.ysum), nullptr, st));
+    HIPTRY(launch_sv(m, sigma, n, grad, (double *)(b + L.ysum), nullptr, st, false));
   } else {
     HIPTRY(launch_jvp(m, sigma, n, grad, (double *)(b + L.y), (double *)(b + L.ysum), nullptr, st));
-    HIPTRY(launch_vjp_partials(m, sigma, n, (double *)(b + L.y), grad, nullptr, st));
+    HIPTRY(launch_vjp_partials(m, sigma, n, (double *)(b + L.y), grad, nullptr, st, false));
   }
   const int64_t nys = gp.fused ? gp.splits : cdiv(n, 256);
-  hipLaunchKernelGGL((k_matvec_finish<C>), dim3(unsigned(pblocks)), dim3(256), 0, st, m->N,
-                     m->M, n, gp.groups, gp.Itiles * 16, elems, gb.out1,
-                     (const double *)(b + L.o1), (const double *)(b + L.ysum), nys,
-                     (const double *)v, lambda, (double *)out);
+  const dim3 grid(unsigned(cdiv(elems, kAprElems)));
+  auto apr = [&](auto tc) {
+    typedef decltype(tc) T;
+    hipLaunchKernelGGL((k_cg_apr<T, C>), grid, dim3(256), 0, st, m->N, m->M, n, gp.splits,
+                       gp.Itiles * 16, elems, (const T *)gb.part, (const double *)(b + L.o1),
+                       (const double *)(b + L.ysum), nys, (const double *)v, lambda,
+                       (double *)out, (double *)(b + L.dpart), (const CGState *)nullptr);
+  };
+  if (use_double(m))
+    apr(double(0));
+  else
+    apr(float(0));
   HIPTRY(hipGetLastError());
   return NQS_OK;
 }
