@@ -1809,7 +1809,7 @@ struct TanhJob {
   int64_t n;
   const int8_t *sigma;
   const T *Wt, *bv;
-  int quant;
+  int quant, pad0;  // explicit padding (zero): job tables are compared byte by byte
   T *Tout;
 };
 template <typename T, bool C>
@@ -1855,12 +1855,12 @@ struct VjpJob {
   const int8_t *sigma;
   const T *Tm;
   const double *u;
-  int rowsP, colsP, splits;
-  int64_t elems;
+  int rowsP, colsP, splits, pad0;  // explicit padding (zero): job tables are compared
+  int64_t elems;                   // byte by byte before an upload
   T *part;
   double *out1;  // [rowsP][colsP] complex double
   double *out;   // packed like the parameters, or NULL (kept in out1)
-  int pblocks;
+  int pblocks, pad1;
   const int *skip;
 };
 template <typename T, bool C>
@@ -1885,6 +1885,14 @@ __global__ __launch_bounds__(256) void kb_vjp_reduce2(const VjpJob<T> *jobs, con
                         J.skip);
 }
 
+// job tables are compared byte by byte with the previous upload: no implicit padding
+static_assert(std::has_unique_object_representations_v<TanhJob<float>> &&
+                  std::has_unique_object_representations_v<JvpJob<float>> &&
+                  std::has_unique_object_representations_v<VjpJob<float>> &&
+                  std::has_unique_object_representations_v<JvpJob<double>> &&
+                  std::has_unique_object_representations_v<VjpJob<double>>,
+              "job structs must not hold padding bytes");
+
 template <typename T>
 hipError_t upload_launch_map(JobBuffer &jb, JobBuffer &mb, const std::vector<T> &jobs,
                              const std::vector<int4> &map, hipStream_t st) {
@@ -1905,7 +1913,7 @@ hipError_t tanh_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, i
     const BatchGradItem &it = items[k];
     const nqs_model *m = it.m;
     TanhJob<T> J{m->N, m->M, it.n, it.sigma, (const T *)m->tab_ptrs[0], (const T *)m->tab_ptrs[1],
-                 int(m->prec == NQS_BF16), (T *)it.Tm};
+                 int(m->prec == NQS_BF16), 0, (T *)it.Tm};
     jobs.push_back(J);
     const int gx = int(cdiv(it.n, 64)), gy = int(cdiv((m->M + 15) / 16, Chunk<T, C>::JT));
     for (int y = 0; y < gy; ++y)
@@ -1962,8 +1970,8 @@ hipError_t vjp_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, bo
     const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
     const int pblocks = int(cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096);
     VjpJob<T> J{m->N,  m->M,    it.n,         it.sigma,  (const T *)it.Tm, it.u,
-                Jtiles * 16, Itiles * 16, splits, elems, (T *)it.part, it.out1,
-                to_params ? it.out : nullptr, pblocks, it.skip};
+                Jtiles * 16, Itiles * 16, splits, 0, elems, (T *)it.part, it.out1,
+                to_params ? it.out : nullptr, pblocks, 0, it.skip};
     jobs.push_back(J);
     for (int z = 0; z < int(cdiv(Itiles, kBNT)); ++z)
       for (int y = 0; y < splits; ++y)
