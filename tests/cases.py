@@ -35,6 +35,10 @@ CASES = {
 BIG = {
     # more than 256 sites: spins read from LDS instead of lane registers
     "tfim300_real_f32": (300, 1, False, 0, (1.0, 0.0), 1.0, False, 0, False, 1, 300),
+    # site counts beyond one LDS window of the FP32 Jacobian-vector kernel for each of its
+    # block shapes (one, two and four hidden chunks per block)
+    "tfim100_cplx_f32_m32": (100, 1, False, 0, (1.0, 0.0), 1.0, False, 0, True, 1, 32),
+    "tfim150_cplx_f32_m100": (150, 1, False, 0, (1.0, 0.0), 0.7, False, 0, True, 1, 100),
     # the 10x10 J1-J2 lattice with alpha = 4 and the 16x16 Heisenberg lattice with
     # alpha = 8 of the large workloads
     "j1j2_10x10_cplx_f32": (10, 2, True, 1, (1.0, 0.5), 0.0, True, 1, True, 1, 400),

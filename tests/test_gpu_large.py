@@ -92,3 +92,32 @@ def test_large_jacobian_and_sv_sampled(lib, name):
     exp = orbm.vjp_entries(pe, s, ej - ej.mean(), ks, N, M, rt) / n + 0.01 * v[ks]
     scale = np.abs(orbm.vjp_entries(pe, s, ej, ks, N, M, rt)).max() / n
     assert np.abs(got[ks] - exp).max() <= t * scale
+
+
+@pytest.mark.parametrize("name,n", [("tfim100_cplx_f32_m32", 130), ("tfim150_cplx_f32_m100", 97),
+                                    ("tfim300_real_f32", 70)])
+def test_jacobian_products_many_sites(lib, name, n):
+    """O v and O^dagger u where the sites span several staged windows of the FP32
+    Jacobian-vector kernel (N above 64, 128 or 256 for one, two or four hidden chunks per
+    block), on ragged sample counts; every entry against the oracle's explicit O."""
+    m, om = cases.build(lib, name)
+    N, M = om.n_sites, om.n_hidden
+    p = cases.params(name, seed=85)
+    pe = cases.oracle_params(name, p)
+    s = cases.configs(name, n, seed=22)
+    rng = np.random.default_rng(23)
+    P = m.n_params
+    u = rng.normal(size=n)
+    v = rng.normal(size=P)
+    if m.is_complex:
+        u = u + 1j * rng.normal(size=n)
+        v = v + 1j * rng.normal(size=P)
+    vjp, jvp = m.log_psi_grad(to_dev(p), to_dev(s), u=to_dev(u), v=to_dev(v))
+    O = orbm.log_derivatives(pe, s, N, M)
+    if not m.is_complex:
+        O = O.real
+    ej = O @ v
+    ev = O.conj().T @ u
+    t = cases.tol(name)
+    assert np.abs(jvp.cpu().numpy() - ej).max() <= t * np.abs(ej).max()
+    assert np.abs(vjp.cpu().numpy() - ev).max() <= t * np.abs(ev).max()
