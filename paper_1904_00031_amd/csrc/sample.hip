@@ -851,6 +851,107 @@ __global__ __launch_bounds__(64 * kElocWaves) void k_local_energy(DevModel dm, T
 }
 
 // ---------------------------------------------------------------------------------
+// Local energy for wide models (M > 256) whose tables do not fit in LDS: a block of
+// kRowsWaves wavefronts takes one sample each (its tanh row in registers, R values per
+// lane) and walks the candidate rows (sites for TFIM, bonds for Heisenberg) in chunks of
+// KB rows. Each chunk's C/S rows are staged in LDS once and read by every wavefront whose
+// sample connects them, so a block reads the tables once for its samples instead of once
+// per sample. Same terms and product order as eloc_regs (Eq. 5).
+// ---------------------------------------------------------------------------------
+constexpr int kRowsWaves = 16;
+
+template <typename T, bool C, int R>
+__global__ __launch_bounds__(64 * kRowsWaves) void k_eloc_rows(DevModel dm, Tables<T> tb,
+                                                               const int8_t *__restrict__ sigma,
+                                                               const T *__restrict__ Tm,
+                                                               int64_t n, double *eloc, int Npad,
+                                                               int KB) {
+  extern __shared__ __align__(16) unsigned char lds_u8[];
+  constexpr int cs = C ? 2 : 1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int N = dm.N, M = dm.M, B = dm.Btot;
+  const bool tfim = dm.ham == NQS_TFIM;
+  const int nrows = tfim ? (dm.h != 0.0 ? N : 0) : B;
+  const T *gC = tfim ? tb.fC : tb.bC;
+  const T *gS = tfim ? tb.fS : tb.bS;
+  T *lC = reinterpret_cast<T *>(lds_u8);  // [KB][M] values of the chunk's rows
+  T *lS = lC + int64_t(KB) * M * cs;
+  int8_t *sig = reinterpret_cast<int8_t *>(lS + int64_t(KB) * M * cs) + wid * Npad;
+  const int64_t smp = int64_t(blockIdx.x) * kRowsWaves + wid;
+  const bool ok = smp < n;
+  const int64_t sr = ok ? smp : n - 1;
+  for (int i = lane; i < N; i += 64) sig[i] = sigma[sr * N + i];
+  V<T, C> t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    t[r] = lane + 64 * r < M ? vload<T, C>(Tm + sr * M * cs, lane + 64 * r)
+                             : vmake<T, C>(T(0), T(0));
+  wave_sync();
+  double diag = 0.0;
+  for (int b = lane; b < B; b += 64)
+    diag += dm.bond_diag[b] * double(sig[dm.bonds[2 * b]]) * double(sig[dm.bonds[2 * b + 1]]);
+  double er = 0.0, ei = 0.0;
+  for (int c0 = 0; c0 < nrows; c0 += KB) {
+    const int kb = nrows - c0 < KB ? nrows - c0 : KB;
+    __syncthreads();  // the previous chunk's rows are no longer read
+    const int64_t ne = int64_t(kb) * M;
+    for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) {
+      vstore<T, C>(lC, e, vload<T, C>(gC, int64_t(c0) * M + e));
+      vstore<T, C>(lS, e, vload<T, C>(gS, int64_t(c0) * M + e));
+    }
+    __syncthreads();
+    if (!ok) continue;
+    for (int q = 0; q < kb; ++q) {
+      const int row = c0 + q;
+      int s;
+      bool conn;
+      double el;
+      if (tfim) {
+        s = sig[row] > 0 ? 1 : -1;
+        conn = true;
+        el = -dm.h;
+      } else {
+        const int si = sig[dm.bonds[2 * row]], sk = sig[dm.bonds[2 * row + 1]];
+        s = si > 0 ? 1 : -1;
+        el = dm.bond_off[row];
+        conn = si != sk && el != 0.0;
+      }
+      if (!__builtin_amdgcn_readfirstlane(int(conn))) continue;  // the same on every lane
+      s = __builtin_amdgcn_readfirstlane(s);
+      const T ts = T(s);
+      V<T, C> p = vmake<T, C>(T(1), T(0));
+      int pe = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j = lane + 64 * r;
+        if (j < M) {
+          const V<T, C> cc = vload<T, C>(lC, int64_t(q) * M + j);
+          const V<T, C> ss = vload<T, C>(lS, int64_t(q) * M + j);
+          p = vmul(p, vsub(cc, vscale(vmul(t[r], ss), ts)));
+        }
+        if ((r & 3) == 3) vrenorm(p, pe);
+      }
+      vrenorm(p, pe);
+      const V<T, C> w = wave_cprod_dpp(p, pe);
+      const double *af = tfim ? tb.fa + 2 * (int64_t(s > 0 ? 0 : 1) * N + row)
+                              : tb.ba + 2 * (int64_t(s > 0 ? 0 : 1) * B + row);
+      const double rr = ldexp(double(w.re), pe), ri = C ? ldexp(double(w.im), pe) : 0.0;
+      er += el * (rr * af[0] - ri * af[1]);
+      ei += el * (rr * af[1] + ri * af[0]);
+    }
+  }
+  const double dsum = wave_sum_dpp(diag);
+  if (ok && lane == 0) {
+    if (C) {
+      eloc[2 * smp] = dsum + er;
+      eloc[2 * smp + 1] = ei;
+    } else {
+      eloc[smp] = dsum + er;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // Local energy with one sample per lane, for small models (M <= 16 TPM, N <= 64, at most
 // 64 connected rows, rows staged in LDS): the lane's tanh row sits in registers, the
 // connected rows (every site for TFIM, every bond for Heisenberg) are visited in a
@@ -1185,6 +1286,33 @@ hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64
   if (tp <= 12) return eloc_r<T, C, 1, 12>(m, sigma, Tm, n, eloc, st);
   if (tp <= 16) return eloc_r<T, C, 1, 16>(m, sigma, Tm, n, eloc, st);
   const int r = (m->M + 63) / 64;
+  {
+    // wide models whose tables exceed LDS: chunks of rows staged per block of samples
+    const int cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
+    const int Npad = round_up(m->N, 16);
+    const size_t per_row = size_t(2) * m->M * sizeof(T) * (C ? 2 : 1);
+    const size_t tab_lds = size_t(2) * cs_rows * m->M * sizeof(T) * (C ? 2 : 1);
+    const size_t fixed = size_t(kRowsWaves) * Npad;
+    const int64_t fit = int64_t((size_t(m->max_lds) - fixed) / per_row);
+    if (tab_lds > size_t(m->max_lds) / 2 && fit >= 1) {
+      const int KB = int(fit < cs_rows ? fit : (cs_rows > 0 ? cs_rows : 1));
+      const size_t lds = size_t(KB) * per_row + fixed;
+      const dim3 grid(unsigned((n + kRowsWaves - 1) / kRowsWaves));
+      auto go = [&](auto kern) -> hipError_t {
+        // dynamic LDS beyond 64 KiB is opted into per instantiation
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 m->max_lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, grid, dim3(64 * kRowsWaves), lds, st, dev_model(m),
+                           tables_of<T>(m), sigma, (const T *)Tm, n, (double *)eloc, Npad, KB);
+        return hipGetLastError();
+      };
+      if (r <= 8) return go(k_eloc_rows<T, C, 8>);
+      if (r <= 16) return go(k_eloc_rows<T, C, 16>);
+      return go(k_eloc_rows<T, C, 32>);
+    }
+  }
   if (r <= 8) return eloc_r<T, C, 8, 0>(m, sigma, Tm, n, eloc, st);
   if (r <= 16) return eloc_r<T, C, 16, 0>(m, sigma, Tm, n, eloc, st);
   return eloc_r<T, C, 32, 0>(m, sigma, Tm, n, eloc, st);
