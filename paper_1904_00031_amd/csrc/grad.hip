@@ -1008,7 +1008,7 @@ __device__ __forceinline__ int svc_rows(int64_t send, int64_t g) {
   return left <= 0 ? 0 : (left < 16 ? int(left) : 16);
 }
 
-// the spin masks of rows lane / 4 (mrow) and lane % 16 (mlo) and the T rows of one
+// the spin masks of rows 4 hi + q (mq[q]) and lane % 16 (mlo) and the T rows of one
 // 16-sample group (rows 4 hi + r, hidden tiles below JV). One code path for every group:
 // rows past the last valid one (rows_here of them, 0 past the end of the split) read the
 // last valid row instead, and their y is zeroed later, so their Z = conj(T) y vanishes
@@ -1019,12 +1019,13 @@ template <typename T, int JT, int JV>
 __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
                                          const T *__restrict__ Tm, int M, int64_t g,
                                          int64_t send, int rows_here, int lane, int lo, int hi,
-                                         uint64_t &mrow, uint64_t &mlo,
+                                         uint64_t (&mq)[4], uint64_t &mlo,
                                          V<T, true> (&tv)[JT][4]) {
   const int64_t gb = rows_here > 0 ? g : send - 1;
   const int rmax = rows_here > 0 ? rows_here - 1 : 0;
   const uint64_t *mb = masks + gb;
-  mrow = mb[min(lane >> 2, rmax)];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) mq[q] = mb[min(4 * hi + q, rmax)];
   mlo = mb[min(lo, rmax)];
   const T *tb = Tm + 2 * gb * int64_t(M);
 #pragma unroll
@@ -1035,31 +1036,6 @@ __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
       tv[a][r] = a < JV ? vload<T, true>(tb + off, a * 16) : vmake<T, true>(T(0), T(0));
   }
 }
-
-// The group's spins as floats in the wavefront's LDS tile [16][kSpinStride]: row rr,
-// column c holds s_c (+/-1) for c < N, 1 at c = N (the ones column of the bias
-// gradients), 0 beyond (rows past the group's end repeat a valid row). Lane l writes row l / 4, columns
-// 16 (l % 4) .. 16 (l % 4) + 15.
-constexpr int kSpinStride = 66;  // 2-float skew per row: conflict-free A-operand reads
-template <typename T>
-__device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, int N, int lane) {
-  const int rr = lane >> 2, c0 = 16 * (lane & 3);
-  const uint32_t bits = uint32_t(mrow >> c0) & 0xffffu;
-  T *dst = tile + rr * kSpinStride + c0;
-#pragma unroll
-  for (int t = 0; t < 16; t += 2) {
-    T v2[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int c = c0 + t + u;
-      const T s = ((bits >> (t + u)) & 1u) ? T(1) : T(-1);
-      v2[u] = c < N ? s : (c == N ? T(1) : T(0));
-    }
-    *reinterpret_cast<float2 *>(dst + t) = make_float2(v2[0], v2[1]);
-  }
-}
-
-
 
 // ---------------------------------------------------------------------------------
 // Fused S v product for complex models with N <= 63 and all VJP tiles in one block.
@@ -1073,19 +1049,20 @@ __device__ __forceinline__ void svc_spin_tile(T *tile, uint64_t mrow, int N, int
 //   within the pair);
 //   then plane h of Z^T S with Z = conj(T) y:
 //     Re Z = Re T Re y + Im T Im y,  Im Z = Re T Im y - Im T Re y  (row M: Z = y).
-// Spins enter as 64-bit masks (k_pack_spins). Both contractions run on the bf16 matrix
+// Spins enter as 64-bit masks (k_pack_spins): the JVP operand through a byte table, the
+// VJP operand and the visible term from the mask bits of each lane's four sample rows
+// (4 hi + q, column lo + 16 c). Both contractions run on the bf16 matrix
 // cores: the FP32 factor (V, then Z) is split exactly into three bf16 parts against the
 // +/-1 spins, so the products are exact and the sums FP32.
 // JT = ceil((M+1)/16) hidden tiles of the VJP output, JV = ceil(M/16) of them carry
 // hidden units in the JVP, NT = ceil((N+1)/16) site tiles.
 // ---------------------------------------------------------------------------------
 // dynamic LDS of k_svc: the bf16 split of V for both planes ([2][G][16 JV] groups of
-// 8 bf16, G = 4 ceil(3 ceil(N / 8) / 4), JV = ceil(M / 16)) and one float spin tile per
-// wavefront
-inline size_t svc_dynamic_lds(int N, int M, int pairs) {
+// 8 bf16, G = 4 ceil(3 ceil(N / 8) / 4), JV = ceil(M / 16))
+inline size_t svc_dynamic_lds(int N, int M) {
   const size_t G = size_t(4) * ((3 * ((N + 7) / 8) + 3) / 4);
   const size_t JVW = size_t((M + 15) / 16) * 16;
-  return 2 * G * JVW * 16 + size_t(2 * pairs) * 16 * kSpinStride * sizeof(float);
+  return 2 * G * JVW * 16;
 }
 
 template <typename T, int JT, int JV, int NT, int PAIRS>
@@ -1102,8 +1079,9 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   typedef typename MF<T>::acc Acc;
   constexpr int JW = JT * 16;
   constexpr int NVA = 4;                        // site columns per lane: lo + 16 c, N <= 63
+  static_assert(NT <= NVA, "site tiles of the VJP within the lane's spin columns");
   extern __shared__ __align__(16) unsigned char lds_u8[];
-  static_assert(sizeof(T) == 4, "spin tiles and the bf16 split are FP32");
+  static_assert(sizeof(T) == 4, "the bf16 split is FP32");
   constexpr int NTH = 128 * PAIRS;
   __shared__ T ybuf[2][PAIRS][2][16][2];  // [parity][pair][plane of origin][row][re, im]
   __shared__ T red[2 * PAIRS][4][64];
@@ -1180,8 +1158,6 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   }
   __syncthreads();
   if (skipped) return;
-  // this wavefront's spin tile, after the JVP operands
-  T *stile = reinterpret_cast<T *>(Vb + 2 * G * JVW) + wid * 16 * kSpinStride;
   bool stalled = false;
   const int64_t sbeg = int64_t(blockIdx.x) * per_split;
   const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
@@ -1214,19 +1190,34 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     for (int a = 0; a < JV; ++a) vbr[a] = vbl[H][a * 16 + lo];
 #pragma unroll
     for (int c = 0; c < NVA; ++c) var[c] = val[H][lo + 16 * c];
+    // spins as factors at column i = lo + 16 c of the sample rows: +/-1 from the mask bit
+    // for i < N, 1 at i = N (the ones column of the bias gradients), 0 beyond (mask bits
+    // are clear from N on)
+    T shi[NVA], slo[NVA];
+#pragma unroll
+    for (int c = 0; c < NVA; ++c) {
+      const int i = lo + 16 * c;
+      shi[c] = i < N ? T(1) : T(0);
+      slo[c] = i < N ? T(-1) : (i == N ? T(1) : T(0));
+    }
+    auto spin = [&](const uint64_t (&m)[4], int q, int c) __attribute__((always_inline)) -> T {
+      const uint32_t w = c < 2 ? uint32_t(m[q]) : uint32_t(m[q] >> 32);
+      return ((w >> (lo + 16 * (c & 1))) & 1u) ? shi[c] : slo[c];
+    };
     const uint4 *tab4 = reinterpret_cast<const uint4 *>(stab);
     const uint4 *Vh = Vb + H * G * JVW + lo;
     // software pipeline: the masks and T rows of the pair's next group are loaded while
     // the current group's O^dagger y contraction runs
     int64_t g = sbeg + 16 * pr;
     int rows_here = svc_rows(send, g);
-    uint64_t mrow, mlo;
+    uint64_t mq[4], mlo;
     V<T, true> tv[JT][4];
-    if (iters > 0) svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mrow, mlo, tv);
+    if (iters > 0) svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mq, mlo, tv);
     for (int64_t it = 0; it < iters; ++it) {
-      // spins of the group into the tile (the previous group's reads are done: same wave)
-      svc_spin_tile<T>(stile, mrow, N, lane);
-      wave_sync();
+      // the masks of rows 4 hi + q of this group (the loads below fetch the next group's)
+      uint64_t mc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mc[q] = mq[q];
       // ---- X_H = S (plane H of V)^T over the valid hidden tiles, bf16 split ----
       // A (sample lo, k group g): the spins of sites 8 (g / 3) .. + 7 from the byte
       // table; sites past N meet zeros in B. Steps unrolled to KSMAX, uniform guards.
@@ -1267,22 +1258,16 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       if constexpr (H == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const T *srow = stile + MF<T>::row(hi, r) * kSpinStride;
 #pragma unroll
-          for (int c = 0; c < NVA; ++c) {
-            // columns >= N of the tile are 1 (c = N) or 0, and va is 0 there
-            const T sgn = srow[lo + 16 * c];
-            yre[r] += sgn * var[c];
-          }
+          for (int c = 0; c < NVA; ++c) yre[r] += spin(mc, r, c) * var[c];  // va is 0 from N on
         }
       }
       if constexpr (H == 1) {
         // the imaginary part of va enters through plane 1's share of Im y
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const T *srow = stile + MF<T>::row(hi, r) * kSpinStride;
 #pragma unroll
-          for (int c = 0; c < NVA; ++c) yim[r] += srow[lo + 16 * c] * var[c];
+          for (int c = 0; c < NVA; ++c) yim[r] += spin(mc, r, c) * var[c];
         }
       }
       const int par = int(it & 1);
@@ -1365,7 +1350,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       // registers are the next iteration's operands with no merge copies
       g += 16 * PAIRS;
       rows_here = svc_rows(send, g);
-      svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mrow, mlo, tv);
+      svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mq, mlo, tv);
       // ---- plane H of Z^T S over the 16 samples, bf16 split of Z ----
       // k of lane group hi: element e < 4 pairs part h of Z at sample 4 hi + e with that
       // sample's spin, e >= 4 part m; a second step takes part l (upper half zero).
@@ -1376,7 +1361,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       for (int b = 0; b < NT; ++b) {
         T bs[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bs[q] = stile[MF<T>::row(hi, q) * kSpinStride + b * 16 + lo];
+        for (int q = 0; q < 4; ++q) bs[q] = spin(mc, q, b);
         if constexpr (AROW) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) ga[b] += (H == 0 ? yre[q] : yim[q]) * bs[q];
@@ -1674,7 +1659,7 @@ hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_par
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
-  const size_t lds = svc_dynamic_lds(m->N, m->M, PAIRS);
+  const size_t lds = svc_dynamic_lds(m->N, m->M);
   // dynamic LDS beyond 64 KiB is opted into once per instantiation (up to the device limit
   // checked by grad_plan)
   static const hipError_t opt = hipFuncSetAttribute(
@@ -2037,7 +2022,7 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
   if (m->is_complex && !use_double(m) && m->N <= 63 && g.Jtiles <= 6 &&
       g.Jtiles * g.NT <= 18) {
     // dynamic LDS of the 4-pair shape plus the kernel's static arrays (<= 24 KiB)
-    const size_t lds = svc_dynamic_lds(m->N, m->M, 4) + 24 * 1024;
+    const size_t lds = svc_dynamic_lds(m->N, m->M) + 24 * 1024;
     if (lds <= size_t(m->max_lds)) {
       g.pair = true;
       g.fused = true;
