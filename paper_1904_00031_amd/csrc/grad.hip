@@ -1085,7 +1085,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
   constexpr int NTH = 128 * PAIRS;
   __shared__ T ybuf[2][PAIRS][2][16][2];  // [parity][pair][plane of origin][row][re, im]
   __shared__ T red[2 * PAIRS][4][64];
-  __shared__ double dsum[2][NTH];
+  __shared__ double dsum[2][2 * PAIRS];
   // spin byte b -> the 8 spins (bit e set: +1, else -1) as bf16, element e = site e
   __shared__ __align__(16) uint32_t stab[256 * 4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1431,19 +1431,23 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     }
   // a wavefront that gave up waiting for its partner poisons the block's sum of y, so
   // the solver reports a non-finite result instead of a wrong one
-  dsum[0][tid] = stalled ? __builtin_nan("") : ysr;
-  dsum[1][tid] = ysi;
-  __syncthreads();
-  for (int w = NTH / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      dsum[0][tid] += dsum[0][tid + w];
-      dsum[1][tid] += dsum[1][tid + w];
+  {
+    // wavefront sums (DPP), then the wavefronts in index order
+    const double wr = wave_sum_dpp(ysr), wi = wave_sum_dpp(ysi);
+    if (lane == 0) {
+      dsum[0][wid] = stalled ? __builtin_nan("") : wr;
+      dsum[1][wid] = wi;
     }
     __syncthreads();
-  }
-  if (tid == 0) {
-    ysum_part[2 * blockIdx.x] = dsum[0][0];
-    ysum_part[2 * blockIdx.x + 1] = dsum[1][0];
+    if (tid == 0) {
+      double sr = 0.0, si = 0.0;
+      for (int w = 0; w < 2 * PAIRS; ++w) {
+        sr += dsum[0][w];
+        si += dsum[1][w];
+      }
+      ysum_part[2 * blockIdx.x] = sr;
+      ysum_part[2 * blockIdx.x + 1] = si;
+    }
   }
 }
 
