@@ -385,8 +385,22 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
       lS[e] = gSe[e];
     }
     for (int64_t e = threadIdx.x; e < we; e += blockDim.x) lW[e] = gW[e];
-    __syncthreads();
   }
+  // |visible-bias factor|^2 of every row for either spin and the color-0 bonds, staged
+  // once per block after the wavefronts' regions: every sweep's proposal draw reads them
+  const int afn = flip ? N : dm.Btot;
+  const int64_t aux_off =
+      (tab_bytes + int64_t(blockDim.x >> 6) * a.wave_bytes + 15) & ~int64_t(15);
+  double *la2 = reinterpret_cast<double *>(lds_u8 + aux_off);  // [2][afn]
+  int *lbond = reinterpret_cast<int *>(la2 + 2 * afn);           // [B0][2]
+  {
+    const double *afb = flip ? tb.fa : tb.ba;
+    for (int e = threadIdx.x; e < 2 * afn; e += blockDim.x)
+      la2[e] = afb[2 * e] * afb[2 * e] + afb[2 * e + 1] * afb[2 * e + 1];
+    if (!flip)
+      for (int e = threadIdx.x; e < 2 * dm.B0; e += blockDim.x) lbond[e] = dm.bonds[e];
+  }
+  __syncthreads();
   if (chain >= a.n_chains) return;
   int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes);
   T *tj = reinterpret_cast<T *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes + a.Npad);
@@ -454,8 +468,6 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
     }
     return o;
   };
-  const double *afb = flip ? tb.fa : tb.ba;
-  const int afn = flip ? N : dm.Btot;
   int64_t acc_count = 0;
   for (int sw = 0; sw < total; ++sw) {
     for (int st0 = 0; st0 < N; st0 += 64) {
@@ -474,14 +486,12 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
           kv = iv;
         } else {
           rowv = rng_index(w.w[0], uint32_t(dm.B0));
-          iv = dm.bonds[2 * rowv];
-          kv = dm.bonds[2 * rowv + 1];
+          iv = lbond[2 * rowv];
+          kv = lbond[2 * rowv + 1];
         }
         uv = rng_uniform(w.w[1], w.w[2]);
-        const double *f0 = afb + 2 * int64_t(rowv);
-        const double *f1 = afb + 2 * (int64_t(afn) + rowv);
-        a2p = f0[0] * f0[0] + f0[1] * f0[1];
-        a2m = f1[0] * f1[0] + f1[1] * f1[1];
+        a2p = la2[rowv];
+        a2m = la2[afn + rowv];
         const float lu = __log2f(float(uv));
         thp = lu - __log2f(float(a2p));
         thm = lu - __log2f(float(a2m));
@@ -1148,6 +1158,14 @@ hipError_t tables_t(const nqs_model *m, const void *params, hipStream_t st) {
   return hipGetLastError();
 }
 
+// LDS of the sweep after the wavefronts' regions: |visible-bias factor|^2 of every row for
+// either spin (2 x rows doubles) and, for exchange moves, the color-0 bonds (2 x B0 ints)
+inline size_t sweep_aux_lds(const nqs_model *m) {
+  const bool flip = m->move == NQS_MOVE_FLIP;
+  const int afn = flip ? m->N : m->Btot;
+  return size_t(16) * afn + (flip ? size_t(0) : size_t(8) * m->B[0]);
+}
+
 template <typename T, bool C, int R>
 hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, int n_discard,
                    uint64_t seed, uint64_t counter, int chain_offset, int8_t *samples,
@@ -1173,28 +1191,31 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   const size_t wave_lds = size_t(wpb) * a.wave_bytes;
   const size_t tab_lds =
       size_t(2 * a.cs_rows + a.w_rows) * m->M * sizeof(T) * (C ? 2 : 1);
+  // the visible-bias factors and bonds after the wavefronts' regions (16-byte aligned)
+  const size_t aux = sweep_aux_lds(m);
+  auto with_aux = [&](size_t base) { return (base + 15) / 16 * 16 + aux; };
   // the staged C/S rows serve both the moves and the local energy only when the move
   // set is contained in the connected set: flips with TFIM, exchanges with Heisenberg
   const bool shared_rows = (m->ham == NQS_TFIM && flip) || (m->ham == NQS_HEISENBERG && !flip);
   dim3 grid((n_chains + wpb - 1) / wpb);
-  const bool tl = shared_rows && tab_lds + wave_lds <= size_t(m->max_lds);
+  const bool tl = shared_rows && with_aux(tab_lds + wave_lds) <= size_t(m->max_lds);
   if constexpr (R <= 4) {
     if (m->N <= 64) {
       if (tl)
         hipLaunchKernelGGL((k_sweep<T, C, R, true, true>), grid, dim3(64 * wpb),
-                           tab_lds + wave_lds, st, dev_model(m), tables_of<T>(m), a);
+                           with_aux(tab_lds + wave_lds), st, dev_model(m), tables_of<T>(m), a);
       else
-        hipLaunchKernelGGL((k_sweep<T, C, R, false, true>), grid, dim3(64 * wpb), wave_lds, st,
-                           dev_model(m), tables_of<T>(m), a);
+        hipLaunchKernelGGL((k_sweep<T, C, R, false, true>), grid, dim3(64 * wpb),
+                           with_aux(wave_lds), st, dev_model(m), tables_of<T>(m), a);
       return hipGetLastError();
     }
   }
   if (tl) {
-    hipLaunchKernelGGL((k_sweep<T, C, R, true, false>), grid, dim3(64 * wpb), tab_lds + wave_lds,
-                       st, dev_model(m), tables_of<T>(m), a);
+    hipLaunchKernelGGL((k_sweep<T, C, R, true, false>), grid, dim3(64 * wpb),
+                       with_aux(tab_lds + wave_lds), st, dev_model(m), tables_of<T>(m), a);
   } else {
-    hipLaunchKernelGGL((k_sweep<T, C, R, false, false>), grid, dim3(64 * wpb), wave_lds, st,
-                       dev_model(m), tables_of<T>(m), a);
+    hipLaunchKernelGGL((k_sweep<T, C, R, false, false>), grid, dim3(64 * wpb),
+                       with_aux(wave_lds), st, dev_model(m), tables_of<T>(m), a);
   }
   return hipGetLastError();
 }
@@ -1343,7 +1364,7 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
   std::vector<int2> tmap;
   std::vector<SweepJob<T>> sj;
   std::vector<int2> smap;
-  size_t wave_max = 0;
+  size_t wave_max = 0, aux_max = 0;
   for (size_t k = 0; k < items.size(); ++k) {
     const BatchSampleItem &it = items[k];
     const nqs_model *m = it.m;
@@ -1379,6 +1400,7 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
     a.Npad = round_up(m->N, 16);
     a.wave_bytes = a.Npad + round_up(m->M * int(sizeof(V<T, C>)), 16);
     if (size_t(a.wave_bytes) > wave_max) wave_max = size_t(a.wave_bytes);
+    if (sweep_aux_lds(m) > aux_max) aux_max = sweep_aux_lds(m);
     for (int c = 0; c < it.n_chains; c += wpb) smap.push_back(make_int2(int(k), c));
     sj.push_back(w);
   }
@@ -1395,8 +1417,8 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
                      (const TabJob<T, PT> *)b->tab_jobs.d, (const int2 *)b->tab_map.d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((k_sweep_batch<T, C, R>), dim3(unsigned(smap.size())), dim3(64 * wpb),
-                     size_t(wpb) * wave_max, st, (const SweepJob<T> *)b->sweep_jobs.d,
-                     (const int2 *)b->sweep_map.d);
+                     (size_t(wpb) * wave_max + 15) / 16 * 16 + aux_max, st,
+                     (const SweepJob<T> *)b->sweep_jobs.d, (const int2 *)b->sweep_map.d);
   return hipGetLastError();
 }
 
