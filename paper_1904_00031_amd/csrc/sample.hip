@@ -963,11 +963,11 @@ __global__ __launch_bounds__(64 * kRowsWaves) void k_eloc_rows(DevModel dm, Tabl
 
 // ---------------------------------------------------------------------------------
 // Local energy with one sample per lane, for small models (M <= 16 TPM, N <= 64, at most
-// 64 connected rows, rows staged in LDS): the lane's tanh row sits in registers, the
-// connected rows (every site for TFIM, every bond for Heisenberg) are visited in a
-// wave-uniform loop with their C/S entries broadcast from LDS, and each lane multiplies its
-// own ratio terms, so no cross-lane reduction is needed. Rows that a lane's sample does
-// not connect are computed and discarded. Same terms as eloc_grouped (Eq. 5).
+// 64 candidate rows, rows staged in LDS): the lane's tanh row sits in registers and the
+// lane visits only the rows its sample connects (every site for TFIM, the bonds with
+// opposite spins for Heisenberg), reading their C/S entries from LDS, and multiplies its
+// own ratio terms, so no cross-lane reduction is needed; the loop runs as many passes as
+// the lane with the most connected rows. Same terms as eloc_grouped (Eq. 5).
 // ---------------------------------------------------------------------------------
 template <typename T, bool C, int TPM>
 __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
@@ -979,15 +979,20 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
   constexpr int MJ = 16 * TPM;
   const int N = dm.N, M = dm.M, B = dm.Btot;
   const bool tfim = dm.ham == NQS_TFIM;
-  // rows staged with the compile-time width MJ; entries past M hold C = 1, S = 0, so their
-  // ratio term is exactly 1 and the product loop has no bound test
+  // rows staged with the compile-time width MJ plus one element (rows one bank pair apart:
+  // lanes on different rows read different banks); entries past M hold C = 1, S = 0, so
+  // their ratio term is exactly 1 and the product loop has no bound test. After the rows:
+  // the element of every row and the visible-bias factors of either spin.
+  constexpr int RW = MJ + 1;
   T *lC = reinterpret_cast<T *>(lds_u8);
-  T *lS = lC + int64_t(cs_rows) * MJ * cs;
+  T *lS = lC + int64_t(cs_rows) * RW * cs;
+  double *lel = reinterpret_cast<double *>(lS + int64_t(cs_rows) * RW * cs);  // [rows]
+  double *laf = lel + cs_rows;  // [2][rows] complex
   {
     const T *gC = tfim ? tb.fC : tb.bC;
     const T *gS = tfim ? tb.fS : tb.bS;
-    for (int e = threadIdx.x; e < cs_rows * MJ; e += blockDim.x) {
-      const int r = e / MJ, j = e - r * MJ;
+    for (int e = threadIdx.x; e < cs_rows * RW; e += blockDim.x) {
+      const int r = e / RW, j = e - r * RW;
       V<T, C> cc = vmake<T, C>(T(1), T(0)), ss = vmake<T, C>(T(0), T(0));
       if (j < M) {
         cc = vload<T, C>(gC, int64_t(r) * M + j);
@@ -996,6 +1001,10 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
       vstore<T, C>(lC, e, cc);
       vstore<T, C>(lS, e, ss);
     }
+    const double *gaf = tfim ? tb.fa : tb.ba;
+    for (int e = threadIdx.x; e < cs_rows; e += blockDim.x)
+      lel[e] = tfim ? -dm.h : dm.bond_off[e];
+    for (int e = threadIdx.x; e < 4 * cs_rows; e += blockDim.x) laf[e] = gaf[e];
     __syncthreads();
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1018,25 +1027,31 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
       const int si = ((mask >> i) & 1ull) ? 1 : -1, sk = ((mask >> k) & 1ull) ? 1 : -1;
       diag += dm.bond_diag[b] * double(si * sk);
     }
-    double er = 0.0, ei = 0.0;
+    // the rows this lane's sample connects (bit c of cmask) and the spin s of each (bit c
+    // of upm: s = +1); each lane then visits only its own rows, in increasing order
+    uint64_t cmask = 0, upm = 0;
     for (int c = 0; c < nrows; ++c) {
-      int sgn;
-      bool conn;
-      double el;
+      bool conn, up;
       if (tfim) {
-        sgn = ((mask >> c) & 1ull) ? 1 : -1;
+        up = (mask >> c) & 1ull;
         conn = true;
-        el = -dm.h;
       } else {
         const int i = dm.bonds[2 * c], k = dm.bonds[2 * c + 1];
         const bool ui = (mask >> i) & 1ull, uk = (mask >> k) & 1ull;
-        sgn = ui ? 1 : -1;
-        el = dm.bond_off[c];
-        conn = ui != uk && el != 0.0;
+        up = ui;
+        conn = ui != uk && dm.bond_off[c] != 0.0;
       }
-      if (__ballot(conn && ok) == 0) continue;  // no lane connects this row
+      cmask |= uint64_t(conn && ok) << c;
+      upm |= uint64_t(up) << c;
+    }
+    double er = 0.0, ei = 0.0;
+    while (__ballot(cmask != 0)) {
+      const bool have = cmask != 0;  // lanes without a row left take row 0 and discard it
+      const int c = have ? int(__builtin_ctzll(cmask)) : 0;
+      cmask &= cmask - 1;
+      const int sgn = ((upm >> c) & 1ull) ? 1 : -1;
       const T ts = T(sgn);
-      const T *crow = lC + int64_t(c) * MJ * cs, *srow = lS + int64_t(c) * MJ * cs;
+      const T *crow = lC + int64_t(c) * RW * cs, *srow = lS + int64_t(c) * RW * cs;
       // four interleaved partial products (j mod 4), so that four independent
       // multiplication chains are in flight, then combined
       V<T, C> pq[4];
@@ -1057,10 +1072,10 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
       V<T, C> p = vmul(vmul(pq[0], pq[1]), vmul(pq[2], pq[3]));
       int pe = (peq[0] + peq[1]) + (peq[2] + peq[3]);
       vrenorm(p, pe);
-      const double *af = tfim ? tb.fa + 2 * (int64_t(sgn > 0 ? 0 : 1) * N + c)
-                              : tb.ba + 2 * (int64_t(sgn > 0 ? 0 : 1) * B + c);
+      const double *af = laf + 2 * (int64_t(sgn > 0 ? 0 : 1) * cs_rows + c);
+      const double el = lel[c];
       const double rr = ldexp(double(p.re), pe), ri = C ? ldexp(double(p.im), pe) : 0.0;
-      if (conn) {
+      if (have) {
         er += el * (rr * af[0] - ri * af[1]);
         ei += el * (rr * af[1] + ri * af[0]);
       }
@@ -1278,7 +1293,9 @@ hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64
   // exceed 256 registers per lane; those keep the grouped kernel)
   if (tp <= 6 && m->N <= 64 && (sizeof(T) == 4 || !C || tp <= 3)) {
     const int cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
-    const size_t tab_lds = size_t(2) * cs_rows * (16 * tp) * sizeof(T) * (C ? 2 : 1);
+    // rows of 16 tp + 1 elements, then the row elements and visible-bias factors (doubles)
+    const size_t tab_lds =
+        size_t(2) * cs_rows * (16 * tp + 1) * sizeof(T) * (C ? 2 : 1) + size_t(40) * cs_rows;
     if (cs_rows <= 64 && tab_lds <= size_t(m->max_lds) / 2) {
       // one block of four wavefronts per compute unit (the row in registers takes up to
       // 512 registers per lane)
