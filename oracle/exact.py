@@ -13,8 +13,9 @@ results); here it pins the oracle itself:
 * ``heisenberg_ring_bethe``: Bethe-ansatz ground energy of the periodic Heisenberg ring.
 
 Pins (tests/test_oracle_exact.py): closed form and Bethe ansatz against sparse ED of the
-Kronecker-built H (N = 9..16 and N = 16, 20), ED against the values printed for these
-models in the literature survey of this build (4x4 Heisenberg and J1-J2).
+Kronecker-built H (N = 9..16 and N = 16, 20), ED against published exact-diagonalisation
+energies of the 4x4 Heisenberg and J1-J2 lattices (tests/golden/reference_energies.txt,
+with their sources).
 """
 import numpy as np
 import scipy.sparse as sp
