@@ -979,27 +979,28 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
   constexpr int MJ = 16 * TPM;
   const int N = dm.N, M = dm.M, B = dm.Btot;
   const bool tfim = dm.ham == NQS_TFIM;
-  // rows staged with the compile-time width MJ plus one element (rows one bank pair apart:
-  // lanes on different rows read different banks); entries past M hold C = 1, S = 0, so
-  // their ratio term is exactly 1 and the product loop has no bound test. After the rows:
-  // the element of every row and the visible-bias factors of either spin.
-  constexpr int RW = MJ + 1;
+  // tables staged transposed, [j][row] with a row stride of 64 (so lanes on different rows
+  // read consecutive elements, at most two rows per bank pair, and element j sits at a
+  // compile-time offset); entries past M hold C = 1, S = 0, so their ratio term is exactly
+  // 1 and the product loop has no bound test. After the tables: the element of every row
+  // and the visible-bias factors of either spin.
+  constexpr int RS = 64;
   T *lC = reinterpret_cast<T *>(lds_u8);
-  T *lS = lC + int64_t(cs_rows) * RW * cs;
-  double *lel = reinterpret_cast<double *>(lS + int64_t(cs_rows) * RW * cs);  // [rows]
+  T *lS = lC + int64_t(MJ) * RS * cs;
+  double *lel = reinterpret_cast<double *>(lS + int64_t(MJ) * RS * cs);  // [rows]
   double *laf = lel + cs_rows;  // [2][rows] complex
   {
     const T *gC = tfim ? tb.fC : tb.bC;
     const T *gS = tfim ? tb.fS : tb.bS;
-    for (int e = threadIdx.x; e < cs_rows * RW; e += blockDim.x) {
-      const int r = e / RW, j = e - r * RW;
+    for (int e = threadIdx.x; e < cs_rows * MJ; e += blockDim.x) {
+      const int r = e / MJ, j = e - r * MJ;
       V<T, C> cc = vmake<T, C>(T(1), T(0)), ss = vmake<T, C>(T(0), T(0));
       if (j < M) {
         cc = vload<T, C>(gC, int64_t(r) * M + j);
         ss = vload<T, C>(gS, int64_t(r) * M + j);
       }
-      vstore<T, C>(lC, e, cc);
-      vstore<T, C>(lS, e, ss);
+      vstore<T, C>(lC, j * RS + r, cc);
+      vstore<T, C>(lS, j * RS + r, ss);
     }
     const double *gaf = tfim ? tb.fa : tb.ba;
     for (int e = threadIdx.x; e < cs_rows; e += blockDim.x)
@@ -1051,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
       cmask &= cmask - 1;
       const int sgn = ((upm >> c) & 1ull) ? 1 : -1;
       const T ts = T(sgn);
-      const T *crow = lC + int64_t(c) * RW * cs, *srow = lS + int64_t(c) * RW * cs;
+      const T *crow = lC + c * cs, *srow = lS + c * cs;
       // four interleaved partial products (j mod 4), so that four independent
       // multiplication chains are in flight, then combined
       V<T, C> pq[4];
@@ -1063,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
       }
 #pragma unroll
       for (int j = 0; j < MJ; ++j) {
-        const V<T, C> cc = vload<T, C>(crow, j), ss = vload<T, C>(srow, j);
+        const V<T, C> cc = vload<T, C>(crow, j * RS), ss = vload<T, C>(srow, j * RS);
         pq[j & 3] = vmul(pq[j & 3], vsub(cc, vscale(vmul(t[j], ss), ts)));
         if ((j & 31) >= 28) vrenorm(pq[j & 3], peq[j & 3]);
       }
@@ -1293,10 +1294,11 @@ hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64
   // exceed 256 registers per lane; those keep the grouped kernel)
   if (tp <= 6 && m->N <= 64 && (sizeof(T) == 4 || !C || tp <= 3)) {
     const int cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
-    // rows of 16 tp + 1 elements, then the row elements and visible-bias factors (doubles)
+    // both tables transposed with a row stride of 64, then the row elements and the
+    // visible-bias factors (doubles)
     const size_t tab_lds =
-        size_t(2) * cs_rows * (16 * tp + 1) * sizeof(T) * (C ? 2 : 1) + size_t(40) * cs_rows;
-    if (cs_rows <= 64 && tab_lds <= size_t(m->max_lds) / 2) {
+        size_t(2) * 64 * (16 * tp) * sizeof(T) * (C ? 2 : 1) + size_t(40) * cs_rows;
+    if (cs_rows <= 64 && tab_lds <= size_t(m->max_lds) * 5 / 8) {
       // one block of four wavefronts per compute unit (the row in registers takes up to
       // 512 registers per lane)
       int64_t blocks = (n + 255) / 256;
