@@ -391,14 +391,43 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
     if (C) ysi += ysum[2 * k + 1];
   }
   if (done) return;
-  const double ybr = block_reduce(ysr, lds) / double(n);
-  const double ybi = C ? block_reduce(ysi, lds) / double(n) : 0.0;
   const int el = threadIdx.x % kAprElems, sl = threadIdx.x / kAprElems;
   const int64_t e = int64_t(blockIdx.x) * kAprElems + el;
+  // parameter index of the element (-1: padding of the tile layout)
+  int64_t k = -1;
+  if (e < elems) {
+    const int jrow = int(e / colsP), icol = int(e % colsP);
+    if (jrow < M && icol < N)
+      k = int64_t(N) + M + int64_t(jrow) * N + icol;  // W_ji
+    else if (jrow < M && icol == N)
+      k = N + jrow;  // b_j
+    else if (jrow == M && icol < N)
+      k = icol;  // a_i
+  }
+  // the direction and O^dagger 1 of the element, loaded with the partial tiles
+  double pr = 0.0, pim = 0.0, o1r = 0.0, o1i = 0.0;
+  if (sl == 0 && k >= 0) {
+    pr = p[C ? 2 * k : k];
+    o1r = o1[C ? 2 * k : k];
+    if (C) {
+      pim = p[2 * k + 1];
+      o1i = o1[2 * k + 1];
+    }
+  }
   double gr = 0.0, gi = 0.0;
   if (e < elems) {
-    // eight loads in flight, added in split order
+    // up to 32 loads in flight per thread, added in split order
     int q = sl;
+    for (; q + 31 * kAprSlices < splits; q += 32 * kAprSlices) {
+      V<T, C> xs[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) xs[u] = vload<T, C>(part, int64_t(q + u * kAprSlices) * elems + e);
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        gr += double(xs[u].re);
+        if (C) gi += double(xs[u].im);
+      }
+    }
     for (; q + 7 * kAprSlices < splits; q += 8 * kAprSlices) {
       V<T, C> xs[8];
 #pragma unroll
@@ -415,37 +444,29 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
       if (C) gi += double(x.im);
     }
   }
+  const double ybr = block_reduce(ysr, lds) / double(n);
+  const double ybi = C ? block_reduce(ysi, lds) / double(n) : 0.0;
   sr[sl][el] = gr;
   si[sl][el] = gi;
   __syncthreads();
   double acc = 0.0;
-  if (sl == 0 && e < elems) {
+  if (sl == 0 && k >= 0) {
     for (int q = 1; q < kAprSlices; ++q) {
       gr += sr[q][el];
       gi += si[q][el];
     }
-    const int jrow = int(e / colsP), icol = int(e % colsP);
-    int64_t k = -1;
-    if (jrow < M && icol < N)
-      k = int64_t(N) + M + int64_t(jrow) * N + icol;  // W_ji
-    else if (jrow < M && icol == N)
-      k = N + jrow;  // b_j
-    else if (jrow == M && icol < N)
-      k = icol;  // a_i
-    if (k >= 0) {
-      if (C) {
-        gr -= ybr * o1[2 * k] - ybi * o1[2 * k + 1];
-        gi -= ybr * o1[2 * k + 1] + ybi * o1[2 * k];
-        const double ar = gr / double(n) + lambda * p[2 * k];
-        const double ai = gi / double(n) + lambda * p[2 * k + 1];
-        Ap[2 * k] = ar;
-        Ap[2 * k + 1] = ai;
-        acc = p[2 * k] * ar + p[2 * k + 1] * ai;
-      } else {
-        const double ar = (gr - ybr * o1[k]) / double(n) + lambda * p[k];
-        Ap[k] = ar;
-        acc = p[k] * ar;
-      }
+    if (C) {
+      gr -= ybr * o1r - ybi * o1i;
+      gi -= ybr * o1i + ybi * o1r;
+      const double ar = gr / double(n) + lambda * pr;
+      const double ai = gi / double(n) + lambda * pim;
+      Ap[2 * k] = ar;
+      Ap[2 * k + 1] = ai;
+      acc = pr * ar + pim * ai;
+    } else {
+      const double ar = (gr - ybr * o1r) / double(n) + lambda * pr;
+      Ap[k] = ar;
+      acc = pr * ar;
     }
   }
   acc = block_reduce(acc, lds);
