@@ -1010,9 +1010,23 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nrows = tfim ? (dm.h != 0.0 ? N : 0) : B;
-  for (int64_t s0 = (int64_t(blockIdx.x) * (blockDim.x >> 6) + wid) * 64; s0 < n;
-       s0 += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t smp = s0 + lane;
+  // Whole rounds give every wavefront 64 samples, one per lane. The samples left after
+  // them (fewer than 64 per wavefront) are spread over every wavefront: spw per wavefront,
+  // L = 64 / spw lanes per sample, each lane taking every L-th of the sample's connected
+  // rows; the L partial sums are then added across the lanes.
+  const int64_t W = int64_t(gridDim.x) * (blockDim.x >> 6);
+  const int64_t wg = int64_t(blockIdx.x) * (blockDim.x >> 6) + wid;
+  const int64_t nfull = n / (64 * W) * (64 * W), rem = n - nfull;
+  int spw = 1;
+  while (int64_t(spw) * W < rem) spw <<= 1;
+  const int64_t rounds = nfull / (64 * W) + (rem > 0 ? 1 : 0);
+  for (int64_t it = 0; it < rounds; ++it) {
+    const bool tail = it * 64 * W >= nfull;
+    const int L = tail ? 64 / spw : 1;
+    const int sub = lane & (L - 1);
+    const int64_t base = tail ? nfull + wg * spw : it * 64 * W + wg * 64;
+    if (base >= n) break;  // the same for every lane of the wavefront
+    const int64_t smp = base + lane / L;
     const bool ok = smp < n;
     const int64_t sr = ok ? smp : n - 1;
     uint64_t mask = 0;  // bit i: spin i up
@@ -1044,6 +1058,16 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
       }
       cmask |= uint64_t(conn && ok) << c;
       upm |= uint64_t(up) << c;
+    }
+    if (L > 1) {
+      // keep the connected rows whose rank among them is sub modulo L
+      uint64_t keep = 0, rest = cmask;
+      for (int rk = 0; rest != 0; ++rk) {
+        const uint64_t bit = rest & (~rest + 1);
+        if ((rk & (L - 1)) == sub) keep |= bit;
+        rest ^= bit;
+      }
+      cmask = keep;
     }
     double er = 0.0, ei = 0.0;
     while (__ballot(cmask != 0)) {
@@ -1081,7 +1105,11 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
         ei += el * (rr * af[1] + ri * af[0]);
       }
     }
-    if (ok) {
+    for (int o = L >> 1; o > 0; o >>= 1) {
+      er += __shfl_xor(er, o);
+      ei += __shfl_xor(ei, o);
+    }
+    if (ok && sub == 0) {
       if (C) {
         eloc[2 * smp] = diag + er;
         eloc[2 * smp + 1] = ei;

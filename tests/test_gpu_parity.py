@@ -346,6 +346,25 @@ def test_sr_matvec_full_size_sampled(lib):
     assert np.abs(got[ks] - exp).max() <= cases.tol(name) * scale
 
 
+@pytest.mark.parametrize("n", [1024 * 200, 1024 * 200 - 37])
+def test_local_energy_full_size_sampled(lib, n):
+    """Local energies of the 40-site Heisenberg ring, complex FP32, alpha = 2, at the
+    benchmark's 204800 samples and at a ragged count: one sample per lane takes more whole
+    rounds than the chip holds at once, and the samples of the last partial round are
+    shared by several lanes each; entries of both parts against the oracle."""
+    name = "heis40_cplx_f32"
+    m, om = cases.build(lib, name)
+    p = cases.params(name, theta=0.3, seed=65)
+    pe = p.astype(np.complex128)
+    s = cases.configs(name, n, seed=66)
+    el = m.local_energy(to_dev(p), to_dev(s)).cpu().numpy()
+    rng = np.random.default_rng(67)
+    ks = np.unique(np.concatenate([np.arange(16), np.arange(n - 96, n),
+                                   rng.integers(0, n, 48)]))
+    eel = oh.local_energy(om, pe, s[ks])
+    assert np.abs(el[ks] - eel).max() <= cases.tol(name) * max(1.0, np.abs(eel).max())
+
+
 @pytest.mark.parametrize("name", ["heis40_cplx_f32", "tfim10_real_f64", "j1j2_4x4_cplx_f64"])
 def test_sr_step_graph_replays_match_direct_launches(lib, name):
     """Chunks of CG iterations replayed from a captured graph (several replays per call,
