@@ -346,16 +346,18 @@ def test_sr_matvec_full_size_sampled(lib):
     assert np.abs(got[ks] - exp).max() <= cases.tol(name) * scale
 
 
-@pytest.mark.parametrize("n", [1024 * 200, 1024 * 200 - 37])
-def test_local_energy_full_size_sampled(lib, n):
-    """Local energies of the 40-site Heisenberg ring, complex FP32, alpha = 2, at the
-    benchmark's 204800 samples and at a ragged count: one sample per lane takes more whole
-    rounds than the chip holds at once, and the samples of the last partial round are
-    shared by several lanes each; entries of both parts against the oracle."""
-    name = "heis40_cplx_f32"
+@pytest.mark.parametrize("name,n", [("heis40_cplx_f32", 1024 * 200),
+                                    ("heis40_cplx_f32", 1024 * 200 - 37),
+                                    ("tfim10_real_f64", 136072)])
+def test_local_energy_full_size_sampled(lib, name, n):
+    """Local energies at sample counts beyond one sample per lane of the whole chip: the
+    40-site Heisenberg ring, complex FP32, alpha = 2, at the benchmark's 204800 samples and
+    at a ragged count, and a 10-site real FP64 TFIM ring (two blocks per compute unit) at
+    136072; the samples of the last partial round are shared by several lanes each (8
+    and 16 on 256 compute units); entries of both parts against the oracle."""
     m, om = cases.build(lib, name)
     p = cases.params(name, theta=0.3, seed=65)
-    pe = p.astype(np.complex128)
+    pe = p.astype(np.complex128 if m.is_complex else np.float64)
     s = cases.configs(name, n, seed=66)
     el = m.local_energy(to_dev(p), to_dev(s)).cpu().numpy()
     rng = np.random.default_rng(67)
