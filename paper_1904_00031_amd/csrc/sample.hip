@@ -967,7 +967,8 @@ __global__ __launch_bounds__(64 * kRowsWaves) void k_eloc_rows(DevModel dm, Tabl
 // lane visits only the rows its sample connects (every site for TFIM, the bonds with
 // opposite spins for Heisenberg), reading their C/S entries from LDS, and multiplies its
 // own ratio terms, so no cross-lane reduction is needed; the loop runs as many passes as
-// the lane with the most connected rows. Same terms as eloc_grouped (Eq. 5).
+// the lane with the most connected rows. In the last, partial grid-stride step several
+// lanes share a sample and add their sums across lanes. Same terms as eloc_grouped (Eq. 5).
 // ---------------------------------------------------------------------------------
 template <typename T, bool C, int TPM>
 __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
@@ -1010,8 +1011,8 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nrows = tfim ? (dm.h != 0.0 ? N : 0) : B;
-  // Whole rounds give every wavefront 64 samples, one per lane. The samples left after
-  // them (fewer than 64 per wavefront) are spread over every wavefront: spw per wavefront,
+  // Whole grid-stride steps give every wavefront 64 samples, one per lane. The samples
+  // left after them (fewer than 64 per wavefront) are spread over every wavefront: spw per wavefront,
   // L = 64 / spw lanes per sample, each lane taking every L-th of the sample's connected
   // rows; the L partial sums are then added across the lanes.
   const int64_t W = int64_t(gridDim.x) * (blockDim.x >> 6);
@@ -1019,8 +1020,8 @@ __global__ __launch_bounds__(256) void k_eloc_lanes(DevModel dm, Tables<T> tb,
   const int64_t nfull = n / (64 * W) * (64 * W), rem = n - nfull;
   int spw = 1;
   while (int64_t(spw) * W < rem) spw <<= 1;
-  const int64_t rounds = nfull / (64 * W) + (rem > 0 ? 1 : 0);
-  for (int64_t it = 0; it < rounds; ++it) {
+  const int64_t steps = nfull / (64 * W) + (rem > 0 ? 1 : 0);
+  for (int64_t it = 0; it < steps; ++it) {
     const bool tail = it * 64 * W >= nfull;
     const int L = tail ? 64 / spw : 1;
     const int sub = lane & (L - 1);

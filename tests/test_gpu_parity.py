@@ -353,7 +353,7 @@ def test_local_energy_full_size_sampled(lib, name, n):
     """Local energies at sample counts beyond one sample per lane of the whole chip: the
     40-site Heisenberg ring, complex FP32, alpha = 2, at the benchmark's 204800 samples and
     at a ragged count, and a 10-site real FP64 TFIM ring (two blocks per compute unit) at
-    136072; the samples of the last partial round are shared by several lanes each (8
+    136072; the samples of the last partial grid-stride step are shared by several lanes each (8
     and 16 on 256 compute units); entries of both parts against the oracle."""
     m, om = cases.build(lib, name)
     p = cases.params(name, theta=0.3, seed=65)
