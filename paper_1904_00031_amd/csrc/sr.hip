@@ -415,8 +415,9 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
     }
   }
   double gr = 0.0, gi = 0.0;
-  if (e < elems) {
-    // up to 32 loads in flight per thread, added in split order
+  if (k >= 0) {
+    // up to 32 loads in flight per thread, added in split order (padding entries of the
+    // tile layout are not read)
     int q = sl;
     for (; q + 31 * kAprSlices < splits; q += 32 * kAprSlices) {
       V<T, C> xs[32];
