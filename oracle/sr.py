@@ -16,7 +16,10 @@ the n samples:
 ``cg`` is textbook conjugate gradients for a Hermitian positive-definite operator, x0 = 0,
 stopping when ||r|| <= tol * ||F|| or after maxiter matrix-vector products.
 
-Pins (tests/test_oracle_sr.py): F against finite differences of the exact energy
+Pins (tests/test_oracle_sr.py): ``stats`` against a hand-built layout whose chain means
+and variance are known in closed form, and the unbiasedness of err^2 (its average over
+many independent Gaussian data sets equals sigma^2 / n); F against finite differences of
+the exact energy
 (dE/dRe p_k = 2 Re F_k, dE/dIm p_k = 2 Im F_k), the quadratic form v^dagger S v against
 the norm of the finite-difference tangent vector projected orthogonally to psi, CG
 against a dense solve, and exact-expectation SR descending to the exact ground energy.
@@ -27,18 +30,28 @@ from . import exact, hamiltonian, lattice, rbm
 
 
 def stats(eloc, n_chains=None):
-    """Mean, variance and error bar of the local energies. The error bar is the
-    standard deviation of per-chain means over sqrt(number of chains) when the samples
-    are laid out [n_sweeps, n_chains] (row-major), else sqrt(var / n)."""
+    """Mean, variance and error bar of the local energies (Sec. 2.2.5: the energy is
+    reported with its statistical uncertainty and its variance).
+
+    mean = <E_loc>, var = <|E_loc - mean|^2> (population averages over the n samples).
+    The error bar is the standard error of the mean estimated from chain means: the
+    samples are laid out [n_sweeps, n_chains] (row-major: sample s = sweep * n_chains +
+    chain), m_c is the mean of Re E_loc over chain c's sweeps, and
+
+        err = sqrt( sum_c (m_c - mean(m))^2 / (C - 1) ) / sqrt(C)
+
+    (the unbiased variance of the C chain means, over C). Without a chain count every
+    sample is its own chain (C = n, one sweep)."""
     e = np.asarray(eloc)
     n = e.size
     mean = e.mean()
     var = np.mean(np.abs(e - mean) ** 2)
-    if n_chains and n_chains > 1 and n % n_chains == 0:
-        cm = e.reshape(-1, n_chains).mean(axis=0)
-        err = np.std(cm.real) / np.sqrt(n_chains)
-    else:
-        err = np.sqrt(var / n)
+    C = int(n_chains) if n_chains else n
+    if C < 2 or n % C:
+        raise ValueError("need at least two chains dividing the sample count")
+    chain_means = e.real.reshape(n // C, C).mean(axis=0)
+    d = chain_means - chain_means.mean()
+    err = np.sqrt(np.sum(d * d) / (C - 1)) / np.sqrt(C)
     return mean, var, err
 
 

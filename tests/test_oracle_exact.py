@@ -31,6 +31,23 @@ def test_tfim_closed_form_golden():
     assert abs(exact.tfim_ground_energy(10, 1.0, 1.0) - golden()["tfim_n10_h1"]) < 1e-13
 
 
+def test_golden_lines_follow_from_the_oracle():
+    # the computed lines of the golden file, re-derived (tests/golden/make_reference_energies.py)
+    gd = golden()
+    assert abs(exact.heisenberg_ring_bethe(20) - gd["heis_ring_n20"]) < 1e-12 * 36
+    assert abs(exact.heisenberg_ring_bethe(40) - gd["heis_ring_n40"]) < 1e-12 * 71
+
+
+@pytest.mark.parametrize("n", [20, 40, 80])
+def test_bethe_ring_against_thermodynamic_limit(n):
+    # Hulthen's infinite-chain energy 1 - 4 ln 2 per site (Pauli units) with the
+    # conformal finite-size term -pi v c / (6 N^2) (v = 2 pi in Pauli units, c = 1); what
+    # is left is the logarithmic correction, below 0.05 / N^2 at these sizes
+    e = exact.heisenberg_ring_bethe(n) / n
+    pred = 1.0 - 4.0 * np.log(2.0) - np.pi ** 2 / (3.0 * n * n)
+    assert abs(e - pred) < 0.05 / (n * n), (e, pred)
+
+
 @pytest.mark.parametrize("n", [10, 12, 16])
 def test_bethe_matches_ed(n):
     bonds, sub = lattice.hypercube(n, 1)

@@ -59,3 +59,34 @@ def test_jvp_vjp_adjoint():
     lhs = np.vdot(u, rbm.jvp(p, s, v, N, M))
     rhs = np.vdot(rbm.vjp(p, s, u, N, M), v)
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("rounded", [False, True])
+def test_vjp_entries_equal_full_vjp(cplx, rounded):
+    # every entry k of O^dagger u taken from its own column equals the full product; the
+    # shapes have N != M so a swapped (row, column) index of W cannot pass
+    from oracle import quant
+    N, M = 5, 3
+    p = synth.rbm_params(N, M, cplx, sigma=0.7, seed=21)
+    s = synth.spin_configs(17, N, seed=22)
+    u = synth.random_vector(17, cplx, 23)
+    rt = quant.bf16 if rounded else None
+    full = rbm.vjp(p, s, u, N, M, round_tanh=rt)
+    ks = np.arange(p.size)
+    got = rbm.vjp_entries(p, s, u, ks, N, M, round_tanh=rt)
+    assert np.allclose(got, full, rtol=1e-13, atol=1e-13)
+    # and the explicit O built element by element from the definition
+    a, b, W = rbm.unpack(p, N, M)
+    t_of = (lambda x: rt(x)) if rt is not None else (lambda x: x)
+    for k in [0, N - 1, N, N + M - 1, N + M, N + M + 1, N + M + N, p.size - 1]:
+        if k < N:
+            col = s[:, k].astype(float)
+        elif k < N + M:
+            col = t_of(np.tanh(b[k - N] + s @ W[k - N]))
+        else:
+            j, i = (k - N - M) // N, (k - N - M) % N
+            th = b[j] + sum(W[j, q] * s[:, q] for q in range(N))
+            col = t_of(np.tanh(th)) * s[:, i]
+        ref = np.sum(np.conj(col) * u)
+        assert abs(got[k] - ref) < 1e-12 * max(1.0, abs(ref)), k

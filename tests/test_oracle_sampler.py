@@ -80,3 +80,27 @@ def test_init_chains():
     assert len({r.tobytes() for r in c}) > 200
     f = sampler.init_chains(model(MOVE_FLIP, n=10), 500, seed=3)
     assert abs(f.mean()) < 0.05
+
+
+@pytest.mark.parametrize("move", [MOVE_FLIP, MOVE_EXCHANGE])
+def test_init_chains_uniform_chi_square(move):
+    # chain initialisation draws uniformly from every allowed configuration: all 2^6
+    # spin rows (flip moves) or all 20 zero-magnetisation rows of six sites (a Fisher-
+    # Yates shuffle whose swap partner is drawn from [0, k] for position k; drawing it
+    # from [0, k) instead, Sattolo's cyclic shuffle, is not uniform here and fails)
+    from scipy.stats import chi2
+    m = model(move)
+    chains = 24000
+    c = sampler.init_chains(m, chains, seed=12)
+    from oracle import lattice
+    confs = lattice.all_configs(6)
+    if move == MOVE_EXCHANGE:
+        confs = confs[confs.sum(axis=1) == 0]
+        assert len(confs) == 20
+    index = {r.tobytes(): k for k, r in enumerate(confs)}
+    hist = np.zeros(len(confs))
+    for r in c:
+        hist[index[r.tobytes()]] += 1
+    expct = chains / len(confs)
+    stat = np.sum((hist - expct) ** 2 / expct)
+    assert chi2.sf(stat, df=len(confs) - 1) > 1e-3, stat

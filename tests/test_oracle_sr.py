@@ -84,3 +84,37 @@ def test_exact_sr_descends_to_ground_energy():
     assert energies[-1] < energies[0]
     assert np.all(np.diff(energies[5:]) < 1e-9)
     assert abs(energies[-1] - e0) / abs(e0) < 2e-3
+
+
+def test_stats_hand_built_chain_means():
+    # chain c holds c + d_s with sweep offsets d_s summing to zero: the chain means are
+    # exactly 0, 1, ..., C-1, so err = sqrt(var(0..C-1, unbiased) / C) = sqrt((C + 1) / 12)
+    C, S = 7, 4
+    d = np.array([0.5, -1.25, 0.25, 0.5])
+    e = np.arange(C)[None, :] + d[:, None]          # [sweeps, chains]
+    mean, var, err = sr.stats(e.ravel(), n_chains=C)
+    assert abs(mean - (C - 1) / 2.0) < 1e-14
+    # population variance: between-chain part (C^2 - 1) / 12 plus the sweep offsets
+    assert abs(var - ((C * C - 1) / 12.0 + np.mean(d * d))) < 1e-13
+    assert abs(err - np.sqrt((C + 1) / 12.0)) < 1e-14
+    # the transposed layout (chains as rows) has different chain means
+    assert abs(sr.stats(e.T.ravel(), n_chains=C)[2] - err) > 0.1
+    # complex energies: the error bar is that of the real part
+    _, _, err_c = sr.stats(e.ravel() + 1j * np.arange(C * S), n_chains=C)
+    assert abs(err_c - err) < 1e-14
+    # no chain count: every sample is a chain
+    x = np.array([1.0, 2.0, 4.0, 7.0])
+    assert abs(sr.stats(x)[2] - np.std(x, ddof=1) / 2.0) < 1e-14
+    with pytest.raises(ValueError):
+        sr.stats(np.ones(6), n_chains=4)
+
+
+def test_stats_error_bar_is_unbiased():
+    # E[err^2] = Var(chain mean) / C = sigma^2 / n for independent samples; a biased
+    # (1/C) variance of the chain means would give (C - 1) / C of it
+    rng = np.random.default_rng(5)
+    C, S, trials, sigma = 4, 3, 20000, 1.7
+    e = rng.normal(0.0, sigma, size=(trials, S * C))
+    err2 = np.array([sr.stats(row, n_chains=C)[2] ** 2 for row in e])
+    ratio = err2.mean() / (sigma ** 2 / (S * C))
+    assert abs(ratio - 1.0) < 0.03, ratio
