@@ -92,7 +92,9 @@ typedef struct {
 
 typedef struct nqs_model nqs_model;
 
-/* Information returned by nqs_sr_step (host struct, filled before the call returns). */
+/* Information of one SR step (Sec. 2.2.5: the energy is reported with its statistical
+ * error and its variance, Fig. 2). nqs_sr_step fills a host struct before it returns;
+ * nqs_sr_step_async writes the same struct to device memory, in stream order. */
 typedef struct {
   int32_t cg_iters;        /* matrix-vector products performed */
   int32_t converged;       /* 1 if ||r|| <= cg_tol * ||F|| */
@@ -100,6 +102,12 @@ typedef struct {
   double energy_re, energy_im;  /* mean local energy */
   double variance;         /* mean |E_loc - E|^2 */
   double force_norm;       /* ||F||_2 */
+  double energy_err;       /* error bar of energy_re: with C chains and the samples laid out
+                              [sweeps, chains], m_c = mean of Re E_loc over chain c and
+                              energy_err = sqrt(sum_c (m_c - mean m)^2 / (C - 1)) / sqrt(C);
+                              n_chains = 0 treats every sample as its own chain */
+  int32_t status;          /* NQS_OK, NQS_ENOTCONV or NQS_ENONFINITE: the step's outcome */
+  int32_t reserved;
 } nqs_sr_info;
 
 /* Lattice helper (Sec. 2.2.1, Hypercube graph): periodic L^ndim hypercube, ndim 1 or 2.
@@ -128,7 +136,15 @@ nqs_status nqs_chain_init(nqs_model *model, int8_t *chain_sigma, int32_t n_chain
  * `sw` of chain c draws Philox4x32-10 with key = seed and counter
  * (chain_offset + c, counter + sw, step, 0): word 0 picks the site (flip) or color-0
  * bond (exchange) as floor(w0 * n / 2^32); words 1, 2 give u = (w1 * 2^21 + w2 >> 11)
- * * 2^-53. Accept iff |psi'/psi|^2 >= 1 or u < |psi'/psi|^2 (decided in double). An
+ * * 2^-53. Accept iff |psi'/psi|^2 >= 1 or u < |psi'/psi|^2. NQS_F64 takes this
+ * decision in double: the wave product of the ratio terms as mantissa x 2^exponent,
+ * scaled by |exp(visible-bias change)|^2 and compared with u. NQS_F32 and NQS_BF16 take
+ * it in the float log domain: each lane forms log2 of the product of |ratio term|^2 of
+ * up to four of its hidden units (hardware log2), the wavefront sums these in float, and
+ * the proposal is accepted iff the sum exceeds log2(u) - log2|exp(visible-bias
+ * change)|^2 (also float). This agrees with the exact rule except within a relative
+ * margin of about 1e-5 around |psi'/psi|^2 = u (the parity tests allow a chain to leave
+ * the FP64 oracle's chain only after a proposal with |u - |psi'/psi|^2| < 1e-4). An
  * exchange of equal spins is an identity move (not counted). After each of the last
  * n_sweeps sweeps the configuration is written to samples[sweep][c][:].
  *  params      (device) packed RBM parameters (master precision; see top)
@@ -138,8 +154,9 @@ nqs_status nqs_chain_init(nqs_model *model, int8_t *chain_sigma, int32_t n_chain
  *  eloc        (device) double/complex double [n_sweeps * n_chains] or NULL: if given,
  *              the local energy of every recorded sample (same values as
  *              nqs_local_energy on `samples`, up to rounding). With at least 16 chains per
- *              compute unit it is evaluated inside the sweep from the chain's cached
- *              hidden-unit angles; otherwise by a separate pass over the samples.
+ *              compute unit and at most 256 hidden units it is evaluated inside the sweep
+ *              from the chain's cached hidden-unit angles; otherwise by a separate pass
+ *              over the samples.
  * Limits: n_chains >= 1, n_sweeps >= 1, n_discard >= 0, chain_offset >= 0. */
 nqs_status nqs_sample(nqs_model *model, const void *params, int8_t *chain_sigma,
                       int32_t n_chains, int32_t n_sweeps, int32_t n_discard, uint64_t seed,
@@ -179,16 +196,36 @@ size_t nqs_sr_workspace_bytes(nqs_model *model, int64_t n);
  *   ||r|| <= cg_tol ||F|| or after cg_maxiter products), S applied implicitly as
  *   S v = O^dagger (O v - mean(O v)) / n, then params <- params - lr x.
  * Real models use real arithmetic throughout. params (device) in/out; sigma (device)
- * [n, N]; eloc (device) [n] double/complex double; workspace (device) of at least
+ * [n, N]; eloc (device) [n] double/complex double; n_chains: the samples are laid out
+ * [n / n_chains sweeps, n_chains chains] for the energy error bar (n_chains divides n;
+ * 0 = every sample its own chain); workspace (device) of at least
  * nqs_sr_workspace_bytes(model, n) bytes; info (host) may be NULL.
  * Synchronises `stream` (the CG loop checks convergence on the host every few
- * iterations). Returns NQS_ENOTCONV if cg_maxiter was reached, NQS_ENONFINITE if the
- * energy, the force or a CG scalar is not finite (params are then left unchanged).
- * Limits: n >= 2, cg_maxiter >= 1, cg_tol >= 0, diag_shift >= 0. */
+ * iterations, while the next chunk of iterations already runs). Returns NQS_ENOTCONV if
+ * cg_maxiter was reached, NQS_ENONFINITE if the energy, the force or a CG scalar is not
+ * finite (params are then left unchanged).
+ * Limits: n >= 2, 0 <= n_chains <= n, cg_maxiter >= 1, cg_tol >= 0, diag_shift >= 0. */
 nqs_status nqs_sr_step(nqs_model *model, void *params, const int8_t *sigma, const void *eloc,
-                       int64_t n, double lr, double diag_shift, double cg_tol,
-                       int32_t cg_maxiter, void *workspace, size_t ws_bytes,
+                       int64_t n, int32_t n_chains, double lr, double diag_shift,
+                       double cg_tol, int32_t cg_maxiter, void *workspace, size_t ws_bytes,
                        nqs_sr_info *info, void *stream);
+
+/* The same SR update, stream-ordered (Sec. 2.2.5, Eq. 2): nothing is read back on the
+ * host, so the call returns after queueing its kernels and may be captured into a
+ * hipGraph. The solve runs exactly cg_maxiter iteration slots; convergence (or a
+ * non-finite scalar) is decided on the device, and the slots after it return at once,
+ * so cg_maxiter is the caller's bound on the work queued (a solve that needs more
+ * iterations ends with NQS_ENOTCONV in info->status). The parameters are updated on the
+ * device only when the energy, the force and every CG scalar are finite. info (device)
+ * receives the step's nqs_sr_info, status included. Results equal those of nqs_sr_step
+ * with the same arguments bit for bit. The call allocates nothing, copies nothing and
+ * never synchronises.
+ * Returns NQS_EINVAL / NQS_ENOMEM / NQS_EDEVICE for argument and launch errors only. */
+nqs_status nqs_sr_step_async(nqs_model *model, void *params, const int8_t *sigma,
+                             const void *eloc, int64_t n, int32_t n_chains, double lr,
+                             double diag_shift, double cg_tol, int32_t cg_maxiter,
+                             void *workspace, size_t ws_bytes, nqs_sr_info *info,
+                             void *stream);
 
 /* The S v product of stochastic reconfiguration on its own (Sec. 2.2.5; the implicit form
  * S v = O^dagger (O v - mean(O v)) / n of the same S as nqs_sr_step), for custom solvers
@@ -247,10 +284,14 @@ nqs_status nqs_set_cg_graphs(nqs_model *model, int32_t enable);
  * chains and samples equal those of nqs_chain_init / nqs_sample on its own model with
  * that seed and chain_offset 0. Sampling (Sec. 2.2.5) runs every chain of every model in
  * one persistent launch, after one launch that refreshes every model's tables; local
- * energies (Eq. 5) are evaluated inside the sweep when eloc is not NULL. The block-to-
- * model tables are uploaded (synchronously) only when buffers or sizes change, so a
- * repeated call with the same arguments issues no host-to-device copy and can be
- * captured into a hipGraph after one uncaptured call. */
+ * energies (Eq. 5) are evaluated inside the sweep when eloc is not NULL. counter_dev
+ * (device, one uint64, may be NULL): when given, the sweep base of the counter is read
+ * from it on the device (the counter argument is then ignored) and advanced by
+ * n_discard + n_sweeps after the sweeps, in stream order, so that replays of a captured
+ * call continue the random stream as consecutive calls would. The block-to-model tables
+ * are uploaded (synchronously) only when buffers or sizes change (not the counter), so a
+ * repeated call with the same buffers issues no host-to-device copy and can be captured
+ * into a hipGraph after one uncaptured call. */
 typedef struct nqs_batch nqs_batch;
 nqs_status nqs_batch_create(const nqs_model_desc *descs, int32_t n_models, nqs_batch **out);
 void nqs_batch_destroy(nqs_batch *batch);
@@ -259,21 +300,38 @@ nqs_status nqs_batch_chain_init(nqs_batch *batch, int8_t *chain_sigma, const int
                                 uint64_t seed, void *stream);
 nqs_status nqs_batch_sample(nqs_batch *batch, const void *params, int8_t *chain_sigma,
                             const int32_t *n_chains, int32_t n_sweeps, int32_t n_discard,
-                            uint64_t seed, uint64_t counter, int8_t *samples,
-                            int64_t *n_accepted, void *eloc, void *stream);
+                            uint64_t seed, uint64_t counter, uint64_t *counter_dev,
+                            int8_t *samples, int64_t *n_accepted, void *eloc, void *stream);
 /* One SR step (Sec. 2.2.5, Eq. 2) of every model of the batch, as nqs_sr_step on each:
  * samples and eloc concatenated in model order (model k: n_samples[k] rows of N_k spins,
- * n_samples[k] local energies), params updated in place, info (host) an array [K]. The
- * solves advance together: every kernel of a CG iteration is one launch for all models,
- * and models that have converged stop updating. Returns NQS_ENONFINITE if any model's
- * solve is non-finite (its parameters are left unchanged), else NQS_ENOTCONV if any
- * model reached cg_maxiter, else NQS_OK. Synchronizes the stream. Workspace:
- * nqs_batch_sr_workspace_bytes(batch, n_samples) bytes (0 if some n_samples[k] < 2). */
+ * n_samples[k] local energies, laid out [sweeps, n_chains[k]] for the error bar;
+ * n_chains (host [K]) may be NULL: every sample its own chain), params updated in place,
+ * info (host) an array [K]. The solves advance together: every kernel of a CG iteration
+ * is one launch for all models, and models that have converged stop updating. Returns
+ * NQS_ENONFINITE if any model's solve is non-finite (its parameters are left unchanged),
+ * else NQS_ENOTCONV if any model reached cg_maxiter, else NQS_OK. Synchronizes the
+ * stream. Workspace: nqs_batch_sr_workspace_bytes(batch, n_samples) bytes (0 if some
+ * n_samples[k] < 2). */
 size_t nqs_batch_sr_workspace_bytes(nqs_batch *batch, const int64_t *n_samples);
 nqs_status nqs_batch_sr_step(nqs_batch *batch, void *params, const int8_t *samples,
-                             const void *eloc, const int64_t *n_samples, double lr,
-                             double diag_shift, double cg_tol, int32_t cg_maxiter,
-                             void *workspace, size_t ws_bytes, nqs_sr_info *info, void *stream);
+                             const void *eloc, const int64_t *n_samples,
+                             const int32_t *n_chains, double lr, double diag_shift,
+                             double cg_tol, int32_t cg_maxiter, void *workspace,
+                             size_t ws_bytes, nqs_sr_info *info, void *stream);
+/* The batched SR step, stream-ordered (Sec. 2.2.5, Eq. 2): as nqs_sr_step_async for every
+ * model of the batch (cg_maxiter iteration slots, convergence decided per model on the
+ * device, parameters updated only where finite), info (device) an array [K] of
+ * nqs_sr_info. Results equal those of nqs_batch_sr_step bit for bit. The job tables that
+ * map blocks to models are uploaded (synchronously) only when buffers or sizes change, so
+ * after one call with the same arguments the call queues kernels only and can be
+ * captured into a hipGraph, together with nqs_batch_sample. A captured graph reads the
+ * job tables of its batch handle: calls on that handle with other buffers or sizes
+ * rewrite them, so give each captured pipeline a handle of its own. */
+nqs_status nqs_batch_sr_step_async(nqs_batch *batch, void *params, const int8_t *samples,
+                                   const void *eloc, const int64_t *n_samples,
+                                   const int32_t *n_chains, double lr, double diag_shift,
+                                   double cg_tol, int32_t cg_maxiter, void *workspace,
+                                   size_t ws_bytes, nqs_sr_info *info, void *stream);
 
 const char *nqs_status_string(nqs_status s);
 

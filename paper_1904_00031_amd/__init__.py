@@ -57,11 +57,22 @@ class SRInfo(ctypes.Structure):
         ("cg_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
         ("cg_resid", ctypes.c_double), ("energy_re", ctypes.c_double),
         ("energy_im", ctypes.c_double), ("variance", ctypes.c_double),
-        ("force_norm", ctypes.c_double),
+        ("force_norm", ctypes.c_double), ("energy_err", ctypes.c_double),
+        ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+SR_INFO_BYTES = ctypes.sizeof(SRInfo)
+
+
+def sr_infos_from_device(buf, count=1):
+    """Decode nqs_sr_info structs written to a device uint8 tensor by the stream-ordered
+    SR calls (copies the bytes to the host; synchronises)."""
+    raw = bytes(buf[:count * SR_INFO_BYTES].cpu().numpy().tobytes())
+    return [SRInfo.from_buffer_copy(raw, k * SR_INFO_BYTES).as_dict() for k in range(count)]
 
 
 def load(path=LIB_PATH):
@@ -85,8 +96,10 @@ def load(path=LIB_PATH):
         "nqs_local_energy": (i32, [vp, vp, vp, i64, vp, vp]),
         "nqs_log_psi_grad": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
         "nqs_sr_workspace_bytes": (ctypes.c_size_t, [vp, i64]),
-        "nqs_sr_step": (i32, [vp, vp, vp, vp, i64, f64, f64, f64, i32, vp, ctypes.c_size_t,
+        "nqs_sr_step": (i32, [vp, vp, vp, vp, i64, i32, f64, f64, f64, i32, vp, ctypes.c_size_t,
                               ctypes.POINTER(SRInfo), vp]),
+        "nqs_sr_step_async": (i32, [vp, vp, vp, vp, i64, i32, f64, f64, f64, i32, vp,
+                                    ctypes.c_size_t, vp, vp]),
         "nqs_sr_prepare": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, vp]),
         "nqs_sr_matvec": (i32, [vp, vp, i64, vp, ctypes.c_size_t, vp, f64, vp, vp]),
         "nqs_set_sv_shape": (i32, [vp, i32]),
@@ -96,10 +109,12 @@ def load(path=LIB_PATH):
         "nqs_batch_n_params": (i64, [vp, i32]),
         "nqs_batch_chain_init": (i32, [vp, vp, ctypes.POINTER(i32), u64, vp]),
         "nqs_batch_sample": (i32, [vp, vp, vp, ctypes.POINTER(i32), i32, i32, u64, u64, vp, vp,
-                                   vp, vp]),
+                                   vp, vp, vp]),
         "nqs_batch_sr_workspace_bytes": (ctypes.c_size_t, [vp, ctypes.POINTER(i64)]),
-        "nqs_batch_sr_step": (i32, [vp, vp, vp, vp, ctypes.POINTER(i64), f64, f64, f64, i32, vp,
-                                    ctypes.c_size_t, ctypes.POINTER(SRInfo), vp]),
+        "nqs_batch_sr_step": (i32, [vp, vp, vp, vp, ctypes.POINTER(i64), vp, f64, f64, f64, i32,
+                                    vp, ctypes.c_size_t, ctypes.POINTER(SRInfo), vp]),
+        "nqs_batch_sr_step_async": (i32, [vp, vp, vp, vp, ctypes.POINTER(i64), vp, f64, f64, f64,
+                                          i32, vp, ctypes.c_size_t, vp, vp]),
         "nqs_autotune": (i32, [vp, vp, vp, i64, vp, ctypes.c_size_t, ctypes.POINTER(TuneReport), vp]),
     }
     for name, (res, args) in sig.items():
@@ -113,11 +128,13 @@ def load(path=LIB_PATH):
 def exported_symbols():
     return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
             "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
-            "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_prepare",
+            "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_step_async",
+            "nqs_sr_prepare",
             "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_set_cg_graphs",
             "nqs_batch_create",
             "nqs_batch_destroy", "nqs_batch_n_params", "nqs_batch_chain_init",
-            "nqs_batch_sample", "nqs_batch_sr_workspace_bytes", "nqs_batch_sr_step"]
+            "nqs_batch_sample", "nqs_batch_sr_workspace_bytes", "nqs_batch_sr_step",
+            "nqs_batch_sr_step_async"]
 
 
 def _check(status, where, allow=(OK,)):
@@ -299,8 +316,7 @@ class Model:
     def sr_workspace_bytes(self, n):
         return int(_lib.nqs_sr_workspace_bytes(self._h, n))
 
-    def sr_step(self, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None):
-        """One SR update of params in place; returns the info dict (cg_iters, energy, ...)."""
+    def _sr_args(self, params, sigma, eloc, workspace):
         import torch
         _need(params, "params", self.param_dtype, (self.n_params,))
         n = sigma.shape[0]
@@ -310,15 +326,38 @@ class Model:
         if workspace is None:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=sigma.device)
         _need(workspace, "workspace", torch.uint8)
-        info = SRInfo()
-        st = _lib.nqs_sr_step(self._h, _ptr(params), _ptr(sigma), _ptr(eloc), n, float(lr),
-                              float(diag_shift), float(cg_tol), int(cg_maxiter), _ptr(workspace),
-                              workspace.numel(), ctypes.byref(info), _stream())
-        _check(st, "nqs_sr_step", allow=(OK, ENOTCONV))
-        d = info.as_dict()
-        d["status"] = st
-        return d
+        return n, workspace
 
+    def sr_step(self, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None,
+                n_chains=0):
+        """One SR update of params in place; returns the info dict (cg_iters, energy,
+        energy_err, status, ...). n_chains: samples laid out [sweeps, n_chains] for the
+        energy error bar (0: every sample its own chain)."""
+        n, workspace = self._sr_args(params, sigma, eloc, workspace)
+        info = SRInfo()
+        st = _lib.nqs_sr_step(self._h, _ptr(params), _ptr(sigma), _ptr(eloc), n, int(n_chains),
+                              float(lr), float(diag_shift), float(cg_tol), int(cg_maxiter),
+                              _ptr(workspace), workspace.numel(), ctypes.byref(info), _stream())
+        _check(st, "nqs_sr_step", allow=(OK, ENOTCONV, ENONFINITE))
+        return info.as_dict()
+
+    def sr_step_async(self, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter,
+                      workspace=None, n_chains=0, info=None):
+        """Stream-ordered SR update (cg_maxiter iteration slots, nothing read back). info: a
+        device uint8 tensor of at least SR_INFO_BYTES that receives the nqs_sr_info; returns
+        it (decode with sr_infos_from_device)."""
+        import torch
+        n, workspace = self._sr_args(params, sigma, eloc, workspace)
+        if info is None:
+            info = torch.zeros(SR_INFO_BYTES, dtype=torch.uint8, device=sigma.device)
+        _need(info, "info", torch.uint8)
+        if info.numel() < SR_INFO_BYTES:
+            raise ValueError("info needs %d bytes" % SR_INFO_BYTES)
+        _check(_lib.nqs_sr_step_async(self._h, _ptr(params), _ptr(sigma), _ptr(eloc), n,
+                                      int(n_chains), float(lr), float(diag_shift), float(cg_tol),
+                                      int(cg_maxiter), _ptr(workspace), workspace.numel(),
+                                      _ptr(info), _stream()), "nqs_sr_step_async")
+        return info
 
     def sr_prepare(self, params, sigma, workspace=None):
         """Prepare the implicit S of these samples; returns the workspace to pass to
@@ -427,7 +466,7 @@ class Batch:
         return chains
 
     def sample(self, params, chains, n_chains, n_sweeps, n_discard, seed, counter,
-               samples=None, n_accepted=None, eloc=None, with_eloc=True):
+               samples=None, n_accepted=None, eloc=None, with_eloc=True, counter_dev=None):
         import torch
         nc = (ctypes.c_int32 * self.K)(*[int(c) for c in n_chains])
         _need(params, "params", self.param_dtype, (sum(self.n_params),))
@@ -443,20 +482,21 @@ class Batch:
                                device=chains.device)
         if eloc is not None:
             _need(eloc, "eloc", self.value_dtype, (n_sweeps * sum(int(c) for c in n_chains),))
+        if counter_dev is not None:
+            _need(counter_dev, "counter_dev", torch.int64, (1,))
         _check(_lib.nqs_batch_sample(self._h, _ptr(params), _ptr(chains), nc, n_sweeps, n_discard,
-                                     seed, counter, _ptr(samples), _ptr(n_accepted), _ptr(eloc),
-                                     _stream()), "nqs_batch_sample")
+                                     seed, counter, _ptr(counter_dev), _ptr(samples),
+                                     _ptr(n_accepted), _ptr(eloc), _stream()), "nqs_batch_sample")
         return samples, eloc
 
     def sr_workspace_bytes(self, n_samples):
         ns = (ctypes.c_int64 * self.K)(*[int(x) for x in n_samples])
         return int(_lib.nqs_batch_sr_workspace_bytes(self._h, ns))
 
-    def sr_step(self, params, samples, eloc, n_samples, lr, diag_shift, cg_tol, cg_maxiter,
-                workspace=None):
-        """One SR step of every model; returns a list of info dicts."""
+    def _sr_args(self, params, samples, eloc, n_samples, n_chains, workspace):
         import torch
         ns = (ctypes.c_int64 * self.K)(*[int(x) for x in n_samples])
+        nc = None if n_chains is None else (ctypes.c_int32 * self.K)(*[int(x) for x in n_chains])
         _need(params, "params", self.param_dtype, (sum(self.n_params),))
         _need(samples, "samples", torch.int8, (sum(int(x) * n for x, n in zip(n_samples, self.n_sites)),))
         _need(eloc, "eloc", self.value_dtype, (sum(int(x) for x in n_samples),))
@@ -464,12 +504,36 @@ class Batch:
         if workspace is None:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=samples.device)
         _need(workspace, "workspace", torch.uint8)
+        return ns, nc, workspace
+
+    def sr_step(self, params, samples, eloc, n_samples, lr, diag_shift, cg_tol, cg_maxiter,
+                workspace=None, n_chains=None):
+        """One SR step of every model; returns a list of info dicts."""
+        ns, nc, workspace = self._sr_args(params, samples, eloc, n_samples, n_chains, workspace)
         infos = (SRInfo * self.K)()
         _check(_lib.nqs_batch_sr_step(self._h, _ptr(params), _ptr(samples), _ptr(eloc), ns,
-                                      float(lr), float(diag_shift), float(cg_tol), int(cg_maxiter),
-                                      _ptr(workspace), workspace.numel(), infos, _stream()),
-               "nqs_batch_sr_step", allow=(OK, ENOTCONV))
+                                      nc, float(lr), float(diag_shift), float(cg_tol),
+                                      int(cg_maxiter), _ptr(workspace), workspace.numel(), infos,
+                                      _stream()),
+               "nqs_batch_sr_step", allow=(OK, ENOTCONV, ENONFINITE))
         return [infos[k].as_dict() for k in range(self.K)]
+
+    def sr_step_async(self, params, samples, eloc, n_samples, lr, diag_shift, cg_tol,
+                      cg_maxiter, workspace=None, n_chains=None, info=None):
+        """Stream-ordered SR step of every model; info: device uint8 tensor of at least
+        K * SR_INFO_BYTES receiving the K nqs_sr_info structs (returned)."""
+        import torch
+        ns, nc, workspace = self._sr_args(params, samples, eloc, n_samples, n_chains, workspace)
+        if info is None:
+            info = torch.zeros(self.K * SR_INFO_BYTES, dtype=torch.uint8, device=samples.device)
+        _need(info, "info", torch.uint8)
+        if info.numel() < self.K * SR_INFO_BYTES:
+            raise ValueError("info needs %d bytes" % (self.K * SR_INFO_BYTES))
+        _check(_lib.nqs_batch_sr_step_async(self._h, _ptr(params), _ptr(samples), _ptr(eloc), ns,
+                                            nc, float(lr), float(diag_shift), float(cg_tol),
+                                            int(cg_maxiter), _ptr(workspace), workspace.numel(),
+                                            _ptr(info), _stream()), "nqs_batch_sr_step_async")
+        return info
 
 
 # C-ABI-named module functions --------------------------------------------------------
@@ -517,5 +581,13 @@ def nqs_autotune(model, params, sigma, workspace=None):
     return model.autotune(params, sigma, workspace)
 
 
-def nqs_sr_step(model, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None):
-    return model.sr_step(params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace)
+def nqs_sr_step(model, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace=None,
+                n_chains=0):
+    return model.sr_step(params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter, workspace,
+                         n_chains)
+
+
+def nqs_sr_step_async(model, params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter,
+                      workspace=None, n_chains=0, info=None):
+    return model.sr_step_async(params, sigma, eloc, lr, diag_shift, cg_tol, cg_maxiter,
+                               workspace, n_chains, info)

@@ -42,7 +42,9 @@ nqs_status ensure_scratch(nqs_model *m, size_t bytes) {
 }  // namespace
 
 DevModel dev_model(const nqs_model *m) {
+  // zero-filled: copies of it go into job tables that are compared byte by byte
   DevModel d;
+  memset(static_cast<void *>(&d), 0, sizeof d);
   d.N = m->N;
   d.M = m->M;
   d.B0 = m->B[0];
@@ -303,49 +305,87 @@ nqs_status nqs_local_energy(nqs_model *m, const void *params, const int8_t *sigm
   return dev(e);
 }
 
-nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
-                            const void *u, void *vjp, const void *v, void *jvp, void *stream) {
+// the Jacobian products of nqs_log_psi_grad with the given scratch (grad_scratch_bytes)
+static nqs_status log_psi_grad_with(nqs_model *m, const void *params, const int8_t *sigma,
+                                    int64_t n, const void *u, void *vjp, const void *v,
+                                    void *jvp, void *scr, hipStream_t st) {
+  hipError_t e = launch_tables(m, params, st);
+  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, scr, true, st);
+  if (e == hipSuccess && u && vjp) {
+    e = launch_vjp_partials(m, sigma, n, (const double *)u, scr, nullptr, st);
+    if (e == hipSuccess) e = launch_vjp_reduce(m, n, scr, (double *)vjp, nullptr, st);
+  }
+  if (e == hipSuccess && v && jvp) {
+    e = launch_prep_dir(m, v, scr, true, st);
+    if (e == hipSuccess) e = launch_jvp(m, sigma, n, scr, (double *)jvp, nullptr, nullptr, st);
+  }
+  return dev(e);
+}
+
+// argument checks shared by both Jacobian entry points; n == 0 is answered here (vjp = 0)
+static nqs_status log_psi_grad_args(nqs_model *m, const void *params, const int8_t *sigma,
+                                    int64_t n, const void *u, void *vjp, const void *v,
+                                    void *jvp, hipStream_t st, bool *done) {
+  *done = true;
   if (!m || !params || n < 0 || (n > 0 && !sigma)) return NQS_EINVAL;
   const bool want_vjp = u && vjp, want_jvp = v && jvp;
   if (!want_vjp && !want_jvp) return NQS_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  const int cs = m->is_complex ? 2 : 1;
   if (n == 0) {
+    const int cs = m->is_complex ? 2 : 1;
     if (want_vjp)
       hipLaunchKernelGGL(k_zero, dim3(grid_for(n_params_of(m) * cs)), dim3(256), 0, st,
                          n_params_of(m) * cs, (double *)vjp);
     return dev(hipGetLastError());
   }
-  nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
-  if (s != NQS_OK) return s;
-  hipError_t e = launch_tables(m, params, st);
-  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, true, st);
-  if (e == hipSuccess && want_vjp) {
-    e = launch_vjp_partials(m, sigma, n, (const double *)u, m->d_scratch, nullptr, st);
-    if (e == hipSuccess) e = launch_vjp_reduce(m, n, m->d_scratch, (double *)vjp, nullptr, st);
-  }
-  if (e == hipSuccess && want_jvp) {
-    e = launch_prep_dir(m, v, m->d_scratch, true, st);
-    if (e == hipSuccess)
-      e = launch_jvp(m, sigma, n, m->d_scratch, (double *)jvp, nullptr, nullptr, st);
-  }
-  return dev(e);
+  *done = false;
+  return NQS_OK;
 }
+
+nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                            const void *u, void *vjp, const void *v, void *jvp, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  bool done;
+  nqs_status s = log_psi_grad_args(m, params, sigma, n, u, vjp, v, jvp, st, &done);
+  if (done) return s;
+  s = ensure_scratch(m, grad_scratch_bytes(m, n));
+  if (s != NQS_OK) return s;
+  return log_psi_grad_with(m, params, sigma, n, u, vjp, v, jvp, m->d_scratch, st);
+}
+
 
 size_t nqs_sr_workspace_bytes(nqs_model *m, int64_t n) {
   if (!m || n < 2) return 0;
   return sr_workspace_bytes(m, n);
 }
 
+static bool sr_args_ok(const nqs_model *m, const void *params, const int8_t *sigma,
+                       const void *eloc, const void *workspace, int64_t n, int32_t n_chains,
+                       double lr, double diag_shift, double cg_tol, int32_t cg_maxiter) {
+  return m && params && sigma && eloc && workspace && n >= 2 && cg_maxiter >= 1 &&
+         cg_tol >= 0 && diag_shift >= 0 && isfinite(lr) && n_chains >= 0 && n_chains != 1 &&
+         n_chains <= n && (n_chains == 0 || n % n_chains == 0);
+}
+
 nqs_status nqs_sr_step(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
-                       int64_t n, double lr, double diag_shift, double cg_tol,
+                       int64_t n, int32_t n_chains, double lr, double diag_shift, double cg_tol,
                        int32_t cg_maxiter, void *workspace, size_t ws_bytes,
                        nqs_sr_info *info, void *stream) {
-  if (!m || !params || !sigma || !eloc || !workspace || n < 2 || cg_maxiter < 1 ||
-      !(cg_tol >= 0) || !(diag_shift >= 0) || !isfinite(lr))
+  if (!sr_args_ok(m, params, sigma, eloc, workspace, n, n_chains, lr, diag_shift, cg_tol,
+                  cg_maxiter))
     return NQS_EINVAL;
-  return sr_step_impl(m, params, sigma, eloc, n, lr, diag_shift, cg_tol, cg_maxiter, workspace,
-                      ws_bytes, info, (hipStream_t)stream);
+  return sr_step_impl(m, params, sigma, eloc, n, n_chains, lr, diag_shift, cg_tol, cg_maxiter,
+                      workspace, ws_bytes, info, false, (hipStream_t)stream);
+}
+
+nqs_status nqs_sr_step_async(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
+                             int64_t n, int32_t n_chains, double lr, double diag_shift,
+                             double cg_tol, int32_t cg_maxiter, void *workspace,
+                             size_t ws_bytes, nqs_sr_info *info, void *stream) {
+  if (!info || !sr_args_ok(m, params, sigma, eloc, workspace, n, n_chains, lr, diag_shift,
+                           cg_tol, cg_maxiter))
+    return NQS_EINVAL;
+  return sr_step_impl(m, params, sigma, eloc, n, n_chains, lr, diag_shift, cg_tol, cg_maxiter,
+                      workspace, ws_bytes, info, true, (hipStream_t)stream);
 }
 
 nqs_status nqs_sr_prepare(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,

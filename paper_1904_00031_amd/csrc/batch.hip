@@ -117,8 +117,8 @@ nqs_status nqs_batch_chain_init(nqs_batch *b, int8_t *chain_sigma, const int32_t
 
 nqs_status nqs_batch_sample(nqs_batch *b, const void *params, int8_t *chain_sigma,
                             const int32_t *n_chains, int32_t n_sweeps, int32_t n_discard,
-                            uint64_t seed, uint64_t counter, int8_t *samples,
-                            int64_t *n_accepted, void *eloc, void *stream) {
+                            uint64_t seed, uint64_t counter, uint64_t *counter_dev,
+                            int8_t *samples, int64_t *n_accepted, void *eloc, void *stream) {
   if (!b || !params || !chain_sigma || !n_chains || !samples || n_sweeps < 1 || n_discard < 0)
     return NQS_EINVAL;
   for (int k = 0; k < b->K; ++k)
@@ -143,7 +143,8 @@ nqs_status nqs_batch_sample(nqs_batch *b, const void *params, int8_t *chain_sigm
     oe += size_t(n_sweeps) * n_chains[k] * value_bytes(m);
     oa += size_t(n_chains[k]);
   }
-  return dev(launch_sample_batch(b, items, n_sweeps, n_discard, counter, (hipStream_t)stream));
+  return dev(launch_sample_batch(b, items, n_sweeps, n_discard, counter, counter_dev,
+                                 (hipStream_t)stream));
 }
 
 size_t nqs_batch_sr_workspace_bytes(nqs_batch *b, const int64_t *n_samples) {
@@ -153,17 +154,39 @@ size_t nqs_batch_sr_workspace_bytes(nqs_batch *b, const int64_t *n_samples) {
   return batch_sr_workspace_bytes(b, n_samples);
 }
 
-nqs_status nqs_batch_sr_step(nqs_batch *b, void *params, const int8_t *samples,
-                             const void *eloc, const int64_t *n_samples, double lr,
-                             double diag_shift, double cg_tol, int32_t cg_maxiter,
-                             void *workspace, size_t ws_bytes, nqs_sr_info *info, void *stream) {
-  if (!b || !params || !samples || !eloc || !n_samples || !workspace || cg_maxiter < 0 ||
-      !(diag_shift >= 0) || !(cg_tol >= 0) || !std::isfinite(lr))
+static nqs_status batch_sr_checked(nqs_batch *b, void *params, const int8_t *samples,
+                                   const void *eloc, const int64_t *n_samples,
+                                   const int32_t *n_chains, double lr, double diag_shift,
+                                   double cg_tol, int32_t cg_maxiter, void *workspace,
+                                   size_t ws_bytes, nqs_sr_info *info, bool async, void *stream) {
+  if (!b || !params || !samples || !eloc || !n_samples || !workspace || cg_maxiter < 1 ||
+      !(diag_shift >= 0) || !(cg_tol >= 0) || !std::isfinite(lr) || (async && !info))
     return NQS_EINVAL;
-  for (int k = 0; k < b->K; ++k)
+  for (int k = 0; k < b->K; ++k) {
     if (n_samples[k] < 2) return NQS_EINVAL;
-  return batch_sr_step_impl(b, params, samples, eloc, n_samples, lr, diag_shift, cg_tol,
-                            cg_maxiter, workspace, ws_bytes, info, (hipStream_t)stream);
+    if (n_chains && (n_chains[k] < 0 || n_chains[k] == 1 || n_chains[k] > n_samples[k] ||
+                     (n_chains[k] > 0 && n_samples[k] % n_chains[k])))
+      return NQS_EINVAL;
+  }
+  return batch_sr_step_impl(b, params, samples, eloc, n_samples, n_chains, lr, diag_shift, cg_tol,
+                            cg_maxiter, workspace, ws_bytes, info, async, (hipStream_t)stream);
+}
+
+nqs_status nqs_batch_sr_step(nqs_batch *b, void *params, const int8_t *samples,
+                             const void *eloc, const int64_t *n_samples, const int32_t *n_chains,
+                             double lr, double diag_shift, double cg_tol, int32_t cg_maxiter,
+                             void *workspace, size_t ws_bytes, nqs_sr_info *info, void *stream) {
+  return batch_sr_checked(b, params, samples, eloc, n_samples, n_chains, lr, diag_shift, cg_tol,
+                          cg_maxiter, workspace, ws_bytes, info, false, stream);
+}
+
+nqs_status nqs_batch_sr_step_async(nqs_batch *b, void *params, const int8_t *samples,
+                                   const void *eloc, const int64_t *n_samples,
+                                   const int32_t *n_chains, double lr, double diag_shift,
+                                   double cg_tol, int32_t cg_maxiter, void *workspace,
+                                   size_t ws_bytes, nqs_sr_info *info, void *stream) {
+  return batch_sr_checked(b, params, samples, eloc, n_samples, n_chains, lr, diag_shift, cg_tol,
+                          cg_maxiter, workspace, ws_bytes, info, true, stream);
 }
 
 }  // extern "C"

@@ -120,9 +120,11 @@ hipError_t launch_vjp_batch(nqs_batch *b, const std::vector<BatchGradItem> &item
 hipError_t launch_tables_batch(nqs_batch *b, const std::vector<const void *> &params,
                                hipStream_t st);
 
-// tables of every model, then every chain of every model in one persistent launch
+// tables of every model, then every chain of every model in one persistent launch; the
+// sweep base is counter, or *counter_dev (advanced by n_discard + n_sweeps afterwards)
 hipError_t launch_sample_batch(nqs_batch *b, const std::vector<BatchSampleItem> &items,
-                               int n_sweeps, int n_discard, uint64_t counter, hipStream_t st);
+                               int n_sweeps, int n_discard, uint64_t counter,
+                               uint64_t *counter_dev, hipStream_t st);
 
 // compute precision of the VALU kernels: double for NQS_F64, float otherwise
 inline bool use_double(const nqs_model *m) { return m->prec == NQS_F64; }
@@ -202,12 +204,15 @@ nqs_status sr_matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws
                           hipStream_t st);
 nqs_status autotune_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
                          void *ws, size_t ws_bytes, nqs_tune_report *rep, hipStream_t st);
+// async: stream-ordered (info is a device pointer); otherwise synchronising (host info)
 nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
-                        int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
-                        void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st);
+                        int64_t n, int64_t n_chains, double lr, double diag_shift, double cg_tol,
+                        int cg_maxiter, void *ws, size_t ws_bytes, nqs_sr_info *info, bool async,
+                        hipStream_t st);
 
 size_t batch_sr_workspace_bytes(nqs_batch *b, const int64_t *n_samples);
 nqs_status batch_sr_step_impl(nqs_batch *b, void *params, const int8_t *samples,
-                              const void *eloc, const int64_t *n_samples, double lr,
-                              double diag_shift, double cg_tol, int cg_maxiter, void *ws,
-                              size_t ws_bytes, nqs_sr_info *info, hipStream_t st);
+                              const void *eloc, const int64_t *n_samples, const int32_t *n_chains,
+                              double lr, double diag_shift, double cg_tol, int cg_maxiter,
+                              void *ws, size_t ws_bytes, nqs_sr_info *info, bool async,
+                              hipStream_t st);

@@ -8,6 +8,8 @@
 // s_k = -s has delta_j = -2 s (W_ji - W_jk). cosh/sinh of 2 W_ji and of 2 (W_ji - W_jk)
 // do not depend on the configuration, so they are tabulated once per call and each ratio
 // term costs one complex multiply-add, with no transcendental function.
+#include <string.h>
+
 #include <type_traits>
 
 #include "internal.hpp"
@@ -776,12 +778,23 @@ struct SweepJob {
   SweepArgs a;
 };
 
+// The sweep base of the counter is an argument, or read from device memory (counter_dev,
+// advanced after the launch by k_advance_counter), so that the job table does not change
+// from call to call and replays of a captured call continue the random stream.
 template <typename T, bool C, int R>
 __global__ __launch_bounds__(256) void k_sweep_batch(const SweepJob<T> *__restrict__ jobs,
-                                                     const int2 *__restrict__ bmap) {
+                                                     const int2 *__restrict__ bmap,
+                                                     uint32_t counter,
+                                                     const uint64_t *counter_dev) {
   const int2 bm = bmap[blockIdx.x];  // (job, first chain of the block)
-  const SweepJob<T> J = jobs[bm.x];
+  SweepJob<T> J = jobs[bm.x];
+  J.a.counter = counter_dev ? uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(*counter_dev)))
+                            : counter;
   sweep_block<T, C, R, false, false>(J.dm, J.tb, J.a, bm.y);
+}
+
+__global__ void k_advance_counter(uint64_t *counter_dev, uint64_t by) {
+  if (threadIdx.x == 0) *counter_dev += by;
 }
 
 template <typename T, typename PT>
@@ -1168,9 +1181,19 @@ __global__ __launch_bounds__(256) void k_log_psi(DevModel dm, Tables<T> tb,
   }
 }
 
+// Job structs are compared byte by byte with the previous upload of their table (a table
+// is uploaded again only when it changed), so every struct that goes into one starts
+// zero-filled: padding bytes are then the same from call to call.
+template <typename S>
+inline void zero_fill(S &x) {
+  static_assert(std::is_trivially_copyable<S>::value, "job structs are plain data");
+  memset(static_cast<void *>(&x), 0, sizeof(S));
+}
+
 template <typename T>
 Tables<T> tables_of(const nqs_model *m) {
   Tables<T> tb;
+  zero_fill(tb);
   tb.Wt = (T *)m->tab_ptrs[0];
   tb.bv = (T *)m->tab_ptrs[1];
   tb.fC = (T *)m->tab_ptrs[2];
@@ -1405,7 +1428,8 @@ namespace {
 
 template <typename T, bool C, int R>
 hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &items,
-                          int n_sweeps, int n_discard, uint64_t counter, hipStream_t st) {
+                          int n_sweeps, int n_discard, uint64_t counter, uint64_t *counter_dev,
+                          hipStream_t st) {
   typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type PT;
   const int wpb = 4;
   std::vector<TabJob<T, PT>> tj;
@@ -1417,6 +1441,7 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
     const BatchSampleItem &it = items[k];
     const nqs_model *m = it.m;
     TabJob<T, PT> t;
+    zero_fill(t);
     t.dm = dev_model(m);
     t.tb = tables_of<T>(m);
     t.p = (const PT *)it.params;
@@ -1429,6 +1454,7 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
     for (int q = 0; q < t.blocks; ++q) tmap.push_back(make_int2(int(k), q));
     tj.push_back(t);
     SweepJob<T> w;
+    zero_fill(w);
     w.dm = dev_model(m);
     w.tb = tables_of<T>(m);
     SweepArgs &a = w.a;
@@ -1438,7 +1464,7 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
     a.n_discard = n_discard;
     a.k0 = uint32_t(it.seed & 0xffffffffu);
     a.k1 = uint32_t(it.seed >> 32);
-    a.counter = uint32_t(counter);
+    a.counter = 0;  // a launch argument (the table stays the same from call to call)
     a.chain_offset = 0;
     a.samples = it.samples;
     a.n_acc = it.n_acc;
@@ -1466,24 +1492,32 @@ hipError_t sample_batch_r(nqs_batch *b, const std::vector<BatchSampleItem> &item
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((k_sweep_batch<T, C, R>), dim3(unsigned(smap.size())), dim3(64 * wpb),
                      (size_t(wpb) * wave_max + 15) / 16 * 16 + aux_max, st,
-                     (const SweepJob<T> *)b->sweep_jobs.d, (const int2 *)b->sweep_map.d);
-  return hipGetLastError();
+                     (const SweepJob<T> *)b->sweep_jobs.d, (const int2 *)b->sweep_map.d,
+                     uint32_t(counter), (const uint64_t *)counter_dev);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (counter_dev) {
+    hipLaunchKernelGGL(k_advance_counter, dim3(1), dim3(64), 0, st, counter_dev,
+                       uint64_t(n_discard) + uint64_t(n_sweeps));
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 template <typename T, bool C>
 hipError_t sample_batch_t(nqs_batch *b, const std::vector<BatchSampleItem> &items,
-                          int n_sweeps, int n_discard, uint64_t counter, hipStream_t st) {
+                          int n_sweeps, int n_discard, uint64_t counter, uint64_t *counter_dev,
+                          hipStream_t st) {
   int r = 1;
   for (const BatchSampleItem &it : items) {
     const int rk = (it.m->M + 63) / 64;
     if (rk > r) r = rk;
   }
-  if (r <= 1) return sample_batch_r<T, C, 1>(b, items, n_sweeps, n_discard, counter, st);
-  if (r <= 2) return sample_batch_r<T, C, 2>(b, items, n_sweeps, n_discard, counter, st);
-  if (r <= 4) return sample_batch_r<T, C, 4>(b, items, n_sweeps, n_discard, counter, st);
-  if (r <= 8) return sample_batch_r<T, C, 8>(b, items, n_sweeps, n_discard, counter, st);
-  if (r <= 16) return sample_batch_r<T, C, 16>(b, items, n_sweeps, n_discard, counter, st);
-  return sample_batch_r<T, C, 32>(b, items, n_sweeps, n_discard, counter, st);
+  if (r <= 1) return sample_batch_r<T, C, 1>(b, items, n_sweeps, n_discard, counter, counter_dev, st);
+  if (r <= 2) return sample_batch_r<T, C, 2>(b, items, n_sweeps, n_discard, counter, counter_dev, st);
+  if (r <= 4) return sample_batch_r<T, C, 4>(b, items, n_sweeps, n_discard, counter, counter_dev, st);
+  if (r <= 8) return sample_batch_r<T, C, 8>(b, items, n_sweeps, n_discard, counter, counter_dev, st);
+  if (r <= 16) return sample_batch_r<T, C, 16>(b, items, n_sweeps, n_discard, counter, counter_dev, st);
+  return sample_batch_r<T, C, 32>(b, items, n_sweeps, n_discard, counter, counter_dev, st);
 }
 
 template <typename T, bool C>
@@ -1495,6 +1529,7 @@ hipError_t tables_batch_t(nqs_batch *b, const std::vector<const void *> &params,
   for (size_t k = 0; k < params.size(); ++k) {
     const nqs_model *m = b->models[k];
     TabJob<T, PT> t;
+    zero_fill(t);
     t.dm = dev_model(m);
     t.tb = tables_of<T>(m);
     t.p = (const PT *)params[k];
@@ -1529,13 +1564,14 @@ hipError_t launch_tables_batch(nqs_batch *b, const std::vector<const void *> &pa
 }
 
 hipError_t launch_sample_batch(nqs_batch *b, const std::vector<BatchSampleItem> &items,
-                               int n_sweeps, int n_discard, uint64_t counter, hipStream_t st) {
+                               int n_sweeps, int n_discard, uint64_t counter,
+                               uint64_t *counter_dev, hipStream_t st) {
   if (items.empty()) return hipSuccess;
   const nqs_model *m = items[0].m;
-  return use_double(m) ? (m->is_complex ? sample_batch_t<double, true>(b, items, n_sweeps, n_discard, counter, st)
-                                        : sample_batch_t<double, false>(b, items, n_sweeps, n_discard, counter, st))
-                       : (m->is_complex ? sample_batch_t<float, true>(b, items, n_sweeps, n_discard, counter, st)
-                                        : sample_batch_t<float, false>(b, items, n_sweeps, n_discard, counter, st));
+#define NQS_SB(T, C) sample_batch_t<T, C>(b, items, n_sweeps, n_discard, counter, counter_dev, st)
+  return use_double(m) ? (m->is_complex ? NQS_SB(double, true) : NQS_SB(double, false))
+                       : (m->is_complex ? NQS_SB(float, true) : NQS_SB(float, false));
+#undef NQS_SB
 }
 
 #define NQS_DISPATCH(FN, ...)                                                              \

@@ -7,6 +7,7 @@
 // All reductions are two-level (per-block partials, then every consumer block sums the
 // partials in a fixed order), so results are bitwise reproducible run to run.
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <cmath>
@@ -19,6 +20,7 @@ namespace {
 struct CGState {
   double E[2];
   double var;
+  double err;  // error bar of Re E from the chain means
   double bnorm;
   double rr[2];  // r^dagger r, double-buffered by iteration parity
   double alpha;
@@ -110,6 +112,69 @@ __global__ __launch_bounds__(256) void k_center_e(int64_t n, const double *e,
                                                    const double *part, int64_t nparts,
                                                    double *u, double *part2, CGState *st) {
   k_center_e_body<C>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, n, e, part, nparts, u, part2, st);
+}
+
+// ---- error bar of the energy (chain means) -----------------------------------------
+// Samples are laid out [S sweeps, nch chains]. Block BX takes chains 64 BX .. 64 BX + 63:
+// thread t sums chain 64 BX + (t & 63) over the sweeps q = t / 64 (mod 4), four slices
+// combined in a fixed order; cm[c] = mean over the sweeps of Re E_loc; per-block partial
+// sums of the chain means follow.
+constexpr int kChainsPerBlock = 64;
+template <bool C>
+__device__ __forceinline__ void k_chain_mean_body(int BX, int64_t n, int64_t nch,
+                                                  const double *e, double *cm,
+                                                  double *cpart) {
+  __shared__ double lds[256];
+  __shared__ double sl[4][kChainsPerBlock];
+  const int64_t S = n / nch;
+  const int ch = threadIdx.x & 63, q0 = threadIdx.x >> 6;
+  const int64_t c = int64_t(BX) * kChainsPerBlock + ch;
+  double s0 = 0.0, s1 = 0.0;
+  if (c < nch) {
+    int64_t q = q0;
+    for (; q + 4 < S; q += 8) {
+      s0 += C ? e[2 * (q * nch + c)] : e[q * nch + c];
+      s1 += C ? e[2 * ((q + 4) * nch + c)] : e[(q + 4) * nch + c];
+    }
+    if (q < S) s0 += C ? e[2 * (q * nch + c)] : e[q * nch + c];
+  }
+  sl[q0][ch] = s0 + s1;
+  __syncthreads();
+  double m = 0.0;
+  if (q0 == 0 && c < nch) {
+    m = (((sl[0][ch] + sl[1][ch]) + sl[2][ch]) + sl[3][ch]) / double(S);
+    cm[c] = m;
+  }
+  m = block_reduce(m, lds);
+  if (threadIdx.x == 0) cpart[BX] = m;
+}
+
+template <bool C>
+__global__ __launch_bounds__(256) void k_chain_mean(int64_t n, int64_t nch, const double *e,
+                                                    double *cm, double *cpart) {
+  k_chain_mean_body<C>(blockIdx.x, n, nch, e, cm, cpart);
+}
+
+// per-block partial sums of (m_c - mean m)^2 (the mean from the partials, in every block)
+__device__ __forceinline__ void k_chain_dev_body(int BX, int64_t nch, const double *cm,
+                                                 const double *cpart, int64_t ncb,
+                                                 double *cpart2) {
+  __shared__ double lds[256];
+  const double mbar = block_sum(cpart, ncb, 1, lds) / double(nch);
+  const int64_t c = int64_t(BX) * 256 + threadIdx.x;
+  double d = 0.0;
+  if (c < nch) {
+    d = cm[c] - mbar;
+    d *= d;
+  }
+  d = block_reduce(d, lds);
+  if (threadIdx.x == 0) cpart2[BX] = d;
+}
+
+__global__ __launch_bounds__(256) void k_chain_dev(int64_t nch, const double *cm,
+                                                   const double *cpart, int64_t ncb,
+                                                   double *cpart2) {
+  k_chain_dev_body(blockIdx.x, nch, cm, cpart, ncb, cpart2);
 }
 
 __global__ void k_fill(int64_t count, double *x, double val) {
@@ -209,10 +274,14 @@ __global__ __launch_bounds__(256) void k_cg_init(int N, int M, int64_t n, const 
 }
 
 __device__ __forceinline__ void k_cg_start_body(int BX, int BY, int BZ, int GX, const double *dpart, int64_t nparts,
-                                                  double tol, int maxiter, CGState *st) {
+                                                  double tol, int maxiter, CGState *st,
+                                                  const double *cpart2, int64_t ncb2,
+                                                  int64_t nch) {
   __shared__ double lds[256];
   double rr = block_sum(dpart, nparts, 1, lds);
+  const double dev2 = block_sum(cpart2, ncb2, 1, lds);
   if (threadIdx.x == 0) {
+    st->err = sqrt(dev2 / double(nch - 1)) / sqrt(double(nch));
     st->rr[0] = rr;
     st->rr[1] = rr;
     st->bnorm = sqrt(rr);
@@ -227,8 +296,11 @@ __device__ __forceinline__ void k_cg_start_body(int BX, int BY, int BZ, int GX, 
 }
 
 __global__ __launch_bounds__(256) void k_cg_start(const double *dpart, int64_t nparts,
-                                                  double tol, int maxiter, CGState *st) {
-  k_cg_start_body(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, dpart, nparts, tol, maxiter, st);
+                                                  double tol, int maxiter, CGState *st,
+                                                  const double *cpart2, int64_t ncb2,
+                                                  int64_t nch) {
+  k_cg_start_body(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, dpart, nparts, tol, maxiter, st,
+                  cpart2, ncb2, nch);
 }
 
 // g = O^dagger y from the first-level sums, then
@@ -557,6 +629,11 @@ __global__ __launch_bounds__(kXrpThreads) void k_cg_xrp(int N, int M, const doub
   }
 }
 
+// whether the step's energy, variance and every CG scalar are finite
+__device__ __forceinline__ bool step_finite(const CGState *st) {
+  return !st->nonfinite && finite(st->E[0]) && finite(st->E[1]) && finite(st->var);
+}
+
 template <typename PT>
 __device__ __forceinline__ void k_update_body(int BX, int BY, int BZ, int GX, int64_t Pc, PT *params, const double *x, double lr) {
   for (int64_t k = BX * int64_t(blockDim.x) + threadIdx.x; k < Pc;
@@ -564,13 +641,36 @@ __device__ __forceinline__ void k_update_body(int BX, int BY, int BZ, int GX, in
     params[k] = PT(double(params[k]) - lr * x[k]);
 }
 
+// p <- p - lr x, only when the step is finite (decided on the device)
 template <typename PT>
-__global__ void k_update(int64_t Pc, PT *params, const double *x, double lr) {
+__global__ void k_update(int64_t Pc, PT *params, const double *x, double lr,
+                         const CGState *st) {
+  if (!step_finite(st)) return;
   k_update_body<PT>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, Pc, params, x, lr);
 }
 
+__device__ __host__ inline void fill_info(const CGState &h, nqs_sr_info *o) {
+  const bool nf = h.nonfinite || !isfinite(h.E[0]) || !isfinite(h.E[1]) || !isfinite(h.var);
+  o->cg_iters = h.iters;
+  o->converged = h.converged;
+  o->cg_resid = h.bnorm > 0 ? sqrt(h.rr[h.iters & 1]) / h.bnorm : 0.0;
+  o->energy_re = h.E[0];
+  o->energy_im = h.E[1];
+  o->variance = h.var;
+  o->force_norm = h.fnorm;
+  o->energy_err = h.err;
+  o->status = nf ? NQS_ENONFINITE : (h.converged ? NQS_OK : NQS_ENOTCONV);
+  o->reserved = 0;
+}
+
+// the step's information, written to device memory in stream order
+__global__ void k_sr_info(const CGState *st, nqs_sr_info *out) {
+  if (threadIdx.x == 0) fill_info(*st, out);
+}
+
 struct SRLayout {
-  size_t grad, y, ysum, u, e_part, e_part2, o1, g, F, x, r, p, Ap, dpart, rpart, state, total;
+  size_t grad, y, ysum, u, e_part, e_part2, cm, c_part, c_part2, o1, g, F, x, r, p, Ap, dpart,
+      rpart, state, total;
 };
 
 SRLayout sr_layout(const nqs_model *m, int64_t n) {
@@ -593,6 +693,9 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   L.u = take(size_t(n) * cs * 8);
   L.e_part = take(size_t(nb) * 16);
   L.e_part2 = take(size_t(nb) * 8);
+  L.cm = take(size_t(n) * 8);
+  L.c_part = take(size_t(cdiv(n, kChainsPerBlock)) * 8);
+  L.c_part2 = take(size_t(nb) * 8);
   L.o1 = take(size_t(P) * cs * 8);
   L.g = take(size_t(P) * cs * 8);
   L.F = take(size_t(P) * cs * 8);
@@ -643,10 +746,13 @@ inline unsigned grid_for(int64_t count) {
   return unsigned(b < 8192 ? (b > 0 ? b : 1) : 8192);
 }
 
+// async: queue cg_maxiter iteration slots and write the information to device memory
+// (info is then a device pointer); otherwise check convergence on the host between
+// chunks and fill the host struct info
 template <typename T, bool C>
 nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
-                   int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
-                   void *ws, nqs_sr_info *info, hipStream_t st) {
+                   int64_t n, int64_t nch, double lr, double diag_shift, double cg_tol,
+                   int cg_maxiter, void *ws, nqs_sr_info *info, bool async, hipStream_t st) {
   SRLayout L = sr_layout(m, n);
   char *b = (char *)ws;
   auto D = [&](size_t off) { return (double *)(b + off); };
@@ -674,6 +780,14 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   hipLaunchKernelGGL((k_center_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
                      (const double *)eloc, D(L.e_part), nb, D(L.u), D(L.e_part2), state);
   HIPTRY(hipGetLastError());
+  // chain means and their spread (error bar)
+  const int64_t ncb = cdiv(nch, kChainsPerBlock), ncb2 = cdiv(nch, 256);
+  hipLaunchKernelGGL((k_chain_mean<C>), dim3(unsigned(ncb)), dim3(256), 0, st, n, nch,
+                     (const double *)eloc, D(L.cm), D(L.c_part));
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL(k_chain_dev, dim3(unsigned(ncb2)), dim3(256), 0, st, nch, D(L.cm),
+                     D(L.c_part), ncb, D(L.c_part2));
+  HIPTRY(hipGetLastError());
   // tanh(theta) of every sample, kept for all products of this step
   HIPTRY(launch_theta_tanh(m, sigma, n, grad, true, st));
   // O^dagger 1 (centring of S v), then g = O^dagger u (force numerator)
@@ -688,22 +802,19 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
                      (T *)gb.vb, gb.va, D(L.dpart), state, split);
   HIPTRY(hipGetLastError());
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, st, D(L.dpart), pblocks, cg_tol,
-                     cg_maxiter, state);
+                     cg_maxiter, state, D(L.c_part2), ncb2, nch);
   HIPTRY(hipGetLastError());
 
   // Chunks of check_every iterations. The state after each chunk is copied to pinned host
   // memory behind the chunk, and the next chunk is queued before the host reads the copy,
   // so the device does not wait for the check; a chunk queued after convergence returns
   // at once in every kernel (the done flag).
-  if (!m->cg_host) HIPTRY(hipHostMalloc(&m->cg_host, 2 * sizeof(CGState), hipHostMallocDefault));
-  for (hipEvent_t &e : m->cg_ev)
-    if (!e) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  CGState *hslot = (CGState *)m->cg_host;
+  CGState *hslot = nullptr;
   CGState hs;
   const int check_every = 8;
   int launched = 0, queued = 0, checked = 0;
   const int *skip = &state->done;
-  auto enqueue = [&](int batch) -> nqs_status {
+  auto enqueue = [&](int batch, bool copy_back) -> nqs_status {
     // one CG iteration = the product's partial tiles, k_cg_apr, k_cg_xr, k_cg_p
     const int64_t ablocks = cdiv(elems, kAprElems);
     auto iterations = [&](int count, hipStream_t s2) -> hipError_t {
@@ -769,12 +880,46 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
     } else {
       HIPTRY(iterations(batch, st));
     }
+    if (!copy_back) return NQS_OK;
     const int slot = queued & 1;
     HIPTRY(hipMemcpyAsync(&hslot[slot], state, sizeof(CGState), hipMemcpyDeviceToHost, st));
     HIPTRY(hipEventRecord(m->cg_ev[slot], st));
     ++queued;
     return NQS_OK;
   };
+  auto launch_update = [&]() -> hipError_t {
+    if (use_double(m))
+      hipLaunchKernelGGL(k_update<double>, dim3(grid_for(Pc)), dim3(256), 0, st, Pc,
+                         (double *)params, (const double *)D(L.x), lr, (const CGState *)state);
+    else
+      hipLaunchKernelGGL(k_update<float>, dim3(grid_for(Pc)), dim3(256), 0, st, Pc,
+                         (float *)params, (const double *)D(L.x), lr, (const CGState *)state);
+    return hipGetLastError();
+  };
+  if (async) {
+    // every iteration slot is queued; the slots after the solve has finished return at
+    // once. Chunks replay the cached graph unless the caller is capturing the stream (the
+    // slots are then recorded into the caller's graph as plain launches).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPTRY(hipStreamIsCapturing(st, &cap));
+    const bool saved = m->cg_graphs;
+    if (cap != hipStreamCaptureStatusNone) m->cg_graphs = false;
+    nqs_status qs = NQS_OK;
+    for (int it = 0; it < cg_maxiter && qs == NQS_OK; it += check_every) {
+      const int batch = cg_maxiter - it < check_every ? cg_maxiter - it : check_every;
+      qs = enqueue(batch, false);
+    }
+    m->cg_graphs = saved;
+    if (qs != NQS_OK) return qs;
+    HIPTRY(launch_update());
+    hipLaunchKernelGGL(k_sr_info, dim3(1), dim3(64), 0, st, (const CGState *)state, info);
+    HIPTRY(hipGetLastError());
+    return NQS_OK;
+  }
+  if (!m->cg_host) HIPTRY(hipHostMalloc(&m->cg_host, 2 * sizeof(CGState), hipHostMallocDefault));
+  for (hipEvent_t &e : m->cg_ev)
+    if (!e) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hslot = (CGState *)m->cg_host;
   // the state before the first chunk (k_cg_start may already have finished the solve)
   HIPTRY(hipMemcpyAsync(&hs, state, sizeof(CGState), hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
@@ -782,7 +927,7 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   while (!done) {
     while (queued - checked < 2 && launched < cg_maxiter) {
       const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
-      const nqs_status qs = enqueue(batch);
+      const nqs_status qs = enqueue(batch, true);
       if (qs != NQS_OK) return qs;
       launched += batch;
     }
@@ -795,28 +940,12 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   }
   // chunks still queued return at once; the state no longer changes once done is set
   // (and the stream orders them before the update below)
-  const bool nonfinite = hs.nonfinite || !std::isfinite(hs.E[0]) || !std::isfinite(hs.var);
-  if (!nonfinite) {
-    if (use_double(m))
-      hipLaunchKernelGGL(k_update<double>, dim3(grid_for(Pc)), dim3(256), 0, st, Pc,
-                         (double *)params, (const double *)D(L.x), lr);
-    else
-      hipLaunchKernelGGL(k_update<float>, dim3(grid_for(Pc)), dim3(256), 0, st, Pc,
-                         (float *)params, (const double *)D(L.x), lr);
-    HIPTRY(hipGetLastError());
-  }
+  nqs_sr_info out;
+  fill_info(hs, &out);
+  if (out.status != NQS_ENONFINITE) HIPTRY(launch_update());
   HIPTRY(hipStreamSynchronize(st));
-  if (info) {
-    info->cg_iters = hs.iters;
-    info->converged = hs.converged;
-    info->cg_resid = hs.bnorm > 0 ? sqrt(hs.rr[hs.iters & 1]) / hs.bnorm : 0.0;
-    info->energy_re = hs.E[0];
-    info->energy_im = hs.E[1];
-    info->variance = hs.var;
-    info->force_norm = hs.fnorm;
-  }
-  if (nonfinite) return NQS_ENONFINITE;
-  return hs.converged ? NQS_OK : NQS_ENOTCONV;
+  if (info) *info = out;
+  return nqs_status(out.status);
 }
 
 template <bool C>
@@ -878,6 +1007,8 @@ template <typename T>
 struct BJob {
   int N, M;
   int64_t n, P, Pc, nb;
+  int64_t nch, ncb, ncb2;  // chains of the error bar, blocks of the chain-mean kernels
+  double *cm, *cpart, *cpart2;
   int pblocks, cblocks, colsP;
   int64_t elems;
   const double *e;
@@ -920,6 +1051,23 @@ __global__ __launch_bounds__(256) void kb_stats2(const BJob<T> *jobs, const int2
   }
 }
 template <typename T, bool C>
+__global__ __launch_bounds__(256) void kb_chain_mean(const BJob<T> *jobs, const int2 *map) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_chain_mean_body<C>(b.y, J.n, J.nch, J.e, J.cm, J.cpart);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void kb_chain_dev(const BJob<T> *jobs, const int2 *map) {
+  const int2 b = map[blockIdx.x];
+  const BJob<T> J = jobs[b.x];
+  k_chain_dev_body(b.y, J.nch, J.cm, J.cpart, J.ncb, J.cpart2);
+}
+template <typename T>
+__global__ void kb_info(const BJob<T> *jobs, int K, nqs_sr_info *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) fill_info(*jobs[k].st, out + k);
+}
+template <typename T, bool C>
 __global__ __launch_bounds__(256) void kb_cg_init(const BJob<T> *jobs, const int2 *map) {
   const int2 b = map[blockIdx.x];
   const BJob<T> J = jobs[b.x];
@@ -930,7 +1078,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_cg_start(const BJob<T> *jobs, double tol,
                                                    int maxiter) {
   const BJob<T> J = jobs[blockIdx.x];
-  k_cg_start_body(0, 0, 0, 1, J.dpart, J.pblocks, tol, maxiter, J.st);
+  k_cg_start_body(0, 0, 0, 1, J.dpart, J.pblocks, tol, maxiter, J.st, J.cpart2, J.ncb2, J.nch);
 }
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void kb_cg_ap(const BJob<T> *jobs, const int2 *map,
@@ -962,14 +1110,13 @@ __global__ __launch_bounds__(256) void kb_update(const BJob<T> *jobs, const int2
                                                  double lr) {
   const int2 b = map[blockIdx.x];
   const BJob<T> J = jobs[b.x];
-  const CGState *st = J.st;
-  if (st->nonfinite || !finite(st->E[0]) || !finite(st->E[1]) || !finite(st->var)) return;
+  if (!step_finite(J.st)) return;
   k_update_body<PT>(b.y, 0, 0, J.cblocks, J.Pc, (PT *)J.params, J.x, lr);
 }
 
 struct BLayout {
-  size_t Tm, Vt, vb, va, ypart, part, out1, y, ysum, u, ones, epart, epart2, o1, g, F, x, r, p, Ap,
-      dpart, rpart, state, total;
+  size_t Tm, Vt, vb, va, ypart, part, out1, y, ysum, u, ones, epart, epart2, cm, cpart, cpart2,
+      o1, g, F, x, r, p, Ap, dpart, rpart, state, total;
 };
 
 BLayout batch_layout(const nqs_model *m, int64_t n) {
@@ -999,6 +1146,9 @@ BLayout batch_layout(const nqs_model *m, int64_t n) {
   L.ones = take(size_t(n) * cs * 8);
   L.epart = take(size_t(nb) * 16);
   L.epart2 = take(size_t(nb) * 8);
+  L.cm = take(size_t(n) * 8);
+  L.cpart = take(size_t(cdiv(n, kChainsPerBlock)) * 8);
+  L.cpart2 = take(size_t(nb) * 8);
   L.o1 = take(size_t(P) * cs * 8);
   L.g = take(size_t(P) * cs * 8);
   L.F = take(size_t(P) * cs * 8);
@@ -1014,21 +1164,23 @@ BLayout batch_layout(const nqs_model *m, int64_t n) {
 }
 
 // job-table slots of the batch handle used by the SR step
-enum { kSlotJobs = 0, kSlotStats, kSlotP, kSlotC, kSlotStart, kSlotStates = 6, kSlotTanh = 10,
+enum { kSlotJobs = 0, kSlotStats, kSlotP, kSlotC, kSlotStart, kSlotChains = 5, kSlotStates = 6,
+       kSlotChainDev = 7, kSlotTanh = 10,
        kSlotJvp = 12,
        kSlotVjp1 = 16, kSlotVjpU = 20, kSlotVjpY = 24 };
 
 template <typename T, bool C>
 nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, const void *eloc,
-                         const int64_t *n_samples, double lr, double diag_shift, double cg_tol,
-                         int cg_maxiter, void *ws, nqs_sr_info *info, hipStream_t st) {
+                         const int64_t *n_samples, const int32_t *n_chains, double lr,
+                         double diag_shift, double cg_tol, int cg_maxiter, void *ws,
+                         nqs_sr_info *info, bool async, hipStream_t st) {
   typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type PT;
   const int K = b->K;
   const int cs = C ? 2 : 1;
   std::vector<BJob<T>> jobs(K);
   std::vector<BatchGradItem> gi(K);
   std::vector<const void *> pk(K);
-  std::vector<int2> map_s, map_p, map_c;
+  std::vector<int2> map_s, map_p, map_c, map_m, map_d;
   std::vector<CGState *> states(K);
   size_t wo = 0, po = 0, so = 0, eo = 0;
   for (int k = 0; k < K; ++k) {
@@ -1038,6 +1190,7 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
     char *w = (char *)ws + wo;
     const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
     BJob<T> &J = jobs[k];
+    memset(static_cast<void *>(&J), 0, sizeof(J));  // compared byte by byte with the last upload
     J.N = m->N;
     J.M = m->M;
     J.n = n;
@@ -1046,6 +1199,12 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
     J.nb = cdiv(n, 256);
     J.pblocks = int(cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096);
     J.cblocks = int(cdiv(P * cs, 256) < 4096 ? cdiv(P * cs, 256) : 4096);
+    J.nch = (n_chains && n_chains[k] > 0) ? n_chains[k] : n;
+    J.ncb = cdiv(J.nch, kChainsPerBlock);
+    J.ncb2 = cdiv(J.nch, 256);
+    J.cm = (double *)(w + L.cm);
+    J.cpart = (double *)(w + L.cpart);
+    J.cpart2 = (double *)(w + L.cpart2);
     const BatchGradSizes z = batch_grad_sizes(m, n);
     J.colsP = z.colsP;
     J.elems = z.elems;
@@ -1091,6 +1250,8 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
     for (int x = 0; x < int(J.nb); ++x) map_s.push_back(make_int2(k, x));
     for (int x = 0; x < J.pblocks; ++x) map_p.push_back(make_int2(k, x));
     for (int x = 0; x < J.cblocks; ++x) map_c.push_back(make_int2(k, x));
+    for (int x = 0; x < int(J.ncb); ++x) map_m.push_back(make_int2(k, x));
+    for (int x = 0; x < int(J.ncb2); ++x) map_d.push_back(make_int2(k, x));
     wo += L.total;
     po += size_t(P) * cs * (std::is_same<T, double>::value ? 8 : 4);
     so += size_t(n) * m->N;
@@ -1105,7 +1266,10 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
   BTRY(b->buf(kSlotStats).upload(map_s.data(), map_s.size() * sizeof(int2), st));
   BTRY(b->buf(kSlotP).upload(map_p.data(), map_p.size() * sizeof(int2), st));
   BTRY(b->buf(kSlotC).upload(map_c.data(), map_c.size() * sizeof(int2), st));
-  if (!b->buf(kSlotJobs).d || !b->buf(kSlotStats).d || !b->buf(kSlotP).d || !b->buf(kSlotC).d)
+  BTRY(b->buf(kSlotChains).upload(map_m.data(), map_m.size() * sizeof(int2), st));
+  BTRY(b->buf(kSlotChainDev).upload(map_d.data(), map_d.size() * sizeof(int2), st));
+  if (!b->buf(kSlotJobs).d || !b->buf(kSlotStats).d || !b->buf(kSlotP).d || !b->buf(kSlotC).d ||
+      !b->buf(kSlotChains).d || !b->buf(kSlotChainDev).d)
     return NQS_EDEVICE;
   const BJob<T> *dj = (const BJob<T> *)b->buf(kSlotJobs).d;
   const int2 *ms = (const int2 *)b->buf(kSlotStats).d;
@@ -1116,6 +1280,12 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
   hipLaunchKernelGGL((kb_stats1<T, C>), dim3(unsigned(map_s.size())), dim3(256), 0, st, dj, ms);
   BTRY(hipGetLastError());
   hipLaunchKernelGGL((kb_stats2<T, C>), dim3(unsigned(map_s.size())), dim3(256), 0, st, dj, ms);
+  BTRY(hipGetLastError());
+  hipLaunchKernelGGL((kb_chain_mean<T, C>), dim3(unsigned(map_m.size())), dim3(256), 0, st, dj,
+                     (const int2 *)b->buf(kSlotChains).d);
+  BTRY(hipGetLastError());
+  hipLaunchKernelGGL((kb_chain_dev<T>), dim3(unsigned(map_d.size())), dim3(256), 0, st, dj,
+                     (const int2 *)b->buf(kSlotChainDev).d);
   BTRY(hipGetLastError());
   BTRY(launch_theta_tanh_batch(b, gi, kSlotTanh, st));
   // O^dagger 1 and the force numerator g = O^dagger (E - E)
@@ -1139,6 +1309,30 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
     gi[k].u = gi[k].y;
     gi[k].out = nullptr;
     gi[k].skip = &states[k]->done;
+  }
+  auto iteration = [&](int parity) -> hipError_t {
+    hipError_t e2 = launch_jvp_batch(b, gi, kSlotJvp, st);
+    if (e2 == hipSuccess) e2 = launch_vjp_batch(b, gi, false, kSlotVjpY, st);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL((kb_cg_ap<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj, mp,
+                       diag_shift);
+    if ((e2 = hipGetLastError()) != hipSuccess) return e2;
+    hipLaunchKernelGGL((kb_cg_xr<T>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj, mc,
+                       parity);
+    if ((e2 = hipGetLastError()) != hipSuccess) return e2;
+    hipLaunchKernelGGL((kb_cg_p<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj, mp,
+                       parity, cg_tol, cg_maxiter);
+    return hipGetLastError();
+  };
+  if (async) {
+    // every iteration slot is queued; finished models return at once in every kernel
+    for (int it = 0; it < cg_maxiter; ++it) BTRY(iteration(it & 1));
+    hipLaunchKernelGGL((kb_update<T, PT>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj,
+                       mc, lr);
+    BTRY(hipGetLastError());
+    hipLaunchKernelGGL((kb_info<T>), dim3(unsigned((K + 63) / 64)), dim3(64), 0, st, dj, K, info);
+    BTRY(hipGetLastError());
+    return NQS_OK;
   }
   std::vector<CGState> hs(K);
   // every model's solver state is gathered into one device array and read in one copy
@@ -1180,20 +1374,7 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
   while (!done) {
     while (queued - checked < 2 && launched < cg_maxiter) {
       const int batch = cg_maxiter - launched < check_every ? cg_maxiter - launched : check_every;
-      for (int q = 0; q < batch; ++q, ++launched) {
-        const int parity = launched & 1;
-        BTRY(launch_jvp_batch(b, gi, kSlotJvp, st));
-        BTRY(launch_vjp_batch(b, gi, false, kSlotVjpY, st));
-        hipLaunchKernelGGL((kb_cg_ap<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj,
-                           mp, diag_shift);
-        BTRY(hipGetLastError());
-        hipLaunchKernelGGL((kb_cg_xr<T>), dim3(unsigned(map_c.size())), dim3(256), 0, st, dj,
-                           mc, parity);
-        BTRY(hipGetLastError());
-        hipLaunchKernelGGL((kb_cg_p<T, C>), dim3(unsigned(map_p.size())), dim3(256), 0, st, dj,
-                           mp, parity, cg_tol, cg_maxiter);
-        BTRY(hipGetLastError());
-      }
+      for (int q = 0; q < batch; ++q, ++launched) BTRY(iteration(launched & 1));
       const int slot = queued & 1;
       BTRY(gather(hslot + size_t(slot) * K));
       BTRY(hipEventRecord(b->cg_ev[slot], st));
@@ -1215,19 +1396,11 @@ nqs_status batch_sr_impl(nqs_batch *b, void *params, const int8_t *samples, cons
 #undef BTRY
   bool any_nonfinite = false, all_conv = true;
   for (int k = 0; k < K; ++k) {
-    const CGState &h = hs[k];
-    const bool nf = h.nonfinite || !std::isfinite(h.E[0]) || !std::isfinite(h.var);
-    any_nonfinite = any_nonfinite || nf;
-    all_conv = all_conv && h.converged;
-    if (info) {
-      info[k].cg_iters = h.iters;
-      info[k].converged = h.converged;
-      info[k].cg_resid = h.bnorm > 0 ? sqrt(h.rr[h.iters & 1]) / h.bnorm : 0.0;
-      info[k].energy_re = h.E[0];
-      info[k].energy_im = h.E[1];
-      info[k].variance = h.var;
-      info[k].force_norm = h.fnorm;
-    }
+    nqs_sr_info o;
+    fill_info(hs[k], &o);
+    any_nonfinite = any_nonfinite || o.status == NQS_ENONFINITE;
+    all_conv = all_conv && o.converged;
+    if (info) info[k] = o;
   }
   if (any_nonfinite) return NQS_ENONFINITE;
   return all_conv ? NQS_OK : NQS_ENOTCONV;
@@ -1276,7 +1449,7 @@ nqs_status autotune_impl(nqs_model *m, const void *params, const int8_t *sigma, 
   hipEvent_t e0, e1;
   HIPTRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return NQS_EDEVICE;
   }
   double us[NQS_TUNE_MAX] = {0, 0, 0, 0};
@@ -1297,8 +1470,8 @@ nqs_status autotune_impl(nqs_model *m, const void *params, const int8_t *sigma, 
     us[c] = 1e3 * double(ms) / reps;
     if (us[c] < us[best]) best = c;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   m->sv_pairs = s == NQS_OK ? cand[best] : keep;
   if (rep) {
     rep->n_candidates = nc;
@@ -1312,11 +1485,14 @@ nqs_status autotune_impl(nqs_model *m, const void *params, const int8_t *sigma, 
 }
 
 nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
-                        int64_t n, double lr, double diag_shift, double cg_tol, int cg_maxiter,
-                        void *ws, size_t ws_bytes, nqs_sr_info *info, hipStream_t st) {
+                        int64_t n, int64_t n_chains, double lr, double diag_shift, double cg_tol,
+                        int cg_maxiter, void *ws, size_t ws_bytes, nqs_sr_info *info, bool async,
+                        hipStream_t st) {
   if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
-#define NQS_SR(T, C) \
-  sr_impl<T, C>(m, params, sigma, eloc, n, lr, diag_shift, cg_tol, cg_maxiter, ws, info, st)
+  const int64_t nch = n_chains > 0 ? n_chains : n;
+#define NQS_SR(T, C)                                                                          \
+  sr_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol, cg_maxiter, ws, info, \
+                async, st)
   if (use_double(m)) return m->is_complex ? NQS_SR(double, true) : NQS_SR(double, false);
   return m->is_complex ? NQS_SR(float, true) : NQS_SR(float, false);
 #undef NQS_SR
@@ -1329,18 +1505,16 @@ size_t batch_sr_workspace_bytes(nqs_batch *b, const int64_t *n_samples) {
 }
 
 nqs_status batch_sr_step_impl(nqs_batch *b, void *params, const int8_t *samples,
-                              const void *eloc, const int64_t *n_samples, double lr,
-                              double diag_shift, double cg_tol, int cg_maxiter, void *ws,
-                              size_t ws_bytes, nqs_sr_info *info, hipStream_t st) {
+                              const void *eloc, const int64_t *n_samples, const int32_t *n_chains,
+                              double lr, double diag_shift, double cg_tol, int cg_maxiter,
+                              void *ws, size_t ws_bytes, nqs_sr_info *info, bool async,
+                              hipStream_t st) {
   if (ws_bytes < batch_sr_workspace_bytes(b, n_samples)) return NQS_ENOMEM;
   const nqs_model *m = b->models[0];
-  if (use_double(m))
-    return m->is_complex ? batch_sr_impl<double, true>(b, params, samples, eloc, n_samples, lr,
-                                                       diag_shift, cg_tol, cg_maxiter, ws, info, st)
-                         : batch_sr_impl<double, false>(b, params, samples, eloc, n_samples, lr,
-                                                        diag_shift, cg_tol, cg_maxiter, ws, info, st);
-  return m->is_complex ? batch_sr_impl<float, true>(b, params, samples, eloc, n_samples, lr,
-                                                    diag_shift, cg_tol, cg_maxiter, ws, info, st)
-                       : batch_sr_impl<float, false>(b, params, samples, eloc, n_samples, lr,
-                                                     diag_shift, cg_tol, cg_maxiter, ws, info, st);
+#define NQS_BSR(T, C)                                                                    \
+  batch_sr_impl<T, C>(b, params, samples, eloc, n_samples, n_chains, lr, diag_shift, cg_tol, \
+                      cg_maxiter, ws, info, async, st)
+  if (use_double(m)) return m->is_complex ? NQS_BSR(double, true) : NQS_BSR(double, false);
+  return m->is_complex ? NQS_BSR(float, true) : NQS_BSR(float, false);
+#undef NQS_BSR
 }

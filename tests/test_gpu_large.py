@@ -121,3 +121,52 @@ def test_jacobian_products_many_sites(lib, name, n):
     t = cases.tol(name)
     assert np.abs(jvp.cpu().numpy() - ej).max() <= t * np.abs(ej).max()
     assert np.abs(vjp.cpu().numpy() - ev).max() <= t * np.abs(ev).max()
+
+
+def _jvp_rows(pe, s, v, N, M, rt, chunk=1024):
+    """O v for many samples without forming O: (O v)_s = sum_i va_i s_i +
+    sum_j t_sj (vb_j + sum_i vW_ji s_i), t = tanh theta (rounded by rt when given)."""
+    va, vb, vW = v[:N], v[N:N + M], v[N + M:].reshape(M, N)
+    out = []
+    for i in range(0, len(s), chunk):
+        sc = s[i:i + chunk].astype(np.float64)
+        t = np.tanh(orbm.theta(pe, sc, N, M))
+        if rt is not None:
+            t = rt(t)
+        out.append(sc @ va + np.sum(t * (vb[None, :] + sc @ vW.T), axis=1))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_large_sv_and_vjp_at_workload_size(lib, name):
+    """The 10x10 J1-J2 and 16x16 Heisenberg lattices at their workloads' 8192 samples per
+    iteration (the same kernels, splits and reduction counts as the benchmark): every O v,
+    and selected entries of O^dagger u and of S v, each from its own oracle column."""
+    m, om = cases.build(lib, name)
+    N, M = om.n_sites, om.n_hidden
+    p = cases.params(name, theta=0.3, seed=87)
+    pe = cases.oracle_params(name, p)
+    rt = cases.round_tanh(name)
+    n = 8192
+    s = cases.configs(name, n, seed=24)
+    rng = np.random.default_rng(25)
+    P = m.n_params
+    u = rng.normal(size=n) + 1j * rng.normal(size=n)
+    v = rng.normal(size=P) + 1j * rng.normal(size=P)
+    # the column-free product equals the oracle's O v on a few rows
+    assert np.allclose(_jvp_rows(pe, s[:8], v, N, M, rt), orbm.jvp(pe, s[:8], v, N, M, rt),
+                       rtol=1e-12, atol=1e-12)
+    vjp, jvp = m.log_psi_grad(to_dev(p), to_dev(s), u=to_dev(u), v=to_dev(v))
+    ej = _jvp_rows(pe, s, v, N, M, rt)
+    ks = np.unique(np.concatenate([[0, N - 1, N, N + M - 1, N + M, P - 1],
+                                   rng.integers(0, P, 40)]))
+    ev = orbm.vjp_entries(pe, s, u, ks, N, M, rt)
+    slack = 2e-3 if rt is not None else 0.0   # bfloat16 rounding ties of tanh(theta)
+    t = cases.tol(name) + slack
+    assert np.abs(jvp.cpu().numpy() - ej).max() <= t * np.abs(ej).max()
+    assert np.abs(vjp.cpu().numpy()[ks] - ev).max() <= t * np.abs(ev).max()
+    ws = m.sr_prepare(to_dev(p), to_dev(s))
+    got = m.sr_matvec(to_dev(s), ws, to_dev(v), diag_shift=0.01).cpu().numpy()
+    exp = orbm.vjp_entries(pe, s, ej - ej.mean(), ks, N, M, rt) / n + 0.01 * v[ks]
+    scale = np.abs(orbm.vjp_entries(pe, s, ej, ks, N, M, rt)).max() / n
+    assert np.abs(got[ks] - exp).max() <= t * scale
