@@ -187,6 +187,21 @@ nqs_status nqs_log_psi_grad(nqs_model *model, const void *params, const int8_t *
                             int64_t n, const void *u, void *vjp, const void *v, void *jvp,
                             void *stream);
 
+/* nqs_log_psi_grad for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation): the same products,
+ * arguments and results (bit for bit), with the call's scratch (tanh(theta) rows,
+ * direction tables, partial tiles) in one fixed 64 MiB array per device that the library
+ * holds for the life of the process, instead of the model's grow-only buffer. The call
+ * allocates and frees nothing and never synchronises. Returns NQS_ENOMEM, before any
+ * launch, when the scratch these n samples need exceeds 64 MiB (about 19 MB of partial
+ * tiles plus 680 bytes per sample for a complex FP32 model with N = 40, M = 80: some
+ * 70,000 samples); the first call on a device looks up the array's address there. Every call on one device shares that
+ * device's array, which keeps the last call's contents: calls that overlap on one device
+ * (other streams or threads) race and must be ordered by the caller. */
+nqs_status nqs_log_psi_grad_noalloc(nqs_model *model, const void *params, const int8_t *sigma,
+                                    int64_t n, const void *u, void *vjp, const void *v,
+                                    void *jvp, void *stream);
+
 /* Device workspace (bytes) needed by nqs_sr_step for n samples. */
 size_t nqs_sr_workspace_bytes(nqs_model *model, int64_t n);
 

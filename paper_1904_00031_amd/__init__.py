@@ -95,6 +95,7 @@ def load(path=LIB_PATH):
         "nqs_log_psi": (i32, [vp, vp, vp, i64, vp, vp]),
         "nqs_local_energy": (i32, [vp, vp, vp, i64, vp, vp]),
         "nqs_log_psi_grad": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
+        "nqs_log_psi_grad_noalloc": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
         "nqs_sr_workspace_bytes": (ctypes.c_size_t, [vp, i64]),
         "nqs_sr_step": (i32, [vp, vp, vp, vp, i64, i32, f64, f64, f64, i32, vp, ctypes.c_size_t,
                               ctypes.POINTER(SRInfo), vp]),
@@ -128,7 +129,7 @@ def load(path=LIB_PATH):
 def exported_symbols():
     return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
             "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
-            "nqs_log_psi_grad", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_step_async",
+            "nqs_log_psi_grad", "nqs_log_psi_grad_noalloc", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_step_async",
             "nqs_sr_prepare",
             "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_set_cg_graphs",
             "nqs_batch_create",
@@ -289,12 +290,16 @@ class Model:
                "nqs_local_energy")
         return out
 
-    def log_psi_grad(self, params, sigma, u=None, v=None, vjp=None, jvp=None):
-        """vjp = O^dagger u (length P), jvp = O v (length n)."""
+    def log_psi_grad(self, params, sigma, u=None, v=None, vjp=None, jvp=None, noalloc=False):
+        """vjp = O^dagger u (length P), jvp = O v (length n). noalloc: through
+        nqs_log_psi_grad_noalloc (the library's fixed per-device scratch, no allocation);
+        outputs must then be given."""
         import torch
         _need(params, "params", self.param_dtype, (self.n_params,))
         n = sigma.shape[0]
         _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        if noalloc and ((u is not None and vjp is None) or (v is not None and jvp is None)):
+            raise ValueError("noalloc: pass the output tensors (vjp, jvp)")
         if u is not None:
             _need(u, "u", self.value_dtype, (n,))
             if vjp is None:
@@ -305,12 +310,13 @@ class Model:
             if jvp is None:
                 jvp = torch.empty(n, dtype=self.value_dtype, device=sigma.device)
             _need(jvp, "jvp", self.value_dtype, (n,))
-        _check(_lib.nqs_log_psi_grad(self._h, _ptr(params), _ptr(sigma), n,
-                                     _ptr(u) if u is not None else None,
-                                     _ptr(vjp) if u is not None else None,
-                                     _ptr(v) if v is not None else None,
-                                     _ptr(jvp) if v is not None else None, _stream()),
-               "nqs_log_psi_grad")
+        fn = _lib.nqs_log_psi_grad_noalloc if noalloc else _lib.nqs_log_psi_grad
+        _check(fn(self._h, _ptr(params), _ptr(sigma), n,
+                  _ptr(u) if u is not None else None,
+                  _ptr(vjp) if u is not None else None,
+                  _ptr(v) if v is not None else None,
+                  _ptr(jvp) if v is not None else None, _stream()),
+               "nqs_log_psi_grad_noalloc" if noalloc else "nqs_log_psi_grad")
         return vjp, jvp
 
     def sr_workspace_bytes(self, n):

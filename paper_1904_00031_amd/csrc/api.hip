@@ -2,12 +2,38 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "internal.hpp"
 
+// Scratch of nqs_log_psi_grad_noalloc: one fixed array per device, held for the life of
+// the process. Host code never passes this name to a kernel (on the host it is only a
+// stand-in for the symbol); it uses the device address returned by hipGetSymbolAddress,
+// looked up once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (resolved on the first call there)
+nqs_status noalloc_scratch(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return NQS_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return NQS_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NQS_OK;
+}
 
 __global__ void k_zero(int64_t count, double *x) {
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < count;
@@ -350,6 +376,20 @@ nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigm
   s = ensure_scratch(m, grad_scratch_bytes(m, n));
   if (s != NQS_OK) return s;
   return log_psi_grad_with(m, params, sigma, n, u, vjp, v, jvp, m->d_scratch, st);
+}
+
+nqs_status nqs_log_psi_grad_noalloc(nqs_model *m, const void *params, const int8_t *sigma,
+                                    int64_t n, const void *u, void *vjp, const void *v,
+                                    void *jvp, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  bool done;
+  nqs_status s = log_psi_grad_args(m, params, sigma, n, u, vjp, v, jvp, st, &done);
+  if (done) return s;
+  if (grad_scratch_bytes(m, n) > kNoAllocScratchBytes) return NQS_ENOMEM;
+  void *scr = nullptr;
+  s = noalloc_scratch(&scr);
+  if (s != NQS_OK) return s;
+  return log_psi_grad_with(m, params, sigma, n, u, vjp, v, jvp, scr, st);
 }
 
 
