@@ -4,19 +4,25 @@ One step = one full pass of the hot path over one batch of synthetic input:
   Metropolis sampling (sweeps with cached hidden angles) + local energies of every
   sample + SR step (log-derivative products O v / O^dagger u inside an FP64 CG solve of
   (S + lambda I) x = F, then the parameter update).
-Default workload: 1D spin-1/2 Heisenberg ring, N = 40, periodic, zero magnetisation via
-nearest-neighbour exchange moves, Marshall-rotated; complex RBM with FP32 contractions,
-alpha = 2 (80 hidden units), parameters N(0, 0.01^2) from seed 1234; 1024 chains x 200
-sweeps = 204,800 samples per step; SR diagonal shift 0.01, learning rate 0.01, CG
-tolerance 1e-8.
 
-Prints one JSON line. value = samples per second of whole steps (sampling + local
-energies + SR). Extra fields: the sampling-only rate, SR iterations per second, CG
-iterations, the roofline of the dominant kernel, and the FP64 oracle timed on the host.
+Headline workload (the largest single-GPU configuration): 2D Heisenberg antiferromagnet
+on the 16 x 16 periodic square lattice, zero magnetisation via nearest-neighbour exchange
+moves, Marshall-rotated; complex RBM with alpha = 8 (2048 hidden units) in the BF16 form
+(weights rounded to bfloat16, float arithmetic, bfloat16 tanh(theta) in the Jacobian
+contractions) with FP64 CG; parameters N(0, 0.01^2) from seed 1234; 8192 chains x 1 sweep
+= 8192 samples per step; SR shift 0.01, lr 0.01, CG tolerance 1e-8, at most 500 products.
+
+Prints one JSON line. value = samples per second of whole steps. Extra fields: phase
+times, the roofline of the step's dominant kernel (measured live with HIP events on the
+launch stream), the other workloads of the benchmark family (10-site TFIM, 40-site
+Heisenberg ring, 10x10 J1-J2 in FP32 and BF16, and the batch of 64 TFIM rings replayed
+from a captured graph) with their own rooflines, the FP64 / FP32 / BF16 forms of the
+40-site ring compared at a fixed energy error, and the FP64 oracle timed on the host.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -25,16 +31,27 @@ sys.path.insert(0, ROOT)
 
 import numpy as np
 
+# MI355X peaks (AMD's published dense figures)
 PEAK_FP32_VALU = 157.3e12
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12
 
+HEADLINE = "heis16x16_cplx_bf16_alpha8"
+METRIC = "samples/s (sweep+E_loc+O_k) and SR iters/s, BF16/FP32 vs FP64 at fixed dE"
+
 WORKLOADS = {
+    # 16x16 Heisenberg, complex RBM alpha = 8 (2048 hidden units), BF16 form, FP64 CG
+    "heis16x16_cplx_bf16_alpha8": dict(L=16, ndim=2, diag=False, ham=1, J=(1.0, 0.0), h=0.0,
+                                       marshall=True, move=1, cplx=True, prec=2, alpha=8,
+                                       chains=8192, sweeps=1, lr=0.01, shift=0.01,
+                                       cg_tol=1e-8, cg_maxiter=500),
+    # 1D Heisenberg ring, N = 40, complex FP32 RBM alpha = 2: 1024 chains x 200 sweeps
     "heisenberg1d_n40_cplx_fp32_alpha2": dict(L=40, ndim=1, diag=False, ham=1, J=(1.0, 0.0), h=0.0,
                                              marshall=True, move=1, cplx=True, prec=1, alpha=2,
                                              chains=1024, sweeps=200, lr=0.01, shift=0.01,
                                              cg_tol=1e-8, cg_maxiter=2000),
+    # 1D TFIM ring, N = 10, real FP64 RBM alpha = 1: 16 chains x 1000 sweeps
     "tfim1d_n10_real_fp64_alpha1": dict(L=10, ndim=1, diag=False, ham=0, J=(1.0, 0.0), h=1.0,
                                        marshall=False, move=0, cplx=False, prec=0, alpha=1,
                                        chains=16, sweeps=1000, lr=0.01, shift=0.01,
@@ -49,51 +66,65 @@ WORKLOADS = {
                                         marshall=True, move=1, cplx=True, prec=2, alpha=4,
                                         chains=4096, sweeps=2, lr=0.01, shift=0.01,
                                         cg_tol=1e-8, cg_maxiter=500),
-    # 16x16 Heisenberg, complex RBM alpha = 8 (2048 hidden units), BF16 form:
-    # 8192 chains x 1 sweep = 8192 samples per step
-    "heis16x16_cplx_bf16_alpha8": dict(L=16, ndim=2, diag=False, ham=1, J=(1.0, 0.0), h=0.0,
-                                       marshall=True, move=1, cplx=True, prec=2, alpha=8,
-                                       chains=8192, sweeps=1, lr=0.01, shift=0.01,
-                                       cg_tol=1e-8, cg_maxiter=500),
+}
+EXTRA_SINGLE = ["heisenberg1d_n40_cplx_fp32_alpha2", "tfim1d_n10_real_fp64_alpha1",
+                "j1j2_10x10_cplx_fp32_alpha4", "j1j2_10x10_cplx_bf16_alpha4"]
+
+# batches of independent models: 64 periodic TFIM rings, N uniform in [16, 128], h uniform in
+# [0.5, 1.5] (numpy PCG64, seed 1234), real FP32 RBM alpha = 2 each, 256 chains x 4 sweeps
+# per ring per step; the step (sampling + stream-ordered SR with at most 100 CG slots) is
+# captured into one graph and replayed
+BATCH_WORKLOADS = {
+    "tfim1d_batch64_n16to128_real_fp32_alpha2": dict(K=64, Nmin=16, Nmax=128, hmin=0.5, hmax=1.5,
+                                                     alpha=2, chains=256, sweeps=4, prec=1,
+                                                     lr=0.01, shift=0.01, cg_tol=1e-8,
+                                                     cg_maxiter=100),
 }
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "reference_energies.txt")
 
-def cpu_baseline(w, N, M, seconds=15.0):
-    """The FP64 oracle (plain numpy, unmodified) on a bounded sample of the same workload:
-    a subset of the chains for a few sweeps, their local energies and one SR step."""
-    import synth
-    from oracle import hamiltonian as oh, lattice as ol, sampler as osamp, sr as osr
+
+def golden(name):
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#") and line.split()[0] == name:
+                return float(line.split()[1])
+    raise KeyError(name)
+
+
+# exact ground energies of the workloads (Pauli units): Bethe ansatz for the 40-site
+# Heisenberg ring, free-fermion closed form for the 10-site TFIM ring
+E_REF = {"heisenberg1d_n40_cplx_fp32_alpha2": "heis_ring_n40",
+         "tfim1d_n10_real_fp64_alpha1": "tfim_n10_h1"}
+FORM_NAMES = {0: "fp64", 1: "fp32", 2: "bf16"}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def host_info():
+    model = platform.processor() or ""
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:
-        cores = 1
-    ob, osub = ol.hypercube(w["L"], w["ndim"], with_diagonals=w["diag"])
-    om = oh.Model(N, M, ob, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
-                  sublattice=osub, move=w["move"], is_complex=w["cplx"])
-    p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
-    P = N + M + N * M
-    # the oracle's SR forms S explicitly ([P, P]); beyond a few thousand parameters that
-    # does not fit, and the baseline then covers sampling and local energies only
-    with_sr = P <= 5000
-    chains, sweeps = (64, 4) if N <= 64 else (16, 1)
-    t0 = time.perf_counter()
-    init = osamp.init_chains(om, chains, seed=1234)
-    total_samples = 0
-    while True:
-        smp, init, _ = osamp.sample(om, p, init, sweeps, 0, seed=1234, counter=total_samples)
-        flat = smp.reshape(-1, N)
-        el = oh.local_energy(om, p, flat)
-        if with_sr:
-            osr.sr_step(om, p, flat, el, w["lr"], w["shift"], w["cg_tol"], w["cg_maxiter"])
-        total_samples += flat.shape[0]
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    what = "local energies and one SR step" if with_sr else "local energies (no SR: the dense S of %d parameters does not fit)" % P
-    return {"value": total_samples / dt, "unit": "samples/s", "cores": int(cores), "kind": "oracle",
-            "sample": "%d chains x %d sweeps per pass, %s per pass, %d passes in %.1f s"
-                      % (chains, sweeps, what, total_samples // (chains * sweeps), dt)}
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return nproc, model
+
+
+# ---- algorithmic work ------------------------------------------------------------------
+def sweep_terms_flops(cplx):
+    """Flops of one ratio term cosh(d) + tanh(theta) sinh(d) and its share of |ratio|^2:
+    complex t S (6) and C - s t S (2), |term|^2 (3), product (1) = 12; real: 4."""
+    return 12.0 if cplx else 4.0
 
 
 def sv_flops(n, N, M, cplx):
@@ -131,9 +162,8 @@ def recorded_traffic(kernel, workload):
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
     try:
-        srcs = fields["sources"].split()
         h = hashlib.sha256()
-        for name in srcs:
+        for name in fields["sources"].split():
             with open(os.path.join(ROOT, name), "rb") as fh:
                 h.update(fh.read())
         if h.hexdigest() != fields["sources_sha256"]:
@@ -154,17 +184,175 @@ def copy_probe(torch, dev, mib=1024, reps=3):
     log("copy probe: %d copies of %d MiB" % (reps, mib))
 
 
-# batches of independent models: 64 periodic TFIM rings, N uniform in [16, 128], h uniform in
-# [0.5, 1.5] (numpy PCG64, seed 1234), real FP32 RBM alpha = 2 each, 256 chains x 4 sweeps
-# per ring per step
-BATCH_WORKLOADS = {
-    "tfim1d_batch64_n16to128_real_fp32_alpha2": dict(K=64, Nmin=16, Nmax=128, hmin=0.5, hmax=1.5,
-                                                     alpha=2, chains=256, sweeps=4, prec=1,
-                                                     lr=0.01, shift=0.01, cg_tol=1e-8,
-                                                     cg_maxiter=500),
-}
+# ---- one model ---------------------------------------------------------------------------
+class Single:
+    def __init__(self, nqs, synth, torch, name, prec=None):
+        self.torch = torch
+        self.name = name
+        self.w = w = WORKLOADS[name]
+        self.prec = w["prec"] if prec is None else prec
+        self.dev = torch.device("cuda:0")
+        self.N = N = w["L"] ** w["ndim"]
+        self.M = M = w["alpha"] * N
+        self.C, self.S = w["chains"], w["sweeps"]
+        bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
+        self.bonds0 = torch.from_numpy(np.asarray(bonds[0], dtype=np.int64)).to(self.dev)
+        self.model = nqs.Model(N, M, bonds, ham=w["ham"], J=w["J"], h=w["h"],
+                               marshall=w["marshall"], sublattice=sub, move=w["move"],
+                               is_complex=w["cplx"], prec=self.prec)
+        p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
+        self.params = torch.from_numpy(p).to(self.dev).to(self.model.param_dtype)
+        self.chains = torch.empty((self.C, N), dtype=torch.int8, device=self.dev)
+        self.model.chain_init(self.chains, seed=1234)
+        self.samples = torch.empty((self.S, self.C, N), dtype=torch.int8, device=self.dev)
+        self.eloc = torch.empty(self.S * self.C, dtype=self.model.value_dtype, device=self.dev)
+        self.ws = torch.empty(self.model.sr_workspace_bytes(self.S * self.C), dtype=torch.uint8,
+                              device=self.dev)
+        self.stream = torch.cuda.current_stream()
+        self.counter = 0
+
+    def step(self, discard, times=None):
+        torch, m, w = self.torch, self.model, self.w
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if times is not None else None
+        if ev:
+            ev[0].record(self.stream)
+        m.sample(self.params, self.chains, self.S, discard, seed=1234, counter=self.counter,
+                 samples=self.samples, eloc=self.eloc)
+        self.counter += self.S + discard
+        if ev:
+            ev[1].record(self.stream)
+        info = m.sr_step(self.params, self.samples.view(self.S * self.C, self.N), self.eloc,
+                         w["lr"], w["shift"], w["cg_tol"], w["cg_maxiter"], workspace=self.ws,
+                         n_chains=self.C)
+        if ev:
+            ev[2].record(self.stream)
+            times.append((ev, info))
+        return info
+
+    def real_move_fraction(self):
+        """Fraction of proposals that are not the identity: 1 for flips; for exchanges the
+        fraction of color-0 bonds with opposite spins in the recorded samples."""
+        if self.w["move"] == 0:
+            return 1.0
+        s = self.samples.view(-1, self.N)
+        b = self.bonds0
+        return float((s[:, b[:, 0]] != s[:, b[:, 1]]).float().mean().item())
+
+    def run(self, steps, warmup, tune=True):
+        torch, m, w = self.torch, self.model, self.w
+        tuning = m.autotune(self.params, self.chains.repeat(self.S, 1), workspace=self.ws) \
+            if tune else None
+        for k in range(warmup):
+            info = self.step(max(10, self.S // 10) if k == 0 else 0)
+            log("%s warmup %d: E=%.6f +- %.2e cg_iters=%d" % (self.name, k, info["energy_re"],
+                                                                info["energy_err"], info["cg_iters"]))
+        torch.cuda.synchronize()
+        times = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step(0, times)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        samp_ms = sum(e[0].elapsed_time(e[1]) for e, _ in times) / steps
+        sr_ms = sum(e[1].elapsed_time(e[2]) for e, _ in times) / steps
+        infos = [i for _, i in times]
+        ms_per_step = wall * 1e3 / steps
+        n = self.S * self.C
+        f_real = self.real_move_fraction()
+
+        # live per-launch timing (HIP events on the launch stream) of the kernels that carry
+        # the work: the sweep (a sampling call without local energies: the parameter-table
+        # refresh and the sweep kernel), the local energies of the samples, one S v product
+        reps = 3
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        smp = torch.empty_like(self.samples)
+        chains = self.chains.clone()
+        m.sample(self.params, chains, self.S, 0, seed=99, counter=10 ** 6, samples=smp)
+        ev[0].record(self.stream)
+        for r in range(reps):
+            m.sample(self.params, chains, self.S, 0, seed=99, counter=10 ** 6 + r * self.S,
+                     samples=smp)
+        ev[1].record(self.stream)
+        torch.cuda.synchronize()
+        sweep_ms = ev[0].elapsed_time(ev[1]) / reps
+        flat = self.samples.view(n, self.N)
+        el2 = torch.empty_like(self.eloc)
+        m.local_energy(self.params, flat, out=el2)
+        ev[0].record(self.stream)
+        for _ in range(reps):
+            m.local_energy(self.params, flat, out=el2)
+        ev[1].record(self.stream)
+        torch.cuda.synchronize()
+        eloc_ms = ev[0].elapsed_time(ev[1]) / reps
+        sv_ws = m.sr_prepare(self.params, flat, workspace=self.ws)
+        gen = torch.Generator(device="cpu").manual_seed(5)
+        v = torch.randn(m.n_params, dtype=m.value_dtype, generator=gen).to(self.dev)
+        sv_out = torch.empty_like(v)
+        m.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
+        sv_reps = 20
+        ev[0].record(self.stream)
+        for _ in range(sv_reps):
+            m.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
+        ev[1].record(self.stream)
+        torch.cuda.synchronize()
+        mv_ms = ev[0].elapsed_time(ev[1]) / sv_reps
+        cg_mean = float(np.mean([i["cg_iters"] for i in infos]))
+
+        # roofline of the dominant kernel of the step
+        cplx = w["cplx"]
+        sweep_flops = float(self.C) * self.S * self.N * f_real * self.M * sweep_terms_flops(cplx)
+        sv_share = mv_ms * cg_mean
+        plane_split = cplx and self.prec != 0 and self.N <= 63
+        if sweep_ms >= sv_share and sweep_ms >= eloc_ms:
+            peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_VALU
+            ach = sweep_flops / (sweep_ms * 1e-3)
+            roof = {"kernel": "k_sweep (Metropolis sweep, one chain per wavefront)",
+                    "bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / peak,
+                    "traffic": recorded_traffic("k_sweep", self.name),
+                    "algorithmic_flops": sweep_flops, "launch_ms": sweep_ms,
+                    "real_move_fraction": f_real}
+        elif plane_split and sv_share >= eloc_ms:
+            nbytes = sv_bytes(n, self.N, self.M, cplx, True)
+            ach = nbytes / (mv_ms * 1e-3)
+            roof = {"kernel": "S v product (direction tables, fused contraction, partial-sum "
+                              "reduction, centring)", "bound": "hbm",
+                    "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM, "traffic": recorded_traffic("sv_product", self.name),
+                    "algorithmic_bytes": nbytes, "launch_ms": mv_ms,
+                    "fp32_equivalent_tflops": sv_flops(n, self.N, self.M, cplx) / (mv_ms * 1e-3) / 1e12}
+        elif sv_share >= eloc_ms:
+            peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_MFMA
+            fl = sv_flops(n, self.N, self.M, cplx)
+            ach = fl / (mv_ms * 1e-3)
+            roof = {"kernel": "S v product (JVP and VJP contractions)", "bound": "mfma",
+                    "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                    "frac": ach / peak, "traffic": recorded_traffic("sv_product", self.name),
+                    "algorithmic_flops": fl, "launch_ms": mv_ms}
+        else:
+            peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_VALU
+            # connected configurations of the samples: every site (TFIM) or the bonds with
+            # opposite spins (Heisenberg, both colors)
+            fl = float(n) * self.N * f_real * self.M * sweep_terms_flops(cplx)
+            ach = fl / (eloc_ms * 1e-3)
+            roof = {"kernel": "local energy", "bound": "alu", "achieved": ach / 1e12,
+                    "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                    "algorithmic_flops": fl, "launch_ms": eloc_ms}
+        return {
+            "ms_per_step": ms_per_step, "samples_per_step": n,
+            "value": n / (ms_per_step * 1e-3),
+            "sr_iters_per_s": 1e3 / ms_per_step,
+            "sampling_samples_per_s": n / (samp_ms * 1e-3),
+            "phase_ms": {"sample_and_eloc": samp_ms, "sr_step": sr_ms},
+            "kernel_ms": {"sweep_call": sweep_ms, "local_energy_call": eloc_ms,
+                          "sv_product": mv_ms},
+            "cg_iters_mean": cg_mean,
+            "energy_last": infos[-1]["energy_re"], "energy_err_last": infos[-1]["energy_err"],
+            "sv_tuning": tuning, "roofline": roof,
+        }
 
 
+# ---- batch of models, graph-captured step ------------------------------------------------
 def batch_instances(w):
     rng = np.random.default_rng(1234)
     Ns = rng.integers(w["Nmin"], w["Nmax"] + 1, size=w["K"])
@@ -172,41 +360,10 @@ def batch_instances(w):
     return [int(x) for x in Ns], [float(x) for x in hs]
 
 
-def batch_cpu_baseline(w, seconds=15.0):
-    """The FP64 oracle on a bounded sample of the batch: the first 8 rings, 16 chains x 4
-    sweeps each, their local energies, and one SR step where the ring's dense S fits."""
-    import synth
-    from oracle import hamiltonian as oh, lattice as ol, sampler as osamp, sr as osr
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:
-        cores = 1
-    Ns, hs = batch_instances(w)
-    t0 = time.perf_counter()
-    total, passes = 0, 0
-    while time.perf_counter() - t0 < seconds:
-        for k in range(8):
-            N, M = Ns[k], w["alpha"] * Ns[k]
-            ob, _ = ol.hypercube(N, 1)
-            om = oh.Model(N, M, ob, ham=oh.TFIM, J=(1.0, 0.0), h=hs[k], move=oh.MOVE_FLIP)
-            p = synth.rbm_params(N, M, False, sigma=0.01, seed=1234 + k)
-            init = osamp.init_chains(om, 16, seed=1234 ^ k)
-            smp, _, _ = osamp.sample(om, p, init, 4, 0, seed=1234 ^ k, counter=0)
-            flat = smp.reshape(-1, N)
-            el = oh.local_energy(om, p, flat)
-            if N + M + N * M <= 5000:
-                osr.sr_step(om, p, flat, el, w["lr"], w["shift"], w["cg_tol"], w["cg_maxiter"])
-            total += flat.shape[0]
-        passes += 1
-    dt = time.perf_counter() - t0
-    return {"value": total / dt, "unit": "samples/s", "cores": int(cores), "kind": "oracle",
-            "sample": "first 8 rings of the batch, 16 chains x 4 sweeps each, local energies, and "
-                      "one SR step for rings with at most 5000 parameters; %d passes in %.1f s"
-                      % (passes, dt)}
-
-
-def bench_batch(args, nqs, synth, torch, name):
+def bench_batch(nqs, synth, torch, name, steps, warmup):
+    """The batched step (one persistent sampling launch for every chain of every ring,
+    local energies in the sweep, stream-ordered SR of every ring) captured into one graph
+    after one direct step, then replayed; the random stream advances on the device."""
     w = BATCH_WORKLOADS[name]
     dev = torch.device("cuda:0")
     Ns, hs = batch_instances(w)
@@ -228,152 +385,194 @@ def bench_batch(args, nqs, synth, torch, name):
     samples = torch.empty(S * spins, dtype=torch.int8, device=dev)
     eloc = torch.empty(S * C * w["K"], dtype=torch.float64, device=dev)
     ws = torch.empty(b.sr_workspace_bytes(ns), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    counter = [0]
+    info = torch.zeros(w["K"] * nqs.SR_INFO_BYTES, dtype=torch.uint8, device=dev)
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
 
     def step(discard):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        b.sample(params, chains, nch, S, discard, seed=1234, counter=counter[0], samples=samples,
-                 eloc=eloc)
-        e1.record(stream)
-        counter[0] += S + discard
-        infos = b.sr_step(params, samples, eloc, ns, w["lr"], w["shift"], w["cg_tol"],
-                          w["cg_maxiter"], workspace=ws)
-        return infos, (e0, e1)
+        b.sample(params, chains, nch, S, discard, seed=1234, counter=0, samples=samples,
+                 eloc=eloc, counter_dev=counter)
+        b.sr_step_async(params, samples, eloc, ns, w["lr"], w["shift"], w["cg_tol"],
+                        w["cg_maxiter"], workspace=ws, n_chains=nch, info=info)
 
-    for k in range(args.warmup):
-        infos, _ = step(10 if k == 0 else 0)
-        log("warmup step %d: max cg_iters %d" % (k, max(i["cg_iters"] for i in infos)))
+    step(10)
+    for _ in range(max(0, warmup - 1)):
+        step(0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s2):
+        with torch.cuda.graph(g, stream=s2):
+            step(0)
+    torch.cuda.synchronize()
+    g.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs, iters = [], []
-    for k in range(args.steps):
-        infos, ev = step(0)
-        evs.append(ev)
-        iters.append(max(i["cg_iters"] for i in infos))
+    for _ in range(steps):
+        g.replay()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    samp_ms = sum(a.elapsed_time(c) for a, c in evs) / args.steps
+    infos = nqs.sr_infos_from_device(info, w["K"])
+    ms_per_step = wall * 1e3 / steps
+    # the sampling launch alone (tables + the persistent sweep with fused local energies)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    st = torch.cuda.current_stream()
+    smp2 = torch.empty_like(samples)
+    el2 = torch.empty_like(eloc)
+    ch2 = chains.clone()
+    reps = 5
+    b2 = nqs.Batch(specs)   # its own job tables: the graph keeps the first handle's
+    b2.sample(params, ch2, nch, S, 0, seed=77, counter=0, samples=smp2, eloc=el2)
+    ev[0].record(st)
+    for r in range(reps):
+        b2.sample(params, ch2, nch, S, 0, seed=77, counter=(r + 1) * S, samples=smp2, eloc=el2)
+    ev[1].record(st)
+    torch.cuda.synchronize()
+    samp_ms = ev[0].elapsed_time(ev[1]) / reps
     n_samp = C * S * w["K"]
-    flops = float(sum(C * S * N * (w["alpha"] * N) * 4 for N in Ns))
+    flops = float(sum(C * S * N * (w["alpha"] * N) * sweep_terms_flops(False) for N in Ns))
     ach = flops / (samp_ms * 1e-3)
-    out = {
-        "metric": "samples/s (sweep+E_loc+O_k) and SR iters/s, BF16/FP32 vs FP64 at fixed dE",
-        "value": n_samp / (ms_per_step * 1e-3), "unit": "samples/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": name, "instances": w["K"], "n_sites_min": min(Ns),
-                   "n_sites_max": max(Ns), "chains_per_instance": C, "sweeps_per_step": S,
-                   "samples_per_step": n_samp, "cg_tol": w["cg_tol"]},
-        "sr_iters_per_s": 1e3 / ms_per_step,
-        "phase_ms": {"sample_and_eloc": samp_ms, "sr_step": ms_per_step - samp_ms},
-        "cg_iters_max_mean": float(np.mean(iters)),
-        "roofline": {"kernel": "batched sweep with fused local energies (one launch)",
+    e_exact = [exact_tfim(N, h) for N, h in zip(Ns, hs)]
+    de = [abs(i["energy_re"] - e) / abs(e) for i, e in zip(infos, e_exact)]
+    return {
+        "workload": name, "graph_replayed": True, "instances": w["K"],
+        "n_sites_min": min(Ns), "n_sites_max": max(Ns), "chains_per_instance": C,
+        "sweeps_per_step": S, "samples_per_step": n_samp, "cg_maxiter": w["cg_maxiter"],
+        "ms_per_step": ms_per_step, "value": n_samp / (ms_per_step * 1e-3),
+        "sr_iters_per_s": 1e3 / ms_per_step, "sampling_launch_ms": samp_ms,
+        "cg_iters_max": max(i["cg_iters"] for i in infos),
+        "converged_models": sum(i["converged"] for i in infos),
+        "rel_energy_error_vs_exact_median": float(np.median(de)),
+        "roofline": {"kernel": "k_sweep_batch (every chain of every ring, fused local energies)",
                      "bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None},
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                     "algorithmic_flops": flops, "launch_ms": samp_ms},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = batch_cpu_baseline(w, args.cpu_seconds)
-    print(json.dumps(out))
 
 
-# exact ground energies of the workloads (Pauli units): Bethe ansatz for the 40-site
-# Heisenberg ring, free-fermion closed form for the 10-site TFIM ring
-E_REF = {"heisenberg1d_n40_cplx_fp32_alpha2": -70.98609115333286,
-         "tfim1d_n10_real_fp64_alpha1": -12.784906442999324}
-FORM_NAMES = {0: "fp64", 1: "fp32", 2: "bf16"}
+def exact_tfim(N, h, J=1.0):
+    """Ferromagnetic periodic TFIM ring, free-fermion closed form (the exact energy each
+    ring's VMC energy is compared with)."""
+    k = (2 * np.arange(N) + 1) * np.pi / N
+    return -float(np.sum(np.sqrt(J * J + h * h - 2 * J * h * np.cos(k))))
 
 
-def run_form(nqs, synth, torch, w, prec, iters):
+# ---- precision forms at a fixed energy error ------------------------------------------
+def run_form(nqs, synth, torch, name, prec, iters):
     """SR trajectory of the workload in one precision form from the common start
-    (parameters N(0, 0.01^2) from seed 1234, chains from seed 1234): per iteration one
-    sampling call and one SR step; returns per-iteration energies and wall times."""
-    dev = torch.device("cuda:0")
-    N = w["L"] ** w["ndim"]
-    M = w["alpha"] * N
-    C, S = w["chains"], w["sweeps"]
-    bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
-    model = nqs.Model(N, M, bonds, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
-                      sublattice=sub, move=w["move"], is_complex=w["cplx"], prec=prec)
-    p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
-    params = torch.from_numpy(p).to(dev).to(model.param_dtype)
-    chains = torch.empty((C, N), dtype=torch.int8, device=dev)
-    model.chain_init(chains, seed=1234)
-    samples = torch.empty((S, C, N), dtype=torch.int8, device=dev)
-    eloc = torch.empty(S * C, dtype=model.value_dtype, device=dev)
-    ws = torch.empty(model.sr_workspace_bytes(S * C), dtype=torch.uint8, device=dev)
-    model.autotune(params, chains.repeat(S, 1), workspace=ws)
-    energies, walls = [], []
+    (parameters N(0, 0.01^2) from seed 1234, chains from seed 1234)."""
+    s = Single(nqs, synth, torch, name, prec=prec)
+    s.model.autotune(s.params, s.chains.repeat(s.S, 1), workspace=s.ws)
+    energies, errs, walls = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    counter = 0
     for k in range(iters):
-        discard = max(10, S // 10) if k == 0 else 0
-        model.sample(params, chains, S, discard, seed=1234, counter=counter, samples=samples,
-                     eloc=eloc)
-        counter += S + discard
-        info = model.sr_step(params, samples.view(S * C, N), eloc, w["lr"], w["shift"],
-                             w["cg_tol"], w["cg_maxiter"], workspace=ws)
+        info = s.step(max(10, s.S // 10) if k == 0 else 0)
         torch.cuda.synchronize()
         energies.append(info["energy_re"])
+        errs.append(info["energy_err"])
         walls.append(time.perf_counter() - t0)
-    return energies, walls, S * C
+    return np.array(energies), np.array(errs), np.array(walls), s.S * s.C
 
 
-def compare_forms(nqs, synth, torch, w, workload, iters):
-    """The same SR trajectory in the FP64, FP32 and BF16 forms: rates, and the time each
-    form needs to reach the energy error that all of them reach (dE = relative error of
-    the 5-iteration running mean of the energy against the exact ground energy)."""
+def compare_forms(nqs, synth, torch, name, iters):
+    """The same SR trajectory in the FP64, FP32 and BF16 forms. dE = |mean energy of the last
+    10% of iterations - E_exact| / |E_exact|, sigma = error bar of that mean (the per-
+    iteration error bars combined as independent). A low-precision form counts as reaching
+    the FP64 form's accuracy when dE_form <= dE_fp64 + 2 sqrt(sigma_form^2 + sigma_fp64^2).
+    time_to_dE: wall time until the 10-iteration running mean first reaches the largest final
+    dE of the three forms (the error all of them reach)."""
+    e_ref = golden(E_REF[name])
     out, runs = {}, {}
     for prec in (0, 1, 2):
-        name = FORM_NAMES[prec]
-        log("forms: %s, %d SR iterations" % (name, iters))
-        energies, walls, n = run_form(nqs, synth, torch, w, prec, iters)
-        runs[name] = ([np.mean(energies[max(0, k - 4):k + 1]) for k in range(len(energies))],
-                      walls, n)
-    # exact ground energy where one is known, else the FP64 form's final energy
-    e_ref = E_REF.get(workload, float(runs["fp64"][0][-1]))
-    curves = {}
-    for name, (sm, walls, n) in runs.items():
-        de = [abs(e - e_ref) / abs(e_ref) for e in sm]
+        fname = FORM_NAMES[prec]
+        log("forms: %s, %d SR iterations" % (fname, iters))
+        runs[fname] = run_form(nqs, synth, torch, name, prec, iters)
+    tail = max(1, iters // 10)
+    for fname, (E, err, walls, n) in runs.items():
         steady = (walls[-1] - walls[0]) / max(1, len(walls) - 1)   # excludes the burn-in call
-        curves[name] = (de, walls)
-        energies = sm
-        out[name] = {"ms_per_iter": 1e3 * steady, "samples_per_s": n / steady,
-                     "sr_iters_per_s": 1.0 / steady, "dE_final": de[-1],
-                     "energy_final": float(energies[-1])}
+        mean = E[-tail:].mean()
+        sig = np.sqrt(np.sum(err[-tail:] ** 2)) / tail / abs(e_ref)
+        out[fname] = {"ms_per_iter": 1e3 * steady, "samples_per_s": n / steady,
+                      "sr_iters_per_s": 1.0 / steady, "energy_final": float(mean),
+                      "dE_final": float(abs(mean - e_ref) / abs(e_ref)), "sigma": float(sig)}
+    ref = out["fp64"]
+    for fname in ("fp32", "bf16"):
+        o = out[fname]
+        o["within_2sigma_of_fp64"] = bool(
+            o["dE_final"] <= ref["dE_final"] + 2 * np.hypot(o["sigma"], ref["sigma"]))
+        o["speedup_vs_fp64"] = ref["ms_per_iter"] / o["ms_per_iter"]
     target = max(v["dE_final"] for v in out.values())
-    if target == 0.0:
-        target = 1e-12
-    for name, (de, walls) in curves.items():
-        k = next(i for i, d in enumerate(de) if d <= target)
-        out[name]["iters_to_dE"] = k + 1
-        out[name]["time_to_dE_s"] = walls[k]
-    return {"dE_target": target, "e_ref": e_ref, "e_ref_kind": "exact" if workload in E_REF
-            else "fp64 form, final", "iters": iters, "forms": out}
+    for fname, (E, err, walls, n) in runs.items():
+        run_mean = np.array([E[max(0, k - 9):k + 1].mean() for k in range(len(E))])
+        de = np.abs(run_mean - e_ref) / abs(e_ref)
+        hit = np.nonzero(de <= target)[0]
+        k = int(hit[0]) if hit.size else len(E) - 1
+        out[fname]["iters_to_dE"] = k + 1
+        out[fname]["time_to_dE_s"] = float(walls[k])
+    return {"workload": name, "e_ref": e_ref, "e_ref_kind": "exact", "iters": iters,
+            "tail_iters": tail, "dE_target": target, "forms": out}
 
 
-def log(msg):
-    print("[bench] " + msg, file=sys.stderr, flush=True)
+# ---- the FP64 oracle on the host ----------------------------------------------------------
+def cpu_baseline(name, seconds):
+    """The FP64 oracle (plain numpy, unmodified: cached-angle Metropolis sweeps, local
+    energies from log psi of every connected configuration, and the SR step with its dense S
+    where that fits) on a bounded sample of the same workload."""
+    import synth
+    from oracle import hamiltonian as oh, lattice as ol, sampler as osamp, sr as osr
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    w = WORKLOADS[name]
+    N = w["L"] ** w["ndim"]
+    M = w["alpha"] * N
+    ob, osub = ol.hypercube(w["L"], w["ndim"], with_diagonals=w["diag"])
+    om = oh.Model(N, M, ob, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
+                  sublattice=osub, move=w["move"], is_complex=w["cplx"])
+    p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
+    P = N + M + N * M
+    with_sr = P <= 5000
+    chains, sweeps = (64, 4) if N <= 64 else (16, 1)
+    t0 = time.perf_counter()
+    init = osamp.init_chains(om, chains, seed=1234)
+    total = 0
+    while True:
+        smp, init, _ = osamp.sample_cached(om, p, init, sweeps, 0, seed=1234, counter=total)
+        flat = smp.reshape(-1, N)
+        el = oh.local_energy(om, p, flat)
+        if with_sr:
+            osr.sr_step(om, p, flat, el, w["lr"], w["shift"], w["cg_tol"], w["cg_maxiter"])
+        total += flat.shape[0]
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    nproc, cpu = host_info()
+    what = ("local energies and one SR step" if with_sr else
+            "local energies (no SR: the oracle's dense S of %d parameters does not fit)" % P)
+    return {"value": total / dt, "unit": "samples/s", "cores": int(threads), "kind": "oracle",
+            "nproc": nproc, "cpu_model": cpu,
+            "sample": "%s: %d chains x %d cached-angle sweeps per pass, %s per pass, %d passes "
+                      "in %.1f s; cores = BLAS threads numpy used"
+                      % (name, chains, sweeps, what, total // (chains * sweeps), dt)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="heisenberg1d_n40_cplx_fp32_alpha2",
-                    choices=list(WORKLOADS) + list(BATCH_WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=HEADLINE, choices=list(WORKLOADS))
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no other workloads, no form comparison)")
+    ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sv-pairs", type=int, default=0, choices=[0, 2, 4],
-                    help="fixed S v kernel shape instead of the autotuner's choice")
-    ap.add_argument("--forms-iters", type=int, default=40,
-                    help="SR iterations per precision form in the FP64/FP32/BF16 comparison "
-                         "(0 = skip)")
+    ap.add_argument("--forms-iters", type=int, default=500,
+                    help="SR iterations per precision form in the FP64/FP32/BF16 comparison on "
+                         "the 40-site ring (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -390,150 +589,47 @@ def main():
     nqs.load()
     if args.copy_probe:
         copy_probe(torch, torch.device("cuda:0"))
-    log("library loaded, building workload " + args.workload)
-    if args.workload in BATCH_WORKLOADS:
-        return bench_batch(args, nqs, synth, torch, args.workload)
-    w = WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    N = w["L"] ** w["ndim"]
-    M = w["alpha"] * N
-    C, S = w["chains"], w["sweeps"]
-    bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
-    model = nqs.Model(N, M, bonds, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
-                      sublattice=sub, move=w["move"], is_complex=w["cplx"], prec=w["prec"])
-    p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234,
-                         dtype=None if w["prec"] == 0 else (np.complex64 if w["cplx"] else np.float32))
-    params = torch.from_numpy(p).to(dev)
-    chains = torch.empty((C, N), dtype=torch.int8, device=dev)
-    model.chain_init(chains, seed=1234)
-    samples = torch.empty((S, C, N), dtype=torch.int8, device=dev)
-    eloc = torch.empty(S * C, dtype=model.value_dtype, device=dev)
-    nacc = torch.zeros(C, dtype=torch.int64, device=dev)
-    ws = torch.empty(model.sr_workspace_bytes(S * C), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    counter = [0]
-
-    def step(discard, times):
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record(stream)
-        model.sample(params, chains, S, discard, seed=1234, counter=counter[0], samples=samples,
-                     n_accepted=nacc, eloc=eloc)
-        counter[0] += S + discard
-        e1.record(stream)
-        info = model.sr_step(params, samples.view(S * C, N), eloc, w["lr"], w["shift"],
-                             w["cg_tol"], w["cg_maxiter"], workspace=ws)
-        e2.record(stream)
-        if times is not None:
-            times.append((e0, e1, e2, info))
-        return info
-
-    # pick the S v kernel shape for this model and sample count (timed on the
-    # initial chains, before the timed region)
-    if args.sv_pairs:
-        model.set_sv_shape(args.sv_pairs)
-        tune = {"fixed_pairs": args.sv_pairs}
-    else:
-        tune = model.autotune(params, chains.repeat(S, 1), workspace=ws)
-    log("S v shape: %s" % tune)
-    for k in range(args.warmup):
-        info = step(max(10, S // 10) if k == 0 else 0, None)
-        log("warmup step %d: E=%.8f cg_iters=%d" % (k, info["energy_re"], info["cg_iters"]))
-    torch.cuda.synchronize()
-    times = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(0, times)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    samp_ms = sum(a.elapsed_time(b) for a, b, c, i in times) / args.steps
-    sr_ms = sum(b.elapsed_time(c) for a, b, c, i in times) / args.steps
-    cg = [i["cg_iters"] for a, b, c, i in times]
-    energies = [i["energy_re"] for a, b, c, i in times]
-    ms_per_step = wall * 1e3 / args.steps
-    n_samp = S * C
-
-    # live per-launch timing of the two parts that carry the work: the sampling call
-    # (sweeps with fused local energies) and one S v product of the CG
-    flat = samples.view(n_samp, N)
-    reps = 5
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record(stream)
-    for _ in range(reps):
-        model.sample(params, chains, S, 0, seed=99, counter=10 ** 6, samples=samples, eloc=eloc)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    sweep_ms = ev[0].elapsed_time(ev[1]) / reps
-    sv_reps = 20
-    sv_ws = model.sr_prepare(params, flat, workspace=ws)
-    gen = torch.Generator(device="cpu").manual_seed(5)
-    v = torch.randn(model.n_params, dtype=model.value_dtype, generator=gen).to(dev)
-    sv_out = torch.empty_like(v)
-    model.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
-    ev[0].record(stream)
-    for _ in range(sv_reps):
-        model.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    mv_ms = ev[0].elapsed_time(ev[1]) / sv_reps
-
-    sweep_flops = float(n_samp) * N * M * (12 if w["cplx"] else 4)
-    mv_flops = sv_flops(n_samp, N, M, w["cplx"])
-    share_sr = sr_ms / (samp_ms + sr_ms)
-    # the plane-split product (complex, FP32 or BF16 form, N <= 63) runs its contractions
-    # on the bf16 matrix cores with an exact three-part split (floor ~3x the flops at the
-    # bf16 rate, below the time to stream T once): bounded by HBM. Other shapes run the
-    # FP32 or FP64 16x16x4 MFMA and are reported against that peak.
-    plane_split = w["cplx"] and w["prec"] != 0 and N <= 63
-    if share_sr > 0.5 and plane_split:
-        nbytes = sv_bytes(n_samp, N, M, w["cplx"], True)
-        ach = nbytes / (mv_ms * 1e-3)
-        roof = {"kernel": "S v product (direction tables, fused contraction, partial-sum "
-                          "reduction, centring)", "bound": "hbm",
-                "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": ach / PEAK_HBM, "traffic": recorded_traffic("sv_product", args.workload),
-                "algorithmic_bytes": nbytes,
-                "fp32_equivalent_tflops": mv_flops / (mv_ms * 1e-3) / 1e12}
-    elif share_sr > 0.5:
-        peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_MFMA
-        ach = mv_flops / (mv_ms * 1e-3)
-        roof = {"kernel": "S v product (direction tables, fused contraction, partial-sum "
-                          "reduction, centring)", "bound": "mfma",
-                "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": recorded_traffic("sv_product", args.workload)}
-    else:
-        peak = PEAK_FP64 if w["prec"] == 0 else PEAK_FP32_VALU
-        ach = sweep_flops / (sweep_ms * 1e-3)
-        roof = {"kernel": "k_sweep", "bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": recorded_traffic("k_sweep", args.workload)}
-
+    log("headline workload " + args.workload)
+    head = Single(nqs, synth, torch, args.workload)
+    r = head.run(args.steps, args.warmup)
+    w = head.w
+    log("headline: %.2f ms/step" % r["ms_per_step"])
     out = {
-        "metric": "samples/s (sweep+E_loc+O_k) and SR iters/s, BF16/FP32 vs FP64 at fixed dE",
-        "value": n_samp / (ms_per_step * 1e-3),
-        "unit": "samples/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": r["value"], "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {0: "f64", 1: "f32", 2: "bf16"}[w["prec"]],
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n_sites": N, "n_hidden": M, "chains": C,
-                   "sweeps_per_step": S, "samples_per_step": n_samp, "cg_tol": w["cg_tol"],
-                   "diag_shift": w["shift"], "lr": w["lr"]},
-        "sr_iters_per_s": 1e3 / ms_per_step,
-        "sampling_samples_per_s": n_samp / (samp_ms * 1e-3),
-        "phase_ms": {"sample_and_eloc": samp_ms, "sr_step": sr_ms},
-        "cg_iters_mean": float(np.mean(cg)),
-        "energy_last": energies[-1],
-        "kernel_ms": {"sample_call": sweep_ms, "sv_product": mv_ms},
-        "sv_tuning": tune,
-        "roofline": roof,
+        "dtype": {0: "f64", 1: "f32", 2: "bf16"}[w["prec"]], "data": "synthetic",
+        "config": {"workload": args.workload, "n_sites": head.N, "n_hidden": head.M,
+                   "chains": head.C, "sweeps_per_step": head.S,
+                   "samples_per_step": head.S * head.C, "cg_tol": w["cg_tol"],
+                   "cg_maxiter": w["cg_maxiter"], "diag_shift": w["shift"], "lr": w["lr"]},
+        "roofline": r["roofline"],
     }
-    log("timed %d steps: %.2f ms/step" % (args.steps, ms_per_step))
-    if args.forms_iters > 0:
-        out["precision_forms"] = compare_forms(nqs, synth, torch, w, args.workload,
-                                               args.forms_iters)
+    for k in ("sr_iters_per_s", "sampling_samples_per_s", "phase_ms", "kernel_ms",
+              "cg_iters_mean", "energy_last", "energy_err_last", "sv_tuning"):
+        out[k] = r[k]
+    if not args.no_extras:
+        others = {}
+        for name in EXTRA_SINGLE:
+            if name == args.workload:
+                continue
+            log("workload " + name)
+            s = Single(nqs, synth, torch, name)
+            o = s.run(args.extra_steps, 2)
+            o["dtype"] = {0: "f64", 1: "f32", 2: "bf16"}[s.prec]
+            others[name] = o
+            del s
+        for name in BATCH_WORKLOADS:
+            log("workload " + name + " (graph-replayed step)")
+            others[name] = bench_batch(nqs, synth, torch, name, args.extra_steps, 2)
+        out["other_workloads"] = others
+        if args.forms_iters > 0:
+            out["precision_forms"] = compare_forms(nqs, synth, torch,
+                                                   "heisenberg1d_n40_cplx_fp32_alpha2",
+                                                   args.forms_iters)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, N, M, args.cpu_seconds)
+        log("oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out))
 
 

@@ -17,12 +17,16 @@ paper leaves open, fixed as conventions both sides follow:
   ``philox``. Chain initialisation: independent +/-1 spins (MOVE_FLIP), or a uniformly
   random permutation (Fisher-Yates) of N/2 up and N/2 down spins (MOVE_EXCHANGE).
 
-This is the definition: log psi(sigma') is recomputed from scratch for every proposal.
-Chains are independent, so all chains advance together as numpy arrays.
+``sample`` is the definition: log psi(sigma') is recomputed from scratch for every
+proposal. ``sample_cached`` runs the same chains with the hidden angles theta = W sigma + b
+kept per chain and moved by the angle change of each accepted proposal, so a proposal costs
+M ln cosh evaluations instead of N M products (the form used to time the oracle on the
+host). Chains are independent, so all chains advance together as numpy arrays.
 
 Pins (tests/test_oracle_sampler.py): the empirical one-step transition row of
 ``metropolis_step`` against the analytic Metropolis kernel, and the histogram of long
-chains against exact |psi|^2 by enumeration (chi-square), on N <= 6.
+chains against exact |psi|^2 by enumeration (chi-square), on N <= 6; ``sample_cached``
+reproduces ``sample`` sample for sample on the same stream (both moves, real and complex).
 """
 import numpy as np
 
@@ -98,6 +102,61 @@ def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain
                 near = np.abs(u - np.exp(np.minimum(two_re, 0.0))) < tie_margin
                 for c in np.nonzero(near)[0]:
                     record_ties.append((int(chains[c]), g, st))
+        if sw >= n_discard:
+            out[sw - n_discard] = sigma
+    return out, sigma, n_acc
+
+
+def sample_cached(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain_offset=0):
+    """``sample`` with cached hidden angles: Delta = a.(sigma' - sigma) +
+    sum_j [ln cosh(theta_j + delta_j) - ln cosh(theta_j)], delta = W (sigma' - sigma), and
+    theta += delta on acceptance. Same random numbers and acceptance rule as ``sample``;
+    returns (samples [n_sweeps, C, N], chain_sigma_out [C, N], n_accepted [C])."""
+    N, M = model.n_sites, model.n_hidden
+    a, b, W = rbm.unpack(params, N, M)
+    sigma = np.array(chain_sigma, dtype=np.int8, copy=True)
+    C = sigma.shape[0]
+    chains = np.arange(C, dtype=np.uint64) + np.uint64(chain_offset)
+    rows = np.arange(C)
+    th = rbm.theta(params, sigma, N, M)                      # [C, M]
+    lc = rbm.ln_cosh(th)
+    out = np.empty((n_sweeps, C, N), dtype=np.int8)
+    n_acc = np.zeros(C, dtype=np.int64)
+    for sw in range(n_discard + n_sweeps):
+        g = counter + sw
+        for st in range(N):
+            w = philox.draw(seed, chains, g, st, philox.TAG_PROPOSAL)
+            u = philox.uniform_from_words(w[:, 1], w[:, 2])
+            if model.move == MOVE_FLIP:
+                i = philox.index_from_word(w[:, 0], N)
+                k = i
+                si = sigma[rows, i].astype(np.float64)
+                real_move = np.ones(C, dtype=bool)
+                delta = -2.0 * si[:, None] * W[:, i].T                # [C, M]
+                dvis = -2.0 * si * a[i]
+            else:
+                bl = model.bonds[0]
+                bidx = philox.index_from_word(w[:, 0], bl.shape[0])
+                i, k = bl[bidx, 0], bl[bidx, 1]
+                si = sigma[rows, i].astype(np.float64)
+                sk = sigma[rows, k].astype(np.float64)
+                real_move = si != sk
+                # sigma'_i = sk, sigma'_k = si
+                delta = (sk - si)[:, None] * W[:, i].T + (si - sk)[:, None] * W[:, k].T
+                dvis = (sk - si) * a[i] + (si - sk) * a[k]
+            lc_new = rbm.ln_cosh(th + delta)
+            two_re = 2.0 * np.real(dvis + np.sum(lc_new - lc, axis=1))
+            accept = real_move & ((two_re >= 0.0) | (u < np.exp(np.minimum(two_re, 0.0))))
+            if model.move == MOVE_FLIP:
+                sigma[rows[accept], i[accept]] = -sigma[rows[accept], i[accept]]
+            else:
+                ia, ka = i[accept], k[accept]
+                vi = sigma[rows[accept], ia].copy()
+                sigma[rows[accept], ia] = sigma[rows[accept], ka]
+                sigma[rows[accept], ka] = vi
+            th[accept] += delta[accept]
+            lc[accept] = lc_new[accept]
+            n_acc += accept
         if sw >= n_discard:
             out[sw - n_discard] = sigma
     return out, sigma, n_acc

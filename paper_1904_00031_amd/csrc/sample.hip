@@ -359,8 +359,10 @@ __device__ __forceinline__ int wave_sum_gt(float x, float th) {
 }
 
 // SM: N <= 64, the spins also held as a wave-uniform bit mask (bit i set: spin i up), so
-// the spins of a proposal and their update are scalar bit operations
-template <typename T, bool C, int R, bool TL, bool SM>
+// the spins of a proposal and their update are scalar bit operations. FE: the fused local
+// energy is compiled in (the single-model sweep fuses it only with at most four hidden
+// units per lane; leaving it out of the other shapes frees their registers)
+template <typename T, bool C, int R, bool TL, bool SM, bool FE = true>
 __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> &tb,
                                             const SweepArgs &a, int chain_base) {
   extern __shared__ __align__(16) unsigned char lds_u8[];
@@ -469,6 +471,30 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
       o.w[r] = row_ld(lW, gW, row, j);
     }
     return o;
+  };
+  // ST (float, more than four hidden units per lane): proposals streamed over the lane's
+  // hidden units, with no row arrays held in registers. RC: the angle change d = W_i (flip)
+  // or W_i - W_k (exchange) and cosh(2 d), sinh(2 d) are formed in registers from the W^T
+  // rows of the move's sites instead of reading the C/S/W table rows.
+  constexpr bool ST = false;
+  constexpr bool RC = false;
+  auto unit_d = [&](int row, int ic, int kc, int j) __attribute__((always_inline)) -> V<T, C> {
+    if constexpr (RC) {
+      V<T, C> d = vload<T, C>(tb.Wt, int64_t(ic) * M + j);
+      if (!flip) d = vsub(d, vload<T, C>(tb.Wt, int64_t(kc) * M + j));
+      return d;
+    } else {
+      return row_ld(lW, gW, row, j);
+    }
+  };
+  auto unit_cs = [&](int row, int ic, int kc, int j, V<T, C> &cc,
+                     V<T, C> &ss) __attribute__((always_inline)) {
+    if constexpr (RC) {
+      vcosh_sinh2<T, C>(unit_d(row, ic, kc, j), cc, ss);
+    } else {
+      cc = row_ld(lC, gC, row, j);
+      ss = row_ld(lS, gS, row, j);
+    }
   };
   int64_t acc_count = 0;
   for (int sw = 0; sw < total; ++sw) {
@@ -598,17 +624,16 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
         }
       } else {
         // the same proposal with the spins in registers or LDS (a plain loop: a closure
-        // here made the compiler keep the chain state in scratch memory)
-        Rows cur = load_rows(__builtin_amdgcn_readlane(rowv, 0));
+        // here made the compiler keep the chain state in scratch memory). Without the
+        // prefetch, the rows of a move are read only once it is known not to be the
+        // identity (an exchange of equal spins reads nothing).
+        Rows cur;
+        if constexpr (PF) cur = load_rows(__builtin_amdgcn_readlane(rowv, 0));
         for (int l = 0; l < nst; ++l) {
           const int ic = __builtin_amdgcn_readlane(iv, l);
           const int kc = __builtin_amdgcn_readlane(kv, l);
           Rows nxt;
-          if constexpr (PF) {
-            nxt = load_rows(__builtin_amdgcn_readlane(rowv, l + 1 < nst ? l + 1 : l));
-          } else {
-            if (l > 0) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
-          }
+          if constexpr (PF) nxt = load_rows(__builtin_amdgcn_readlane(rowv, l + 1 < nst ? l + 1 : l));
           int s, sk;
           if (sregs) {
             s = __builtin_amdgcn_readlane(ic < 64 ? sp0 : (ic < 128 ? sp1 : (ic < 192 ? sp2 : sp3)),
@@ -622,6 +647,43 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
           }
           if (sk != s) {  // an exchange of equal spins is the identity move
           const T ts = T(s);
+          int accept;
+          if constexpr (ST) {
+            // streamed over the lane's hidden units: the ratio terms and the decision (same
+            // grouping of four units per logarithm as below), then, on acceptance, the
+            // unit's factors read (or formed) again for the updates of theta and t
+            const int row = __builtin_amdgcn_readlane(rowv, l);
+            float lp = 0.f, pm = 1.f;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const int j = lane + 64 * r < M ? lane + 64 * r : 0;
+              V<T, C> cc, ss;
+              unit_cs(row, ic, kc, j, cc, ss);
+              const V<T, C> tm = vsub(cc, vscale(vmul(t[r], ss), ts));
+              if (lane + 64 * r < M) pm *= float(vabs2(tm));
+              if ((r & 3) == 3 || r == R - 1) {
+                lp += __log2f(pm);
+                pm = 1.f;
+              }
+            }
+            accept = wave_sum_gt(lp, readlane_v(s > 0 ? thp : thm, l));
+            if (accept) {
+#pragma unroll
+              for (int r = 0; r < R; ++r) {
+                if (lane + 64 * r < M) {
+                  const int j = lane + 64 * r;
+                  V<T, C> cc, ss;
+                  unit_cs(row, ic, kc, j, cc, ss);
+                  const V<T, C> d = unit_d(row, ic, kc, j);
+                  const V<T, C> tm = vsub(cc, vscale(vmul(t[r], ss), ts));
+                  thr[r] -= 2.0 * double(s) * double(d.re);
+                  if (C) thi[r] -= 2.0 * double(s) * double(d.im);
+                  t[r] = vdiv(vsub(vmul(cc, t[r]), vscale(ss, ts)), tm);
+                }
+              }
+            }
+          } else {
+          if constexpr (!PF) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
           V<T, C> term[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) term[r] = vsub(cur.c[r], vscale(vmul(t[r], cur.s[r]), ts));
@@ -632,7 +694,6 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
             for (int r = 0; r < R; ++r)
               tn[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
           }
-          int accept;
           if constexpr (sizeof(T) == 4) {
             // log-domain decision: accept iff sum_j log2|term_j|^2 > log2(u) - log2|a|^2
             float lp = 0.f;
@@ -684,6 +745,9 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
                   t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
               }
             }
+          }
+          }
+          if (accept) {
               // spin registers (one lane each) and the LDS copy
               if (sregs) {
                 if (ic < 64)
@@ -734,7 +798,7 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
       const int64_t smp = int64_t(sw - a.n_discard) * a.n_chains + chain;
       int8_t *dst = a.samples + smp * N;
       for (int i = lane; i < N; i += 64) dst[i] = sig[i];
-      if (a.eloc) {
+      if (FE && a.eloc) {
         double er, ei;
         if (M <= 256) {
 #pragma unroll
@@ -763,7 +827,7 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
 
 template <typename T, bool C, int R, bool TL, bool SM>
 __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepArgs a) {
-  sweep_block<T, C, R, TL, SM>(dm, tb, a, blockIdx.x * (blockDim.x >> 6));
+  sweep_block<T, C, R, TL, SM, (R <= 4)>(dm, tb, a, blockIdx.x * (blockDim.x >> 6));
 }
 
 // ---------------------------------------------------------------------------------

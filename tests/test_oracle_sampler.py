@@ -104,3 +104,19 @@ def test_init_chains_uniform_chi_square(move):
     expct = chains / len(confs)
     stat = np.sum((hist - expct) ** 2 / expct)
     assert chi2.sf(stat, df=len(confs) - 1) > 1e-3, stat
+
+
+@pytest.mark.parametrize("move,cplx", [(MOVE_FLIP, False), (MOVE_FLIP, True), (MOVE_EXCHANGE, True),
+                                       (MOVE_EXCHANGE, False)])
+def test_cached_sampler_equals_definition(move, cplx):
+    # the cached-angle chains equal the recompute-from-scratch chains on the same stream
+    # (decisions could differ only at exact near-ties, none of which occur here)
+    b, sub = lattice.hypercube(10, 1)
+    ham = TFIM if move == MOVE_FLIP else HEISENBERG
+    m = Model(10, 13, b, ham=ham, J=(1.0, 0.0), h=1.0, sublattice=sub, move=move, is_complex=cplx)
+    p = synth.rbm_params(10, 13, cplx, sigma=0.4, seed=35)
+    init = sampler.init_chains(m, 24, seed=36)
+    a1, l1, n1 = sampler.sample(m, p, init, 6, 3, seed=36, counter=11)
+    a2, l2, n2 = sampler.sample_cached(m, p, init, 6, 3, seed=36, counter=11)
+    assert np.array_equal(a1, a2) and np.array_equal(l1, l2) and np.array_equal(n1, n2)
+    assert n1.sum() > 0
