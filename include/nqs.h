@@ -8,10 +8,11 @@
  *    only borrows them for the duration of the call. Pointers marked (host) are host
  *    memory. The library allocates device memory only for the per-model tables created
  *    in nqs_model_create and for one grow-only scratch buffer per model, used by
- *    nqs_sample (when it computes local energies), nqs_local_energy and nqs_log_psi_grad
- *    (about n * n_hidden complex values in the compute precision). Growing it allocates
- *    and synchronises the device; calls with one handle must therefore be issued on one
- *    stream.
+ *    nqs_sample (local energies evaluated after the sweep, and the chains' hidden angles
+ *    of float models with more than 256 hidden units), nqs_local_energy and
+ *    nqs_log_psi_grad (about n * n_hidden complex values in the compute precision, or
+ *    n_chains * n_hidden complex doubles). Growing it allocates and synchronises the
+ *    device; calls with one handle must therefore be issued on one stream.
  *  - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL = the null
  *    stream), except where a call states it synchronises.
  *  - Argument errors are detected on the host before any launch and returned as

@@ -291,14 +291,18 @@ nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int
   const bool fuse = eloc && int64_t(n_chains) >= 16 * int64_t(m->cu_count) &&
                     (m->M + 63) / 64 <= 4;
   const int64_t n = int64_t(n_sweeps) * n_chains;
-  if (eloc && !fuse) {
-    nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
+  // one scratch buffer serves the wide sweep's chain angles, then the local energies
+  size_t need = sweep_scratch_bytes(m, n_chains);
+  if (eloc && !fuse && grad_scratch_bytes(m, n) > need) need = grad_scratch_bytes(m, n);
+  if (need) {
+    nqs_status s = ensure_scratch(m, need);
     if (s != NQS_OK) return s;
   }
   hipError_t e = launch_tables(m, params, st);
   if (e == hipSuccess)
     e = launch_sweep(m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter, chain_offset,
-                     samples, n_accepted, fuse ? eloc : nullptr, st);
+                     samples, n_accepted, fuse ? eloc : nullptr,
+                     sweep_scratch_bytes(m, n_chains) ? m->d_scratch : nullptr, st);
   if (e == hipSuccess && eloc && !fuse) {
     e = launch_theta_tanh(m, samples, n, m->d_scratch, false, st);
     if (e == hipSuccess)

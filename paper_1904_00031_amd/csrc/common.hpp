@@ -160,55 +160,6 @@ __device__ __forceinline__ V<T, C> vtanh(V<T, C> z) {
   }
 }
 
-// cosh(2 d) and sinh(2 d) of a (complex) angle d. Single precision: the hardware
-// exponential and reciprocal, with sinh of a small real part from its series (no
-// cancellation between e and 1/e); sine and cosine of the imaginary part from their
-// Taylor series to the y^9 / y^10 terms when every lane's |y| < 1/2 (truncation below
-// 2e-11), else the library sincosf; each result within a few units of 2^-24 of
-// max(1, |value|). Double precision: the library functions.
-template <typename T, bool C>
-__device__ __forceinline__ void vcosh_sinh2(V<T, C> d, V<T, C> &ch_out, V<T, C> &sh_out) {
-  const T x = T(2) * d.re;
-  T ch, sh;
-  if constexpr (sizeof(T) == 4) {
-    const float e = __expf(x);
-    const float ei = __builtin_amdgcn_rcpf(e);
-    const float x2 = x * x;
-    const float series = x * (1.f + x2 * (1.f / 6.f + x2 * (1.f / 120.f)));
-    ch = 0.5f * (e + ei);
-    sh = fabsf(x) < 0.125f ? series : 0.5f * (e - ei);
-  } else {
-    ch = cosh(x);
-    sh = sinh(x);
-  }
-  if constexpr (C) {
-    const T y = T(2) * d.im;
-    T sy, cy;
-    if constexpr (sizeof(T) == 4) {
-      if (__ballot(fabsf(y) >= 0.5f) == 0) {
-        const float y2 = y * y;
-        sy = y * (1.f - y2 * (1.f / 6.f) *
-                            (1.f - y2 * (1.f / 20.f) *
-                                       (1.f - y2 * (1.f / 42.f) * (1.f - y2 * (1.f / 72.f)))));
-        cy = 1.f - y2 * 0.5f *
-                       (1.f - y2 * (1.f / 12.f) *
-                                  (1.f - y2 * (1.f / 30.f) *
-                                             (1.f - y2 * (1.f / 56.f) *
-                                                        (1.f - y2 * (1.f / 90.f)))));
-      } else {
-        sincosf(y, &sy, &cy);
-      }
-    } else {
-      sincos(y, &sy, &cy);
-    }
-    ch_out = vmake<T, C>(ch * cy, sh * sy);
-    sh_out = vmake<T, C>(sh * cy, ch * sy);
-  } else {
-    ch_out = vmake<T, C>(ch, T(0));
-    sh_out = vmake<T, C>(sh, T(0));
-  }
-}
-
 template <typename T, bool C>
 __device__ __forceinline__ V<T, C> vlncosh(V<T, C> z) {
   const T ln2 = T(0.69314718055994530942);

@@ -329,7 +329,8 @@ __device__ __forceinline__ void eloc_grouped(const DevModel &dm, const Tables<T>
 // TL, the C/S rows of every connected configuration (which then include the move rows)
 // and the W rows of the moves are staged in LDS; otherwise they are read from global
 // memory, with the next proposal's rows fetched one step ahead for small R (the
-// counter-based stream makes the next proposal known). After each recorded sweep the
+// counter-based stream makes the next proposal known). Float models with more than four
+// units per lane and tables in global memory run k_sweep_wide instead. After each recorded sweep the
 // chain's local energy is evaluated from its cached t.
 // ---------------------------------------------------------------------------------
 struct SweepArgs {
@@ -471,30 +472,6 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
       o.w[r] = row_ld(lW, gW, row, j);
     }
     return o;
-  };
-  // ST (float, more than four hidden units per lane): proposals streamed over the lane's
-  // hidden units, with no row arrays held in registers. RC: the angle change d = W_i (flip)
-  // or W_i - W_k (exchange) and cosh(2 d), sinh(2 d) are formed in registers from the W^T
-  // rows of the move's sites instead of reading the C/S/W table rows.
-  constexpr bool ST = false;
-  constexpr bool RC = false;
-  auto unit_d = [&](int row, int ic, int kc, int j) __attribute__((always_inline)) -> V<T, C> {
-    if constexpr (RC) {
-      V<T, C> d = vload<T, C>(tb.Wt, int64_t(ic) * M + j);
-      if (!flip) d = vsub(d, vload<T, C>(tb.Wt, int64_t(kc) * M + j));
-      return d;
-    } else {
-      return row_ld(lW, gW, row, j);
-    }
-  };
-  auto unit_cs = [&](int row, int ic, int kc, int j, V<T, C> &cc,
-                     V<T, C> &ss) __attribute__((always_inline)) {
-    if constexpr (RC) {
-      vcosh_sinh2<T, C>(unit_d(row, ic, kc, j), cc, ss);
-    } else {
-      cc = row_ld(lC, gC, row, j);
-      ss = row_ld(lS, gS, row, j);
-    }
   };
   int64_t acc_count = 0;
   for (int sw = 0; sw < total; ++sw) {
@@ -648,41 +625,6 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
           if (sk != s) {  // an exchange of equal spins is the identity move
           const T ts = T(s);
           int accept;
-          if constexpr (ST) {
-            // streamed over the lane's hidden units: the ratio terms and the decision (same
-            // grouping of four units per logarithm as below), then, on acceptance, the
-            // unit's factors read (or formed) again for the updates of theta and t
-            const int row = __builtin_amdgcn_readlane(rowv, l);
-            float lp = 0.f, pm = 1.f;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const int j = lane + 64 * r < M ? lane + 64 * r : 0;
-              V<T, C> cc, ss;
-              unit_cs(row, ic, kc, j, cc, ss);
-              const V<T, C> tm = vsub(cc, vscale(vmul(t[r], ss), ts));
-              if (lane + 64 * r < M) pm *= float(vabs2(tm));
-              if ((r & 3) == 3 || r == R - 1) {
-                lp += __log2f(pm);
-                pm = 1.f;
-              }
-            }
-            accept = wave_sum_gt(lp, readlane_v(s > 0 ? thp : thm, l));
-            if (accept) {
-#pragma unroll
-              for (int r = 0; r < R; ++r) {
-                if (lane + 64 * r < M) {
-                  const int j = lane + 64 * r;
-                  V<T, C> cc, ss;
-                  unit_cs(row, ic, kc, j, cc, ss);
-                  const V<T, C> d = unit_d(row, ic, kc, j);
-                  const V<T, C> tm = vsub(cc, vscale(vmul(t[r], ss), ts));
-                  thr[r] -= 2.0 * double(s) * double(d.re);
-                  if (C) thi[r] -= 2.0 * double(s) * double(d.im);
-                  t[r] = vdiv(vsub(vmul(cc, t[r]), vscale(ss, ts)), tm);
-                }
-              }
-            }
-          } else {
           if constexpr (!PF) cur = load_rows(__builtin_amdgcn_readlane(rowv, l));
           V<T, C> term[R];
 #pragma unroll
@@ -745,7 +687,6 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
                   t[r] = vdiv(vsub(vmul(cur.c[r], t[r]), vscale(cur.s[r], ts)), term[r]);
               }
             }
-          }
           }
           if (accept) {
               // spin registers (one lane each) and the LDS copy
@@ -828,6 +769,288 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
 template <typename T, bool C, int R, bool TL, bool SM>
 __global__ __launch_bounds__(256) void k_sweep(DevModel dm, Tables<T> tb, SweepArgs a) {
   sweep_block<T, C, R, TL, SM, (R <= 4)>(dm, tb, a, blockIdx.x * (blockDim.x >> 6));
+}
+
+// ---------------------------------------------------------------------------------
+// Metropolis sweeps of wide models (float forms, more than 256 hidden units): the hidden
+// units of one chain are split over the G wavefronts of a block, 64 KW units per
+// wavefront (lane l of wavefront w owns units 64 (KW w + r) + l, r < KW), so that each
+// wavefront holds few angles and rows and several blocks share a compute unit. Every
+// wavefront draws the same random numbers and keeps its own copy of the spins. A proposal:
+// each wavefront forms the ratio terms of its units and the float logarithm of their
+// product in groups of four units per lane, sums it over its lanes (DPP) and writes the sum
+// to LDS; after one barrier every wavefront adds the G sums in wavefront order and takes
+// the same decision (slots alternate between consecutive non-identity proposals, so one
+// barrier per proposal suffices). Theta is cached in double, t = tanh theta in float,
+// updated as in k_sweep and recomputed from theta after every sweep. The C/S/W rows of a
+// move are read from the parameter tables once the move is known not to be the identity.
+// ---------------------------------------------------------------------------------
+constexpr int kWideUnits = 8;   // hidden units per lane of one wavefront
+
+// sum over the wavefront of x, valid in lane 63: DPP row sums, then the row broadcasts
+__device__ __forceinline__ float wave_sum_to_last(float x) {
+  x += dpp_v<DPP_QP_XOR1>(x);
+  x += dpp_v<DPP_QP_XOR2>(x);
+  x += dpp_v<DPP_ROR4>(x);
+  x += dpp_v<DPP_ROR8>(x);
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), DPP_BCAST15, 0xA, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), DPP_BCAST31, 0xC, 0xF, false));
+  return x;
+}
+
+// Hidden angles theta[c][j] = b_j + sum_i W_ji sigma_ci of every chain in double on the
+// FP64 matrix cores (16x16x4): a wavefront takes 16 chains x 64 hidden units (four 16-unit
+// tiles), the spins (+/-1) and the float weights are exact in double, so only the order of
+// the double additions differs from a sequential sum. Grid (ceil(C / 64), ceil(M / 64)).
+template <bool C>
+__global__ __launch_bounds__(256) void k_theta64(int N, int M, int n_chains,
+                                                 const int8_t *__restrict__ sigma,
+                                                 const float *__restrict__ Wt,
+                                                 const float *__restrict__ bv, double *theta) {
+  typedef double doublex4_t __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lo = lane & 15, hi = lane >> 4;
+  const int c0 = blockIdx.x * 64 + wid * 16;
+  const int jb = blockIdx.y * 64;
+  const int crow = c0 + lo;
+  const int8_t *srow = sigma + int64_t(crow < n_chains ? crow : 0) * N;
+  doublex4_t ar[4], ai[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ar[q] = doublex4_t{0, 0, 0, 0};
+    ai[q] = doublex4_t{0, 0, 0, 0};
+  }
+  for (int k0 = 0; k0 < N; k0 += 4) {
+    const int k = k0 + hi;
+    const double a = (crow < n_chains && k < N) ? double(srow[k]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = jb + 16 * q + lo;
+      const bool ok = k < N && j < M;
+      const int64_t e = ok ? int64_t(k) * M + j : 0;
+      const double wr = ok ? double(C ? Wt[2 * e] : Wt[e]) : 0.0;
+      ar[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wr, ar[q], 0, 0, 0);
+      if constexpr (C) {
+        const double wi = ok ? double(Wt[2 * e + 1]) : 0.0;
+        ai[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wi, ai[q], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = jb + 16 * q + lo;
+    if (j >= M) continue;
+    const double br = C ? double(bv[2 * j]) : double(bv[j]);
+    const double bi = C ? double(bv[2 * j + 1]) : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = c0 + hi + 4 * r;
+      if (c >= n_chains) continue;
+      if (C) {
+        theta[2 * (int64_t(c) * M + j)] = ar[q][r] + br;
+        theta[2 * (int64_t(c) * M + j) + 1] = ai[q][r] + bi;
+      } else {
+        theta[int64_t(c) * M + j] = ar[q][r] + br;
+      }
+    }
+  }
+}
+
+template <bool C>
+__global__ __launch_bounds__(256, 3) void k_sweep_wide(DevModel dm, Tables<float> tb, SweepArgs a,
+                                                    int G, const double *__restrict__ theta0) {
+  typedef float T;
+  constexpr int KW = kWideUnits;
+  extern __shared__ __align__(16) unsigned char lds_u8[];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int chain = blockIdx.x;
+  const int N = dm.N, M = dm.M;
+  const bool flip = dm.move == NQS_MOVE_FLIP;
+  const T *gC = flip ? tb.fC : tb.bC;
+  const T *gS = flip ? tb.fS : tb.bS;
+  const T *gW = flip ? tb.Wt : tb.Wd;
+  // LDS: spins of every wavefront [G][Npad], the two slot rows of wavefront sums [2][G],
+  // then |visible-bias factor|^2 [2][rows] and the color-0 bonds [B0][2]
+  int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + int64_t(wid) * a.Npad);
+  float *slots = reinterpret_cast<float *>(lds_u8 + int64_t(G) * a.Npad);
+  const int afn = flip ? N : dm.Btot;
+  const int64_t aux_off = (int64_t(G) * a.Npad + 8 * G + 15) & ~int64_t(15);
+  double *la2 = reinterpret_cast<double *>(lds_u8 + aux_off);
+  int *lbond = reinterpret_cast<int *>(la2 + 2 * afn);
+  {
+    const double *afb = flip ? tb.fa : tb.ba;
+    for (int e = threadIdx.x; e < 2 * afn; e += blockDim.x)
+      la2[e] = afb[2 * e] * afb[2 * e] + afb[2 * e + 1] * afb[2 * e + 1];
+    if (!flip)
+      for (int e = threadIdx.x; e < 2 * dm.B0; e += blockDim.x) lbond[e] = dm.bonds[e];
+  }
+  for (int i = lane; i < N; i += 64) sig[i] = a.chain_sigma[int64_t(chain) * N + i];
+  __syncthreads();
+
+  // this lane's units, their angles in double and t = tanh(theta) in float
+  const int j0 = 64 * KW * wid + lane;
+  double thr[KW], thi[KW];
+  V<T, C> t[KW];
+#pragma unroll
+  for (int r = 0; r < KW; ++r) {
+    const int j = j0 + 64 * r;
+    thr[r] = 0.0;
+    thi[r] = 0.0;
+    t[r] = vmake<T, C>(T(0), T(0));
+    if (j < M) {
+      V<double, C> acc;
+      if (theta0) {
+        acc = vload<double, C>(theta0, int64_t(chain) * M + j);
+      } else {
+        acc = vload<double, C>(tb.bv, j);
+        for (int i = 0; i < N; ++i) {
+          const double sv = double(sig[i]);
+          V<double, C> w = vload<double, C>(tb.Wt, int64_t(i) * M + j);
+          acc.re += sv * w.re;
+          if (C) acc.im += sv * w.im;
+        }
+      }
+      thr[r] = acc.re;
+      thi[r] = C ? acc.im : 0.0;
+      t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
+    }
+  }
+  const uint32_t cid = a.chain_offset + uint32_t(chain);
+  const int total = a.n_discard + a.n_sweeps;
+  const bool sregs = N <= 256;
+  int sp0 = 0, sp1 = 0, sp2 = 0, sp3 = 0;
+  if (sregs) {
+    sp0 = lane < N ? sig[lane] : 0;
+    sp1 = lane + 64 < N ? sig[lane + 64] : 0;
+    sp2 = lane + 128 < N ? sig[lane + 128] : 0;
+    sp3 = lane + 192 < N ? sig[lane + 192] : 0;
+  }
+  int64_t acc_count = 0;
+  int parity = 0;
+  for (int sw = 0; sw < total; ++sw) {
+    for (int st0 = 0; st0 < N; st0 += 64) {
+      const int nst = N - st0 < 64 ? N - st0 : 64;
+      int rowv = 0, iv = 0, kv = 0;
+      float thp = 0.f, thm = 0.f;
+      if (lane < nst) {
+        const Philox4 w = philox4x32_10(cid, a.counter + uint32_t(sw), uint32_t(st0 + lane),
+                                        TAG_PROPOSAL, a.k0, a.k1);
+        if (flip) {
+          iv = rng_index(w.w[0], uint32_t(N));
+          rowv = iv;
+          kv = iv;
+        } else {
+          rowv = rng_index(w.w[0], uint32_t(dm.B0));
+          iv = lbond[2 * rowv];
+          kv = lbond[2 * rowv + 1];
+        }
+        const double uv = rng_uniform(w.w[1], w.w[2]);
+        const float lu = __log2f(float(uv));
+        thp = lu - __log2f(float(la2[rowv]));
+        thm = lu - __log2f(float(la2[afn + rowv]));
+      }
+      for (int l = 0; l < nst; ++l) {
+        const int ic = __builtin_amdgcn_readlane(iv, l);
+        const int kc = __builtin_amdgcn_readlane(kv, l);
+        int s, sk;
+        if (sregs) {
+          s = __builtin_amdgcn_readlane(ic < 64 ? sp0 : (ic < 128 ? sp1 : (ic < 192 ? sp2 : sp3)),
+                                        ic & 63);
+          sk = flip ? -s
+                    : __builtin_amdgcn_readlane(
+                          kc < 64 ? sp0 : (kc < 128 ? sp1 : (kc < 192 ? sp2 : sp3)), kc & 63);
+        } else {
+          s = __builtin_amdgcn_readfirstlane(int(sig[ic]));
+          sk = flip ? -s : __builtin_amdgcn_readfirstlane(int(sig[kc]));
+        }
+        if (sk == s) continue;  // an exchange of equal spins is the identity move
+        const int row = __builtin_amdgcn_readlane(rowv, l);
+        const T ts = T(s);
+        V<T, C> cc[KW], ss[KW], term[KW];
+#pragma unroll
+        for (int r = 0; r < KW; ++r) {
+          const int j = j0 + 64 * r < M ? j0 + 64 * r : 0;
+          cc[r] = vload<T, C>(gC, int64_t(row) * M + j);
+          ss[r] = vload<T, C>(gS, int64_t(row) * M + j);
+        }
+        float lp = 0.f;
+#pragma unroll
+        for (int r0 = 0; r0 < KW; r0 += 4) {
+          float pm = 1.f;
+#pragma unroll
+          for (int r = r0; r < r0 + 4; ++r) {
+            term[r] = vsub(cc[r], vscale(vmul(t[r], ss[r]), ts));
+            if (j0 + 64 * r < M) pm *= float(vabs2(term[r]));
+          }
+          lp += __log2f(pm);
+        }
+        const float wsum = wave_sum_to_last(lp);
+        if (lane == 63) slots[parity * G + wid] = wsum;
+        __syncthreads();
+        float tot = 0.f;
+        for (int g = 0; g < G; ++g) tot += slots[parity * G + g];
+        parity ^= 1;
+        const float th = readlane_v(s > 0 ? thp : thm, l);
+        const int accept = __builtin_amdgcn_readfirstlane(int(tot > th));
+        if (accept) {
+          // the angle change (W row of the move) is read only for accepted moves
+          V<T, C> ww[KW];
+#pragma unroll
+          for (int r = 0; r < KW; ++r)
+            ww[r] = vload<T, C>(gW, int64_t(row) * M + (j0 + 64 * r < M ? j0 + 64 * r : 0));
+#pragma unroll
+          for (int r = 0; r < KW; ++r) {
+            if (j0 + 64 * r < M) {
+              thr[r] -= 2.0 * double(s) * double(ww[r].re);
+              if (C) thi[r] -= 2.0 * double(s) * double(ww[r].im);
+              t[r] = vdiv(vsub(vmul(cc[r], t[r]), vscale(ss[r], ts)), term[r]);
+            }
+          }
+          if (sregs) {
+            if (ic < 64)
+              sp0 = lane == (ic & 63) ? -s : sp0;
+            else if (ic < 128)
+              sp1 = lane == (ic & 63) ? -s : sp1;
+            else if (ic < 192)
+              sp2 = lane == (ic & 63) ? -s : sp2;
+            else
+              sp3 = lane == (ic & 63) ? -s : sp3;
+            if (!flip) {
+              if (kc < 64)
+                sp0 = lane == (kc & 63) ? s : sp0;
+              else if (kc < 128)
+                sp1 = lane == (kc & 63) ? s : sp1;
+              else if (kc < 192)
+                sp2 = lane == (kc & 63) ? s : sp2;
+              else
+                sp3 = lane == (kc & 63) ? s : sp3;
+            }
+          }
+          if (lane == 0) {
+            sig[ic] = int8_t(-s);
+            if (!flip) sig[kc] = int8_t(s);
+          }
+          if (!sregs) wave_sync();
+          ++acc_count;
+        }
+      }
+    }
+    wave_sync();
+    // end of sweep: tanh from the exact angles
+#pragma unroll
+    for (int r = 0; r < KW; ++r)
+      if (j0 + 64 * r < M) t[r] = vtanh<T, C>(vmake<T, C>(T(thr[r]), T(thi[r])));
+    if (wid == 0 && sw >= a.n_discard) {
+      const int64_t smp = int64_t(sw - a.n_discard) * a.n_chains + chain;
+      int8_t *dst = a.samples + smp * N;
+      for (int i = lane; i < N; i += 64) dst[i] = sig[i];
+    }
+  }
+  if (wid == 0) {
+    for (int i = lane; i < N; i += 64) a.chain_sigma[int64_t(chain) * N + i] = sig[i];
+    if (lane == 0 && a.n_acc) a.n_acc[chain] = acc_count;
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -1301,7 +1524,7 @@ inline size_t sweep_aux_lds(const nqs_model *m) {
 template <typename T, bool C, int R>
 hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, int n_discard,
                    uint64_t seed, uint64_t counter, int chain_offset, int8_t *samples,
-                   int64_t *n_acc, void *eloc, hipStream_t st) {
+                   int64_t *n_acc, void *eloc, void *scratch, hipStream_t st) {
   const int wpb = 4;
   SweepArgs a;
   a.chain_sigma = cs;
@@ -1342,6 +1565,27 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
       return hipGetLastError();
     }
   }
+  if constexpr (sizeof(T) == 4 && R > 4) {
+    if (!tl) {
+      // wide models: the chains' angles on the matrix cores (into the model's scratch, when
+      // given), then the hidden units of a chain split over G wavefronts of one block
+      const double *th0 = nullptr;
+      if (scratch) {
+        hipLaunchKernelGGL((k_theta64<C>), dim3((n_chains + 63) / 64, (m->M + 63) / 64),
+                           dim3(256), 0, st, m->N, m->M, n_chains, (const int8_t *)cs,
+                           (const float *)m->tab_ptrs[0], (const float *)m->tab_ptrs[1],
+                           (double *)scratch);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        th0 = (const double *)scratch;
+      }
+      const int G = (m->M + 64 * kWideUnits - 1) / (64 * kWideUnits);
+      const size_t lds = ((size_t(G) * a.Npad + 8 * G + 15) / 16 * 16) + aux;
+      hipLaunchKernelGGL((k_sweep_wide<C>), dim3(n_chains), dim3(64 * G), lds, st,
+                         dev_model(m), tables_of<float>(m), a, G, th0);
+      return hipGetLastError();
+    }
+  }
   if (tl) {
     hipLaunchKernelGGL((k_sweep<T, C, R, true, false>), grid, dim3(64 * wpb),
                        with_aux(tab_lds + wave_lds), st, dev_model(m), tables_of<T>(m), a);
@@ -1355,12 +1599,12 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
 template <typename T, bool C>
 hipError_t sweep_t(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, int n_discard,
                    uint64_t seed, uint64_t counter, int chain_offset, int8_t *samples,
-                   int64_t *n_acc, void *eloc, hipStream_t st) {
+                   int64_t *n_acc, void *eloc, void *scratch, hipStream_t st) {
   int r = (m->M + 63) / 64;
 #define NQS_SWEEP_CASE(RR)                                                                 \
   if (r <= RR)                                                                             \
     return sweep_r<T, C, RR>(m, cs, n_chains, n_sweeps, n_discard, seed, counter,          \
-                             chain_offset, samples, n_acc, eloc, st);
+                             chain_offset, samples, n_acc, eloc, scratch, st);
   NQS_SWEEP_CASE(1)
   NQS_SWEEP_CASE(2)
   NQS_SWEEP_CASE(4)
@@ -1664,9 +1908,16 @@ hipError_t launch_chain_init(const nqs_model *m, int8_t *sig, int n_chains, uint
 
 hipError_t launch_sweep(const nqs_model *m, int8_t *chain_sigma, int n_chains, int n_sweeps,
                         int n_discard, uint64_t seed, uint64_t counter, int chain_offset,
-                        int8_t *samples, int64_t *n_acc, void *eloc, hipStream_t st) {
+                        int8_t *samples, int64_t *n_acc, void *eloc, void *scratch,
+                        hipStream_t st) {
   return NQS_DISPATCH(sweep_t, m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter,
-                      chain_offset, samples, n_acc, eloc, st);
+                      chain_offset, samples, n_acc, eloc, scratch, st);
+}
+
+size_t sweep_scratch_bytes(const nqs_model *m, int n_chains) {
+  // the wide sweep's angles [chains][M] in (complex) double; other shapes need none
+  const bool wide = !use_double(m) && (m->M + 63) / 64 > 4;
+  return wide ? size_t(n_chains) * m->M * (m->is_complex ? 16 : 8) : 0;
 }
 
 hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, const void *Tm,
