@@ -13,6 +13,8 @@ cites, in float64 / complex128 numpy. Modules:
 * ``lattice``      - hypercubic graphs with colored edges (Sec. 2.2.1).
 * ``philox``       - Philox4x32-10 counter-based generator (Salmon et al., SC'11).
 * ``rbm``          - RBM amplitude and its analytic log-derivatives (Sec. 2.2.2, 2.2.5).
+* ``rbm_symm``     - the symmetric RBM (RbmSpinSymm, Sec. 2.2.2): filters shared over a
+                     group of lattice symmetries.
 * ``hamiltonian``  - TFIM / Heisenberg / J1-J2 connected elements and the local
                      energy of Eq. 5 (Sec. 2.2.1, 2.2.5).
 * ``sampler``      - Metropolis chains on |psi|^2 (Eq. 4, Sec. 2.2.5).

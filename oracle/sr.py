@@ -103,6 +103,11 @@ def sr_step(model, params, samples, eloc, lr, diag_shift, cg_tol, cg_maxiter, we
     """One SR update from samples [n, N] and their local energies [n].
     Returns (new_params, info dict). round_tanh: see rbm.log_derivatives."""
     O = rbm.log_derivatives(params, samples, model.n_sites, model.n_hidden, round_tanh)
+    return sr_step_from_O(O, params, eloc, lr, diag_shift, cg_tol, cg_maxiter, weights)
+
+
+def sr_step_from_O(O, params, eloc, lr, diag_shift, cg_tol, cg_maxiter, weights=None):
+    """The SR update of any ansatz from its log-derivatives O [n, P] at the samples."""
     e = np.asarray(eloc)
     if not np.iscomplexobj(params):
         O = O.real
