@@ -35,6 +35,7 @@ import numpy as np
 PEAK_FP32_VALU = 157.3e12
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64 = 78.6e12
+PEAK_BF16_MFMA = 2500e12
 PEAK_HBM = 8.0e12
 
 HEADLINE = "heis16x16_cplx_bf16_alpha8"
@@ -66,9 +67,16 @@ WORKLOADS = {
                                         marshall=True, move=1, cplx=True, prec=2, alpha=4,
                                         chains=4096, sweeps=2, lr=0.01, shift=0.01,
                                         cg_tol=1e-8, cg_maxiter=500),
+    # the symmetric RBM (filters shared over the 256 translations) on the 16x16 lattice,
+    # alpha = 8 (the same 2048 hidden units, 2057 parameters), BF16 form
+    "heis16x16_symm_cplx_bf16_alpha8": dict(L=16, ndim=2, diag=False, ham=1, J=(1.0, 0.0), h=0.0,
+                                            marshall=True, move=1, cplx=True, prec=2, alpha=8,
+                                            chains=8192, sweeps=1, lr=0.01, shift=0.01,
+                                            cg_tol=1e-8, cg_maxiter=500, symm=True),
 }
 EXTRA_SINGLE = ["heisenberg1d_n40_cplx_fp32_alpha2", "tfim1d_n10_real_fp64_alpha1",
-                "j1j2_10x10_cplx_fp32_alpha4", "j1j2_10x10_cplx_bf16_alpha4"]
+                "j1j2_10x10_cplx_fp32_alpha4", "j1j2_10x10_cplx_bf16_alpha4",
+                "heis16x16_symm_cplx_bf16_alpha8"]
 
 # batches of independent models: 64 periodic TFIM rings, N uniform in [16, 128], h uniform in
 # [0.5, 1.5] (numpy PCG64, seed 1234), real FP32 RBM alpha = 2 each, 256 chains x 4 sweeps
@@ -197,10 +205,16 @@ class Single:
         self.C, self.S = w["chains"], w["sweeps"]
         bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
         self.bonds0 = torch.from_numpy(np.asarray(bonds[0], dtype=np.int64)).to(self.dev)
+        symm = nqs.nqs_hypercube_translations(w["L"], w["ndim"]) if w.get("symm") else None
         self.model = nqs.Model(N, M, bonds, ham=w["ham"], J=w["J"], h=w["h"],
                                marshall=w["marshall"], sublattice=sub, move=w["move"],
-                               is_complex=w["cplx"], prec=self.prec)
-        p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
+                               is_complex=w["cplx"], prec=self.prec, symm=symm)
+        if symm is None:
+            p = synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)
+        else:
+            rng = np.random.default_rng(1234)
+            P = self.model.n_params
+            p = rng.normal(0.0, 0.01, P) + (1j * rng.normal(0.0, 0.01, P) if w["cplx"] else 0)
         self.params = torch.from_numpy(p).to(self.dev).to(self.model.param_dtype)
         self.chains = torch.empty((self.C, N), dtype=torch.int8, device=self.dev)
         self.model.chain_init(self.chains, seed=1234)
@@ -238,8 +252,15 @@ class Single:
         b = self.bonds0
         return float((s[:, b[:, 0]] != s[:, b[:, 1]]).float().mean().item())
 
+    def fused_eloc(self):
+        """Whether nqs_sample evaluates the local energies inside the sweep (at least 16
+        chains per compute unit and at most 256 hidden units)."""
+        cus = self.torch.cuda.get_device_properties(0).multi_processor_count
+        return self.C >= 16 * cus and self.M <= 256
+
     def run(self, steps, warmup, tune=True):
         torch, m, w = self.torch, self.model, self.w
+        nqs = sys.modules["paper_1904_00031_amd"]
         tuning = m.autotune(self.params, self.chains.repeat(self.S, 1), workspace=self.ws) \
             if tune else None
         for k in range(warmup):
@@ -247,105 +268,102 @@ class Single:
             log("%s warmup %d: E=%.6f +- %.2e cg_iters=%d" % (self.name, k, info["energy_re"],
                                                                 info["energy_err"], info["cg_iters"]))
         torch.cuda.synchronize()
-        times = []
+        # the sweep kernel of every timed step is bracketed by HIP events on its stream
+        m.time_kernel(nqs.TIME_SWEEP)
+        times, sweep_k = [], []
         t0 = time.perf_counter()
         for _ in range(steps):
-            self.step(0, times)
+            self.step(0, times)          # the SR step synchronises the stream
+            sweep_k.append(m.kernel_ms())
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        m.time_kernel(nqs.TIME_NONE)
         samp_ms = sum(e[0].elapsed_time(e[1]) for e, _ in times) / steps
         sr_ms = sum(e[1].elapsed_time(e[2]) for e, _ in times) / steps
         infos = [i for _, i in times]
         ms_per_step = wall * 1e3 / steps
         n = self.S * self.C
         f_real = self.real_move_fraction()
+        sweep_ms = float(np.mean(sweep_k))
 
-        # live per-launch timing (HIP events on the launch stream) of the kernels that carry
-        # the work: the sweep (a sampling call without local energies: the parameter-table
-        # refresh and the sweep kernel), the local energies of the samples, one S v product
-        reps = 3
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        smp = torch.empty_like(self.samples)
-        chains = self.chains.clone()
-        m.sample(self.params, chains, self.S, 0, seed=99, counter=10 ** 6, samples=smp)
-        ev[0].record(self.stream)
-        for r in range(reps):
-            m.sample(self.params, chains, self.S, 0, seed=99, counter=10 ** 6 + r * self.S,
-                     samples=smp)
-        ev[1].record(self.stream)
-        torch.cuda.synchronize()
-        sweep_ms = ev[0].elapsed_time(ev[1]) / reps
+        # after the timed region: the local-energy kernel and one S v product (the CG's
+        # products replay from graphs), each bracketed by the library's events
         flat = self.samples.view(n, self.N)
         el2 = torch.empty_like(self.eloc)
-        m.local_energy(self.params, flat, out=el2)
-        ev[0].record(self.stream)
+        reps = 5
+        m.time_kernel(nqs.TIME_ELOC)
+        el_k = []
         for _ in range(reps):
             m.local_energy(self.params, flat, out=el2)
-        ev[1].record(self.stream)
-        torch.cuda.synchronize()
-        eloc_ms = ev[0].elapsed_time(ev[1]) / reps
+            el_k.append(m.kernel_ms())
+        eloc_ms = float(np.mean(el_k[1:]))
         sv_ws = m.sr_prepare(self.params, flat, workspace=self.ws)
         gen = torch.Generator(device="cpu").manual_seed(5)
         v = torch.randn(m.n_params, dtype=m.value_dtype, generator=gen).to(self.dev)
         sv_out = torch.empty_like(v)
-        m.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
-        sv_reps = 20
-        ev[0].record(self.stream)
-        for _ in range(sv_reps):
+        m.time_kernel(nqs.TIME_SV)
+        sv_k = []
+        for _ in range(21):
             m.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
-        ev[1].record(self.stream)
-        torch.cuda.synchronize()
-        mv_ms = ev[0].elapsed_time(ev[1]) / sv_reps
+            sv_k.append(m.kernel_ms())
+        m.time_kernel(nqs.TIME_NONE)
+        mv_ms = float(np.mean(sv_k[1:]))
         cg_mean = float(np.mean([i["cg_iters"] for i in infos]))
 
-        # roofline of the dominant kernel of the step
+        # roofline of the kernel (or the S v product) that takes most of a step
         cplx = w["cplx"]
         sweep_flops = float(self.C) * self.S * self.N * f_real * self.M * sweep_terms_flops(cplx)
-        sv_share = mv_ms * cg_mean
+        share = {"sweep": sweep_ms, "sv": mv_ms * cg_mean,
+                 "eloc": 0.0 if self.fused_eloc() else eloc_ms}
+        dom = max(share, key=share.get)
         plane_split = cplx and self.prec != 0 and self.N <= 63
-        if sweep_ms >= sv_share and sweep_ms >= eloc_ms:
+        if dom == "sweep":
             peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_VALU
             ach = sweep_flops / (sweep_ms * 1e-3)
-            roof = {"kernel": "k_sweep (Metropolis sweep, one chain per wavefront)",
+            roof = {"kernel": "k_sweep_wide" if (self.prec != 0 and self.M > 256) else "k_sweep",
                     "bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": ach / peak,
                     "traffic": recorded_traffic("k_sweep", self.name),
                     "algorithmic_flops": sweep_flops, "launch_ms": sweep_ms,
                     "real_move_fraction": f_real}
-        elif plane_split and sv_share >= eloc_ms:
+        elif dom == "sv" and plane_split:
             nbytes = sv_bytes(n, self.N, self.M, cplx, True)
             ach = nbytes / (mv_ms * 1e-3)
-            roof = {"kernel": "S v product (direction tables, fused contraction, partial-sum "
-                              "reduction, centring)", "bound": "hbm",
+            roof = {"kernel": "S v product: k_prep_dir + k_svc + k_cg_apr", "bound": "hbm",
                     "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                     "frac": ach / PEAK_HBM, "traffic": recorded_traffic("sv_product", self.name),
                     "algorithmic_bytes": nbytes, "launch_ms": mv_ms,
                     "fp32_equivalent_tflops": sv_flops(n, self.N, self.M, cplx) / (mv_ms * 1e-3) / 1e12}
-        elif sv_share >= eloc_ms:
+        elif dom == "sv":
+            # the contractions run on the bf16 matrix cores with the float operand split
+            # exactly into three bf16 parts: float arithmetic, reported against the float
+            # matrix peak, with the bf16 peak alongside (3x the flops on bf16 instructions)
             peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_MFMA
             fl = sv_flops(n, self.N, self.M, cplx)
             ach = fl / (mv_ms * 1e-3)
-            roof = {"kernel": "S v product (JVP and VJP contractions)", "bound": "mfma",
-                    "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                    "frac": ach / peak, "traffic": recorded_traffic("sv_product", self.name),
+            roof = {"kernel": "S v product: k_prep_dir + k_jvp32 + k_jvp_finish + k_vjp + k_cg_apr"
+                              if self.prec != 0 else "S v product (FP64 matrix cores)",
+                    "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / peak,
+                    "traffic": recorded_traffic("sv_product", self.name),
                     "algorithmic_flops": fl, "launch_ms": mv_ms}
+            if self.prec != 0:
+                roof["bf16_split_frac_of_bf16_peak"] = 3 * fl / (mv_ms * 1e-3) / PEAK_BF16_MFMA
         else:
             peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_VALU
-            # connected configurations of the samples: every site (TFIM) or the bonds with
-            # opposite spins (Heisenberg, both colors)
             fl = float(n) * self.N * f_real * self.M * sweep_terms_flops(cplx)
             ach = fl / (eloc_ms * 1e-3)
             roof = {"kernel": "local energy", "bound": "alu", "achieved": ach / 1e12,
                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                     "algorithmic_flops": fl, "launch_ms": eloc_ms}
+        roof["step_share_ms"] = share
         return {
             "ms_per_step": ms_per_step, "samples_per_step": n,
             "value": n / (ms_per_step * 1e-3),
             "sr_iters_per_s": 1e3 / ms_per_step,
             "sampling_samples_per_s": n / (samp_ms * 1e-3),
             "phase_ms": {"sample_and_eloc": samp_ms, "sr_step": sr_ms},
-            "kernel_ms": {"sweep_call": sweep_ms, "local_energy_call": eloc_ms,
-                          "sv_product": mv_ms},
+            "kernel_ms": {"sweep": sweep_ms, "local_energy": eloc_ms, "sv_product": mv_ms},
             "cg_iters_mean": cg_mean,
             "energy_last": infos[-1]["energy_re"], "energy_err_last": infos[-1]["energy_err"],
             "sv_tuning": tuning, "roofline": roof,

@@ -20,8 +20,9 @@
  *  - A handle must not be used from two threads at once.
  *  - Spins are int8, +1 (up) or -1 (down). Configuration arrays are row-major [n, N].
  *  - RBM parameters are packed p = [a (N) | b (M) | W (M x N, row j, column i)], with
- *    P = N + M + N*M entries, in the model's master precision: double for NQS_F64,
- *    float for NQS_F32 and NQS_BF16; complex models interleave (re, im) pairs.
+ *    P = N + M + N*M entries (symmetric RBM: see nqs_model_desc), in the model's master
+ *    precision: double for NQS_F64, float for NQS_F32 and NQS_BF16; complex models
+ *    interleave (re, im) pairs.
  *  - Results that are per-configuration scalars (log psi, local energies, Jacobian
  *    products) and the SR vectors are always double (complex: interleaved double
  *    pairs), whatever the compute precision.
@@ -73,8 +74,16 @@ typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;
  *    swaps the spins of a uniform color-0 bond (conserves total magnetisation; chains
  *    are initialised at zero magnetisation, so N must be even).
  *  - n_hidden = M hidden units (alpha = M / N); is_complex selects complex parameters.
+ *  - n_symm > 0 selects the symmetric RBM (RbmSpinSymm, Sec. 2.2.2): a group of G =
+ *    n_symm site permutations, symm [G][n_sites] (host; g maps site i to symm[g][i], and
+ *    (T_g sigma)_i = sigma_symm[g][i]), and alpha = M / G filters; hidden unit (f, g)
+ *    has theta_fg = b_f + sum_i W_fi sigma_symm[g][i], so psi(T_g sigma) = psi(sigma) when
+ *    the permutations form a group. Parameters are then packed p = [a (1) | b (alpha) |
+ *    W (alpha x N, row f, column i)], P = 1 + alpha + alpha N (nqs_n_params). Every entry
+ *    point of a single model accepts such a model; the batch entry points do not.
  * Limits: 2 <= n_sites <= 1024, 1 <= n_hidden <= 2048, bonds within [0, n_sites),
- * i != j, n_bonds[0] >= 1 for exchange moves.
+ * i != j, n_bonds[0] >= 1 for exchange moves; n_symm divides n_hidden and every row of
+ * symm is a permutation of 0 .. n_sites - 1.
  */
 typedef struct {
   int32_t n_sites;
@@ -89,6 +98,8 @@ typedef struct {
   int32_t marshall;
   const int8_t *sublattice;     /* host [n_sites], 0/1; required when marshall != 0 */
   int32_t move;                 /* nqs_move */
+  int32_t n_symm;               /* 0: RBM; G > 0: symmetric RBM over G site permutations */
+  const int32_t *symm;          /* host [n_symm][n_sites]; NULL when n_symm == 0 */
 } nqs_model_desc;
 
 typedef struct nqs_model nqs_model;
@@ -119,6 +130,12 @@ typedef struct {
  * sublattice [L^ndim]; n_bonds[2] receives the counts. Requires 3 <= L <= 1024. */
 nqs_status nqs_hypercube(int32_t L, int32_t ndim, int32_t with_diagonals, int32_t *bonds0,
                          int32_t *bonds1, int8_t *sublattice, int32_t *n_bonds);
+
+/* The L^ndim translations of the periodic hypercube of nqs_hypercube as site
+ * permutations (the symmetry group of a symmetric RBM on it): perm (host) [L^ndim][L^ndim]
+ * receives perm[g][s] = site s moved by the lattice vector of site g (g = 0 is the
+ * identity). Requires 3 <= L and L^ndim <= 1024. */
+nqs_status nqs_hypercube_translations(int32_t L, int32_t ndim, int32_t *perm);
 
 /* Create a model handle: validates the description and uploads the bond tables. */
 nqs_status nqs_model_create(const nqs_model_desc *desc, nqs_model **out);
@@ -286,6 +303,19 @@ nqs_status nqs_set_sv_shape(nqs_model *model, int32_t pairs);
  * those of the plain launches. enable = 0 launches every kernel directly (for callers
  * that capture the whole step into a graph of their own). */
 nqs_status nqs_set_cg_graphs(nqs_model *model, int32_t enable);
+
+/* Timing of one kind of kernel launch, for measurement (no effect on results): while
+ * what != NQS_TIME_NONE the model records pairs of HIP events on the launch stream right
+ * before and right after the kernels of that kind in each call, and nqs_kernel_ms returns
+ * the sum of the times between the pairs of the last such call (it waits for them).
+ *  NQS_TIME_SWEEP - the Metropolis sweep kernel of nqs_sample (not the table refresh, the
+ *                   chain-angle set-up or local energies evaluated after the sweep)
+ *  NQS_TIME_SV    - the kernels of one nqs_sr_matvec product (direction tables, the
+ *                   contractions, the reduced product), without the gaps between them
+ *  NQS_TIME_ELOC  - the local-energy kernel of nqs_local_energy (not tanh(theta)) */
+typedef enum { NQS_TIME_NONE = 0, NQS_TIME_SWEEP = 1, NQS_TIME_SV = 2, NQS_TIME_ELOC = 3 } nqs_time_what;
+nqs_status nqs_time_kernel(nqs_model *model, int32_t what);
+nqs_status nqs_kernel_ms(nqs_model *model, float *ms);
 
 /* ---- Batches of independent models (uneven sizes) --------------------------------
  * A batch holds K models created from K descriptions (all with the same is_complex and

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnqs.so")
 
 F64, F32, BF16 = 0, 1, 2
+TIME_NONE, TIME_SWEEP, TIME_SV, TIME_ELOC = 0, 1, 2, 3
 TFIM, HEISENBERG = 0, 1
 MOVE_FLIP, MOVE_EXCHANGE = 0, 1
 OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
@@ -38,6 +39,7 @@ class _Desc(ctypes.Structure):
         ("n_bonds", ctypes.c_int32 * 2), ("bonds", ctypes.c_void_p * 2),
         ("ham", ctypes.c_int32), ("J", ctypes.c_double * 2), ("h", ctypes.c_double),
         ("marshall", ctypes.c_int32), ("sublattice", ctypes.c_void_p), ("move", ctypes.c_int32),
+        ("n_symm", ctypes.c_int32), ("symm", ctypes.c_void_p),
     ]
 
 
@@ -87,6 +89,7 @@ def load(path=LIB_PATH):
     sig = {
         "nqs_status_string": (ctypes.c_char_p, [i32]),
         "nqs_hypercube": (i32, [i32, i32, i32, vp, vp, vp, vp]),
+        "nqs_hypercube_translations": (i32, [i32, i32, vp]),
         "nqs_model_create": (i32, [ctypes.POINTER(_Desc), ctypes.POINTER(vp)]),
         "nqs_model_destroy": (None, [vp]),
         "nqs_n_params": (i64, [vp]),
@@ -105,6 +108,8 @@ def load(path=LIB_PATH):
         "nqs_sr_matvec": (i32, [vp, vp, i64, vp, ctypes.c_size_t, vp, f64, vp, vp]),
         "nqs_set_sv_shape": (i32, [vp, i32]),
         "nqs_set_cg_graphs": (i32, [vp, i32]),
+        "nqs_time_kernel": (i32, [vp, i32]),
+        "nqs_kernel_ms": (i32, [vp, ctypes.POINTER(ctypes.c_float)]),
         "nqs_batch_create": (i32, [ctypes.POINTER(_Desc), i32, ctypes.POINTER(vp)]),
         "nqs_batch_destroy": (None, [vp]),
         "nqs_batch_n_params": (i64, [vp, i32]),
@@ -127,11 +132,13 @@ def load(path=LIB_PATH):
 
 
 def exported_symbols():
-    return ["nqs_status_string", "nqs_hypercube", "nqs_model_create", "nqs_model_destroy",
+    return ["nqs_status_string", "nqs_hypercube", "nqs_hypercube_translations",
+            "nqs_model_create", "nqs_model_destroy",
             "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
             "nqs_log_psi_grad", "nqs_log_psi_grad_noalloc", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_step_async",
             "nqs_sr_prepare",
             "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_set_cg_graphs",
+            "nqs_time_kernel", "nqs_kernel_ms",
             "nqs_batch_create",
             "nqs_batch_destroy", "nqs_batch_n_params", "nqs_batch_chain_init",
             "nqs_batch_sample", "nqs_batch_sr_workspace_bytes", "nqs_batch_sr_step",
@@ -181,8 +188,19 @@ def nqs_hypercube(L, ndim, with_diagonals=False):
     return [b0[:nb[0]].copy(), b1[:nb[1]].copy()], sub
 
 
-def _fill_desc(d, n_sites, n_hidden, bonds, ham, J, h, marshall, sub, move, is_complex, prec):
-    """Fill an nqs_model_desc; bonds (two int32 [B, 2] arrays) and sub must stay alive."""
+def nqs_hypercube_translations(L, ndim):
+    """The L^ndim translations of the periodic hypercube as site permutations [G, N]."""
+    load()
+    n = L ** ndim
+    perm = np.zeros((n, n), dtype=np.int32)
+    _check(_lib.nqs_hypercube_translations(L, ndim, perm.ctypes.data), "nqs_hypercube_translations")
+    return perm
+
+
+def _fill_desc(d, n_sites, n_hidden, bonds, ham, J, h, marshall, sub, move, is_complex, prec,
+               symm=None):
+    """Fill an nqs_model_desc; bonds (two int32 [B, 2] arrays), sub and symm (int32 [G, N])
+    must stay alive."""
     d.n_sites, d.n_hidden = int(n_sites), int(n_hidden)
     d.is_complex, d.prec = int(bool(is_complex)), int(prec)
     for c in range(2):
@@ -194,13 +212,16 @@ def _fill_desc(d, n_sites, n_hidden, bonds, ham, J, h, marshall, sub, move, is_c
     d.marshall = int(bool(marshall))
     d.sublattice = sub.ctypes.data if sub is not None else None
     d.move = int(move)
+    d.n_symm = 0 if symm is None else int(symm.shape[0])
+    d.symm = symm.ctypes.data if symm is not None else None
 
 
 class Model:
     """Handle of one lattice model + RBM shape + compute precision (nqs_model_create)."""
 
     def __init__(self, n_sites, n_hidden, bonds, ham=TFIM, J=(1.0, 0.0), h=1.0, marshall=False,
-                 sublattice=None, move=MOVE_FLIP, is_complex=False, prec=F64):
+                 sublattice=None, move=MOVE_FLIP, is_complex=False, prec=F64, symm=None):
+        """symm: site permutations [G, N] of a symmetric RBM (n_hidden = alpha G), or None."""
         load()
         self.n_sites, self.n_hidden = int(n_sites), int(n_hidden)
         self.is_complex, self.prec = bool(is_complex), int(prec)
@@ -209,9 +230,11 @@ class Model:
         while len(self._bonds) < 2:
             self._bonds.append(np.zeros((0, 2), dtype=np.int32))
         self._sub = None if sublattice is None else np.ascontiguousarray(np.asarray(sublattice, dtype=np.int8))
+        self._symm = None if symm is None else np.ascontiguousarray(np.asarray(symm, dtype=np.int32))
+        self.n_symm = 0 if symm is None else int(self._symm.shape[0])
         d = _Desc()
         _fill_desc(d, self.n_sites, self.n_hidden, self._bonds, self.ham, J, h, marshall,
-                   self._sub, self.move, self.is_complex, self.prec)
+                   self._sub, self.move, self.is_complex, self.prec, self._symm)
         h_ = ctypes.c_void_p()
         _check(_lib.nqs_model_create(ctypes.byref(d), ctypes.byref(h_)), "nqs_model_create")
         self._h = h_
@@ -417,6 +440,17 @@ class Model:
 
     def set_cg_graphs(self, enable):
         _check(_lib.nqs_set_cg_graphs(self._h, int(bool(enable))), "nqs_set_cg_graphs")
+
+    def time_kernel(self, what):
+        """Record HIP events around launches of one kind (TIME_SWEEP, TIME_SV, TIME_ELOC;
+        TIME_NONE stops)."""
+        _check(_lib.nqs_time_kernel(self._h, int(what)), "nqs_time_kernel")
+
+    def kernel_ms(self):
+        """Milliseconds between the events of the last timed launch (waits for it)."""
+        ms = ctypes.c_float()
+        _check(_lib.nqs_kernel_ms(self._h, ctypes.byref(ms)), "nqs_kernel_ms")
+        return float(ms.value)
 
 
 class Batch:

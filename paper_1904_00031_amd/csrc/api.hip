@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -48,9 +49,7 @@ inline unsigned grid_for(int64_t count) {
 
 nqs_status dev(hipError_t e) { return e == hipSuccess ? NQS_OK : NQS_EDEVICE; }
 
-int64_t n_params_of(const nqs_model *m) {
-  return int64_t(m->N) + m->M + int64_t(m->N) * m->M;
-}
+int64_t n_params_of(const nqs_model *m) { return n_params_model(m); }
 
 nqs_status ensure_scratch(nqs_model *m, size_t bytes) {
   if (m->scratch_bytes >= bytes) return NQS_OK;
@@ -132,6 +131,20 @@ nqs_status nqs_hypercube(int32_t L, int32_t ndim, int32_t with_diagonals, int32_
   return NQS_OK;
 }
 
+nqs_status nqs_hypercube_translations(int32_t L, int32_t ndim, int32_t *perm) {
+  if (L < 3 || (ndim != 1 && ndim != 2) || !perm) return NQS_EINVAL;
+  const int n = ndim == 1 ? L : L * L;
+  if (n > 1024) return NQS_EINVAL;
+  for (int g = 0; g < n; ++g) {
+    const int gx = g % L, gy = ndim == 2 ? g / L : 0;
+    for (int s = 0; s < n; ++s) {
+      const int x = s % L, y = ndim == 2 ? s / L : 0;
+      perm[int64_t(g) * n + s] = (x + gx) % L + (ndim == 2 ? L * ((y + gy) % L) : 0);
+    }
+  }
+  return NQS_OK;
+}
+
 nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
   if (!d || !out) return NQS_EINVAL;
   *out = nullptr;
@@ -151,6 +164,18 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
   }
   if (d->move == NQS_MOVE_EXCHANGE && (d->n_bonds[0] < 1 || d->n_sites % 2)) return NQS_EINVAL;
   if (d->marshall && !d->sublattice) return NQS_EINVAL;
+  if (d->n_symm < 0 || (d->n_symm > 0 && (!d->symm || d->n_hidden % d->n_symm))) return NQS_EINVAL;
+  if (d->n_symm > 0) {
+    std::vector<char> seen(d->n_sites);
+    for (int g = 0; g < d->n_symm; ++g) {
+      std::fill(seen.begin(), seen.end(), 0);
+      for (int i = 0; i < d->n_sites; ++i) {
+        const int k = d->symm[int64_t(g) * d->n_sites + i];
+        if (k < 0 || k >= d->n_sites || seen[k]) return NQS_EINVAL;
+        seen[k] = 1;
+      }
+    }
+  }
 
   nqs_model *m = new (std::nothrow) nqs_model();
   if (!m) return NQS_ENOMEM;
@@ -240,6 +265,19 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
     total += (sizes[k] + 255) / 256 * 256;
   }
   if (ok) ok = hipMalloc(&m->d_tables, total) == hipSuccess;
+  // symmetric RBM: the permutations and the expanded-parameter buffers
+  if (ok && d->n_symm > 0) {
+    m->G = d->n_symm;
+    m->alpha = m->M / m->G;
+    const size_t pe = size_t(n_params_exp(m)) * (m->is_complex ? 2 : 1);
+    ok = hipMalloc(&m->d_perm, size_t(m->G) * m->N * sizeof(int)) == hipSuccess &&
+         hipMalloc(&m->d_pexp, pe * (use_double(m) ? 8 : 4)) == hipSuccess &&
+         hipMalloc(&m->d_vexp, pe * 8) == hipSuccess &&
+         hipMalloc(&m->d_gexp, pe * 8) == hipSuccess;
+    if (ok)
+      ok = hipMemcpy(m->d_perm, d->symm, size_t(m->G) * m->N * sizeof(int),
+                     hipMemcpyHostToDevice) == hipSuccess;
+  }
   if (!ok) {
     nqs_model_destroy(m);
     return NQS_ENOMEM;
@@ -257,12 +295,19 @@ void nqs_model_destroy(nqs_model *m) {
   if (m->d_bond_diag) (void)hipFree(m->d_bond_diag);
   if (m->d_bond_off) (void)hipFree(m->d_bond_off);
   if (m->d_tables) (void)hipFree(m->d_tables);
+  if (m->d_perm) (void)hipFree(m->d_perm);
+  if (m->d_pexp) (void)hipFree(m->d_pexp);
+  if (m->d_vexp) (void)hipFree(m->d_vexp);
+  if (m->d_gexp) (void)hipFree(m->d_gexp);
   if (m->d_scratch) (void)hipFree(m->d_scratch);
   if (m->cg_exec) (void)hipGraphExecDestroy(m->cg_exec);
   if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
   if (m->cg_host) (void)hipHostFree(m->cg_host);
   for (hipEvent_t e : m->cg_ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto &pair : m->time_ev)
+    for (hipEvent_t e : pair)
+      if (e) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -298,7 +343,9 @@ nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int
     nqs_status s = ensure_scratch(m, need);
     if (s != NQS_OK) return s;
   }
-  hipError_t e = launch_tables(m, params, st);
+  hipError_t e;
+  params = model_params(m, params, st, &e);
+  if (e == hipSuccess) e = launch_tables(m, params, st);
   if (e == hipSuccess)
     e = launch_sweep(m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter, chain_offset,
                      samples, n_accepted, fuse ? eloc : nullptr,
@@ -316,7 +363,9 @@ nqs_status nqs_log_psi(nqs_model *m, const void *params, const int8_t *sigma, in
   if (!m || !params || n < 0 || (n > 0 && (!sigma || !logpsi))) return NQS_EINVAL;
   if (n == 0) return NQS_OK;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_tables(m, params, st);
+  hipError_t e;
+  params = model_params(m, params, st, &e);
+  if (e == hipSuccess) e = launch_tables(m, params, st);
   if (e == hipSuccess) e = launch_log_psi(m, sigma, n, logpsi, st);
   return dev(e);
 }
@@ -328,25 +377,40 @@ nqs_status nqs_local_energy(nqs_model *m, const void *params, const int8_t *sigm
   hipStream_t st = (hipStream_t)stream;
   nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
   if (s != NQS_OK) return s;
-  hipError_t e = launch_tables(m, params, st);
+  hipError_t e;
+  params = model_params(m, params, st, &e);
+  if (e == hipSuccess) e = launch_tables(m, params, st);
   if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, m->d_scratch, false, st);
+  time_begin(m, NQS_TIME_ELOC);
+  time_mark(m, NQS_TIME_ELOC, 0, st);
   if (e == hipSuccess)
     e = launch_local_energy(m, sigma, grad_buffers(m, n, m->d_scratch).Tm, n, eloc, st);
+  time_mark(m, NQS_TIME_ELOC, 1, st);
   return dev(e);
 }
 
 // the Jacobian products of nqs_log_psi_grad with the given scratch (grad_scratch_bytes)
+// (symmetric RBM: the products of the expanded RBM, with the direction expanded before the
+// JVP and the VJP summed over the symmetry copies after it)
 static nqs_status log_psi_grad_with(nqs_model *m, const void *params, const int8_t *sigma,
                                     int64_t n, const void *u, void *vjp, const void *v,
                                     void *jvp, void *scr, hipStream_t st) {
-  hipError_t e = launch_tables(m, params, st);
+  hipError_t e;
+  params = model_params(m, params, st, &e);
+  if (e == hipSuccess) e = launch_tables(m, params, st);
   if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, scr, true, st);
   if (e == hipSuccess && u && vjp) {
     e = launch_vjp_partials(m, sigma, n, (const double *)u, scr, nullptr, st);
-    if (e == hipSuccess) e = launch_vjp_reduce(m, n, scr, (double *)vjp, nullptr, st);
+    double *out = m->G ? m->d_gexp : (double *)vjp;
+    if (e == hipSuccess) e = launch_vjp_reduce(m, n, scr, out, nullptr, st);
+    if (e == hipSuccess && m->G) e = launch_symm_reduce(m, m->d_gexp, (double *)vjp, st);
   }
   if (e == hipSuccess && v && jvp) {
-    e = launch_prep_dir(m, v, scr, true, st);
+    if (m->G) {
+      e = launch_symm_expand_dir(m, (const double *)v, m->d_vexp, nullptr, st);
+      v = m->d_vexp;
+    }
+    if (e == hipSuccess) e = launch_prep_dir(m, v, scr, true, st);
     if (e == hipSuccess) e = launch_jvp(m, sigma, n, scr, (double *)jvp, nullptr, nullptr, st);
   }
   return dev(e);
@@ -457,6 +521,30 @@ nqs_status nqs_autotune(nqs_model *m, const void *params, const int8_t *sigma, i
 nqs_status nqs_set_cg_graphs(nqs_model *m, int32_t enable) {
   if (!m) return NQS_EINVAL;
   m->cg_graphs = enable != 0;
+  return NQS_OK;
+}
+
+nqs_status nqs_time_kernel(nqs_model *m, int32_t what) {
+  if (!m || what < NQS_TIME_NONE || what > NQS_TIME_ELOC) return NQS_EINVAL;
+  for (auto &pair : m->time_ev)
+    for (hipEvent_t &e : pair)
+      if (!e && hipEventCreate(&e) != hipSuccess) return NQS_EDEVICE;
+  m->time_what = what;
+  m->time_n = 0;
+  return NQS_OK;
+}
+
+nqs_status nqs_kernel_ms(nqs_model *m, float *ms) {
+  if (!m || !ms || m->time_n < 1) return NQS_EINVAL;
+  double total = 0.0;
+  for (int k = 0; k < m->time_n; ++k) {
+    float t = 0.f;
+    if (hipEventSynchronize(m->time_ev[k][1]) != hipSuccess ||
+        hipEventElapsedTime(&t, m->time_ev[k][0], m->time_ev[k][1]) != hipSuccess)
+      return NQS_EDEVICE;
+    total += t;
+  }
+  *ms = float(total);
   return NQS_OK;
 }
 

@@ -23,6 +23,13 @@ struct CgGraphKey {
 
 struct nqs_model {
   int N, M, is_complex, prec, ham, move, marshall;
+  // symmetric RBM: G site permutations (device [G][N]), alpha = M / G filters; the kernels
+  // run the equivalent plain RBM on parameters expanded into d_pexp, with v_exp / g_exp
+  // buffers for the Jacobian products (expanded layout, complex double)
+  int G = 0, alpha = 0;
+  int *d_perm = nullptr;
+  void *d_pexp = nullptr;
+  double *d_vexp = nullptr, *d_gexp = nullptr;
   int B[2], Btot;
   double J[2], h;
   int device;
@@ -49,7 +56,25 @@ struct nqs_model {
   // (two slots) and the events that mark each copy complete
   void *cg_host = nullptr;
   hipEvent_t cg_ev[2] = {nullptr, nullptr};
+  // timing of one kind of kernel launch (nqs_time_kernel): pairs of events recorded around
+  // each kernel (or launcher) of it, summed by nqs_kernel_ms
+  static constexpr int kTimeSlots = 8;
+  int time_what = 0;
+  mutable int time_n = 0;  // pairs recorded in the last timed call
+  hipEvent_t time_ev[kTimeSlots][2] = {};
 };
+
+// timing marks: time_begin() when a timed call starts, then time_mark(0) / time_mark(1)
+// around each of its kernels (events of the next pair)
+inline void time_begin(const nqs_model *m, int what) {
+  if (m->time_what == what) m->time_n = 0;
+}
+inline void time_mark(const nqs_model *m, int what, int which, hipStream_t st) {
+  if (m->time_what != what || m->time_n >= nqs_model::kTimeSlots) return;
+  const hipEvent_t e = m->time_ev[m->time_n][which];
+  if (e) (void)hipEventRecord(e, st);
+  if (which == 1) ++m->time_n;
+}
 
 // Device copy of a host-built job table. upload() copies only when the bytes differ from
 // the previous upload, so a repeated call with the same buffers and sizes issues no
@@ -128,6 +153,25 @@ hipError_t launch_sample_batch(nqs_batch *b, const std::vector<BatchSampleItem> 
 
 // compute precision of the VALU kernels: double for NQS_F64, float otherwise
 inline bool use_double(const nqs_model *m) { return m->prec == NQS_F64; }
+
+// ---- symmetric RBM (symm.hip) -------------------------------------------------------
+inline int64_t n_params_exp(const nqs_model *m) {
+  return int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+}
+inline int64_t n_params_model(const nqs_model *m) {
+  return m->G ? 1 + m->alpha + int64_t(m->alpha) * m->N : n_params_exp(m);
+}
+// p_exp (expanded RBM, master precision) from p_sym: a_i = a, b_fG+g = b_f,
+// W_fG+g,perm[g][i] = W_fi
+hipError_t launch_symm_expand(const nqs_model *m, const void *p_sym, void *p_exp, hipStream_t st);
+// the same expansion of a direction in (complex) double; skip (may be NULL): nonzero -> return
+hipError_t launch_symm_expand_dir(const nqs_model *m, const double *v_sym, double *v_exp,
+                                  const int *skip, hipStream_t st);
+// g_sym = E^T g_exp (sum over the symmetry copies of every parameter), (complex) double
+hipError_t launch_symm_reduce(const nqs_model *m, const double *g_exp, double *g_sym,
+                              hipStream_t st);
+// the parameters the kernels read: p itself, or its expansion into d_pexp (launched here)
+const void *model_params(nqs_model *m, const void *p, hipStream_t st, hipError_t *err);
 
 DevModel dev_model(const nqs_model *m);
 

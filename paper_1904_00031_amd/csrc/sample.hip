@@ -1555,6 +1555,8 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   dim3 grid((n_chains + wpb - 1) / wpb);
   const bool tl = shared_rows && with_aux(tab_lds + wave_lds) <= size_t(m->max_lds);
   if constexpr (R <= 4) {
+    time_begin(m, NQS_TIME_SWEEP);
+    time_mark(m, NQS_TIME_SWEEP, 0, st);
     if (m->N <= 64) {
       if (tl)
         hipLaunchKernelGGL((k_sweep<T, C, R, true, true>), grid, dim3(64 * wpb),
@@ -1562,6 +1564,7 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
       else
         hipLaunchKernelGGL((k_sweep<T, C, R, false, true>), grid, dim3(64 * wpb),
                            with_aux(wave_lds), st, dev_model(m), tables_of<T>(m), a);
+      time_mark(m, NQS_TIME_SWEEP, 1, st);
       return hipGetLastError();
     }
   }
@@ -1581,10 +1584,17 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
       }
       const int G = (m->M + 64 * kWideUnits - 1) / (64 * kWideUnits);
       const size_t lds = ((size_t(G) * a.Npad + 8 * G + 15) / 16 * 16) + aux;
+      time_begin(m, NQS_TIME_SWEEP);
+      time_mark(m, NQS_TIME_SWEEP, 0, st);
       hipLaunchKernelGGL((k_sweep_wide<C>), dim3(n_chains), dim3(64 * G), lds, st,
                          dev_model(m), tables_of<float>(m), a, G, th0);
+      time_mark(m, NQS_TIME_SWEEP, 1, st);
       return hipGetLastError();
     }
+  }
+  if constexpr (R > 4) {
+    time_begin(m, NQS_TIME_SWEEP);
+    time_mark(m, NQS_TIME_SWEEP, 0, st);
   }
   if (tl) {
     hipLaunchKernelGGL((k_sweep<T, C, R, true, false>), grid, dim3(64 * wpb),
@@ -1593,6 +1603,7 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
     hipLaunchKernelGGL((k_sweep<T, C, R, false, false>), grid, dim3(64 * wpb),
                        with_aux(wave_lds), st, dev_model(m), tables_of<T>(m), a);
   }
+  time_mark(m, NQS_TIME_SWEEP, 1, st);
   return hipGetLastError();
 }
 

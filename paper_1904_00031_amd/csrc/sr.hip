@@ -670,7 +670,7 @@ __global__ void k_sr_info(const CGState *st, nqs_sr_info *out) {
 
 struct SRLayout {
   size_t grad, y, ysum, u, e_part, e_part2, cm, c_part, c_part2, o1, g, F, x, r, p, Ap, dpart,
-      rpart, state, total;
+      rpart, vexp, apexp, o1s, gs, state, total;
 };
 
 SRLayout sr_layout(const nqs_model *m, int64_t n) {
@@ -712,6 +712,14 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   }
   const int64_t cb = cdiv(P * cs, 256) < 4096 ? cdiv(P * cs, 256) : 4096;
   L.rpart = take(size_t(cb) * 8);
+  // symmetric RBM: the expanded direction and product, O^dagger 1 and the force numerator
+  // in the symmetric parameters (the CG vectors above hold the symmetric ones)
+  const size_t se = m->G ? size_t(P) * cs * 8 : 0;
+  const size_t ss = m->G ? size_t(n_params_model(m)) * cs * 8 : 0;
+  L.vexp = take(se);
+  L.apexp = take(se);
+  L.o1s = take(ss);
+  L.gs = take(ss);
   L.state = take(sizeof(CGState));
   L.total = off;
   return L;
@@ -744,6 +752,76 @@ __global__ void k_ones(int64_t n, double *u) {
 inline unsigned grid_for(int64_t count) {
   int64_t b = cdiv(count, 256);
   return unsigned(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+// ---- symmetric RBM: CG in the symmetric parameters --------------------------------------
+// F = g / n; x = 0; r = p = F; variance; partials of ||F||^2 (no direction tables: the
+// direction is expanded before every product)
+template <bool C>
+__global__ __launch_bounds__(256) void k_symm_cg_init(int64_t Ps, int64_t n, const double *part2,
+                                                      int64_t nparts, const double *g, double *F,
+                                                      double *x, double *r, double *p,
+                                                      double *dpart, CGState *st) {
+  __shared__ double lds[256];
+  constexpr int cs = C ? 2 : 1;
+  if (blockIdx.x == 0) {
+    const double var = block_sum(part2, nparts, 1, lds) / double(n);
+    if (threadIdx.x == 0) st->var = var;
+  }
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Ps; k += int64_t(gridDim.x) * 256) {
+#pragma unroll
+    for (int c = 0; c < cs; ++c) {
+      const double f = g[cs * k + c] / double(n);
+      F[cs * k + c] = f;
+      x[cs * k + c] = 0.0;
+      r[cs * k + c] = f;
+      p[cs * k + c] = f;
+      acc += f * f;
+    }
+  }
+  acc = block_reduce(acc, lds);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+}
+
+// Ap += lambda p on the reduced product; partials of Re(p^dagger Ap)
+__global__ __launch_bounds__(256) void k_symm_shift_dot(int64_t Pc, const double *p,
+                                                        double lambda, double *Ap, double *dpart,
+                                                        const CGState *st) {
+  if (st && st->done) return;
+  __shared__ double lds[256];
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Pc; k += int64_t(gridDim.x) * 256) {
+    const double a = Ap[k] + lambda * p[k];
+    Ap[k] = a;
+    acc += p[k] * a;
+  }
+  acc = block_reduce(acc, lds);
+  if (threadIdx.x == 0 && dpart) dpart[blockIdx.x] = acc;
+}
+
+// rr_new from partials; convergence; beta = rr_new / rr; p = r + beta p (no tables)
+__global__ __launch_bounds__(256) void k_cg_p_plain(int64_t Pc, const double *rpart,
+                                                    int64_t nparts, int parity, double tol,
+                                                    int maxiter, const double *r, double *p,
+                                                    CGState *st) {
+  if (st->done) return;
+  __shared__ double lds[256];
+  const double rr_new = block_sum(rpart, nparts, 1, lds);
+  const double beta = rr_new / st->rr[parity];
+  const int iters = st->iters + 1;
+  const bool conv = sqrt(rr_new) <= tol * st->bnorm;
+  const bool bad = !(finite(rr_new) && finite(st->alpha));
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Pc; k += int64_t(gridDim.x) * 256)
+    p[k] = r[k] + beta * p[k];
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rr[parity ^ 1] = rr_new;
+    st->iters = iters;
+    st->converged = conv;
+    st->nonfinite = bad;
+    st->done = conv || bad || iters >= maxiter;
+  }
 }
 
 // async: queue cg_maxiter iteration slots and write the information to device memory
@@ -948,12 +1026,136 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   return nqs_status(out.status);
 }
 
+// SR step of a symmetric RBM (Sec. 2.2.2, 2.2.5): the samples' tanh(theta) rows and the
+// Jacobian products of the expanded RBM, with the CG in the symmetric parameters:
+// S_sym v = E^T S_exp E v, F_sym = E^T F_exp. Convergence is checked on the host after
+// every chunk of 8 iterations (async: cg_maxiter slots, nothing read back).
+template <typename T, bool C>
+nqs_status sr_symm_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
+                        int64_t n, int64_t nch, double lr, double diag_shift, double cg_tol,
+                        int cg_maxiter, void *ws, nqs_sr_info *info, bool async, hipStream_t st) {
+  SRLayout L = sr_layout(m, n);
+  char *b = (char *)ws;
+  auto D = [&](size_t off) { return (double *)(b + off); };
+  CGState *state = (CGState *)(b + L.state);
+  void *grad = b + L.grad;
+  const int cs = C ? 2 : 1;
+  const int N = m->N, M = m->M;
+  const int64_t Ps = n_params_model(m), Pcs = Ps * cs;
+  const int64_t nb = cdiv(n, 256);
+  const int64_t sblocks = cdiv(Ps, 256) < 4096 ? cdiv(Ps, 256) : 4096;
+  const int64_t scblocks = cdiv(Pcs, 256) < 4096 ? cdiv(Pcs, 256) : 4096;
+  const GradPlan gp = grad_plan(m, n);
+  const GradBuffers gb = grad_buffers(m, n, grad);
+  const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
+  const int64_t nys = gp.fused ? gp.splits : nb;
+  const int64_t ablocks = cdiv(elems, kAprElems);
+
+  hipError_t e0;
+  const void *pe = model_params(m, params, st, &e0);
+  HIPTRY(e0);
+  HIPTRY(launch_tables(m, pe, st));
+  hipLaunchKernelGGL((k_sum_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
+                     (const double *)eloc, D(L.e_part));
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL((k_center_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
+                     (const double *)eloc, D(L.e_part), nb, D(L.u), D(L.e_part2), state);
+  HIPTRY(hipGetLastError());
+  const int64_t ncb = cdiv(nch, kChainsPerBlock), ncb2 = cdiv(nch, 256);
+  hipLaunchKernelGGL((k_chain_mean<C>), dim3(unsigned(ncb)), dim3(256), 0, st, n, nch,
+                     (const double *)eloc, D(L.cm), D(L.c_part));
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL(k_chain_dev, dim3(unsigned(ncb2)), dim3(256), 0, st, nch, D(L.cm),
+                     D(L.c_part), ncb, D(L.c_part2));
+  HIPTRY(hipGetLastError());
+  HIPTRY(launch_theta_tanh(m, sigma, n, grad, true, st));
+  // O^dagger 1 and the force numerator, expanded, then summed to the symmetric parameters
+  hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, D(L.y));
+  HIPTRY(hipGetLastError());
+  HIPTRY(launch_vjp_partials(m, sigma, n, D(L.y), grad, nullptr, st));
+  HIPTRY(launch_vjp_reduce(m, n, grad, D(L.o1), nullptr, st));
+  HIPTRY(launch_symm_reduce(m, D(L.o1), D(L.o1s), st));
+  HIPTRY(launch_vjp_partials(m, sigma, n, D(L.u), grad, nullptr, st));
+  HIPTRY(launch_vjp_reduce(m, n, grad, D(L.g), nullptr, st));
+  HIPTRY(launch_symm_reduce(m, D(L.g), D(L.gs), st));
+  (void)M;
+  hipLaunchKernelGGL((k_symm_cg_init<C>), dim3(unsigned(sblocks)), dim3(256), 0, st, Ps, n,
+                     D(L.e_part2), nb, D(L.gs), D(L.F), D(L.x), D(L.r), D(L.p), D(L.dpart),
+                     state);
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, st, D(L.dpart), sblocks, cg_tol,
+                     cg_maxiter, state, D(L.c_part2), ncb2, nch);
+  HIPTRY(hipGetLastError());
+  const int *skip = &state->done;
+  auto iteration = [&](int parity) -> hipError_t {
+    hipError_t e = launch_symm_expand_dir(m, D(L.p), D(L.vexp), skip, st);
+    if (e == hipSuccess) e = launch_prep_dir(m, D(L.vexp), grad, !gp.fused, st);
+    if (e != hipSuccess) return e;
+    if (gp.fused) {
+      e = launch_sv(m, sigma, n, grad, D(L.ysum), skip, st, false);
+    } else {
+      e = launch_jvp(m, sigma, n, grad, D(L.y), D(L.ysum), skip, st);
+      if (e == hipSuccess) e = launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, st, false);
+    }
+    if (e != hipSuccess) return e;
+    // expanded (g - ybar O^dagger 1) / n, then summed over the symmetry copies
+    hipLaunchKernelGGL((k_cg_apr<T, C>), dim3(unsigned(ablocks)), dim3(256), 0, st, N, m->M, n,
+                       gp.splits, gp.Itiles * 16, elems, (const T *)gb.part, D(L.o1), D(L.ysum),
+                       nys, D(L.vexp), 0.0, D(L.apexp), D(L.dpart), state);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_symm_reduce(m, D(L.apexp), D(L.Ap), st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_symm_shift_dot, dim3(unsigned(sblocks)), dim3(256), 0, st, Pcs,
+                       D(L.p), diag_shift, D(L.Ap), D(L.dpart), (const CGState *)state);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.dpart),
+                       sblocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.rpart),
+                       scblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p), state);
+    return hipGetLastError();
+  };
+  auto update = [&]() -> hipError_t {
+    if (use_double(m))
+      hipLaunchKernelGGL(k_update<double>, dim3(grid_for(Pcs)), dim3(256), 0, st, Pcs,
+                         (double *)params, (const double *)D(L.x), lr, (const CGState *)state);
+    else
+      hipLaunchKernelGGL(k_update<float>, dim3(grid_for(Pcs)), dim3(256), 0, st, Pcs,
+                         (float *)params, (const double *)D(L.x), lr, (const CGState *)state);
+    return hipGetLastError();
+  };
+  if (async) {
+    for (int it = 0; it < cg_maxiter; ++it) HIPTRY(iteration(it & 1));
+    HIPTRY(update());
+    hipLaunchKernelGGL(k_sr_info, dim3(1), dim3(64), 0, st, (const CGState *)state, info);
+    HIPTRY(hipGetLastError());
+    return NQS_OK;
+  }
+  CGState hs;
+  int launched = 0;
+  for (;;) {
+    HIPTRY(hipMemcpyAsync(&hs, state, sizeof(CGState), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (hs.done || launched >= cg_maxiter) break;
+    const int batch = cg_maxiter - launched < 8 ? cg_maxiter - launched : 8;
+    for (int q = 0; q < batch; ++q, ++launched) HIPTRY(iteration(launched & 1));
+  }
+  nqs_sr_info out;
+  fill_info(hs, &out);
+  if (out.status != NQS_ENONFINITE) HIPTRY(update());
+  HIPTRY(hipStreamSynchronize(st));
+  if (info) *info = out;
+  return nqs_status(out.status);
+}
+
 template <bool C>
 nqs_status prepare_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
                         void *ws, hipStream_t st) {
   SRLayout L = sr_layout(m, n);
   char *b = (char *)ws;
   void *grad = b + L.grad;
+  hipError_t e0;
+  params = model_params(m, params, st, &e0);
+  HIPTRY(e0);
   HIPTRY(launch_tables(m, params, st));
   HIPTRY(launch_theta_tanh(m, sigma, n, grad, true, st));
   hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, (double *)(b + L.y));
@@ -972,22 +1174,40 @@ nqs_status matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws, c
   const GradPlan gp = grad_plan(m, n);
   const GradBuffers gb = grad_buffers(m, n, grad);
   const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
+  // symmetric RBM: the product of the expanded RBM on E v, summed back over the copies
+  const void *v_in = v;
+  void *out_sym = out;
+  if (m->G) {
+    HIPTRY(launch_symm_expand_dir(m, (const double *)v, (double *)(b + L.vexp), nullptr, st));
+    v = b + L.vexp;
+    out = b + L.apexp;
+  }
+  const double lambda_exp = m->G ? 0.0 : lambda;
+  // (timing marks around each launcher: the product's kernel time without the gaps)
+  time_begin(m, NQS_TIME_SV);
+  time_mark(m, NQS_TIME_SV, 0, st);
   HIPTRY(launch_prep_dir(m, v, grad, !gp.fused, st));
+  time_mark(m, NQS_TIME_SV, 1, st);
   // the partial tiles of the product, summed over the sample splits by the kernel of the
   // CG iterations (no solver state)
+  time_mark(m, NQS_TIME_SV, 0, st);
   if (gp.fused) {
     HIPTRY(launch_sv(m, sigma, n, grad, (double *)(b + L.ysum), nullptr, st, false));
   } else {
     HIPTRY(launch_jvp(m, sigma, n, grad, (double *)(b + L.y), (double *)(b + L.ysum), nullptr, st));
+    time_mark(m, NQS_TIME_SV, 1, st);
+    time_mark(m, NQS_TIME_SV, 0, st);
     HIPTRY(launch_vjp_partials(m, sigma, n, (double *)(b + L.y), grad, nullptr, st, false));
   }
+  time_mark(m, NQS_TIME_SV, 1, st);
+  time_mark(m, NQS_TIME_SV, 0, st);
   const int64_t nys = gp.fused ? gp.splits : cdiv(n, 256);
   const dim3 grid(unsigned(cdiv(elems, kAprElems)));
   auto apr = [&](auto tc) {
     typedef decltype(tc) T;
     hipLaunchKernelGGL((k_cg_apr<T, C>), grid, dim3(256), 0, st, m->N, m->M, n, gp.splits,
                        gp.Itiles * 16, elems, (const T *)gb.part, (const double *)(b + L.o1),
-                       (const double *)(b + L.ysum), nys, (const double *)v, lambda,
+                       (const double *)(b + L.ysum), nys, (const double *)v, lambda_exp,
                        (double *)out, (double *)(b + L.dpart), (const CGState *)nullptr);
   };
   if (use_double(m))
@@ -995,6 +1215,15 @@ nqs_status matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws, c
   else
     apr(float(0));
   HIPTRY(hipGetLastError());
+  if (m->G) {
+    HIPTRY(launch_symm_reduce(m, (const double *)out, (double *)out_sym, st));
+    const int64_t Pcs = n_params_model(m) * (C ? 2 : 1);
+    hipLaunchKernelGGL(k_symm_shift_dot, dim3(grid_for(Pcs)), dim3(256), 0, st, Pcs,
+                       (const double *)v_in, lambda, (double *)out_sym, (double *)nullptr,
+                       (const CGState *)nullptr);
+    HIPTRY(hipGetLastError());
+  }
+  time_mark(m, NQS_TIME_SV, 1, st);
   return NQS_OK;
 }
 
@@ -1491,8 +1720,10 @@ nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const v
   if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
   const int64_t nch = n_chains > 0 ? n_chains : n;
 #define NQS_SR(T, C)                                                                          \
-  sr_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol, cg_maxiter, ws, info, \
-                async, st)
+  (m->G ? sr_symm_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol,         \
+                             cg_maxiter, ws, info, async, st)                                 \
+        : sr_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol, cg_maxiter,   \
+                        ws, info, async, st))
   if (use_double(m)) return m->is_complex ? NQS_SR(double, true) : NQS_SR(double, false);
   return m->is_complex ? NQS_SR(float, true) : NQS_SR(float, false);
 #undef NQS_SR
