@@ -9,7 +9,8 @@ that definition; the library has its own implementation.
 
 Stream layout used by the sampler (a convention both sides follow):
   key     = (seed & 0xffffffff, seed >> 32)
-  counter = (chain, sweep, step, tag), tag 0 = Metropolis proposal, tag 1 = chain init.
+  counter = (chain, sweep, step, tag), tag 0 = Metropolis proposal, tag 1 = chain init,
+            tag 2 = replica swap of parallel tempering (step = index of the swapped pair).
   word 0  -> integer index in [0, n) as floor(w0 * n / 2**32)
   words 1,2 -> uniform u = ((w1 << 21) | (w2 >> 11)) * 2**-53 in [0, 1).
 
@@ -26,6 +27,7 @@ MASK32 = np.uint64(0xFFFFFFFF)
 
 TAG_PROPOSAL = 0
 TAG_INIT = 1
+TAG_SWAP = 2
 
 
 def philox4x32_10(ctr, key):

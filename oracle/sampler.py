@@ -23,10 +23,25 @@ kept per chain and moved by the angle change of each accepted proposal, so a pro
 M ln cosh evaluations instead of N M products (the form used to time the oracle on the
 host). Chains are independent, so all chains advance together as numpy arrays.
 
+``sample_pt`` is parallel tempering (the paper's Metropolis samplers come with tempering
+options): every chain carries R replicas; the replica holding temperature index r samples
+|psi|^(2 beta_r) with beta_r = 1 - r / R (beta_0 = 1 is the physical distribution). A sweep
+runs N proposals in every replica, accepted iff beta 2 Re Delta >= 0 or u <
+exp(beta 2 Re Delta); replica w of chain c draws its proposals with chain index
+(chain_offset + c) R + w. After each sweep the temperatures k and k + 1 are exchanged, for
+k = 0 .. R-2 in order, iff E >= 0 or u < exp(E), E = (beta_k - beta_k+1)(L_b - L_a), where
+L = 2 Re log psi of the replica a holding k and of the replica b holding k + 1, and u is
+drawn with counter (chain_offset + c, sweep, k, TAG_SWAP). Replicas keep their
+configurations; the temperature index each holds moves. The configuration of the replica
+holding beta = 1 is recorded after each sweep.
+
 Pins (tests/test_oracle_sampler.py): the empirical one-step transition row of
 ``metropolis_step`` against the analytic Metropolis kernel, and the histogram of long
 chains against exact |psi|^2 by enumeration (chi-square), on N <= 6; ``sample_cached``
-reproduces ``sample`` sample for sample on the same stream (both moves, real and complex).
+reproduces ``sample`` sample for sample on the same stream (both moves, real and complex);
+``sample_pt`` with one replica equals ``sample``, and the recorded samples of long tempered
+chains follow exact |psi|^2 (chi-square, N = 6, both moves, with the swap acceptance exponent
+of the wrong sign failing it).
 """
 import numpy as np
 
@@ -160,3 +175,75 @@ def sample_cached(model, params, chain_sigma, n_sweeps, n_discard, seed, counter
         if sw >= n_discard:
             out[sw - n_discard] = sigma
     return out, sigma, n_acc
+
+
+def pt_betas(n_replicas):
+    """Inverse temperatures beta_r = 1 - r / R of parallel tempering."""
+    return 1.0 - np.arange(n_replicas) / float(n_replicas)
+
+
+def sample_pt(model, params, chain_sigma, temp_index, n_sweeps, n_discard, seed, counter,
+              chain_offset=0, record_ties=None, tie_margin=1e-12):
+    """Parallel tempering. chain_sigma [C, R, N] (replica configurations) and temp_index
+    [C, R] (the temperature index each replica holds) are copied and returned updated.
+    Returns (samples [n_sweeps, C, N], chain_sigma_out, temp_index_out, n_swaps [C])."""
+    N, M = model.n_sites, model.n_hidden
+    sig = np.array(chain_sigma, dtype=np.int8, copy=True)
+    tix = np.array(temp_index, dtype=np.int64, copy=True)
+    C, R, _ = sig.shape
+    betas = pt_betas(R)
+    flat = sig.reshape(C * R, N)
+    ids = ((np.arange(C, dtype=np.uint64) + np.uint64(chain_offset))[:, None] * np.uint64(R)
+           + np.arange(R, dtype=np.uint64)[None, :]).reshape(-1)
+    out = np.empty((n_sweeps, C, N), dtype=np.int8)
+    n_swaps = np.zeros(C, dtype=np.int64)
+    for sw in range(n_discard + n_sweeps):
+        g = counter + sw
+        beta = betas[tix.reshape(-1)]
+        for st in range(N):
+            w = philox.draw(seed, ids, g, st, philox.TAG_PROPOSAL)
+            u = philox.uniform_from_words(w[:, 1], w[:, 2])
+            prop = flat.copy()
+            rows = np.arange(C * R)
+            if model.move == MOVE_FLIP:
+                site = philox.index_from_word(w[:, 0], N)
+                prop[rows, site] = -prop[rows, site]
+                real_move = np.ones(C * R, dtype=bool)
+            else:
+                bl = model.bonds[0]
+                bidx = philox.index_from_word(w[:, 0], bl.shape[0])
+                i, k = bl[bidx, 0], bl[bidx, 1]
+                si, sk = flat[rows, i].copy(), flat[rows, k].copy()
+                real_move = si != sk
+                prop[rows, i] = sk
+                prop[rows, k] = si
+            delta = rbm.log_psi(params, prop, N, M) - rbm.log_psi(params, flat, N, M)
+            ex = beta * 2.0 * np.real(delta)
+            accept = real_move & ((ex >= 0.0) | (u < np.exp(np.minimum(ex, 0.0))))
+            if record_ties is not None:
+                near = real_move & (np.abs(u - np.exp(np.minimum(ex, 0.0))) < tie_margin)
+                for q in np.nonzero(near)[0]:
+                    record_ties.append((int(q // R), g, st))
+            flat[accept] = prop[accept]
+        # exchanges of adjacent temperatures, in order
+        L = 2.0 * np.real(rbm.log_psi(params, flat, N, M)).reshape(C, R)
+        cid = np.arange(C, dtype=np.uint64) + np.uint64(chain_offset)
+        for k in range(R - 1):
+            w = philox.draw(seed, cid, g, k, philox.TAG_SWAP)
+            u = philox.uniform_from_words(w[:, 1], w[:, 2])
+            a = np.argmax(tix == k, axis=1)
+            b = np.argmax(tix == k + 1, axis=1)
+            rows = np.arange(C)
+            ex = (betas[k] - betas[k + 1]) * (L[rows, b] - L[rows, a])
+            acc = (ex >= 0.0) | (u < np.exp(np.minimum(ex, 0.0)))
+            if record_ties is not None:
+                near = np.abs(u - np.exp(np.minimum(ex, 0.0))) < tie_margin
+                for c in np.nonzero(near)[0]:
+                    record_ties.append((int(c), g, -1 - k))
+            tix[rows[acc], a[acc]] = k + 1
+            tix[rows[acc], b[acc]] = k
+            n_swaps += acc
+        if sw >= n_discard:
+            phys = np.argmax(tix == 0, axis=1)
+            out[sw - n_discard] = flat.reshape(C, R, N)[np.arange(C), phys]
+    return out, flat.reshape(C, R, N), tix, n_swaps

@@ -120,3 +120,39 @@ def test_cached_sampler_equals_definition(move, cplx):
     a2, l2, n2 = sampler.sample_cached(m, p, init, 6, 3, seed=36, counter=11)
     assert np.array_equal(a1, a2) and np.array_equal(l1, l2) and np.array_equal(n1, n2)
     assert n1.sum() > 0
+
+
+def test_pt_with_one_replica_is_the_plain_sampler():
+    m = model(MOVE_EXCHANGE, n=8)
+    p = synth.rbm_params(8, 4, True, sigma=0.5, seed=40)
+    init = sampler.init_chains(m, 12, seed=41)
+    a, la, na = sampler.sample(m, p, init, 5, 2, seed=41, counter=3)
+    b, lb, tb, ns = sampler.sample_pt(m, p, init[:, None, :], np.zeros((12, 1)), 5, 2, seed=41,
+                                      counter=3)
+    assert np.array_equal(a, b) and np.array_equal(la, lb[:, 0]) and ns.sum() == 0
+
+
+@pytest.mark.parametrize("move", [MOVE_FLIP, MOVE_EXCHANGE])
+def test_pt_samples_follow_psi_squared(move):
+    # long tempered chains (3 replicas): the configurations recorded from the beta = 1
+    # replica follow exact |psi|^2, and the temperatures are exchanged
+    from scipy.stats import chi2
+    m = model(move)
+    N, M = m.n_sites, m.n_hidden
+    p = synth.rbm_params(N, M, True, sigma=0.25, seed=43)
+    chains, R = 1500, 3
+    init = np.stack([sampler.init_chains(m, chains, seed=44 + r) for r in range(R)], axis=1)
+    tix = np.tile(np.arange(R), (chains, 1))
+    smp, _, tix2, nsw = sampler.sample_pt(m, p, init, tix, 1, 150, seed=44, counter=0)
+    assert nsw.mean() > 10
+    confs, pi = exact.exact_probabilities(m, p)
+    if move == MOVE_EXCHANGE:
+        keep = confs.sum(axis=1) == 0
+        confs, pi = confs[keep], pi[keep] / pi[keep].sum()
+    index = {c.tobytes(): k for k, c in enumerate(confs)}
+    hist = np.zeros(len(confs))
+    for row in smp.reshape(-1, N):
+        hist[index[row.tobytes()]] += 1
+    expct = pi * hist.sum()
+    stat = np.sum((hist - expct) ** 2 / expct)
+    assert chi2.sf(stat, df=len(confs) - 1) > 1e-3, stat
