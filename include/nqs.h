@@ -181,6 +181,30 @@ nqs_status nqs_sample(nqs_model *model, const void *params, int8_t *chain_sigma,
                       uint64_t counter, int32_t chain_offset, int8_t *samples,
                       int64_t *n_accepted, void *eloc, void *stream);
 
+/* Metropolis sampling with parallel tempering (Sec. 2.2.5: the samplers' tempering
+ * option). Each of the n_chains chains carries R = n_replicas replicas (2 <= R <= 16);
+ * replica w of chain c is row c R + w of chain_sigma (device [n_chains, R, N], in/out) and
+ * holds the temperature index temp_index[c R + w] (device int32, in/out; the indices of a
+ * chain are a permutation of 0 .. R-1, e.g. w at the first call), i.e. it samples
+ * |psi|^(2 beta) with beta_r = 1 - r / R. A sweep runs N proposals in every replica, drawn
+ * as in nqs_sample with chain index (chain_offset + c) R + w and accepted iff
+ * |psi'/psi|^(2 beta) >= 1 or u < |psi'/psi|^(2 beta). After each sweep the temperatures
+ * k and k + 1 are exchanged, for k = 0 .. R-2 in order, iff E >= 0 or u < exp(E) with
+ * E = (beta_k - beta_k+1)(L_b - L_a), L = 2 Re log psi (in double, from the replicas'
+ * exact angles) of the replicas a, b holding k, k + 1, and u from Philox4x32-10 counter
+ * (chain_offset + c, counter + sweep, k, 2). After each of the last n_sweeps sweeps the
+ * configuration of the replica holding beta = 1 is written to samples[sweep][c][:]
+ * (device [n_sweeps, n_chains, N]). n_accepted (device int64 [n_chains R], may be NULL):
+ * accepted proposals per replica; n_swaps (device int64 [n_chains], may be NULL): accepted
+ * exchanges; eloc (device [n_sweeps n_chains], may be NULL): local energies of the recorded
+ * samples. One block per chain, one wavefront per replica (hence R <= 4); float models with
+ * more than 256 hidden units are not tempered (NQS_EUNSUPPORTED). */
+nqs_status nqs_sample_pt(nqs_model *model, const void *params, int8_t *chain_sigma,
+                         int32_t *temp_index, int32_t n_chains, int32_t n_replicas,
+                         int32_t n_sweeps, int32_t n_discard, uint64_t seed, uint64_t counter,
+                         int32_t chain_offset, int8_t *samples, int64_t *n_accepted,
+                         int64_t *n_swaps, void *eloc, void *stream);
+
 /* log psi(sigma) = sum_i a_i sigma_i + sum_j ln cosh(theta_j), theta = W sigma + b
  * (Sec. 2.2.2: RBM as a one-layer ln cosh network plus visible bias; the constant
  * M ln 2 of prod_j 2 cosh is dropped). sigma (device) [n, N]; logpsi (device) [n]

@@ -102,7 +102,8 @@ def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain
 
     Returns (samples [n_sweeps, C, N], chain_sigma_out [C, N], n_accepted [C]).
     If ``record_ties`` is a list, each proposal with |u - exp(2 Re Delta)| < tie_margin is
-    appended to it as (chain, sweep, step)."""
+    appended to it as (chain, sweep, step): the chain's row, the sweep counted from the
+    first of this call (discarded ones included) and the proposal within the sweep."""
     sigma = np.array(chain_sigma, dtype=np.int8, copy=True)
     C, N = sigma.shape
     chains = np.arange(C, dtype=np.uint64) + np.uint64(chain_offset)
@@ -116,7 +117,7 @@ def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain
             if record_ties is not None:
                 near = np.abs(u - np.exp(np.minimum(two_re, 0.0))) < tie_margin
                 for c in np.nonzero(near)[0]:
-                    record_ties.append((int(chains[c]), g, st))
+                    record_ties.append((int(chains[c]) - chain_offset, sw, st))
         if sw >= n_discard:
             out[sw - n_discard] = sigma
     return out, sigma, n_acc
@@ -223,7 +224,7 @@ def sample_pt(model, params, chain_sigma, temp_index, n_sweeps, n_discard, seed,
             if record_ties is not None:
                 near = real_move & (np.abs(u - np.exp(np.minimum(ex, 0.0))) < tie_margin)
                 for q in np.nonzero(near)[0]:
-                    record_ties.append((int(q // R), g, st))
+                    record_ties.append((int(q // R), sw, st))
             flat[accept] = prop[accept]
         # exchanges of adjacent temperatures, in order
         L = 2.0 * np.real(rbm.log_psi(params, flat, N, M)).reshape(C, R)
@@ -239,7 +240,7 @@ def sample_pt(model, params, chain_sigma, temp_index, n_sweeps, n_discard, seed,
             if record_ties is not None:
                 near = np.abs(u - np.exp(np.minimum(ex, 0.0))) < tie_margin
                 for c in np.nonzero(near)[0]:
-                    record_ties.append((int(c), g, -1 - k))
+                    record_ties.append((int(c), sw, -1 - k))
             tix[rows[acc], a[acc]] = k + 1
             tix[rows[acc], b[acc]] = k
             n_swaps += acc

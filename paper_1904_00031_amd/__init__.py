@@ -95,6 +95,8 @@ def load(path=LIB_PATH):
         "nqs_n_params": (i64, [vp]),
         "nqs_chain_init": (i32, [vp, vp, i32, u64, i32, vp]),
         "nqs_sample": (i32, [vp, vp, vp, i32, i32, i32, u64, u64, i32, vp, vp, vp, vp]),
+        "nqs_sample_pt": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, u64, u64, i32, vp, vp, vp, vp,
+                                vp]),
         "nqs_log_psi": (i32, [vp, vp, vp, i64, vp, vp]),
         "nqs_local_energy": (i32, [vp, vp, vp, i64, vp, vp]),
         "nqs_log_psi_grad": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
@@ -134,7 +136,8 @@ def load(path=LIB_PATH):
 def exported_symbols():
     return ["nqs_status_string", "nqs_hypercube", "nqs_hypercube_translations",
             "nqs_model_create", "nqs_model_destroy",
-            "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_log_psi", "nqs_local_energy",
+            "nqs_n_params", "nqs_chain_init", "nqs_sample", "nqs_sample_pt", "nqs_log_psi",
+            "nqs_local_energy",
             "nqs_log_psi_grad", "nqs_log_psi_grad_noalloc", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_step_async",
             "nqs_sr_prepare",
             "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_set_cg_graphs",
@@ -287,6 +290,34 @@ class Model:
         _check(_lib.nqs_sample(self._h, _ptr(params), _ptr(chain_sigma), C, n_sweeps, n_discard,
                                seed, counter, chain_offset, _ptr(samples), _ptr(n_accepted),
                                _ptr(eloc), _stream()), "nqs_sample")
+        return samples, eloc
+
+    def sample_pt(self, params, replicas, temp_index, n_sweeps, n_discard, seed, counter,
+                  chain_offset=0, samples=None, n_accepted=None, n_swaps=None, eloc=None,
+                  with_eloc=False):
+        """Parallel tempering: replicas [C, R, N] int8 and temp_index [C, R] int32 (both
+        updated in place); returns (samples [S, C, N], eloc)."""
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        C, R = replicas.shape[0], replicas.shape[1]
+        _need(replicas, "replicas", torch.int8, (C, R, self.n_sites))
+        _need(temp_index, "temp_index", torch.int32, (C, R))
+        dev = replicas.device
+        if samples is None:
+            samples = torch.empty((n_sweeps, C, self.n_sites), dtype=torch.int8, device=dev)
+        _need(samples, "samples", torch.int8, (n_sweeps, C, self.n_sites))
+        if n_accepted is not None:
+            _need(n_accepted, "n_accepted", torch.int64, (C * R,))
+        if n_swaps is not None:
+            _need(n_swaps, "n_swaps", torch.int64, (C,))
+        if with_eloc and eloc is None:
+            eloc = torch.empty(n_sweeps * C, dtype=self.value_dtype, device=dev)
+        if eloc is not None:
+            _need(eloc, "eloc", self.value_dtype, (n_sweeps * C,))
+        _check(_lib.nqs_sample_pt(self._h, _ptr(params), _ptr(replicas), _ptr(temp_index), C, R,
+                                  n_sweeps, n_discard, seed, counter, chain_offset, _ptr(samples),
+                                  _ptr(n_accepted), _ptr(n_swaps), _ptr(eloc), _stream()),
+               "nqs_sample_pt")
         return samples, eloc
 
     def log_psi(self, params, sigma, out=None):

@@ -1,4 +1,5 @@
 // C ABI of libnqs: argument validation, model handles and dispatch to the kernels.
+#include <limits.h>
 #include <math.h>
 #include <string.h>
 
@@ -351,6 +352,37 @@ nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int
                      samples, n_accepted, fuse ? eloc : nullptr,
                      sweep_scratch_bytes(m, n_chains) ? m->d_scratch : nullptr, st);
   if (e == hipSuccess && eloc && !fuse) {
+    e = launch_theta_tanh(m, samples, n, m->d_scratch, false, st);
+    if (e == hipSuccess)
+      e = launch_local_energy(m, samples, grad_buffers(m, n, m->d_scratch).Tm, n, eloc, st);
+  }
+  return dev(e);
+}
+
+nqs_status nqs_sample_pt(nqs_model *m, const void *params, int8_t *chain_sigma,
+                         int32_t *temp_index, int32_t n_chains, int32_t n_replicas,
+                         int32_t n_sweeps, int32_t n_discard, uint64_t seed, uint64_t counter,
+                         int32_t chain_offset, int8_t *samples, int64_t *n_accepted,
+                         int64_t *n_swaps, void *eloc, void *stream) {
+  if (!m || !params || !chain_sigma || !temp_index || !samples || n_chains < 1 ||
+      n_replicas < 2 || n_replicas > 4 || n_sweeps < 1 || n_discard < 0 || chain_offset < 0 ||
+      int64_t(n_chains) * n_replicas > INT32_MAX)
+    return NQS_EINVAL;
+  if (!pt_supported(m)) return NQS_EUNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = int64_t(n_sweeps) * n_chains;
+  if (eloc) {
+    nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
+    if (s != NQS_OK) return s;
+  }
+  hipError_t e;
+  params = model_params(m, params, st, &e);
+  if (e == hipSuccess) e = launch_tables(m, params, st);
+  const PtArgs pt{n_replicas, temp_index, n_swaps};
+  if (e == hipSuccess)
+    e = launch_sweep(m, chain_sigma, n_chains * n_replicas, n_sweeps, n_discard, seed, counter,
+                     chain_offset, samples, n_accepted, nullptr, nullptr, st, &pt);
+  if (e == hipSuccess && eloc) {
     e = launch_theta_tanh(m, samples, n, m->d_scratch, false, st);
     if (e == hipSuccess)
       e = launch_local_energy(m, samples, grad_buffers(m, n, m->d_scratch).Tm, n, eloc, st);

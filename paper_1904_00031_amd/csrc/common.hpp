@@ -219,7 +219,7 @@ __device__ __forceinline__ double rng_uniform(uint32_t w1, uint32_t w2) {
   return double(x) * 0x1.0p-53;
 }
 
-enum { TAG_PROPOSAL = 0, TAG_INIT = 1 };
+enum { TAG_PROPOSAL = 0, TAG_INIT = 1, TAG_SWAP = 2 };
 
 // ---------------------------------------------------------------------------------
 // Wave-wide reductions (all 64 lanes receive the result).
@@ -404,6 +404,6 @@ struct Tables {
   T *bS;    // [Btot][M] sinh(2 (W_ji - W_jk))
   double *fa;  // [2][N]    exp(-2 s a_i),           s = +1 -> row 0, s = -1 -> row 1
   double *ba;  // [2][Btot] exp(-2 s (a_i - a_k)),   s = sigma_i
-  double *av;  // [N]       a (double)
+  double *av;  // [N][2]    a (double, re and im)
   T *Wd;       // [B0][M]   W_ji - W_jk for the color-0 bond (i, k)
 };

@@ -179,12 +179,23 @@ DevModel dev_model(const nqs_model *m);
 hipError_t launch_tables(const nqs_model *m, const void *params, hipStream_t st);
 hipError_t launch_chain_init(const nqs_model *m, int8_t *sig, int n_chains, uint64_t seed,
                              int chain_offset, hipStream_t st);
+// parallel tempering of nqs_sample_pt: n_rep replicas per chain (chain_sigma [C R][N]),
+// temperature index of every replica (device [C R], in/out), accepted exchanges per chain
+struct PtArgs {
+  int n_rep;
+  int *temp;
+  int64_t *n_swap;
+};
+// whether the sweep kernels temper this model (not the wide float sweep)
+inline bool pt_supported(const nqs_model *m) { return use_double(m) || m->M <= 256; }
+
 // scratch: device memory of sweep_scratch_bytes(m, n_chains) bytes for the chains' angles
-// of the wide sweep (NULL: the sweep forms them itself)
+// of the wide sweep (NULL: the sweep forms them itself). pt: tempering (n_chains then
+// counts replicas, C R), or NULL
 hipError_t launch_sweep(const nqs_model *m, int8_t *chain_sigma, int n_chains, int n_sweeps,
                         int n_discard, uint64_t seed, uint64_t counter, int chain_offset,
                         int8_t *samples, int64_t *n_acc, void *eloc, void *scratch,
-                        hipStream_t st);
+                        hipStream_t st, const PtArgs *pt = nullptr);
 size_t sweep_scratch_bytes(const nqs_model *m, int n_chains);
 // local energies from rows Tm [n][M] of tanh(theta) (compute precision)
 hipError_t launch_local_energy(const nqs_model *m, const int8_t *sigma, const void *Tm,

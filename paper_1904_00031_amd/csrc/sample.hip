@@ -333,6 +333,7 @@ __device__ __forceinline__ void eloc_grouped(const DevModel &dm, const Tables<T>
 // units per lane and tables in global memory run k_sweep_wide instead. After each recorded sweep the
 // chain's local energy is evaluated from its cached t.
 // ---------------------------------------------------------------------------------
+constexpr int kMaxReplicas = 4;   // replicas are the (at most 4) wavefronts of a block
 struct SweepArgs {
   int8_t *chain_sigma;
   int n_chains, n_sweeps, n_discard;
@@ -344,6 +345,15 @@ struct SweepArgs {
   int w_rows;        // W rows of the moves (N for flips, B0 for exchanges)
   int wave_bytes;    // per-wavefront LDS: spins (Npad bytes), then t (M values)
   int Npad;
+  // parallel tempering (n_rep > 1): a block holds one tempered chain, wavefront w its
+  // replica w; chain rows, proposal streams and n_acc are per replica (chain c R + w);
+  // temp holds the temperature index of every replica [C R] (in/out), n_swap [C] the
+  // accepted exchanges, group_offset the first chain index of the swap streams
+  int n_rep;
+  int *temp;
+  int64_t *n_swap;
+  uint32_t group_offset;
+  double betas[kMaxReplicas];
 };
 
 // whether the wavefront's sum of x exceeds th, the same on every lane: row sums by DPP,
@@ -405,8 +415,19 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
     if (!flip)
       for (int e = threadIdx.x; e < 2 * dm.B0; e += blockDim.x) lbond[e] = dm.bonds[e];
   }
+  // parallel tempering: the replicas' 2 Re log psi and temperature indices after the
+  // auxiliary tables
+  const bool pt = a.n_rep > 1;
+  const int64_t pt_off = (aux_off + int64_t(16) * afn + (flip ? 0 : int64_t(8) * dm.B0) + 15) &
+                         ~int64_t(15);
+  double *ptL = reinterpret_cast<double *>(lds_u8 + pt_off);   // [R]
+  int *ptT = reinterpret_cast<int *>(ptL + kMaxReplicas);      // [R]
+  if (pt && lane == 0) ptT[wid] = a.temp[chain];
   __syncthreads();
   if (chain >= a.n_chains) return;
+  // inverse temperature of this replica (1 without tempering)
+  double beta = pt ? a.betas[ptT[wid]] : 1.0;
+  int64_t n_swaps = 0;
   int8_t *sig = reinterpret_cast<int8_t *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes);
   T *tj = reinterpret_cast<T *>(lds_u8 + tab_bytes + int64_t(wid) * a.wave_bytes + a.Npad);
   for (int i = lane; i < N; i += 64) sig[i] = a.chain_sigma[int64_t(chain) * N + i];
@@ -497,7 +518,8 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
         uv = rng_uniform(w.w[1], w.w[2]);
         a2p = la2[rowv];
         a2m = la2[afn + rowv];
-        const float lu = __log2f(float(uv));
+        // |ratio|^(2 beta) > u  <=>  log2 |ratio|^2 > log2(u) / beta
+        const float lu = pt ? float(double(__log2f(float(uv))) / beta) : __log2f(float(uv));
         thp = lu - __log2f(float(a2p));
         thm = lu - __log2f(float(a2m));
       }
@@ -560,7 +582,8 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
               }
               const T pmw = wave_prod_dpp(pm, pe);
               const double a2 = readlane_v(s > 0 ? a2p : a2m, l);
-              const double q = ldexp(double(pmw), pe) * a2;
+              double q = ldexp(double(pmw), pe) * a2;
+              if (pt && beta != 1.0) q = exp(beta * log(q));   // |psi'/psi|^(2 beta)
               const double u = readlane_v(uv, l);
               accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
             }
@@ -668,7 +691,8 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
             }
             const T pmw = wave_prod_dpp(pm, pe);
             const double a2 = readlane_v(s > 0 ? a2p : a2m, l);
-            const double q = ldexp(double(pmw), pe) * a2;
+            double q = ldexp(double(pmw), pe) * a2;
+            if (pt && beta != 1.0) q = exp(beta * log(q));   // |psi'/psi|^(2 beta)
             const double u = readlane_v(uv, l);
             accept = __builtin_amdgcn_readfirstlane(int((q >= 1.0) || (u < q)));
           }
@@ -735,8 +759,43 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
         thi[r] = 0.0;
       }
     }
-    if (sw >= a.n_discard) {
-      const int64_t smp = int64_t(sw - a.n_discard) * a.n_chains + chain;
+    if (pt) {
+      // exchanges of adjacent temperatures: every replica's L = 2 Re log psi in double from
+      // its exact angles and spins, then one thread decides k = 0 .. R-2 in order
+      double lr = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (lane + 64 * r < M) lr += vlncosh<double, C>(vmake<double, C>(thr[r], thi[r])).re;
+      for (int i = lane; i < N; i += 64) lr += tb.av[2 * i] * double(sig[i]);
+      lr = wave_sum_dpp(lr);
+      if (lane == 0) ptL[wid] = 2.0 * lr;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t gid = a.group_offset + uint32_t(chain / a.n_rep);
+        for (int k = 0; k + 1 < a.n_rep; ++k) {
+          int ia = 0, ib = 0;
+          for (int q = 0; q < a.n_rep; ++q) {
+            if (ptT[q] == k) ia = q;
+            if (ptT[q] == k + 1) ib = q;
+          }
+          const double ex = (a.betas[k] - a.betas[k + 1]) * (ptL[ib] - ptL[ia]);
+          const Philox4 w = philox4x32_10(gid, a.counter + uint32_t(sw), uint32_t(k), TAG_SWAP,
+                                          a.k0, a.k1);
+          const double u = rng_uniform(w.w[1], w.w[2]);
+          if (ex >= 0.0 || u < exp(ex)) {
+            ptT[ia] = k + 1;
+            ptT[ib] = k;
+            ++n_swaps;
+          }
+        }
+      }
+      __syncthreads();
+      beta = a.betas[ptT[wid]];
+    }
+    if (sw >= a.n_discard && (!pt || ptT[wid] == 0)) {
+      // tempering: only the replica holding beta = 1 records, as sample c of the sweep
+      const int64_t smp = pt ? int64_t(sw - a.n_discard) * (a.n_chains / a.n_rep) + chain / a.n_rep
+                             : int64_t(sw - a.n_discard) * a.n_chains + chain;
       int8_t *dst = a.samples + smp * N;
       for (int i = lane; i < N; i += 64) dst[i] = sig[i];
       if (FE && a.eloc) {
@@ -764,6 +823,10 @@ __device__ __forceinline__ void sweep_block(const DevModel &dm, const Tables<T> 
   }
   for (int i = lane; i < N; i += 64) a.chain_sigma[int64_t(chain) * N + i] = sig[i];
   if (lane == 0 && a.n_acc) a.n_acc[chain] = acc_count;
+  if (pt && lane == 0) {
+    a.temp[chain] = ptT[wid];
+    if (wid == 0 && a.n_swap) a.n_swap[chain / a.n_rep] = n_swaps;
+  }
 }
 
 template <typename T, bool C, int R, bool TL, bool SM>
@@ -1524,9 +1587,21 @@ inline size_t sweep_aux_lds(const nqs_model *m) {
 template <typename T, bool C, int R>
 hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, int n_discard,
                    uint64_t seed, uint64_t counter, int chain_offset, int8_t *samples,
-                   int64_t *n_acc, void *eloc, void *scratch, hipStream_t st) {
-  const int wpb = 4;
+                   int64_t *n_acc, void *eloc, void *scratch, hipStream_t st,
+                   const PtArgs *pt) {
+  // tempering: one block per tempered chain, one wavefront per replica
+  const int wpb = pt ? pt->n_rep : 4;
   SweepArgs a;
+  memset(static_cast<void *>(&a), 0, sizeof a);
+  if (pt) {
+    if (pt->n_rep < 2 || pt->n_rep > kMaxReplicas || n_chains % pt->n_rep) return hipErrorInvalidValue;
+    a.n_rep = pt->n_rep;
+    a.temp = pt->temp;
+    a.n_swap = pt->n_swap;
+    a.group_offset = uint32_t(chain_offset);
+    for (int r = 0; r < pt->n_rep; ++r) a.betas[r] = 1.0 - double(r) / double(pt->n_rep);
+    chain_offset *= pt->n_rep;   // proposal streams: (chain_offset + c) R + w
+  }
   a.chain_sigma = cs;
   a.n_chains = n_chains;
   a.n_sweeps = n_sweeps;
@@ -1546,8 +1621,9 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   const size_t wave_lds = size_t(wpb) * a.wave_bytes;
   const size_t tab_lds =
       size_t(2 * a.cs_rows + a.w_rows) * m->M * sizeof(T) * (C ? 2 : 1);
-  // the visible-bias factors and bonds after the wavefronts' regions (16-byte aligned)
-  const size_t aux = sweep_aux_lds(m);
+  // the visible-bias factors and bonds after the wavefronts' regions (16-byte aligned), and
+  // with tempering the replicas' log amplitudes and temperature indices
+  const size_t aux = sweep_aux_lds(m) + (pt ? 16 + 12 * kMaxReplicas : 0);
   auto with_aux = [&](size_t base) { return (base + 15) / 16 * 16 + aux; };
   // the staged C/S rows serve both the moves and the local energy only when the move
   // set is contained in the connected set: flips with TFIM, exchanges with Heisenberg
@@ -1570,6 +1646,7 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
   }
   if constexpr (sizeof(T) == 4 && R > 4) {
     if (!tl) {
+      if (pt) return hipErrorNotSupported;   // the wide sweep does not temper
       // wide models: the chains' angles on the matrix cores (into the model's scratch, when
       // given), then the hidden units of a chain split over G wavefronts of one block
       const double *th0 = nullptr;
@@ -1610,12 +1687,13 @@ hipError_t sweep_r(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, i
 template <typename T, bool C>
 hipError_t sweep_t(const nqs_model *m, int8_t *cs, int n_chains, int n_sweeps, int n_discard,
                    uint64_t seed, uint64_t counter, int chain_offset, int8_t *samples,
-                   int64_t *n_acc, void *eloc, void *scratch, hipStream_t st) {
+                   int64_t *n_acc, void *eloc, void *scratch, hipStream_t st,
+                   const PtArgs *pt) {
   int r = (m->M + 63) / 64;
 #define NQS_SWEEP_CASE(RR)                                                                 \
   if (r <= RR)                                                                             \
     return sweep_r<T, C, RR>(m, cs, n_chains, n_sweeps, n_discard, seed, counter,          \
-                             chain_offset, samples, n_acc, eloc, scratch, st);
+                             chain_offset, samples, n_acc, eloc, scratch, st, pt);
   NQS_SWEEP_CASE(1)
   NQS_SWEEP_CASE(2)
   NQS_SWEEP_CASE(4)
@@ -1920,9 +1998,9 @@ hipError_t launch_chain_init(const nqs_model *m, int8_t *sig, int n_chains, uint
 hipError_t launch_sweep(const nqs_model *m, int8_t *chain_sigma, int n_chains, int n_sweeps,
                         int n_discard, uint64_t seed, uint64_t counter, int chain_offset,
                         int8_t *samples, int64_t *n_acc, void *eloc, void *scratch,
-                        hipStream_t st) {
+                        hipStream_t st, const PtArgs *pt) {
   return NQS_DISPATCH(sweep_t, m, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter,
-                      chain_offset, samples, n_acc, eloc, scratch, st);
+                      chain_offset, samples, n_acc, pt ? nullptr : eloc, scratch, st, pt);
 }
 
 size_t sweep_scratch_bytes(const nqs_model *m, int n_chains) {

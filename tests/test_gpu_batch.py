@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+import cases
 import synth
 from oracle import hamiltonian as oh, lattice as ol, sampler as osamp
 
@@ -69,10 +70,7 @@ def check_batch(lib, kinds, prec, cplx, n_chains, margin, tol):
         exp, _, _ = osamp.sample(om, pe, ini, S, D, seed=9 ^ k, counter=5, record_ties=ties,
                                  tie_margin=margin)
         got = smp[so:so + S * C * N].reshape(S, C, N)
-        for c in range(C):
-            bad = np.nonzero(np.any(got[:, c] != exp[:, c], axis=1))[0]
-            if bad.size:
-                assert any(tc == c and sw <= bad[0] for tc, sw, _ in ties), (k, c, bad[0])
+        cases.compare_chains(got, exp, ties, D)
         eg = el[eo:eo + S * C]
         ee = oh.local_energy(om, pe, got.reshape(-1, N))
         assert np.abs(eg - ee).max() <= tol * max(1.0, np.abs(ee).max()), k

@@ -96,20 +96,6 @@ def test_chain_init_bit_exact(lib, name):
     assert np.array_equal(ch.cpu().numpy(), exp)
 
 
-def _compare_chains(got, exp, ties, n_sweeps):
-    """Bit-exact, except that a chain may diverge after a recorded near-tie."""
-    if np.array_equal(got, exp):
-        return 0
-    diverged = 0
-    for c in range(got.shape[1]):
-        bad = np.nonzero(np.any(got[:, c] != exp[:, c], axis=1))[0]
-        if bad.size:
-            first = bad[0]
-            assert any(tc == c and sw <= first for tc, sw, _ in ties), (c, first)
-            diverged += 1
-    return diverged
-
-
 @pytest.mark.parametrize("name,margin", [("tfim10_real_f64", 1e-12), ("heis40_cplx_f64", 1e-12),
                                          ("j1j2_4x4_cplx_f64", 1e-12), ("tfim37_cplx_f64", 1e-12),
                                          ("j1j2_6x6_cplx_f64", 1e-12), ("heis12_real_f64_flip", 1e-12),
@@ -130,7 +116,7 @@ def test_sampling_matches_oracle(lib, name, margin):
                                      init, n_sweeps, n_discard, seed=1234, counter=17,
                                      record_ties=ties, tie_margin=margin)
     got = smp.cpu().numpy()
-    diverged = _compare_chains(got, exp, ties, n_sweeps)
+    diverged = cases.compare_chains(got, exp, ties, n_discard)
     if diverged == 0:
         assert np.array_equal(ch.cpu().numpy(), last)
         assert np.array_equal(nacc.cpu().numpy(), nacc_o)

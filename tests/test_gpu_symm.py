@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+import cases
 from oracle import hamiltonian as oh, lattice as ol, quant, rbm_symm, sampler as osamp, sr as osr
 
 pytestmark = pytest.mark.gpu
@@ -127,10 +128,7 @@ def test_symm_sampling_matches_oracle(lib, name, margin):
     exp, _, _ = osamp.sample(om, pe, init, S, D, seed=21, counter=3, record_ties=ties,
                              tie_margin=margin)
     got = smp.cpu().numpy()
-    for c in range(C):
-        bad = np.nonzero(np.any(got[:, c] != exp[:, c], axis=1))[0]
-        if bad.size:
-            assert any(tc == c and sw <= bad[0] for tc, sw, _ in ties), (c, bad[0])
+    cases.compare_chains(got, exp, ties, D)
 
 
 @pytest.mark.parametrize("name", SMALL)
