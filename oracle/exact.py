@@ -9,6 +9,7 @@ results); here it pins the oracle itself:
   is spin up (sz = +1).
 * ``marshall_unitary``: the diagonal U = prod_{i in sublattice 1} sz_i.
 * ``exact_energy``: <psi|H|psi>/<psi|psi> by full enumeration.
+* ``ground_state``: the lowest eigenvector (targets of the supervised loss).
 * ``tfim_ground_energy``: free-fermion closed form of the periodic TFIM ring.
 * ``heisenberg_ring_bethe``: Bethe-ansatz ground energy of the periodic Heisenberg ring.
 
@@ -103,6 +104,20 @@ def ground_energy(model, sector_sz=None, k=1):
         return np.linalg.eigvalsh(H.toarray())[:k]
     vals = spla.eigsh(H, k=k, which="SA", tol=1e-12)[0]
     return np.sort(vals)
+
+
+def ground_state(model):
+    """Lowest eigenvalue and eigenvector of the Kronecker-built H over all 2**N basis states
+    (lattice.all_configs order), with the phase fixed so that its largest component is real
+    and positive."""
+    H = sparse_hamiltonian(model)
+    if H.shape[0] <= 2048:
+        vals, vecs = np.linalg.eigh(H.toarray())
+    else:
+        vals, vecs = spla.eigsh(H, k=1, which="SA", tol=1e-13)
+    v = vecs[:, np.argmin(vals)]
+    k = np.argmax(np.abs(v))
+    return float(np.min(vals)), v * (np.conj(v[k]) / abs(v[k]))
 
 
 def tfim_ground_energy(n, J=1.0, h=1.0):
