@@ -205,6 +205,49 @@ nqs_status nqs_sample_pt(nqs_model *model, const void *params, int8_t *chain_sig
                          int32_t chain_offset, int8_t *samples, int64_t *n_accepted,
                          int64_t *n_swaps, void *eloc, void *stream);
 
+/* ---- Supervised learning (Sec. 2.2.3): the negative log overlap of Eq. 1 with a target
+ * state t, minimised by the update of Eq. 2 from configurations drawn from |t|^2. ----
+ *
+ * Targets are given on a training set of n_states configurations (states, device int8
+ * [n_states, N], +1/-1) with log t (device, the model's value type: complex double [n_states]
+ * re/im interleaved for complex models, double for real models, i.e. positive targets).
+ *
+ * nqs_target_cdf: cdf[k] = sum_{i <= k} |t_i|^2 / max_i |t_i|^2 (device double [n_states],
+ * summed in a fixed order). */
+nqs_status nqs_target_cdf(nqs_model *model, const void *log_target, int64_t n_states,
+                          double *cdf, void *stream);
+
+/* nqs_target_draw: n direct draws from |t|^2: draw s takes the Philox4x32-10 uniform u of
+ * counter (s, counter, 0, 3) under key seed and picks the first k with cdf[k] > u cdf_last;
+ * it writes the configuration to sigma[s] (device int8 [n, N]), log t_k to
+ * log_target_out[s] (device, value type [n]) and k to index[s] (device int64 [n], may be
+ * NULL). */
+nqs_status nqs_target_draw(nqs_model *model, const double *cdf, int64_t n_states,
+                           const int8_t *states, const void *log_target, int64_t n,
+                           uint64_t seed, uint64_t counter, int8_t *sigma, void *log_target_out,
+                           int64_t *index, void *stream);
+
+/* Result of one supervised step (host memory). */
+typedef struct {
+  double loss;       /* Monte Carlo estimate of Eq. 1: -log(|sum conj R|^2 / (n sum |R|^2)),
+                        R_s = psi(sigma_s) / t(sigma_s) */
+  double overlap;    /* exp(-loss) */
+  double grad_norm;  /* ||g||_2 of the gradient below */
+  int32_t status;    /* NQS_OK, or NQS_ENONFINITE (parameters left unchanged) */
+  int32_t reserved;
+} nqs_overlap_info;
+
+/* nqs_overlap_step: one step of Eq. 2 from n >= 1 samples sigma (device int8 [n, N]) drawn
+ * from |t|^2, with their log t (device, value type [n]): p <- p - lr g with
+ * g = dL/dconj(p) = O^dagger u, u_s = |R_s|^2 / sum |R|^2 - conj(R_s) / sum conj(R)
+ * (for real parameters the real part, half of dL/dp: the convention of the SR force).
+ * params: device, the model's parameter type, updated in place unless the loss or the
+ * gradient is not finite. Uses the model's scratch (allocated on first use); synchronises
+ * the stream to fill info (host, may be NULL). */
+nqs_status nqs_overlap_step(nqs_model *model, void *params, const int8_t *sigma,
+                            const void *log_target, int64_t n, double lr,
+                            nqs_overlap_info *info, void *stream);
+
 /* log psi(sigma) = sum_i a_i sigma_i + sum_j ln cosh(theta_j), theta = W sigma + b
  * (Sec. 2.2.2: RBM as a one-layer ln cosh network plus visible bias; the constant
  * M ln 2 of prod_j 2 cosh is dropped). sigma (device) [n, N]; logpsi (device) [n]

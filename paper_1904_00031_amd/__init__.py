@@ -70,6 +70,16 @@ class SRInfo(ctypes.Structure):
 SR_INFO_BYTES = ctypes.sizeof(SRInfo)
 
 
+class OverlapInfo(ctypes.Structure):
+    _fields_ = [
+        ("loss", ctypes.c_double), ("overlap", ctypes.c_double), ("grad_norm", ctypes.c_double),
+        ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 def sr_infos_from_device(buf, count=1):
     """Decode nqs_sr_info structs written to a device uint8 tensor by the stream-ordered
     SR calls (copies the bytes to the host; synchronises)."""
@@ -100,6 +110,9 @@ def load(path=LIB_PATH):
         "nqs_log_psi": (i32, [vp, vp, vp, i64, vp, vp]),
         "nqs_local_energy": (i32, [vp, vp, vp, i64, vp, vp]),
         "nqs_log_psi_grad": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
+        "nqs_target_cdf": (i32, [vp, vp, i64, vp, vp]),
+        "nqs_target_draw": (i32, [vp, vp, i64, vp, vp, i64, u64, u64, vp, vp, vp, vp]),
+        "nqs_overlap_step": (i32, [vp, vp, vp, vp, i64, ctypes.c_double, vp, vp]),
         "nqs_log_psi_grad_noalloc": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
         "nqs_sr_workspace_bytes": (ctypes.c_size_t, [vp, i64]),
         "nqs_sr_step": (i32, [vp, vp, vp, vp, i64, i32, f64, f64, f64, i32, vp, ctypes.c_size_t,
@@ -142,6 +155,7 @@ def exported_symbols():
             "nqs_sr_prepare",
             "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_set_cg_graphs",
             "nqs_time_kernel", "nqs_kernel_ms",
+            "nqs_target_cdf", "nqs_target_draw", "nqs_overlap_step",
             "nqs_batch_create",
             "nqs_batch_destroy", "nqs_batch_n_params", "nqs_batch_chain_init",
             "nqs_batch_sample", "nqs_batch_sr_workspace_bytes", "nqs_batch_sr_step",
@@ -418,6 +432,47 @@ class Model:
                                       int(cg_maxiter), _ptr(workspace), workspace.numel(),
                                       _ptr(info), _stream()), "nqs_sr_step_async")
         return info
+
+    def target_cdf(self, log_target):
+        """Cumulative |t|^2 (scaled) of a training set's log targets [n_states]."""
+        import torch
+        n = log_target.shape[0]
+        _need(log_target, "log_target", self.value_dtype, (n,))
+        cdf = torch.empty(n, dtype=torch.float64, device=log_target.device)
+        _check(_lib.nqs_target_cdf(self._h, _ptr(log_target), n, _ptr(cdf), _stream()),
+               "nqs_target_cdf")
+        return cdf
+
+    def target_draw(self, cdf, states, log_target, n, seed, counter):
+        """n draws from |t|^2 over the training set; returns (sigma [n, N], log t [n],
+        index [n])."""
+        import torch
+        ns = states.shape[0]
+        _need(cdf, "cdf", torch.float64, (ns,))
+        _need(states, "states", torch.int8, (ns, self.n_sites))
+        _need(log_target, "log_target", self.value_dtype, (ns,))
+        dev = states.device
+        sigma = torch.empty((n, self.n_sites), dtype=torch.int8, device=dev)
+        lt = torch.empty(n, dtype=self.value_dtype, device=dev)
+        idx = torch.empty(n, dtype=torch.int64, device=dev)
+        _check(_lib.nqs_target_draw(self._h, _ptr(cdf), ns, _ptr(states), _ptr(log_target), n,
+                                    seed, counter, _ptr(sigma), _ptr(lt), _ptr(idx), _stream()),
+               "nqs_target_draw")
+        return sigma, lt, idx
+
+    def overlap_step(self, params, sigma, log_target, lr):
+        """One step of Eq. 2 from target-distributed samples (params updated in place);
+        returns the info dict (loss, overlap, grad_norm, status)."""
+        import torch
+        _need(params, "params", self.param_dtype, (self.n_params,))
+        n = sigma.shape[0]
+        _need(sigma, "sigma", torch.int8, (n, self.n_sites))
+        _need(log_target, "log_target", self.value_dtype, (n,))
+        info = OverlapInfo()
+        _check(_lib.nqs_overlap_step(self._h, _ptr(params), _ptr(sigma), _ptr(log_target), n,
+                                     float(lr), ctypes.byref(info), _stream()),
+               "nqs_overlap_step", allow=(OK, ENONFINITE))
+        return info.as_dict()
 
     def sr_prepare(self, params, sigma, workspace=None):
         """Prepare the implicit S of these samples; returns the workspace to pass to

@@ -493,6 +493,34 @@ nqs_status nqs_log_psi_grad_noalloc(nqs_model *m, const void *params, const int8
 }
 
 
+nqs_status nqs_target_cdf(nqs_model *m, const void *log_target, int64_t n_states, double *cdf,
+                          void *stream) {
+  if (!m || !log_target || !cdf || n_states < 1) return NQS_EINVAL;
+  return dev(launch_target_cdf(m, log_target, n_states, cdf, (hipStream_t)stream));
+}
+
+nqs_status nqs_target_draw(nqs_model *m, const double *cdf, int64_t n_states,
+                           const int8_t *states, const void *log_target, int64_t n,
+                           uint64_t seed, uint64_t counter, int8_t *sigma, void *log_target_out,
+                           int64_t *index, void *stream) {
+  if (!m || !cdf || !states || !log_target || n_states < 1 || n < 0 ||
+      (n > 0 && (!sigma || !log_target_out)))
+    return NQS_EINVAL;
+  if (n == 0) return NQS_OK;
+  return dev(launch_target_draw(m, cdf, n_states, states, log_target, n, seed, counter, sigma,
+                                log_target_out, index, (hipStream_t)stream));
+}
+
+nqs_status nqs_overlap_step(nqs_model *m, void *params, const int8_t *sigma,
+                            const void *log_target, int64_t n, double lr,
+                            nqs_overlap_info *info, void *stream) {
+  if (!m || !params || !sigma || !log_target || n < 1 || !isfinite(lr)) return NQS_EINVAL;
+  nqs_status s = ensure_scratch(m, overlap_scratch_bytes(m, n));
+  if (s != NQS_OK) return s;
+  return overlap_step_impl(m, params, sigma, log_target, n, lr, m->d_scratch, info,
+                           (hipStream_t)stream);
+}
+
 size_t nqs_sr_workspace_bytes(nqs_model *m, int64_t n) {
   if (!m || n < 2) return 0;
   return sr_workspace_bytes(m, n);

@@ -219,7 +219,7 @@ __device__ __forceinline__ double rng_uniform(uint32_t w1, uint32_t w2) {
   return double(x) * 0x1.0p-53;
 }
 
-enum { TAG_PROPOSAL = 0, TAG_INIT = 1, TAG_SWAP = 2 };
+enum { TAG_PROPOSAL = 0, TAG_INIT = 1, TAG_SWAP = 2, TAG_TARGET = 3 };
 
 // ---------------------------------------------------------------------------------
 // Wave-wide reductions (all 64 lanes receive the result).

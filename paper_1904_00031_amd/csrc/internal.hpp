@@ -254,6 +254,18 @@ GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch);
 hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, double *out,
                              const int *skip, hipStream_t st);
 
+// ---- supervised learning (overlap.hip) -------------------------------------------------
+hipError_t launch_target_cdf(const nqs_model *m, const void *log_t, int64_t n_states,
+                             double *cdf, hipStream_t st);
+hipError_t launch_target_draw(const nqs_model *m, const double *cdf, int64_t n_states,
+                              const int8_t *states, const void *log_t, int64_t n,
+                              uint64_t seed, uint64_t counter, int8_t *sigma, void *log_t_out,
+                              int64_t *index, hipStream_t st);
+size_t overlap_scratch_bytes(const nqs_model *m, int64_t n);
+nqs_status overlap_step_impl(nqs_model *m, void *params, const int8_t *sigma,
+                             const void *log_t, int64_t n, double lr, void *scratch,
+                             nqs_overlap_info *info, hipStream_t st);
+
 // ---- SR (sr.hip) --------------------------------------------------------------------
 size_t sr_workspace_bytes(const nqs_model *m, int64_t n);
 nqs_status sr_prepare_impl(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
