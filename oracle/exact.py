@@ -71,10 +71,11 @@ def marshall_unitary(model):
     return U
 
 
-def exact_energy(model, params):
+def exact_energy(model, params, machine=None):
     """<psi|H|psi>/<psi|psi> over all 2**N basis states (Sec. 2.2.5 first line of Eq. 5)."""
     confs = lattice.all_configs(model.n_sites)
-    lp = rbm.log_psi(params, confs, model.n_sites, model.n_hidden)
+    lp = (rbm.log_psi(params, confs, model.n_sites, model.n_hidden) if machine is None
+          else machine.log_psi(params, confs))
     psi = np.exp(lp - np.max(lp.real))
     H = sparse_hamiltonian(model)
     return (np.vdot(psi, H @ psi) / np.vdot(psi, psi))

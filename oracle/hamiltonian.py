@@ -91,10 +91,16 @@ def connected(model, sigma):
     return diag, off
 
 
-def local_energy(model, params, sigma):
-    """E_loc for each row of sigma [n, N] (Eq. 5), ratios from log psi differences."""
+def local_energy(model, params, sigma, machine=None):
+    """E_loc for each row of sigma [n, N] (Eq. 5), ratios from log psi differences.
+    machine: any ansatz with log_psi(params, sigma) (default: the RBM of the model)."""
     sig = np.atleast_2d(np.asarray(sigma))
-    lp = rbm.log_psi(params, sig, model.n_sites, model.n_hidden)
+    if machine is None:
+        def log_psi(p, s):
+            return rbm.log_psi(p, s, model.n_sites, model.n_hidden)
+    else:
+        log_psi = machine.log_psi
+    lp = log_psi(params, sig)
     out = np.zeros(sig.shape[0], dtype=np.complex128)
     for k in range(sig.shape[0]):
         diag, off = connected(model, sig[k])
@@ -102,7 +108,7 @@ def local_energy(model, params, sigma):
         if off:
             sps = np.array([sp for sp, _ in off])
             els = np.array([el for _, el in off])
-            lpp = rbm.log_psi(params, sps, model.n_sites, model.n_hidden)
+            lpp = log_psi(params, sps)
             e += np.sum(els * np.exp(lpp - lp[k]))
         out[k] = e
     if not model.is_complex and not np.iscomplexobj(params):

@@ -69,7 +69,7 @@ def init_chains(model, n_chains, seed, chain_offset=0):
     return out
 
 
-def metropolis_step(model, params, sigma, seed, chain_ids, sweep, step):
+def metropolis_step(model, params, sigma, seed, chain_ids, sweep, step, machine=None):
     """One proposal + accept/reject for every chain. sigma [C, N] is updated in place.
     Returns a bool array: accepted (real moves only)."""
     N, M = model.n_sites, model.n_hidden
@@ -89,7 +89,10 @@ def metropolis_step(model, params, sigma, seed, chain_ids, sweep, step):
         real_move = si != sk
         prop[rows, i] = sk
         prop[rows, k] = si
-    delta = rbm.log_psi(params, prop, N, M) - rbm.log_psi(params, sigma, N, M)
+    if machine is None:
+        delta = rbm.log_psi(params, prop, N, M) - rbm.log_psi(params, sigma, N, M)
+    else:
+        delta = machine.log_psi(params, prop) - machine.log_psi(params, sigma)
     two_re = 2.0 * np.real(delta)
     accept = real_move & ((two_re >= 0.0) | (u < np.exp(np.minimum(two_re, 0.0))))
     sigma[accept] = prop[accept]
@@ -97,13 +100,14 @@ def metropolis_step(model, params, sigma, seed, chain_ids, sweep, step):
 
 
 def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain_offset=0,
-           record_ties=None, tie_margin=1e-12):
+           record_ties=None, tie_margin=1e-12, machine=None):
     """Run every chain for n_discard + n_sweeps sweeps of N proposals.
 
     Returns (samples [n_sweeps, C, N], chain_sigma_out [C, N], n_accepted [C]).
     If ``record_ties`` is a list, each proposal with |u - exp(2 Re Delta)| < tie_margin is
     appended to it as (chain, sweep, step): the chain's row, the sweep counted from the
-    first of this call (discarded ones included) and the proposal within the sweep."""
+    first of this call (discarded ones included) and the proposal within the sweep.
+    machine: any ansatz with log_psi(params, sigma) (default: the RBM of the model)."""
     sigma = np.array(chain_sigma, dtype=np.int8, copy=True)
     C, N = sigma.shape
     chains = np.arange(C, dtype=np.uint64) + np.uint64(chain_offset)
@@ -112,7 +116,7 @@ def sample(model, params, chain_sigma, n_sweeps, n_discard, seed, counter, chain
     for sw in range(n_discard + n_sweeps):
         g = counter + sw
         for st in range(N):
-            acc, two_re, u = metropolis_step(model, params, sigma, seed, chains, g, st)
+            acc, two_re, u = metropolis_step(model, params, sigma, seed, chains, g, st, machine)
             n_acc += acc
             if record_ties is not None:
                 near = np.abs(u - np.exp(np.minimum(two_re, 0.0))) < tie_margin

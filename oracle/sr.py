@@ -99,10 +99,14 @@ def cg(matvec, b, tol, maxiter):
 
 
 def sr_step(model, params, samples, eloc, lr, diag_shift, cg_tol, cg_maxiter, weights=None,
-            round_tanh=None):
+            round_tanh=None, machine=None):
     """One SR update from samples [n, N] and their local energies [n].
-    Returns (new_params, info dict). round_tanh: see rbm.log_derivatives."""
-    O = rbm.log_derivatives(params, samples, model.n_sites, model.n_hidden, round_tanh)
+    Returns (new_params, info dict). round_tanh: see rbm.log_derivatives. machine: any
+    ansatz with log_derivatives(params, sigma) (default: the RBM of the model)."""
+    if machine is None:
+        O = rbm.log_derivatives(params, samples, model.n_sites, model.n_hidden, round_tanh)
+    else:
+        O = machine.log_derivatives(params, samples)
     return sr_step_from_O(O, params, eloc, lr, diag_shift, cg_tol, cg_maxiter, weights)
 
 
