@@ -60,6 +60,7 @@ typedef enum {
 typedef enum { NQS_F64 = 0, NQS_F32 = 1, NQS_BF16 = 2 } nqs_prec;
 typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_hamiltonian;
 typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;
+typedef enum { NQS_ACT_LNCOSH = 0, NQS_ACT_TANH = 1 } nqs_activation;
 
 /*
  * Model description (host memory; everything is copied by nqs_model_create).
@@ -81,9 +82,19 @@ typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;
  *    the permutations form a group. Parameters are then packed p = [a (1) | b (alpha) |
  *    W (alpha x N, row f, column i)], P = 1 + alpha + alpha N (nqs_n_params). Every entry
  *    point of a single model accepts such a model; the batch entry points do not.
+ *  - n_layers > 0 selects the feed-forward network (FFNN, Sec. 2.2.2) instead of an RBM:
+ *    L = n_layers dense layers, each followed by its activation (layer_sizes[l] outputs,
+ *    activations[l] an nqs_activation):
+ *      z_0 = sigma, y_l = W_l z_(l-1) + b_l, z_l = f_l(y_l), log psi = sum_k z_L,k,
+ *    so that one ln cosh layer is the RBM without visible bias. n_hidden is ignored.
+ *    Parameters are packed layer by layer as [b_l (n_l) | W_l (n_l x n_(l-1), row j,
+ *    column k)] with n_0 = n_sites. FFNN models run nqs_log_psi, nqs_local_energy,
+ *    nqs_sample, nqs_log_psi_grad, nqs_sr_step(_async) and nqs_overlap_step in FP64 or
+ *    FP32 (not BF16); the other entry points return NQS_EUNSUPPORTED.
  * Limits: 2 <= n_sites <= 1024, 1 <= n_hidden <= 2048, bonds within [0, n_sites),
  * i != j, n_bonds[0] >= 1 for exchange moves; n_symm divides n_hidden and every row of
- * symm is a permutation of 0 .. n_sites - 1.
+ * symm is a permutation of 0 .. n_sites - 1; 1 <= n_layers <= 4 with widths 1 .. 512
+ * (not together with n_symm).
  */
 typedef struct {
   int32_t n_sites;
@@ -100,6 +111,9 @@ typedef struct {
   int32_t move;                 /* nqs_move */
   int32_t n_symm;               /* 0: RBM; G > 0: symmetric RBM over G site permutations */
   const int32_t *symm;          /* host [n_symm][n_sites]; NULL when n_symm == 0 */
+  int32_t n_layers;             /* 0: RBM; 1..4: FFNN with the layers below */
+  const int32_t *layer_sizes;   /* host [n_layers]; NULL when n_layers == 0 */
+  const int32_t *activations;   /* host [n_layers], nqs_activation */
 } nqs_model_desc;
 
 typedef struct nqs_model nqs_model;

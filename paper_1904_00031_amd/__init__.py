@@ -20,6 +20,7 @@ F64, F32, BF16 = 0, 1, 2
 TIME_NONE, TIME_SWEEP, TIME_SV, TIME_ELOC = 0, 1, 2, 3
 TFIM, HEISENBERG = 0, 1
 MOVE_FLIP, MOVE_EXCHANGE = 0, 1
+ACT_LNCOSH, ACT_TANH = 0, 1
 OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 
 _lib = None
@@ -40,6 +41,8 @@ class _Desc(ctypes.Structure):
         ("ham", ctypes.c_int32), ("J", ctypes.c_double * 2), ("h", ctypes.c_double),
         ("marshall", ctypes.c_int32), ("sublattice", ctypes.c_void_p), ("move", ctypes.c_int32),
         ("n_symm", ctypes.c_int32), ("symm", ctypes.c_void_p),
+        ("n_layers", ctypes.c_int32), ("layer_sizes", ctypes.c_void_p),
+        ("activations", ctypes.c_void_p),
     ]
 
 
@@ -215,7 +218,7 @@ def nqs_hypercube_translations(L, ndim):
 
 
 def _fill_desc(d, n_sites, n_hidden, bonds, ham, J, h, marshall, sub, move, is_complex, prec,
-               symm=None):
+               symm=None, layers=None, acts=None):
     """Fill an nqs_model_desc; bonds (two int32 [B, 2] arrays), sub and symm (int32 [G, N])
     must stay alive."""
     d.n_sites, d.n_hidden = int(n_sites), int(n_hidden)
@@ -231,14 +234,20 @@ def _fill_desc(d, n_sites, n_hidden, bonds, ham, J, h, marshall, sub, move, is_c
     d.move = int(move)
     d.n_symm = 0 if symm is None else int(symm.shape[0])
     d.symm = symm.ctypes.data if symm is not None else None
+    d.n_layers = 0 if layers is None else int(layers.shape[0])
+    d.layer_sizes = layers.ctypes.data if layers is not None else None
+    d.activations = acts.ctypes.data if acts is not None else None
 
 
 class Model:
     """Handle of one lattice model + RBM shape + compute precision (nqs_model_create)."""
 
     def __init__(self, n_sites, n_hidden, bonds, ham=TFIM, J=(1.0, 0.0), h=1.0, marshall=False,
-                 sublattice=None, move=MOVE_FLIP, is_complex=False, prec=F64, symm=None):
-        """symm: site permutations [G, N] of a symmetric RBM (n_hidden = alpha G), or None."""
+                 sublattice=None, move=MOVE_FLIP, is_complex=False, prec=F64, symm=None,
+                 layers=None, activations=None):
+        """symm: site permutations [G, N] of a symmetric RBM (n_hidden = alpha G), or None.
+        layers / activations: widths and ACT_* codes of a feed-forward network (n_hidden is
+        then ignored), or None for an RBM."""
         load()
         self.n_sites, self.n_hidden = int(n_sites), int(n_hidden)
         self.is_complex, self.prec = bool(is_complex), int(prec)
@@ -249,9 +258,17 @@ class Model:
         self._sub = None if sublattice is None else np.ascontiguousarray(np.asarray(sublattice, dtype=np.int8))
         self._symm = None if symm is None else np.ascontiguousarray(np.asarray(symm, dtype=np.int32))
         self.n_symm = 0 if symm is None else int(self._symm.shape[0])
+        self._layers = None if layers is None else np.ascontiguousarray(np.asarray(layers, dtype=np.int32))
+        self._acts = None
+        if layers is not None:
+            acts = [ACT_LNCOSH] * len(layers) if activations is None else activations
+            self._acts = np.ascontiguousarray(np.asarray(acts, dtype=np.int32))
+            self.n_hidden = int(self._layers[0])
+        self.layers = None if layers is None else [int(x) for x in self._layers]
         d = _Desc()
         _fill_desc(d, self.n_sites, self.n_hidden, self._bonds, self.ham, J, h, marshall,
-                   self._sub, self.move, self.is_complex, self.prec, self._symm)
+                   self._sub, self.move, self.is_complex, self.prec, self._symm, self._layers,
+                   self._acts)
         h_ = ctypes.c_void_p()
         _check(_lib.nqs_model_create(ctypes.byref(d), ctypes.byref(h_)), "nqs_model_create")
         self._h = h_

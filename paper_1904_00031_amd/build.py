@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnqs.so")
-SOURCES = ["api.hip", "sample.hip", "grad.hip", "sr.hip", "batch.hip", "symm.hip", "overlap.hip"]
+SOURCES = ["api.hip", "sample.hip", "grad.hip", "sr.hip", "batch.hip", "symm.hip", "overlap.hip", "ffnn.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in generated code

@@ -166,6 +166,15 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
   if (d->move == NQS_MOVE_EXCHANGE && (d->n_bonds[0] < 1 || d->n_sites % 2)) return NQS_EINVAL;
   if (d->marshall && !d->sublattice) return NQS_EINVAL;
   if (d->n_symm < 0 || (d->n_symm > 0 && (!d->symm || d->n_hidden % d->n_symm))) return NQS_EINVAL;
+  if (d->n_layers < 0 || d->n_layers > kFfMaxLayers) return NQS_EINVAL;
+  if (d->n_layers > 0) {
+    if (!d->layer_sizes || !d->activations || d->n_symm > 0) return NQS_EINVAL;
+    for (int l = 0; l < d->n_layers; ++l)
+      if (d->layer_sizes[l] < 1 || d->layer_sizes[l] > kFfMaxWidth ||
+          (d->activations[l] != NQS_ACT_LNCOSH && d->activations[l] != NQS_ACT_TANH))
+        return NQS_EINVAL;
+    if (d->prec == NQS_BF16) return NQS_EUNSUPPORTED;
+  }
   if (d->n_symm > 0) {
     std::vector<char> seen(d->n_sites);
     for (int g = 0; g < d->n_symm; ++g) {
@@ -181,7 +190,34 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
   nqs_model *m = new (std::nothrow) nqs_model();
   if (!m) return NQS_ENOMEM;
   m->N = d->n_sites;
-  m->M = d->n_hidden;
+  m->M = d->n_layers > 0 ? d->layer_sizes[0] : d->n_hidden;
+  if (d->n_layers > 0) {
+    // the network's layout: parameter, table, Z-row and G-row offsets of every layer
+    FfDev &f = m->ff;
+    f.L = d->n_layers;
+    f.N = d->n_sites;
+    f.w[0] = d->n_sites;
+    f.maxw = d->n_sites;
+    int64_t p = 0, t = 0;
+    int zc = 0, gc = 0;
+    for (int l = 0; l < f.L; ++l) {
+      f.w[l + 1] = d->layer_sizes[l];
+      f.act[l] = d->activations[l];
+      f.maxw = f.w[l + 1] > f.maxw ? f.w[l + 1] : f.maxw;
+      f.poff[l] = p;
+      p += int64_t(f.w[l + 1]) * (1 + f.w[l]);
+      f.toff[l] = t;
+      t += int64_t(f.w[l]) * f.w[l + 1];
+      f.goff[l] = gc;
+      gc += f.w[l + 1];
+      f.zoff[l] = l == 0 ? 0 : zc;
+      if (l > 0) zc += f.w[l];
+    }
+    f.P = p;
+    f.tab = t;
+    f.zcols = zc;
+    f.gcols = gc;
+  }
   m->is_complex = d->is_complex ? 1 : 0;
   m->prec = d->prec;
   m->ham = d->ham;
@@ -279,6 +315,8 @@ nqs_status nqs_model_create(const nqs_model_desc *d, nqs_model **out) {
       ok = hipMemcpy(m->d_perm, d->symm, size_t(m->G) * m->N * sizeof(int),
                      hipMemcpyHostToDevice) == hipSuccess;
   }
+  if (ok && m->ff.L)
+    ok = hipMalloc(&m->d_fftab, size_t(m->ff.tab) * es) == hipSuccess;
   if (!ok) {
     nqs_model_destroy(m);
     return NQS_ENOMEM;
@@ -296,6 +334,7 @@ void nqs_model_destroy(nqs_model *m) {
   if (m->d_bond_diag) (void)hipFree(m->d_bond_diag);
   if (m->d_bond_off) (void)hipFree(m->d_bond_off);
   if (m->d_tables) (void)hipFree(m->d_tables);
+  if (m->d_fftab) (void)hipFree(m->d_fftab);
   if (m->d_perm) (void)hipFree(m->d_perm);
   if (m->d_pexp) (void)hipFree(m->d_pexp);
   if (m->d_vexp) (void)hipFree(m->d_vexp);
@@ -329,6 +368,15 @@ nqs_status nqs_sample(nqs_model *m, const void *params, int8_t *chain_sigma, int
       n_discard < 0 || chain_offset < 0)
     return NQS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  if (m->ff.L) {
+    hipError_t e = launch_ff_tables(m, params, st);
+    if (e == hipSuccess)
+      e = launch_ff_sweep(m, params, chain_sigma, n_chains, n_sweeps, n_discard, seed, counter,
+                          chain_offset, samples, n_accepted, st);
+    if (e == hipSuccess && eloc)
+      e = launch_ff_local_energy(m, params, samples, int64_t(n_sweeps) * n_chains, eloc, st);
+    return dev(e);
+  }
   // With fewer than 16 chains per compute unit (at most one wavefront per SIMD pair) the
   // sweep is latency-bound and local energies are cheaper as a separate full-occupancy
   // pass over the recorded samples; with many chains they are fused into the sweep, unless
@@ -368,7 +416,7 @@ nqs_status nqs_sample_pt(nqs_model *m, const void *params, int8_t *chain_sigma,
       n_replicas < 2 || n_replicas > 4 || n_sweeps < 1 || n_discard < 0 || chain_offset < 0 ||
       int64_t(n_chains) * n_replicas > INT32_MAX)
     return NQS_EINVAL;
-  if (!pt_supported(m)) return NQS_EUNSUPPORTED;
+  if (m->ff.L || !pt_supported(m)) return NQS_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = int64_t(n_sweeps) * n_chains;
   if (eloc) {
@@ -396,6 +444,11 @@ nqs_status nqs_log_psi(nqs_model *m, const void *params, const int8_t *sigma, in
   if (n == 0) return NQS_OK;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
+  if (m->ff.L) {
+    e = launch_ff_tables(m, params, st);
+    if (e == hipSuccess) e = launch_ff_log_psi(m, params, sigma, n, logpsi, st);
+    return dev(e);
+  }
   params = model_params(m, params, st, &e);
   if (e == hipSuccess) e = launch_tables(m, params, st);
   if (e == hipSuccess) e = launch_log_psi(m, sigma, n, logpsi, st);
@@ -407,6 +460,11 @@ nqs_status nqs_local_energy(nqs_model *m, const void *params, const int8_t *sigm
   if (!m || !params || n < 0 || (n > 0 && (!sigma || !eloc))) return NQS_EINVAL;
   if (n == 0) return NQS_OK;
   hipStream_t st = (hipStream_t)stream;
+  if (m->ff.L) {
+    hipError_t e = launch_ff_tables(m, params, st);
+    if (e == hipSuccess) e = launch_ff_local_energy(m, params, sigma, n, eloc, st);
+    return dev(e);
+  }
   nqs_status s = ensure_scratch(m, grad_scratch_bytes(m, n));
   if (s != NQS_OK) return s;
   hipError_t e;
@@ -473,6 +531,18 @@ nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigm
   bool done;
   nqs_status s = log_psi_grad_args(m, params, sigma, n, u, vjp, v, jvp, st, &done);
   if (done) return s;
+  if (m->ff.L) {
+    s = ensure_scratch(m, ff_grad_scratch_bytes(m, n));
+    if (s != NQS_OK) return s;
+    hipError_t e = launch_ff_tables(m, params, st);
+    if (e == hipSuccess) e = launch_ff_fb(m, params, sigma, n, m->d_scratch, st);
+    if (e == hipSuccess && u && vjp)
+      e = launch_ff_vjp(m, sigma, n, (const double *)u, m->d_scratch, (double *)vjp, nullptr, st);
+    if (e == hipSuccess && v && jvp)
+      e = launch_ff_jvp(m, params, sigma, n, (const double *)v, m->d_scratch, (double *)jvp,
+                        nullptr, nullptr, st);
+    return dev(e);
+  }
   s = ensure_scratch(m, grad_scratch_bytes(m, n));
   if (s != NQS_OK) return s;
   return log_psi_grad_with(m, params, sigma, n, u, vjp, v, jvp, m->d_scratch, st);
@@ -485,6 +555,7 @@ nqs_status nqs_log_psi_grad_noalloc(nqs_model *m, const void *params, const int8
   bool done;
   nqs_status s = log_psi_grad_args(m, params, sigma, n, u, vjp, v, jvp, st, &done);
   if (done) return s;
+  if (m->ff.L) return NQS_EUNSUPPORTED;
   if (grad_scratch_bytes(m, n) > kNoAllocScratchBytes) return NQS_ENOMEM;
   void *scr = nullptr;
   s = noalloc_scratch(&scr);
@@ -559,6 +630,7 @@ nqs_status nqs_sr_step_async(nqs_model *m, void *params, const int8_t *sigma, co
 nqs_status nqs_sr_prepare(nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
                           void *workspace, size_t ws_bytes, void *stream) {
   if (!m || !params || !sigma || !workspace || n < 2) return NQS_EINVAL;
+  if (m->ff.L) return NQS_EUNSUPPORTED;
   return sr_prepare_impl(m, params, sigma, n, workspace, ws_bytes, (hipStream_t)stream);
 }
 
@@ -567,6 +639,7 @@ nqs_status nqs_sr_matvec(nqs_model *m, const int8_t *sigma, int64_t n, void *wor
                          void *stream) {
   if (!m || !sigma || !workspace || !v || !out || n < 2 || !(diag_shift >= 0))
     return NQS_EINVAL;
+  if (m->ff.L) return NQS_EUNSUPPORTED;
   return sr_matvec_impl(m, sigma, n, workspace, ws_bytes, v, diag_shift, out,
                         (hipStream_t)stream);
 }
@@ -575,6 +648,7 @@ nqs_status nqs_autotune(nqs_model *m, const void *params, const int8_t *sigma, i
                         void *workspace, size_t ws_bytes, nqs_tune_report *report,
                         void *stream) {
   if (!m || !params || !sigma || !workspace || n < 2) return NQS_EINVAL;
+  if (m->ff.L) return NQS_EUNSUPPORTED;
   return autotune_impl(m, params, sigma, n, workspace, ws_bytes, report, (hipStream_t)stream);
 }
 

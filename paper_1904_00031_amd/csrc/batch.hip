@@ -60,7 +60,7 @@ nqs_status nqs_batch_create(const nqs_model_desc *descs, int32_t n_models, nqs_b
   *out = nullptr;
   for (int k = 0; k < n_models; ++k)
     if (descs[k].is_complex != descs[0].is_complex || descs[k].prec != descs[0].prec ||
-        descs[k].n_symm != 0)
+        descs[k].n_symm != 0 || descs[k].n_layers != 0)
       return NQS_EINVAL;
   nqs_batch *b = new (std::nothrow) nqs_batch();
   if (!b) return NQS_ENOMEM;

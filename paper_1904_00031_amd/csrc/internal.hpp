@@ -21,8 +21,27 @@ struct CgGraphKey {
   }
 };
 
+// the feed-forward network of a model (zero layers: an RBM). Offsets count elements of
+// the value type (complex elements for complex models).
+constexpr int kFfMaxLayers = 4;
+constexpr int kFfMaxWidth = 512;
+struct FfDev {
+  int L, N, maxw;
+  int w[kFfMaxLayers + 1];      // widths, w[0] = N
+  int act[kFfMaxLayers];        // nqs_activation of each layer
+  int64_t poff[kFfMaxLayers];   // b_l at poff[l], W_l [w[l+1]][w[l]] at poff[l] + w[l+1]
+  int64_t toff[kFfMaxLayers];   // W_l transposed [w[l]][w[l+1]] at toff[l] of the table
+  int zoff[kFfMaxLayers];       // columns of z_l (input of layer l, l >= 1) in a Z row
+  int goff[kFfMaxLayers];       // columns of g_l = d log psi / d y_l in a G row
+  int zcols, gcols;
+  int64_t P, tab;               // parameters and table elements
+};
+
 struct nqs_model {
   int N, M, is_complex, prec, ham, move, marshall;
+  // FFNN (ff.L > 0): the layer table d_fftab (W_l transposed, compute precision)
+  FfDev ff = {};
+  void *d_fftab = nullptr;
   // symmetric RBM: G site permutations (device [G][N]), alpha = M / G filters; the kernels
   // run the equivalent plain RBM on parameters expanded into d_pexp, with v_exp / g_exp
   // buffers for the Jacobian products (expanded layout, complex double)
@@ -159,6 +178,7 @@ inline int64_t n_params_exp(const nqs_model *m) {
   return int64_t(m->N) + m->M + int64_t(m->N) * m->M;
 }
 inline int64_t n_params_model(const nqs_model *m) {
+  if (m->ff.L) return m->ff.P;
   return m->G ? 1 + m->alpha + int64_t(m->alpha) * m->N : n_params_exp(m);
 }
 // p_exp (expanded RBM, master precision) from p_sym: a_i = a, b_fG+g = b_f,
@@ -253,6 +273,32 @@ GradBuffers grad_buffers(const nqs_model *m, int64_t n, void *scratch);
 // out[k] = sum of partials (double, params layout)
 hipError_t launch_vjp_reduce(const nqs_model *m, int64_t n, void *scratch, double *out,
                              const int *skip, hipStream_t st);
+
+// ---- feed-forward network (ffnn.hip) ----------------------------------------------------
+// every launcher refreshes nothing: launch_ff_tables(params) first
+hipError_t launch_ff_tables(const nqs_model *m, const void *params, hipStream_t st);
+hipError_t launch_ff_log_psi(const nqs_model *m, const void *params, const int8_t *sigma,
+                             int64_t n, void *out, hipStream_t st);
+hipError_t launch_ff_local_energy(const nqs_model *m, const void *params, const int8_t *sigma,
+                                  int64_t n, void *eloc, hipStream_t st);
+hipError_t launch_ff_sweep(const nqs_model *m, const void *params, int8_t *chain_sigma,
+                           int n_chains, int n_sweeps, int n_discard, uint64_t seed,
+                           uint64_t counter, int chain_offset, int8_t *samples, int64_t *n_acc,
+                           hipStream_t st);
+// scratch of the Jacobian products of n samples: Z and G rows, direction tables, VJP partials
+size_t ff_grad_scratch_bytes(const nqs_model *m, int64_t n);
+// forward and backward pass of every sample: Z (layer inputs) and G rows into scratch
+hipError_t launch_ff_fb(const nqs_model *m, const void *params, const int8_t *sigma, int64_t n,
+                        void *scratch, hipStream_t st);
+// y = O v (complex double [n]) and per-block partial sums of y (ysum may be NULL); v:
+// (complex) double, params layout; skip (may be NULL): nonzero -> kernels return
+hipError_t launch_ff_jvp(const nqs_model *m, const void *params, const int8_t *sigma,
+                         int64_t n, const double *v, void *scratch, double *y, double *ysum,
+                         const int *skip, hipStream_t st);
+int64_t ff_jvp_blocks(const nqs_model *m, int64_t n);
+// out = O^dagger u ((complex) double, params layout)
+hipError_t launch_ff_vjp(const nqs_model *m, const int8_t *sigma, int64_t n, const double *u,
+                         void *scratch, double *out, const int *skip, hipStream_t st);
 
 // ---- supervised learning (overlap.hip) -------------------------------------------------
 hipError_t launch_target_cdf(const nqs_model *m, const void *log_t, int64_t n_states,

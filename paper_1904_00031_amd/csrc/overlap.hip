@@ -243,10 +243,15 @@ hipError_t launch_target_draw(const nqs_model *m, const double *cdf, int64_t n_s
   return hipGetLastError();
 }
 
+// the Jacobian scratch of the model's ansatz (RBM or FFNN) at the start of the scratch
+size_t jac_bytes(const nqs_model *m, int64_t n) {
+  return m->ff.L ? ff_grad_scratch_bytes(m, n) : grad_scratch_bytes(m, n);
+}
+
 size_t overlap_scratch_bytes(const nqs_model *m, int64_t n) {
   const size_t cs = m->is_complex ? 2 : 1;
   auto r = [](size_t b) { return (b + 255) / 256 * 256; };
-  return r(grad_scratch_bytes(m, n)) + r(cs * 8 * size_t(n)) * 2 +
+  return r(jac_bytes(m, n)) + r(cs * 8 * size_t(n)) * 2 +
          r(cs * 8 * size_t(n_params_model(m))) + r(8 * (4 * kOvMaxParts + 1)) +
          r(sizeof(OvState)) + 256;
 }
@@ -257,7 +262,7 @@ nqs_status overlap_step_impl(nqs_model *m, void *params, const int8_t *sigma,
   const int cs = m->is_complex ? 2 : 1;
   auto r = [](size_t b) { return (b + 255) / 256 * 256; };
   char *base = (char *)scratch;
-  size_t off = r(grad_scratch_bytes(m, n));
+  size_t off = r(jac_bytes(m, n));
   double *lp = (double *)(base + off);
   off += r(cs * 8 * size_t(n));
   double *u = (double *)(base + off);
@@ -271,10 +276,12 @@ nqs_status overlap_step_impl(nqs_model *m, void *params, const int8_t *sigma,
   double *gn = (double *)(base + off);
   const int64_t Pc = cs * n_params_model(m);
 
-  hipError_t e;
-  const void *pe = model_params(m, params, st, &e);
-  if (e == hipSuccess) e = launch_tables(m, pe, st);
-  if (e == hipSuccess) e = launch_log_psi(m, sigma, n, lp, st);
+  hipError_t e = hipSuccess;
+  const bool ff = m->ff.L > 0;
+  const void *pe = ff ? params : model_params(m, params, st, &e);
+  if (e == hipSuccess) e = ff ? launch_ff_tables(m, pe, st) : launch_tables(m, pe, st);
+  if (e == hipSuccess)
+    e = ff ? launch_ff_log_psi(m, pe, sigma, n, lp, st) : launch_log_psi(m, sigma, n, lp, st);
   const unsigned nb = ov_blocks(n);
   double *pmax = part + 3 * kOvMaxParts + 1;
   if (e == hipSuccess) {
@@ -287,10 +294,15 @@ nqs_status overlap_step_impl(nqs_model *m, void *params, const int8_t *sigma,
                        (const double *)log_t, state, u);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, scratch, true, st);
-  if (e == hipSuccess) e = launch_vjp_partials(m, sigma, n, u, scratch, nullptr, st);
-  if (e == hipSuccess) e = launch_vjp_reduce(m, n, scratch, m->G ? m->d_gexp : g, nullptr, st);
-  if (e == hipSuccess && m->G) e = launch_symm_reduce(m, m->d_gexp, g, st);
+  if (ff) {
+    if (e == hipSuccess) e = launch_ff_fb(m, pe, sigma, n, scratch, st);
+    if (e == hipSuccess) e = launch_ff_vjp(m, sigma, n, u, scratch, g, nullptr, st);
+  } else {
+    if (e == hipSuccess) e = launch_theta_tanh(m, sigma, n, scratch, true, st);
+    if (e == hipSuccess) e = launch_vjp_partials(m, sigma, n, u, scratch, nullptr, st);
+    if (e == hipSuccess) e = launch_vjp_reduce(m, n, scratch, m->G ? m->d_gexp : g, nullptr, st);
+    if (e == hipSuccess && m->G) e = launch_symm_reduce(m, m->d_gexp, g, st);
+  }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_ov_gnorm, dim3(1), dim3(kOvThreads), 0, st, Pc, g, gn);
     if (use_double(m))

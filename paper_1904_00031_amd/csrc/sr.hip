@@ -670,12 +670,13 @@ __global__ void k_sr_info(const CGState *st, nqs_sr_info *out) {
 
 struct SRLayout {
   size_t grad, y, ysum, u, e_part, e_part2, cm, c_part, c_part2, o1, g, F, x, r, p, Ap, dpart,
-      rpart, vexp, apexp, o1s, gs, state, total;
+      rpart, vexp, apexp, o1s, gs, ybar, state, total;
 };
 
 SRLayout sr_layout(const nqs_model *m, int64_t n) {
   const int cs = m->is_complex ? 2 : 1;
-  const int64_t P = int64_t(m->N) + m->M + int64_t(m->N) * m->M;
+  const bool ff = m->ff.L > 0;
+  const int64_t P = ff ? m->ff.P : int64_t(m->N) + m->M + int64_t(m->N) * m->M;
   const int64_t nb = cdiv(n, 256);
   const int64_t pb = cdiv(P, 256) < 4096 ? cdiv(P, 256) : 4096;
   SRLayout L;
@@ -685,9 +686,9 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  L.grad = take(grad_scratch_bytes(m, n));
+  L.grad = take(ff ? ff_grad_scratch_bytes(m, n) : grad_scratch_bytes(m, n));
   L.y = take(size_t(n) * cs * 8);
-  const int64_t ns = grad_plan(m, n).splits;
+  const int64_t ns = ff ? ff_jvp_blocks(m, n) : grad_plan(m, n).splits;
   const int64_t ncap = ns > 2 * int64_t(m->cu_count) ? ns : 2 * int64_t(m->cu_count);
   L.ysum = take(size_t(nb > ncap ? nb : ncap) * 16);
   L.u = take(size_t(n) * cs * 8);
@@ -707,7 +708,7 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
     // partial sums of p^dagger Ap: per block of the parameter range, or of the VJP tile
     // layout (k_cg_apr), whichever has more blocks
     const GradPlan gq = grad_plan(m, n);
-    const int64_t ab = cdiv(int64_t(gq.Jtiles) * 16 * gq.Itiles * 16, kAprElems);
+    const int64_t ab = ff ? 0 : cdiv(int64_t(gq.Jtiles) * 16 * gq.Itiles * 16, kAprElems);
     L.dpart = take(size_t(pb > ab ? pb : ab) * 8);
   }
   const int64_t cb = cdiv(P * cs, 256) < 4096 ? cdiv(P * cs, 256) : 4096;
@@ -720,6 +721,7 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   L.apexp = take(se);
   L.o1s = take(ss);
   L.gs = take(ss);
+  L.ybar = take(16);
   L.state = take(sizeof(CGState));
   L.total = off;
   return L;
@@ -1121,6 +1123,129 @@ nqs_status sr_symm_impl(nqs_model *m, void *params, const int8_t *sigma, const v
     else
       hipLaunchKernelGGL(k_update<float>, dim3(grid_for(Pcs)), dim3(256), 0, st, Pcs,
                          (float *)params, (const double *)D(L.x), lr, (const CGState *)state);
+    return hipGetLastError();
+  };
+  if (async) {
+    for (int it = 0; it < cg_maxiter; ++it) HIPTRY(iteration(it & 1));
+    HIPTRY(update());
+    hipLaunchKernelGGL(k_sr_info, dim3(1), dim3(64), 0, st, (const CGState *)state, info);
+    HIPTRY(hipGetLastError());
+    return NQS_OK;
+  }
+  CGState hs;
+  int launched = 0;
+  for (;;) {
+    HIPTRY(hipMemcpyAsync(&hs, state, sizeof(CGState), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (hs.done || launched >= cg_maxiter) break;
+    const int batch = cg_maxiter - launched < 8 ? cg_maxiter - launched : 8;
+    for (int q = 0; q < batch; ++q, ++launched) HIPTRY(iteration(launched & 1));
+  }
+  nqs_sr_info out;
+  fill_info(hs, &out);
+  if (out.status != NQS_ENONFINITE) HIPTRY(update());
+  HIPTRY(hipStreamSynchronize(st));
+  if (info) *info = out;
+  return nqs_status(out.status);
+}
+
+// ---- feed-forward network: the same CG with the network's Jacobian products ----------
+// ybar = mean of y = O p from the JVP's block partials (fixed order)
+__global__ __launch_bounds__(256) void k_ff_ybar(const double *ysum, int64_t nparts, int64_t n,
+                                                 double *ybar, const CGState *st) {
+  if (st && st->done) return;
+  __shared__ double lds[256];
+  const double a = block_sum(ysum, nparts, 2, lds);
+  const double b = block_sum(ysum + 1, nparts, 2, lds);
+  if (threadIdx.x == 0) {
+    ybar[0] = a / double(n);
+    ybar[1] = b / double(n);
+  }
+}
+
+// Ap = (O^dagger y - ybar O^dagger 1) / n, in place on O^dagger y
+template <bool C>
+__global__ void k_ff_apr(int64_t P, int64_t n, const double *o1, const double *ybar,
+                         double *Ap, const CGState *st) {
+  if (st && st->done) return;
+  const double yr = ybar[0], yi = C ? ybar[1] : 0.0, inv = 1.0 / double(n);
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < P;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    if (C) {
+      const double orr = o1[2 * k], oi = o1[2 * k + 1];
+      Ap[2 * k] = (Ap[2 * k] - (yr * orr - yi * oi)) * inv;
+      Ap[2 * k + 1] = (Ap[2 * k + 1] - (yr * oi + yi * orr)) * inv;
+    } else {
+      Ap[k] = (Ap[k] - yr * o1[k]) * inv;
+    }
+  }
+}
+
+template <typename T, bool C>
+nqs_status sr_ff_impl(nqs_model *m, void *params, const int8_t *sigma, const void *eloc,
+                      int64_t n, int64_t nch, double lr, double diag_shift, double cg_tol,
+                      int cg_maxiter, void *ws, nqs_sr_info *info, bool async, hipStream_t st) {
+  SRLayout L = sr_layout(m, n);
+  char *b = (char *)ws;
+  auto D = [&](size_t off) { return (double *)(b + off); };
+  CGState *state = (CGState *)(b + L.state);
+  void *grad = b + L.grad;
+  const int cs = C ? 2 : 1;
+  const int64_t Ps = n_params_model(m), Pcs = Ps * cs;
+  const int64_t nb = cdiv(n, 256);
+  const int64_t sblocks = cdiv(Ps, 256) < 4096 ? cdiv(Ps, 256) : 4096;
+  const int64_t scblocks = cdiv(Pcs, 256) < 4096 ? cdiv(Pcs, 256) : 4096;
+  const int64_t jb = ff_jvp_blocks(m, n);
+
+  HIPTRY(launch_ff_tables(m, params, st));
+  hipLaunchKernelGGL((k_sum_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
+                     (const double *)eloc, D(L.e_part));
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL((k_center_e<C>), dim3(unsigned(nb)), dim3(256), 0, st, n,
+                     (const double *)eloc, D(L.e_part), nb, D(L.u), D(L.e_part2), state);
+  HIPTRY(hipGetLastError());
+  const int64_t ncb = cdiv(nch, kChainsPerBlock), ncb2 = cdiv(nch, 256);
+  hipLaunchKernelGGL((k_chain_mean<C>), dim3(unsigned(ncb)), dim3(256), 0, st, n, nch,
+                     (const double *)eloc, D(L.cm), D(L.c_part));
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL(k_chain_dev, dim3(unsigned(ncb2)), dim3(256), 0, st, nch, D(L.cm),
+                     D(L.c_part), ncb, D(L.c_part2));
+  HIPTRY(hipGetLastError());
+  // the network's rows, O^dagger 1 and the force numerator
+  HIPTRY(launch_ff_fb(m, params, sigma, n, grad, st));
+  hipLaunchKernelGGL((k_ones<C>), dim3(grid_for(n)), dim3(256), 0, st, n, D(L.y));
+  HIPTRY(hipGetLastError());
+  HIPTRY(launch_ff_vjp(m, sigma, n, D(L.y), grad, D(L.o1), nullptr, st));
+  HIPTRY(launch_ff_vjp(m, sigma, n, D(L.u), grad, D(L.g), nullptr, st));
+  hipLaunchKernelGGL((k_symm_cg_init<C>), dim3(unsigned(sblocks)), dim3(256), 0, st, Ps, n,
+                     D(L.e_part2), nb, D(L.g), D(L.F), D(L.x), D(L.r), D(L.p), D(L.dpart),
+                     state);
+  HIPTRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, st, D(L.dpart), sblocks, cg_tol,
+                     cg_maxiter, state, D(L.c_part2), ncb2, nch);
+  HIPTRY(hipGetLastError());
+  const int *skip = &state->done;
+  auto iteration = [&](int parity) -> hipError_t {
+    hipError_t e = launch_ff_jvp(m, params, sigma, n, D(L.p), grad, D(L.y), D(L.ysum), skip, st);
+    if (e == hipSuccess) e = launch_ff_vjp(m, sigma, n, D(L.y), grad, D(L.Ap), skip, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ff_ybar, dim3(1), dim3(256), 0, st, D(L.ysum), jb, n, D(L.ybar),
+                       (const CGState *)state);
+    hipLaunchKernelGGL((k_ff_apr<C>), dim3(unsigned(sblocks)), dim3(256), 0, st, Ps, n,
+                       D(L.o1), D(L.ybar), D(L.Ap), (const CGState *)state);
+    hipLaunchKernelGGL(k_symm_shift_dot, dim3(unsigned(sblocks)), dim3(256), 0, st, Pcs,
+                       D(L.p), diag_shift, D(L.Ap), D(L.dpart), (const CGState *)state);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.dpart),
+                       sblocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.rpart),
+                       scblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p), state);
+    return hipGetLastError();
+  };
+  auto update = [&]() -> hipError_t {
+    hipLaunchKernelGGL(k_update<T>, dim3(grid_for(Pcs)), dim3(256), 0, st, Pcs, (T *)params,
+                       (const double *)D(L.x), lr, (const CGState *)state);
     return hipGetLastError();
   };
   if (async) {
@@ -1720,7 +1845,9 @@ nqs_status sr_step_impl(nqs_model *m, void *params, const int8_t *sigma, const v
   if (ws_bytes < sr_layout(m, n).total) return NQS_ENOMEM;
   const int64_t nch = n_chains > 0 ? n_chains : n;
 #define NQS_SR(T, C)                                                                          \
-  (m->G ? sr_symm_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol,         \
+  (m->ff.L ? sr_ff_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol,        \
+                              cg_maxiter, ws, info, async, st) :                              \
+   m->G ? sr_symm_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol,         \
                              cg_maxiter, ws, info, async, st)                                 \
         : sr_impl<T, C>(m, params, sigma, eloc, n, nch, lr, diag_shift, cg_tol, cg_maxiter,   \
                         ws, info, async, st))

@@ -4,6 +4,7 @@ import numpy as np
 
 import synth
 from oracle import hamiltonian as oh
+from oracle import sr as osr
 from oracle import lattice as ol
 
 # name: (L, ndim, diagonals, ham, J, h, marshall, move, complex, prec, M)
@@ -135,3 +136,15 @@ def compare_chains(got, exp, ties, n_discard):
             assert any(tc == c and sw - n_discard <= bad[0] for tc, sw, _ in ties), (c, bad[0])
             diverged += 1
     return diverged
+
+
+def cg_sensitivity(O, el, shift, iters, rel=1e-15, seed=0):
+    """How far the oracle's own CG result moves when every matrix-vector product is
+    perturbed by `rel` relative noise: finite-precision CG amplifies rounding by a factor
+    that grows with the condition number of S + shift I."""
+    F = osr.force(O, el)
+    A = osr.s_matrix(O) + shift * np.eye(O.shape[1])
+    x0, _, _ = osr.cg(lambda v: A @ v, F, 0.0, iters)
+    rng = np.random.default_rng(seed)
+    x1, _, _ = osr.cg(lambda v: (A @ v) * (1 + rel * rng.normal(size=v.shape)), F, 0.0, iters)
+    return np.abs(x1 - x0).max() / np.abs(x0).max()

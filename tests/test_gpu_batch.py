@@ -100,7 +100,6 @@ def test_batch_mixed_models_fp64(lib):
 
 def check_batch_sr(lib, kinds, prec, cplx, n_list, fp64):
     from oracle import rbm as orbm, sr as osr
-    from test_gpu_parity import cg_sensitivity
     b, specs, oracles = make(lib, kinds, prec, cplx)
     ps = params_of(oracles, cplx, prec, seed=200)
     ss, els = [], []
@@ -129,7 +128,7 @@ def check_batch_sr(lib, kinds, prec, cplx, n_list, fp64):
             O = orbm.log_derivatives(pe, ss[k], om.n_sites, om.n_hidden)
             if not cplx:
                 O = O.real
-            tol = max(1e-9, 10 * cg_sensitivity(O, els[k], 0.01, 12))
+            tol = max(1e-9, 10 * cases.cg_sensitivity(O, els[k], 0.01, 12))
             assert np.abs(step_g - step_o).max() <= tol * np.abs(step_o).max(), k
         else:
             assert np.abs(step_g - step_o).max() <= 1e-4 * np.abs(step_o).max() + 1e-7, k

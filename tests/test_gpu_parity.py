@@ -152,18 +152,6 @@ def test_fused_local_energy_matches_oracle(lib, name):
     assert np.abs(el.cpu().numpy() - exp).max() <= cases.tol(name) * scale
 
 
-def cg_sensitivity(O, el, shift, iters, rel=1e-15, seed=0):
-    """How far the oracle's own CG result moves when every matrix-vector product is
-    perturbed by `rel` relative noise: finite-precision CG amplifies rounding by a factor
-    that grows with the condition number of S + shift I."""
-    F = osr.force(O, el)
-    A = osr.s_matrix(O) + shift * np.eye(O.shape[1])
-    x0, _, _ = osr.cg(lambda v: A @ v, F, 0.0, iters)
-    rng = np.random.default_rng(seed)
-    x1, _, _ = osr.cg(lambda v: (A @ v) * (1 + rel * rng.normal(size=v.shape)), F, 0.0, iters)
-    return np.abs(x1 - x0).max() / np.abs(x0).max()
-
-
 @pytest.mark.parametrize("name", ["tfim10_real_f64", "heis40_cplx_f32", "j1j2_4x4_cplx_f64", "heis6x6_cplx_f32"])
 def test_local_energy_fused_in_sweep(lib, name):
     """With >= 16 chains per compute unit the local energies are evaluated inside the
@@ -205,7 +193,7 @@ def test_sr_step_fixed_iterations(lib, name):
     O = orbm.log_derivatives(pe, s, om.n_sites, om.n_hidden)
     if not m.is_complex:
         O = O.real
-    tol = max(1e-9, 10 * cg_sensitivity(O, el, 0.01, 12))
+    tol = max(1e-9, 10 * cases.cg_sensitivity(O, el, 0.01, 12))
     dx = pt.cpu().numpy() - p_new
     assert np.abs(dx).max() <= tol * np.abs(p_new - pe).max()
 

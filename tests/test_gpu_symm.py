@@ -164,7 +164,6 @@ def test_symm_jvp_vjp_and_sv(lib, name):
 
 @pytest.mark.parametrize("name", ["symm_tfim10_real_f64", "symm_heis20_cplx_f64"])
 def test_symm_sr_step_fixed_iterations(lib, name):
-    from test_gpu_parity import cg_sensitivity
     m, om, perm, alpha = build(lib, name)
     p = params(name, 0.5, 23)
     pe = oracle_params(name, p)
@@ -181,7 +180,7 @@ def test_symm_sr_step_fixed_iterations(lib, name):
     assert abs(info["energy_re"] - np.real(io["energy"])) <= 1e-10 * abs(io["energy"])
     if not m.is_complex:
         O = O.real
-    tol = max(1e-9, 10 * cg_sensitivity(O, el, 0.01, 12))
+    tol = max(1e-9, 10 * cases.cg_sensitivity(O, el, 0.01, 12))
     assert np.abs(pt.cpu().numpy() - p_new).max() <= tol * np.abs(p_new - pe).max()
     # the stream-ordered step gives the same parameters
     pa = to_dev(p.copy())
