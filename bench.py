@@ -15,9 +15,11 @@ contractions) with FP64 CG; parameters N(0, 0.01^2) from seed 1234; 8192 chains 
 Prints one JSON line. value = samples per second of whole steps. Extra fields: phase
 times, the roofline of the step's dominant kernel (measured live with HIP events on the
 launch stream), the other workloads of the benchmark family (10-site TFIM, 40-site
-Heisenberg ring, 10x10 J1-J2 in FP32 and BF16, and the batch of 64 TFIM rings replayed
-from a captured graph) with their own rooflines, the FP64 / FP32 / BF16 forms of the
-40-site ring compared at a fixed energy error, and the FP64 oracle timed on the host.
+Heisenberg ring, 10x10 J1-J2 in FP32 and BF16, the symmetric RBM, the batch of 64 TFIM
+rings replayed from a captured graph, parallel tempering on the 6x6 J1-J2 lattice, a
+two-layer feed-forward network on the 40-site ring, and supervised learning of a 20-site
+target) with their own rooflines or rates, the FP64 / FP32 / BF16 forms of the 40-site
+ring compared at a fixed energy error, and the FP64 oracle timed on the host.
 """
 import argparse
 import json
@@ -88,6 +90,28 @@ BATCH_WORKLOADS = {
                                                      lr=0.01, shift=0.01, cg_tol=1e-8,
                                                      cg_maxiter=100),
 }
+
+# parallel tempering: 10x10 is beyond the tempered FP32 sweep (at most 256 hidden units),
+# so the 6x6 J1-J2 lattice (J2 = 0.5), complex FP32 RBM alpha = 4, 2048 tempered chains of
+# 4 replicas (beta = 1, 3/4, 1/2, 1/4), 4 recorded sweeps per step with local energies
+PT_WORKLOAD = dict(name="j1j2_6x6_cplx_fp32_alpha4_pt4", L=6, ndim=2, diag=True, ham=1,
+                   J=(1.0, 0.5), h=0.0, marshall=True, move=1, cplx=True, prec=1, alpha=4,
+                   chains=2048, replicas=4, sweeps=4)
+
+# the feed-forward network: 40-site Heisenberg ring, two dense layers 40 -> 80 -> 40 with
+# ln cosh activations, complex FP32, parameters N(0, 0.01^2); 1024 chains x 20 sweeps per
+# step, SR with shift 0.01, lr 0.01, CG tolerance 1e-8, at most 200 products
+FF_WORKLOAD = dict(name="heisenberg1d_n40_cplx_fp32_ffnn80x40", L=40, ndim=1, diag=False, ham=1,
+                   J=(1.0, 0.0), h=0.0, marshall=True, move=1, cplx=True, prec=1,
+                   layers=[80, 40], acts=[0, 0], chains=1024, sweeps=20, lr=0.01, shift=0.01,
+                   cg_tol=1e-8, cg_maxiter=200)
+
+# supervised learning (Eq. 1, Eq. 2): a 20-site training set (all 2^20 configurations) whose
+# target is a teacher RBM (20 hidden units, complex, N(0, 0.1^2), seed 7); student complex
+# FP32 RBM with 40 hidden units, N(0, 0.01^2) from seed 1234; 16384 direct draws per step,
+# SGD with lr 0.05
+SUP_WORKLOAD = dict(name="supervised_n20_teacher_rbm_student_alpha2_fp32", N=20, M_teacher=20,
+                    M=40, prec=1, batch=16384, lr=0.05)
 
 GOLDEN = os.path.join(ROOT, "tests", "golden", "reference_energies.txt")
 
@@ -371,6 +395,202 @@ class Single:
 
 
 # ---- batch of models, graph-captured step ------------------------------------------------
+def bench_pt(nqs, synth, torch, steps, warmup):
+    """Tempered sampling with local energies: recorded samples per second, the sweep
+    kernel's roofline over every replica's proposals, exchange acceptance."""
+    w = PT_WORKLOAD
+    dev = torch.device("cuda:0")
+    N = w["L"] ** w["ndim"]
+    M = w["alpha"] * N
+    C, R, S = w["chains"], w["replicas"], w["sweeps"]
+    bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
+    m = nqs.Model(N, M, bonds, ham=w["ham"], J=w["J"], h=w["h"], marshall=w["marshall"],
+                  sublattice=sub, move=w["move"], is_complex=w["cplx"], prec=w["prec"])
+    p = torch.from_numpy(synth.rbm_params(N, M, w["cplx"], sigma=0.01, seed=1234)).to(dev)
+    p = p.to(m.param_dtype)
+    ch = torch.empty((C * R, N), dtype=torch.int8, device=dev)
+    m.chain_init(ch, seed=1234)
+    reps = ch.view(C, R, N)
+    tix = torch.arange(R, dtype=torch.int32, device=dev).repeat(C, 1).contiguous()
+    samples = torch.empty((S, C, N), dtype=torch.int8, device=dev)
+    eloc = torch.empty(S * C, dtype=m.value_dtype, device=dev)
+    nsw = torch.zeros(C, dtype=torch.int64, device=dev)
+    counter = 0
+    for k in range(warmup):
+        m.sample_pt(p, reps, tix, S, 10 if k == 0 else 0, seed=1234, counter=counter,
+                    samples=samples, eloc=eloc)
+        counter += S + (10 if k == 0 else 0)
+    torch.cuda.synchronize()
+    m.time_kernel(nqs.TIME_SWEEP)
+    sweep_k, swaps = [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.sample_pt(p, reps, tix, S, 0, seed=1234, counter=counter, samples=samples, eloc=eloc,
+                    n_swaps=nsw)
+        counter += S
+        sweep_k.append(m.kernel_ms())
+        swaps += int(nsw.sum().item())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m.time_kernel(nqs.TIME_NONE)
+    ms = wall * 1e3 / steps
+    sweep_ms = float(np.mean(sweep_k))
+    b = torch.from_numpy(np.asarray(bonds[0], dtype=np.int64)).to(dev)
+    s = samples.view(-1, N)
+    f_real = float((s[:, b[:, 0]] != s[:, b[:, 1]]).float().mean().item())
+    fl = float(C) * R * S * N * f_real * M * sweep_terms_flops(w["cplx"])
+    ach = fl / (sweep_ms * 1e-3)
+    return {"workload": w["name"], "dtype": "f32", "ms_per_step": ms,
+            "samples_per_step": S * C, "value": S * C / (ms * 1e-3), "unit": "samples/s",
+            "replica_sweeps_per_s": C * R * S / (ms * 1e-3),
+            "swap_acceptance": swaps / float(steps * S * C * (R - 1)),
+            "energy_per_site": float(eloc.real.mean().item()) / N,
+            "roofline": {"kernel": "k_sweep (tempered)", "bound": "alu", "achieved": ach / 1e12,
+                         "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                         "algorithmic_flops": fl, "launch_ms": sweep_ms,
+                         "real_move_fraction": f_real}}
+
+
+def ff_macs(layers, N, first=True):
+    """Multiply-adds of one forward pass of the dense layers (from layer 0 or layer 1)."""
+    w = [N] + list(layers)
+    return sum(w[l] * w[l + 1] for l in range(0 if first else 1, len(layers)))
+
+
+def bench_ffnn(nqs, synth, torch, steps, warmup):
+    """The network's VMC step (sampling + local energies + SR): samples per second, phase
+    and kernel times, and the roofline of the kernel that takes most of the step."""
+    w = FF_WORKLOAD
+    dev = torch.device("cuda:0")
+    N = w["L"] ** w["ndim"]
+    C, S = w["chains"], w["sweeps"]
+    bonds, sub = nqs.nqs_hypercube(w["L"], w["ndim"], w["diag"])
+    m = nqs.Model(N, w["layers"][0], bonds, ham=w["ham"], J=w["J"], h=w["h"],
+                  marshall=w["marshall"], sublattice=sub, move=w["move"], is_complex=w["cplx"],
+                  prec=w["prec"], layers=w["layers"], activations=w["acts"])
+    rng = np.random.default_rng(1234)
+    P = m.n_params
+    p = rng.normal(0, 0.01, P) + 1j * rng.normal(0, 0.01, P)
+    params = torch.from_numpy(p).to(dev).to(m.param_dtype)
+    ch = torch.empty((C, N), dtype=torch.int8, device=dev)
+    m.chain_init(ch, seed=1234)
+    samples = torch.empty((S, C, N), dtype=torch.int8, device=dev)
+    eloc = torch.empty(S * C, dtype=m.value_dtype, device=dev)
+    ws = torch.empty(m.sr_workspace_bytes(S * C), dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream()
+    counter = 0
+
+    def step(discard, ev=None):
+        nonlocal counter
+        if ev:
+            ev[0].record(st)
+        m.sample(params, ch, S, discard, seed=1234, counter=counter, samples=samples, eloc=eloc)
+        counter += S + discard
+        if ev:
+            ev[1].record(st)
+        info = m.sr_step(params, samples.view(S * C, N), eloc, w["lr"], w["shift"], w["cg_tol"],
+                         w["cg_maxiter"], workspace=ws, n_chains=C)
+        if ev:
+            ev[2].record(st)
+        return info
+
+    for k in range(warmup):
+        step(10 if k == 0 else 0)
+    torch.cuda.synchronize()
+    m.time_kernel(nqs.TIME_SWEEP)
+    evs, infos, sweep_k = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        infos.append(step(0, ev))
+        evs.append(ev)
+        sweep_k.append(m.kernel_ms())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n = S * C
+    flat = samples.view(n, N)
+    m.time_kernel(nqs.TIME_ELOC)
+    el_k = []
+    for _ in range(4):
+        m.local_energy(params, flat, out=torch.empty_like(eloc))
+        el_k.append(m.kernel_ms())
+    m.time_kernel(nqs.TIME_SV)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    v = torch.randn(P, dtype=m.value_dtype, generator=gen).to(dev)
+    u = torch.randn(n, dtype=m.value_dtype, generator=gen).to(dev)
+    sv_k = []
+    for _ in range(6):
+        m.log_psi_grad(params, flat, u=u, v=v)
+        sv_k.append(m.kernel_ms())
+    m.time_kernel(nqs.TIME_NONE)
+    ms = wall * 1e3 / steps
+    sweep_ms, eloc_ms, sv_ms = (float(np.mean(sweep_k)), float(np.mean(el_k[1:])),
+                                float(np.mean(sv_k[1:])))
+    cg_mean = float(np.mean([i["cg_iters"] for i in infos]))
+    b = torch.from_numpy(np.asarray(bonds[0], dtype=np.int64)).to(dev)
+    f_real = float((flat[:, b[:, 0]] != flat[:, b[:, 1]]).float().mean().item())
+    cm = 8.0   # flops of a complex multiply-add
+    later = ff_macs(w["layers"], N, first=False)
+    per_prop = cm * later + 4.0 * 2 * w["layers"][0]   # later layers + two angle columns
+    sweep_fl = float(C) * S * N * f_real * per_prop
+    eloc_fl = float(n) * len(bonds[0]) * f_real * per_prop
+    sv_fl = float(n) * 2 * cm * ff_macs(w["layers"], N)
+    share = {"sweep": sweep_ms, "eloc": eloc_ms, "sv": sv_ms * cg_mean}
+    dom = max(share, key=share.get)
+    fl, kms, kname = {"sweep": (sweep_fl, sweep_ms, "k_ff_sweep"),
+                      "eloc": (eloc_fl, eloc_ms, "k_ff_eloc"),
+                      "sv": (sv_fl, sv_ms, "k_ff_prep_dir + k_ff_jvp + k_ff_vjp + "
+                                          "k_ff_vjp_reduce")}[dom]
+    ach = fl / (kms * 1e-3)
+    return {"workload": w["name"], "dtype": "f32", "ms_per_step": ms, "samples_per_step": n,
+            "value": n / (ms * 1e-3), "unit": "samples/s", "sr_iters_per_s": 1e3 / ms,
+            "phase_ms": {"sample_and_eloc": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+                         "sr_step": float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))},
+            "kernel_ms": {"sweep": sweep_ms, "local_energy": eloc_ms, "jvp_plus_vjp": sv_ms},
+            "cg_iters_mean": cg_mean, "energy_last": infos[-1]["energy_re"],
+            "roofline": {"kernel": kname, "bound": "alu", "achieved": ach / 1e12,
+                         "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": ach / PEAK_FP32_VALU, "traffic": None, "algorithmic_flops": fl,
+                         "launch_ms": kms, "step_share_ms": share}}
+
+
+def bench_supervised(nqs, synth, torch, steps, warmup):
+    """Supervised steps (direct draws from |t|^2 + the overlap step): steps and draws per
+    second, the loss before and after."""
+    w = SUP_WORKLOAD
+    dev = torch.device("cuda:0")
+    N, M = w["N"], w["M"]
+    bonds, sub = nqs.nqs_hypercube(N, 1)
+    teacher = nqs.Model(N, w["M_teacher"], bonds, is_complex=True, prec=0)
+    student = nqs.Model(N, M, bonds, is_complex=True, prec=w["prec"])
+    pt = torch.from_numpy(synth.rbm_params(N, w["M_teacher"], True, sigma=0.1, seed=7)).to(dev)
+    ps = torch.from_numpy(synth.rbm_params(N, M, True, sigma=0.01, seed=1234)).to(dev)
+    ps = ps.to(student.param_dtype)
+    idx = np.arange(2 ** N, dtype=np.int64)
+    bits = (idx[:, None] >> np.arange(N - 1, -1, -1)[None, :]) & 1
+    states = torch.from_numpy((1 - 2 * bits).astype(np.int8)).to(dev)
+    log_t = teacher.log_psi(pt, states)
+    cdf = student.target_cdf(log_t)
+    B = w["batch"]
+    infos = []
+    for k in range(warmup):
+        sig, ltb, _ = student.target_draw(cdf, states, log_t, B, seed=1234, counter=k)
+        infos.append(student.overlap_step(ps, sig, ltb, w["lr"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sig, ltb, _ = student.target_draw(cdf, states, log_t, B, seed=1234,
+                                          counter=warmup + k)
+        infos.append(student.overlap_step(ps, sig, ltb, w["lr"]))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"workload": w["name"], "dtype": "f32", "ms_per_step": ms, "draws_per_step": B,
+            "value": B / (ms * 1e-3), "unit": "samples/s", "steps_per_s": 1e3 / ms,
+            "loss_first": infos[0]["loss"], "loss_last": infos[-1]["loss"],
+            "training_set": 2 ** N}
+
+
 def batch_instances(w):
     rng = np.random.default_rng(1234)
     Ns = rng.integers(w["Nmin"], w["Nmax"] + 1, size=w["K"])
@@ -640,6 +860,12 @@ def main():
         for name in BATCH_WORKLOADS:
             log("workload " + name + " (graph-replayed step)")
             others[name] = bench_batch(nqs, synth, torch, name, args.extra_steps, 2)
+        log("workload " + PT_WORKLOAD["name"] + " (parallel tempering)")
+        others[PT_WORKLOAD["name"]] = bench_pt(nqs, synth, torch, args.extra_steps, 2)
+        log("workload " + FF_WORKLOAD["name"] + " (feed-forward network)")
+        others[FF_WORKLOAD["name"]] = bench_ffnn(nqs, synth, torch, args.extra_steps, 2)
+        log("workload " + SUP_WORKLOAD["name"] + " (supervised)")
+        others[SUP_WORKLOAD["name"]] = bench_supervised(nqs, synth, torch, 5 * args.extra_steps, 3)
         out["other_workloads"] = others
         if args.forms_iters > 0:
             out["precision_forms"] = compare_forms(nqs, synth, torch,

@@ -392,7 +392,9 @@ nqs_status nqs_set_cg_graphs(nqs_model *model, int32_t enable);
  *  NQS_TIME_SWEEP - the Metropolis sweep kernel of nqs_sample (not the table refresh, the
  *                   chain-angle set-up or local energies evaluated after the sweep)
  *  NQS_TIME_SV    - the kernels of one nqs_sr_matvec product (direction tables, the
- *                   contractions, the reduced product), without the gaps between them
+ *                   contractions, the reduced product), without the gaps between them;
+ *                   for a feed-forward network the O^dagger u and O v kernels of one
+ *                   nqs_log_psi_grad call (not its forward-backward pass)
  *  NQS_TIME_ELOC  - the local-energy kernel of nqs_local_energy (not tanh(theta)) */
 typedef enum { NQS_TIME_NONE = 0, NQS_TIME_SWEEP = 1, NQS_TIME_SV = 2, NQS_TIME_ELOC = 3 } nqs_time_what;
 nqs_status nqs_time_kernel(nqs_model *model, int32_t what);

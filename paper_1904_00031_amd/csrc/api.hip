@@ -534,6 +534,7 @@ nqs_status nqs_log_psi_grad(nqs_model *m, const void *params, const int8_t *sigm
   if (m->ff.L) {
     s = ensure_scratch(m, ff_grad_scratch_bytes(m, n));
     if (s != NQS_OK) return s;
+    time_begin(m, NQS_TIME_SV);   // the network's products: one timing pair per launcher
     hipError_t e = launch_ff_tables(m, params, st);
     if (e == hipSuccess) e = launch_ff_fb(m, params, sigma, n, m->d_scratch, st);
     if (e == hipSuccess && u && vjp)

@@ -773,13 +773,27 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
     }
 }
 
+// Blocks of a launch are dispatched to the 8 XCDs of the device round-robin (block L to
+// XCD L % 8, as that XCD's (L / 8)-th block), and every XCD has its own L2. The blocks of
+// the site tiles (z) that read the same T rows (hidden tiles x, sample split y) are given
+// consecutive slots on one XCD, so that the rows come from HBM once and from that XCD's L2
+// for the other site tiles.
+constexpr int kXcds = 8;
+
 template <typename T, bool C, int JT, int NT>
-__global__ __launch_bounds__(256) void k_vjp(int N, int M, int64_t n,
-                                              const int8_t *__restrict__ sigma,
+__global__ __launch_bounds__(256) void k_vjp(int gx, int gz, int64_t total, int N, int M,
+                                              int64_t n, const int8_t *__restrict__ sigma,
                                               const T *__restrict__ Tm,
                                               const double *__restrict__ u, int64_t per_split,
                                               int rowsP, int colsP, T *part, const int *skip) {
-  k_vjp_body<T, C, JT, NT>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, N, M, n, sigma, Tm, u, per_split, rowsP, colsP, part, skip);
+  const int64_t per = (total + kXcds - 1) / kXcds;
+  const int64_t L = blockIdx.x;
+  const int64_t lam = (L % kXcds) * per + L / kXcds;
+  if (lam >= total) return;
+  const int bz = int(lam % gz);
+  const int64_t rest = lam / gz;
+  k_vjp_body<T, C, JT, NT>(int(rest % gx), int(rest / gx), bz, gx, N, M, n, sigma, Tm, u,
+                           per_split, rowsP, colsP, part, skip);
 }
 
 // sum over the 16 lanes of each DPP row (every lane of the row receives the total)
@@ -1617,10 +1631,12 @@ hipError_t vjp_tile(const nqs_model *m, const int8_t *sigma, int64_t n, const do
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
-  dim3 grid(unsigned(cdiv(g.Jtiles, JT)), unsigned(g.splits), unsigned(cdiv(g.Itiles, NT)));
-  hipLaunchKernelGGL((k_vjp<T, C, JT, NT>), grid, dim3(256), 0, st, m->N, m->M, n, sigma,
-                     (const T *)(base + L.Tm), u, g.per_split, g.Jtiles * 16, g.Itiles * 16,
-                     (T *)(base + L.part), skip);
+  const int gx = int(cdiv(g.Jtiles, JT)), gz = int(cdiv(g.Itiles, NT));
+  const int64_t total = int64_t(gx) * g.splits * gz;
+  const dim3 grid(unsigned(kXcds * cdiv(total, kXcds)));
+  hipLaunchKernelGGL((k_vjp<T, C, JT, NT>), grid, dim3(256), 0, st, gx, gz, total, m->N, m->M,
+                     n, sigma, (const T *)(base + L.Tm), u, g.per_split, g.Jtiles * 16,
+                     g.Itiles * 16, (T *)(base + L.part), skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !reduce) return e;
   const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;

@@ -387,6 +387,16 @@ __global__ __launch_bounds__(256) void k_cg_xr(int64_t Pc, const double *dpart, 
   k_cg_xr_body(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, Pc, dpart, nparts, parity, x, r, p, Ap, rpart, st);
 }
 
+// the sum of a CG step's block partials, once (block_sum in one block, the same order as
+// each consumer block would take): the consumers then read a single partial
+__global__ __launch_bounds__(256) void k_psum(const double *part, int64_t nparts, double *out,
+                                              const CGState *st) {
+  if (st->done) return;
+  __shared__ double lds[256];
+  const double s = block_sum(part, nparts, 1, lds);
+  if (threadIdx.x == 0) *out = s;
+}
+
 // rr_new from partials; convergence; beta = rr_new / rr ; p = r + beta p (+ direction
 // tables for the next product)
 template <typename T, bool C>
@@ -670,7 +680,7 @@ __global__ void k_sr_info(const CGState *st, nqs_sr_info *out) {
 
 struct SRLayout {
   size_t grad, y, ysum, u, e_part, e_part2, cm, c_part, c_part2, o1, g, F, x, r, p, Ap, dpart,
-      rpart, vexp, apexp, o1s, gs, ybar, state, total;
+      rpart, vexp, apexp, o1s, gs, ybar, psum, state, total;
 };
 
 SRLayout sr_layout(const nqs_model *m, int64_t n) {
@@ -722,6 +732,7 @@ SRLayout sr_layout(const nqs_model *m, int64_t n) {
   L.o1s = take(ss);
   L.gs = take(ss);
   L.ybar = take(16);
+  L.psum = take(16);
   L.state = take(sizeof(CGState));
   L.total = off;
   return L;
@@ -920,11 +931,15 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
           if ((e2 = hipGetLastError()) != hipSuccess) return e2;
           continue;
         }
-        hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, s2, Pc, D(L.dpart),
-                           ablocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+        hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, s2, D(L.dpart), ablocks, D(L.psum),
+                           (const CGState *)state);
+        hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, s2, Pc, D(L.psum),
+                           int64_t(1), parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
+        hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, s2, D(L.rpart), cblocks, D(L.psum) + 1,
+                           (const CGState *)state);
         hipLaunchKernelGGL((k_cg_p<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, s2, N, M,
-                           D(L.rpart), cblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
+                           D(L.psum) + 1, int64_t(1), parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
                            (T *)gb.Vt, (T *)gb.vb, gb.va, state, split);
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
       }
@@ -1109,11 +1124,16 @@ nqs_status sr_symm_impl(nqs_model *m, void *params, const int8_t *sigma, const v
     hipLaunchKernelGGL(k_symm_shift_dot, dim3(unsigned(sblocks)), dim3(256), 0, st, Pcs,
                        D(L.p), diag_shift, D(L.Ap), D(L.dpart), (const CGState *)state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.dpart),
-                       sblocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.dpart), sblocks, D(L.psum),
+                       (const CGState *)state);
+    hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.psum),
+                       int64_t(1), parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.rpart),
-                       scblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p), state);
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.rpart), scblocks, D(L.psum) + 1,
+                       (const CGState *)state);
+    hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs,
+                       D(L.psum) + 1, int64_t(1), parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
+                       state);
     return hipGetLastError();
   };
   auto update = [&]() -> hipError_t {
@@ -1236,11 +1256,16 @@ nqs_status sr_ff_impl(nqs_model *m, void *params, const int8_t *sigma, const voi
     hipLaunchKernelGGL(k_symm_shift_dot, dim3(unsigned(sblocks)), dim3(256), 0, st, Pcs,
                        D(L.p), diag_shift, D(L.Ap), D(L.dpart), (const CGState *)state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.dpart),
-                       sblocks, parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.dpart), sblocks, D(L.psum),
+                       (const CGState *)state);
+    hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.psum),
+                       int64_t(1), parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.rpart),
-                       scblocks, parity, cg_tol, cg_maxiter, D(L.r), D(L.p), state);
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.rpart), scblocks, D(L.psum) + 1,
+                       (const CGState *)state);
+    hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs,
+                       D(L.psum) + 1, int64_t(1), parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
+                       state);
     return hipGetLastError();
   };
   auto update = [&]() -> hipError_t {
