@@ -660,14 +660,18 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
     // FP32: 16-sample groups on the bf16 matrix cores. Lane (lo, hi) holds Z at samples
     // 4 hi + q (q < 4) of hidden row lo of each tile, split exactly into three bf16
     // parts (step 1: parts h and m, step 2: part l with a zero half) against the spins
-    // of the same samples, which are exact in bf16. The next group's u, spins and T
-    // entries are loaded while the current group is contracted (rows past the end of the
-    // split read its last row and get u = 0, so their Z vanishes).
-    VjpGroup<T, C, JT, NT> cur, nxt;
+    // of the same samples, which are exact in bf16. The u, spins and T entries of the next
+    // two groups are loaded while the current group is contracted (with one wavefront per
+    // SIMD the loads, not the matrix cores, set the pace; rows past the end of the split
+    // read its last row and get u = 0, so their Z vanishes).
+    VjpGroup<T, C, JT, NT> cur, nxt, nx2;
     const int64_t s0 = sbeg + 16 * wid;
-    if (s0 < send) vjp_group_load(cur, sigma, Tm, u, N, M, s0, send, hi, lo, jt0, it0);
+    if (s0 < send) {
+      vjp_group_load(cur, sigma, Tm, u, N, M, s0, send, hi, lo, jt0, it0);
+      vjp_group_load(nxt, sigma, Tm, u, N, M, s0 + 64, send, hi, lo, jt0, it0);
+    }
     for (int64_t s = s0; s < send; s += 64) {
-      vjp_group_load(nxt, sigma, Tm, u, N, M, s + 64, send, hi, lo, jt0, it0);
+      vjp_group_load(nx2, sigma, Tm, u, N, M, s + 128, send, hi, lo, jt0, it0);
       uint4 sb[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
@@ -712,6 +716,7 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
         }
       }
       cur = nxt;
+      nxt = nx2;
     }
   } else
   for (int64_t s = sbeg + 4 * wid; s < send; s += 16) {

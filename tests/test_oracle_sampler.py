@@ -156,3 +156,37 @@ def test_pt_samples_follow_psi_squared(move):
     expct = pi * hist.sum()
     stat = np.sum((hist - expct) ** 2 / expct)
     assert chi2.sf(stat, df=len(confs) - 1) > 1e-3, stat
+
+
+@pytest.mark.parametrize("move", [MOVE_FLIP, MOVE_EXCHANGE])
+def test_pt_hot_replicas_follow_tempered_distribution(move):
+    # after a long run the replica holding temperature index k is distributed as
+    # |psi|^(2 beta_k) / Z (beta_k = 1 - k / R): a check of the beta weighting of both the
+    # Metropolis and the exchange decisions, across independent chains
+    from scipy.stats import chi2
+    m = model(move)
+    N, M = m.n_sites, m.n_hidden
+    p = synth.rbm_params(N, M, True, sigma=0.4, seed=47)
+    chains, R = 2000, 3
+    init = np.stack([sampler.init_chains(m, chains, seed=48 + r) for r in range(R)], axis=1)
+    tix = np.tile(np.arange(R), (chains, 1))
+    _, last, tix2, _ = sampler.sample_pt(m, p, init, tix, 1, 120, seed=48, counter=0)
+    confs, pi1 = exact.exact_probabilities(m, p)
+    if move == MOVE_EXCHANGE:
+        keep = confs.sum(axis=1) == 0
+        confs, pi1 = confs[keep], pi1[keep]
+    index = {c.tobytes(): k for k, c in enumerate(confs)}
+    for k in (1, 2):
+        beta = sampler.pt_betas(R)[k]
+        pk = pi1 ** beta
+        pk = pk / pk.sum()
+        rows = last[np.arange(chains), np.argmax(tix2 == k, axis=1)]
+        hist = np.zeros(len(confs))
+        for row in rows:
+            hist[index[row.tobytes()]] += 1
+        stat = np.sum((hist - pk * chains) ** 2 / (pk * chains))
+        assert chi2.sf(stat, df=len(confs) - 1) > 1e-3, (k, stat)
+        # and not the beta = 1 distribution (the pin sees beta)
+        p1 = pi1 / pi1.sum()
+        stat1 = np.sum((hist - p1 * chains) ** 2 / (p1 * chains))
+        assert chi2.sf(stat1, df=len(confs) - 1) < 1e-3, (k, stat1)
