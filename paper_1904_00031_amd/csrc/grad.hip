@@ -660,18 +660,14 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
     // FP32: 16-sample groups on the bf16 matrix cores. Lane (lo, hi) holds Z at samples
     // 4 hi + q (q < 4) of hidden row lo of each tile, split exactly into three bf16
     // parts (step 1: parts h and m, step 2: part l with a zero half) against the spins
-    // of the same samples, which are exact in bf16. The u, spins and T entries of the next
-    // two groups are loaded while the current group is contracted (with one wavefront per
-    // SIMD the loads, not the matrix cores, set the pace; rows past the end of the split
-    // read its last row and get u = 0, so their Z vanishes).
-    VjpGroup<T, C, JT, NT> cur, nxt, nx2;
+    // of the same samples, which are exact in bf16. The next group's u, spins and T
+    // entries are loaded while the current group is contracted (rows past the end of the
+    // split read its last row and get u = 0, so their Z vanishes).
+    VjpGroup<T, C, JT, NT> cur, nxt;
     const int64_t s0 = sbeg + 16 * wid;
-    if (s0 < send) {
-      vjp_group_load(cur, sigma, Tm, u, N, M, s0, send, hi, lo, jt0, it0);
-      vjp_group_load(nxt, sigma, Tm, u, N, M, s0 + 64, send, hi, lo, jt0, it0);
-    }
+    if (s0 < send) vjp_group_load(cur, sigma, Tm, u, N, M, s0, send, hi, lo, jt0, it0);
     for (int64_t s = s0; s < send; s += 64) {
-      vjp_group_load(nx2, sigma, Tm, u, N, M, s + 128, send, hi, lo, jt0, it0);
+      vjp_group_load(nxt, sigma, Tm, u, N, M, s + 64, send, hi, lo, jt0, it0);
       uint4 sb[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
@@ -716,7 +712,6 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
         }
       }
       cur = nxt;
-      nxt = nx2;
     }
   } else
   for (int64_t s = sbeg + 4 * wid; s < send; s += 16) {
@@ -799,6 +794,148 @@ __global__ __launch_bounds__(256) void k_vjp(int gx, int gz, int64_t total, int 
   const int64_t rest = lam / gz;
   k_vjp_body<T, C, JT, NT>(int(rest % gx), int(rest / gx), bz, gx, N, M, n, sigma, Tm, u,
                            per_split, rowsP, colsP, part, skip);
+}
+
+// ---------------------------------------------------------------------------------
+// O^dagger u for FP32 / BF16 models whose site tiles all fit one block (5 to 17 tiles of 16
+// sites): each block covers JT hidden tiles x every site tile over its sample split, so
+// the exact bf16 split of Z = conj(T) u is formed once per element (not once per site-tile
+// block). The spin operand comes from a table of bf16 quads written once per SR step
+// (k_sigma_quads): sq[g][i] holds the spins of samples 4g .. 4g + 3 at site column i (1 in
+// the bias column i = N, 0 past it and for samples past n), which is the MFMA's B operand
+// of a lane as loaded. Two blocks per compute unit.
+// sq[g][i] = 4 bf16 (samples 4g + q, q = 0..3, in the order of the lane's B operand)
+__global__ void k_sigma_quads(int N, int cols, int64_t n, int64_t groups,
+                              const int8_t *__restrict__ sigma, uint2 *__restrict__ sq) {
+  const int64_t total = groups * cols;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t g = e / cols;
+    const int i = int(e % cols);
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = 4 * g + q;
+      v[q] = row >= n ? 0.f : (i < N ? float(sigma[row * N + i]) : (i == N ? 1.f : 0.f));
+    }
+    sq[e] = make_uint2(pack_hi(v[0], v[1]), pack_hi(v[2], v[3]));
+  }
+}
+
+template <bool C, int JT, int NT>
+__global__ __launch_bounds__(256, 2) void k_vjp_wide(int gx, int nt, int M, int64_t n,
+                                                     const uint2 *__restrict__ sq, int cols,
+                                                     const float *__restrict__ Tm,
+                                                     const double *__restrict__ u,
+                                                     int64_t per_split, int rowsP, float *part,
+                                                     const int *skip) {
+  if (skip && *skip) return;
+  typedef floatx4 Acc;
+  __shared__ float red[4][4][64][C ? 2 : 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lo = lane & 15, hi = lane >> 4;
+  const int bx = int(blockIdx.x % unsigned(gx)), by = int(blockIdx.x / unsigned(gx));
+  const int jt0 = bx * JT;
+  const int64_t sbeg = int64_t(by) * per_split;
+  const int64_t send = sbeg + per_split < n ? sbeg + per_split : n;
+  Acc ar[JT][NT], ai[JT][NT];
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      ar[a][b] = Acc{0, 0, 0, 0};
+      ai[a][b] = Acc{0, 0, 0, 0};
+    }
+  for (int64_t s = sbeg + 16 * wid; s < send; s += 64) {
+    V<float, C> uu[4], tv[JT][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = s + 4 * hi + q;
+      const bool ok = row < send;
+      const int64_t rc = ok ? row : send - 1;
+      const V<float, C> x =
+          vmake<float, C>(float(u[C ? 2 * rc : rc]), C ? float(u[2 * rc + 1]) : 0.f);
+      uu[q] = ok ? x : vmake<float, C>(0.f, 0.f);
+#pragma unroll
+      for (int a = 0; a < JT; ++a) {
+        const int j = (jt0 + a) * 16 + lo;
+        tv[a][q] = vload<float, C>(Tm, rc * M + (j < M ? j : 0));
+      }
+    }
+    const uint2 *sqg = sq + ((s + 4 * hi) >> 2) * int64_t(cols) + lo;
+    uint4 sb[NT];
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      if (b < nt) {
+        const uint2 w = sqg[16 * b];
+        sb[b] = make_uint4(w.x, w.y, w.x, w.y);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < JT; ++a) {
+      const int j = (jt0 + a) * 16 + lo;
+      V<float, C> z[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        z[q] = j < M ? vmul(vconj(tv[a][q]), uu[q])
+                     : (j == M ? uu[q] : vmake<float, C>(0.f, 0.f));
+#pragma unroll
+      for (int pl = 0; pl < (C ? 2 : 1); ++pl) {
+        float zz[4], r[4], l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          zz[q] = pl ? z[q].im : z[q].re;
+          r[q] = bf16_rest(zz[q]);
+          l[q] = bf16_rest(r[q]);
+        }
+        const uint4 a0 = make_uint4(pack_hi(zz[0], zz[1]), pack_hi(zz[2], zz[3]),
+                                    pack_hi(r[0], r[1]), pack_hi(r[2], r[3]));
+        const uint4 a1 = make_uint4(pack_hi(l[0], l[1]), pack_hi(l[2], l[3]), 0u, 0u);
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+          if (b < nt) {
+            if (pl) {
+              ai[a][b] = mfma_bf16(a0, sb[b], ai[a][b]);
+              ai[a][b] = mfma_bf16(a1, sb[b], ai[a][b]);
+            } else {
+              ar[a][b] = mfma_bf16(a0, sb[b], ar[a][b]);
+              ar[a][b] = mfma_bf16(a1, sb[b], ar[a][b]);
+            }
+          }
+        }
+      }
+    }
+  }
+  const int tid = threadIdx.x;
+  const int r = tid >> 6, l = tid & 63;
+  const int colsP = cols;
+#pragma unroll
+  for (int a = 0; a < JT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      if (b >= nt) continue;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        red[wid][q][lane][0] = ar[a][b][q];
+        if constexpr (C) red[wid][q][lane][C ? 1 : 0] = ai[a][b][q];
+      }
+      __syncthreads();
+      const int jrow = (jt0 + a) * 16 + MF<float>::row(l >> 4, r);
+      const int icol = b * 16 + (l & 15);
+      if (jrow < rowsP) {
+        const int64_t o = (int64_t(by) * rowsP + jrow) * colsP + icol;
+        const float sr = red[0][r][l][0] + red[1][r][l][0] + red[2][r][l][0] + red[3][r][l][0];
+        if constexpr (C) {
+          const float si = red[0][r][l][C ? 1 : 0] + red[1][r][l][C ? 1 : 0] +
+                           red[2][r][l][C ? 1 : 0] + red[3][r][l][C ? 1 : 0];
+          part[2 * o] = sr;
+          part[2 * o + 1] = si;
+        } else {
+          part[o] = sr;
+        }
+      }
+    }
 }
 
 // sum over the 16 lanes of each DPP row (every lane of the row receives the total)
@@ -1539,7 +1676,7 @@ __global__ void k_vjp_reduce2(int N, int M, int groups, int colsP, int64_t elems
 // scratch layout (byte offsets), all regions 256-byte aligned
 // ---------------------------------------------------------------------------------
 struct GradLayout {
-  size_t Vt, vb, va, ypart, Tm, masks, part, out1, total;
+  size_t Vt, vb, va, ypart, Tm, masks, sq, part, out1, total;
 };
 
 GradLayout grad_layout(const nqs_model *m, int64_t n) {
@@ -1561,6 +1698,8 @@ GradLayout grad_layout(const nqs_model *m, int64_t n) {
   L.ypart = take(size_t(g.jchunks) * size_t(n) * 16);
   L.Tm = take(size_t(n) * m->M * es + 128 * es);  // slack: whole-tile reads past the last row
   L.masks = take(g.pair ? size_t(n) * 8 : 0);
+  // spin quads of k_vjp_wide: [4 ceil(n / 16)][16 Itiles] uint2
+  L.sq = take(g.wide ? size_t(4 * cdiv(n > 0 ? n : 1, 16)) * g.Itiles * 16 * 8 : 0);
   // sized for the largest split count any plan of this device uses, so that a later
   // change of the tuned S v shape never outgrows a workspace sized earlier
   const size_t splits_cap = size_t(g.splits) > size_t(2 * m->cu_count) ? size_t(g.splits)
@@ -1600,6 +1739,14 @@ hipError_t tanh_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scra
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pack_spins, dim3(unsigned(cdiv(n, 256))), dim3(256), 0, st, m->N, n,
                        sigma, (uint64_t *)(base + L.masks));
+  }
+  if (g.wide && for_grad) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t groups = 4 * cdiv(n, 16);
+    const int64_t b = cdiv(groups * g.Itiles * 16, 256);
+    hipLaunchKernelGGL(k_sigma_quads, dim3(unsigned(b < 8192 ? b : 8192)), dim3(256), 0, st,
+                       m->N, g.Itiles * 16, n, groups, sigma, (uint2 *)(base + L.sq));
   }
   return hipGetLastError();
 }
@@ -1651,10 +1798,36 @@ hipError_t vjp_tile(const nqs_model *m, const int8_t *sigma, int64_t n, const do
   return hipGetLastError();
 }
 
+template <bool C, int JT, int NT>
+hipError_t vjp_wide(const nqs_model *m, int64_t n, const double *u, void *scratch,
+                    const int *skip, hipStream_t st, bool reduce) {
+  GradPlan g = grad_plan(m, n);
+  GradLayout L = grad_layout(m, n);
+  char *base = (char *)scratch;
+  const int gx = int(cdiv(g.Jtiles, JT));
+  hipLaunchKernelGGL((k_vjp_wide<C, JT, NT>), dim3(unsigned(int64_t(gx) * g.splits)), dim3(256),
+                     0, st, gx, g.Itiles, m->M, n, (const uint2 *)(base + L.sq), g.Itiles * 16,
+                     (const float *)(base + L.Tm), u, g.per_split, g.Jtiles * 16,
+                     (float *)(base + L.part), skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !reduce) return e;
+  const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
+  hipLaunchKernelGGL((k_vjp_reduce1<float, C>), dim3(unsigned(cdiv(elems, 256)), g.groups),
+                     dim3(256), 0, st, g.splits, g.groups, elems, (const float *)(base + L.part),
+                     (double *)(base + L.out1), skip);
+  return hipGetLastError();
+}
+
 template <typename T, bool C>
 hipError_t vjp_t(const nqs_model *m, const int8_t *sigma, int64_t n, const double *u,
                  void *scratch, const int *skip, hipStream_t st, bool reduce) {
   GradPlan g = grad_plan(m, n);
+  if constexpr (sizeof(T) == 4) {
+    if (g.wide) {
+      if (g.JT == 2) return vjp_wide<C, 2, 8>(m, n, u, scratch, skip, st, reduce);
+      return vjp_wide<C, 1, 17>(m, n, u, scratch, skip, st, reduce);
+    }
+  }
 #define NQS_VJP_CASE(A, B) \
   if (g.JT == A && g.NT == B) return vjp_tile<T, C, A, B>(m, sigma, n, u, scratch, skip, st, reduce);
   NQS_VJP_CASE(1, 1)
@@ -2062,6 +2235,20 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
     }
   }
   g.pairs = g.pair ? (m->sv_pairs == 4 ? 4 : 2) : 0;
+  // FP32 / BF16 with 5 to 17 site tiles: every site tile in one block (k_vjp_wide), 2 (up
+  // to 8 tiles) or 1 hidden tiles per block, two blocks per compute unit
+  g.wide = false;
+  if (!g.fused && !use_double(m) && g.Itiles >= 5 && g.Itiles <= 17) {
+    g.wide = true;
+    g.JT = g.Itiles <= 8 ? 2 : 1;
+    g.NT = g.Itiles;
+    const int64_t tb = cdiv(g.Jtiles, g.JT);
+    int64_t sp = 2 * int64_t(m->cu_count) / tb;
+    if (sp < 1) sp = 1;
+    if (sp > steps) sp = steps;
+    g.per_split = rup(cdiv(n > 0 ? n : 1, sp), 16);
+    g.splits = int(cdiv(n > 0 ? n : 1, g.per_split));
+  }
   if (g.fused) {
     // fused S v: two blocks of 4 wavefronts per compute unit (one of 8 with 4 pairs),
     // splits of whole 16-sample groups

@@ -233,6 +233,7 @@ struct GradPlan {
   int64_t per_split;  // samples per split (multiple of 16)
   int groups;    // first-level reduction groups of the VJP partials
   bool fused;    // all VJP tiles fit one block: S v in one pass (k_sv)
+  bool wide;     // FP32 VJP with every site tile in one block (k_vjp_wide, spin quads)
   bool pair;     // fused, complex FP32 and N <= 63: plane-split pairs on spin masks (k_svc)
   int pairs;     // wavefront pairs per k_svc block
   int jchunks;   // hidden chunks (8 tiles FP32, 4 FP64) of the JVP / tanh kernels (grid y)
