@@ -325,61 +325,102 @@ class Single:
         gen = torch.Generator(device="cpu").manual_seed(5)
         v = torch.randn(m.n_params, dtype=m.value_dtype, generator=gen).to(self.dev)
         sv_out = torch.empty_like(v)
+        # the product's kernels: the library's event pair around each of them (direction
+        # tables, O v, O^dagger y or the fused product, reduction), per product
         m.time_kernel(nqs.TIME_SV)
-        sv_k = []
+        sv_pairs = []
         for _ in range(21):
             m.sr_matvec(flat, sv_ws, v, w["shift"], out=sv_out)
-            sv_k.append(m.kernel_ms())
+            sv_pairs.append(m.kernel_times())
         m.time_kernel(nqs.TIME_NONE)
-        mv_ms = float(np.mean(sv_k[1:]))
+        sv_pairs = np.array(sv_pairs[1:])
+        pair_ms = sv_pairs.mean(axis=0)
+        mv_ms = float(pair_ms.sum())
         cg_mean = float(np.mean([i["cg_iters"] for i in infos]))
 
-        # roofline of the kernel (or the S v product) that takes most of a step
+        # roofline of the single kernel with the largest device time per step: the sweep,
+        # the local energies (when not fused into the sweep), or one of the S v product's
+        # kernels times the CG iterations per step (the product's kernels, each timed by
+        # the library's event pair: direction tables, O v, O^dagger y or the fused product,
+        # the reduction)
         cplx = w["cplx"]
-        sweep_flops = float(self.C) * self.S * self.N * f_real * self.M * sweep_terms_flops(cplx)
-        share = {"sweep": sweep_ms, "sv": mv_ms * cg_mean,
-                 "eloc": 0.0 if self.fused_eloc() else eloc_ms}
+        es = (16 if cplx else 8) if self.prec == 0 else (8 if cplx else 4)
+        fused_sv = len(pair_ms) == 3
+        share = {"sweep": sweep_ms}
+        if not self.fused_eloc():
+            share["eloc"] = eloc_ms
+        if fused_sv:
+            share["sv_fused"] = float(pair_ms[1]) * cg_mean
+        else:
+            share["jvp"] = float(pair_ms[1]) * cg_mean
+            share["vjp"] = float(pair_ms[2]) * cg_mean
         dom = max(share, key=share.get)
-        plane_split = cplx and self.prec != 0 and self.N <= 63
-        if dom == "sweep":
+        itiles = (self.N + 1 + 15) // 16
+        if dom == "sweep" and self.prec != 0 and self.M > 256:
+            # the wide sweep reads the two table rows (M values each) of every non-identity
+            # proposal from global memory (16.8 MB of tables, no reuse across chains)
+            nbytes = float(self.C) * self.S * self.N * f_real * 2 * self.M * es
+            ach = nbytes / (sweep_ms * 1e-3)
+            roof = {"kernel": "k_sweep_wide", "bound": "hbm", "achieved": ach / 1e9,
+                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
+                    "traffic": recorded_traffic("k_sweep_wide", self.name),
+                    "algorithmic_bytes": nbytes, "launch_ms": sweep_ms,
+                    "real_move_fraction": f_real,
+                    "ratio_term_tflops": float(self.C) * self.S * self.N * f_real * self.M *
+                    sweep_terms_flops(cplx) / (sweep_ms * 1e-3) / 1e12}
+        elif dom == "sweep":
             peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_VALU
-            ach = sweep_flops / (sweep_ms * 1e-3)
-            roof = {"kernel": "k_sweep_wide" if (self.prec != 0 and self.M > 256) else "k_sweep",
-                    "bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
-                    "unit": "TFLOP/s", "frac": ach / peak,
+            fl = float(self.C) * self.S * self.N * f_real * self.M * sweep_terms_flops(cplx)
+            ach = fl / (sweep_ms * 1e-3)
+            roof = {"kernel": "k_sweep", "bound": "alu", "achieved": ach / 1e12,
+                    "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
                     "traffic": recorded_traffic("k_sweep", self.name),
-                    "algorithmic_flops": sweep_flops, "launch_ms": sweep_ms,
-                    "real_move_fraction": f_real}
-        elif dom == "sv" and plane_split:
-            nbytes = sv_bytes(n, self.N, self.M, cplx, True)
-            ach = nbytes / (mv_ms * 1e-3)
-            roof = {"kernel": "S v product: k_prep_dir + k_svc + k_cg_apr", "bound": "hbm",
-                    "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                    "frac": ach / PEAK_HBM, "traffic": recorded_traffic("sv_product", self.name),
-                    "algorithmic_bytes": nbytes, "launch_ms": mv_ms,
-                    "fp32_equivalent_tflops": sv_flops(n, self.N, self.M, cplx) / (mv_ms * 1e-3) / 1e12}
-        elif dom == "sv":
-            # the contractions run on the bf16 matrix cores with the float operand split
-            # exactly into three bf16 parts: float arithmetic, reported against the float
-            # matrix peak, with the bf16 peak alongside (3x the flops on bf16 instructions)
+                    "algorithmic_flops": fl, "launch_ms": sweep_ms, "real_move_fraction": f_real}
+        elif dom == "sv_fused" and cplx and self.prec != 0 and self.N <= 63:
+            # the plane-split fused product streams the T rows and spin masks once
+            nbytes = float(n) * self.M * 8 + 8.0 * n
+            t = float(pair_ms[1])
+            ach = nbytes / (t * 1e-3)
+            roof = {"kernel": "k_svc", "bound": "hbm", "achieved": ach / 1e9,
+                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
+                    "traffic": recorded_traffic("k_svc", self.name),
+                    "algorithmic_bytes": nbytes, "launch_ms": t,
+                    "fp32_equivalent_tflops": sv_flops(n, self.N, self.M, cplx) / (t * 1e-3) / 1e12}
+        elif dom in ("jvp", "vjp", "sv_fused"):
+            # contractions against the spin matrix: 4 n N M flops each side (complex), 2 n N M
+            # (real); the FP32 forms run them on the bf16 matrix cores with the float operand
+            # split exactly into three bf16 parts, so the float result is reported against
+            # the float matrix peak, with the bf16 instructions' rate alongside
+            t = float(pair_ms[1] if dom in ("jvp", "sv_fused") else pair_ms[2])
+            side = (4.0 if cplx else 2.0) * n * self.N * self.M
+            fl = 2 * side if dom == "sv_fused" else side
             peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_MFMA
-            fl = sv_flops(n, self.N, self.M, cplx)
-            ach = fl / (mv_ms * 1e-3)
-            roof = {"kernel": "S v product: k_prep_dir + k_jvp32 + k_jvp_finish + k_vjp + k_cg_apr"
-                              if self.prec != 0 else "S v product (FP64 matrix cores)",
-                    "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
+            ach = fl / (t * 1e-3)
+            name = {"jvp": "k_jvp32" if self.prec != 0 else "k_jvp",
+                    "vjp": ("k_vjp_wide" if 5 <= itiles <= 17 else "k_vjp"),
+                    "sv_fused": "k_sv"}[dom]
+            roof = {"kernel": name, "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": ach / peak,
-                    "traffic": recorded_traffic("sv_product", self.name),
-                    "algorithmic_flops": fl, "launch_ms": mv_ms}
+                    "traffic": recorded_traffic(name, self.name),
+                    "algorithmic_flops": fl, "launch_ms": t}
             if self.prec != 0:
-                roof["bf16_split_frac_of_bf16_peak"] = 3 * fl / (mv_ms * 1e-3) / PEAK_BF16_MFMA
+                # VJP: parts h, m in one 16x16x32 instruction and l in a second (4x the
+                # flops); JVP: three parts (3x)
+                mult = 4.0 if dom == "vjp" else 3.0
+                roof["bf16_instruction_frac_of_bf16_peak"] = mult * ach / PEAK_BF16_MFMA
         else:
             peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_VALU
             fl = float(n) * self.N * f_real * self.M * sweep_terms_flops(cplx)
             ach = fl / (eloc_ms * 1e-3)
-            roof = {"kernel": "local energy", "bound": "alu", "achieved": ach / 1e12,
+            roof = {"kernel": "k_eloc_rows" if self.M > 256 else "local energy",
+                    "bound": "alu", "achieved": ach / 1e12,
                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                     "algorithmic_flops": fl, "launch_ms": eloc_ms}
+        # the whole S v product for reference (sum of its kernels' times)
+        svf = sv_flops(n, self.N, self.M, cplx)
+        roof["sv_product"] = {"ms": mv_ms, "kernel_ms": [float(x) for x in pair_ms],
+                              "fp32_equivalent_tflops": svf / (mv_ms * 1e-3) / 1e12,
+                              "frac_of_fp32_matrix_peak": svf / (mv_ms * 1e-3) / PEAK_FP32_MFMA}
         roof["step_share_ms"] = share
         return {
             "ms_per_step": ms_per_step, "samples_per_step": n,
@@ -813,6 +854,11 @@ def main():
                          "the 40-site ring (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--extra", default=None,
+                    choices=(EXTRA_SINGLE + list(BATCH_WORKLOADS) +
+                             [PT_WORKLOAD["name"], FF_WORKLOAD["name"], SUP_WORKLOAD["name"]]),
+                    help="run only this one of the other workloads (--extra-steps steps) and "
+                         "print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (chains sharded across GPUs, "
@@ -827,6 +873,21 @@ def main():
     nqs.load()
     if args.copy_probe:
         copy_probe(torch, torch.device("cuda:0"))
+    if args.extra:
+        log("workload " + args.extra)
+        if args.extra in BATCH_WORKLOADS:
+            rec = bench_batch(nqs, synth, torch, args.extra, args.extra_steps, 2)
+        elif args.extra == PT_WORKLOAD["name"]:
+            rec = bench_pt(nqs, synth, torch, args.extra_steps, 2)
+        elif args.extra == FF_WORKLOAD["name"]:
+            rec = bench_ffnn(nqs, synth, torch, args.extra_steps, 2)
+        elif args.extra == SUP_WORKLOAD["name"]:
+            rec = bench_supervised(nqs, synth, torch, 5 * args.extra_steps, 3)
+        else:
+            s = Single(nqs, synth, torch, args.extra)
+            rec = s.run(args.extra_steps, 2)
+        print(json.dumps({"extra": args.extra, "record": rec}))
+        return
     log("headline workload " + args.workload)
     head = Single(nqs, synth, torch, args.workload)
     r = head.run(args.steps, args.warmup)

@@ -399,6 +399,12 @@ nqs_status nqs_set_cg_graphs(nqs_model *model, int32_t enable);
 typedef enum { NQS_TIME_NONE = 0, NQS_TIME_SWEEP = 1, NQS_TIME_SV = 2, NQS_TIME_ELOC = 3 } nqs_time_what;
 nqs_status nqs_time_kernel(nqs_model *model, int32_t what);
 nqs_status nqs_kernel_ms(nqs_model *model, float *ms);
+/* The individual pairs of the last timed call, in launch order: ms[k] (host, k < cap) for
+ * k < *count (host; at most 8 pairs are recorded per call). For NQS_TIME_SV the pairs of
+ * one nqs_sr_matvec product are, in order: the direction tables, the O v kernels, the
+ * O^dagger y kernel (the fused S v kernel, for shapes that fuse both), the reduction into
+ * (S + lambda I) v. */
+nqs_status nqs_kernel_times(nqs_model *model, float *ms, int32_t cap, int32_t *count);
 
 /* ---- Batches of independent models (uneven sizes) --------------------------------
  * A batch holds K models created from K descriptions (all with the same is_complex and

@@ -128,6 +128,8 @@ def load(path=LIB_PATH):
         "nqs_set_cg_graphs": (i32, [vp, i32]),
         "nqs_time_kernel": (i32, [vp, i32]),
         "nqs_kernel_ms": (i32, [vp, ctypes.POINTER(ctypes.c_float)]),
+        "nqs_kernel_times": (i32, [vp, ctypes.POINTER(ctypes.c_float), i32,
+                                   ctypes.POINTER(ctypes.c_int32)]),
         "nqs_batch_create": (i32, [ctypes.POINTER(_Desc), i32, ctypes.POINTER(vp)]),
         "nqs_batch_destroy": (None, [vp]),
         "nqs_batch_n_params": (i64, [vp, i32]),
@@ -157,7 +159,7 @@ def exported_symbols():
             "nqs_log_psi_grad", "nqs_log_psi_grad_noalloc", "nqs_sr_workspace_bytes", "nqs_sr_step", "nqs_sr_step_async",
             "nqs_sr_prepare",
             "nqs_sr_matvec", "nqs_autotune", "nqs_set_sv_shape", "nqs_set_cg_graphs",
-            "nqs_time_kernel", "nqs_kernel_ms",
+            "nqs_time_kernel", "nqs_kernel_ms", "nqs_kernel_times",
             "nqs_target_cdf", "nqs_target_draw", "nqs_overlap_step",
             "nqs_batch_create",
             "nqs_batch_destroy", "nqs_batch_n_params", "nqs_batch_chain_init",
@@ -554,6 +556,13 @@ class Model:
         ms = ctypes.c_float()
         _check(_lib.nqs_kernel_ms(self._h, ctypes.byref(ms)), "nqs_kernel_ms")
         return float(ms.value)
+
+    def kernel_times(self):
+        """The event pairs of the last timed call, one time (ms) per launch, in order."""
+        buf = (ctypes.c_float * 8)()
+        count = ctypes.c_int32()
+        _check(_lib.nqs_kernel_times(self._h, buf, 8, ctypes.byref(count)), "nqs_kernel_times")
+        return [float(buf[k]) for k in range(count.value)]
 
 
 class Batch:

@@ -683,6 +683,20 @@ nqs_status nqs_kernel_ms(nqs_model *m, float *ms) {
   return NQS_OK;
 }
 
+nqs_status nqs_kernel_times(nqs_model *m, float *ms, int32_t cap, int32_t *count) {
+  if (!m || !ms || !count || cap < 1 || m->time_n < 1) return NQS_EINVAL;
+  const int k_end = m->time_n < cap ? m->time_n : cap;
+  for (int k = 0; k < k_end; ++k) {
+    float t = 0.f;
+    if (hipEventSynchronize(m->time_ev[k][1]) != hipSuccess ||
+        hipEventElapsedTime(&t, m->time_ev[k][0], m->time_ev[k][1]) != hipSuccess)
+      return NQS_EDEVICE;
+    ms[k] = t;
+  }
+  *count = k_end;
+  return NQS_OK;
+}
+
 nqs_status nqs_set_sv_shape(nqs_model *m, int32_t pairs) {
   if (!m || (pairs != 2 && pairs != 4)) return NQS_EINVAL;
   m->sv_pairs = pairs;

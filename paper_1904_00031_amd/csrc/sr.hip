@@ -387,14 +387,28 @@ __global__ __launch_bounds__(256) void k_cg_xr(int64_t Pc, const double *dpart, 
   k_cg_xr_body(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, Pc, dpart, nparts, parity, x, r, p, Ap, rpart, st);
 }
 
-// the sum of a CG step's block partials, once (block_sum in one block, the same order as
-// each consumer block would take): the consumers then read a single partial
-__global__ __launch_bounds__(256) void k_psum(const double *part, int64_t nparts, double *out,
-                                              const CGState *st) {
+// the sum of a CG step's block partials, once, in a fixed order (1024 threads, four
+// independent strided sums each, then a tree): the consumers then read a single partial
+__global__ __launch_bounds__(1024) void k_psum(const double *part, int64_t nparts, double *out,
+                                               const CGState *st) {
   if (st->done) return;
-  __shared__ double lds[256];
-  const double s = block_sum(part, nparts, 1, lds);
-  if (threadIdx.x == 0) *out = s;
+  __shared__ double lds[1024];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t k = threadIdx.x;
+  for (; k + 3 * 1024 < nparts; k += 4 * 1024) {
+    a0 += part[k];
+    a1 += part[k + 1024];
+    a2 += part[k + 2 * 1024];
+    a3 += part[k + 3 * 1024];
+  }
+  for (; k < nparts; k += 1024) a0 += part[k];
+  lds[threadIdx.x] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = lds[0];
 }
 
 // rr_new from partials; convergence; beta = rr_new / rr ; p = r + beta p (+ direction
@@ -453,17 +467,24 @@ __global__ __launch_bounds__(256) void k_cg_p(int N, int M, const double *rpart,
 // A block takes 32 elements of the tile layout; its 8 thread slices sum every eighth
 // split of them, and the slices are added in a fixed order (deterministic). Elements
 // outside the parameters are idle.
-constexpr int kAprElems = 32, kAprSlices = 8;
+// SL slices of 256 / SL elements per block: 8 slices (32 elements) when there are many
+// sample splits to add, one slice (256 elements) when there are few
+constexpr int kAprElems = 32;
+inline int apr_slices(int splits) { return splits >= 8 ? 8 : 1; }
+inline int64_t apr_blocks(int64_t elems, int splits) {
+  return (elems + 256 / apr_slices(splits) - 1) / (256 / apr_slices(splits));
+}
 
-template <typename T, bool C>
-__global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int splits,
+template <typename T, bool C, int SL>
+__global__ __launch_bounds__(256) void k_cg_apr_t(int N, int M, int64_t n, int splits,
                                                 int colsP, int64_t elems,
                                                 const T *__restrict__ part,
                                                 const double *o1, const double *ysum,
                                                 int64_t nys, const double *p, double lambda,
                                                 double *Ap, double *dpart, const CGState *st) {
   __shared__ double lds[256];
-  __shared__ double sr[kAprSlices][kAprElems], si[kAprSlices][kAprElems];
+  constexpr int kE = 256 / SL;
+  __shared__ double sr[SL][kE], si[SL][kE];
   // the solver state and the sums of y in one memory round trip (no state: a single
   // product, always computed)
   const int done = st ? st->done : 0;
@@ -473,8 +494,8 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
     if (C) ysi += ysum[2 * k + 1];
   }
   if (done) return;
-  const int el = threadIdx.x % kAprElems, sl = threadIdx.x / kAprElems;
-  const int64_t e = int64_t(blockIdx.x) * kAprElems + el;
+  const int el = threadIdx.x % kE, sl = threadIdx.x / kE;
+  const int64_t e = int64_t(blockIdx.x) * kE + el;
   // parameter index of the element (-1: padding of the tile layout)
   int64_t k = -1;
   if (e < elems) {
@@ -501,27 +522,27 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
     // up to 32 loads in flight per thread, added in split order (padding entries of the
     // tile layout are not read)
     int q = sl;
-    for (; q + 31 * kAprSlices < splits; q += 32 * kAprSlices) {
+    for (; q + 31 * SL < splits; q += 32 * SL) {
       V<T, C> xs[32];
 #pragma unroll
-      for (int u = 0; u < 32; ++u) xs[u] = vload<T, C>(part, int64_t(q + u * kAprSlices) * elems + e);
+      for (int u = 0; u < 32; ++u) xs[u] = vload<T, C>(part, int64_t(q + u * SL) * elems + e);
 #pragma unroll
       for (int u = 0; u < 32; ++u) {
         gr += double(xs[u].re);
         if (C) gi += double(xs[u].im);
       }
     }
-    for (; q + 7 * kAprSlices < splits; q += 8 * kAprSlices) {
+    for (; q + 7 * SL < splits; q += 8 * SL) {
       V<T, C> xs[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) xs[u] = vload<T, C>(part, int64_t(q + u * kAprSlices) * elems + e);
+      for (int u = 0; u < 8; ++u) xs[u] = vload<T, C>(part, int64_t(q + u * SL) * elems + e);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         gr += double(xs[u].re);
         if (C) gi += double(xs[u].im);
       }
     }
-    for (; q < splits; q += kAprSlices) {
+    for (; q < splits; q += SL) {
       const V<T, C> x = vload<T, C>(part, int64_t(q) * elems + e);
       gr += double(x.re);
       if (C) gi += double(x.im);
@@ -534,7 +555,7 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
   __syncthreads();
   double acc = 0.0;
   if (sl == 0 && k >= 0) {
-    for (int q = 1; q < kAprSlices; ++q) {
+    for (int q = 1; q < SL; ++q) {
       gr += sr[q][el];
       gi += si[q][el];
     }
@@ -554,6 +575,21 @@ __global__ __launch_bounds__(256) void k_cg_apr(int N, int M, int64_t n, int spl
   }
   acc = block_reduce(acc, lds);
   if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+}
+
+// launch of the CG product reduction with the slice count of the split count
+template <typename T, bool C>
+void k_cg_apr_launch(int64_t elems, hipStream_t st, int N, int M, int64_t n, int splits,
+                     int colsP, const T *part, const double *o1, const double *ysum, int64_t nys,
+                     const double *p, double lambda, double *Ap, double *dpart,
+                     const CGState *state) {
+  const dim3 grid(unsigned(apr_blocks(elems, splits)));
+  if (apr_slices(splits) == 8)
+    hipLaunchKernelGGL((k_cg_apr_t<T, C, 8>), grid, dim3(256), 0, st, N, M, n, splits, colsP,
+                       elems, part, o1, ysum, nys, p, lambda, Ap, dpart, state);
+  else
+    hipLaunchKernelGGL((k_cg_apr_t<T, C, 1>), grid, dim3(256), 0, st, N, M, n, splits, colsP,
+                       elems, part, o1, ysum, nys, p, lambda, Ap, dpart, state);
 }
 
 // ---- x, r and p of one CG iteration in one block (small parameter counts) ----------
@@ -907,7 +943,7 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
   const int *skip = &state->done;
   auto enqueue = [&](int batch, bool copy_back) -> nqs_status {
     // one CG iteration = the product's partial tiles, k_cg_apr, k_cg_xr, k_cg_p
-    const int64_t ablocks = cdiv(elems, kAprElems);
+    const int64_t ablocks = apr_blocks(elems, gp.splits);
     auto iterations = [&](int count, hipStream_t s2) -> hipError_t {
       for (int q = 0; q < count; ++q) {
         const int parity = q & 1;  // chunks start at an even iteration
@@ -920,9 +956,9 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
             e2 = launch_vjp_partials(m, sigma, n, D(L.y), grad, skip, s2, false);
         }
         if (e2 != hipSuccess) return e2;
-        hipLaunchKernelGGL((k_cg_apr<T, C>), dim3(unsigned(ablocks)), dim3(256), 0, s2, N, M, n,
-                           gp.splits, gp.Itiles * 16, elems, (const T *)gb.part, D(L.o1),
-                           D(L.ysum), nys, D(L.p), diag_shift, D(L.Ap), D(L.dpart), state);
+        k_cg_apr_launch<T, C>(elems, s2, N, M, n, gp.splits, gp.Itiles * 16,
+                              (const T *)gb.part, D(L.o1), D(L.ysum), nys, D(L.p), diag_shift,
+                              D(L.Ap), D(L.dpart), state);
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
         if (P <= kXrpMaxParams) {
           hipLaunchKernelGGL((k_cg_xrp<T, C>), dim3(1), dim3(kXrpThreads), 0, s2, N, M,
@@ -931,12 +967,12 @@ nqs_status sr_impl(nqs_model *m, void *params, const int8_t *sigma, const void *
           if ((e2 = hipGetLastError()) != hipSuccess) return e2;
           continue;
         }
-        hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, s2, D(L.dpart), ablocks, D(L.psum),
+        hipLaunchKernelGGL(k_psum, dim3(1), dim3(1024), 0, s2, D(L.dpart), ablocks, D(L.psum),
                            (const CGState *)state);
         hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(cblocks)), dim3(256), 0, s2, Pc, D(L.psum),
                            int64_t(1), parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
         if ((e2 = hipGetLastError()) != hipSuccess) return e2;
-        hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, s2, D(L.rpart), cblocks, D(L.psum) + 1,
+        hipLaunchKernelGGL(k_psum, dim3(1), dim3(1024), 0, s2, D(L.rpart), cblocks, D(L.psum) + 1,
                            (const CGState *)state);
         hipLaunchKernelGGL((k_cg_p<T, C>), dim3(unsigned(pblocks)), dim3(256), 0, s2, N, M,
                            D(L.psum) + 1, int64_t(1), parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
@@ -1066,7 +1102,7 @@ nqs_status sr_symm_impl(nqs_model *m, void *params, const int8_t *sigma, const v
   const GradBuffers gb = grad_buffers(m, n, grad);
   const int64_t elems = int64_t(gp.Jtiles) * 16 * gp.Itiles * 16;
   const int64_t nys = gp.fused ? gp.splits : nb;
-  const int64_t ablocks = cdiv(elems, kAprElems);
+  const int64_t ablocks = apr_blocks(elems, gp.splits);
 
   hipError_t e0;
   const void *pe = model_params(m, params, st, &e0);
@@ -1116,20 +1152,19 @@ nqs_status sr_symm_impl(nqs_model *m, void *params, const int8_t *sigma, const v
     }
     if (e != hipSuccess) return e;
     // expanded (g - ybar O^dagger 1) / n, then summed over the symmetry copies
-    hipLaunchKernelGGL((k_cg_apr<T, C>), dim3(unsigned(ablocks)), dim3(256), 0, st, N, m->M, n,
-                       gp.splits, gp.Itiles * 16, elems, (const T *)gb.part, D(L.o1), D(L.ysum),
-                       nys, D(L.vexp), 0.0, D(L.apexp), D(L.dpart), state);
+    k_cg_apr_launch<T, C>(elems, st, N, m->M, n, gp.splits, gp.Itiles * 16, (const T *)gb.part,
+                          D(L.o1), D(L.ysum), nys, D(L.vexp), 0.0, D(L.apexp), D(L.dpart), state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_symm_reduce(m, D(L.apexp), D(L.Ap), st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_symm_shift_dot, dim3(unsigned(sblocks)), dim3(256), 0, st, Pcs,
                        D(L.p), diag_shift, D(L.Ap), D(L.dpart), (const CGState *)state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.dpart), sblocks, D(L.psum),
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(1024), 0, st, D(L.dpart), sblocks, D(L.psum),
                        (const CGState *)state);
     hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.psum),
                        int64_t(1), parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.rpart), scblocks, D(L.psum) + 1,
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(1024), 0, st, D(L.rpart), scblocks, D(L.psum) + 1,
                        (const CGState *)state);
     hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs,
                        D(L.psum) + 1, int64_t(1), parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
@@ -1256,12 +1291,12 @@ nqs_status sr_ff_impl(nqs_model *m, void *params, const int8_t *sigma, const voi
     hipLaunchKernelGGL(k_symm_shift_dot, dim3(unsigned(sblocks)), dim3(256), 0, st, Pcs,
                        D(L.p), diag_shift, D(L.Ap), D(L.dpart), (const CGState *)state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.dpart), sblocks, D(L.psum),
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(1024), 0, st, D(L.dpart), sblocks, D(L.psum),
                        (const CGState *)state);
     hipLaunchKernelGGL(k_cg_xr, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs, D(L.psum),
                        int64_t(1), parity, D(L.x), D(L.r), D(L.p), D(L.Ap), D(L.rpart), state);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_psum, dim3(1), dim3(256), 0, st, D(L.rpart), scblocks, D(L.psum) + 1,
+    hipLaunchKernelGGL(k_psum, dim3(1), dim3(1024), 0, st, D(L.rpart), scblocks, D(L.psum) + 1,
                        (const CGState *)state);
     hipLaunchKernelGGL(k_cg_p_plain, dim3(unsigned(scblocks)), dim3(256), 0, st, Pcs,
                        D(L.psum) + 1, int64_t(1), parity, cg_tol, cg_maxiter, D(L.r), D(L.p),
@@ -1352,13 +1387,12 @@ nqs_status matvec_impl(nqs_model *m, const int8_t *sigma, int64_t n, void *ws, c
   time_mark(m, NQS_TIME_SV, 1, st);
   time_mark(m, NQS_TIME_SV, 0, st);
   const int64_t nys = gp.fused ? gp.splits : cdiv(n, 256);
-  const dim3 grid(unsigned(cdiv(elems, kAprElems)));
   auto apr = [&](auto tc) {
     typedef decltype(tc) T;
-    hipLaunchKernelGGL((k_cg_apr<T, C>), grid, dim3(256), 0, st, m->N, m->M, n, gp.splits,
-                       gp.Itiles * 16, elems, (const T *)gb.part, (const double *)(b + L.o1),
-                       (const double *)(b + L.ysum), nys, (const double *)v, lambda_exp,
-                       (double *)out, (double *)(b + L.dpart), (const CGState *)nullptr);
+    k_cg_apr_launch<T, C>(elems, st, m->N, m->M, n, gp.splits, gp.Itiles * 16,
+                          (const T *)gb.part, (const double *)(b + L.o1),
+                          (const double *)(b + L.ysum), nys, (const double *)v, lambda_exp,
+                          (double *)out, (double *)(b + L.dpart), (const CGState *)nullptr);
   };
   if (use_double(m))
     apr(double(0));
