@@ -1751,11 +1751,21 @@ hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64
       // one block of four wavefronts per compute unit (the row in registers takes up to
       // 512 registers per lane)
       int64_t blocks = (n + 255) / 256;
-      // up to 48 hidden units the row and products fit two wavefronts per SIMD
-      const int per_cu = tp <= 3 ? 2 : 1;
+      // up to 48 hidden units the row and products fit two wavefronts per SIMD, when two
+      // blocks' tables also fit the LDS of a compute unit (the spreading of the last
+      // grid-stride step assumes every block is resident at once)
+      int per_cu = tp <= 3 ? 2 : 1;
+      const int by_lds = int(size_t(m->max_lds) / tab_lds);
+      if (per_cu > by_lds) per_cu = by_lds < 1 ? 1 : by_lds;
       if (blocks > int64_t(per_cu) * m->cu_count) blocks = int64_t(per_cu) * m->cu_count;
 #define NQS_ELOC_LANES(TPM)                                                                   \
   if (tp <= TPM) {                                                                            \
+    if (tab_lds > 65536) {                                                                    \
+      const hipError_t e = hipFuncSetAttribute(                                               \
+          reinterpret_cast<const void *>(k_eloc_lanes<T, C, TPM>),                            \
+          hipFuncAttributeMaxDynamicSharedMemorySize, m->max_lds);                            \
+      if (e != hipSuccess) return e;                                                          \
+    }                                                                                         \
     hipLaunchKernelGGL((k_eloc_lanes<T, C, TPM>), dim3(unsigned(blocks)), dim3(256), tab_lds, \
                        st, dev_model(m), tables_of<T>(m), sigma, (const T *)Tm, n,            \
                        (double *)eloc, cs_rows);                                              \
