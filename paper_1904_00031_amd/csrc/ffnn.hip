@@ -52,30 +52,24 @@ __device__ V<double, C> ff_layers(const FfDev &f, const T *__restrict__ P,
     const int wi = f.w[l], wo = f.w[l + 1];
     const int nr = (wo + 63) >> 6;
     const T *W = Wt + cs * f.toff[l];
-    V<T, C> acc[kFfR];
-#pragma unroll
-    for (int r = 0; r < kFfR; ++r) {
+    // per output chunk the inputs in order, their weights loaded eight at a time (the
+    // loads of a group are in flight together)
+    for (int r = 0; r < nr; ++r) {
       const int j = lane + 64 * r;
-      acc[r] = (r < nr && j < wo) ? vload<T, C>(P, f.poff[l] + j) : vmake<T, C>(T(0), T(0));
-    }
-    for (int k = 0; k < wi; ++k) {
-      const V<T, C> z = vload<T, C>(zi, k);
-      const T *Wk = W + int64_t(cs) * k * wo;
+      const int jc = j < wo ? j : wo - 1;
+      V<T, C> acc = vload<T, C>(P, f.poff[l] + jc);
+      int k = 0;
+      for (; k + 8 <= wi; k += 8) {
+        V<T, C> wv[8];
 #pragma unroll
-      for (int r = 0; r < kFfR; ++r) {
-        if (r < nr) {
-          int j = lane + 64 * r;
-          j = j < wo ? j : wo - 1;
-          acc[r] = vadd(acc[r], vmul(vload<T, C>(Wk, j), z));
-        }
+        for (int q = 0; q < 8; ++q) wv[q] = vload<T, C>(W, int64_t(k + q) * wo + jc);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc = vadd(acc, vmul(wv[q], vload<T, C>(zi, k + q)));
       }
-    }
-#pragma unroll
-    for (int r = 0; r < kFfR; ++r) {
-      const int j = lane + 64 * r;
-      if (r < nr && j < wo) {
-        if (grow) vstore(grow, f.goff[l] + j, ff_dact<T, C>(f.act[l], acc[r]));
-        const V<T, C> z = ff_act<T, C>(f.act[l], acc[r]);
+      for (; k < wi; ++k) acc = vadd(acc, vmul(vload<T, C>(W, int64_t(k) * wo + jc), vload<T, C>(zi, k)));
+      if (j < wo) {
+        if (grow) vstore(grow, f.goff[l] + j, ff_dact<T, C>(f.act[l], acc));
+        const V<T, C> z = ff_act<T, C>(f.act[l], acc);
         if (l + 1 < f.L) {
           vstore(zo, j, z);
           if (zrow) vstore(zrow, f.zoff[l + 1] + j, z);
@@ -373,7 +367,15 @@ __global__ __launch_bounds__(256) void k_ff_fb(FfDev f, FfWave fw, const T *P, c
         const int k = lane + 64 * r;
         if (k >= wo) break;
         V<T, C> acc = vmake<T, C>(T(0), T(0));
-        for (int j = 0; j < wn; ++j)
+        int j = 0;
+        for (; j + 8 <= wn; j += 8) {
+          V<T, C> wv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) wv[q] = vload<T, C>(Wn, int64_t(j + q) * wo + k);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc = vadd(acc, vmul(wv[q], vload<T, C>(za, j + q)));
+        }
+        for (; j < wn; ++j)
           acc = vadd(acc, vmul(vload<T, C>(Wn, int64_t(j) * wo + k), vload<T, C>(za, j)));
         vstore(grow, f.goff[l] + k, vmul(vload<T, C>(grow, f.goff[l] + k), acc));
       }
@@ -430,7 +432,15 @@ __global__ __launch_bounds__(256) void k_ff_jvp(FfDev f, FfWave fw, const int8_t
         const int j = lane + 64 * r;
         if (j >= wo) break;
         V<T, C> t = vload<T, C>(v, f.poff[l] + j);
-        for (int k = 0; k < wi; ++k)
+        int k = 0;
+        for (; k + 8 <= wi; k += 8) {
+          V<T, C> wv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) wv[q] = vload<T, C>(Vl, int64_t(k + q) * wo + j);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) t = vadd(t, vmul(wv[q], vload<T, C>(za, k + q)));
+        }
+        for (; k < wi; ++k)
           t = vadd(t, vmul(vload<T, C>(Vl, int64_t(k) * wo + j), vload<T, C>(za, k)));
         const V<T, C> q = vmul(vload<T, C>(grow, f.goff[l] + j), t);
         tr += double(q.re);
