@@ -51,6 +51,22 @@ __device__ __forceinline__ floatx4 mfma_bf16(uint4 a, uint4 b, floatx4 c) {
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// T rows of FP32 models: element idx of [n][M] as FP32 values, or (TB, the BF16 form,
+// whose rows are bfloat16 by definition) as bfloat16 (re, im) pairs of 4 bytes (2 real)
+template <typename T, bool C, bool TB>
+__device__ __forceinline__ V<T, C> tload(const T *__restrict__ Tm, int64_t idx) {
+  static_assert(!TB || sizeof(T) == 4, "bfloat16 T rows belong to FP32 models");
+  if constexpr (!TB) {
+    return vload<T, C>(Tm, idx);
+  } else if constexpr (C) {
+    const uint32_t w = reinterpret_cast<const uint32_t *>(Tm)[idx];
+    return vmake<float, true>(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+  } else {
+    const uint32_t h = reinterpret_cast<const unsigned short *>(Tm)[idx];
+    return vmake<float, false>(__uint_as_float(h << 16), 0.f);
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // Direction v (double, packed like the parameters) -> compute-precision tables.
 // ---------------------------------------------------------------------------------
@@ -158,7 +174,16 @@ __device__ __forceinline__ void k_theta_tanh_body(int BX, int BY, int BZ, int GX
           tv.re = T(bf16_round(float(tv.re)));
           if (C) tv.im = T(bf16_round(float(tv.im)));
         }
-        vstore<T, C>(Tout, row * M + j, tv);
+        if (sizeof(T) == 4 && quant == 2) {  // stored as bfloat16 (exact: rounded above)
+          const uint32_t hr = __float_as_uint(float(tv.re)) >> 16;
+          if constexpr (C)
+            reinterpret_cast<uint32_t *>(Tout)[row * M + j] =
+                hr | (__float_as_uint(float(tv.im)) & 0xffff0000u);
+          else
+            reinterpret_cast<unsigned short *>(Tout)[row * M + j] = (unsigned short)hr;
+        } else {
+          vstore<T, C>(Tout, row * M + j, tv);
+        }
       }
     }
   }
@@ -311,7 +336,7 @@ __device__ __forceinline__ uint4 spins8_bf16(uint32_t a, uint32_t b) {
 
 inline int jvp32_cw(int jchunks) { return jchunks >= 3 ? 4 : (jchunks == 2 ? 2 : 1); }
 
-template <bool C>
+template <bool C, bool TB = false>
 __device__ __forceinline__ void k_jvp32_body(int BX, int BY, int CW, int jchunks, int N, int M,
                                              int64_t n, const int8_t *__restrict__ sigma,
                                              const float *__restrict__ Tm,
@@ -460,7 +485,7 @@ __device__ __forceinline__ void k_jvp32_body(int BX, int BY, int CW, int jchunks
       for (int r = 0; r < 4; ++r) {
         const int64_t row = s0 + 16 * g + 4 * hi + r;
         const bool ok = j < M && row < n;
-        const V<float, C> x = vload<float, C>(Tm, ok ? row * M + j : 0);
+        const V<float, C> x = tload<float, C, TB>(Tm, ok ? row * M + j : 0);
         tv[q][r] = ok ? x : vmake<float, C>(0.f, 0.f);
       }
     }
@@ -517,7 +542,7 @@ __device__ __forceinline__ void k_jvp32_body(int BX, int BY, int CW, int jchunks
   }
 }
 
-template <bool C>
+template <bool C, bool TB>
 __global__ __launch_bounds__(256, 2) void k_jvp32(int CW, int jchunks, int N, int M, int64_t n,
                                                    const int8_t *__restrict__ sigma,
                                                    const float *__restrict__ Tm,
@@ -525,8 +550,8 @@ __global__ __launch_bounds__(256, 2) void k_jvp32(int CW, int jchunks, int N, in
                                                    const float *__restrict__ vb,
                                                    const double *__restrict__ va,
                                                    double *ypart, const int *skip) {
-  k_jvp32_body<C>(blockIdx.x, blockIdx.y, CW, jchunks, N, M, n, sigma, Tm, Vt, vb, va, ypart,
-                  skip);
+  k_jvp32_body<C, TB>(blockIdx.x, blockIdx.y, CW, jchunks, N, M, n, sigma, Tm, Vt, vb, va,
+                      ypart, skip);
 }
 
 template <typename T, bool C>
@@ -607,7 +632,7 @@ struct VjpGroup {
   int8_t sp[NT][4];
   V<T, C> tv[JT][4];
 };
-template <typename T, bool C, int JT, int NT>
+template <typename T, bool C, int JT, int NT, bool TB>
 __device__ __forceinline__ void vjp_group_load(VjpGroup<T, C, JT, NT> &g,
                                                const int8_t *__restrict__ sigma,
                                                const T *__restrict__ Tm,
@@ -629,12 +654,12 @@ __device__ __forceinline__ void vjp_group_load(VjpGroup<T, C, JT, NT> &g,
 #pragma unroll
     for (int a = 0; a < JT; ++a) {
       const int j = (jt0 + a) * 16 + lo;
-      g.tv[a][q] = vload<T, C>(Tm, rc * M + (j < M ? j : 0));
+      g.tv[a][q] = tload<T, C, TB>(Tm, rc * M + (j < M ? j : 0));
     }
   }
 }
 
-template <typename T, bool C, int JT, int NT>
+template <typename T, bool C, int JT, int NT, bool TB = false>
 __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N, int M, int64_t n,
                                               const int8_t *__restrict__ sigma,
                                               const T *__restrict__ Tm,
@@ -665,9 +690,10 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
     // split read its last row and get u = 0, so their Z vanishes).
     VjpGroup<T, C, JT, NT> cur, nxt;
     const int64_t s0 = sbeg + 16 * wid;
-    if (s0 < send) vjp_group_load(cur, sigma, Tm, u, N, M, s0, send, hi, lo, jt0, it0);
+    if (s0 < send)
+      vjp_group_load<T, C, JT, NT, TB>(cur, sigma, Tm, u, N, M, s0, send, hi, lo, jt0, it0);
     for (int64_t s = s0; s < send; s += 64) {
-      vjp_group_load(nxt, sigma, Tm, u, N, M, s + 64, send, hi, lo, jt0, it0);
+      vjp_group_load<T, C, JT, NT, TB>(nxt, sigma, Tm, u, N, M, s + 64, send, hi, lo, jt0, it0);
       uint4 sb[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
@@ -724,7 +750,7 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
     for (int a = 0; a < JT; ++a) {
       const int j = (jt0 + a) * 16 + lo;
       if (sok && j < M)
-        z[a] = vmul(vconj(vload<T, C>(Tm, srow * M + j)), uu);
+        z[a] = vmul(vconj(tload<T, C, TB>(Tm, srow * M + j)), uu);
       else
         z[a] = (sok && j == M) ? uu : vmake<T, C>(T(0), T(0));
     }
@@ -780,7 +806,7 @@ __device__ __forceinline__ void k_vjp_body(int BX, int BY, int BZ, int GX, int N
 // for the other site tiles.
 constexpr int kXcds = 8;
 
-template <typename T, bool C, int JT, int NT>
+template <typename T, bool C, int JT, int NT, bool TB>
 __global__ __launch_bounds__(256) void k_vjp(int gx, int gz, int64_t total, int N, int M,
                                               int64_t n, const int8_t *__restrict__ sigma,
                                               const T *__restrict__ Tm,
@@ -792,8 +818,8 @@ __global__ __launch_bounds__(256) void k_vjp(int gx, int gz, int64_t total, int 
   if (lam >= total) return;
   const int bz = int(lam % gz);
   const int64_t rest = lam / gz;
-  k_vjp_body<T, C, JT, NT>(int(rest % gx), int(rest / gx), bz, gx, N, M, n, sigma, Tm, u,
-                           per_split, rowsP, colsP, part, skip);
+  k_vjp_body<T, C, JT, NT, TB>(int(rest % gx), int(rest / gx), bz, gx, N, M, n, sigma, Tm, u,
+                               per_split, rowsP, colsP, part, skip);
 }
 
 // ---------------------------------------------------------------------------------
@@ -822,7 +848,7 @@ __global__ void k_sigma_quads(int N, int cols, int64_t n, int64_t groups,
   }
 }
 
-template <bool C, int JT, int NT>
+template <bool C, int JT, int NT, bool TB>
 __global__ __launch_bounds__(256, 2) void k_vjp_wide(int gx, int nt, int M, int64_t n,
                                                      const uint2 *__restrict__ sq, int cols,
                                                      const float *__restrict__ Tm,
@@ -859,7 +885,7 @@ __global__ __launch_bounds__(256, 2) void k_vjp_wide(int gx, int nt, int M, int6
 #pragma unroll
       for (int a = 0; a < JT; ++a) {
         const int j = (jt0 + a) * 16 + lo;
-        tv[a][q] = vload<float, C>(Tm, rc * M + (j < M ? j : 0));
+        tv[a][q] = tload<float, C, TB>(Tm, rc * M + (j < M ? j : 0));
       }
     }
     const uint2 *sqg = sq + ((s + 4 * hi) >> 2) * int64_t(cols) + lo;
@@ -1171,7 +1197,7 @@ __device__ __forceinline__ int svc_rows(int64_t send, int64_t g) {
 // exactly; columns j >= M of the last tile read the next row (or the slack after T) and
 // meet zero direction entries in the JVP and ignored output rows in the VJP. Addresses
 // are a uniform row base plus a 32-bit lane offset.
-template <typename T, int JT, int JV>
+template <typename T, int JT, int JV, bool TB>
 __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
                                          const T *__restrict__ Tm, int M, int64_t g,
                                          int64_t send, int rows_here, int lane, int lo, int hi,
@@ -1183,13 +1209,14 @@ __device__ __forceinline__ void svc_load(const uint64_t *__restrict__ masks,
 #pragma unroll
   for (int q = 0; q < 4; ++q) mq[q] = mb[min(4 * hi + q, rmax)];
   mlo = mb[min(lo, rmax)];
-  const T *tb = Tm + 2 * gb * int64_t(M);
+  // (complex entries of 8 bytes, or 4 as bfloat16 pairs: one T unit per entry)
+  const T *tb = Tm + (TB ? 1 : 2) * gb * int64_t(M);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const uint32_t off = uint32_t(2 * (min(MF<T>::row(hi, r), rmax) * M + lo));
+    const uint32_t off = uint32_t((TB ? 1 : 2) * (min(MF<T>::row(hi, r), rmax) * M + lo));
 #pragma unroll
     for (int a = 0; a < JT; ++a)
-      tv[a][r] = a < JV ? vload<T, true>(tb + off, a * 16) : vmake<T, true>(T(0), T(0));
+      tv[a][r] = a < JV ? tload<T, true, TB>(tb + off, a * 16) : vmake<T, true>(T(0), T(0));
   }
 }
 
@@ -1221,7 +1248,7 @@ inline size_t svc_dynamic_lds(int N, int M) {
   return 2 * G * JVW * 16;
 }
 
-template <typename T, int JT, int JV, int NT, int PAIRS>
+template <typename T, int JT, int JV, int NT, int PAIRS, bool TB>
 __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
                                                 const uint64_t *__restrict__ masks,
                                                 const T *__restrict__ Tm,
@@ -1368,7 +1395,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
     int rows_here = svc_rows(send, g);
     uint64_t mq[4], mlo;
     V<T, true> tv[JT][4];
-    if (iters > 0) svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mq, mlo, tv);
+    if (iters > 0) svc_load<T, JT, JV, TB>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mq, mlo, tv);
     for (int64_t it = 0; it < iters; ++it) {
       // the masks of rows 4 hi + q of this group (the loads below fetch the next group's)
       uint64_t mc[4];
@@ -1506,7 +1533,7 @@ __global__ __launch_bounds__(128 * PAIRS, 2) void k_svc(int N, int M, int64_t n,
       // registers are the next iteration's operands with no merge copies
       g += 16 * PAIRS;
       rows_here = svc_rows(send, g);
-      svc_load<T, JT, JV>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mq, mlo, tv);
+      svc_load<T, JT, JV, TB>(masks, Tm, M, g, send, rows_here, lane, lo, hi, mq, mlo, tv);
       // ---- plane H of Z^T S over the 16 samples, bf16 split of Z ----
       // k of lane group hi: element e < 4 pairs part h of Z at sample 4 hi + e with that
       // sample's spin, e >= 4 part m; a second step takes part l (upper half zero).
@@ -1732,7 +1759,8 @@ hipError_t tanh_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scra
   char *base = (char *)scratch;
   hipLaunchKernelGGL((k_theta_tanh<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256),
                      0, st, m->N, m->M, n, sigma, (const T *)m->tab_ptrs[0],
-                     (const T *)m->tab_ptrs[1], int(for_grad && m->prec == NQS_BF16),
+                     (const T *)m->tab_ptrs[1],
+                     for_grad && m->prec == NQS_BF16 ? (g.tbf ? 2 : 1) : 0,
                      (T *)(base + L.Tm));
   if (g.pair) {
     hipError_t e = hipGetLastError();
@@ -1760,10 +1788,16 @@ hipError_t jvp_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scrat
   if constexpr (sizeof(T) == 4) {
     const int cw = jvp32_cw(g.jchunks);
     const dim3 grid(unsigned(cdiv(n > 0 ? n : 1, 256 / cw)), unsigned(cdiv(g.jchunks, cw)));
-    hipLaunchKernelGGL((k_jvp32<C>), grid, dim3(256), 0, st, cw, g.jchunks, m->N, m->M, n, sigma,
-                       (const T *)(base + L.Tm), (const T *)(base + L.Vt),
-                       (const T *)(base + L.vb), (const double *)(base + L.va),
-                       (double *)(base + L.ypart), skip);
+#define NQS_JVP32(TB)                                                                      \
+  hipLaunchKernelGGL((k_jvp32<C, TB>), grid, dim3(256), 0, st, cw, g.jchunks, m->N, m->M, n,   \
+                     sigma, (const T *)(base + L.Tm), (const T *)(base + L.Vt),                \
+                     (const T *)(base + L.vb), (const double *)(base + L.va),                  \
+                     (double *)(base + L.ypart), skip)
+    if (g.tbf)
+      NQS_JVP32(true);
+    else
+      NQS_JVP32(false);
+#undef NQS_JVP32
   } else {
     hipLaunchKernelGGL((k_jvp<T, C>), dim3(unsigned(g.jvp_blocks), g.jchunks), dim3(256), 0, st,
                        m->N, m->M, n, sigma, (const T *)(base + L.Tm), (const T *)(base + L.Vt),
@@ -1786,9 +1820,19 @@ hipError_t vjp_tile(const nqs_model *m, const int8_t *sigma, int64_t n, const do
   const int gx = int(cdiv(g.Jtiles, JT)), gz = int(cdiv(g.Itiles, NT));
   const int64_t total = int64_t(gx) * g.splits * gz;
   const dim3 grid(unsigned(kXcds * cdiv(total, kXcds)));
-  hipLaunchKernelGGL((k_vjp<T, C, JT, NT>), grid, dim3(256), 0, st, gx, gz, total, m->N, m->M,
-                     n, sigma, (const T *)(base + L.Tm), u, g.per_split, g.Jtiles * 16,
-                     g.Itiles * 16, (T *)(base + L.part), skip);
+#define NQS_VJPT(TB)                                                                          \
+  hipLaunchKernelGGL((k_vjp<T, C, JT, NT, TB>), grid, dim3(256), 0, st, gx, gz, total, m->N,   \
+                     m->M, n, sigma, (const T *)(base + L.Tm), u, g.per_split, g.Jtiles * 16,  \
+                     g.Itiles * 16, (T *)(base + L.part), skip)
+  bool done = false;
+  if constexpr (C && sizeof(T) == 4) {
+    if (g.tbf) {
+      NQS_VJPT(true);
+      done = true;
+    }
+  }
+  if (!done) NQS_VJPT(false);
+#undef NQS_VJPT
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !reduce) return e;
   const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
@@ -1805,10 +1849,16 @@ hipError_t vjp_wide(const nqs_model *m, int64_t n, const double *u, void *scratc
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
   const int gx = int(cdiv(g.Jtiles, JT));
-  hipLaunchKernelGGL((k_vjp_wide<C, JT, NT>), dim3(unsigned(int64_t(gx) * g.splits)), dim3(256),
-                     0, st, gx, g.Itiles, m->M, n, (const uint2 *)(base + L.sq), g.Itiles * 16,
-                     (const float *)(base + L.Tm), u, g.per_split, g.Jtiles * 16,
-                     (float *)(base + L.part), skip);
+#define NQS_VJPW(TB)                                                                          \
+  hipLaunchKernelGGL((k_vjp_wide<C, JT, NT, TB>), dim3(unsigned(int64_t(gx) * g.splits)),      \
+                     dim3(256), 0, st, gx, g.Itiles, m->M, n, (const uint2 *)(base + L.sq),    \
+                     g.Itiles * 16, (const float *)(base + L.Tm), u, g.per_split,              \
+                     g.Jtiles * 16, (float *)(base + L.part), skip)
+  if (g.tbf)
+    NQS_VJPW(true);
+  else
+    NQS_VJPW(false);
+#undef NQS_VJPW
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !reduce) return e;
   const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
@@ -1851,26 +1901,33 @@ hipError_t vjp_t(const nqs_model *m, const int8_t *sigma, int64_t n, const doubl
   return hipErrorInvalidValue;
 }
 
+template <int JT, int JV, int NT, int PAIRS, bool TB>
+hipError_t svc_run(const nqs_model *m, const GradPlan &g, const GradLayout &L, int64_t n,
+                   char *base, double *ysum_part, const int *skip, hipStream_t st) {
+  const size_t lds = svc_dynamic_lds(m->N, m->M);
+  // dynamic LDS beyond 64 KiB is opted into once per instantiation (up to the device limit
+  // checked by grad_plan)
+  static const hipError_t opt = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(&k_svc<float, JT, JV, NT, PAIRS, TB>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, m->max_lds - 24 * 1024);
+  if (opt != hipSuccess) return opt;
+  hipLaunchKernelGGL((k_svc<float, JT, JV, NT, PAIRS, TB>), dim3(unsigned(g.splits)),
+                     dim3(128 * PAIRS), lds, st, m->N, m->M, n,
+                     (const uint64_t *)(base + L.masks), (const float *)(base + L.Tm),
+                     (const float *)(base + L.Vt), (const float *)(base + L.vb),
+                     (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
+                     g.Itiles * 16, (float *)(base + L.part), ysum_part, skip);
+  return hipGetLastError();
+}
+
 template <int JT, int JV, int NT, int PAIRS>
 hipError_t svc_go(const nqs_model *m, int64_t n, void *scratch, double *ysum_part,
                   const int *skip, hipStream_t st, bool reduce) {
   GradPlan g = grad_plan(m, n);
   GradLayout L = grad_layout(m, n);
   char *base = (char *)scratch;
-  const size_t lds = svc_dynamic_lds(m->N, m->M);
-  // dynamic LDS beyond 64 KiB is opted into once per instantiation (up to the device limit
-  // checked by grad_plan)
-  static const hipError_t opt = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(&k_svc<float, JT, JV, NT, PAIRS>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, m->max_lds - 24 * 1024);
-  if (opt != hipSuccess) return opt;
-  hipLaunchKernelGGL((k_svc<float, JT, JV, NT, PAIRS>), dim3(unsigned(g.splits)),
-                     dim3(128 * PAIRS), lds, st, m->N, m->M, n,
-                     (const uint64_t *)(base + L.masks), (const float *)(base + L.Tm),
-                     (const float *)(base + L.Vt), (const float *)(base + L.vb),
-                     (const double *)(base + L.va), g.per_split, g.Jtiles * 16,
-                     g.Itiles * 16, (float *)(base + L.part), ysum_part, skip);
-  hipError_t e = hipGetLastError();
+  hipError_t e = g.tbf ? svc_run<JT, JV, NT, PAIRS, true>(m, g, L, n, base, ysum_part, skip, st)
+                       : svc_run<JT, JV, NT, PAIRS, false>(m, g, L, n, base, ysum_part, skip, st);
   if (e != hipSuccess || !reduce) return e;
   const int64_t elems = int64_t(g.Jtiles) * 16 * g.Itiles * 16;
   hipLaunchKernelGGL((k_vjp_reduce1<float, true>), dim3(unsigned(cdiv(elems, 256)), g.groups),
@@ -2249,6 +2306,10 @@ GradPlan grad_plan(const nqs_model *m, int64_t n) {
     g.per_split = rup(cdiv(n > 0 ? n : 1, sp), 16);
     g.splits = int(cdiv(n > 0 ? n : 1, g.per_split));
   }
+  // the BF16 form keeps its (bfloat16) T rows for the Jacobian products in 2 bytes per
+  // value where every kernel that reads them can: k_jvp32 with k_vjp_wide, or with k_svc
+  // and k_vjp (complex)
+  g.tbf = m->prec == NQS_BF16 && (g.wide || g.pair);
   if (g.fused) {
     // fused S v: two blocks of 4 wavefronts per compute unit (one of 8 with 4 pairs),
     // splits of whole 16-sample groups

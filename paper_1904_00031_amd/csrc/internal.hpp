@@ -235,6 +235,7 @@ struct GradPlan {
   bool fused;    // all VJP tiles fit one block: S v in one pass (k_sv)
   bool wide;     // FP32 VJP with every site tile in one block (k_vjp_wide, spin quads)
   bool pair;     // fused, complex FP32 and N <= 63: plane-split pairs on spin masks (k_svc)
+  bool tbf;      // BF16 form: T rows of the Jacobian products stored as bfloat16
   int pairs;     // wavefront pairs per k_svc block
   int jchunks;   // hidden chunks (8 tiles FP32, 4 FP64) of the JVP / tanh kernels (grid y)
   int64_t jvp_blocks; // sample tiles of 64 in the JVP / tanh kernels
