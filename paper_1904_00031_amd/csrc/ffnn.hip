@@ -39,34 +39,45 @@ __device__ __forceinline__ V<T, C> ff_dact(int a, V<T, C> y) {
   return a == NQS_ACT_LNCOSH ? t : vsub(vmake<T, C>(T(1), T(0)), vmul(t, t));
 }
 
+// b + sum_(k < wi) W[k stride + j] z_k: the weights loaded eight at a time, four partial
+// sums (k mod 4) added in a fixed order at the end (short dependency chains for the one
+// wavefront that evaluates a configuration)
+template <typename T, bool C>
+__device__ __forceinline__ V<T, C> ff_dot(V<T, C> b, const T *__restrict__ W, int64_t stride,
+                                          int j, const T *z, int wi) {
+  V<T, C> a[4] = {b, vmake<T, C>(T(0), T(0)), vmake<T, C>(T(0), T(0)),
+                  vmake<T, C>(T(0), T(0))};
+  int k = 0;
+  for (; k + 8 <= wi; k += 8) {
+    V<T, C> wv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) wv[q] = vload<T, C>(W, int64_t(k + q) * stride + j);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q & 3] = vadd(a[q & 3], vmul(wv[q], vload<T, C>(z, k + q)));
+  }
+  for (; k < wi; ++k) a[0] = vadd(a[0], vmul(vload<T, C>(W, int64_t(k) * stride + j), vload<T, C>(z, k)));
+  return vadd(vadd(a[0], a[1]), vadd(a[2], a[3]));
+}
+
 // Layers l0 .. L-1 of one configuration whose layer-l0 input is in zi (LDS); zo is the
 // other LDS buffer. zrow / grow (may be NULL): global Z and G rows that receive the layer
-// inputs and f'(y_l). Returns the wave-uniform sum of the last layer's outputs.
+// inputs and f'(y_l). Wt holds the transposed weights from table offset tbase on (the
+// whole table in global memory, or layers 1.. staged in LDS). Returns the wave-uniform sum
+// of the last layer's outputs.
 template <typename T, bool C>
 __device__ V<double, C> ff_layers(const FfDev &f, const T *__restrict__ P,
-                                  const T *__restrict__ Wt, int l0, T *zi, T *zo, int lane,
-                                  T *zrow, T *grow) {
+                                  const T *__restrict__ Wt, int64_t tbase, int l0, T *zi, T *zo,
+                                  int lane, T *zrow, T *grow) {
   constexpr int cs = C ? 2 : 1;
   double tr = 0.0, ti = 0.0;
   for (int l = l0; l < f.L; ++l) {
     const int wi = f.w[l], wo = f.w[l + 1];
     const int nr = (wo + 63) >> 6;
-    const T *W = Wt + cs * f.toff[l];
-    // per output chunk the inputs in order, their weights loaded eight at a time (the
-    // loads of a group are in flight together)
+    const T *W = Wt + cs * (f.toff[l] - tbase);
     for (int r = 0; r < nr; ++r) {
       const int j = lane + 64 * r;
       const int jc = j < wo ? j : wo - 1;
-      V<T, C> acc = vload<T, C>(P, f.poff[l] + jc);
-      int k = 0;
-      for (; k + 8 <= wi; k += 8) {
-        V<T, C> wv[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) wv[q] = vload<T, C>(W, int64_t(k + q) * wo + jc);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc = vadd(acc, vmul(wv[q], vload<T, C>(zi, k + q)));
-      }
-      for (; k < wi; ++k) acc = vadd(acc, vmul(vload<T, C>(W, int64_t(k) * wo + jc), vload<T, C>(zi, k)));
+      const V<T, C> acc = ff_dot<T, C>(vload<T, C>(P, f.poff[l] + jc), W, wo, jc, zi, wi);
       if (j < wo) {
         if (grow) vstore(grow, f.goff[l] + j, ff_dact<T, C>(f.act[l], acc));
         const V<T, C> z = ff_act<T, C>(f.act[l], acc);
@@ -87,10 +98,11 @@ __device__ V<double, C> ff_layers(const FfDev &f, const T *__restrict__ P,
   return vmake<double, C>(wave_sum(tr), C ? wave_sum(ti) : 0.0);
 }
 
-// log psi from first-layer angles th (lane units j = lane + 64 r of layer 0)
+// log psi from first-layer angles th (lane units j = lane + 64 r of layer 0); Wl: the
+// weights of layers 1.. (table offset toff[1] on)
 template <typename T, bool C>
 __device__ V<double, C> ff_from_theta(const FfDev &f, const T *__restrict__ P,
-                                      const T *__restrict__ Wt, const V<double, C> *th, T *zi,
+                                      const T *__restrict__ Wl, const V<double, C> *th, T *zi,
                                       T *zo, int lane) {
   const int w1 = f.w[1];
   double tr = 0.0, ti = 0.0;
@@ -109,7 +121,7 @@ __device__ V<double, C> ff_from_theta(const FfDev &f, const T *__restrict__ P,
   }
   if (f.L == 1) return vmake<double, C>(wave_sum(tr), C ? wave_sum(ti) : 0.0);
   wave_sync();
-  return ff_layers<T, C>(f, P, Wt, 1, zi, zo, lane, nullptr, nullptr);
+  return ff_layers<T, C>(f, P, Wl, f.toff[1], 1, zi, zo, lane, nullptr, nullptr);
 }
 
 // theta = W_0 sigma + b_0 in double from the spins in LDS
@@ -164,6 +176,21 @@ struct FfWave {
   __host__ __device__ int bytes() const { return Npad + 2 * zbytes; }
 };
 
+// The weights of layers 1.. (table elements toff[1] .. tab) copied into LDS after the
+// wavefronts' buffers (wpb of them) by the whole block; returns that copy
+template <typename T, bool C>
+__device__ __forceinline__ const T *ff_stage_layers(const FfDev &f, FfWave fw, int wpb,
+                                                    const T *__restrict__ Wt) {
+  extern __shared__ __align__(16) unsigned char ff_lds[];
+  constexpr int cs = C ? 2 : 1;
+  T *dst = reinterpret_cast<T *>(ff_lds + int64_t(wpb) * fw.bytes());
+  const int64_t n = int64_t(cs) * (f.tab - f.toff[1]);
+  const T *src = Wt + int64_t(cs) * f.toff[1];
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+  __syncthreads();
+  return dst;
+}
+
 template <typename T, bool C>
 __device__ __forceinline__ void ff_wave_ptrs(FfWave fw, int wid, int8_t **sig, T **za, T **zb) {
   extern __shared__ __align__(16) unsigned char ff_lds[];
@@ -200,14 +227,14 @@ __global__ __launch_bounds__(256) void k_ff_log_psi(FfDev f, FfWave fw, const T 
   for (int64_t s = int64_t(blockIdx.x) * (blockDim.x >> 6) + wid; s < n; s += waves) {
     for (int i = lane; i < f.N; i += 64) vstore(za, i, vmake<T, C>(T(sigma[s * f.N + i]), T(0)));
     wave_sync();
-    const V<double, C> lp = ff_layers<T, C>(f, P, Wt, 0, za, zb, lane, nullptr, nullptr);
+    const V<double, C> lp = ff_layers<T, C>(f, P, Wt, 0, 0, za, zb, lane, nullptr, nullptr);
     if (lane == 0) vstore(out, s, lp);
     wave_sync();
   }
 }
 
 // E_loc (Eq. 5) of every configuration from the ratios psi(sigma') / psi(sigma)
-template <typename T, bool C>
+template <typename T, bool C, bool WL>
 __global__ __launch_bounds__(256) void k_ff_eloc(FfDev f, FfWave fw, DevModel dm, const T *P,
                                                  const T *Wt, const int8_t *sigma, int64_t n,
                                                  double *eloc) {
@@ -215,6 +242,9 @@ __global__ __launch_bounds__(256) void k_ff_eloc(FfDev f, FfWave fw, DevModel dm
   int8_t *sig;
   T *za, *zb;
   ff_wave_ptrs<T, C>(fw, wid, &sig, &za, &zb);
+  constexpr int cs = C ? 2 : 1;
+  const T *Wl = WL ? ff_stage_layers<T, C>(f, fw, int(blockDim.x >> 6), Wt)
+                   : Wt + int64_t(cs) * f.toff[1];
   const bool tfim = dm.ham == NQS_TFIM;
   const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
   V<double, C> th[kFfR], th2[kFfR];
@@ -222,7 +252,7 @@ __global__ __launch_bounds__(256) void k_ff_eloc(FfDev f, FfWave fw, DevModel dm
     for (int i = lane; i < f.N; i += 64) sig[i] = sigma[s * f.N + i];
     wave_sync();
     ff_theta<T, C>(f, P, Wt, sig, lane, th);
-    const V<double, C> lp = ff_from_theta<T, C>(f, P, Wt, th, za, zb, lane);
+    const V<double, C> lp = ff_from_theta<T, C>(f, P, Wl, th, za, zb, lane);
     double diag = 0.0;
     for (int b = lane; b < dm.Btot; b += 64)
       diag += dm.bond_diag[b] * double(sig[dm.bonds[2 * b]]) * double(sig[dm.bonds[2 * b + 1]]);
@@ -243,7 +273,7 @@ __global__ __launch_bounds__(256) void k_ff_eloc(FfDev f, FfWave fw, DevModel dm
         if (sig[i] == sig[k] || el == 0.0) continue;
       }
       ff_move<T, C>(f, Wt, th, i, double(sig[i]), k, k >= 0 ? double(sig[k]) : 0.0, lane, th2);
-      const V<double, C> lq = ff_from_theta<T, C>(f, P, Wt, th2, za, zb, lane);
+      const V<double, C> lq = ff_from_theta<T, C>(f, P, Wl, th2, za, zb, lane);
       const double e = exp(lq.re - lp.re);
       if (C) {
         double sn, cn;
@@ -278,11 +308,15 @@ struct FfSweepArgs {
 // identity exchange and the accept rule of the RBM sweep; the ratio from log psi of the
 // proposed configuration, evaluated from the updated first-layer angles, in double for
 // FP64 models and through the FP32 layers otherwise
-template <typename T, bool C>
+template <typename T, bool C, bool WL>
 __global__ __launch_bounds__(256) void k_ff_sweep(FfDev f, FfWave fw, DevModel dm, const T *P,
                                                   const T *Wt, FfSweepArgs a) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int chain = blockIdx.x * (blockDim.x >> 6) + wid;
+  constexpr int cs = C ? 2 : 1;
+  // (the staging barrier comes before any wavefront leaves)
+  const T *Wl = WL ? ff_stage_layers<T, C>(f, fw, int(blockDim.x >> 6), Wt)
+                   : Wt + int64_t(cs) * f.toff[1];
   if (chain >= a.n_chains) return;
   int8_t *sig;
   T *za, *zb;
@@ -293,7 +327,7 @@ __global__ __launch_bounds__(256) void k_ff_sweep(FfDev f, FfWave fw, DevModel d
   wave_sync();
   V<double, C> th[kFfR], th2[kFfR];
   ff_theta<T, C>(f, P, Wt, sig, lane, th);
-  V<double, C> lp = ff_from_theta<T, C>(f, P, Wt, th, za, zb, lane);
+  V<double, C> lp = ff_from_theta<T, C>(f, P, Wl, th, za, zb, lane);
   const uint32_t cid = a.chain_offset + uint32_t(chain);
   int64_t acc_count = 0;
   const int total = a.n_discard + a.n_sweeps;
@@ -315,7 +349,7 @@ __global__ __launch_bounds__(256) void k_ff_sweep(FfDev f, FfWave fw, DevModel d
       const int sk = k >= 0 ? sig[k] : 0;
       if (!flip && si == sk) continue;   // an exchange of equal spins is the identity move
       ff_move<T, C>(f, Wt, th, i, double(si), k, double(sk), lane, th2);
-      const V<double, C> lq = ff_from_theta<T, C>(f, P, Wt, th2, za, zb, lane);
+      const V<double, C> lq = ff_from_theta<T, C>(f, P, Wl, th2, za, zb, lane);
       const double ex = 2.0 * (lq.re - lp.re);
       const int accept = __builtin_amdgcn_readfirstlane(int(ex >= 0.0 || u < exp(ex)));
       if (accept) {
@@ -355,7 +389,7 @@ __global__ __launch_bounds__(256) void k_ff_fb(FfDev f, FfWave fw, const T *P, c
     T *grow = G + int64_t(cs) * s * f.gcols;
     for (int i = lane; i < f.N; i += 64) vstore(za, i, vmake<T, C>(T(sigma[s * f.N + i]), T(0)));
     wave_sync();
-    ff_layers<T, C>(f, P, Wt, 0, za, zb, lane, zrow, grow);
+    ff_layers<T, C>(f, P, Wt, 0, 0, za, zb, lane, zrow, grow);
     // backward: g_l = f'(y_l) * (W_(l+1)^T g_(l+1)); every lane reads back only the G
     // entries it wrote itself, and shares g_(l+1) through LDS
     for (int l = f.L - 2; l >= 0; --l) {
@@ -366,17 +400,7 @@ __global__ __launch_bounds__(256) void k_ff_fb(FfDev f, FfWave fw, const T *P, c
       for (int r = 0; r < kFfR; ++r) {
         const int k = lane + 64 * r;
         if (k >= wo) break;
-        V<T, C> acc = vmake<T, C>(T(0), T(0));
-        int j = 0;
-        for (; j + 8 <= wn; j += 8) {
-          V<T, C> wv[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) wv[q] = vload<T, C>(Wn, int64_t(j + q) * wo + k);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) acc = vadd(acc, vmul(wv[q], vload<T, C>(za, j + q)));
-        }
-        for (; j < wn; ++j)
-          acc = vadd(acc, vmul(vload<T, C>(Wn, int64_t(j) * wo + k), vload<T, C>(za, j)));
+        const V<T, C> acc = ff_dot<T, C>(vmake<T, C>(T(0), T(0)), Wn, wo, k, za, wn);
         vstore(grow, f.goff[l] + k, vmul(vload<T, C>(grow, f.goff[l] + k), acc));
       }
       wave_sync();
@@ -431,17 +455,7 @@ __global__ __launch_bounds__(256) void k_ff_jvp(FfDev f, FfWave fw, const int8_t
       for (int r = 0; r < kFfR; ++r) {
         const int j = lane + 64 * r;
         if (j >= wo) break;
-        V<T, C> t = vload<T, C>(v, f.poff[l] + j);
-        int k = 0;
-        for (; k + 8 <= wi; k += 8) {
-          V<T, C> wv[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) wv[q] = vload<T, C>(Vl, int64_t(k + q) * wo + j);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) t = vadd(t, vmul(wv[q], vload<T, C>(za, k + q)));
-        }
-        for (; k < wi; ++k)
-          t = vadd(t, vmul(vload<T, C>(Vl, int64_t(k) * wo + j), vload<T, C>(za, k)));
+        const V<T, C> t = ff_dot<T, C>(vload<T, C>(v, f.poff[l] + j), Vl, wo, j, za, wi);
         const V<T, C> q = vmul(vload<T, C>(grow, f.goff[l] + j), t);
         tr += double(q.re);
         ti += double(q.im);
@@ -577,6 +591,22 @@ int ff_wpb(const nqs_model *m) {
   return w;
 }
 
+// LDS bytes of the staged weights of layers 1.. (0: not staged, the table is read from
+// global memory): staged when they fit next to the wavefronts' buffers
+size_t ff_stage_bytes(const nqs_model *m) {
+  const FfDev &f = m->ff;
+  if (f.L < 2) return 0;
+  const size_t el = (use_double(m) ? 8 : 4) * (m->is_complex ? 2 : 1);
+  const size_t b = size_t(f.tab - f.toff[1]) * el;
+  return size_t(ff_wpb(m)) * ff_wave(m).bytes() + b <= size_t(m->max_lds) ? b : 0;
+}
+
+// dynamic LDS above 64 KiB, opted into once per kernel
+hipError_t ff_lds_optin(const void *fn, size_t bytes, const nqs_model *m) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, m->max_lds);
+}
+
 unsigned ff_grid(const nqs_model *m, int64_t items) {
   const int wpb = ff_wpb(m);
   const int64_t b = cdiv(items, wpb);
@@ -632,9 +662,25 @@ hipError_t ff_launch_all(const nqs_model *m, int what, const void *params, const
   if (what == 0)
     hipLaunchKernelGGL((k_ff_log_psi<T, C>), dim3(ff_grid(m, n)), dim3(64 * wpb), lds, st, f,
                        fw, P, Wt, sigma, n, (double *)out);
-  else
-    hipLaunchKernelGGL((k_ff_eloc<T, C>), dim3(ff_grid(m, n)), dim3(64 * wpb), lds, st, f, fw,
-                       dev_model(m), P, Wt, sigma, n, (double *)out);
+  else {
+    const size_t sb = ff_stage_bytes(m);
+    if (sb) {
+      const hipError_t e =
+          ff_lds_optin(reinterpret_cast<const void *>(k_ff_eloc<T, C, true>), lds + sb, m);
+      if (e != hipSuccess) return e;
+      // as many blocks as stay resident, two per compute unit at most (the registers of
+      // k_ff_eloc allow two wavefronts per SIMD); each stages the weights once
+      const int64_t per_cu = int64_t(m->max_lds) / int64_t(lds + sb);
+      const int64_t cap = int64_t(m->cu_count) * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
+      const int64_t nb = cdiv(n, wpb);
+      hipLaunchKernelGGL((k_ff_eloc<T, C, true>), dim3(unsigned(nb < cap ? nb : cap)),
+                         dim3(64 * wpb), lds + sb, st, f, fw, dev_model(m), P, Wt, sigma, n,
+                         (double *)out);
+    } else {
+      hipLaunchKernelGGL((k_ff_eloc<T, C, false>), dim3(ff_grid(m, n)), dim3(64 * wpb), lds, st,
+                         f, fw, dev_model(m), P, Wt, sigma, n, (double *)out);
+    }
+  }
   return hipGetLastError();
 }
 
@@ -669,11 +715,23 @@ hipError_t ff_sweep_t(const nqs_model *m, const void *params, int8_t *cs, int n_
   a.n_acc = n_acc;
   const FfWave fw = ff_wave(m);
   const int wpb = ff_wpb(m);
+  const size_t sb = ff_stage_bytes(m);
+  const size_t lds = size_t(wpb) * fw.bytes();
+  if (sb) {
+    const hipError_t e =
+        ff_lds_optin(reinterpret_cast<const void *>(k_ff_sweep<T, C, true>), lds + sb, m);
+    if (e != hipSuccess) return e;
+  }
   time_begin(m, NQS_TIME_SWEEP);
   time_mark(m, NQS_TIME_SWEEP, 0, st);
-  hipLaunchKernelGGL((k_ff_sweep<T, C>), dim3(unsigned(cdiv(n_chains, wpb))), dim3(64 * wpb),
-                     size_t(wpb) * fw.bytes(), st, m->ff, fw, dev_model(m), (const T *)params,
-                     (const T *)m->d_fftab, a);
+  if (sb)
+    hipLaunchKernelGGL((k_ff_sweep<T, C, true>), dim3(unsigned(cdiv(n_chains, wpb))),
+                       dim3(64 * wpb), lds + sb, st, m->ff, fw, dev_model(m), (const T *)params,
+                       (const T *)m->d_fftab, a);
+  else
+    hipLaunchKernelGGL((k_ff_sweep<T, C, false>), dim3(unsigned(cdiv(n_chains, wpb))),
+                       dim3(64 * wpb), lds, st, m->ff, fw, dev_model(m), (const T *)params,
+                       (const T *)m->d_fftab, a);
   time_mark(m, NQS_TIME_SWEEP, 1, st);
   return hipGetLastError();
 }
