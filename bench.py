@@ -179,10 +179,12 @@ def sv_bytes(n, N, M, cplx, masks):
     return float(n) * M * es + spins + 2.0 * P * (16 if cplx else 8)
 
 
-def recorded_traffic(kernel, workload):
+def recorded_traffic(kernel, workload, real_move_fraction=None):
     """HBM bytes per launch of `kernel` on `workload` from the committed FETCH_SIZE /
     WRITE_SIZE counter summary, if one exists for the current kernel sources (the summary
-    records a hash of them); None otherwise."""
+    records a hash of them); None otherwise. A sweep's record also holds the fraction of
+    non-identity proposals of its run: the bytes are scaled to this run's fraction (the
+    table rows are fetched per non-identity proposal)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, workload))
     if not os.path.exists(path):
@@ -200,7 +202,10 @@ def recorded_traffic(kernel, workload):
                 h.update(fh.read())
         if h.hexdigest() != fields["sources_sha256"]:
             return None
-        return float(fields["hbm_bytes_per_launch"])
+        b = float(fields["hbm_bytes_per_launch"])
+        if real_move_fraction is not None and "real_move_fraction" in fields:
+            b *= real_move_fraction / float(fields["real_move_fraction"])
+        return b
     except (KeyError, OSError, ValueError):
         return None
 
@@ -363,7 +368,7 @@ class Single:
             ach = nbytes / (sweep_ms * 1e-3)
             roof = {"kernel": "k_sweep_wide", "bound": "hbm", "achieved": ach / 1e9,
                     "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
-                    "traffic": recorded_traffic("k_sweep_wide", self.name),
+                    "traffic": recorded_traffic("k_sweep_wide", self.name, f_real),
                     "algorithmic_bytes": nbytes, "launch_ms": sweep_ms,
                     "real_move_fraction": f_real,
                     "ratio_term_tflops": float(self.C) * self.S * self.N * f_real * self.M *
@@ -429,7 +434,7 @@ class Single:
             "sampling_samples_per_s": n / (samp_ms * 1e-3),
             "phase_ms": {"sample_and_eloc": samp_ms, "sr_step": sr_ms},
             "kernel_ms": {"sweep": sweep_ms, "local_energy": eloc_ms, "sv_product": mv_ms},
-            "cg_iters_mean": cg_mean,
+            "cg_iters_mean": cg_mean, "real_move_fraction": f_real,
             "energy_last": infos[-1]["energy_re"], "energy_err_last": infos[-1]["energy_err"],
             "sv_tuning": tuning, "roofline": roof,
         }
@@ -905,7 +910,8 @@ def main():
         "roofline": r["roofline"],
     }
     for k in ("sr_iters_per_s", "sampling_samples_per_s", "phase_ms", "kernel_ms",
-              "cg_iters_mean", "energy_last", "energy_err_last", "sv_tuning"):
+              "cg_iters_mean", "real_move_fraction", "energy_last", "energy_err_last",
+              "sv_tuning"):
         out[k] = r[k]
     if not args.no_extras:
         others = {}
