@@ -393,26 +393,30 @@ class Single:
                     "fp32_equivalent_tflops": sv_flops(n, self.N, self.M, cplx) / (t * 1e-3) / 1e12}
         elif dom in ("jvp", "vjp", "sv_fused"):
             # contractions against the spin matrix: 4 n N M flops each side (complex), 2 n N M
-            # (real); the FP32 forms run them on the bf16 matrix cores with the float operand
-            # split exactly into three bf16 parts, so the float result is reported against
-            # the float matrix peak, with the bf16 instructions' rate alongside
+            # (real). FP64 models run them on the FP64 matrix cores; the FP32 / BF16 forms on
+            # the bf16 matrix cores with the float operand split exactly into three bf16
+            # parts: VJP parts h, m in one 16x16x32 instruction and l in a second (4x the
+            # flops), JVP three parts (3x). Those are reported against the bf16 peak by the
+            # flops of the bf16 instructions issued, with the float-equivalent rate alongside
             t = float(pair_ms[1] if dom in ("jvp", "sv_fused") else pair_ms[2])
             side = (4.0 if cplx else 2.0) * n * self.N * self.M
             fl = 2 * side if dom == "sv_fused" else side
-            peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_MFMA
-            ach = fl / (t * 1e-3)
             name = {"jvp": "k_jvp32" if self.prec != 0 else "k_jvp",
                     "vjp": ("k_vjp_wide" if 5 <= itiles <= 17 else "k_vjp"),
                     "sv_fused": "k_sv"}[dom]
+            if self.prec == 0:
+                ach, peak, ifl = fl / (t * 1e-3), PEAK_FP64, fl
+            else:
+                mult = {"jvp": 3.0, "vjp": 4.0, "sv_fused": 3.5}[dom]
+                ifl = mult * fl
+                ach, peak = ifl / (t * 1e-3), PEAK_BF16_MFMA
             roof = {"kernel": name, "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": ach / peak,
                     "traffic": recorded_traffic(name, self.name),
-                    "algorithmic_flops": fl, "launch_ms": t}
+                    "algorithmic_flops": ifl, "launch_ms": t}
             if self.prec != 0:
-                # VJP: parts h, m in one 16x16x32 instruction and l in a second (4x the
-                # flops); JVP: three parts (3x)
-                mult = 4.0 if dom == "vjp" else 3.0
-                roof["bf16_instruction_frac_of_bf16_peak"] = mult * ach / PEAK_BF16_MFMA
+                roof["float_equivalent_flops"] = fl
+                roof["float_equivalent_frac_of_fp32_matrix_peak"] = fl / (t * 1e-3) / PEAK_FP32_MFMA
         else:
             peak = PEAK_FP64 if self.prec == 0 else PEAK_FP32_VALU
             fl = float(n) * self.N * f_real * self.M * sweep_terms_flops(cplx)
@@ -468,16 +472,18 @@ def bench_pt(nqs, synth, torch, steps, warmup):
         counter += S + (10 if k == 0 else 0)
     torch.cuda.synchronize()
     m.time_kernel(nqs.TIME_SWEEP)
-    sweep_k, swaps = [], 0
+    sweep_k = []
+    swaps_dev = torch.zeros((), dtype=torch.int64, device=dev)
     t0 = time.perf_counter()
     for _ in range(steps):
         m.sample_pt(p, reps, tix, S, 0, seed=1234, counter=counter, samples=samples, eloc=eloc,
                     n_swaps=nsw)
         counter += S
         sweep_k.append(m.kernel_ms())
-        swaps += int(nsw.sum().item())
+        swaps_dev += nsw.sum()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    swaps = int(swaps_dev.item())
     m.time_kernel(nqs.TIME_NONE)
     ms = wall * 1e3 / steps
     sweep_ms = float(np.mean(sweep_k))
