@@ -864,13 +864,19 @@ __device__ __forceinline__ float wave_sum_to_last(float x) {
 // Hidden angles theta[c][j] = b_j + sum_i W_ji sigma_ci of every chain in double on the
 // FP64 matrix cores (16x16x4): a wavefront takes 16 chains x 64 hidden units (four 16-unit
 // tiles), the spins (+/-1) and the float weights are exact in double, so only the order of
-// the double additions differs from a sequential sum. Grid (ceil(C / 64), ceil(M / 64)).
+// the double additions differs from a sequential sum. The four wavefronts of a block share
+// the 64 hidden units: their weights are staged in LDS 64 sites at a time (one read of the
+// table per block instead of per wavefront). Grid (ceil(C / 64), ceil(M / 64)).
+constexpr int kTh64Sites = 64;
+
 template <bool C>
 __global__ __launch_bounds__(256) void k_theta64(int N, int M, int n_chains,
                                                  const int8_t *__restrict__ sigma,
                                                  const float *__restrict__ Wt,
                                                  const float *__restrict__ bv, double *theta) {
   typedef double doublex4_t __attribute__((ext_vector_type(4)));
+  // [site of the chunk][hidden unit of the block] (re, im), zero past N and past M
+  __shared__ float2 lw[kTh64Sites][64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int lo = lane & 15, hi = lane >> 4;
   const int c0 = blockIdx.x * 64 + wid * 16;
@@ -883,19 +889,29 @@ __global__ __launch_bounds__(256) void k_theta64(int N, int M, int n_chains,
     ar[q] = doublex4_t{0, 0, 0, 0};
     ai[q] = doublex4_t{0, 0, 0, 0};
   }
-  for (int k0 = 0; k0 < N; k0 += 4) {
-    const int k = k0 + hi;
-    const double a = (crow < n_chains && k < N) ? double(srow[k]) : 0.0;
+  for (int kc = 0; kc < N; kc += kTh64Sites) {
+    if (kc > 0) __syncthreads();  // the previous chunk is no longer read
+    for (int e = threadIdx.x; e < kTh64Sites * 64; e += 256) {
+      const int kk = e >> 6, jj = e & 63;
+      const int k = kc + kk, j = jb + jj;
+      float2 w = make_float2(0.f, 0.f);
+      if (k < N && j < M) {
+        const int64_t x = int64_t(k) * M + j;
+        w = C ? make_float2(Wt[2 * x], Wt[2 * x + 1]) : make_float2(Wt[x], 0.f);
+      }
+      lw[kk][jj] = w;
+    }
+    __syncthreads();
+    const int kn = N - kc < kTh64Sites ? N - kc : kTh64Sites;
+    for (int k0 = 0; k0 < kn; k0 += 4) {
+      const int kk = k0 + hi, k = kc + kk;
+      const double a = (crow < n_chains && kk < kn) ? double(srow[k]) : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = jb + 16 * q + lo;
-      const bool ok = k < N && j < M;
-      const int64_t e = ok ? int64_t(k) * M + j : 0;
-      const double wr = ok ? double(C ? Wt[2 * e] : Wt[e]) : 0.0;
-      ar[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wr, ar[q], 0, 0, 0);
-      if constexpr (C) {
-        const double wi = ok ? double(Wt[2 * e + 1]) : 0.0;
-        ai[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wi, ai[q], 0, 0, 0);
+      for (int q = 0; q < 4; ++q) {
+        const float2 w = lw[kk < kTh64Sites ? kk : 0][16 * q + lo];
+        ar[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, double(w.x), ar[q], 0, 0, 0);
+        if constexpr (C)
+          ai[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, double(w.y), ai[q], 0, 0, 0);
       }
     }
   }
