@@ -382,8 +382,9 @@ class Single:
                     "traffic": recorded_traffic("k_sweep", self.name),
                     "algorithmic_flops": fl, "launch_ms": sweep_ms, "real_move_fraction": f_real}
         elif dom == "sv_fused" and cplx and self.prec != 0 and self.N <= 63:
-            # the plane-split fused product streams the T rows and spin masks once
-            nbytes = float(n) * self.M * 8 + 8.0 * n
+            # the plane-split fused product streams the T rows (complex FP32, or bfloat16
+            # pairs in the BF16 form) and spin masks once
+            nbytes = float(n) * self.M * (4 if self.prec == 2 else 8) + 8.0 * n
             t = float(pair_ms[1])
             ach = nbytes / (t * 1e-3)
             roof = {"kernel": "k_svc", "bound": "hbm", "achieved": ach / 1e9,
