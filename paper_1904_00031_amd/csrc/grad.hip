@@ -117,11 +117,23 @@ struct Chunk {
   static constexpr int JT = (sizeof(T) == 8 || C) ? 4 : 8;
 };
 
+// spins s0 s1 (bytes 0 and 2 of u, +/-1 or 0) -> two bf16 in one dword
+__device__ __forceinline__ uint32_t spin_pair_bf16(uint32_t u) {
+  return ((u << 8) & 0x80008000u) | ((u & 0x00010001u) * 0x3f80u);
+}
+__device__ __forceinline__ uint4 spins8_bf16(uint32_t a, uint32_t b) {
+  return make_uint4(spin_pair_bf16((a & 0xffu) | ((a & 0xff00u) << 8)),
+                    spin_pair_bf16(((a >> 16) & 0xffu) | ((a >> 8) & 0xff0000u)),
+                    spin_pair_bf16((b & 0xffu) | ((b & 0xff00u) << 8)),
+                    spin_pair_bf16(((b >> 16) & 0xffu) | ((b >> 8) & 0xff0000u)));
+}
+
 template <typename T, bool C>
 __device__ __forceinline__ void k_theta_tanh_body(int BX, int BY, int BZ, int GX, int N, int M,
                                                   int64_t n, const int8_t *__restrict__ sigma,
                                                   const T *__restrict__ Wt,
-                                                  const T *__restrict__ bv, int quant, T *Tout) {
+                                                  const T *__restrict__ bv, int quant, int wbf,
+                                                  T *Tout) {
   typedef typename MF<T>::acc Acc;
   constexpr int JT = Chunk<T, C>::JT;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -137,6 +149,65 @@ __device__ __forceinline__ void k_theta_tanh_body(int BX, int BY, int BZ, int GX
     tr[a] = Acc{0, 0, 0, 0};
     ti[a] = Acc{0, 0, 0, 0};
   }
+  if constexpr (sizeof(T) == 4) {
+    // FP32 / BF16 forms on the bf16 matrix cores (16x16x32): the spins are exact in bf16
+    // and so is each weight of the BF16 form (wbf); an FP32 weight is split exactly into
+    // three bf16 parts (h, m, l), so every product is exact and the sums are FP32, as on
+    // the FP32 matrix cores. Per step of 32 sites: lane (lo, hi) holds the spins of sample
+    // s0 + lo at sites k0 + 8 hi .. + 7 (A) and the weights of those sites at unit
+    // (jt0 + q) 16 + lo (B).
+    const bool al8 = (N & 7) == 0 && (reinterpret_cast<uintptr_t>(sigma) & 7) == 0;
+    const int nparts = wbf ? 1 : 3;
+    for (int k0 = 0; k0 < N; k0 += 32) {
+      const int kb = k0 + 8 * hi;
+      uint32_t sa = 0, sb = 0;  // spin bytes (+1 / -1, 0 past N and past n)
+      if (rowA_ok && kb < N) {
+        if (al8) {
+          const uint2 w = *reinterpret_cast<const uint2 *>(srow + kb);
+          sa = w.x;
+          sb = w.y;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t x = kb + e < N ? uint32_t(uint8_t(srow[kb + e])) : 0u;
+            if (e < 4) sa |= x << (8 * e);
+            else sb |= x << (8 * (e - 4));
+          }
+        }
+      }
+      const uint4 av = spins8_bf16(sa, sb);
+#pragma unroll
+      for (int q = 0; q < JT; ++q) {
+        const int j = (jt0 + q) * 16 + lo;
+        float wr[8], wi[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = kb + e;
+          const bool ok = k < N && j < M;
+          const V<float, C> x = vload<float, C>(Wt, ok ? int64_t(k) * M + j : 0);
+          wr[e] = ok ? x.re : 0.f;
+          wi[e] = ok ? (C ? x.im : 0.f) : 0.f;
+        }
+        for (int part = 0; part < nparts; ++part) {
+          const uint4 br = make_uint4(pack_hi(wr[0], wr[1]), pack_hi(wr[2], wr[3]),
+                                      pack_hi(wr[4], wr[5]), pack_hi(wr[6], wr[7]));
+          tr[q] = mfma_bf16(av, br, tr[q]);
+          if constexpr (C) {
+            const uint4 bi = make_uint4(pack_hi(wi[0], wi[1]), pack_hi(wi[2], wi[3]),
+                                        pack_hi(wi[4], wi[5]), pack_hi(wi[6], wi[7]));
+            ti[q] = mfma_bf16(av, bi, ti[q]);
+          }
+          if (part + 1 < nparts) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              wr[e] = bf16_rest(wr[e]);
+              if constexpr (C) wi[e] = bf16_rest(wi[e]);
+            }
+          }
+        }
+      }
+    }
+  } else
   // k outer, tiles inner: the A operand and the JT weight loads of a step are issued
   // together (clamped addresses, selects instead of branches)
 #pragma unroll 2
@@ -194,8 +265,9 @@ __global__ __launch_bounds__(256) void k_theta_tanh(int N, int M, int64_t n,
                                                      const int8_t *__restrict__ sigma,
                                                      const T *__restrict__ Wt,
                                                      const T *__restrict__ bv, int quant,
-                                                     T *Tout) {
-  k_theta_tanh_body<T, C>(blockIdx.x, blockIdx.y, 0, 0, N, M, n, sigma, Wt, bv, quant, Tout);
+                                                     int wbf, T *Tout) {
+  k_theta_tanh_body<T, C>(blockIdx.x, blockIdx.y, 0, 0, N, M, n, sigma, Wt, bv, quant, wbf,
+                          Tout);
 }
 
 // ---------------------------------------------------------------------------------
@@ -322,17 +394,6 @@ __device__ __forceinline__ void k_jvp_body(int BX, int BY, int BZ, int GX, int N
 // term, summed in FP64 by one lane per sample.
 // ---------------------------------------------------------------------------------
 constexpr int kJvpLdsWords = 9216;  // 256 rows x 144 B, 128 x 272 B or 64 x 528 B
-
-// spins s0 s1 (bytes 0 and 2 of u, +/-1 or 0) -> two bf16 in one dword
-__device__ __forceinline__ uint32_t spin_pair_bf16(uint32_t u) {
-  return ((u << 8) & 0x80008000u) | ((u & 0x00010001u) * 0x3f80u);
-}
-__device__ __forceinline__ uint4 spins8_bf16(uint32_t a, uint32_t b) {
-  return make_uint4(spin_pair_bf16((a & 0xffu) | ((a & 0xff00u) << 8)),
-                    spin_pair_bf16(((a >> 16) & 0xffu) | ((a >> 8) & 0xff0000u)),
-                    spin_pair_bf16((b & 0xffu) | ((b & 0xff00u) << 8)),
-                    spin_pair_bf16(((b >> 16) & 0xffu) | ((b >> 8) & 0xff0000u)));
-}
 
 inline int jvp32_cw(int jchunks) { return jchunks >= 3 ? 4 : (jchunks == 2 ? 2 : 1); }
 
@@ -1761,7 +1822,7 @@ hipError_t tanh_t(const nqs_model *m, const int8_t *sigma, int64_t n, void *scra
                      0, st, m->N, m->M, n, sigma, (const T *)m->tab_ptrs[0],
                      (const T *)m->tab_ptrs[1],
                      for_grad && m->prec == NQS_BF16 ? (g.tbf ? 2 : 1) : 0,
-                     (T *)(base + L.Tm));
+                     int(m->prec == NQS_BF16), (T *)(base + L.Tm));
   if (g.pair) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -2049,14 +2110,15 @@ struct TanhJob {
   int64_t n;
   const int8_t *sigma;
   const T *Wt, *bv;
-  int quant, pad0;  // explicit padding (zero): job tables are compared byte by byte
+  int quant, wbf;  // wbf: weights exact in bfloat16 (BF16 form)
   T *Tout;
 };
 template <typename T, bool C>
 __global__ __launch_bounds__(256) void kb_theta_tanh(const TanhJob<T> *jobs, const int4 *map) {
   const int4 b = map[blockIdx.x];
   const TanhJob<T> J = jobs[b.x];
-  k_theta_tanh_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Wt, J.bv, J.quant, J.Tout);
+  k_theta_tanh_body<T, C>(b.y, b.z, 0, 0, J.N, J.M, J.n, J.sigma, J.Wt, J.bv, J.quant, J.wbf,
+                          J.Tout);
 }
 
 template <typename T>
@@ -2153,7 +2215,7 @@ hipError_t tanh_batch_t(nqs_batch *b, const std::vector<BatchGradItem> &items, i
     const BatchGradItem &it = items[k];
     const nqs_model *m = it.m;
     TanhJob<T> J{m->N, m->M, it.n, it.sigma, (const T *)m->tab_ptrs[0], (const T *)m->tab_ptrs[1],
-                 int(m->prec == NQS_BF16), 0, (T *)it.Tm};
+                 int(m->prec == NQS_BF16), int(m->prec == NQS_BF16), (T *)it.Tm};
     jobs.push_back(J);
     const int gx = int(cdiv(it.n, 64)), gy = int(cdiv((m->M + 15) / 16, Chunk<T, C>::JT));
     for (int y = 0; y < gy; ++y)
