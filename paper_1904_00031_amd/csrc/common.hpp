@@ -257,7 +257,8 @@ __device__ __forceinline__ void wave_prod_norm(T &mant, int &ex) {
 }
 
 // rescale a complex running product by a power of two so that max(|re|, |im|) is in
-// [0.5, 1); the exponent moves to ex (exact)
+// [0.5, 1); the exponent moves to ex (exact). Branch-free: a zero product has exponent 0
+// and is left as it is.
 template <typename T, bool C>
 __device__ __forceinline__ void vrenorm(V<T, C> &p, int &ex) {
   T a = p.re < T(0) ? -p.re : p.re;
@@ -265,13 +266,12 @@ __device__ __forceinline__ void vrenorm(V<T, C> &p, int &ex) {
     T b = p.im < T(0) ? -p.im : p.im;
     a = a > b ? a : b;
   }
-  if (a > T(0)) {
-    int e;
-    nfrexp(a, &e);
-    p.re = nldexp(p.re, -e);
-    if constexpr (C) p.im = nldexp(p.im, -e);
-    ex += e;
-  }
+  int e;
+  nfrexp(a, &e);
+  e = a > T(0) ? e : 0;
+  p.re = nldexp(p.re, -e);
+  if constexpr (C) p.im = nldexp(p.im, -e);
+  ex += e;
 }
 
 // ---------------------------------------------------------------------------------

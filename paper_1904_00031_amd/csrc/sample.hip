@@ -1263,9 +1263,12 @@ __global__ __launch_bounds__(64 * kRowsWaves) void k_eloc_rows(DevModel dm, Tabl
   const int nrows = tfim ? (dm.h != 0.0 ? N : 0) : B;
   const T *gC = tfim ? tb.fC : tb.bC;
   const T *gS = tfim ? tb.fS : tb.bS;
-  T *lC = reinterpret_cast<T *>(lds_u8);  // [KB][M] values of the chunk's rows
-  T *lS = lC + int64_t(KB) * M * cs;
-  int8_t *sig = reinterpret_cast<int8_t *>(lS + int64_t(KB) * M * cs) + wid * Npad;
+  // [KB][Mp] values of the chunk's rows, Mp = 64 R: entries past M hold C = 1, S = 0, so
+  // the product loop needs no bound test
+  const int Mp = 64 * R;
+  T *lC = reinterpret_cast<T *>(lds_u8);
+  T *lS = lC + int64_t(KB) * Mp * cs;
+  int8_t *sig = reinterpret_cast<int8_t *>(lS + int64_t(KB) * Mp * cs) + wid * Npad;
   const int64_t smp = int64_t(blockIdx.x) * kRowsWaves + wid;
   const bool ok = smp < n;
   const int64_t sr = ok ? smp : n - 1;
@@ -1283,10 +1286,12 @@ __global__ __launch_bounds__(64 * kRowsWaves) void k_eloc_rows(DevModel dm, Tabl
   for (int c0 = 0; c0 < nrows; c0 += KB) {
     const int kb = nrows - c0 < KB ? nrows - c0 : KB;
     __syncthreads();  // the previous chunk's rows are no longer read
-    const int64_t ne = int64_t(kb) * M;
+    const int64_t ne = int64_t(kb) * Mp;
     for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) {
-      vstore<T, C>(lC, e, vload<T, C>(gC, int64_t(c0) * M + e));
-      vstore<T, C>(lS, e, vload<T, C>(gS, int64_t(c0) * M + e));
+      const int q = int(e / Mp), j = int(e - int64_t(q) * Mp);
+      const int64_t g = int64_t(c0 + q) * M + j;
+      vstore<T, C>(lC, e, j < M ? vload<T, C>(gC, g) : vmake<T, C>(T(1), T(0)));
+      vstore<T, C>(lS, e, j < M ? vload<T, C>(gS, g) : vmake<T, C>(T(0), T(0)));
     }
     __syncthreads();
     if (!ok) continue;
@@ -1313,11 +1318,9 @@ __global__ __launch_bounds__(64 * kRowsWaves) void k_eloc_rows(DevModel dm, Tabl
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int j = lane + 64 * r;
-        if (j < M) {
-          const V<T, C> cc = vload<T, C>(lC, int64_t(q) * M + j);
-          const V<T, C> ss = vload<T, C>(lS, int64_t(q) * M + j);
-          p = vmul(p, vsub(cc, vscale(vmul(t[r], ss), ts)));
-        }
+        const V<T, C> cc = vload<T, C>(lC, int64_t(q) * Mp + j);
+        const V<T, C> ss = vload<T, C>(lS, int64_t(q) * Mp + j);
+        p = vmul(p, vsub(cc, vscale(vmul(t[r], ss), ts)));
         if ((r & 3) == 3) vrenorm(p, pe);
       }
       vrenorm(p, pe);
@@ -1805,7 +1808,9 @@ hipError_t eloc_t(const nqs_model *m, const int8_t *sigma, const void *Tm, int64
     // wide models whose tables exceed LDS: chunks of rows staged per block of samples
     const int cs_rows = m->ham == NQS_TFIM ? m->N : m->Btot;
     const int Npad = round_up(m->N, 16);
-    const size_t per_row = size_t(2) * m->M * sizeof(T) * (C ? 2 : 1);
+    // rows padded to 64 R values, R the register count of the instance launched below
+    const int Rsel = r <= 8 ? 8 : (r <= 16 ? 16 : 32);
+    const size_t per_row = size_t(2) * 64 * Rsel * sizeof(T) * (C ? 2 : 1);
     const size_t tab_lds = size_t(2) * cs_rows * m->M * sizeof(T) * (C ? 2 : 1);
     const size_t fixed = size_t(kRowsWaves) * Npad;
     const int64_t fit = int64_t((size_t(m->max_lds) - fixed) / per_row);
