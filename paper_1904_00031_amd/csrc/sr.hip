@@ -428,8 +428,7 @@ __device__ __forceinline__ void k_cg_p_body(int BX, int BY, int BZ, int GX, int 
   const int iters = st->iters + 1;
   const bool conv = sqrt(rr_new) <= tol * st->bnorm;
   const bool bad = !(finite(rr_new) && finite(st->alpha));
-  for (int64_t k = int64_t(BX) * 256 + threadIdx.x; k < P;
-       k += int64_t(GX) * 256) {
+  auto update = [&](int64_t k) __attribute__((always_inline)) {
     double pr, pi = 0.0;
     if (C) {
       pr = r[2 * k] + beta * p[2 * k];
@@ -441,6 +440,21 @@ __device__ __forceinline__ void k_cg_p_body(int BX, int BY, int BZ, int GX, int 
       p[k] = pr;
     }
     dir_write<T, C>(N, M, k, pr, pi, Vt, vb, va, split);
+  };
+  // a and b in parameter order
+  for (int64_t k = int64_t(BX) * 256 + threadIdx.x; k < N + M; k += int64_t(GX) * 256)
+    update(k);
+  // W in tiles of 8 sites x 8 hidden units per 64 threads (site fastest): the reads of r
+  // and p and the writes of V^T and of its bf16 split all cover whole 64- or 128-byte
+  // runs (parameter order alone would scatter the transposed writes)
+  const int tN = (N + 7) >> 3;
+  const int64_t nt = int64_t(tN) * ((M + 7) >> 3) * 64;
+  for (int64_t g = int64_t(BX) * 256 + threadIdx.x; g < nt; g += int64_t(GX) * 256) {
+    const int64_t tile = g >> 6;
+    const int lane = int(g & 63);
+    const int i = int(tile % tN) * 8 + (lane & 7);
+    const int j = int(tile / tN) * 8 + (lane >> 3);
+    if (i < N && j < M) update(int64_t(N) + M + int64_t(j) * N + i);
   }
   __syncthreads();
   if (BX == 0 && threadIdx.x == 0) {
