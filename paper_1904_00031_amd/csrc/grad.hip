@@ -149,85 +149,93 @@ __device__ __forceinline__ void k_theta_tanh_body(int BX, int BY, int BZ, int GX
     tr[a] = Acc{0, 0, 0, 0};
     ti[a] = Acc{0, 0, 0, 0};
   }
+  // FP32 / BF16 forms on the bf16 matrix cores (16x16x32) for the BF16 form and for FP32
+  // models with at least 128 sites (fewer sites pad the 32-site steps and the three parts
+  // of FP32 weights cost more than the FP32 instruction saves); the others below
+  bool bf16_cores = false;
+  if constexpr (sizeof(T) == 4) bf16_cores = wbf || N >= 128;
   if constexpr (sizeof(T) == 4) {
-    // FP32 / BF16 forms on the bf16 matrix cores (16x16x32): the spins are exact in bf16
-    // and so is each weight of the BF16 form (wbf); an FP32 weight is split exactly into
-    // three bf16 parts (h, m, l), so every product is exact and the sums are FP32, as on
-    // the FP32 matrix cores. Per step of 32 sites: lane (lo, hi) holds the spins of sample
-    // s0 + lo at sites k0 + 8 hi .. + 7 (A) and the weights of those sites at unit
-    // (jt0 + q) 16 + lo (B).
-    const bool al8 = (N & 7) == 0 && (reinterpret_cast<uintptr_t>(sigma) & 7) == 0;
-    const int nparts = wbf ? 1 : 3;
-    for (int k0 = 0; k0 < N; k0 += 32) {
-      const int kb = k0 + 8 * hi;
-      uint32_t sa = 0, sb = 0;  // spin bytes (+1 / -1, 0 past N and past n)
-      if (rowA_ok && kb < N) {
-        if (al8) {
-          const uint2 w = *reinterpret_cast<const uint2 *>(srow + kb);
-          sa = w.x;
-          sb = w.y;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const uint32_t x = kb + e < N ? uint32_t(uint8_t(srow[kb + e])) : 0u;
-            if (e < 4) sa |= x << (8 * e);
-            else sb |= x << (8 * (e - 4));
-          }
-        }
-      }
-      const uint4 av = spins8_bf16(sa, sb);
-#pragma unroll
-      for (int q = 0; q < JT; ++q) {
-        const int j = (jt0 + q) * 16 + lo;
-        float wr[8], wi[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = kb + e;
-          const bool ok = k < N && j < M;
-          const V<float, C> x = vload<float, C>(Wt, ok ? int64_t(k) * M + j : 0);
-          wr[e] = ok ? x.re : 0.f;
-          wi[e] = ok ? (C ? x.im : 0.f) : 0.f;
-        }
-        for (int part = 0; part < nparts; ++part) {
-          const uint4 br = make_uint4(pack_hi(wr[0], wr[1]), pack_hi(wr[2], wr[3]),
-                                      pack_hi(wr[4], wr[5]), pack_hi(wr[6], wr[7]));
-          tr[q] = mfma_bf16(av, br, tr[q]);
-          if constexpr (C) {
-            const uint4 bi = make_uint4(pack_hi(wi[0], wi[1]), pack_hi(wi[2], wi[3]),
-                                        pack_hi(wi[4], wi[5]), pack_hi(wi[6], wi[7]));
-            ti[q] = mfma_bf16(av, bi, ti[q]);
-          }
-          if (part + 1 < nparts) {
-#pragma unroll
+    if (bf16_cores) {
+      // the spins are exact in bf16 and so is each weight of the BF16 form (wbf); an FP32
+      // weight is split exactly into three bf16 parts (h, m, l), so every product is exact
+      // and the sums are FP32, as on the FP32 matrix cores. Per step of 32 sites: lane
+      // (lo, hi) holds the spins of sample s0 + lo at sites k0 + 8 hi .. + 7 (A) and the
+      // weights of those sites at unit (jt0 + q) 16 + lo (B).
+      const bool al8 = (N & 7) == 0 && (reinterpret_cast<uintptr_t>(sigma) & 7) == 0;
+      const int nparts = wbf ? 1 : 3;
+      for (int k0 = 0; k0 < N; k0 += 32) {
+        const int kb = k0 + 8 * hi;
+        uint32_t sa = 0, sb = 0;  // spin bytes (+1 / -1, 0 past N and past n)
+        if (rowA_ok && kb < N) {
+          if (al8) {
+            const uint2 w = *reinterpret_cast<const uint2 *>(srow + kb);
+            sa = w.x;
+            sb = w.y;
+          } else {
+  #pragma unroll
             for (int e = 0; e < 8; ++e) {
-              wr[e] = bf16_rest(wr[e]);
-              if constexpr (C) wi[e] = bf16_rest(wi[e]);
+              const uint32_t x = kb + e < N ? uint32_t(uint8_t(srow[kb + e])) : 0u;
+              if (e < 4) sa |= x << (8 * e);
+              else sb |= x << (8 * (e - 4));
+            }
+          }
+        }
+        const uint4 av = spins8_bf16(sa, sb);
+  #pragma unroll
+        for (int q = 0; q < JT; ++q) {
+          const int j = (jt0 + q) * 16 + lo;
+          float wr[8], wi[8];
+  #pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int k = kb + e;
+            const bool ok = k < N && j < M;
+            const V<float, C> x = vload<float, C>(Wt, ok ? int64_t(k) * M + j : 0);
+            wr[e] = ok ? x.re : 0.f;
+            wi[e] = ok ? (C ? x.im : 0.f) : 0.f;
+          }
+          for (int part = 0; part < nparts; ++part) {
+            const uint4 br = make_uint4(pack_hi(wr[0], wr[1]), pack_hi(wr[2], wr[3]),
+                                        pack_hi(wr[4], wr[5]), pack_hi(wr[6], wr[7]));
+            tr[q] = mfma_bf16(av, br, tr[q]);
+            if constexpr (C) {
+              const uint4 bi = make_uint4(pack_hi(wi[0], wi[1]), pack_hi(wi[2], wi[3]),
+                                          pack_hi(wi[4], wi[5]), pack_hi(wi[6], wi[7]));
+              ti[q] = mfma_bf16(av, bi, ti[q]);
+            }
+            if (part + 1 < nparts) {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                wr[e] = bf16_rest(wr[e]);
+                if constexpr (C) wi[e] = bf16_rest(wi[e]);
+              }
             }
           }
         }
       }
     }
-  } else
-  // k outer, tiles inner: the A operand and the JT weight loads of a step are issued
-  // together (clamped addresses, selects instead of branches)
+  }
+  if (!bf16_cores) {
+    // k outer, tiles inner: the A operand and the JT weight loads of a step are issued
+    // together (clamped addresses, selects instead of branches)
 #pragma unroll 2
-  for (int k0 = 0; k0 < N; k0 += 4) {
-    const int k = k0 + hi;
-    const bool kok = k < N;
-    const int8_t sv = srow[kok ? k : 0];
-    const T a = (rowA_ok && kok) ? T(sv) : T(0);
-    V<T, C> w[JT];
+    for (int k0 = 0; k0 < N; k0 += 4) {
+      const int k = k0 + hi;
+      const bool kok = k < N;
+      const int8_t sv = srow[kok ? k : 0];
+      const T a = (rowA_ok && kok) ? T(sv) : T(0);
+      V<T, C> w[JT];
 #pragma unroll
-    for (int q = 0; q < JT; ++q) {
-      const int j = (jt0 + q) * 16 + lo;
-      const bool ok = kok && j < M;
-      const V<T, C> x = vload<T, C>(Wt, ok ? int64_t(k) * M + j : 0);
-      w[q] = ok ? x : vmake<T, C>(T(0), T(0));
-    }
+      for (int q = 0; q < JT; ++q) {
+        const int j = (jt0 + q) * 16 + lo;
+        const bool ok = kok && j < M;
+        const V<T, C> x = vload<T, C>(Wt, ok ? int64_t(k) * M + j : 0);
+        w[q] = ok ? x : vmake<T, C>(T(0), T(0));
+      }
 #pragma unroll
-    for (int q = 0; q < JT; ++q) {
-      tr[q] = MF<T>::mma(a, w[q].re, tr[q]);
-      if constexpr (C) ti[q] = MF<T>::mma(a, w[q].im, ti[q]);
+      for (int q = 0; q < JT; ++q) {
+        tr[q] = MF<T>::mma(a, w[q].re, tr[q]);
+        if constexpr (C) ti[q] = MF<T>::mma(a, w[q].im, ti[q]);
+      }
     }
   }
 #pragma unroll
